@@ -1,0 +1,121 @@
+"""Derived quantities, discretization nodes and multipole helpers (oracle).
+
+Test infrastructure only (see oracle/__init__.py).
+
+Conventions (paper sec. 2): time dependence e^{-i omega t}; wavenumber k_j =
+omega * n_j (mu = 1, eps = n^2); Bloch phase alpha = e^{i kappa d}; Rayleigh-Bloch
+wavenumbers kappa_n = kappa + 2 pi n / d and k_{j,n} = sqrt(k_j^2 - kappa_n^2)
+taken with non-negative real or imaginary part (eq. rad1/rad2).  The incidence
+angle phi is measured from the downward normal: kappa = k_1 sin(phi), and the
+incident wave is exp(i (kappa x - k_1 cos(phi) y)) in the top layer only.
+
+Outgoing multipole of order n about c: H_n(k |x-c|) e^{i n theta(x-c)}.
+Incoming (local) term: J_n(k |x-c|) e^{i n theta(x-c)}.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.special as sp
+
+
+def sqrt_branch(v):
+    """sqrt(v) for real v, non-negative real part or positive imaginary part."""
+    v = np.asarray(v, dtype=float)
+    out = np.where(v >= 0, np.sqrt(np.abs(v)) + 0j, 1j * np.sqrt(np.abs(v)))
+    return out
+
+
+def outgoing(n, k, vx, vy):
+    """H_n(k r) e^{i n theta} at displacement (vx, vy); broadcasts over n."""
+    r = np.hypot(vx, vy)
+    th = np.arctan2(vy, vx)
+    return sp.hankel1(n, k * r) * np.exp(1j * n * th)
+
+
+def incoming(n, k, vx, vy):
+    """J_n(k r) e^{i n theta} at displacement (vx, vy); broadcasts over n."""
+    r = np.hypot(vx, vy)
+    th = np.arctan2(vy, vx)
+    return sp.jv(n, k * r) * np.exp(1j * n * th)
+
+
+def grad_wave(fun, n, k, vx, vy):
+    """(d/dx, d/dy) of Z_n(k r) e^{i n theta} for Z in {J, H}.
+
+    From (d_x + i d_y) Z_n e^{in theta} = -k Z_{n+1} e^{i(n+1) theta} and
+    (d_x - i d_y) Z_n e^{in theta} = k Z_{n-1} e^{i(n-1) theta}.
+    """
+    fm = fun(n - 1, k, vx, vy)
+    fp = fun(n + 1, k, vx, vy)
+    return 0.5 * k * (fm - fp), 0.5j * k * (fm + fp)
+
+
+class Geometry:
+    """All derived quantities of one Problem (geometry + one incidence)."""
+
+    def __init__(self, pb):
+        self.pb = pb
+        dd = pb.disc
+        self.d, self.h = float(pb.d), float(pb.h)
+        self.k1, self.k2, self.k3 = (pb.omega * n for n in pb.n_layer)
+        self.kl = (self.k1, self.k2, self.k3)
+        self.P = int(pb.P)
+        self.M = int(len(pb.x))
+        self.cx = np.asarray(pb.x, float)
+        self.cy = np.asarray(pb.y, float)
+        self.rad = np.asarray(pb.radius, float)
+        self.kp = pb.omega * np.asarray(pb.n_incl, float)
+        self.kappa = self.k1 * np.sin(pb.phi)
+        self.alpha = np.exp(1j * self.kappa * self.d)
+        self.cosphi = np.cos(pb.phi)
+        # Rayleigh-Bloch orders (eq. rad1/rad2)
+        self.rb = dd.n_rb_lo + np.arange(dd.Nrb)
+        self.kapn = self.kappa + 2 * np.pi * self.rb / self.d
+        self.k1n = sqrt_branch(self.k1 ** 2 - self.kapn ** 2)
+        self.k3n = sqrt_branch(self.k3 ** 2 - self.kapn ** 2)
+        # interface nodes: cell-centred, equispaced in x, weight d/N
+        N = dd.N
+        self.N = N
+        self.hs = self.d / N
+        self.xg = -self.d / 2 + (np.arange(N) + 0.5) * self.hs
+        self.y0 = float(dd.y0)
+        # wall nodes: Gauss-Legendre on each layer's wall
+        spans = ((self.h, self.y0), (-self.h, self.h), (-self.y0, -self.h))
+        self.yw = []
+        for Nw, (a, b) in zip(dd.Nw, spans):
+            t, _ = np.polynomial.legendre.leggauss(Nw)
+            self.yw.append(0.5 * (a + b) + 0.5 * (b - a) * t)
+        # Gamma_u / Gamma_d nodes
+        self.xu = -self.d / 2 + (np.arange(dd.Nu) + 0.5) * self.d / dd.Nu
+        # J expansion centres of layers 1, 2, 3 and their orders
+        yc = 0.5 * (self.h + self.y0)
+        self.jc = ((0.0, yc), (0.0, 0.0), (0.0, -yc))
+        self.Q = tuple(int(q) for q in dd.Q)
+        # column layout of the empty-structure unknowns
+        sizes = [("mu1", N), ("sig1", N), ("mu2", N), ("sig2", N),
+                 ("a2", 2 * self.Q[1] + 1), ("a1", 2 * self.Q[0] + 1),
+                 ("a3", 2 * self.Q[2] + 1), ("c", dd.Nrb), ("d", dd.Nrb)]
+        self.col = {}
+        o = 0
+        for nm, s in sizes:
+            self.col[nm] = slice(o, o + s)
+            o += s
+        self.n_alpha = o
+        # row layout of the conditions
+        rs = [("g1v", N), ("g1n", N), ("g2v", N), ("g2n", N),
+              ("w2v", dd.Nw[1]), ("w2d", dd.Nw[1]),
+              ("w1v", dd.Nw[0]), ("w1d", dd.Nw[0]),
+              ("w3v", dd.Nw[2]), ("w3d", dd.Nw[2]),
+              ("uv", dd.Nu), ("un", dd.Nu), ("dv", dd.Nu), ("dn", dd.Nu)]
+        self.row = {}
+        o = 0
+        for nm, s in rs:
+            self.row[nm] = slice(o, o + s)
+            o += s
+        self.n_rows = o
+        self.nb = 2 * self.P + 1
+        self.n_beta = self.M * self.nb
+
+    def u_inc(self, x, y):
+        """Incident plane wave (top layer only)."""
+        return np.exp(1j * (self.kappa * x - self.k1 * self.cosphi * y))

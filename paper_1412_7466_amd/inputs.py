@@ -1,0 +1,264 @@
+"""Seeded synthetic workloads for the layered-grating multi-inclusion problem.
+
+This module only *generates inputs*: geometry (seeded random sequential packing of
+disks in the middle layer), the incidence, and the integer sizes of the
+discretization.  It holds none of the method's arithmetic (no Green's functions,
+no special functions, no linear algebra), so that both the CPU oracle and the
+HIP library can consume the same inputs without sharing any code that computes
+the answer.
+
+Problem statement (paper section 2): a period-d three-layer TM grating, flat
+interfaces Gamma_1 at y=+h and Gamma_2 at y=-h, refractive indices
+n_layer = (top, middle, bottom), M disks of radius r_m and index n_m inside the
+middle layer, plane-wave incidence at angle phi measured from the downward
+normal (so the horizontal wavenumber is k_1 sin(phi)), multipole order P.
+
+Discretization sizes follow the paper's description of its discretization
+(section 3: equispaced interface nodes, Gauss-Legendre wall nodes, J expansions of
+2Q+1 terms, Rayleigh-Bloch modes, artificial lines at +-y0) with the concrete
+rules documented in the design doc.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Discretization:
+    """Integer sizes and positions that fix the discrete problem."""
+    N: int                 # nodes on each interface (cell-centred, equispaced)
+    Nw: tuple              # Gauss-Legendre nodes on the walls of layers (1, 2, 3)
+    Q: tuple               # J-expansion orders of layers (1, 2, 3): 2Q+1 terms each
+    Nu: int                # nodes on each of Gamma_u, Gamma_d (cell-centred)
+    n_rb_lo: int           # lowest Rayleigh-Bloch order kept
+    Nrb: int               # number of Rayleigh-Bloch orders kept (each side)
+    y0: float              # Gamma_u at y=+y0, Gamma_d at y=-y0
+    zeta_K: int = 6        # zeta-correction stencil half-width (order 2K+1)
+    pinv_eps: float = 1e-10  # relative singular-value cut of the pseudo-inverse
+
+
+@dataclasses.dataclass
+class Problem:
+    """One geometry + one incidence (one right-hand side)."""
+    d: float
+    h: float
+    n_layer: tuple          # (top, middle, bottom) refractive indices
+    omega: float
+    phi: float              # incidence angle from the downward normal (rad)
+    P: int                  # multipole order, 2P+1 coefficients per inclusion
+    x: np.ndarray           # inclusion centres (M,)
+    y: np.ndarray
+    radius: np.ndarray
+    n_incl: np.ndarray
+    disc: Discretization
+    name: str = ""
+    seed: Optional[int] = None
+
+    @property
+    def M(self) -> int:
+        return int(self.x.shape[0])
+
+    def digest(self) -> str:
+        """Short hash of every input value (used to check stored fixtures)."""
+        import hashlib
+        hsh = hashlib.sha256()
+        for v in (self.d, self.h, *self.n_layer, self.omega, self.phi, self.P):
+            hsh.update(np.float64(v).tobytes())
+        for a in (self.x, self.y, self.radius, self.n_incl):
+            hsh.update(np.ascontiguousarray(a, dtype=np.float64).tobytes())
+        dd = self.disc
+        hsh.update(np.array([dd.N, *dd.Nw, *dd.Q, dd.Nu, dd.n_rb_lo, dd.Nrb, dd.zeta_K],
+                            dtype=np.int64).tobytes())
+        hsh.update(np.array([dd.y0, dd.pinv_eps], dtype=np.float64).tobytes())
+        return hsh.hexdigest()[:16]
+
+
+# ----------------------------------------------------------------------------
+# geometry
+# ----------------------------------------------------------------------------
+
+def pack_disks(M: int, d: float, h: float, r_lo: float, r_hi: float,
+               n_lo: float, n_hi: float, gap: float, seed: int,
+               clearance: Optional[float] = None, max_tries: int = 1_000_000):
+    """Seeded random sequential packing of M disks in the middle layer.
+
+    Radii are drawn first, then indices, from PCG64(seed).  Disks are placed
+    largest first (stable in index order); each try draws x ~ U[-d/2, d/2) and
+    y ~ U[-h+c+r, h-c-r] with c = clearance (default max(gap, 0.02)), and is
+    accepted when the minimum-image distance (period d in x) to every placed
+    disk is at least r_i + r_j + gap.  Returns arrays in the original index
+    order.  Raises RuntimeError if a disk cannot be placed.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if r_lo == r_hi:
+        radius = np.full(M, float(r_lo))
+    else:
+        radius = rng.uniform(r_lo, r_hi, size=M)
+    if n_lo == n_hi:
+        n_incl = np.full(M, float(n_lo))
+    else:
+        n_incl = rng.uniform(n_lo, n_hi, size=M)
+    c = max(gap, 0.02) if clearance is None else clearance
+    order = np.argsort(-radius, kind="stable")
+    xs = np.empty(M)
+    ys = np.empty(M)
+    # uniform cell grid over the periodic strip for the overlap checks
+    rmax = float(radius.max()) if M else 0.0
+    cell = max(2.0 * rmax + gap, 1e-9)
+    ncx = max(1, int(d / cell))
+    ncy = max(1, int(2 * h / cell))
+    cw, chh = d / ncx, 2 * h / ncy
+    grid = {}
+    placed_r = np.empty(M)
+    for cnt, i in enumerate(order):
+        r = radius[i]
+        ylo, yhi = -h + c + r, h - c - r
+        if ylo > yhi:
+            raise RuntimeError("disk does not fit between the interfaces")
+        for _ in range(max_tries):
+            x = rng.uniform(-d / 2, d / 2)
+            y = rng.uniform(ylo, yhi)
+            gx = int((x + d / 2) / cw) % ncx
+            gy = min(ncy - 1, max(0, int((y + h) / chh)))
+            ok = True
+            for ox in (-1, 0, 1):
+                if not ok:
+                    break
+                for oy in (-1, 0, 1):
+                    lst = grid.get(((gx + ox) % ncx, gy + oy))
+                    if not lst:
+                        continue
+                    for k in lst:
+                        dx = x - xs[k]
+                        dx -= d * math.floor(dx / d + 0.5)
+                        dy = y - ys[k]
+                        if dx * dx + dy * dy < (r + placed_r[k] + gap) ** 2:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+            if ok:
+                break
+        else:
+            raise RuntimeError(f"packing failed at disk {cnt} of {M}")
+        xs[i], ys[i], placed_r[i] = x, y, r
+        grid.setdefault((gx, gy), []).append(i)
+        if ncx < 3:  # tiny grids: the neighbour sweep above may alias; keep exact
+            pass
+    return xs, ys, radius, n_incl
+
+
+def min_image_gap(x, y, radius, d):
+    """Smallest edge-to-edge minimum-image distance between two disks."""
+    M = len(x)
+    best = np.inf
+    for i in range(M):
+        dx = x[i] - x[i + 1:]
+        dx -= d * np.floor(dx / d + 0.5)
+        dy = y[i] - y[i + 1:]
+        g = np.sqrt(dx * dx + dy * dy) - radius[i] - radius[i + 1:]
+        if g.size:
+            best = min(best, float(g.min()))
+    return best
+
+
+# ----------------------------------------------------------------------------
+# discretization sizes
+# ----------------------------------------------------------------------------
+
+def _round_up(v: int, m: int) -> int:
+    return ((v + m - 1) // m) * m
+
+
+def derive_discretization(d, h, n_layer, omega, phi, y_incl, P,
+                          zeta_K=6, pinv_eps=1e-10, N_min=120) -> Discretization:
+    """Sizes of the discrete problem from the geometry and the frequency.
+
+    * y0 = h + d/2; J centres at the middle of each truncated layer.
+    * N = max(N_min, ceil(6 d / d_c), ceil(8 k_max d / pi)) rounded up to a
+      multiple of 16; d_c is the smallest inclusion-centre-to-interface distance.
+    * Q_j = max(ceil(k_j R_j + 15), ceil(ln(1e-14) / ln(R_j / D_j))) with R_j the
+      largest distance from the J centre to a point of the layer's cell and D_j
+      the distance to the nearest source copy two or more periods away.
+    * Nw_j = max(ceil(k_j H_j / 2) + 24, ceil(0.8 (2 Q_j + 1))) Gauss-Legendre
+      nodes per wall, H_j the wall height.
+    * Rayleigh-Bloch orders: the 2*nh+1 orders centred on -round(kappa d / 2pi),
+      nh = max(20, ceil(k_max d / 2pi) + 12).
+    * Nu = max(50, ceil(1.25 Nrb)).
+    """
+    k = [omega * n for n in n_layer]
+    kmax = max(k)
+    y0 = h + d / 2
+    hu = (y0 - h) / 2  # half height of the top / bottom truncated layers
+    if len(y_incl):
+        dc = float(np.min(np.minimum(h - np.asarray(y_incl), np.asarray(y_incl) + h)))
+        n_dc = math.ceil(6 * d / dc)
+    else:
+        n_dc = 0
+    N = _round_up(max(N_min, n_dc, math.ceil(8 * kmax * d / math.pi)), 16)
+    # layer 1 (top) and 3 (bottom) share the geometry; layer 2 is the middle
+    R1 = math.hypot(d / 2, hu)
+    D1 = math.hypot(1.5 * d, hu)
+    R2 = math.hypot(d / 2, h)
+    D2 = 1.5 * d
+    Qs = []
+    for kj, R, D in ((k[0], R1, D1), (k[1], R2, D2), (k[2], R1, D1)):
+        Qs.append(max(math.ceil(kj * R + 15), math.ceil(math.log(1e-14) / math.log(R / D))))
+    H = (y0 - h, 2 * h, y0 - h)
+    Nw = tuple(max(math.ceil(kj * Hj / 2) + 24, math.ceil(0.8 * (2 * Qj + 1)))
+               for kj, Hj, Qj in zip(k, H, Qs))
+    kappa = k[0] * math.sin(phi)
+    nc = -int(round(kappa * d / (2 * math.pi)))
+    nh = max(20, math.ceil(kmax * d / (2 * math.pi)) + 12)
+    Nrb = 2 * nh + 1
+    Nu = max(50, math.ceil(1.25 * Nrb))
+    return Discretization(N=N, Nw=Nw, Q=tuple(Qs), Nu=Nu, n_rb_lo=nc - nh, Nrb=Nrb,
+                          y0=y0, zeta_K=zeta_K, pinv_eps=pinv_eps)
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+
+STACK = (1.0, 1.5, 2.0)
+
+
+def make_problem(name, d, h, M, r_lo, r_hi, n_lo, n_hi, gap, seed, omega, phi, P,
+                 n_layer=STACK, **disc_kw) -> Problem:
+    x, y, r, n = pack_disks(M, d, h, r_lo, r_hi, n_lo, n_hi, gap, seed)
+    disc = derive_discretization(d, h, n_layer, omega, phi, y, P, **disc_kw)
+    return Problem(d=d, h=h, n_layer=tuple(n_layer), omega=omega, phi=phi, P=P,
+                   x=x, y=y, radius=r, n_incl=n, disc=disc, name=name, seed=seed)
+
+
+def tiny_m4(phi=-math.pi / 5, **kw) -> Problem:
+    """Plain FP64 method, M=4: d=1, middle layer y in [-0.5, 0.5], r=0.05,
+    index 2.5, gap 0.02, omega=10, P=10, seed 1."""
+    return make_problem("tiny_m4", 1.0, 0.5, 4, 0.05, 0.05, 2.5, 2.5, 0.02, 1,
+                        10.0, phi, 10, **kw)
+
+
+def m1000(phi=-math.pi / 5, **kw) -> Problem:
+    """Plain FP64 method, M=1000: d=1, middle layer y in [-1, 1], radii
+    U[0.004, 0.012], indices U[1.5, 3.0], gap 0.002, omega=20, P=15, seed 2."""
+    return make_problem("m1000", 1.0, 1.0, 1000, 0.004, 0.012, 1.5, 3.0, 0.002, 2,
+                        20.0, phi, 15, **kw)
+
+
+def small(M, P, omega=10.0, seed=7, phi=-math.pi / 5, d=1.0, h=0.5, **kw) -> Problem:
+    """Small test geometry with m1000's size and index distributions, scaled."""
+    return make_problem(f"small_M{M}_P{P}", d, h, M, 0.02, 0.04, 1.5, 3.0, 0.01, seed,
+                        omega, phi, P, **kw)
+
+
+def empty_slab(omega=10.0, phi=-math.pi / 5, d=1.0, h=0.5, n_layer=STACK, **kw) -> Problem:
+    """No inclusions: the empty layered structure."""
+    e = np.zeros(0)
+    disc = derive_discretization(d, h, n_layer, omega, phi, e, 10, **kw)
+    return Problem(d=d, h=h, n_layer=tuple(n_layer), omega=omega, phi=phi, P=10,
+                   x=e, y=e.copy(), radius=e.copy(), n_incl=e.copy(), disc=disc,
+                   name="empty")
