@@ -1,0 +1,176 @@
+/*
+ * grating.h - C ABI of the MI355X (gfx950) solver for plane-wave scattering from a
+ * three-layer periodic grating with many circular inclusions in its middle layer.
+ *
+ * Method: J. Lai, M. Kobayashi, A. Barnett, "A fast and robust solver for the
+ * scattering from a layered periodic structure containing multi-particle
+ * inclusions".  Section 2 states the problem (TM Helmholtz, quasi-periodicity,
+ * Rayleigh-Bloch radiation conditions); section 3 the empty-structure system
+ * A alpha = f (eq. matA, Arhs); section 4 the single-inclusion scattering matrix
+ * S and the translation operator T (eqs. scat, trans, scattmatrix); section 5 the
+ * coupling blocks B, C (eqs. matB, matC), the pseudo-inverse A^+ (eq. applypA)
+ * and the left-preconditioned Schur system solved by GMRES; section 6 the flux
+ * identity and Bragg amplitudes.
+ *
+ * Conventions
+ *  - Every call returns grt_status; no C++ exception crosses the ABI.  On error
+ *    grt_error_message(ctx) describes the failure (owned by ctx, valid until the
+ *    next call on ctx).
+ *  - Coefficient vectors (beta, K beta, right-hand side) are complex FP64,
+ *    interleaved (re, im), laid out [M][2P+1] with the order n = -P..P at index
+ *    n + P.  They live in DEVICE memory owned by the caller, on the context's
+ *    device, contiguous; the library never frees caller memory.
+ *  - Host arrays passed to grt_set_problem are copied; the caller keeps them.
+ *  - Work is enqueued on the context stream.  grt_apply and grt_rhs are
+ *    asynchronous; grt_solve and grt_bragg synchronise before returning.
+ *  - One context per host thread.  Call order:
+ *      create -> set_problem -> build -> {apply | rhs | solve | bragg}* -> destroy;
+ *    set_problem invalidates build.
+ */
+#ifndef GRATING_H
+#define GRATING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GRT_OK = 0,
+  GRT_EINVAL = -1,  /* bad size or value (P outside [1,40], omega <= 0, |phi| >= pi/2, NaN...) */
+  GRT_EGEOM = -2,   /* disks overlap (minimum image) or touch an interface            */
+  GRT_ENOMEM = -3,  /* device allocation failed                                       */
+  GRT_EHIP = -4,    /* a HIP / rocSOLVER call failed                                  */
+  GRT_ENOCONV = -5, /* GMRES did not reach the tolerance; beta and stats still written */
+  GRT_ESTATE = -6,  /* call out of order (e.g. apply before build)                     */
+  GRT_EUNSUP = -7   /* unsupported option                                             */
+} grt_status;
+
+typedef enum { GRT_FP64 = 0, GRT_FP32 = 1 } grt_precision;
+
+typedef struct grt_ctx grt_ctx;
+
+/* Layered structure and its discretization (paper sec. 3).  Flat interfaces
+ * Gamma_1: y = +h and Gamma_2: y = -h; artificial lines Gamma_u, Gamma_d at +-y0;
+ * period d.  Discretization: N equispaced (cell-centred) nodes per interface,
+ * Nw[l] Gauss-Legendre nodes on the walls of layer l (0 top, 1 middle, 2 bottom),
+ * J expansions of orders -Q[l]..Q[l] about (0, +-(h+y0)/2) and (0, 0), Nu nodes on
+ * Gamma_u and on Gamma_d, Rayleigh-Bloch orders n_rb_lo .. n_rb_lo + Nrb - 1,
+ * zeta-corrected trapezoid stencils of half-width zeta_K, and the pseudo-inverse
+ * singular-value cut pinv_eps (relative to the largest singular value). */
+typedef struct {
+  double d, h, y0;
+  double n_layer[3]; /* refractive indices: top (incidence side), middle, bottom */
+  int N;
+  int Nw[3];
+  int Q[3];
+  int Nu;
+  int n_rb_lo, Nrb;
+  int zeta_K;
+  double pinv_eps;
+} grt_layers;
+
+/* M disks (paper sec. 4, 5): centres (x, y), radius and refractive index. */
+typedef struct {
+  int64_t M;
+  const double *x, *y, *radius, *n_incl;
+} grt_inclusions;
+
+/* Plane wave of frequency omega (k_l = omega * n_l), angle phi from the downward
+ * normal (horizontal wavenumber k_1 sin phi), TM polarisation; multipole order P
+ * (2P+1 coefficients per inclusion). */
+typedef struct {
+  double omega;
+  double phi;
+  int P;
+} grt_incidence;
+
+typedef struct {
+  double tol;      /* stop when ||b - K x|| / ||b|| <= tol                   */
+  int maxit;       /* total Arnoldi steps                                    */
+  int restart;     /* Krylov dimension per cycle                             */
+  int use_x0;      /* 1: beta_dev holds the initial guess on entry           */
+} grt_solve_opts;
+
+typedef struct {
+  int iters;            /* Arnoldi steps taken                               */
+  int cycles;           /* restart cycles                                    */
+  double rel_resid;     /* true relative residual ||b - K x|| / ||b|| (FP64)  */
+  double seconds;       /* wall time of the solve                            */
+} grt_solve_stats;
+
+typedef struct {
+  int64_t M;
+  int P;
+  int64_t n_beta;   /* M (2P+1): complex entries of a coefficient vector     */
+  int64_t n_rows;   /* rows of A                                             */
+  int64_t n_alpha;  /* columns of A                                          */
+  int64_t rank;     /* singular values kept by the pseudo-inverse            */
+  int Nrb;
+} grt_sizes;
+
+/* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = a stream the context creates and owns). */
+grt_status grt_create(grt_ctx** out, int hip_device, void* hip_stream);
+grt_status grt_destroy(grt_ctx* ctx);
+const char* grt_error_message(const grt_ctx* ctx);
+
+/* Copy and validate the problem (sec. 2).  GRT_EGEOM if two disks overlap under
+ * the minimum image in x or a disk crosses an interface. */
+grt_status grt_set_problem(grt_ctx* ctx, const grt_layers* lay, const grt_inclusions* inc,
+                           const grt_incidence* wave);
+
+/* Build everything the apply needs, on the device: the Mie diagonal S (sec. 4.1),
+ * the matrix A (sec. 3, eq. matA) with zeta-corrected self blocks, its SVD and the
+ * truncated pseudo-inverse factors (eq. applypA), the L2L table and f (eq. Arhs). */
+grt_status grt_build(grt_ctx* ctx);
+
+grt_status grt_query(const grt_ctx* ctx, grt_sizes* out);
+
+/* y = K x with K = I - S T + S B_phys A^+ C, the left-preconditioned Schur
+ * operator of sec. 5 (B_phys = -B of the paper).  x, y: device [M][2P+1] complex
+ * FP64, may not alias.  precision must be GRT_FP64. */
+grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision);
+
+/* Diagnostic parts of the apply: y = T x (translation among inclusions and their
+ * near copies, sec. 4.2 / eq. repre3_mod) and y = B_phys A^+ C x (the low-rank
+ * layer correction, sec. 5).  Same layout as grt_apply. */
+grt_status grt_apply_T(grt_ctx* ctx, const void* x_dev, void* y_dev);
+grt_status grt_apply_lowrank(grt_ctx* ctx, const void* x_dev, void* y_dev);
+
+/* b = S B_phys A^+ f, the right-hand side of the reduced system (device). */
+grt_status grt_rhs(grt_ctx* ctx, void* b_dev);
+
+/* Solve K beta = b by restarted GMRES in FP64 on the device (sec. 5).  beta_dev
+ * (device) receives the solution; with opts->use_x0 it holds the initial guess
+ * on entry.  GRT_ENOCONV if tol is not reached (beta and stats still written). */
+grt_status grt_solve(grt_ctx* ctx, const grt_solve_opts* opts, void* beta_dev,
+                     grt_solve_stats* stats);
+
+/* Bragg amplitudes (sec. 2 eq. rad1/rad2, sec. 6): from beta (device) form
+ * alpha = A^+ (f - C beta) and return, for each of the Nrb orders (host arrays of
+ * length >= Nrb): orders[i], c[2i..2i+1], d[2i..2i+1] (re, im), the reflected and
+ * transmitted energy fractions R[i], T[i] (zero for evanescent orders) and the
+ * flux error |sum R + sum T - 1|. */
+grt_status grt_bragg(grt_ctx* ctx, const void* beta_dev, int64_t cap, int* orders, double* c,
+                     double* d, double* R, double* T, double* flux_err);
+
+/* Copy the equilibrated matrix A (column-major [n_alpha][n_rows] complex) and its
+ * column scales to host buffers (diagnostics / tests). */
+grt_status grt_get_A(grt_ctx* ctx, double* A_host, double* colscale_host);
+
+/* Copy the Mie diagonal [M][2P+1] complex to a host buffer (diagnostics / tests). */
+grt_status grt_get_mie(grt_ctx* ctx, double* s_host);
+
+/* Kernel timing for measurement tools.  While enabled, every launch of the
+ * translation kernel (the dense part of K, sec. 4.2) is bracketed by HIP events on
+ * the context stream.  grt_profile_read synchronises the stream, returns the total
+ * milliseconds and the number of launches since the previous read, and resets them. */
+grt_status grt_profile_enable(grt_ctx* ctx, int enable);
+grt_status grt_profile_read(grt_ctx* ctx, double* m2l_ms_total, int64_t* m2l_launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRATING_H */

@@ -1,0 +1,480 @@
+// The apply of the reduced operator K = I - S T + S B_phys A^+ C (paper sec. 5).
+//
+// Kernels, in launch order:
+//  m2l_kernel<P>     alpha^T_j[n] = sum_m sum_l alpha^l sum_nu t^{(jml)}_{nu-n} x_m[nu]
+//                    with t_q = H_q(k2 rho) e^{i q phi} (Graf, sec. 4.2) for the three
+//                    near copies l = -1, 0, 1 (eq. repre3_mod), (j,m,l) != (j,j,0).
+//                    The three copies are summed at the generator level, so one
+//                    Toeplitz product is done per (j, m).  H_0, H_1 come from
+//                    dev_bessel.h and H_q by upward recurrence; e^{iq phi} by powers.
+//  cx_kernel         g = C x: multipole fields at the Gamma_1 / Gamma_2 nodes (value,
+//                    d/dy, three copies) and at the middle walls (value, d/dx,
+//                    cancelled form alpha^2 Phi(L-d) - alpha^{-1} Phi(L+2d)).
+//  gemv (setup.hip)  t = Sigma^+ U^* g, w = E V t  (eq. applypA)
+//  bx_kernel<P>      alpha^L_j[n] from the interface densities (P2L by Graf for H_0)
+//  l2l_kernel        alpha^L_j[n] += sum_q a2_q J_{q-n}(k2 rho_j) e^{i(q-n) phi_j} (L2L)
+//  combine_kernel    y = x - s o (alpha^T - alpha^L)
+#include <algorithm>
+#include <cstdio>
+
+#include "dev_bessel.h"
+#include "grt_internal.h"
+
+namespace {
+
+constexpr int M2L_THREADS = 64;
+constexpr int M2L_MAXCHUNK = 32;
+
+template <int P>
+__global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restrict__ cx,
+                                                          const double* __restrict__ cy,
+                                                          const cd* __restrict__ x, cd* partial,
+                                                          int M, int chunk, double k, double d,
+                                                          cd alpha, cd alpha_inv) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ cd sx[M2L_MAXCHUNK * NB];
+  __shared__ double scx[M2L_MAXCHUNK], scy[M2L_MAXCHUNK];
+  const int j = blockIdx.x * M2L_THREADS + threadIdx.x;
+  const int m0 = blockIdx.y * chunk;
+  const int cnt = min(chunk, M - m0);
+  for (int t = threadIdx.x; t < cnt * NB; t += M2L_THREADS) sx[t] = x[(size_t)m0 * NB + t];
+  for (int t = threadIdx.x; t < cnt; t += M2L_THREADS) {
+    scx[t] = cx[m0 + t];
+    scy[t] = cy[m0 + t];
+  }
+  __syncthreads();
+  const bool live = j < M;
+  const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
+  cd acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
+  const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
+  for (int mm = 0; mm < cnt; ++mm) {
+    const int m = m0 + mm;
+    const cd* b = sx + mm * NB;
+    cd hp[3], hc[3], cc[3], cq[3];
+    double rz2[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      double dx = xj - scx[mm] - (l - 1) * d;
+      double dy = yj - scy[mm];
+      bool self = (j == m) && (l == 1);
+      double r = sqrt(dx * dx + dy * dy);
+      if (self || !live) r = 1.0;
+      double z = k * r;
+      double ir = 1.0 / r;
+      cd h0, h1;
+      hankel01(z, h0, h1);
+      cd w = (self || !live) ? cd{0.0, 0.0} : wl[l];
+      hp[l] = w * h0;
+      hc[l] = w * h1;
+      cc[l] = cd{dx * ir, dy * ir};
+      cq[l] = cc[l];
+      rz2[l] = 2.0 / z;
+    }
+    {
+      cd t0 = hp[0] + hp[1] + hp[2];
+#pragma unroll
+      for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
+    }
+#pragma unroll
+    for (int q = 1; q <= 2 * P; ++q) {
+      cd tp{0.0, 0.0}, tm{0.0, 0.0};
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        // hc * cq and hc * conj(cq) share the four real products
+        double ac = hc[l].r * cq[l].r, bd = hc[l].i * cq[l].i;
+        double ad = hc[l].r * cq[l].i, bc = hc[l].i * cq[l].r;
+        tp.r += ac - bd;
+        tp.i += ad + bc;
+        tm.r += ac + bd;
+        tm.i += bc - ad;
+      }
+      if (q & 1) tm = -tm;  // H_{-q} = (-1)^q H_q
+      // acc[n] += t_q x[n+q]  (n = -P..P-q),  acc[n] += t_{-q} x[n-q]  (n = -P+q..P)
+#pragma unroll
+      for (int n = 0; n + q < NB; ++n) cmac(acc[n], tp, b[n + q]);
+#pragma unroll
+      for (int n = q; n < NB; ++n) cmac(acc[n], tm, b[n - q]);
+      if (q < 2 * P) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          cd hn = (q * rz2[l]) * hc[l] - hp[l];
+          hp[l] = hc[l];
+          hc[l] = hn;
+          cq[l] = cq[l] * cc[l];
+        }
+      }
+    }
+  }
+  if (live) {
+    cd* out = partial + ((size_t)blockIdx.y * M + j) * NB;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) out[n] = acc[n];
+  }
+}
+
+// Field of all multipoles (and their copies) at the C targets.
+//   target t < N: Gamma_1 node, t < 2N: Gamma_2 node (value, d/dy over 3 copies),
+//   t < 2N + Nw2: middle wall node (value, d/dx, cancelled two-term form).
+// partial[chunk][t][0..1] = (value, derivative)
+__global__ void __launch_bounds__(64) cx_kernel(DevGeom g, const double* __restrict__ cx,
+                                                const double* __restrict__ cy,
+                                                const cd* __restrict__ x, cd* partial, int chunk) {
+  const int P = g.P, NB = 2 * P + 1;
+  const int nt = 2 * g.N + g.Nw[1];
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int m0 = blockIdx.y * chunk;
+  int m1 = min(g.M, m0 + chunk);
+  if (t >= nt) return;
+  double tx[3], ty;
+  cd w[3];
+  int nimg;
+  bool wall = t >= 2 * g.N;
+  if (!wall) {
+    int i = t % g.N;
+    double x0 = -0.5 * g.d + (i + 0.5) * g.hs;
+    ty = (t < g.N) ? g.h : -g.h;
+    // copies of the source at x_m + l d are equivalent to targets at x - l d
+    tx[0] = x0 + g.d; w[0] = g.alpha_inv;  // l = -1
+    tx[1] = x0;       w[1] = cd{1.0, 0.0};
+    tx[2] = x0 - g.d; w[2] = g.alpha;      // l = +1
+    nimg = 3;
+  } else {
+    ty = g.yw[1][t - 2 * g.N];
+    tx[0] = -1.5 * g.d; w[0] = g.alpha * g.alpha;
+    tx[1] = 1.5 * g.d;  w[1] = -g.alpha_inv;
+    nimg = 2;
+  }
+  const double k = g.k[1];
+  cd val{0, 0}, A{0, 0}, B{0, 0};  // A = sum x[n] F_{n-1}, B = sum x[n] F_{n+1}
+  for (int m = m0; m < m1; ++m) {
+    const cd* b = x + (size_t)m * NB;
+    for (int im = 0; im < nimg; ++im) {
+      double vx = tx[im] - cx[m], vy = ty - cy[m];
+      double r = sqrt(vx * vx + vy * vy);
+      double z = k * r;
+      cd e{vx / r, vy / r};
+      cd hprev, hcur;
+      hankel01(z, hprev, hcur);
+      // order 0
+      cd sv{0, 0}, sa{0, 0}, sb{0, 0};
+      cd F0 = hprev;
+      cmac(sv, F0, b[P]);
+      if (P >= 1) { cmac(sa, F0, b[P + 1]); cmac(sb, F0, b[P - 1]); }
+      cd ep = e;
+      double rz2 = 2.0 / z;
+      for (int mo = 1; mo <= P + 1; ++mo) {
+        // hcur = H_mo
+        cd Fp = hcur * ep;                   // F_mo
+        cd Fm = hcur * conj(ep);             // F_{-mo} = (-1)^mo H_mo e^{-i mo theta}
+        if (mo & 1) Fm = -Fm;
+        if (mo <= P) { cmac(sv, Fp, b[P + mo]); cmac(sv, Fm, b[P - mo]); }
+        // A: x[n] F_{n-1}: F_mo pairs with n = mo + 1, F_{-mo} with n = 1 - mo
+        if (mo + 1 <= P) cmac(sa, Fp, b[P + mo + 1]);
+        if (1 - mo >= -P) cmac(sa, Fm, b[P + 1 - mo]);
+        // B: x[n] F_{n+1}: F_mo pairs with n = mo - 1, F_{-mo} with n = -mo - 1
+        if (mo - 1 <= P) cmac(sb, Fp, b[P + mo - 1]);
+        if (-mo - 1 >= -P) cmac(sb, Fm, b[P - mo - 1]);
+        cd hn = (mo * rz2) * hcur - hprev;
+        hprev = hcur;
+        hcur = hn;
+        ep = ep * e;
+      }
+      val += w[im] * sv;
+      A += w[im] * sa;
+      B += w[im] * sb;
+    }
+  }
+  // derivative: d/dx = (k/2)(A - B), d/dy = (ik/2)(A + B)
+  cd der = wall ? (0.5 * k) * (A - B) : times_i((0.5 * k) * (A + B));
+  cd* o = partial + ((size_t)blockIdx.y * nt + t) * 2;
+  o[0] = val;
+  o[1] = der;
+}
+
+// g (rows Gamma_1 v/n, Gamma_2 v/n, wall-2 v/d) from the chunk partials.
+__global__ void cx_reduce_kernel(DevGeom g, const cd* partial, int nchunks, cd* gv) {
+  const int nt = 2 * g.N + g.Nw[1];
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  cd v{0, 0}, dv{0, 0};
+  for (int c = 0; c < nchunks; ++c) {
+    v += partial[((size_t)c * nt + t) * 2];
+    dv += partial[((size_t)c * nt + t) * 2 + 1];
+  }
+  const int N = g.N;
+  if (t < N) {  // Gamma_1: row is u_1 - u_2, the inclusions live in layer 2
+    gv[g.row_off[RB_G1V] + t] = -v;
+    gv[g.row_off[RB_G1N] + t] = -dv;
+  } else if (t < 2 * N) {
+    gv[g.row_off[RB_G2V] + t - N] = v;
+    gv[g.row_off[RB_G2N] + t - N] = dv;
+  } else {
+    gv[g.row_off[RB_W2V] + t - 2 * N] = v;
+    gv[g.row_off[RB_W2D] + t - 2 * N] = dv;
+  }
+}
+
+// Incoming coefficients at inclusion j from the interface densities (P2L):
+//   alpha_j[n] += (i/4) hs alpha^l [G_n sigma - (ik/2)(G_{n-1} + G_{n+1}) mu],
+//   G_n = H_n(k|v|) e^{-in theta_v}, v = node copy - c_j.
+// Sources: 2 lines x N nodes x 3 copies = 6N node-copies, chunked over blockIdx.y.
+template <int P>
+__global__ void __launch_bounds__(64) bx_kernel(DevGeom g, const double* __restrict__ cx,
+                                                const double* __restrict__ cy,
+                                                const cd* __restrict__ w, cd* partial, int chunk) {
+  constexpr int NB = 2 * P + 1;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s0 = blockIdx.y * chunk;
+  const int s1 = min(6 * g.N, s0 + chunk);
+  const bool live = j < g.M;
+  const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
+  const double k = g.k[1];
+  cd acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
+  for (int sidx = s0; sidx < s1; ++sidx) {
+    int line = sidx / (3 * g.N);
+    int rem = sidx - line * 3 * g.N;
+    int l = rem / g.N - 1;
+    int i = rem - (l + 1) * g.N;
+    double sxp = -0.5 * g.d + (i + 0.5) * g.hs + l * g.d;
+    double syp = line == 0 ? g.h : -g.h;
+    cd mu = w[g.col_off[line == 0 ? CB_MU1 : CB_MU2] + i];
+    cd sg = w[g.col_off[line == 0 ? CB_SIG1 : CB_SIG2] + i];
+    cd ph = (l == 0) ? cd{1.0, 0.0} : (l > 0 ? g.alpha : g.alpha_inv);
+    cd pre = times_i((0.25 * g.hs) * ph);  // (i/4) hs alpha^l
+    cd csig = pre * sg;
+    cd cmu = pre * times_i((-0.5 * k) * mu);  // -(ik/2) mu * pre
+    double vx = sxp - xj, vy = syp - yj;
+    double r = sqrt(vx * vx + vy * vy);
+    double z = k * r;
+    cd e{vx / r, vy / r};
+    cd ec = conj(e);
+    cd hprev, hcur;
+    hankel01(z, hprev, hcur);
+    // G_n for n = 0..P+1 (positive) and negative via (-1)^n H_n e^{in theta}
+    cd Gp[P + 2], Gm[P + 2];
+    Gp[0] = hprev;
+    Gm[0] = hprev;
+    cd ep = ec, em = e;
+    double rz2 = 2.0 / z;
+#pragma unroll
+    for (int n = 1; n <= P + 1; ++n) {
+      Gp[n] = hcur * ep;
+      Gm[n] = (n & 1) ? -(hcur * em) : hcur * em;
+      cd hn = (n * rz2) * hcur - hprev;
+      hprev = hcur;
+      hcur = hn;
+      ep = ep * ec;
+      em = em * e;
+    }
+#pragma unroll
+    for (int n = -P; n <= P; ++n) {
+      cd G = n >= 0 ? Gp[n] : Gm[-n];
+      cd Gl = (n - 1) >= 0 ? Gp[n - 1] : Gm[1 - n];
+      cd Gr = (n + 1) >= 0 ? Gp[n + 1] : Gm[-n - 1];
+      cmac(acc[n + P], csig, G);
+      cmac(acc[n + P], cmu, Gl + Gr);
+    }
+  }
+  if (live) {
+    cd* out = partial + ((size_t)blockIdx.y * g.M + j) * NB;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) out[n] = acc[n];
+  }
+}
+
+// L2L: out[j][n] = sum_q a2_q E_j[q - n], E_j[m] = J_m(k2 rho_j) e^{i m phi_j}.
+__global__ void l2l_kernel(int M, int P, int Q2, const cd* __restrict__ E,
+                           const cd* __restrict__ a2, cd* out) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  int NB = 2 * P + 1;
+  if (idx >= M * NB) return;
+  int j = idx / NB, n = idx - j * NB - P;
+  int L = Q2 + P;
+  const cd* e = E + (size_t)j * (2 * L + 1) + L;
+  cd acc{0, 0};
+  for (int q = -Q2; q <= Q2; ++q) cmac(acc, a2[q + Q2], e[q - n]);
+  out[idx] = acc;
+}
+
+// y = x - s o (sum_c pT[c] - sum_c pB[c] - pL); any of the parts may be absent.
+__global__ void combine_kernel(int nbeta, const cd* x, const cd* s, const cd* pT, int nT,
+                               const cd* pB, int nB, const cd* pL, cd* y, int mode) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbeta) return;
+  cd t{0, 0}, b{0, 0};
+  for (int c = 0; c < nT; ++c) t += pT[(size_t)c * nbeta + i];
+  for (int c = 0; c < nB; ++c) b += pB[(size_t)c * nbeta + i];
+  if (pL) b += pL[i];
+  if (mode == 0) {  // full K
+    y[i] = x[i] - s[i] * (t - b);
+  } else if (mode == 1) {  // T x only
+    y[i] = t;
+  } else if (mode == 2) {  // B A^+ C x only
+    y[i] = b;
+  } else {  // rhs: s o (B part)
+    y[i] = s[i] * b;
+  }
+}
+
+// Event pair for timing one translation launch (when profiling is on).
+hipEvent_t* prof_pair(grt_ctx* c) {
+  if (!c->prof) return nullptr;
+  if (c->prof_used + 2 > c->prof_ev.size()) {
+    for (int t = 0; t < 64; ++t) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      c->prof_ev.push_back(e);
+    }
+  }
+  hipEvent_t* p = &c->prof_ev[c->prof_used];
+  c->prof_used += 2;
+  return p;
+}
+
+template <int P>
+void launch_m2l(grt_ctx* c, const cd* x) {
+  dim3 grid((unsigned)((c->M + M2L_THREADS - 1) / M2L_THREADS), c->m2l_nchunks);
+  hipEvent_t* ev = prof_pair(c);
+  if (ev) hipEventRecord(ev[0], c->stream);
+  m2l_kernel<P><<<grid, M2L_THREADS, 0, c->stream>>>(c->d_cx, c->d_cy, x, c->d_pT, (int)c->M,
+                                                     c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
+                                                     c->g.alpha_inv);
+  if (ev) hipEventRecord(ev[1], c->stream);
+}
+
+template <int P>
+void launch_bx(grt_ctx* c, const cd* w) {
+  dim3 grid((unsigned)((c->M + 63) / 64), c->b_nchunks);
+  bx_kernel<P><<<grid, 64, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, w, c->d_pB, c->b_chunk);
+}
+
+#define GRT_P_DISPATCH(FN, P, ...)                        \
+  switch (P) {                                            \
+    case 1: FN<1>(__VA_ARGS__); break;                    \
+    case 2: FN<2>(__VA_ARGS__); break;                    \
+    case 3: FN<3>(__VA_ARGS__); break;                    \
+    case 4: FN<4>(__VA_ARGS__); break;                    \
+    case 5: FN<5>(__VA_ARGS__); break;                    \
+    case 6: FN<6>(__VA_ARGS__); break;                    \
+    case 8: FN<8>(__VA_ARGS__); break;                    \
+    case 10: FN<10>(__VA_ARGS__); break;                  \
+    case 12: FN<12>(__VA_ARGS__); break;                  \
+    case 15: FN<15>(__VA_ARGS__); break;                  \
+    case 20: FN<20>(__VA_ARGS__); break;                  \
+    default: return set_err(c, GRT_EUNSUP, "multipole order P not compiled in"); \
+  }
+
+}  // namespace
+
+bool supported_P(int P) {
+  switch (P) {
+    case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 12: case 15: case 20:
+      return true;
+    default:
+      return false;
+  }
+}
+
+grt_status apply_alloc(grt_ctx* c) {
+  const int64_t M = c->M;
+  // vectors of the low-rank path: also needed without inclusions (Bragg amplitudes)
+  GRT_HIP(c, hipMalloc(&c->d_gvec, sizeof(cd) * (size_t)c->n_g));
+  GRT_HIP(c, hipMalloc(&c->d_tvec, sizeof(cd) * (size_t)std::max(1, c->rank)));
+  GRT_HIP(c, hipMalloc(&c->d_wvec, sizeof(cd) * (size_t)c->n_b));
+  if (M == 0) return GRT_OK;
+  int chunk = c->m2l_chunk;
+  if (chunk > M2L_MAXCHUNK) chunk = M2L_MAXCHUNK;
+  c->m2l_chunk = chunk;
+  c->m2l_nchunks = (int)((M + chunk - 1) / chunk);
+  const int nt = 2 * c->g.N + c->g.Nw[1];
+  c->c_nchunks = (int)((M + c->c_chunk - 1) / c->c_chunk);
+  c->b_nchunks = (6 * c->g.N + c->b_chunk - 1) / c->b_chunk;
+  GRT_HIP(c, hipMalloc(&c->d_pT, sizeof(cd) * (size_t)c->m2l_nchunks * c->n_beta));
+  GRT_HIP(c, hipMalloc(&c->d_pC, sizeof(cd) * (size_t)c->c_nchunks * nt * 2));
+  GRT_HIP(c, hipMalloc(&c->d_pB, sizeof(cd) * (size_t)c->b_nchunks * c->n_beta));
+  GRT_HIP(c, hipMalloc(&c->d_pL, sizeof(cd) * (size_t)c->n_beta));
+  return GRT_OK;
+}
+
+// w = A^+ g on the prefix entries B reads, then alpha^L into pB (partials) and pL.
+static grt_status lowrank_tail(grt_ctx* c, const cd* gvec) {
+  hipStream_t s = c->stream;
+  launch_gemv_rows(s, c->d_W1, gvec, c->d_tvec, c->rank, c->n_g);
+  launch_gemv_rows(s, c->d_W2, c->d_tvec, c->d_wvec, c->n_b, c->rank);
+  GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec);
+  int NB = c->nb;
+  int tot = (int)(c->M * NB);
+  l2l_kernel<<<(tot + 255) / 256, 256, 0, s>>>((int)c->M, c->P, c->g.Q[1], c->d_l2l,
+                                               c->d_wvec + c->g.col_off[CB_A2], c->d_pL);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
+
+static grt_status cx_apply(grt_ctx* c, const cd* x) {
+  const int nt = 2 * c->g.N + c->g.Nw[1];
+  dim3 grid((nt + 63) / 64, c->c_nchunks);
+  cx_kernel<<<grid, 64, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, x, c->d_pC, c->c_chunk);
+  cx_reduce_kernel<<<(nt + 255) / 256, 256, 0, c->stream>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
+
+static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode) {
+  if (c->M == 0) return GRT_OK;
+  hipStream_t s = c->stream;
+  bool needT = (mode == 0 || mode == 1);
+  bool needB = (mode == 0 || mode == 2);
+  if (needT) GRT_P_DISPATCH(launch_m2l, c->P, c, x);
+  if (needB) {
+    grt_status st = cx_apply(c, x);
+    if (st != GRT_OK) return st;
+    st = lowrank_tail(c, c->d_gvec);
+    if (st != GRT_OK) return st;
+  }
+  int n = (int)c->n_beta;
+  combine_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, x, c->d_mie, c->d_pT, needT ? c->m2l_nchunks : 0,
+                                                 c->d_pB, needB ? c->b_nchunks : 0,
+                                                 needB ? c->d_pL : nullptr, y, mode);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
+
+grt_status apply_K(grt_ctx* c, const cd* x, cd* y) { return run_apply(c, x, y, 0); }
+grt_status apply_T_only(grt_ctx* c, const cd* x, cd* y) { return run_apply(c, x, y, 1); }
+grt_status apply_lowrank_only(grt_ctx* c, const cd* x, cd* y) { return run_apply(c, x, y, 2); }
+
+grt_status rhs_b(grt_ctx* c, cd* b) {
+  if (c->M == 0) return GRT_OK;
+  grt_status st = lowrank_tail(c, c->d_f);
+  if (st != GRT_OK) return st;
+  int n = (int)c->n_beta;
+  combine_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(n, nullptr, c->d_mie, nullptr, 0, c->d_pB,
+                                                         c->b_nchunks, c->d_pL, b, 3);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
+
+__global__ void sub_kernel(int n, const cd* a, const cd* b, cd* o) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] - (b ? b[i] : cd{0, 0});
+}
+
+// c and d blocks of alpha = A^+ (f - C beta) into out[0 .. 2 Nrb).
+grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out) {
+  hipStream_t s = c->stream;
+  if (c->M > 0) {
+    grt_status st = cx_apply(c, beta);
+    if (st != GRT_OK) return st;
+  }
+  // g = f - C beta (prefix rows; both vanish elsewhere)
+  sub_kernel<<<(c->n_g + 255) / 256, 256, 0, s>>>(c->n_g, c->d_f, c->M > 0 ? c->d_gvec : nullptr,
+                                                   c->d_gvec);
+  launch_gemv_rows(s, c->d_W1, c->d_gvec, c->d_tvec, c->rank, c->n_g);
+  launch_gemv_rows(s, c->d_W3, c->d_tvec, out, 2 * c->g.Nrb, c->rank);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}

@@ -1,0 +1,413 @@
+// C ABI of the grating library: context, validation, orchestration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "grt_internal.h"
+
+grt_status set_err(grt_ctx* c, grt_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define GRT_CHECK_CTX(c)                   \
+  do {                                     \
+    if (!(c)) return GRT_EINVAL;           \
+    (c)->err.clear();                      \
+  } while (0)
+
+namespace {
+
+void free_all(grt_ctx* c) {
+  void* bufs[] = {c->d_cx, c->d_cy, c->d_rad, c->d_kp, c->d_yw, c->d_wcorr, c->d_A,
+                  c->d_colscale, c->d_sv, c->d_U, c->d_VH, c->d_W1, c->d_W2, c->d_W3,
+                  c->d_mie, c->d_l2l, c->d_f, c->d_pT, c->d_pC, c->d_pB, c->d_pL,
+                  c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_cs, c->d_sn,
+                  c->d_gv, c->d_y, c->d_scal, c->d_dotpart};
+  for (void* p : bufs)
+    if (p) hipFree(p);
+  c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal = nullptr;
+  c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_mie = c->d_l2l =
+      c->d_f = c->d_pT = c->d_pC = c->d_pB = c->d_pL = c->d_gvec = c->d_tvec = c->d_wvec =
+          c->d_V = c->d_H = c->d_cs = c->d_sn = c->d_gv = c->d_y = c->d_dotpart = nullptr;
+  c->krylov_restart = 0;
+  c->built = false;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+}  // namespace
+
+extern "C" {
+
+grt_status grt_create(grt_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return GRT_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GRT_EHIP;
+  if (hip_device < 0 || hip_device >= ndev) return GRT_EINVAL;
+  grt_ctx* c = new (std::nothrow) grt_ctx();
+  if (!c) return GRT_ENOMEM;
+  c->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete c;
+    return GRT_EHIP;
+  }
+  if (hip_stream) {
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return GRT_EHIP;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return GRT_OK;
+}
+
+grt_status grt_destroy(grt_ctx* c) {
+  if (!c) return GRT_OK;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_all(c);
+  for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
+  if (c->h_pinned) hipHostFree(c->h_pinned);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+  return GRT_OK;
+}
+
+const char* grt_error_message(const grt_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusions* inc,
+                           const grt_incidence* wave) {
+  GRT_CHECK_CTX(c);
+  if (!lay || !inc || !wave) return set_err(c, GRT_EINVAL, "null argument");
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_all(c);
+  c->have_problem = false;
+  const grt_layers& L = *lay;
+  if (!finite_pos(L.d) || !finite_pos(L.h) || !(std::isfinite(L.y0) && L.y0 > L.h))
+    return set_err(c, GRT_EINVAL, "need d > 0, h > 0, y0 > h");
+  for (int l = 0; l < 3; ++l) {
+    if (!finite_pos(L.n_layer[l])) return set_err(c, GRT_EINVAL, "layer indices must be > 0");
+    if (L.Nw[l] < 1 || L.Nw[l] > 100000) return set_err(c, GRT_EINVAL, "bad wall node count");
+    if (L.Q[l] < 0 || L.Q[l] > 400) return set_err(c, GRT_EINVAL, "J order Q must be in [0, 400]");
+  }
+  if (L.zeta_K < 1 || L.zeta_K > 16) return set_err(c, GRT_EINVAL, "zeta_K must be in [1, 16]");
+  if (L.N < 2 * L.zeta_K + 1 || L.N > 1000000) return set_err(c, GRT_EINVAL, "N too small for the stencil");
+  if (L.Nu < 1 || L.Nrb < 1 || L.Nrb > 100000) return set_err(c, GRT_EINVAL, "bad Nu / Nrb");
+  if (!(L.pinv_eps > 0 && L.pinv_eps < 1)) return set_err(c, GRT_EINVAL, "pinv_eps must be in (0, 1)");
+  if (!finite_pos(wave->omega)) return set_err(c, GRT_EINVAL, "omega must be > 0");
+  if (!std::isfinite(wave->phi) || std::fabs(wave->phi) >= M_PI / 2)
+    return set_err(c, GRT_EINVAL, "|phi| must be < pi/2");
+  if (wave->P < 1 || wave->P > 40) return set_err(c, GRT_EINVAL, "P must be in [1, 40]");
+  if (!supported_P(wave->P)) return set_err(c, GRT_EUNSUP, "multipole order P not compiled in");
+  const int64_t M = inc->M;
+  if (M < 0 || M > 10000000) return set_err(c, GRT_EINVAL, "bad M");
+  if (M > 0 && (!inc->x || !inc->y || !inc->radius || !inc->n_incl))
+    return set_err(c, GRT_EINVAL, "null inclusion arrays");
+  if (L.Q[1] + wave->P + 1 > 511) return set_err(c, GRT_EINVAL, "Q[1] + P too large");
+  c->hx.assign(inc->x, inc->x + M);
+  c->hy.assign(inc->y, inc->y + M);
+  c->hr.assign(inc->radius, inc->radius + M);
+  c->hn.assign(inc->n_incl, inc->n_incl + M);
+  for (int64_t m = 0; m < M; ++m) {
+    if (!std::isfinite(c->hx[m]) || !std::isfinite(c->hy[m]) || !finite_pos(c->hr[m]) ||
+        !finite_pos(c->hn[m]))
+      return set_err(c, GRT_EINVAL, "non-finite or non-positive inclusion data");
+    if (std::fabs(c->hy[m]) + c->hr[m] >= L.h)
+      return set_err(c, GRT_EGEOM, "inclusion " + std::to_string(m) + " touches an interface");
+  }
+  // minimum-image overlap check on a cell grid
+  if (M > 1) {
+    double rmax = *std::max_element(c->hr.begin(), c->hr.end());
+    double cell = std::max(2.0 * rmax, 1e-12);
+    int ncx = std::max(1, (int)(L.d / cell));
+    int ncy = std::max(1, (int)(2 * L.h / cell));
+    std::vector<std::vector<int>> grid((size_t)ncx * ncy);
+    auto cidx = [&](double x, double y, int& gx, int& gy) {
+      double xw = x - L.d * std::floor(x / L.d + 0.5);
+      gx = std::min(ncx - 1, std::max(0, (int)((xw + 0.5 * L.d) / (L.d / ncx))));
+      gy = std::min(ncy - 1, std::max(0, (int)((y + L.h) / (2 * L.h / ncy))));
+    };
+    for (int64_t m = 0; m < M; ++m) {
+      int gx, gy;
+      cidx(c->hx[m], c->hy[m], gx, gy);
+      for (int ox = -1; ox <= 1; ++ox)
+        for (int oy = -1; oy <= 1; ++oy) {
+          int qx = ((gx + ox) % ncx + ncx) % ncx, qy = gy + oy;
+          if (qy < 0 || qy >= ncy) continue;
+          for (int o : grid[(size_t)qx * ncy + qy]) {
+            double dx = c->hx[m] - c->hx[o];
+            dx -= L.d * std::floor(dx / L.d + 0.5);
+            double dy = c->hy[m] - c->hy[o];
+            double rr = c->hr[m] + c->hr[o];
+            if (dx * dx + dy * dy <= rr * rr)
+              return set_err(c, GRT_EGEOM, "inclusions " + std::to_string(o) + " and " +
+                                               std::to_string(m) + " overlap");
+          }
+        }
+      grid[(size_t)gx * ncy + gy].push_back((int)m);
+    }
+  }
+  c->lay = L;
+  c->inc = *wave;
+  c->M = M;
+  c->P = wave->P;
+  c->nb = 2 * wave->P + 1;
+  c->n_beta = M * c->nb;
+  // derived device geometry
+  DevGeom& g = c->g;
+  g = DevGeom{};
+  g.d = L.d;
+  g.h = L.h;
+  g.y0 = L.y0;
+  g.hs = L.d / L.N;
+  for (int l = 0; l < 3; ++l) {
+    g.k[l] = wave->omega * L.n_layer[l];
+    g.Nw[l] = L.Nw[l];
+    g.Q[l] = L.Q[l];
+  }
+  g.kappa = g.k[0] * std::sin(wave->phi);
+  g.alpha = cd{std::cos(g.kappa * L.d), std::sin(g.kappa * L.d)};
+  g.alpha_inv = cd{g.alpha.r, -g.alpha.i};
+  g.N = L.N;
+  g.Nu = L.Nu;
+  g.n_rb_lo = L.n_rb_lo;
+  g.Nrb = L.Nrb;
+  g.zeta_K = L.zeta_K;
+  g.P = wave->P;
+  g.M = (int)M;
+  g.jcy[0] = 0.5 * (L.h + L.y0);
+  g.jcy[1] = 0.0;
+  g.jcy[2] = -0.5 * (L.h + L.y0);
+  int rs[RB_COUNT] = {L.N, L.N, L.N, L.N, L.Nw[1], L.Nw[1], L.Nw[0], L.Nw[0],
+                      L.Nw[2], L.Nw[2], L.Nu, L.Nu, L.Nu, L.Nu};
+  g.row_off[0] = 0;
+  for (int b = 0; b < RB_COUNT; ++b) g.row_off[b + 1] = g.row_off[b] + rs[b];
+  int cs[CB_COUNT] = {L.N, L.N, L.N, L.N, 2 * L.Q[1] + 1, 2 * L.Q[0] + 1, 2 * L.Q[2] + 1,
+                      L.Nrb, L.Nrb};
+  g.col_off[0] = 0;
+  for (int b = 0; b < CB_COUNT; ++b) g.col_off[b + 1] = g.col_off[b] + cs[b];
+  g.n_rows = g.row_off[RB_COUNT];
+  g.n_alpha = g.col_off[CB_COUNT];
+  c->n_g = g.row_off[RB_W1V];
+  c->n_b = g.col_off[CB_A1];
+  c->have_problem = true;
+  return GRT_OK;
+}
+
+grt_status grt_build(grt_ctx* c) {
+  GRT_CHECK_CTX(c);
+  if (!c->have_problem) return set_err(c, GRT_ESTATE, "set_problem first");
+  GRT_HIP(c, hipSetDevice(c->device));
+  if (c->built) return GRT_OK;
+  const int64_t M = c->M;
+  if (M > 0) {
+    std::vector<double> kp(M);
+    for (int64_t m = 0; m < M; ++m) kp[m] = c->inc.omega * c->hn[m];
+    GRT_HIP(c, hipMalloc(&c->d_cx, sizeof(double) * M));
+    GRT_HIP(c, hipMalloc(&c->d_cy, sizeof(double) * M));
+    GRT_HIP(c, hipMalloc(&c->d_rad, sizeof(double) * M));
+    GRT_HIP(c, hipMalloc(&c->d_kp, sizeof(double) * M));
+    GRT_HIP(c, hipMemcpy(c->d_cx, c->hx.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+    GRT_HIP(c, hipMemcpy(c->d_cy, c->hy.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+    GRT_HIP(c, hipMemcpy(c->d_rad, c->hr.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+    GRT_HIP(c, hipMemcpy(c->d_kp, kp.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+  }
+  grt_status st = setup_build(c);
+  if (st != GRT_OK) return st;
+  st = apply_alloc(c);
+  if (st != GRT_OK) return st;
+  c->built = true;
+  return GRT_OK;
+}
+
+grt_status grt_query(const grt_ctx* c, grt_sizes* out) {
+  if (!c || !out) return GRT_EINVAL;
+  if (!c->have_problem) return GRT_ESTATE;
+  out->M = c->M;
+  out->P = c->P;
+  out->n_beta = c->n_beta;
+  out->n_rows = c->g.n_rows;
+  out->n_alpha = c->g.n_alpha;
+  out->rank = c->built ? c->rank : 0;
+  out->Nrb = c->g.Nrb;
+  return GRT_OK;
+}
+
+static grt_status check_built(grt_ctx* c) {
+  if (!c->built) return set_err(c, GRT_ESTATE, "build first");
+  GRT_HIP(c, hipSetDevice(c->device));
+  return GRT_OK;
+}
+
+grt_status grt_apply(grt_ctx* c, const void* x, void* y, int precision) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
+  if (precision != GRT_FP64) return set_err(c, GRT_EUNSUP, "only GRT_FP64 is available here");
+  return apply_K(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+}
+
+grt_status grt_apply_T(grt_ctx* c, const void* x, void* y) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
+  return apply_T_only(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+}
+
+grt_status grt_apply_lowrank(grt_ctx* c, const void* x, void* y) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
+  return apply_lowrank_only(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+}
+
+grt_status grt_rhs(grt_ctx* c, void* b) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (!b) return set_err(c, GRT_EINVAL, "null vector");
+  return rhs_b(c, static_cast<cd*>(b));
+}
+
+grt_status grt_solve(grt_ctx* c, const grt_solve_opts* o, void* beta, grt_solve_stats* stats) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (!o || !beta) return set_err(c, GRT_EINVAL, "null argument");
+  if (!(o->tol > 0 && o->tol < 1)) return set_err(c, GRT_EINVAL, "tol must be in (0, 1)");
+  grt_solve_stats tmp{};
+  grt_solve_stats* sp = stats ? stats : &tmp;
+  if (c->M == 0) {
+    *sp = grt_solve_stats{};
+    return GRT_OK;
+  }
+  return gmres_solve(c, o, static_cast<cd*>(beta), sp);
+}
+
+namespace {
+// R_n, T_n for the propagating orders and the flux error |sum R + sum T - 1|.
+__global__ void bragg_finish_kernel(DevGeom g, double k1cos, const cd* cdv, double* R, double* T,
+                                    double* flux) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < g.Nrb; ++i) {
+    double kapn = g.kappa + 2.0 * M_PI * (g.n_rb_lo + i) / g.d;
+    double v1 = g.k[0] * g.k[0] - kapn * kapn;
+    double v3 = g.k[2] * g.k[2] - kapn * kapn;
+    double r = v1 > 0 ? sqrt(v1) * cabs2(cdv[i]) / k1cos : 0.0;
+    double t = v3 > 0 ? sqrt(v3) * cabs2(cdv[g.Nrb + i]) / k1cos : 0.0;
+    R[i] = r;
+    T[i] = t;
+    s += r + t;
+  }
+  *flux = fabs(s - 1.0);
+}
+}  // namespace
+
+grt_status grt_bragg(grt_ctx* c, const void* beta, int64_t cap, int* orders, double* cc,
+                     double* dd, double* R, double* T, double* flux_err) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  const int Nrb = c->g.Nrb;
+  if (cap < Nrb || !orders || !cc || !dd || !R || !T || !flux_err)
+    return set_err(c, GRT_EINVAL, "output arrays too small or null");
+  if (c->M > 0 && !beta) return set_err(c, GRT_EINVAL, "null beta");
+  cd* dcd = nullptr;
+  double* dr = nullptr;
+  GRT_HIP(c, hipMalloc(&dcd, sizeof(cd) * 2 * Nrb));
+  GRT_HIP(c, hipMalloc(&dr, sizeof(double) * (2 * Nrb + 1)));
+  st = bragg_alpha(c, static_cast<const cd*>(beta), dcd);
+  if (st == GRT_OK) {
+    bragg_finish_kernel<<<1, 64, 0, c->stream>>>(c->g, c->g.k[0] * std::cos(c->inc.phi), dcd, dr,
+                                                 dr + Nrb, dr + 2 * Nrb);
+    std::vector<cd> hcd(2 * Nrb);
+    std::vector<double> hr(2 * Nrb + 1);
+    hipError_t e1 = hipMemcpyAsync(hcd.data(), dcd, sizeof(cd) * 2 * Nrb, hipMemcpyDeviceToHost, c->stream);
+    hipError_t e2 = hipMemcpyAsync(hr.data(), dr, sizeof(double) * (2 * Nrb + 1), hipMemcpyDeviceToHost, c->stream);
+    hipError_t e3 = hipStreamSynchronize(c->stream);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+      st = set_err(c, GRT_EHIP, "bragg copy failed");
+    } else {
+      for (int i = 0; i < Nrb; ++i) {
+        orders[i] = c->g.n_rb_lo + i;
+        cc[2 * i] = hcd[i].r;
+        cc[2 * i + 1] = hcd[i].i;
+        dd[2 * i] = hcd[Nrb + i].r;
+        dd[2 * i + 1] = hcd[Nrb + i].i;
+        R[i] = hr[i];
+        T[i] = hr[Nrb + i];
+      }
+      *flux_err = hr[2 * Nrb];
+    }
+  }
+  hipFree(dcd);
+  hipFree(dr);
+  return st;
+}
+
+grt_status grt_get_A(grt_ctx* c, double* A_host, double* colscale_host) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  size_t nA = (size_t)c->g.n_rows * c->g.n_alpha;
+  if (A_host) GRT_HIP(c, hipMemcpy(A_host, c->d_A, sizeof(cd) * nA, hipMemcpyDeviceToHost));
+  if (colscale_host)
+    GRT_HIP(c, hipMemcpy(colscale_host, c->d_colscale, sizeof(double) * c->g.n_alpha,
+                         hipMemcpyDeviceToHost));
+  return GRT_OK;
+}
+
+grt_status grt_profile_enable(grt_ctx* c, int enable) {
+  GRT_CHECK_CTX(c);
+  c->prof = enable != 0;
+  return GRT_OK;
+}
+
+grt_status grt_profile_read(grt_ctx* c, double* m2l_ms_total, int64_t* m2l_launches) {
+  GRT_CHECK_CTX(c);
+  if (!m2l_ms_total || !m2l_launches) return set_err(c, GRT_EINVAL, "null output");
+  GRT_HIP(c, hipSetDevice(c->device));
+  GRT_HIP(c, hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
+    float ms = 0.0f;
+    GRT_HIP(c, hipEventElapsedTime(&ms, c->prof_ev[i], c->prof_ev[i + 1]));
+    c->prof_ms += ms;
+    c->prof_count += 1;
+  }
+  c->prof_used = 0;
+  *m2l_ms_total = c->prof_ms;
+  *m2l_launches = c->prof_count;
+  c->prof_ms = 0.0;
+  c->prof_count = 0;
+  return GRT_OK;
+}
+
+grt_status grt_get_mie(grt_ctx* c, double* s_host) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (!s_host) return set_err(c, GRT_EINVAL, "null buffer");
+  if (c->M > 0)
+    GRT_HIP(c, hipMemcpy(s_host, c->d_mie, sizeof(cd) * c->n_beta, hipMemcpyDeviceToHost));
+  return GRT_OK;
+}
+
+}  // extern "C"

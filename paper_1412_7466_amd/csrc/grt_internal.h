@@ -1,0 +1,122 @@
+// Internal declarations of the grating library (host + device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "dev_common.h"
+#include "../../include/grating.h"
+
+// Row blocks of the empty-structure system, in storage order.
+enum RowBlock { RB_G1V = 0, RB_G1N, RB_G2V, RB_G2N, RB_W2V, RB_W2D, RB_W1V, RB_W1D,
+                RB_W3V, RB_W3D, RB_UV, RB_UN, RB_DV, RB_DN, RB_COUNT };
+// Column blocks (unknowns alpha), in storage order.
+enum ColBlock { CB_MU1 = 0, CB_SIG1, CB_MU2, CB_SIG2, CB_A2, CB_A1, CB_A3, CB_C, CB_D, CB_COUNT };
+
+// Everything a device kernel needs to know about one problem (passed by value).
+struct DevGeom {
+  double d, h, y0, hs;          // period, half thickness, Gamma_u height, d/N
+  double k[3];                  // layer wavenumbers (top, middle, bottom)
+  double kappa;                 // k_1 sin(phi)
+  cd alpha, alpha_inv;          // Bloch phase e^{i kappa d} and its inverse
+  int N, Nu, n_rb_lo, Nrb, zeta_K, P, M;
+  int Nw[3], Q[3];
+  double jcy[3];                // J-expansion centres (0, jcy[l])
+  int row_off[RB_COUNT + 1];
+  int col_off[CB_COUNT + 1];
+  int n_rows, n_alpha;
+  const double* yw[3];          // wall nodes (device)
+  const cd* wcorr;              // zeta-correction weights [4][2K+1]: S1, T1, S2, T2
+};
+
+struct grt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // problem (host copies)
+  bool have_problem = false, built = false;
+  grt_layers lay{};
+  grt_incidence inc{};
+  int64_t M = 0;
+  std::vector<double> hx, hy, hr, hn;
+  // derived
+  DevGeom g{};
+  int P = 0, nb = 0;
+  int64_t n_beta = 0;
+  int n_g = 0;   // rows of C that are nonzero (prefix): Gamma_1, Gamma_2, wall 2
+  int n_b = 0;   // entries of alpha read by B (prefix): mu1, sig1, mu2, sig2, a2
+  int rank = 0;
+  // device buffers owned by the context
+  double *d_cx = nullptr, *d_cy = nullptr, *d_rad = nullptr, *d_kp = nullptr;
+  double* d_yw = nullptr;
+  cd* d_wcorr = nullptr;
+  cd* d_A = nullptr;        // [n_alpha][n_rows] column-major, equilibrated
+  double* d_colscale = nullptr;
+  double* d_sv = nullptr;
+  cd* d_U = nullptr;        // [min][n_rows] column-major
+  cd* d_VH = nullptr;       // [n_alpha][n_alpha] column-major (V^H)
+  cd* d_W1 = nullptr;       // [rank][n_g]   row-major: Sigma^+ U^H (prefix rows)
+  cd* d_W2 = nullptr;       // [n_b][rank]   row-major: E V (prefix entries)
+  cd* d_W3 = nullptr;       // [2 Nrb][rank] row-major: E V (c, d entries)
+  cd* d_mie = nullptr;      // [M][nb]
+  cd* d_l2l = nullptr;      // [M][2(Q2+P)+1]  J_m(k rho_j) e^{i m phi_j}
+  cd* d_f = nullptr;        // [n_g] right-hand side prefix
+  // apply workspace
+  int m2l_chunk = 16, m2l_nchunks = 0;
+  int c_chunk = 64, c_nchunks = 0;
+  int b_chunk = 64, b_nchunks = 0;
+  cd* d_pT = nullptr;       // [m2l_nchunks][M][nb]
+  cd* d_pC = nullptr;       // [c_nchunks][n_ctgt][2]
+  cd* d_pB = nullptr;       // [b_nchunks][M][nb]
+  cd* d_pL = nullptr;       // [M][nb]
+  cd* d_gvec = nullptr;     // [n_g]
+  cd* d_tvec = nullptr;     // [rank]
+  cd* d_wvec = nullptr;     // [n_b]
+  // GMRES workspace
+  int krylov_restart = 0;
+  cd* d_V = nullptr;        // [restart+1][n_beta]
+  cd* d_H = nullptr;        // [restart+1][restart] (column j contiguous: H[j*(restart+1)+i])
+  cd* d_cs = nullptr;
+  cd* d_sn = nullptr;
+  cd* d_gv = nullptr;       // [restart+1]
+  cd* d_y = nullptr;
+  double* d_scal = nullptr; // scratch scalars
+  cd* d_dotpart = nullptr;  // [restart+1][n_dot_blocks]
+  int n_dot_blocks = 0;
+  double* h_pinned = nullptr;
+  // kernel timing (HIP events around every translation-kernel launch)
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;  // pairs: start, stop
+  size_t prof_used = 0;             // events in use (even)
+  double prof_ms = 0.0;             // accumulated from drained pairs
+  int64_t prof_count = 0;
+};
+
+// status helpers ---------------------------------------------------------------
+grt_status set_err(grt_ctx* c, grt_status s, const std::string& msg);
+#define GRT_HIP(ctx, call)                                                           \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return set_err(ctx, GRT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// setup (setup.hip)
+grt_status setup_build(grt_ctx* c);
+void launch_gemv_rows(hipStream_t s, const cd* W, const cd* x, cd* y, int rows, int cols);
+
+// apply (apply.hip)
+bool supported_P(int P);
+grt_status apply_K(grt_ctx* c, const cd* x, cd* y);
+grt_status apply_T_only(grt_ctx* c, const cd* x, cd* y);
+grt_status apply_lowrank_only(grt_ctx* c, const cd* x, cd* y);
+grt_status rhs_b(grt_ctx* c, cd* b);
+grt_status lowrank_from_g(grt_ctx* c, cd* pB_out_sum_into, bool mult_s, const cd* x, cd* y);
+grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out_cd /* device [2 Nrb] */);
+grt_status apply_alloc(grt_ctx* c);
+
+// krylov (krylov.hip)
+grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_stats* st);

@@ -1,0 +1,612 @@
+// Device-side construction of everything the apply needs (paper sec. 3, 4.1, 5).
+//
+//  * the rectangular empty-structure matrix A of eq. matA, one thread per entry:
+//    layer potentials summed over the copies l = -1, 0, 1 with phases alpha^l
+//    (eqs. repre1-repre3), the same-line kernel differences S_ka - S_kb and
+//    T_ka - T_kb on the flat interfaces with zeta-corrected trapezoid weights
+//    (the paper's locally corrected Nystrom rule), J-expansion columns, wall
+//    discrepancies in the cancelled form alpha u(L) - u(L+d) =
+//    alpha^2 Phi(L-d) - alpha^{-1} Phi(L+2d), Rayleigh-Bloch columns (eq. bound3);
+//  * unit-norm column equilibration, SVD by rocSOLVER, truncated Sigma^+ and the
+//    three factor blocks the apply streams (eq. applypA: A^+ g = V Sigma^+ U^* g);
+//  * the Mie (single-disk) scattering coefficients (sec. 4.1);
+//  * the L2L table J_m(k_2 rho_j) e^{i m phi_j} of every inclusion about the middle
+//    J centre (Graf's theorem for J);
+//  * the incident data f of eq. Arhs.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "dev_bessel.h"
+#include "grt_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// quadrature nodes and correction weights
+// ---------------------------------------------------------------------------
+
+// Gauss-Legendre nodes of order n on [a, b], ascending (Newton on P_n from the
+// Chebyshev-like initial guess).
+__global__ void gl_nodes_kernel(int n, double a, double b, double* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = cos(GRT_PI * (i + 0.75) / (n + 0.5));
+  for (int it = 0; it < 100; ++it) {
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double pn = (n == 1) ? x : p1, pm = (n == 1) ? 1.0 : p0;
+    double dp = n * (x * pn - pm) / (x * x - 1.0);
+    double dx = pn / dp;
+    x -= dx;
+    if (fabs(dx) < 1e-16) break;
+  }
+  // roots from the guess above come largest first; store ascending
+  out[i] = 0.5 * (a + b) + 0.5 * (b - a) * (-x);
+}
+
+// zeta(s) for s >= 3 by direct summation with an Euler-Maclaurin tail.
+__device__ double zeta_odd(double s) {
+  const int Nz = 100;
+  double acc = 0.0;
+  for (int n = Nz - 1; n >= 1; --n) acc += pow((double)n, -s);
+  double Nd = Nz;
+  acc += pow(Nd, 1.0 - s) / (s - 1.0) + 0.5 * pow(Nd, -s) + s * pow(Nd, -s - 1.0) / 12.0 -
+         s * (s + 1.0) * (s + 2.0) * pow(Nd, -s - 3.0) / 720.0;
+  return acc;
+}
+
+// The split K(s) = phi(s) ln|s| + psi(s) of the flat-line kernel differences:
+//   S_ka - S_kb: phi = -[J0(ka s) - J0(kb s)] / (2 pi), psi(0) = -ln(ka/kb) / (2 pi)
+//   T_ka - T_kb: phi = -[ka J1(ka s) - kb J1(kb s)] / (2 pi s), phi(0) = -(ka^2-kb^2)/(4 pi),
+//     psi(0) = i (ka^2-kb^2)/8 - [ka^2 ln(ka/2) - kb^2 ln(kb/2)]/(4 pi) + (ka^2-kb^2)(1-2 gamma)/(8 pi)
+// (small-argument series of J0, Y0, J1, Y1; the hypersingular parts cancel).
+__device__ void phi_vals(double ka, double kb, double s, bool tker, double& phi) {
+  if (s == 0.0) {
+    phi = tker ? -(ka * ka - kb * kb) / (4.0 * GRT_PI) : 0.0;
+    return;
+  }
+  double a0, a1, b0, b1, ya0, ya1, yb0, yb1;
+  bessel01(ka * s, a0, a1, ya0, ya1);
+  bessel01(kb * s, b0, b1, yb0, yb1);
+  phi = tker ? -(ka * a1 - kb * b1) / (2.0 * GRT_PI * s) : -(a0 - b0) / (2.0 * GRT_PI);
+}
+
+// Single thread: Fornberg finite-difference weights on the stencil -K..K (unit
+// spacing), then the zeta-corrected trapezoid weights for the four self blocks
+//   w_p = hs sum_k 2 zeta'(-2k)/(2k)! c^{(2k)}_p phi(p hs) + [p = 0] hs (psi(0) + phi(0) ln(hs / 2 pi)),
+//   2 zeta'(-2k)/(2k)! = (-1)^k zeta(2k+1) / (2 pi)^{2k}.
+__global__ void zeta_weights_kernel(int K, double hs, double k1, double k2, double k3, cd* w) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n = 2 * K + 1;
+  const int m = 2 * K;
+  double z[33];
+  double c[33][33];  // c[q][j]
+  for (int j = 0; j < n; ++j) z[j] = (double)(j - K);
+  for (int q = 0; q <= m; ++q)
+    for (int j = 0; j < n; ++j) c[q][j] = 0.0;
+  double c1 = 1.0, c4 = z[0];
+  c[0][0] = 1.0;
+  for (int i = 1; i < n; ++i) {
+    int mn = i < m ? i : m;
+    double c2 = 1.0, c5 = c4;
+    c4 = z[i];
+    for (int j = 0; j < i; ++j) {
+      double c3 = z[i] - z[j];
+      c2 *= c3;
+      if (j == i - 1) {
+        for (int k = mn; k >= 1; --k) c[k][i] = c1 * (k * c[k - 1][i - 1] - c5 * c[k][i - 1]) / c2;
+        c[0][i] = -c1 * c5 * c[0][i - 1] / c2;
+      }
+      for (int k = mn; k >= 1; --k) c[k][j] = (c4 * c[k][j] - k * c[k - 1][j]) / c3;
+      c[0][j] = c4 * c[0][j] / c3;
+    }
+    c1 = c2;
+  }
+  double zc[17];
+  for (int k = 1; k <= K; ++k) {
+    double sgn = (k & 1) ? -1.0 : 1.0;
+    zc[k] = sgn * zeta_odd(2.0 * k + 1.0) / pow(2.0 * GRT_PI, 2.0 * k);
+  }
+  const double gam = GRT_EULER_GAMMA;
+  for (int blk = 0; blk < 4; ++blk) {
+    bool tker = blk & 1;
+    double ka = (blk < 2) ? k1 : k2;
+    double kb = (blk < 2) ? k2 : k3;
+    double phi0 = tker ? -(ka * ka - kb * kb) / (4.0 * GRT_PI) : 0.0;
+    cd psi0;
+    if (!tker) {
+      psi0 = cd{-log(ka / kb) / (2.0 * GRT_PI), 0.0};
+    } else {
+      double d2 = ka * ka - kb * kb;
+      psi0 = cd{-(ka * ka * log(0.5 * ka) - kb * kb * log(0.5 * kb)) / (4.0 * GRT_PI) +
+                    d2 * (1.0 - 2.0 * gam) / (8.0 * GRT_PI),
+                0.125 * d2};
+    }
+    for (int j = 0; j < n; ++j) {
+      double ph;
+      phi_vals(ka, kb, fabs((double)(j - K)) * hs, tker, ph);
+      double acc = 0.0;
+      for (int k = 1; k <= K; ++k) acc += zc[k] * c[2 * k][j];
+      cd wj{hs * acc * ph, 0.0};
+      if (j == K) {
+        wj.r += hs * (psi0.r + phi0 * log(hs / (2.0 * GRT_PI)));
+        wj.i += hs * psi0.i;
+      }
+      w[blk * n + j] = wj;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// matrix entries
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ cd alpha_pow(const DevGeom& g, int l) {
+  if (l == 0) return cd{1.0, 0.0};
+  cd r = (l > 0) ? g.alpha : g.alpha_inv;
+  int a = l > 0 ? l : -l;
+  cd o{1.0, 0.0};
+  for (int t = 0; t < a; ++t) o = o * r;
+  return o;
+}
+
+// Single-layer G = (i/4) H0(kr) and double-layer dG/dn_y = (ik/4) H1(kr) R_y / r
+// (source normal +y), R = target - source; with deriv, their derivatives along
+// the unit direction (tx, ty) at the target:
+//   dS = -(ik/4) H1 (R.t)/r,  dD = (ik/4) [-k H2 R_y (R.t)/r^2 + H1 t_y / r].
+__device__ void lp_kernels(double k, double Rx, double Ry, bool deriv, double tx, double ty,
+                           cd& S, cd& D) {
+  double r = sqrt(Rx * Rx + Ry * Ry);
+  double z = k * r;
+  cd h0, h1;
+  hankel01(z, h0, h1);
+  if (!deriv) {
+    S = times_i(0.25 * h0);
+    D = times_i((0.25 * k * Ry / r) * h1);
+    return;
+  }
+  cd h2 = (2.0 / z) * h1 - h0;
+  double Rt = Rx * tx + Ry * ty;
+  S = times_i((-0.25 * k * Rt / r) * h1);
+  D = times_i((0.25 * k) * ((-k * Ry * Rt / (r * r)) * h2 + (ty / r) * h1));
+}
+
+// Three-copy trapezoid sum from interface node j on the line y = ys.
+__device__ void three_copy(const DevGeom& g, double k, double tx, double ty, int j, double ys,
+                           bool deriv, double dx, double dy, cd& S, cd& D) {
+  double sx = -0.5 * g.d + (j + 0.5) * g.hs;
+  S = cd{0, 0};
+  D = cd{0, 0};
+  for (int l = -1; l <= 1; ++l) {
+    cd a, b;
+    lp_kernels(k, tx - (sx + l * g.d), ty - ys, deriv, dx, dy, a, b);
+    cd w = alpha_pow(g, l);
+    S += w * a;
+    D += w * b;
+  }
+  S = g.hs * S;
+  D = g.hs * D;
+}
+
+// Wall discrepancy alpha u(L) - u(R) of the three copies of node j, cancelled:
+// alpha^2 Phi(-3d/2, y) - alpha^{-1} Phi(3d/2, y), Phi the l = 0 copy.
+__device__ void wall_cancelled(const DevGeom& g, double k, double y, int j, double ys, bool deriv,
+                               cd& S, cd& D) {
+  double sx = -0.5 * g.d + (j + 0.5) * g.hs;
+  cd a1, b1, a2, b2;
+  lp_kernels(k, -1.5 * g.d - sx, y - ys, deriv, 1.0, 0.0, a1, b1);
+  lp_kernels(k, 1.5 * g.d - sx, y - ys, deriv, 1.0, 0.0, a2, b2);
+  cd w1 = g.alpha * g.alpha, w2 = -g.alpha_inv;
+  S = g.hs * (w1 * a1 + w2 * a2);
+  D = g.hs * (w1 * b1 + w2 * b2);
+}
+
+// Same-line self block entry (target node i, source node j) of S_ka - S_kb or
+// T_ka - T_kb: punctured three-copy trapezoid sum plus stencil corrections.
+__device__ cd self_entry(const DevGeom& g, double ka, double kb, bool tker, const cd* wc, int i,
+                         int j) {
+  cd acc{0, 0};
+  const int N = g.N, K = g.zeta_K;
+  for (int l = -1; l <= 1; ++l) {
+    cd w = alpha_pow(g, l);
+    if (!(l == 0 && i == j)) {
+      double s = fabs((double)(i - j - l * N)) * g.hs;
+      cd ha0, ha1, hb0, hb1;
+      hankel01(ka * s, ha0, ha1);
+      hankel01(kb * s, hb0, hb1);
+      cd kv = tker ? times_i((0.25 / s) * (ka * ha1 - kb * hb1)) : times_i(0.25 * (ha0 - hb0));
+      acc += (g.hs) * (w * kv);
+    }
+    int p = j + l * N - i;
+    if (p >= -K && p <= K) acc += w * wc[p + K];
+  }
+  return acc;
+}
+
+// J-expansion column q of layer `lay` at target (tx, ty): J_q(k r) e^{i q theta}
+// or its derivative along (dx, dy) from (d_x +- i d_y) Z_q e^{iq theta} =
+// -+ k Z_{q+-1} e^{i(q+-1) theta}.
+__device__ cd jcol(const DevGeom& g, int lay, int q, double tx, double ty, bool deriv, double dx,
+                   double dy) {
+  double k = g.k[lay];
+  double vx = tx, vy = ty - g.jcy[lay];
+  double r = sqrt(vx * vx + vy * vy);
+  double jm, j0, jp;
+  bessel_j_three(k * r, q, jm, j0, jp);
+  cd e = (r > 0) ? cd{vx / r, vy / r} : cd{1.0, 0.0};
+  auto epow = [&](int n) { return n >= 0 ? cpowi(e, n) : cpowi(conj(e), -n); };
+  if (!deriv) return j0 * epow(q);
+  cd fm = jm * epow(q - 1), fp = jp * epow(q + 1);
+  cd gx = (0.5 * k) * (fm - fp);
+  cd gy = times_i((0.5 * k) * (fm + fp));
+  return dx * gx + dy * gy;
+}
+
+__device__ cd kz_branch(double k, double kap) {
+  double v = k * k - kap * kap;
+  return v >= 0 ? cd{sqrt(v), 0.0} : cd{0.0, sqrt(-v)};
+}
+
+__device__ cd A_entry(const DevGeom& g, int row, int col) {
+  int rb = 0;
+  while (row >= g.row_off[rb + 1]) ++rb;
+  int cb = 0;
+  while (col >= g.col_off[cb + 1]) ++cb;
+  int i = row - g.row_off[rb];
+  int j = col - g.col_off[cb];
+  const double h = g.h, d = g.d;
+  const double k1 = g.k[0], k2 = g.k[1], k3 = g.k[2];
+  const int K2 = 2 * g.zeta_K + 1;
+  cd S, D;
+  cd zero{0, 0};
+  switch (rb) {
+    case RB_G1V:
+    case RB_G1N: {
+      bool dv = (rb == RB_G1N);
+      double tx = -0.5 * d + (i + 0.5) * g.hs, ty = h;
+      switch (cb) {
+        case CB_MU1:
+          return dv ? self_entry(g, k1, k2, true, g.wcorr + 1 * K2, i, j)
+                    : (i == j ? cd{1, 0} : zero);
+        case CB_SIG1:
+          return dv ? (i == j ? cd{-1, 0} : zero) : self_entry(g, k1, k2, false, g.wcorr, i, j);
+        case CB_MU2:
+        case CB_SIG2:
+          three_copy(g, k2, tx, ty, j, -h, dv, 0.0, 1.0, S, D);
+          return -(cb == CB_MU2 ? D : S);
+        case CB_A2: return -jcol(g, 1, j - g.Q[1], tx, ty, dv, 0.0, 1.0);
+        case CB_A1: return jcol(g, 0, j - g.Q[0], tx, ty, dv, 0.0, 1.0);
+        default: return zero;
+      }
+    }
+    case RB_G2V:
+    case RB_G2N: {
+      bool dv = (rb == RB_G2N);
+      double tx = -0.5 * d + (i + 0.5) * g.hs, ty = -h;
+      switch (cb) {
+        case CB_MU1:
+        case CB_SIG1:
+          three_copy(g, k2, tx, ty, j, h, dv, 0.0, 1.0, S, D);
+          return (cb == CB_MU1 ? D : S);
+        case CB_MU2:
+          return dv ? self_entry(g, k2, k3, true, g.wcorr + 3 * K2, i, j)
+                    : (i == j ? cd{1, 0} : zero);
+        case CB_SIG2:
+          return dv ? (i == j ? cd{-1, 0} : zero)
+                    : self_entry(g, k2, k3, false, g.wcorr + 2 * K2, i, j);
+        case CB_A2: return jcol(g, 1, j - g.Q[1], tx, ty, dv, 0.0, 1.0);
+        case CB_A3: return -jcol(g, 2, j - g.Q[2], tx, ty, dv, 0.0, 1.0);
+        default: return zero;
+      }
+    }
+    case RB_W2V: case RB_W2D: case RB_W1V: case RB_W1D: case RB_W3V: case RB_W3D: {
+      int lay = (rb <= RB_W2D) ? 1 : (rb <= RB_W1D ? 0 : 2);
+      bool dv = (rb == RB_W2D || rb == RB_W1D || rb == RB_W3D);
+      double y = g.yw[lay][i];
+      double k = g.k[lay];
+      int jcb = (lay == 1) ? CB_A2 : (lay == 0 ? CB_A1 : CB_A3);
+      bool top_line = (cb == CB_MU1 || cb == CB_SIG1);
+      bool bot_line = (cb == CB_MU2 || cb == CB_SIG2);
+      if ((top_line && lay != 2) || (bot_line && lay != 0)) {
+        wall_cancelled(g, k, y, j, top_line ? h : -h, dv, S, D);
+        return (cb == CB_MU1 || cb == CB_MU2) ? D : S;
+      }
+      if (cb == jcb) {
+        int q = j - g.Q[lay];
+        cd L = jcol(g, lay, q, -0.5 * d, y, dv, 1.0, 0.0);
+        cd R = jcol(g, lay, q, 0.5 * d, y, dv, 1.0, 0.0);
+        return g.alpha * L - R;
+      }
+      return zero;
+    }
+    case RB_UV: case RB_UN: case RB_DV: case RB_DN: {
+      bool upper = (rb == RB_UV || rb == RB_UN);
+      bool dv = (rb == RB_UN || rb == RB_DN);
+      double tx = -0.5 * d + (i + 0.5) * d / g.Nu;
+      double ty = upper ? g.y0 : -g.y0;
+      double k = upper ? k1 : k3;
+      if (upper && (cb == CB_MU1 || cb == CB_SIG1)) {
+        three_copy(g, k, tx, ty, j, h, dv, 0.0, 1.0, S, D);
+        return cb == CB_MU1 ? D : S;
+      }
+      if (!upper && (cb == CB_MU2 || cb == CB_SIG2)) {
+        three_copy(g, k, tx, ty, j, -h, dv, 0.0, 1.0, S, D);
+        return cb == CB_MU2 ? D : S;
+      }
+      if (upper && cb == CB_A1) return jcol(g, 0, j - g.Q[0], tx, ty, dv, 0.0, 1.0);
+      if (!upper && cb == CB_A3) return jcol(g, 2, j - g.Q[2], tx, ty, dv, 0.0, 1.0);
+      if ((upper && cb == CB_C) || (!upper && cb == CB_D)) {
+        double kapn = g.kappa + 2.0 * GRT_PI * (g.n_rb_lo + j) / d;
+        cd e = cexpi(kapn * tx);
+        if (!dv) return -e;
+        cd kz = kz_branch(k, kapn);
+        cd ik = times_i(kz);
+        return upper ? -(ik * e) : (ik * e);
+      }
+      return zero;
+    }
+    default:
+      return zero;
+  }
+}
+
+__global__ void assemble_A_kernel(DevGeom g, cd* A) {
+  int row = blockIdx.x * blockDim.x + threadIdx.x;
+  int col = blockIdx.y;
+  if (row >= g.n_rows || col >= g.n_alpha) return;
+  A[(size_t)col * g.n_rows + row] = A_entry(g, row, col);
+}
+
+// One block per column: 2-norm, then scale the column to unit norm.
+__global__ void equilibrate_kernel(cd* A, int n_rows, int n_cols, double* scale) {
+  int col = blockIdx.x;
+  if (col >= n_cols) return;
+  cd* a = A + (size_t)col * n_rows;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int r = threadIdx.x; r < n_rows; r += blockDim.x) s += cabs2(a[r]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  double nrm = sqrt(red[0]);
+  double sc = nrm > 0 ? 1.0 / nrm : 1.0;
+  for (int r = threadIdx.x; r < n_rows; r += blockDim.x) a[r] = sc * a[r];
+  if (threadIdx.x == 0) scale[col] = sc;
+}
+
+// W1[k][i] = conj(U[i][k]) / sigma_k (k < rank, i < n_g)
+__global__ void build_W1_kernel(const cd* U, int ldu, const double* sv, int rank, int n_g, cd* W1) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= n_g || k >= rank) return;
+  cd u = U[(size_t)k * ldu + i];
+  W1[(size_t)k * n_g + i] = (1.0 / sv[k]) * conj(u);
+}
+
+// W[i][k] = E[i0 + i] * conj(VH[k][i0 + i]) (V = (V^H)^H, E the column scales)
+__global__ void build_Wv_kernel(const cd* VH, int ldv, const double* E, int i0, int rows, int rank,
+                                cd* W) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (k >= rank || i >= rows) return;
+  cd v = VH[(size_t)(i0 + i) * ldv + k];
+  W[(size_t)i * rank + k] = E[i0 + i] * conj(v);
+}
+
+// Mie coefficients of every disk (sec. 4.1), s_{-n} = s_n:
+//   s_n = -[k2 J_n'(x) J_n(y) - kp J_n(x) J_n'(y)] / [k2 H_n'(x) J_n(y) - kp H_n(x) J_n'(y)],
+// x = k2 R, y = kp R; Z_n' = Z_{n-1} - (n/x) Z_n, Z_0' = -Z_1.
+__global__ void mie_kernel(int M, int P, double k2, const double* rad, const double* kp, cd* s) {
+  int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double R = rad[m];
+  double x = k2 * R, y = kp[m] * R;
+  double jx[48], jy[48];
+  bessel_jn_array(x, P + 1, jx);
+  bessel_jn_array(y, P + 1, jy);
+  cd hprev, hcur;
+  hankel01(x, hprev, hcur);  // H_0, H_1
+  int nb = 2 * P + 1;
+  cd H[48];
+  H[0] = hprev;
+  H[1] = hcur;
+  for (int n = 1; n <= P; ++n) H[n + 1] = (2.0 * n / x) * H[n] - H[n - 1];
+  for (int n = 0; n <= P; ++n) {
+    double djx = (n == 0) ? -jx[1] : jx[n - 1] - (n / x) * jx[n];
+    double djy = (n == 0) ? -jy[1] : jy[n - 1] - (n / y) * jy[n];
+    cd dH = (n == 0) ? -H[1] : H[n - 1] - (n / x) * H[n];
+    double num = k2 * djx * jy[n] - kp[m] * jx[n] * djy;
+    cd den = (k2 * jy[n]) * dH - (kp[m] * djy) * H[n];
+    cd sn = cdiv(cd{-num, 0.0}, den);
+    s[(size_t)m * nb + P + n] = sn;
+    s[(size_t)m * nb + P - n] = sn;
+  }
+}
+
+// L2L generator of every inclusion: E_j[m] = J_m(k2 rho) e^{i m phi}, m = -L..L,
+// rho e^{i phi} = c_j - (0, 0).
+__global__ void l2l_table_kernel(int M, int L, double k2, const double* cx, const double* cy,
+                                 cd* E) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  double vx = cx[j], vy = cy[j];
+  double r = sqrt(vx * vx + vy * vy);
+  double jn[512];
+  bessel_jn_array(k2 * r, L, jn);
+  cd e = (r > 0) ? cd{vx / r, vy / r} : cd{1.0, 0.0};
+  cd ep{1.0, 0.0};
+  cd* row = E + (size_t)j * (2 * L + 1);
+  for (int m = 0; m <= L; ++m) {
+    row[L + m] = jn[m] * ep;
+    double sg = (m & 1) ? -1.0 : 1.0;
+    row[L - m] = (sg * jn[m]) * conj(ep);
+    ep = ep * e;
+  }
+}
+
+// f of eq. Arhs restricted to the Gamma_1 rows: -u_inc and -d_y u_inc at y = h.
+__global__ void rhs_f_kernel(DevGeom g, double k1cos, int n_g, cd* f) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_g) return;
+  cd v{0, 0};
+  if (r < 2 * g.N) {
+    int i = r % g.N;
+    double x = -0.5 * g.d + (i + 0.5) * g.hs;
+    cd ui = cexpi(g.kappa * x - k1cos * g.h);
+    v = (r < g.N) ? -ui : times_i(k1cos * ui);
+  }
+  f[r] = v;
+}
+
+// y[i] = sum_k W[i][k] x[k], one 64-lane wavefront per row.
+__global__ void __launch_bounds__(256) gemv_rows_kernel(const cd* __restrict__ W,
+                                                        const cd* __restrict__ x, cd* y, int rows,
+                                                        int cols) {
+  int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (wave >= rows) return;
+  const cd* w = W + (size_t)wave * cols;
+  double ar = 0.0, ai = 0.0;
+  for (int k = lane; k < cols; k += 64) {
+    cd a = w[k], b = x[k];
+    ar = fma(a.r, b.r, ar);
+    ar = fma(-a.i, b.i, ar);
+    ai = fma(a.r, b.i, ai);
+    ai = fma(a.i, b.r, ai);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_xor(ar, off, 64);
+    ai += __shfl_xor(ai, off, 64);
+  }
+  if (lane == 0) y[wave] = cd{ar, ai};
+}
+
+}  // namespace
+
+void launch_gemv_rows(hipStream_t s, const cd* W, const cd* x, cd* y, int rows, int cols) {
+  if (rows <= 0) return;
+  int blocks = (rows + 3) / 4;
+  gemv_rows_kernel<<<blocks, 256, 0, s>>>(W, x, y, rows, cols);
+}
+
+static grt_status rocblas_err(grt_ctx* c, const char* what, int st) {
+  return set_err(c, GRT_EHIP, std::string(what) + " failed with rocBLAS status " + std::to_string(st));
+}
+
+grt_status setup_build(grt_ctx* c) {
+  hipStream_t s = c->stream;
+  DevGeom& g = c->g;
+  const int K = g.zeta_K;
+  // wall nodes
+  const int nwt = g.Nw[0] + g.Nw[1] + g.Nw[2];
+  GRT_HIP(c, hipMalloc(&c->d_yw, sizeof(double) * nwt));
+  double spans[3][2] = {{g.h, g.y0}, {-g.h, g.h}, {-g.y0, -g.h}};
+  int off = 0;
+  for (int l = 0; l < 3; ++l) {
+    gl_nodes_kernel<<<(g.Nw[l] + 63) / 64, 64, 0, s>>>(g.Nw[l], spans[l][0], spans[l][1],
+                                                        c->d_yw + off);
+    g.yw[l] = c->d_yw + off;
+    off += g.Nw[l];
+  }
+  GRT_HIP(c, hipMalloc(&c->d_wcorr, sizeof(cd) * 4 * (2 * K + 1)));
+  zeta_weights_kernel<<<1, 64, 0, s>>>(K, g.hs, g.k[0], g.k[1], g.k[2], c->d_wcorr);
+  g.wcorr = c->d_wcorr;
+  GRT_HIP(c, hipGetLastError());
+
+  // A, equilibrated
+  const size_t nA = (size_t)g.n_rows * g.n_alpha;
+  GRT_HIP(c, hipMalloc(&c->d_A, sizeof(cd) * nA));
+  GRT_HIP(c, hipMalloc(&c->d_colscale, sizeof(double) * g.n_alpha));
+  {
+    dim3 grid((g.n_rows + 127) / 128, g.n_alpha);
+    assemble_A_kernel<<<grid, 128, 0, s>>>(g, c->d_A);
+    GRT_HIP(c, hipGetLastError());
+    equilibrate_kernel<<<g.n_alpha, 256, 0, s>>>(c->d_A, g.n_rows, g.n_alpha, c->d_colscale);
+    GRT_HIP(c, hipGetLastError());
+  }
+
+  // SVD of the equilibrated A (a copy: gesvd overwrites its input)
+  const int m = g.n_rows, n = g.n_alpha, mn = std::min(m, n);
+  cd* Awork = nullptr;
+  double* Ework = nullptr;
+  int* dinfo = nullptr;
+  GRT_HIP(c, hipMalloc(&Awork, sizeof(cd) * nA));
+  GRT_HIP(c, hipMemcpyAsync(Awork, c->d_A, sizeof(cd) * nA, hipMemcpyDeviceToDevice, s));
+  GRT_HIP(c, hipMalloc(&c->d_sv, sizeof(double) * mn));
+  GRT_HIP(c, hipMalloc(&c->d_U, sizeof(cd) * (size_t)m * mn));
+  GRT_HIP(c, hipMalloc(&c->d_VH, sizeof(cd) * (size_t)n * n));
+  GRT_HIP(c, hipMalloc(&Ework, sizeof(double) * std::max(1, mn - 1)));
+  GRT_HIP(c, hipMalloc(&dinfo, sizeof(int)));
+  rocblas_handle hb;
+  rocblas_status rs = rocblas_create_handle(&hb);
+  if (rs != rocblas_status_success) return rocblas_err(c, "rocblas_create_handle", rs);
+  rocblas_set_stream(hb, s);
+  rs = rocsolver_zgesvd(hb, rocblas_svect_singular, rocblas_svect_singular, m, n,
+                        reinterpret_cast<rocblas_double_complex*>(Awork), m, c->d_sv,
+                        reinterpret_cast<rocblas_double_complex*>(c->d_U), m,
+                        reinterpret_cast<rocblas_double_complex*>(c->d_VH), n, Ework,
+                        rocblas_outofplace, dinfo);
+  if (rs != rocblas_status_success) {
+    rocblas_destroy_handle(hb);
+    return rocblas_err(c, "rocsolver_zgesvd", rs);
+  }
+  int hinfo = 0;
+  std::vector<double> sv(mn);
+  GRT_HIP(c, hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+  GRT_HIP(c, hipMemcpyAsync(sv.data(), c->d_sv, sizeof(double) * mn, hipMemcpyDeviceToHost, s));
+  GRT_HIP(c, hipStreamSynchronize(s));
+  rocblas_destroy_handle(hb);
+  hipFree(Awork);
+  hipFree(Ework);
+  hipFree(dinfo);
+  if (hinfo != 0)
+    return set_err(c, GRT_EHIP, "rocsolver_zgesvd did not converge (info=" + std::to_string(hinfo) + ")");
+  int rank = 0;
+  for (int k = 0; k < mn; ++k)
+    if (sv[k] >= c->lay.pinv_eps * sv[0] && sv[k] > 0) ++rank;
+  c->rank = rank;
+
+  // factor blocks streamed by the apply
+  GRT_HIP(c, hipMalloc(&c->d_W1, sizeof(cd) * (size_t)rank * c->n_g));
+  GRT_HIP(c, hipMalloc(&c->d_W2, sizeof(cd) * (size_t)c->n_b * rank));
+  GRT_HIP(c, hipMalloc(&c->d_W3, sizeof(cd) * (size_t)2 * g.Nrb * rank));
+  {
+    dim3 g1((c->n_g + 255) / 256, rank);
+    build_W1_kernel<<<g1, 256, 0, s>>>(c->d_U, m, c->d_sv, rank, c->n_g, c->d_W1);
+    dim3 g2((rank + 255) / 256, c->n_b);
+    build_Wv_kernel<<<g2, 256, 0, s>>>(c->d_VH, n, c->d_colscale, 0, c->n_b, rank, c->d_W2);
+    dim3 g3((rank + 255) / 256, 2 * g.Nrb);
+    build_Wv_kernel<<<g3, 256, 0, s>>>(c->d_VH, n, c->d_colscale, g.col_off[CB_C], 2 * g.Nrb, rank,
+                                       c->d_W3);
+    GRT_HIP(c, hipGetLastError());
+  }
+
+  // inclusions: Mie diagonal and L2L table
+  if (c->M > 0) {
+    GRT_HIP(c, hipMalloc(&c->d_mie, sizeof(cd) * c->n_beta));
+    mie_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, c->P, g.k[1], c->d_rad, c->d_kp,
+                                                      c->d_mie);
+    int L = g.Q[1] + c->P;
+    GRT_HIP(c, hipMalloc(&c->d_l2l, sizeof(cd) * (size_t)c->M * (2 * L + 1)));
+    l2l_table_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, L, g.k[1], c->d_cx, c->d_cy,
+                                                            c->d_l2l);
+    GRT_HIP(c, hipGetLastError());
+  }
+  GRT_HIP(c, hipMalloc(&c->d_f, sizeof(cd) * c->n_g));
+  rhs_f_kernel<<<(c->n_g + 255) / 256, 256, 0, s>>>(g, g.k[0] * cos(c->inc.phi), c->n_g, c->d_f);
+  GRT_HIP(c, hipGetLastError());
+  GRT_HIP(c, hipStreamSynchronize(s));
+  return GRT_OK;
+}

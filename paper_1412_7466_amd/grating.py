@@ -1,0 +1,271 @@
+"""Thin ctypes binding of libgrating.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts a
+``paper_1412_7466_amd.inputs.Problem`` into the C structs of include/grating.h,
+allocates device vectors with torch, and passes pointers and the stream.  It
+raises if the library is missing: there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrating.so")
+
+GRT_OK, GRT_EINVAL, GRT_EGEOM, GRT_ENOMEM, GRT_EHIP, GRT_ENOCONV, GRT_ESTATE, GRT_EUNSUP = \
+    0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "GRT_OK", -1: "GRT_EINVAL", -2: "GRT_EGEOM", -3: "GRT_ENOMEM", -4: "GRT_EHIP",
+                -5: "GRT_ENOCONV", -6: "GRT_ESTATE", -7: "GRT_EUNSUP"}
+GRT_FP64, GRT_FP32 = 0, 1
+
+
+class grt_layers(C.Structure):
+    _fields_ = [("d", C.c_double), ("h", C.c_double), ("y0", C.c_double),
+                ("n_layer", C.c_double * 3), ("N", C.c_int), ("Nw", C.c_int * 3),
+                ("Q", C.c_int * 3), ("Nu", C.c_int), ("n_rb_lo", C.c_int), ("Nrb", C.c_int),
+                ("zeta_K", C.c_int), ("pinv_eps", C.c_double)]
+
+
+class grt_inclusions(C.Structure):
+    _fields_ = [("M", C.c_int64), ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
+                ("radius", C.POINTER(C.c_double)), ("n_incl", C.POINTER(C.c_double))]
+
+
+class grt_incidence(C.Structure):
+    _fields_ = [("omega", C.c_double), ("phi", C.c_double), ("P", C.c_int)]
+
+
+class grt_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("restart", C.c_int),
+                ("use_x0", C.c_int)]
+
+
+class grt_solve_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("rel_resid", C.c_double),
+                ("seconds", C.c_double)]
+
+
+class grt_sizes(C.Structure):
+    _fields_ = [("M", C.c_int64), ("P", C.c_int), ("n_beta", C.c_int64), ("n_rows", C.c_int64),
+                ("n_alpha", C.c_int64), ("rank", C.c_int64), ("Nrb", C.c_int)]
+
+
+# name -> (restype, argtypes); mirrors include/grating.h
+_VP = C.c_void_p
+_PROTOS = {
+    "grt_create": (C.c_int, [C.POINTER(_VP), C.c_int, _VP]),
+    "grt_destroy": (C.c_int, [_VP]),
+    "grt_error_message": (C.c_char_p, [_VP]),
+    "grt_set_problem": (C.c_int, [_VP, C.POINTER(grt_layers), C.POINTER(grt_inclusions),
+                                  C.POINTER(grt_incidence)]),
+    "grt_build": (C.c_int, [_VP]),
+    "grt_query": (C.c_int, [_VP, C.POINTER(grt_sizes)]),
+    "grt_apply": (C.c_int, [_VP, _VP, _VP, C.c_int]),
+    "grt_apply_T": (C.c_int, [_VP, _VP, _VP]),
+    "grt_apply_lowrank": (C.c_int, [_VP, _VP, _VP]),
+    "grt_rhs": (C.c_int, [_VP, _VP]),
+    "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
+    "grt_bragg": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
+                            C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                            C.POINTER(C.c_double)]),
+    "grt_get_A": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "grt_get_mie": (C.c_int, [_VP, C.POINTER(C.c_double)]),
+    "grt_profile_enable": (C.c_int, [_VP, C.c_int]),
+    "grt_profile_read": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgrating.so and declare every prototype; raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not built: run `python -m paper_1412_7466_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class GratingError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Context:
+    """One problem on one GPU.  Vectors are torch complex128 tensors on the device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = device
+        self.stream = torch.cuda.Stream(device=device)
+        h = _VP()
+        st = self.lib.grt_create(C.byref(h), device, _VP(self.stream.cuda_stream))
+        if st != GRT_OK:
+            raise GratingError(st, "grt_create failed")
+        self.h = h
+        self.sizes = None
+
+    # -- plumbing ------------------------------------------------------------
+    def _check(self, st):
+        if st != GRT_OK:
+            msg = self.lib.grt_error_message(self.h)
+            raise GratingError(st, msg.decode() if msg else "")
+
+    def _enter(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.grt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- problem ---------------------------------------------------------------
+    def set_problem(self, pb):
+        dd = pb.disc
+        lay = grt_layers(d=pb.d, h=pb.h, y0=dd.y0, n_layer=(C.c_double * 3)(*pb.n_layer),
+                         N=dd.N, Nw=(C.c_int * 3)(*dd.Nw), Q=(C.c_int * 3)(*dd.Q), Nu=dd.Nu,
+                         n_rb_lo=dd.n_rb_lo, Nrb=dd.Nrb, zeta_K=dd.zeta_K,
+                         pinv_eps=dd.pinv_eps)
+        self._arrs = [np.ascontiguousarray(a, dtype=np.float64)
+                      for a in (pb.x, pb.y, pb.radius, pb.n_incl)]
+        inc = grt_inclusions(M=pb.M, x=_dptr(self._arrs[0]), y=_dptr(self._arrs[1]),
+                             radius=_dptr(self._arrs[2]), n_incl=_dptr(self._arrs[3]))
+        wave = grt_incidence(omega=pb.omega, phi=pb.phi, P=pb.P)
+        self._check(self.lib.grt_set_problem(self.h, C.byref(lay), C.byref(inc), C.byref(wave)))
+        self.pb = pb
+        self.sizes = self.query()
+
+    def build(self):
+        self._enter()
+        self._check(self.lib.grt_build(self.h))
+        self._leave()
+        self.sizes = self.query()
+
+    def query(self):
+        s = grt_sizes()
+        self._check(self.lib.grt_query(self.h, C.byref(s)))
+        return s
+
+    def new_vec(self):
+        return self.torch.zeros(int(self.sizes.n_beta), dtype=self.torch.complex128,
+                                device=f"cuda:{self.device}")
+
+    def _vec_ptr(self, t):
+        if t.dtype != self.torch.complex128 or not t.is_contiguous() or t.numel() != self.sizes.n_beta:
+            raise ValueError("expected a contiguous complex128 vector of length n_beta")
+        return _VP(t.data_ptr())
+
+    # -- operator --------------------------------------------------------------
+    def apply(self, x, y=None):
+        y = self.new_vec() if y is None else y
+        self._enter()
+        self._check(self.lib.grt_apply(self.h, self._vec_ptr(x), self._vec_ptr(y), GRT_FP64))
+        self._leave()
+        return y
+
+    def apply_T(self, x, y=None):
+        y = self.new_vec() if y is None else y
+        self._enter()
+        self._check(self.lib.grt_apply_T(self.h, self._vec_ptr(x), self._vec_ptr(y)))
+        self._leave()
+        return y
+
+    def apply_lowrank(self, x, y=None):
+        y = self.new_vec() if y is None else y
+        self._enter()
+        self._check(self.lib.grt_apply_lowrank(self.h, self._vec_ptr(x), self._vec_ptr(y)))
+        self._leave()
+        return y
+
+    def rhs(self, b=None):
+        b = self.new_vec() if b is None else b
+        self._enter()
+        self._check(self.lib.grt_rhs(self.h, self._vec_ptr(b)))
+        self._leave()
+        return b
+
+    def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, out=None, check=True):
+        beta = self.new_vec() if out is None else out
+        if x0 is not None:
+            beta.copy_(x0)
+        opts = grt_solve_opts(tol=tol, maxit=maxit, restart=restart, use_x0=int(x0 is not None))
+        stats = grt_solve_stats()
+        self._enter()
+        st = self.lib.grt_solve(self.h, C.byref(opts), self._vec_ptr(beta), C.byref(stats))
+        self._leave()
+        if check or st != GRT_ENOCONV:
+            self._check(st)
+        return beta, stats
+
+    def bragg(self, beta=None):
+        n = int(self.sizes.Nrb)
+        orders = (C.c_int * n)()
+        c = np.zeros(2 * n)
+        d = np.zeros(2 * n)
+        R = np.zeros(n)
+        T = np.zeros(n)
+        flux = C.c_double(0)
+        bp = self._vec_ptr(beta) if beta is not None else _VP(0)
+        self._enter()
+        self._check(self.lib.grt_bragg(self.h, bp, n, orders, _dptr(c), _dptr(d), _dptr(R),
+                                       _dptr(T), C.byref(flux)))
+        self._leave()
+        return dict(orders=np.array(orders[:]), c=c[0::2] + 1j * c[1::2], d=d[0::2] + 1j * d[1::2],
+                    R=R, T=T, flux_err=flux.value)
+
+    def get_A(self):
+        s = self.sizes
+        A = np.zeros(2 * s.n_rows * s.n_alpha)
+        E = np.zeros(s.n_alpha)
+        self._check(self.lib.grt_get_A(self.h, _dptr(A), _dptr(E)))
+        A = (A[0::2] + 1j * A[1::2]).reshape(s.n_alpha, s.n_rows).T
+        return A, E
+
+    def profile(self, enable=True):
+        self._check(self.lib.grt_profile_enable(self.h, int(enable)))
+
+    def profile_read(self):
+        """(total ms, launches) of the translation kernel since the last read."""
+        ms = C.c_double(0)
+        n = C.c_int64(0)
+        self._check(self.lib.grt_profile_read(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def get_mie(self):
+        s = np.zeros(2 * self.sizes.n_beta)
+        self._check(self.lib.grt_get_mie(self.h, _dptr(s)))
+        return s[0::2] + 1j * s[1::2]
+
+
+def exported_symbols():
+    """Names declared in include/grating.h (parsed from the header text)."""
+    import re
+    hdr = os.path.join(_HERE, "..", "include", "grating.h")
+    txt = open(hdr).read()
+    return sorted(set(re.findall(r"^\s*(?:grt_status|const char\s*\*)\s*(grt_\w+)\s*\(", txt, re.M)))

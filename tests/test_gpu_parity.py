@@ -1,0 +1,148 @@
+"""Parity of the HIP library (through the C ABI) with the CPU FP64 oracle.
+
+Tolerance: 1e-9 relative on coefficient vectors and Bragg amplitudes (the bar of
+the method's FP64 path); pieces computed without the pseudo-inverse (Mie
+diagonal, matrix A, translation T) are held to 1e-12.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1412_7466_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+WOOD = math.asin((2 * math.pi - 10.0) / 10.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+def _ctx(pb):
+    from paper_1412_7466_amd.grating import Context
+    say(f"[gpu] case {pb.name} M={pb.M} P={pb.P} phi={pb.phi:.6f} N={pb.disc.N}")
+    ctx = Context(0)
+    ctx.set_problem(pb)
+    ctx.build()
+    return ctx
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _randvec(torch, n, seed, P):
+    rng = np.random.default_rng(seed)
+    nb = 2 * P + 1
+    v = (rng.standard_normal((n // nb, nb)) + 1j * rng.standard_normal((n // nb, nb)))
+    v *= 0.5 ** np.abs(np.arange(-P, P + 1))[None, :]
+    return v.reshape(-1), torch.tensor(v.reshape(-1), dtype=torch.complex128, device="cuda:0")
+
+
+def test_tiny_pieces_and_solve(torch_cuda, tiny_oracle):
+    torch = torch_cuda
+    pb, red = tiny_oracle
+    ctx = _ctx(pb)
+    G = red.G
+    assert ctx.sizes.n_rows == G.n_rows and ctx.sizes.n_alpha == G.n_alpha
+    # Mie diagonal
+    s = ctx.get_mie()
+    assert rel(s, red.s) < 1e-13
+    # equilibrated A and its column scales
+    A, E = ctx.get_A()
+    assert np.max(np.abs(E / red.pinv.E - 1)) < 1e-12
+    Ao = red.A * red.pinv.E[None, :]
+    assert np.max(np.abs(A - Ao)) < 1e-12
+    # translation and low-rank parts
+    xh, xd = _randvec(torch, G.n_beta, 1, G.P)
+    yT = _np(ctx.apply_T(xd))
+    assert rel(yT, red.T_apply(xh)) < 1e-12
+    yL = _np(ctx.apply_lowrank(xd))
+    assert rel(yL, red.lowrank_apply(xh)) < 1e-9
+    yK = _np(ctx.apply(xd))
+    assert rel(yK, red.K_apply(xh)) < 1e-9
+    b = _np(ctx.rhs())
+    assert rel(b, red.rhs()) < 1e-9
+    # solve
+    beta_o = red.solve_lu()
+    beta, st = ctx.solve(tol=1e-12, restart=100)
+    say(f"[gpu] tiny iters={st.iters} resid={st.rel_resid:.2e}")
+    assert st.rel_resid <= 1e-12
+    assert rel(_np(beta), beta_o) < 1e-9
+    # Bragg amplitudes
+    og = ctx.bragg(beta)
+    oo = red.bragg(beta_o)
+    assert np.array_equal(og["orders"], oo["orders"])
+    sel1, sel3 = oo["prop1"], oo["prop3"]
+    vg = np.concatenate([og["c"][sel1], og["d"][sel3]])
+    vo = np.concatenate([oo["c"][sel1], oo["d"][sel3]])
+    assert rel(vg, vo) < 1e-9
+    assert og["flux_err"] < 1e-10
+
+
+@pytest.mark.parametrize("M,P,seed,phi", [(1, 5, 3, -math.pi / 5), (3, 1, 5, 0.3),
+                                          (67, 4, 6, -math.pi / 5), (20, 10, 8, WOOD),
+                                          (12, 15, 9, 0.5)])
+def test_small_solves(torch_cuda, M, P, seed, phi):
+    from oracle.solver import Reduced
+    pb = inputs.small(M, P, seed=seed, phi=phi)
+    red = Reduced(pb)
+    ctx = _ctx(pb)
+    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    assert rel(_np(ctx.apply_T(xd)), red.T_apply(xh)) < 1e-12
+    assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+    beta_o = red.solve_lu()
+    beta, st = ctx.solve(tol=1e-12, restart=150)
+    say(f"[gpu] M={M} P={P} iters={st.iters} resid={st.rel_resid:.2e}")
+    assert rel(_np(beta), beta_o) < 1e-9
+    og = ctx.bragg(beta)
+    oo = red.bragg(beta_o)
+    vg = np.concatenate([og["c"][oo["prop1"]], og["d"][oo["prop3"]]])
+    vo = np.concatenate([oo["c"][oo["prop1"]], oo["d"][oo["prop3"]]])
+    assert rel(vg, vo) < 1e-9
+    assert og["flux_err"] < 1e-9
+
+
+@pytest.mark.parametrize("phi", [-math.pi / 5, WOOD])
+def test_empty_slab(torch_cuda, phi):
+    from oracle.solver import Reduced
+    pb = inputs.empty_slab(phi=phi)
+    red = Reduced(pb)
+    ctx = _ctx(pb)
+    og = ctx.bragg(None)
+    oo = red.bragg(np.zeros(0))
+    assert abs(og["flux_err"]) < 1e-11
+    vg = np.concatenate([og["c"][oo["prop1"]], og["d"][oo["prop3"]]])
+    vo = np.concatenate([oo["c"][oo["prop1"]], oo["d"][oo["prop3"]]])
+    assert rel(vg, vo) < 1e-10
+
+
+def test_invalid_geometry_rejected(torch_cuda):
+    from paper_1412_7466_amd.grating import Context, GratingError, GRT_EGEOM
+    pb = inputs.small(4, 4, seed=3)
+    pb.x = pb.x.copy()
+    pb.y = pb.y.copy()
+    pb.x[1] = pb.x[0] + 0.5 * pb.radius[0]
+    pb.y[1] = pb.y[0]
+    ctx = Context(0)
+    with pytest.raises(GratingError) as ei:
+        ctx.set_problem(pb)
+    assert ei.value.status == GRT_EGEOM
