@@ -22,187 +22,297 @@
 
 namespace {
 
-constexpr int M2L_THREADS = 64;
-constexpr int M2L_MAXCHUNK = 32;
+constexpr int M2L_WAVES = 4;     // waves per block: same 64 targets, sources split 4 ways
+constexpr int M2L_THREADS = 64 * M2L_WAVES;
+constexpr int M2L_TILE = 16;     // sources staged in LDS at a time, per wave
+constexpr int M2L_QB = 4;        // generator orders produced per block of the contraction
 
+// Translation of the outgoing coefficients of sources [m0, m1) (and of their
+// copies l = -1, 0, 1) into incoming coefficients at 64 targets (one per lane);
+// the block's four waves take a quarter of the sources each and are summed
+// through LDS at the end.
+//  * per (target, source) the generators of the three copies are summed first:
+//      tau_q = sum_l alpha^l H_q(k rho_l) e^{i q phi_l},  q = -2P..2P,
+//    produced M2L_QB orders at a time by the upward recurrence;
+//  * the Toeplitz product acc[n] += tau_{nu-n} x[nu] is then done source-value
+//    major: each x[nu] is read once from LDS per block of orders (a broadcast:
+//    every lane reads the same address) and feeds up to 2*M2L_QB complex FMAs.
 template <int P>
 __global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restrict__ cx,
                                                           const double* __restrict__ cy,
                                                           const cd* __restrict__ x, cd* partial,
                                                           int M, int chunk, double k, double d,
-                                                          cd alpha, cd alpha_inv) {
+                                                          cd alpha, cd alpha_inv,
+                                                          const double* __restrict__ htab) {
   constexpr int NB = 2 * P + 1;
-  __shared__ cd sx[M2L_MAXCHUNK * NB];
-  __shared__ double scx[M2L_MAXCHUNK], scy[M2L_MAXCHUNK];
-  const int j = blockIdx.x * M2L_THREADS + threadIdx.x;
+  constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
+  constexpr int STAGE = M2L_WAVES * M2L_TILE * (2 * NB + 2);  // doubles: x tiles + centres
+  constexpr int RED = 2 * NB * 64;                             // doubles: one wave's acc
+  constexpr int BUF = STAGE > RED ? STAGE : RED;
+  __shared__ double smem[BUF];
+  __shared__ double stab[HTAB_SIZE];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  cd* sx = reinterpret_cast<cd*>(smem) + wv * M2L_TILE * NB;
+  double* scx = smem + 2 * M2L_WAVES * M2L_TILE * NB + wv * 2 * M2L_TILE;
+  double* scy = scx + M2L_TILE;
+  const int j = blockIdx.x * 64 + lane;
   const int m0 = blockIdx.y * chunk;
-  const int cnt = min(chunk, M - m0);
-  for (int t = threadIdx.x; t < cnt * NB; t += M2L_THREADS) sx[t] = x[(size_t)m0 * NB + t];
-  for (int t = threadIdx.x; t < cnt; t += M2L_THREADS) {
-    scx[t] = cx[m0 + t];
-    scy[t] = cy[m0 + t];
-  }
-  __syncthreads();
+  const int m1 = min(M, m0 + chunk);
+  const int per = (m1 - m0 + M2L_WAVES - 1) / M2L_WAVES;
+  const int s0 = m0 + wv * per;
+  const int s1 = min(m1, s0 + per);
+  const int ntile = (per + M2L_TILE - 1) / M2L_TILE;  // same for every wave: barriers match
+  for (int t = threadIdx.x; t < HTAB_SIZE; t += M2L_THREADS) stab[t] = htab[t];
   const bool live = j < M;
   const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
   cd acc[NB];
 #pragma unroll
   for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
   const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
-  for (int mm = 0; mm < cnt; ++mm) {
-    const int m = m0 + mm;
-    const cd* b = sx + mm * NB;
-    cd hp[3], hc[3], cc[3], cq[3];
-    double rz2[3];
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      double dx = xj - scx[mm] - (l - 1) * d;
-      double dy = yj - scy[mm];
-      bool self = (j == m) && (l == 1);
-      double r = sqrt(dx * dx + dy * dy);
-      if (self || !live) r = 1.0;
-      double z = k * r;
-      double ir = 1.0 / r;
-      cd h0, h1;
-      hankel01(z, h0, h1);
-      cd w = (self || !live) ? cd{0.0, 0.0} : wl[l];
-      hp[l] = w * h0;
-      hc[l] = w * h1;
-      cc[l] = cd{dx * ir, dy * ir};
-      cq[l] = cc[l];
-      rz2[l] = 2.0 / z;
+  for (int it = 0; it < ntile; ++it) {
+    const int ts = s0 + it * M2L_TILE;
+    const int cnt = max(0, min(M2L_TILE, s1 - ts));
+    __syncthreads();
+    for (int t = lane; t < cnt * NB; t += 64) sx[t] = x[(size_t)ts * NB + t];
+    for (int t = lane; t < cnt; t += 64) {
+      scx[t] = cx[ts + t];
+      scy[t] = cy[ts + t];
     }
-    {
-      cd t0 = hp[0] + hp[1] + hp[2];
-#pragma unroll
-      for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
-    }
-#pragma unroll
-    for (int q = 1; q <= 2 * P; ++q) {
-      cd tp{0.0, 0.0}, tm{0.0, 0.0};
+    __syncthreads();
+    for (int mm = 0; mm < cnt; ++mm) {
+      const int m = ts + mm;
+      const cd* b = sx + mm * NB;
+      cd hp[3], hc[3], cc[3], cq[3];
+      double rz2[3];
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
-        // hc * cq and hc * conj(cq) share the four real products
-        double ac = hc[l].r * cq[l].r, bd = hc[l].i * cq[l].i;
-        double ad = hc[l].r * cq[l].i, bc = hc[l].i * cq[l].r;
-        tp.r += ac - bd;
-        tp.i += ad + bc;
-        tm.r += ac + bd;
-        tm.i += bc - ad;
+        double dx = xj - scx[mm] - (l - 1) * d;
+        double dy = yj - scy[mm];
+        bool off = (j == m && l == 1) || !live;
+        double r = sqrt(dx * dx + dy * dy);
+        if (off) r = 1.0;
+        double z = k * r;
+        double ir = 1.0 / r;
+        cd h0, h1;
+        hankel01_tab(z, stab, h0, h1);
+        cd w = off ? cd{0.0, 0.0} : wl[l];
+        hp[l] = w * h0;
+        hc[l] = w * h1;
+        cc[l] = cd{dx * ir, dy * ir};
+        cq[l] = cc[l];
+        rz2[l] = 2.0 / z;
       }
-      if (q & 1) tm = -tm;  // H_{-q} = (-1)^q H_q
-      // acc[n] += t_q x[n+q]  (n = -P..P-q),  acc[n] += t_{-q} x[n-q]  (n = -P+q..P)
+      {
+        cd t0 = hp[0] + hp[1] + hp[2];
 #pragma unroll
-      for (int n = 0; n + q < NB; ++n) cmac(acc[n], tp, b[n + q]);
+        for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
+      }
 #pragma unroll
-      for (int n = q; n < NB; ++n) cmac(acc[n], tm, b[n - q]);
-      if (q < 2 * P) {
+      for (int qb = 0; qb < NQB; ++qb) {
+        cd tp[M2L_QB], tm[M2L_QB];
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          cd hn = (q * rz2[l]) * hc[l] - hp[l];
-          hp[l] = hc[l];
-          hc[l] = hn;
-          cq[l] = cq[l] * cc[l];
+        for (int u = 0; u < M2L_QB; ++u) {
+          const int q = 1 + qb * M2L_QB + u;
+          tp[u] = cd{0.0, 0.0};
+          tm[u] = cd{0.0, 0.0};
+          if (q <= 2 * P) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+              double ac = hc[l].r * cq[l].r, bd = hc[l].i * cq[l].i;
+              double ad = hc[l].r * cq[l].i, bc = hc[l].i * cq[l].r;
+              tp[u].r += ac - bd;
+              tp[u].i += ad + bc;
+              tm[u].r += ac + bd;
+              tm[u].i += bc - ad;
+            }
+            if (q & 1) tm[u] = -tm[u];  // H_{-q} = (-1)^q H_q
+            if (q < 2 * P) {
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                cd hn = (q * rz2[l]) * hc[l] - hp[l];
+                hp[l] = hc[l];
+                hc[l] = hn;
+                cq[l] = cq[l] * cc[l];
+              }
+            }
+          }
+        }
+        // LDS contents may be re-read here: keeps x[nu] out of registers across blocks
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int nu = 0; nu < NB; ++nu) {
+          bool need = false;
+#pragma unroll
+          for (int u = 0; u < M2L_QB; ++u) {
+            const int q = 1 + qb * M2L_QB + u;
+            if (q <= 2 * P && (nu - q >= 0 || nu + q < NB)) need = true;
+          }
+          if (!need) continue;
+          const cd bv = b[nu];
+#pragma unroll
+          for (int u = 0; u < M2L_QB; ++u) {
+            const int q = 1 + qb * M2L_QB + u;
+            if (q > 2 * P) continue;
+            if (nu - q >= 0) cmac(acc[nu - q], tp[u], bv);   // acc[n] += t_q x[n+q]
+            if (nu + q < NB) cmac(acc[nu + q], tm[u], bv);   // acc[n] += t_{-q} x[n-q]
+          }
         }
       }
     }
   }
-  if (live) {
+  // sum the four waves' partial results through LDS: wave 3, then 2, then 1 add into
+  // the buffer in turn, wave 0 adds its own and stores
+  cd* red = reinterpret_cast<cd*>(smem);
+  for (int src = M2L_WAVES - 1; src >= 1; --src) {
+    __syncthreads();
+    if (wv == src) {
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        cd v = acc[n];
+        if (src != M2L_WAVES - 1) v += red[n * 64 + lane];
+        red[n * 64 + lane] = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (wv == 0 && live) {
     cd* out = partial + ((size_t)blockIdx.y * M + j) * NB;
 #pragma unroll
-    for (int n = 0; n < NB; ++n) out[n] = acc[n];
+    for (int n = 0; n < NB; ++n) out[n] = acc[n] + red[n * 64 + lane];
   }
 }
 
-// Field of all multipoles (and their copies) at the C targets.
+constexpr int CX_TILE = 32;  // inclusions staged in LDS at a time
+
+// Field of all multipoles (and their copies) at the C targets, one per lane:
 //   target t < N: Gamma_1 node, t < 2N: Gamma_2 node (value, d/dy over 3 copies),
-//   t < 2N + Nw2: middle wall node (value, d/dx, cancelled two-term form).
-// partial[chunk][t][0..1] = (value, derivative)
+//   t < 2N + Nw2: middle wall node (value, d/dx, cancelled two-term form
+//   alpha^2 Phi(L-d) - alpha^{-1} Phi(L+2d), Phi the l = 0 field).
+// With F_n = H_n(k r) e^{in theta}: value = sum x[n] F_n and, by
+// (d_x +- i d_y) F_n = -+ k F_{n+-1}, d/dx = (k/2)(A - B), d/dy = (ik/2)(A + B)
+// with A = sum x[n] F_{n-1}, B = sum x[n] F_{n+1}.
+// partial[chunk][t][0..1] = (value, derivative) over the chunk's inclusions.
+template <int P>
 __global__ void __launch_bounds__(64) cx_kernel(DevGeom g, const double* __restrict__ cx,
                                                 const double* __restrict__ cy,
-                                                const cd* __restrict__ x, cd* partial, int chunk) {
-  const int P = g.P, NB = 2 * P + 1;
+                                                const cd* __restrict__ x, cd* partial, int chunk,
+                                                const double* __restrict__ htab) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ cd sx[CX_TILE * NB];
+  __shared__ double scx[CX_TILE], scy[CX_TILE];
+  __shared__ double stab[HTAB_SIZE];
   const int nt = 2 * g.N + g.Nw[1];
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int m0 = blockIdx.y * chunk;
-  int m1 = min(g.M, m0 + chunk);
-  if (t >= nt) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m0 = blockIdx.y * chunk;
+  const int m1 = min(g.M, m0 + chunk);
+  for (int i = threadIdx.x; i < HTAB_SIZE; i += 64) stab[i] = htab[i];
+  const bool live = t < nt;
+  const int tt = live ? t : 0;
   double tx[3], ty;
   cd w[3];
-  int nimg;
-  bool wall = t >= 2 * g.N;
+  const bool wall = tt >= 2 * g.N;
   if (!wall) {
-    int i = t % g.N;
+    int i = tt % g.N;
     double x0 = -0.5 * g.d + (i + 0.5) * g.hs;
-    ty = (t < g.N) ? g.h : -g.h;
+    ty = (tt < g.N) ? g.h : -g.h;
     // copies of the source at x_m + l d are equivalent to targets at x - l d
     tx[0] = x0 + g.d; w[0] = g.alpha_inv;  // l = -1
     tx[1] = x0;       w[1] = cd{1.0, 0.0};
     tx[2] = x0 - g.d; w[2] = g.alpha;      // l = +1
-    nimg = 3;
   } else {
-    ty = g.yw[1][t - 2 * g.N];
+    ty = g.yw[1][tt - 2 * g.N];
     tx[0] = -1.5 * g.d; w[0] = g.alpha * g.alpha;
     tx[1] = 1.5 * g.d;  w[1] = -g.alpha_inv;
-    nimg = 2;
+    tx[2] = 1.5 * g.d;  w[2] = cd{0.0, 0.0};  // unused
   }
+  const int nimg = wall ? 2 : 3;
   const double k = g.k[1];
-  cd val{0, 0}, A{0, 0}, B{0, 0};  // A = sum x[n] F_{n-1}, B = sum x[n] F_{n+1}
-  for (int m = m0; m < m1; ++m) {
-    const cd* b = x + (size_t)m * NB;
-    for (int im = 0; im < nimg; ++im) {
-      double vx = tx[im] - cx[m], vy = ty - cy[m];
-      double r = sqrt(vx * vx + vy * vy);
-      double z = k * r;
-      cd e{vx / r, vy / r};
-      cd hprev, hcur;
-      hankel01(z, hprev, hcur);
-      // order 0
-      cd sv{0, 0}, sa{0, 0}, sb{0, 0};
-      cd F0 = hprev;
-      cmac(sv, F0, b[P]);
-      if (P >= 1) { cmac(sa, F0, b[P + 1]); cmac(sb, F0, b[P - 1]); }
-      cd ep = e;
-      double rz2 = 2.0 / z;
-      for (int mo = 1; mo <= P + 1; ++mo) {
-        // hcur = H_mo
-        cd Fp = hcur * ep;                   // F_mo
-        cd Fm = hcur * conj(ep);             // F_{-mo} = (-1)^mo H_mo e^{-i mo theta}
-        if (mo & 1) Fm = -Fm;
-        if (mo <= P) { cmac(sv, Fp, b[P + mo]); cmac(sv, Fm, b[P - mo]); }
-        // A: x[n] F_{n-1}: F_mo pairs with n = mo + 1, F_{-mo} with n = 1 - mo
-        if (mo + 1 <= P) cmac(sa, Fp, b[P + mo + 1]);
-        if (1 - mo >= -P) cmac(sa, Fm, b[P + 1 - mo]);
-        // B: x[n] F_{n+1}: F_mo pairs with n = mo - 1, F_{-mo} with n = -mo - 1
-        if (mo - 1 <= P) cmac(sb, Fp, b[P + mo - 1]);
-        if (-mo - 1 >= -P) cmac(sb, Fm, b[P - mo - 1]);
-        cd hn = (mo * rz2) * hcur - hprev;
-        hprev = hcur;
-        hcur = hn;
-        ep = ep * e;
+  cd val{0, 0}, A{0, 0}, B{0, 0};
+  for (int ts = m0; ts < m1; ts += CX_TILE) {
+    const int cnt = min(CX_TILE, m1 - ts);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt * NB; i += 64) sx[i] = x[(size_t)ts * NB + i];
+    for (int i = threadIdx.x; i < cnt; i += 64) {
+      scx[i] = cx[ts + i];
+      scy[i] = cy[ts + i];
+    }
+    __syncthreads();
+    for (int mm = 0; mm < cnt; ++mm) {
+      const cd* b = sx + mm * NB;
+#pragma unroll
+      for (int im = 0; im < 3; ++im) {
+        if (im >= nimg) break;
+        double vx = tx[im] - scx[mm], vy = ty - scy[mm];
+        double r = sqrt(vx * vx + vy * vy);
+        double z = k * r;
+        double ir = 1.0 / r;
+        cd e{vx * ir, vy * ir};
+        cd hprev, hcur;
+        hankel01_tab(z, stab, hprev, hcur);
+        cd sv{0, 0}, sa{0, 0}, sb{0, 0};
+        cmac(sv, hprev, b[P]);
+        if (P >= 1) {
+          cmac(sa, hprev, b[P + 1]);
+          cmac(sb, hprev, b[P - 1]);
+        }
+        cd ep = e;
+        double rz2 = 2.0 / z;
+#pragma unroll
+        for (int mo = 1; mo <= P + 1; ++mo) {
+          cd Fp = hcur * ep;                 // F_mo
+          cd Fm = hcur * conj(ep);           // F_{-mo} = (-1)^mo H_mo e^{-i mo theta}
+          if (mo & 1) Fm = -Fm;
+          if (mo <= P) {
+            cmac(sv, Fp, b[P + mo]);
+            cmac(sv, Fm, b[P - mo]);
+          }
+          if (mo + 1 <= P) cmac(sa, Fp, b[P + mo + 1]);
+          if (1 - mo >= -P) cmac(sa, Fm, b[P + 1 - mo]);
+          if (mo - 1 <= P) cmac(sb, Fp, b[P + mo - 1]);
+          if (-mo - 1 >= -P) cmac(sb, Fm, b[P - mo - 1]);
+          if (mo <= P) {
+            cd hn = (mo * rz2) * hcur - hprev;
+            hprev = hcur;
+            hcur = hn;
+            ep = ep * e;
+          }
+        }
+        val += w[im] * sv;
+        A += w[im] * sa;
+        B += w[im] * sb;
       }
-      val += w[im] * sv;
-      A += w[im] * sa;
-      B += w[im] * sb;
     }
   }
-  // derivative: d/dx = (k/2)(A - B), d/dy = (ik/2)(A + B)
+  if (!live) return;
   cd der = wall ? (0.5 * k) * (A - B) : times_i((0.5 * k) * (A + B));
   cd* o = partial + ((size_t)blockIdx.y * nt + t) * 2;
   o[0] = val;
   o[1] = der;
 }
 
-// g (rows Gamma_1 v/n, Gamma_2 v/n, wall-2 v/d) from the chunk partials.
-__global__ void cx_reduce_kernel(DevGeom g, const cd* partial, int nchunks, cd* gv) {
+// g (rows Gamma_1 v/n, Gamma_2 v/n, wall-2 v/d) from the chunk partials: one
+// wavefront per target, lanes over chunks, fixed-order tree sum.
+__global__ void __launch_bounds__(256) cx_reduce_kernel(DevGeom g, const cd* partial, int nchunks,
+                                                        cd* gv) {
   const int nt = 2 * g.N + g.Nw[1];
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (t >= nt) return;
-  cd v{0, 0}, dv{0, 0};
-  for (int c = 0; c < nchunks; ++c) {
-    v += partial[((size_t)c * nt + t) * 2];
-    dv += partial[((size_t)c * nt + t) * 2 + 1];
+  double vr = 0, vi = 0, dr = 0, di = 0;
+  for (int c = lane; c < nchunks; c += 64) {
+    cd v = partial[((size_t)c * nt + t) * 2];
+    cd dv = partial[((size_t)c * nt + t) * 2 + 1];
+    vr += v.r; vi += v.i; dr += dv.r; di += dv.i;
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    vr += __shfl_xor(vr, off, 64);
+    vi += __shfl_xor(vi, off, 64);
+    dr += __shfl_xor(dr, off, 64);
+    di += __shfl_xor(di, off, 64);
+  }
+  if (lane != 0) return;
+  cd v{vr, vi}, dv{dr, di};
   const int N = g.N;
   if (t < N) {  // Gamma_1: row is u_1 - u_2, the inclusions live in layer 2
     gv[g.row_off[RB_G1V] + t] = -v;
@@ -223,7 +333,8 @@ __global__ void cx_reduce_kernel(DevGeom g, const cd* partial, int nchunks, cd* 
 template <int P>
 __global__ void __launch_bounds__(64) bx_kernel(DevGeom g, const double* __restrict__ cx,
                                                 const double* __restrict__ cy,
-                                                const cd* __restrict__ w, cd* partial, int chunk) {
+                                                const cd* __restrict__ w, cd* partial, int chunk,
+                                                const double* __restrict__ htab) {
   constexpr int NB = 2 * P + 1;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int s0 = blockIdx.y * chunk;
@@ -253,7 +364,7 @@ __global__ void __launch_bounds__(64) bx_kernel(DevGeom g, const double* __restr
     cd e{vx / r, vy / r};
     cd ec = conj(e);
     cd hprev, hcur;
-    hankel01(z, hprev, hcur);
+    hankel01_tab(z, htab, hprev, hcur);
     // G_n for n = 0..P+1 (positive) and negative via (-1)^n H_n e^{in theta}
     cd Gp[P + 2], Gm[P + 2];
     Gp[0] = hprev;
@@ -287,17 +398,25 @@ __global__ void __launch_bounds__(64) bx_kernel(DevGeom g, const double* __restr
 }
 
 // L2L: out[j][n] = sum_q a2_q E_j[q - n], E_j[m] = J_m(k2 rho_j) e^{i m phi_j}.
-__global__ void l2l_kernel(int M, int P, int Q2, const cd* __restrict__ E,
-                           const cd* __restrict__ a2, cd* out) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  int NB = 2 * P + 1;
-  if (idx >= M * NB) return;
-  int j = idx / NB, n = idx - j * NB - P;
-  int L = Q2 + P;
-  const cd* e = E + (size_t)j * (2 * L + 1) + L;
-  cd acc{0, 0};
-  for (int q = -Q2; q <= Q2; ++q) cmac(acc, a2[q + Q2], e[q - n]);
-  out[idx] = acc;
+// One block per inclusion: its E_j row and a2 are staged in LDS.
+__global__ void __launch_bounds__(64) l2l_kernel(int M, int P, int Q2, const cd* __restrict__ E,
+                                                 const cd* __restrict__ a2, cd* out) {
+  extern __shared__ cd l2l_smem[];
+  const int j = blockIdx.x;
+  const int NB = 2 * P + 1;
+  const int L = Q2 + P;
+  cd* se = l2l_smem;               // 2L + 1
+  cd* sa = l2l_smem + 2 * L + 1;   // 2 Q2 + 1
+  const cd* e = E + (size_t)j * (2 * L + 1);
+  for (int i = threadIdx.x; i < 2 * L + 1; i += blockDim.x) se[i] = e[i];
+  for (int i = threadIdx.x; i < 2 * Q2 + 1; i += blockDim.x) sa[i] = a2[i];
+  __syncthreads();
+  for (int nn = threadIdx.x; nn < NB; nn += blockDim.x) {
+    const int n = nn - P;
+    cd acc{0, 0};
+    for (int q = -Q2; q <= Q2; ++q) cmac(acc, sa[q + Q2], se[L + q - n]);
+    out[(size_t)j * NB + nn] = acc;
+  }
 }
 
 // y = x - s o (sum_c pT[c] - sum_c pB[c] - pL); any of the parts may be absent.
@@ -337,19 +456,28 @@ hipEvent_t* prof_pair(grt_ctx* c) {
 
 template <int P>
 void launch_m2l(grt_ctx* c, const cd* x) {
-  dim3 grid((unsigned)((c->M + M2L_THREADS - 1) / M2L_THREADS), c->m2l_nchunks);
+  dim3 grid((unsigned)((c->M + 63) / 64), c->m2l_nchunks);
   hipEvent_t* ev = prof_pair(c);
   if (ev) hipEventRecord(ev[0], c->stream);
   m2l_kernel<P><<<grid, M2L_THREADS, 0, c->stream>>>(c->d_cx, c->d_cy, x, c->d_pT, (int)c->M,
                                                      c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
-                                                     c->g.alpha_inv);
+                                                     c->g.alpha_inv, c->d_htab);
   if (ev) hipEventRecord(ev[1], c->stream);
+}
+
+template <int P>
+void launch_cx(grt_ctx* c, const cd* x) {
+  const int nt = 2 * c->g.N + c->g.Nw[1];
+  dim3 grid((nt + 63) / 64, c->c_nchunks);
+  cx_kernel<P><<<grid, 64, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, x, c->d_pC, c->c_chunk,
+                                            c->d_htab);
 }
 
 template <int P>
 void launch_bx(grt_ctx* c, const cd* w) {
   dim3 grid((unsigned)((c->M + 63) / 64), c->b_nchunks);
-  bx_kernel<P><<<grid, 64, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, w, c->d_pB, c->b_chunk);
+  bx_kernel<P><<<grid, 64, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, w, c->d_pB, c->b_chunk,
+                                           c->d_htab);
 }
 
 #define GRT_P_DISPATCH(FN, P, ...)                        \
@@ -386,13 +514,21 @@ grt_status apply_alloc(grt_ctx* c) {
   GRT_HIP(c, hipMalloc(&c->d_tvec, sizeof(cd) * (size_t)std::max(1, c->rank)));
   GRT_HIP(c, hipMalloc(&c->d_wvec, sizeof(cd) * (size_t)c->n_b));
   if (M == 0) return GRT_OK;
-  int chunk = c->m2l_chunk;
-  if (chunk > M2L_MAXCHUNK) chunk = M2L_MAXCHUNK;
-  c->m2l_chunk = chunk;
-  c->m2l_nchunks = (int)((M + chunk - 1) / chunk);
+  // Work split: every kernel gets enough (target tile, source chunk) blocks to
+  // give each of the 1024 SIMDs about two waves; partial sums per chunk are
+  // added in a fixed order afterwards (deterministic results).
+  auto split = [](int64_t nsrc, int64_t tiles, int64_t want_waves, int64_t min_chunk,
+                  int& chunk, int& nchunks) {
+    int64_t nc = std::max<int64_t>(1, (want_waves + tiles - 1) / tiles);
+    nc = std::min<int64_t>(nc, std::max<int64_t>(1, (nsrc + min_chunk - 1) / min_chunk));
+    int64_t ch = (nsrc + nc - 1) / nc;
+    chunk = (int)ch;
+    nchunks = (int)((nsrc + ch - 1) / ch);
+  };
   const int nt = 2 * c->g.N + c->g.Nw[1];
-  c->c_nchunks = (int)((M + c->c_chunk - 1) / c->c_chunk);
-  c->b_nchunks = (6 * c->g.N + c->b_chunk - 1) / c->b_chunk;
+  split(M, (M + 63) / 64, 2048 / M2L_WAVES, 4 * M2L_WAVES, c->m2l_chunk, c->m2l_nchunks);
+  split(M, (nt + 63) / 64, 2048, 4, c->c_chunk, c->c_nchunks);
+  split(6 * (int64_t)c->g.N, (M + 63) / 64, 1024, 16, c->b_chunk, c->b_nchunks);
   GRT_HIP(c, hipMalloc(&c->d_pT, sizeof(cd) * (size_t)c->m2l_nchunks * c->n_beta));
   GRT_HIP(c, hipMalloc(&c->d_pC, sizeof(cd) * (size_t)c->c_nchunks * nt * 2));
   GRT_HIP(c, hipMalloc(&c->d_pB, sizeof(cd) * (size_t)c->b_nchunks * c->n_beta));
@@ -406,19 +542,20 @@ static grt_status lowrank_tail(grt_ctx* c, const cd* gvec) {
   launch_gemv_rows(s, c->d_W1, gvec, c->d_tvec, c->rank, c->n_g);
   launch_gemv_rows(s, c->d_W2, c->d_tvec, c->d_wvec, c->n_b, c->rank);
   GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec);
-  int NB = c->nb;
-  int tot = (int)(c->M * NB);
-  l2l_kernel<<<(tot + 255) / 256, 256, 0, s>>>((int)c->M, c->P, c->g.Q[1], c->d_l2l,
-                                               c->d_wvec + c->g.col_off[CB_A2], c->d_pL);
+  {
+    const int L = c->g.Q[1] + c->P;
+    size_t sh = sizeof(cd) * (size_t)(2 * L + 1 + 2 * c->g.Q[1] + 1);
+    l2l_kernel<<<(unsigned)c->M, 64, sh, s>>>((int)c->M, c->P, c->g.Q[1], c->d_l2l,
+                                             c->d_wvec + c->g.col_off[CB_A2], c->d_pL);
+  }
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
 
 static grt_status cx_apply(grt_ctx* c, const cd* x) {
   const int nt = 2 * c->g.N + c->g.Nw[1];
-  dim3 grid((nt + 63) / 64, c->c_nchunks);
-  cx_kernel<<<grid, 64, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, x, c->d_pC, c->c_chunk);
-  cx_reduce_kernel<<<(nt + 255) / 256, 256, 0, c->stream>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
+  GRT_P_DISPATCH(launch_cx, c->P, c, x);
+  cx_reduce_kernel<<<(nt + 3) / 4, 256, 0, c->stream>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }

@@ -27,11 +27,12 @@ void free_all(grt_ctx* c) {
   void* bufs[] = {c->d_cx, c->d_cy, c->d_rad, c->d_kp, c->d_yw, c->d_wcorr, c->d_A,
                   c->d_colscale, c->d_sv, c->d_U, c->d_VH, c->d_W1, c->d_W2, c->d_W3,
                   c->d_mie, c->d_l2l, c->d_f, c->d_pT, c->d_pC, c->d_pB, c->d_pL,
-                  c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_cs, c->d_sn,
+                  c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_cs, c->d_sn, c->d_htab,
                   c->d_gv, c->d_y, c->d_scal, c->d_dotpart};
   for (void* p : bufs)
     if (p) hipFree(p);
-  c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal = nullptr;
+  c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal =
+      c->d_htab = nullptr;
   c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_mie = c->d_l2l =
       c->d_f = c->d_pT = c->d_pC = c->d_pB = c->d_pL = c->d_gvec = c->d_tvec = c->d_wvec =
           c->d_V = c->d_H = c->d_cs = c->d_sn = c->d_gv = c->d_y = c->d_dotpart = nullptr;

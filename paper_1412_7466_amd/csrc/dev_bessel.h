@@ -181,3 +181,121 @@ __host__ __device__ inline void bessel_j_three(double x, int q, double& jm, doub
     jpl = -sg * a;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Fast H_0, H_1 for the apply kernels.
+//
+// For z >= 1/2 the factor B_nu(t) = H_nu(1/t) e^{-i/t} t^{-1/2}, t = 1/z, is smooth
+// and slowly varying on t in [0, 2] (it tends to sqrt(2/pi) e^{-i(nu pi/2 + pi/4)} as
+// t -> 0, DLMF 10.17.5).  It is tabulated as piecewise Chebyshev interpolants of
+// degree HTAB_DEG on HTAB_NI equal intervals of t, converted to monomials in the
+// local variable x in [-1, 1]; the table is built on the device from bessel01 above.
+// Then H_nu(z) = B_nu(1/z) e^{iz} z^{-1/2}.  For z < 1/2 the ascending series
+// (DLMF 10.2.2, 10.8.1) are summed directly.
+// ---------------------------------------------------------------------------
+#define HTAB_NI 32
+#define HTAB_DEG 8
+#define HTAB_TMAX 2.0
+#define HTAB_STRIDE (4 * (HTAB_DEG + 1))  // doubles per interval: [coef][B0r, B0i, B1r, B1i]
+#define HTAB_SIZE (HTAB_NI * HTAB_STRIDE)
+
+// Coefficients of interval k (out[HTAB_STRIDE]).
+__host__ __device__ inline void htab_interval(int k, double* out) {
+  const int D = HTAB_DEG, n = D + 1;
+  const double w = HTAB_TMAX / HTAB_NI;
+  double f[4][HTAB_DEG + 1];
+  for (int j = 0; j < n; ++j) {
+    double x = cos(GRT_PI * (j + 0.5) / n);
+    double t = (k + 0.5) * w + 0.5 * w * x;
+    double z = 1.0 / t;
+    double j0, j1, y0, y1;
+    bessel01(z, j0, j1, y0, y1);
+    double s, c;
+    sincos(z, &s, &c);
+    double sq = sqrt(z);
+    // B = H e^{-iz} sqrt(z)
+    f[0][j] = sq * (j0 * c + y0 * s);
+    f[1][j] = sq * (y0 * c - j0 * s);
+    f[2][j] = sq * (j1 * c + y1 * s);
+    f[3][j] = sq * (y1 * c - j1 * s);
+  }
+  for (int fn = 0; fn < 4; ++fn) {
+    double ch[HTAB_DEG + 1];
+    for (int m = 0; m < n; ++m) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += f[fn][j] * cos(GRT_PI * m * (j + 0.5) / n);
+      ch[m] = (m == 0 ? 1.0 : 2.0) * acc / n;
+    }
+    // Chebyshev -> monomial: T_{m+1} = 2x T_m - T_{m-1}
+    double tm1[HTAB_DEG + 1], tm[HTAB_DEG + 1], mono[HTAB_DEG + 1];
+    for (int i = 0; i < n; ++i) { tm1[i] = 0.0; tm[i] = 0.0; mono[i] = 0.0; }
+    tm1[0] = 1.0;           // T_0
+    tm[1] = 1.0;            // T_1
+    for (int i = 0; i < n; ++i) mono[i] += ch[0] * tm1[i];
+    if (n > 1)
+      for (int i = 0; i < n; ++i) mono[i] += ch[1] * tm[i];
+    for (int m = 2; m < n; ++m) {
+      double nx[HTAB_DEG + 1];
+      for (int i = 0; i < n; ++i) nx[i] = (i > 0 ? 2.0 * tm[i - 1] : 0.0) - tm1[i];
+      for (int i = 0; i < n; ++i) { tm1[i] = tm[i]; tm[i] = nx[i]; }
+      for (int i = 0; i < n; ++i) mono[i] += ch[m] * tm[i];
+    }
+    for (int i = 0; i < n; ++i) out[4 * i + fn] = mono[i];
+  }
+}
+
+// Ascending series for z < 1/2 (a dozen terms reach full precision there).
+__host__ __device__ __forceinline__ void hankel01_series(double z, cd& h0, cd& h1) {
+  double q = 0.25 * z * z;
+  double tj0 = 1.0, tj1 = 1.0;  // (-q)^k / (k!)^2, (-q)^k / (k! (k+1)!)
+  double j0 = 1.0, j1 = 1.0, s0 = 0.0, s1 = 0.0;
+  double hk = 0.0;                                   // harmonic number H_k
+  const double g = GRT_EULER_GAMMA;
+  s1 = (-g + (1.0 - g));                              // psi(1) + psi(2) at k = 0
+  for (int k = 1; k < 12; ++k) {
+    tj0 *= -q / ((double)k * k);
+    tj1 *= -q / ((double)k * (k + 1));
+    j0 += tj0;
+    j1 += tj1;
+    hk += 1.0 / k;
+    s0 += -hk * tj0;                                  // (-1)^{k+1} H_k q^k / (k!)^2
+    s1 += (2.0 * (hk - g) + 1.0 / (k + 1)) * tj1;     // (psi(k+1) + psi(k+2)) term
+  }
+  double hz = 0.5 * z;
+  j1 *= hz;
+  double lg = log(hz);
+  double y0 = GRT_2_PI * ((lg + g) * j0 + s0);
+  double y1 = -GRT_2_PI / z + GRT_2_PI * lg * j1 - (hz / GRT_PI) * s1;
+  h0 = cd{j0, y0};
+  h1 = cd{j1, y1};
+}
+
+// H_0, H_1 at z > 0 from the table (tab: HTAB_SIZE doubles, any address space).
+template <typename TabPtr>
+__host__ __device__ __forceinline__ void hankel01_tab(double z, TabPtr tab, cd& h0, cd& h1) {
+  if (z < 1.0 / HTAB_TMAX) {
+    hankel01_series(z, h0, h1);
+    return;
+  }
+  double t = 1.0 / z;
+  double u = t * (HTAB_NI / HTAB_TMAX);
+  int k = (int)u;
+  k = k < HTAB_NI - 1 ? k : HTAB_NI - 1;
+  double x = 2.0 * (u - k) - 1.0;
+  TabPtr c = tab + k * HTAB_STRIDE;
+  double a0 = c[4 * HTAB_DEG + 0], a1 = c[4 * HTAB_DEG + 1];
+  double a2 = c[4 * HTAB_DEG + 2], a3 = c[4 * HTAB_DEG + 3];
+#pragma unroll
+  for (int i = HTAB_DEG - 1; i >= 0; --i) {
+    a0 = fma(a0, x, c[4 * i + 0]);
+    a1 = fma(a1, x, c[4 * i + 1]);
+    a2 = fma(a2, x, c[4 * i + 2]);
+    a3 = fma(a3, x, c[4 * i + 3]);
+  }
+  double s, cs;
+  sincos(z, &s, &cs);
+  double r = sqrt(t);
+  double er = cs * r, ei = s * r;
+  h0 = cd{er * a0 - ei * a1, er * a1 + ei * a0};
+  h1 = cd{er * a2 - ei * a3, er * a3 + ei * a2};
+}

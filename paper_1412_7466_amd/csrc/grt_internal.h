@@ -64,6 +64,7 @@ struct grt_ctx {
   cd* d_mie = nullptr;      // [M][nb]
   cd* d_l2l = nullptr;      // [M][2(Q2+P)+1]  J_m(k rho_j) e^{i m phi_j}
   cd* d_f = nullptr;        // [n_g] right-hand side prefix
+  double* d_htab = nullptr; // H_0, H_1 interpolation table (HTAB_SIZE doubles)
   // apply workspace
   int m2l_chunk = 16, m2l_nchunks = 0;
   int c_chunk = 64, c_nchunks = 0;

@@ -493,6 +493,12 @@ __global__ void __launch_bounds__(256) gemv_rows_kernel(const cd* __restrict__ W
   if (lane == 0) y[wave] = cd{ar, ai};
 }
 
+// One thread per interval of the H_0, H_1 interpolation table.
+__global__ void htab_kernel(double* tab) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < HTAB_NI) htab_interval(k, tab + k * HTAB_STRIDE);
+}
+
 }  // namespace
 
 void launch_gemv_rows(hipStream_t s, const cd* W, const cd* x, cd* y, int rows, int cols) {
@@ -520,6 +526,8 @@ grt_status setup_build(grt_ctx* c) {
     g.yw[l] = c->d_yw + off;
     off += g.Nw[l];
   }
+  GRT_HIP(c, hipMalloc(&c->d_htab, sizeof(double) * HTAB_SIZE));
+  htab_kernel<<<1, 64, 0, s>>>(c->d_htab);
   GRT_HIP(c, hipMalloc(&c->d_wcorr, sizeof(cd) * 4 * (2 * K + 1)));
   zeta_weights_kernel<<<1, 64, 0, s>>>(K, g.hs, g.k[0], g.k[1], g.k[2], c->d_wcorr);
   g.wcorr = c->d_wcorr;
