@@ -87,17 +87,24 @@ typedef struct {
 } grt_incidence;
 
 typedef struct {
-  double tol;      /* stop when ||b - K x|| / ||b|| <= tol                   */
+  double tol;      /* stop when ||b - K x|| / ||b|| <= tol (FP64 residual)  */
   int maxit;       /* total Arnoldi steps                                    */
   int restart;     /* Krylov dimension per cycle                             */
   int use_x0;      /* 1: beta_dev holds the initial guess on entry           */
+  int precision;   /* GRT_FP64: GMRES on K in FP64.  GRT_FP32: FP64 iterative
+                      refinement r = b - K x, x += e, with e from GMRES (FP64
+                      orthogonalisation) on K32, whose translation between
+                      well-separated inclusions runs in FP32 (FP32 accumulate)  */
+  double inner_tol;/* GRT_FP32: relative tolerance of each inner solve (0: 1e-5) */
+  int max_refine;  /* GRT_FP32: most refinement steps (0: 10)                */
 } grt_solve_opts;
 
 typedef struct {
-  int iters;            /* Arnoldi steps taken                               */
+  int iters;            /* Arnoldi steps taken (all inner solves)            */
   int cycles;           /* restart cycles                                    */
   double rel_resid;     /* true relative residual ||b - K x|| / ||b|| (FP64)  */
   double seconds;       /* wall time of the solve                            */
+  int refine_steps;     /* GRT_FP32: FP64 refinement steps taken             */
 } grt_solve_stats;
 
 typedef struct {
@@ -130,7 +137,11 @@ grt_status grt_query(const grt_ctx* ctx, grt_sizes* out);
 
 /* y = K x with K = I - S T + S B_phys A^+ C, the left-preconditioned Schur
  * operator of sec. 5 (B_phys = -B of the paper).  x, y: device [M][2P+1] complex
- * FP64, may not alias.  precision must be GRT_FP64. */
+ * FP64, may not alias.  precision GRT_FP64: everything in FP64.  GRT_FP32: the
+ * translation T between inclusion pairs whose scaled distance k2*rho keeps every
+ * H_q, q <= 2P, inside the FP32 range runs in FP32 with FP32 accumulation (the
+ * Hankel generator itself is FP64); the remaining near pairs, the layer
+ * correction and the preconditioner stay FP64. */
 grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision);
 
 /* Diagnostic parts of the apply: y = T x (translation among inclusions and their

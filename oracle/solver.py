@@ -14,6 +14,15 @@ columns of A are equilibrated to unit 2-norm first; Sigma^+ keeps 1/sigma_j for
 sigma_j >= eps * sigma_1 and drops the rest ("truncate"); the literal cap
 min(1/sigma_j, 1/eps) is available as rule="cap".
 
+Reading (scaling): the paper does not discuss the scaling of the multipole basis.
+With the orders P used here the outgoing coefficients of small disks span dozens
+of decades and K itself is numerically singular, so the system is solved in the
+basis normalised by each multipole's size on its own disk boundary: with
+D = diag(|H_|n|(k_2 R_m)|), GMRES (and LU) run on D K D^{-1} (D beta) = D b and
+beta = D^{-1} (D beta).  This is a diagonal similarity: the exact solution is
+unchanged, and the stopping test is the relative residual of the normalised
+system.
+
 Outputs (sec. 2, sec. 6): the Rayleigh-Bloch coefficients c_n, d_n are the last
 two blocks of alpha = A^+ (f - C beta); for propagating orders
 R_n = k_{1,n} |c_n|^2 / (k_1 cos phi), T_n = k_{3,n} |d_n|^2 / (k_1 cos phi), and the
@@ -25,6 +34,7 @@ import time
 
 import numpy as np
 import scipy.linalg as sla
+import scipy.special as sp
 
 from .common import Geometry
 from .layered import assemble_A, rhs_f
@@ -68,6 +78,9 @@ class Reduced:
         self.f = rhs_f(G)
         self.pinv = PseudoInverse(self.A, pb.disc.pinv_eps, pinv_rule)
         self.s = mie_coefficients(G.k2, G.kp, G.rad, G.P).reshape(-1) if G.M else np.zeros(0)
+        n = np.abs(np.arange(-G.P, G.P + 1))
+        self.D = (np.abs(sp.hankel1(n[None, :], G.k2 * G.rad[:, None])).reshape(-1)
+                  if G.M else np.zeros(0))
         if dense is None:
             dense = G.n_beta <= 4000
         self.dense = dense
@@ -103,13 +116,19 @@ class Reduced:
 
     # -- solves ------------------------------------------------------------
     def solve_lu(self):
-        K = self.K_dense()
-        return sla.lu_solve(sla.lu_factor(K), self.rhs())
+        """LU of the normalised system D K D^{-1} (D beta) = D b."""
+        D = self.D
+        Kh = D[:, None] * self.K_dense() / D[None, :]
+        return sla.lu_solve(sla.lu_factor(Kh), D * self.rhs()) / D
 
-    def solve_gmres(self, tol=1e-11, maxit=2000, x0=None):
-        beta, it, res = gmres(self.K_apply, self.rhs(), tol=tol, maxit=maxit, x0=x0)
+    def solve_gmres(self, tol=1e-11, maxit=2000, x0=None, restart=None):
+        """GMRES on the normalised system; tol is its relative residual."""
+        D = self.D
+        xh0 = None if x0 is None else D * x0
+        bh, it, res = gmres(lambda v: D * self.K_apply(v / D), D * self.rhs(), tol=tol,
+                            maxit=maxit, x0=xh0, restart=restart)
         self.gmres_iters, self.gmres_resid = it, res
-        return beta
+        return bh / D
 
     def solve_full_ls(self):
         """Least squares of the whole system [[A, C], [-S B_phys, I - S T]] (small only).
@@ -120,13 +139,16 @@ class Reduced:
         """
         G = self.G
         n = G.n_beta
-        top = np.hstack([self.A, self.C])
-        bot = np.hstack([-self.s[:, None] * self.B, np.eye(n) - self.s[:, None] * self.T])
+        D = self.D
+        # beta columns in normalised units (D beta), inclusion rows scaled by D
+        top = np.hstack([self.A, self.C / D[None, :]])
+        bot = np.hstack([-(D * self.s)[:, None] * self.B,
+                         D[:, None] * (np.eye(n) - self.s[:, None] * self.T) / D[None, :]])
         F = np.vstack([top, bot])
         rhs = np.concatenate([self.f, np.zeros(n, complex)])
         pi = PseudoInverse(F, self.G.pb.disc.pinv_eps)
         sol = pi.apply(rhs)
-        return sol[G.n_alpha:], sol[:G.n_alpha]
+        return sol[G.n_alpha:] / D, sol[:G.n_alpha]
 
     # -- outputs -------------------------------------------------------------
     def alpha_vec(self, beta):

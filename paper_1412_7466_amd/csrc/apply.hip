@@ -15,6 +15,7 @@
 //  l2l_kernel        alpha^L_j[n] += sum_q a2_q J_{q-n}(k2 rho_j) e^{i(q-n) phi_j} (L2L)
 //  combine_kernel    y = x - s o (alpha^T - alpha^L)
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 
 #include "dev_bessel.h"
@@ -27,34 +28,142 @@ constexpr int M2L_THREADS = 64 * M2L_WAVES;
 constexpr int M2L_TILE = 16;     // sources staged in LDS at a time, per wave
 constexpr int M2L_QB = 4;        // generator orders produced per block of the contraction
 
-// Translation of the outgoing coefficients of sources [m0, m1) (and of their
-// copies l = -1, 0, 1) into incoming coefficients at 64 targets (one per lane);
-// the block's four waves take a quarter of the sources each and are summed
-// through LDS at the end.
-//  * per (target, source) the generators of the three copies are summed first:
-//      tau_q = sum_l alpha^l H_q(k rho_l) e^{i q phi_l},  q = -2P..2P,
-//    produced M2L_QB orders at a time by the upward recurrence;
-//  * the Toeplitz product acc[n] += tau_{nu-n} x[nu] is then done source-value
-//    major: each x[nu] is read once from LDS per block of orders (a broadcast:
-//    every lane reads the same address) and feeds up to 2*M2L_QB complex FMAs.
-template <int P>
-__global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restrict__ cx,
-                                                          const double* __restrict__ cy,
-                                                          const cd* __restrict__ x, cd* partial,
-                                                          int M, int chunk, double k, double d,
-                                                          cd alpha, cd alpha_inv,
-                                                          const double* __restrict__ htab) {
+__device__ __forceinline__ void cmac(cf& acc, cf a, cf b) {
+  acc.r = fmaf(a.r, b.r, acc.r);
+  acc.r = fmaf(-a.i, b.i, acc.r);
+  acc.i = fmaf(a.r, b.i, acc.i);
+  acc.i = fmaf(a.i, b.r, acc.i);
+}
+__device__ __forceinline__ cd to_acc(cd v, cd*) { return v; }
+__device__ __forceinline__ cf to_acc(cd v, cf*) { return cf{(float)v.r, (float)v.i}; }
+
+// Contribution of one source inclusion (and its copies l = -1, 0, 1) to the incoming
+// coefficients acc[n] of one target, n = -P..P at index n + P:
+//   acc[n] += sum_nu tau_{nu-n} x[nu],  tau_q = sum_l alpha^l H_q(k rho_l) e^{i q phi_l},
+//   rho_l e^{i phi_l} = (dx - l d) + i dy  (Graf's theorem for each copy).
+// The generator is FP64 (H_0, H_1 from the table, upward recurrence, powers of
+// e^{i phi}) and is produced M2L_QB orders at a time; T is the accumulation type
+// (cd: FP64, cf: FP32 with FP32 accumulation).  Each x[nu] is read once per block of
+// orders and feeds up to 2 M2L_QB complex FMAs.  skip0 drops the copy l = 0 (the
+// excluded self term); dead drops everything.  With zsafe > 0 the pair is dropped
+// too when a kept copy has k rho < zsafe (left to the FP64 near-pair pass).
+template <int P, typename T, typename BP, typename TabPtr>
+__device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double dy, double k,
+                                                double d, const cd* wl, bool skip0, bool dead,
+                                                TabPtr tab, double zsafe) {
   constexpr int NB = 2 * P + 1;
   constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
-  constexpr int STAGE = M2L_WAVES * M2L_TILE * (2 * NB + 2);  // doubles: x tiles + centres
-  constexpr int RED = 2 * NB * 64;                             // doubles: one wave's acc
+  cd hp[3], hc[3], cc[3], cq[3];
+  double rz2[3];
+  double zz[3];
+  bool near = false;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    double ex = dx - (l - 1) * d;
+    bool off = (skip0 && l == 1) || dead;
+    double r = sqrt(ex * ex + dy * dy);
+    if (off) r = 1.0;
+    double z = k * r;
+    zz[l] = z;
+    if (!off && z < zsafe) near = true;
+    double ir = 1.0 / r;
+    cc[l] = cd{ex * ir, dy * ir};
+    cq[l] = cc[l];
+    rz2[l] = 2.0 / z;
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    bool off = (skip0 && l == 1) || dead || near;
+    cd h0, h1;
+    hankel01_tab(zz[l], tab, h0, h1);
+    cd w = off ? cd{0.0, 0.0} : wl[l];
+    hp[l] = w * h0;
+    hc[l] = w * h1;
+  }
+  {
+    T t0 = to_acc(hp[0] + hp[1] + hp[2], (T*)nullptr);
+#pragma unroll
+    for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
+  }
+#pragma unroll
+  for (int qb = 0; qb < NQB; ++qb) {
+    T tp[M2L_QB], tm[M2L_QB];
+#pragma unroll
+    for (int u = 0; u < M2L_QB; ++u) {
+      const int q = 1 + qb * M2L_QB + u;
+      cd sp{0.0, 0.0}, sm{0.0, 0.0};
+      if (q <= 2 * P) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          double ac = hc[l].r * cq[l].r, bd = hc[l].i * cq[l].i;
+          double ad = hc[l].r * cq[l].i, bc = hc[l].i * cq[l].r;
+          sp.r += ac - bd;
+          sp.i += ad + bc;
+          sm.r += ac + bd;
+          sm.i += bc - ad;
+        }
+        if (q & 1) sm = -sm;  // H_{-q} = (-1)^q H_q
+        if (q < 2 * P) {
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            cd hn = (q * rz2[l]) * hc[l] - hp[l];
+            hp[l] = hc[l];
+            hc[l] = hn;
+            cq[l] = cq[l] * cc[l];
+          }
+        }
+      }
+      tp[u] = to_acc(sp, (T*)nullptr);
+      tm[u] = to_acc(sm, (T*)nullptr);
+    }
+    // x may be re-read here: keeps x[nu] out of registers across blocks of orders
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int nu = 0; nu < NB; ++nu) {
+      bool need = false;
+#pragma unroll
+      for (int u = 0; u < M2L_QB; ++u) {
+        const int q = 1 + qb * M2L_QB + u;
+        if (q <= 2 * P && (nu - q >= 0 || nu + q < NB)) need = true;
+      }
+      if (!need) continue;
+      const T bv = b[nu];
+#pragma unroll
+      for (int u = 0; u < M2L_QB; ++u) {
+        const int q = 1 + qb * M2L_QB + u;
+        if (q > 2 * P) continue;
+        if (nu - q >= 0) cmac(acc[nu - q], tp[u], bv);   // acc[n] += t_q x[n+q]
+        if (nu + q < NB) cmac(acc[nu + q], tm[u], bv);   // acc[n] += t_{-q} x[n-q]
+      }
+    }
+  }
+}
+
+// Translation of the outgoing coefficients of sources [m0, m1) (and of their
+// copies l = -1, 0, 1) into incoming coefficients at 64 targets (one per lane);
+// the block's four waves take a quarter of the sources each, stage them in LDS
+// (every lane then reads the same address: a broadcast) and are summed through
+// LDS at the end.  T = cd: FP64; T = cf: FP32 contraction and accumulation with
+// pairs closer than zsafe left out.
+template <int P, typename T>
+__global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restrict__ cx,
+                                                          const double* __restrict__ cy,
+                                                          const T* __restrict__ x, T* partial,
+                                                          int M, int chunk, double k, double d,
+                                                          cd alpha, cd alpha_inv,
+                                                          const double* __restrict__ htab,
+                                                          double zsafe) {
+  constexpr int NB = 2 * P + 1;
+  constexpr int TW = sizeof(T) / sizeof(double);  // doubles per complex value (1 or 2)
+  constexpr int STAGE = M2L_WAVES * M2L_TILE * (TW * NB + 2);
+  constexpr int RED = TW * NB * 64;
   constexpr int BUF = STAGE > RED ? STAGE : RED;
   __shared__ double smem[BUF];
   __shared__ double stab[HTAB_SIZE];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  cd* sx = reinterpret_cast<cd*>(smem) + wv * M2L_TILE * NB;
-  double* scx = smem + 2 * M2L_WAVES * M2L_TILE * NB + wv * 2 * M2L_TILE;
+  T* sx = reinterpret_cast<T*>(smem) + wv * M2L_TILE * NB;
+  double* scx = smem + TW * M2L_WAVES * M2L_TILE * NB + wv * 2 * M2L_TILE;
   double* scy = scx + M2L_TILE;
   const int j = blockIdx.x * 64 + lane;
   const int m0 = blockIdx.y * chunk;
@@ -66,9 +175,9 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restri
   for (int t = threadIdx.x; t < HTAB_SIZE; t += M2L_THREADS) stab[t] = htab[t];
   const bool live = j < M;
   const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
-  cd acc[NB];
+  T acc[NB];
 #pragma unroll
-  for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
+  for (int n = 0; n < NB; ++n) acc[n] = T{0, 0};
   const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
   for (int it = 0; it < ntile; ++it) {
     const int ts = s0 + it * M2L_TILE;
@@ -82,105 +191,69 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restri
     __syncthreads();
     for (int mm = 0; mm < cnt; ++mm) {
       const int m = ts + mm;
-      const cd* b = sx + mm * NB;
-      cd hp[3], hc[3], cc[3], cq[3];
-      double rz2[3];
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        double dx = xj - scx[mm] - (l - 1) * d;
-        double dy = yj - scy[mm];
-        bool off = (j == m && l == 1) || !live;
-        double r = sqrt(dx * dx + dy * dy);
-        if (off) r = 1.0;
-        double z = k * r;
-        double ir = 1.0 / r;
-        cd h0, h1;
-        hankel01_tab(z, stab, h0, h1);
-        cd w = off ? cd{0.0, 0.0} : wl[l];
-        hp[l] = w * h0;
-        hc[l] = w * h1;
-        cc[l] = cd{dx * ir, dy * ir};
-        cq[l] = cc[l];
-        rz2[l] = 2.0 / z;
-      }
-      {
-        cd t0 = hp[0] + hp[1] + hp[2];
-#pragma unroll
-        for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
-      }
-#pragma unroll
-      for (int qb = 0; qb < NQB; ++qb) {
-        cd tp[M2L_QB], tm[M2L_QB];
-#pragma unroll
-        for (int u = 0; u < M2L_QB; ++u) {
-          const int q = 1 + qb * M2L_QB + u;
-          tp[u] = cd{0.0, 0.0};
-          tm[u] = cd{0.0, 0.0};
-          if (q <= 2 * P) {
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-              double ac = hc[l].r * cq[l].r, bd = hc[l].i * cq[l].i;
-              double ad = hc[l].r * cq[l].i, bc = hc[l].i * cq[l].r;
-              tp[u].r += ac - bd;
-              tp[u].i += ad + bc;
-              tm[u].r += ac + bd;
-              tm[u].i += bc - ad;
-            }
-            if (q & 1) tm[u] = -tm[u];  // H_{-q} = (-1)^q H_q
-            if (q < 2 * P) {
-#pragma unroll
-              for (int l = 0; l < 3; ++l) {
-                cd hn = (q * rz2[l]) * hc[l] - hp[l];
-                hp[l] = hc[l];
-                hc[l] = hn;
-                cq[l] = cq[l] * cc[l];
-              }
-            }
-          }
-        }
-        // LDS contents may be re-read here: keeps x[nu] out of registers across blocks
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int nu = 0; nu < NB; ++nu) {
-          bool need = false;
-#pragma unroll
-          for (int u = 0; u < M2L_QB; ++u) {
-            const int q = 1 + qb * M2L_QB + u;
-            if (q <= 2 * P && (nu - q >= 0 || nu + q < NB)) need = true;
-          }
-          if (!need) continue;
-          const cd bv = b[nu];
-#pragma unroll
-          for (int u = 0; u < M2L_QB; ++u) {
-            const int q = 1 + qb * M2L_QB + u;
-            if (q > 2 * P) continue;
-            if (nu - q >= 0) cmac(acc[nu - q], tp[u], bv);   // acc[n] += t_q x[n+q]
-            if (nu + q < NB) cmac(acc[nu + q], tm[u], bv);   // acc[n] += t_{-q} x[n-q]
-          }
-        }
-      }
+      pair_accumulate<P, T>(acc, sx + mm * NB, xj - scx[mm], yj - scy[mm], k, d, wl, j == m,
+                            !live, stab, zsafe);
     }
   }
   // sum the four waves' partial results through LDS: wave 3, then 2, then 1 add into
   // the buffer in turn, wave 0 adds its own and stores
-  cd* red = reinterpret_cast<cd*>(smem);
+  T* red = reinterpret_cast<T*>(smem);
   for (int src = M2L_WAVES - 1; src >= 1; --src) {
     __syncthreads();
     if (wv == src) {
 #pragma unroll
       for (int n = 0; n < NB; ++n) {
-        cd v = acc[n];
-        if (src != M2L_WAVES - 1) v += red[n * 64 + lane];
+        T v = acc[n];
+        if (src != M2L_WAVES - 1) {
+          T o = red[n * 64 + lane];
+          v.r += o.r;
+          v.i += o.i;
+        }
         red[n * 64 + lane] = v;
       }
     }
   }
   __syncthreads();
   if (wv == 0 && live) {
-    cd* out = partial + ((size_t)blockIdx.y * M + j) * NB;
+    T* out = partial + ((size_t)blockIdx.y * M + j) * NB;
 #pragma unroll
-    for (int n = 0; n < NB; ++n) out[n] = acc[n] + red[n * 64 + lane];
+    for (int n = 0; n < NB; ++n) {
+      T o = red[n * 64 + lane];
+      out[n] = T{acc[n].r + o.r, acc[n].i + o.i};
+    }
   }
+}
+
+// FP64 translation over the near-pair lists (CSR by target): the pairs the FP32
+// pass leaves out.  One lane per target; x is read from global memory.
+template <int P>
+__global__ void __launch_bounds__(64) m2l_near_kernel(const double* __restrict__ cx,
+                                                      const double* __restrict__ cy,
+                                                      const cd* __restrict__ x,
+                                                      const int* __restrict__ noff,
+                                                      const int* __restrict__ nlist, cd* out,
+                                                      int M, double k, double d, cd alpha,
+                                                      cd alpha_inv,
+                                                      const double* __restrict__ htab) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ double stab[HTAB_SIZE];
+  for (int t = threadIdx.x; t < HTAB_SIZE; t += 64) stab[t] = htab[t];
+  __syncthreads();
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= M) return;
+  const double xj = cx[j], yj = cy[j];
+  cd acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
+  const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
+  for (int e = noff[j]; e < noff[j + 1]; ++e) {
+    const int m = nlist[e];
+    pair_accumulate<P, cd>(acc, x + (size_t)m * NB, xj - cx[m], yj - cy[m], k, d, wl, j == m,
+                           false, stab, 0.0);
+  }
+  cd* o = out + (size_t)j * NB;
+#pragma unroll
+  for (int n = 0; n < NB; ++n) o[n] = acc[n];
 }
 
 constexpr int CX_TILE = 32;  // inclusions staged in LDS at a time
@@ -326,16 +399,22 @@ __global__ void __launch_bounds__(256) cx_reduce_kernel(DevGeom g, const cd* par
   }
 }
 
-// Incoming coefficients at inclusion j from the interface densities (P2L):
+// Incoming coefficients at inclusion j from the interface densities (P2L, Graf's
+// theorem for H_0 about c_j):
 //   alpha_j[n] += (i/4) hs alpha^l [G_n sigma - (ik/2)(G_{n-1} + G_{n+1}) mu],
-//   G_n = H_n(k|v|) e^{-in theta_v}, v = node copy - c_j.
-// Sources: 2 lines x N nodes x 3 copies = 6N node-copies, chunked over blockIdx.y.
+//   G_n = H_n(k|v|) e^{-in theta_v}, v = node copy - c_j,
+// the mu term being d/dy of the sigma term (gradient identity).  Sources: 2 lines x
+// N nodes x 3 copies = 6N node-copies, chunked over blockIdx.y.  Each G_m is used
+// as soon as it is generated: it feeds acc[m] (sigma) and acc[m -+ 1] (mu).
 template <int P>
 __global__ void __launch_bounds__(64) bx_kernel(DevGeom g, const double* __restrict__ cx,
                                                 const double* __restrict__ cy,
                                                 const cd* __restrict__ w, cd* partial, int chunk,
                                                 const double* __restrict__ htab) {
   constexpr int NB = 2 * P + 1;
+  __shared__ double stab[HTAB_SIZE];
+  for (int i = threadIdx.x; i < HTAB_SIZE; i += 64) stab[i] = htab[i];
+  __syncthreads();
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int s0 = blockIdx.y * chunk;
   const int s1 = min(6 * g.N, s0 + chunk);
@@ -346,48 +425,54 @@ __global__ void __launch_bounds__(64) bx_kernel(DevGeom g, const double* __restr
 #pragma unroll
   for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
   for (int sidx = s0; sidx < s1; ++sidx) {
-    int line = sidx / (3 * g.N);
-    int rem = sidx - line * 3 * g.N;
-    int l = rem / g.N - 1;
-    int i = rem - (l + 1) * g.N;
-    double sxp = -0.5 * g.d + (i + 0.5) * g.hs + l * g.d;
-    double syp = line == 0 ? g.h : -g.h;
-    cd mu = w[g.col_off[line == 0 ? CB_MU1 : CB_MU2] + i];
-    cd sg = w[g.col_off[line == 0 ? CB_SIG1 : CB_SIG2] + i];
-    cd ph = (l == 0) ? cd{1.0, 0.0} : (l > 0 ? g.alpha : g.alpha_inv);
-    cd pre = times_i((0.25 * g.hs) * ph);  // (i/4) hs alpha^l
-    cd csig = pre * sg;
-    cd cmu = pre * times_i((-0.5 * k) * mu);  // -(ik/2) mu * pre
-    double vx = sxp - xj, vy = syp - yj;
-    double r = sqrt(vx * vx + vy * vy);
-    double z = k * r;
-    cd e{vx / r, vy / r};
-    cd ec = conj(e);
+    const int line = sidx / (3 * g.N);
+    const int rem = sidx - line * 3 * g.N;
+    const int l = rem / g.N - 1;
+    const int i = rem - (l + 1) * g.N;
+    const double sxp = -0.5 * g.d + (i + 0.5) * g.hs + l * g.d;
+    const double syp = line == 0 ? g.h : -g.h;
+    const cd mu = w[g.col_off[line == 0 ? CB_MU1 : CB_MU2] + i];
+    const cd sg = w[g.col_off[line == 0 ? CB_SIG1 : CB_SIG2] + i];
+    const cd ph = (l == 0) ? cd{1.0, 0.0} : (l > 0 ? g.alpha : g.alpha_inv);
+    const cd pre = times_i((0.25 * g.hs) * ph);        // (i/4) hs alpha^l
+    const cd csig = pre * sg;
+    const cd cmu = pre * times_i((-0.5 * k) * mu);     // -(ik/2) mu (i/4) hs alpha^l
+    const double vx = sxp - xj, vy = syp - yj;
+    const double r = sqrt(vx * vx + vy * vy);
+    const double z = k * r;
+    const double ir = 1.0 / r;
+    const cd e{vx * ir, vy * ir};
+    const cd ec = conj(e);
     cd hprev, hcur;
-    hankel01_tab(z, htab, hprev, hcur);
-    // G_n for n = 0..P+1 (positive) and negative via (-1)^n H_n e^{in theta}
-    cd Gp[P + 2], Gm[P + 2];
-    Gp[0] = hprev;
-    Gm[0] = hprev;
-    cd ep = ec, em = e;
-    double rz2 = 2.0 / z;
-#pragma unroll
-    for (int n = 1; n <= P + 1; ++n) {
-      Gp[n] = hcur * ep;
-      Gm[n] = (n & 1) ? -(hcur * em) : hcur * em;
-      cd hn = (n * rz2) * hcur - hprev;
-      hprev = hcur;
-      hcur = hn;
-      ep = ep * ec;
-      em = em * e;
+    hankel01_tab(z, stab, hprev, hcur);
+    // order 0: G_0 = H_0 -> acc[0] (sigma), acc[+-1] (mu)
+    cmac(acc[P], csig, hprev);
+    if (P >= 1) {
+      cmac(acc[P + 1], cmu, hprev);
+      cmac(acc[P - 1], cmu, hprev);
     }
+    cd ep = ec, em = e;
+    const double rz2 = 2.0 / z;
 #pragma unroll
-    for (int n = -P; n <= P; ++n) {
-      cd G = n >= 0 ? Gp[n] : Gm[-n];
-      cd Gl = (n - 1) >= 0 ? Gp[n - 1] : Gm[1 - n];
-      cd Gr = (n + 1) >= 0 ? Gp[n + 1] : Gm[-n - 1];
-      cmac(acc[n + P], csig, G);
-      cmac(acc[n + P], cmu, Gl + Gr);
+    for (int m = 1; m <= P + 1; ++m) {
+      const cd Gp = hcur * ep;                                  // G_m = H_m e^{-im theta}
+      const cd Gm = (m & 1) ? -(hcur * em) : hcur * em;        // G_{-m} = (-1)^m H_m e^{im theta}
+      if (m <= P) {
+        cmac(acc[P + m], csig, Gp);
+        cmac(acc[P - m], csig, Gm);
+      }
+      // G_m feeds acc[m - 1] and acc[m + 1]; G_{-m} feeds acc[-m + 1] and acc[-m - 1]
+      if (m - 1 <= P) cmac(acc[P + m - 1], cmu, Gp);
+      if (m + 1 <= P) cmac(acc[P + m + 1], cmu, Gp);
+      if (1 - m >= -P) cmac(acc[P + 1 - m], cmu, Gm);
+      if (-m - 1 >= -P) cmac(acc[P - m - 1], cmu, Gm);
+      if (m <= P) {
+        const cd hn = (m * rz2) * hcur - hprev;
+        hprev = hcur;
+        hcur = hn;
+        ep = ep * ec;
+        em = em * e;
+      }
     }
   }
   if (live) {
@@ -459,10 +544,89 @@ void launch_m2l(grt_ctx* c, const cd* x) {
   dim3 grid((unsigned)((c->M + 63) / 64), c->m2l_nchunks);
   hipEvent_t* ev = prof_pair(c);
   if (ev) hipEventRecord(ev[0], c->stream);
-  m2l_kernel<P><<<grid, M2L_THREADS, 0, c->stream>>>(c->d_cx, c->d_cy, x, c->d_pT, (int)c->M,
-                                                     c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
-                                                     c->g.alpha_inv, c->d_htab);
+  m2l_kernel<P, cd><<<grid, M2L_THREADS, 0, c->stream>>>(
+      c->d_cx, c->d_cy, x, c->d_pT, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
+      c->g.alpha_inv, c->d_htab, 0.0);
   if (ev) hipEventRecord(ev[1], c->stream);
+}
+
+template <int P>
+void launch_m2l32(grt_ctx* c, const cf* x32) {
+  dim3 grid((unsigned)((c->M + 63) / 64), c->m2l_nchunks);
+  hipEvent_t* ev = prof_pair(c);
+  if (ev) hipEventRecord(ev[0], c->stream);
+  m2l_kernel<P, cf><<<grid, M2L_THREADS, 0, c->stream>>>(
+      c->d_cx, c->d_cy, x32, c->d_pT32, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
+      c->g.alpha_inv, c->d_htab, c->zsafe);
+  if (ev) hipEventRecord(ev[1], c->stream);
+}
+
+template <int P>
+void launch_near(grt_ctx* c, const cd* x) {
+  m2l_near_kernel<P><<<(unsigned)((c->M + 63) / 64), 64, 0, c->stream>>>(
+      c->d_cx, c->d_cy, x, c->d_noff, c->d_nlist, c->d_pN, (int)c->M, c->g.k[1], c->g.d,
+      c->g.alpha, c->g.alpha_inv, c->d_htab);
+}
+
+__global__ void to_f32_kernel(const cd* x, cf* y, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = cf{(float)x[i].r, (float)x[i].i};
+}
+
+// y = x - s o ((sum_c pT32[c] + pN) - sum_c pB[c] - pL): the mixed-precision apply.
+__global__ void combine_mixed_kernel(int nbeta, const cd* x, const cd* s, const cf* pT, int nT,
+                                     const cd* pN, const cd* pB, int nB, const cd* pL, cd* y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbeta) return;
+  cd t = pN[i];
+  for (int c = 0; c < nT; ++c) {
+    cf v = pT[(size_t)c * nbeta + i];
+    t.r += v.r;
+    t.i += v.i;
+  }
+  cd b = pL[i];
+  for (int c = 0; c < nB; ++c) b += pB[(size_t)c * nbeta + i];
+  y[i] = x[i] - s[i] * (t - b);
+}
+
+// Near-pair lists: pairs (j, m) with some kept copy at k rho < zsafe.
+__device__ bool near_pair(const double* cx, const double* cy, int j, int m, double k, double d,
+                          double zsafe) {
+  for (int l = -1; l <= 1; ++l) {
+    if (j == m && l == 0) continue;
+    double dx = cx[j] - cx[m] - l * d, dy = cy[j] - cy[m];
+    if (k * sqrt(dx * dx + dy * dy) < zsafe) return true;
+  }
+  return false;
+}
+
+__global__ void near_count_kernel(const double* cx, const double* cy, int M, double k, double d,
+                                  double zsafe, int* cnt) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  int c = 0;
+  for (int m = 0; m < M; ++m) c += near_pair(cx, cy, j, m, k, d, zsafe);
+  cnt[j] = c;
+}
+
+// exclusive prefix sum of cnt[0..M) into off[0..M] (one thread; setup only)
+__global__ void near_scan_kernel(const int* cnt, int M, int* off) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int s = 0;
+  for (int j = 0; j < M; ++j) {
+    off[j] = s;
+    s += cnt[j];
+  }
+  off[M] = s;
+}
+
+__global__ void near_fill_kernel(const double* cx, const double* cy, int M, double k, double d,
+                                 double zsafe, const int* off, int* list) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  int p = off[j];
+  for (int m = 0; m < M; ++m)
+    if (near_pair(cx, cy, j, m, k, d, zsafe)) list[p++] = m;
 }
 
 template <int P>
@@ -533,6 +697,34 @@ grt_status apply_alloc(grt_ctx* c) {
   GRT_HIP(c, hipMalloc(&c->d_pC, sizeof(cd) * (size_t)c->c_nchunks * nt * 2));
   GRT_HIP(c, hipMalloc(&c->d_pB, sizeof(cd) * (size_t)c->b_nchunks * c->n_beta));
   GRT_HIP(c, hipMalloc(&c->d_pL, sizeof(cd) * (size_t)c->n_beta));
+  // mixed-precision path: FP32 copy of x, FP32 partials, near-pair lists and results.
+  // zsafe: the smallest k2*rho with (2P-1)! (2/z)^{2P} / pi <= 1e30, the large-order
+  // size of |H_{2P}(z)|, so that every FP32 generator value and product stays finite.
+  {
+    const int q = 2 * c->P;
+    c->zsafe = 1.1 * 2.0 * std::exp((std::lgamma((double)q) - std::log(M_PI * 1e30)) / q);
+    GRT_HIP(c, hipMalloc(&c->d_x32, sizeof(cf) * (size_t)c->n_beta));
+    GRT_HIP(c, hipMalloc(&c->d_pT32, sizeof(cf) * (size_t)c->m2l_nchunks * c->n_beta));
+    GRT_HIP(c, hipMalloc(&c->d_pN, sizeof(cd) * (size_t)c->n_beta));
+    GRT_HIP(c, hipMalloc(&c->d_noff, sizeof(int) * (size_t)(M + 1)));
+    int* cnt = nullptr;
+    GRT_HIP(c, hipMalloc(&cnt, sizeof(int) * (size_t)M));
+    const unsigned nbk = (unsigned)((M + 127) / 128);
+    near_count_kernel<<<nbk, 128, 0, c->stream>>>(c->d_cx, c->d_cy, (int)M, c->g.k[1], c->g.d,
+                                                   c->zsafe, cnt);
+    near_scan_kernel<<<1, 64, 0, c->stream>>>(cnt, (int)M, c->d_noff);
+    int total = 0;
+    GRT_HIP(c, hipMemcpyAsync(&total, c->d_noff + M, sizeof(int), hipMemcpyDeviceToHost,
+                              c->stream));
+    GRT_HIP(c, hipStreamSynchronize(c->stream));
+    c->n_near = total;
+    GRT_HIP(c, hipMalloc(&c->d_nlist, sizeof(int) * (size_t)std::max(1, total)));
+    near_fill_kernel<<<nbk, 128, 0, c->stream>>>(c->d_cx, c->d_cy, (int)M, c->g.k[1], c->g.d,
+                                                  c->zsafe, c->d_noff, c->d_nlist);
+    GRT_HIP(c, hipGetLastError());
+    GRT_HIP(c, hipStreamSynchronize(c->stream));
+    hipFree(cnt);
+  }
   return GRT_OK;
 }
 
@@ -581,6 +773,26 @@ static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode) {
 }
 
 grt_status apply_K(grt_ctx* c, const cd* x, cd* y) { return run_apply(c, x, y, 0); }
+
+// K32 x: FP32 translation between well-separated pairs, FP64 for near pairs, the
+// layer correction and the preconditioner.
+grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y) {
+  if (c->M == 0) return GRT_OK;
+  hipStream_t s = c->stream;
+  const int n = (int)c->n_beta;
+  to_f32_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, c->d_x32, n);
+  GRT_P_DISPATCH(launch_m2l32, c->P, c, c->d_x32);
+  GRT_P_DISPATCH(launch_near, c->P, c, x);
+  grt_status st = cx_apply(c, x);
+  if (st != GRT_OK) return st;
+  st = lowrank_tail(c, c->d_gvec);
+  if (st != GRT_OK) return st;
+  combine_mixed_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, x, c->d_mie, c->d_pT32, c->m2l_nchunks,
+                                                       c->d_pN, c->d_pB, c->b_nchunks, c->d_pL,
+                                                       y);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
 grt_status apply_T_only(grt_ctx* c, const cd* x, cd* y) { return run_apply(c, x, y, 1); }
 grt_status apply_lowrank_only(grt_ctx* c, const cd* x, cd* y) { return run_apply(c, x, y, 2); }
 

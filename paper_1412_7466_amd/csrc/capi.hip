@@ -28,7 +28,8 @@ void free_all(grt_ctx* c) {
                   c->d_colscale, c->d_sv, c->d_U, c->d_VH, c->d_W1, c->d_W2, c->d_W3,
                   c->d_mie, c->d_l2l, c->d_f, c->d_pT, c->d_pC, c->d_pB, c->d_pL,
                   c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_cs, c->d_sn, c->d_htab,
-                  c->d_gv, c->d_y, c->d_scal, c->d_dotpart};
+                  c->d_gv, c->d_y, c->d_scal, c->d_dotpart, c->d_res, c->d_x32, c->d_pT32,
+                  c->d_pN, c->d_noff, c->d_nlist, c->d_dnorm, c->d_dinv, c->d_xtmp};
   for (void* p : bufs)
     if (p) hipFree(p);
   c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal =
@@ -36,6 +37,15 @@ void free_all(grt_ctx* c) {
   c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_mie = c->d_l2l =
       c->d_f = c->d_pT = c->d_pC = c->d_pB = c->d_pL = c->d_gvec = c->d_tvec = c->d_wvec =
           c->d_V = c->d_H = c->d_cs = c->d_sn = c->d_gv = c->d_y = c->d_dotpart = nullptr;
+  c->d_res = nullptr;
+  c->d_x32 = nullptr;
+  c->d_pT32 = nullptr;
+  c->d_pN = nullptr;
+  c->d_noff = nullptr;
+  c->d_nlist = nullptr;
+  c->n_near = 0;
+  c->d_dnorm = c->d_dinv = nullptr;
+  c->d_xtmp = nullptr;
   c->krylov_restart = 0;
   c->built = false;
 }
@@ -78,6 +88,8 @@ grt_status grt_destroy(grt_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   free_all(c);
   for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_res)
+    if (e) hipEventDestroy(e);
   if (c->h_pinned) hipHostFree(c->h_pinned);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
@@ -259,8 +271,10 @@ grt_status grt_apply(grt_ctx* c, const void* x, void* y, int precision) {
   grt_status st = check_built(c);
   if (st != GRT_OK) return st;
   if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
-  if (precision != GRT_FP64) return set_err(c, GRT_EUNSUP, "only GRT_FP64 is available here");
-  return apply_K(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+  if (precision == GRT_FP64) return apply_K(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+  if (precision == GRT_FP32)
+    return apply_K_mixed(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+  return set_err(c, GRT_EINVAL, "precision must be GRT_FP64 or GRT_FP32");
 }
 
 grt_status grt_apply_T(grt_ctx* c, const void* x, void* y) {
@@ -293,6 +307,8 @@ grt_status grt_solve(grt_ctx* c, const grt_solve_opts* o, void* beta, grt_solve_
   if (st != GRT_OK) return st;
   if (!o || !beta) return set_err(c, GRT_EINVAL, "null argument");
   if (!(o->tol > 0 && o->tol < 1)) return set_err(c, GRT_EINVAL, "tol must be in (0, 1)");
+  if (o->precision != GRT_FP64 && o->precision != GRT_FP32)
+    return set_err(c, GRT_EINVAL, "precision must be GRT_FP64 or GRT_FP32");
   grt_solve_stats tmp{};
   grt_solve_stats* sp = stats ? stats : &tmp;
   if (c->M == 0) {

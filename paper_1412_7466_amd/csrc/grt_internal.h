@@ -62,6 +62,9 @@ struct grt_ctx {
   cd* d_W2 = nullptr;       // [n_b][rank]   row-major: E V (prefix entries)
   cd* d_W3 = nullptr;       // [2 Nrb][rank] row-major: E V (c, d entries)
   cd* d_mie = nullptr;      // [M][nb]
+  double* d_dnorm = nullptr; // [M][nb] |H_|n|(k2 R_m)|: scaling of the normalised system
+  double* d_dinv = nullptr;  // [M][nb] 1 / d_dnorm
+  cd* d_xtmp = nullptr;      // [M][nb] scratch of the normalised apply
   cd* d_l2l = nullptr;      // [M][2(Q2+P)+1]  J_m(k rho_j) e^{i m phi_j}
   cd* d_f = nullptr;        // [n_g] right-hand side prefix
   double* d_htab = nullptr; // H_0, H_1 interpolation table (HTAB_SIZE doubles)
@@ -76,6 +79,14 @@ struct grt_ctx {
   cd* d_gvec = nullptr;     // [n_g]
   cd* d_tvec = nullptr;     // [rank]
   cd* d_wvec = nullptr;     // [n_b]
+  // mixed precision: FP32 translation for well-separated pairs, FP64 near-pair lists
+  double zsafe = 0.0;
+  cf* d_x32 = nullptr;      // [n_beta]
+  cf* d_pT32 = nullptr;     // [m2l_nchunks][M][nb]
+  cd* d_pN = nullptr;       // [M][nb]
+  int* d_noff = nullptr;    // [M+1] CSR offsets
+  int* d_nlist = nullptr;   // [n_near]
+  int64_t n_near = 0;
   // GMRES workspace
   int krylov_restart = 0;
   cd* d_V = nullptr;        // [restart+1][n_beta]
@@ -87,6 +98,8 @@ struct grt_ctx {
   double* d_scal = nullptr; // scratch scalars
   cd* d_dotpart = nullptr;  // [restart+1][n_dot_blocks]
   int n_dot_blocks = 0;
+  double* d_res = nullptr;   // residual estimate of every Arnoldi step
+  hipEvent_t ev_res[2] = {nullptr, nullptr};
   double* h_pinned = nullptr;
   // kernel timing (HIP events around every translation-kernel launch)
   bool prof = false;
@@ -112,6 +125,7 @@ void launch_gemv_rows(hipStream_t s, const cd* W, const cd* x, cd* y, int rows, 
 // apply (apply.hip)
 bool supported_P(int P);
 grt_status apply_K(grt_ctx* c, const cd* x, cd* y);
+grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y);
 grt_status apply_T_only(grt_ctx* c, const cd* x, cd* y);
 grt_status apply_lowrank_only(grt_ctx* c, const cd* x, cd* y);
 grt_status rhs_b(grt_ctx* c, cd* b);

@@ -42,18 +42,20 @@ __global__ void __launch_bounds__(KT) dots_kernel(const cd* __restrict__ V, size
   }
 }
 
-// out[v] (+)= sum_b partial[v][b]  (fixed order: deterministic)
-__global__ void reduce_dots_kernel(const cd* partial, int nblk, int nvec, cd* out, int accumulate) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nvec) return;
-  cd s{0, 0};
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)v * nblk + b];
-  out[v] = accumulate ? out[v] + s : s;
-}
-
-// w[i] -= sum_v h[v] V_v[i]
+// h[v] = sum_b partial[v][b] (fixed order), then w[i] -= sum_v h[v] V_v[i].
+// Every block redoes the small reduction; block 0 also stores h into the
+// Hessenberg column (pass 0) or adds it (pass 1: the re-orthogonalisation).
 __global__ void __launch_bounds__(KT) update_kernel(const cd* __restrict__ V, size_t ldv, cd* w,
-                                                     int n, const cd* __restrict__ h, int nvec) {
+                                                     int n, const cd* __restrict__ partial,
+                                                     int nblk, int nvec, cd* hcol, int pass) {
+  __shared__ cd h[1024];
+  for (int v = threadIdx.x; v < nvec; v += KT) {
+    cd s{0, 0};
+    for (int b = 0; b < nblk; ++b) s += partial[(size_t)v * nblk + b];
+    h[v] = s;
+    if (blockIdx.x == 0) hcol[v] = pass ? hcol[v] + s : s;
+  }
+  __syncthreads();
   int i = blockIdx.x * KT + threadIdx.x;
   if (i >= n) return;
   cd acc = w[i];
@@ -111,14 +113,19 @@ __global__ void axpy_basis_kernel(cd* x, const cd* __restrict__ V, size_t ldv, i
   x[i] = acc;
 }
 
-// Column j of H gets the rotations of columns 0..j-1, then a new rotation that
-// zeroes H[j+1][j]; g is rotated alongside.  With c = a/den, s = b/den the rotation
-// [[conj c, conj s], [-s, c]] maps (a, b) to (den, 0).  res = |g[j+1]|.
-__global__ void givens_kernel(cd* H, int ldh, cd* cs, cd* sn, cd* g, int j, const double* hnext,
-                              double* res) {
+// ||w|| from the norm partials; then column j of H gets the rotations of columns
+// 0..j-1 and a new rotation that zeroes H[j+1][j]; g is rotated alongside.  With
+// c = a/den, s = b/den the rotation [[conj c, conj s], [-s, c]] maps (a, b) to
+// (den, 0).  res = |g[j+1]|, the residual norm of the current iterate.
+__global__ void givens_kernel(cd* H, int ldh, cd* cs, cd* sn, cd* g, int j, const double* npart,
+                              int nblk, double* hnext, double* res) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s2 = 0.0;
+  for (int b = 0; b < nblk; ++b) s2 += npart[b];
+  double hn = sqrt(s2);
+  *hnext = hn;
   cd* h = H + (size_t)j * ldh;
-  h[j + 1] = cd{*hnext, 0.0};
+  h[j + 1] = cd{hn, 0.0};
   for (int i = 0; i < j; ++i) {
     cd t = conj(cs[i]) * h[i] + conj(sn[i]) * h[i + 1];
     h[i + 1] = -(sn[i] * h[i]) + cs[i] * h[i + 1];
@@ -134,7 +141,7 @@ __global__ void givens_kernel(cd* H, int ldh, cd* cs, cd* sn, cd* g, int j, cons
   h[j + 1] = cd{0.0, 0.0};
   g[j + 1] = -(s * g[j]);
   g[j] = conj(c) * g[j];
-  *res = sqrt(cabs2(g[j + 1]));
+  res[j] = sqrt(cabs2(g[j + 1]));
 }
 
 // back substitution R y = g for the leading k x k triangle
@@ -158,19 +165,24 @@ __global__ void init_g_kernel(cd* g, int len, const double* beta) {
 static grt_status ensure_workspace(grt_ctx* c, int m) {
   if (c->krylov_restart == m && c->d_V) return GRT_OK;
   hipFree(c->d_V); hipFree(c->d_H); hipFree(c->d_cs); hipFree(c->d_sn); hipFree(c->d_gv);
-  hipFree(c->d_y); hipFree(c->d_scal); hipFree(c->d_dotpart);
+  hipFree(c->d_y); hipFree(c->d_scal); hipFree(c->d_dotpart); hipFree(c->d_res);
   const size_t n = (size_t)c->n_beta;
-  c->n_dot_blocks = (int)std::min<size_t>(128, (n + KT * 4 - 1) / (KT * 4));
+  c->n_dot_blocks = (int)std::min<size_t>(16, (n + KT * 4 - 1) / (KT * 4));
   if (c->n_dot_blocks < 1) c->n_dot_blocks = 1;
-  GRT_HIP(c, hipMalloc(&c->d_V, sizeof(cd) * n * (m + 2)));
+  GRT_HIP(c, hipMalloc(&c->d_V, sizeof(cd) * n * (m + 4)));
   GRT_HIP(c, hipMalloc(&c->d_H, sizeof(cd) * (size_t)(m + 1) * (m + 1)));
   GRT_HIP(c, hipMalloc(&c->d_cs, sizeof(cd) * (m + 1)));
   GRT_HIP(c, hipMalloc(&c->d_sn, sizeof(cd) * (m + 1)));
   GRT_HIP(c, hipMalloc(&c->d_gv, sizeof(cd) * (m + 2)));
   GRT_HIP(c, hipMalloc(&c->d_y, sizeof(cd) * (m + 1)));
   GRT_HIP(c, hipMalloc(&c->d_scal, sizeof(double) * (16 + c->n_dot_blocks)));
+  GRT_HIP(c, hipMalloc(&c->d_res, sizeof(double) * (m + 1)));
+  if (!c->ev_res[0]) {
+    GRT_HIP(c, hipEventCreateWithFlags(&c->ev_res[0], hipEventDisableTiming));
+    GRT_HIP(c, hipEventCreateWithFlags(&c->ev_res[1], hipEventDisableTiming));
+  }
   GRT_HIP(c, hipMalloc(&c->d_dotpart, sizeof(cd) * ((size_t)(m + 2) * c->n_dot_blocks + 2 * (size_t)(m + 2))));
-  if (!c->h_pinned) GRT_HIP(c, hipHostMalloc(&c->h_pinned, sizeof(double) * 8));
+  if (!c->h_pinned) GRT_HIP(c, hipHostMalloc(&c->h_pinned, sizeof(double) * 16));
   c->krylov_restart = m;
   return GRT_OK;
 }
@@ -197,6 +209,124 @@ static grt_status read_scalar(grt_ctx* c, const double* dev, double* host) {
     if (s_ != GRT_OK) return s_;   \
   } while (0)
 
+__global__ void add_vec_kernel(cd* x, const cd* e, int n) {
+  int i = blockIdx.x * KT + threadIdx.x;
+  if (i < n) x[i] = x[i] + e[i];
+}
+
+typedef grt_status (*KOp)(grt_ctx*, const cd*, cd*);
+
+// y = d o x (elementwise; y may alias x)
+__global__ void dscale_kernel(const cd* x, const double* d, cd* y, int n) {
+  int i = blockIdx.x * KT + threadIdx.x;
+  if (i < n) y[i] = d[i] * x[i];
+}
+
+// The normalised operators D K D^{-1} (D = |H_|n|(k2 R_m)|, a diagonal similarity
+// that keeps the reduced system well conditioned when high-order coefficients are
+// tiny): scale the input by D^{-1}, apply, scale the output by D.
+static grt_status apply_hat(grt_ctx* c, KOp op, const cd* xh, cd* y) {
+  const int n = (int)c->n_beta;
+  const int gridn = (n + KT - 1) / KT;
+  dscale_kernel<<<gridn, KT, 0, c->stream>>>(xh, c->d_dinv, c->d_xtmp, n);
+  grt_status st = op(c, c->d_xtmp, y);
+  if (st != GRT_OK) return st;
+  dscale_kernel<<<gridn, KT, 0, c->stream>>>(y, c->d_dnorm, y, n);
+  return GRT_OK;
+}
+static grt_status apply_K_hat(grt_ctx* c, const cd* x, cd* y) { return apply_hat(c, apply_K, x, y); }
+static grt_status apply_K_mixed_hat(grt_ctx* c, const cd* x, cd* y) {
+  return apply_hat(c, apply_K_mixed, x, y);
+}
+
+struct CoreResult {
+  int iters = 0, cycles = 0;
+  double rel = 1.0;
+  bool converged = false;
+};
+
+// Restarted GMRES for op(x) = b from the iterate in x (updated in place).  b must not
+// live in basis slots 0..m.  Stops at ||b - op x|| <= tol ||b|| or after maxit steps.
+static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double tol, int maxit,
+                             int m, CoreResult* res) {
+  const int n = (int)c->n_beta;
+  hipStream_t s = c->stream;
+  const size_t ldv = (size_t)n;
+  cd* V = c->d_V;
+  const int ldh = m + 1;
+  const int gridn = (n + KT - 1) / KT;
+  const int nblk = c->n_dot_blocks;
+  double* d_bn = c->d_scal + 0;
+  double* d_beta = c->d_scal + 1;
+  double* d_hn = c->d_scal + 2;
+  double* d_npart = c->d_scal + 16;
+  double* d_res = c->d_res;
+  double* h_res = c->h_pinned + 8;
+  GRT_TRY(vec_norm(c, bvec, n, d_bn));
+  double bn = 0.0;
+  GRT_TRY(read_scalar(c, d_bn, &bn));
+  *res = CoreResult{};
+  if (!(bn > 0)) {
+    res->rel = 0.0;
+    res->converged = true;
+    return GRT_OK;
+  }
+  int total = 0;
+  while (true) {
+    // r = b - op x into V_0
+    GRT_TRY(op(c, x, V + ldv));  // temp in slot 1
+    sub_vec_kernel<<<gridn, KT, 0, s>>>(bvec, V + ldv, V, n);
+    GRT_TRY(vec_norm(c, V, n, d_beta));
+    double beta = 0.0;
+    GRT_TRY(read_scalar(c, d_beta, &beta));
+    res->rel = beta / bn;
+    if (res->rel <= tol) { res->converged = true; break; }
+    if (total >= maxit) break;
+    scale_kernel<<<gridn, KT, 0, s>>>(V, V, n, d_beta);
+    init_g_kernel<<<1, 1024, 0, s>>>(c->d_gv, m + 1, d_beta);
+    // Arnoldi steps.  The host never waits on the step it just queued: the
+    // residual estimate of step j is checked after step j+1 has been queued, so
+    // at most one step is computed past convergence (and discarded: the
+    // least-squares solve uses columns 0..k-1 only, which that step leaves intact).
+    int k = 0;
+    int queued = 0;
+    for (int j = 0; j < m && total + queued < maxit; ++j) {
+      cd* w = V + (size_t)(j + 1) * ldv;
+      GRT_TRY(op(c, V + (size_t)j * ldv, w));
+      cd* hcol = c->d_H + (size_t)j * ldh;
+      for (int pass = 0; pass < 2; ++pass) {
+        dim3 gd(nblk, j + 1);
+        dots_kernel<<<gd, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, nblk);
+        update_kernel<<<gridn, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, nblk, j + 1, hcol, pass);
+      }
+      norm2_kernel<<<nblk, KT, 0, s>>>(w, n, d_npart, nblk);
+      givens_kernel<<<1, 64, 0, s>>>(c->d_H, ldh, c->d_cs, c->d_sn, c->d_gv, j, d_npart, nblk,
+                                     d_hn, d_res);
+      scale_kernel<<<gridn, KT, 0, s>>>(w, w, n, d_hn);
+      GRT_HIP(c, hipGetLastError());
+      GRT_HIP(c, hipMemcpyAsync(h_res + (j & 1), d_res + j, sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+      GRT_HIP(c, hipEventRecord(c->ev_res[j & 1], s));
+      ++queued;
+      if (j >= 1) {
+        GRT_HIP(c, hipEventSynchronize(c->ev_res[(j - 1) & 1]));
+        if (h_res[(j - 1) & 1] / bn <= tol) { k = j; break; }
+      }
+      k = j + 1;
+    }
+    if (k == queued) {  // the last queued step has not been checked yet
+      GRT_HIP(c, hipEventSynchronize(c->ev_res[(k - 1) & 1]));
+    }
+    total += k;
+    backsolve_kernel<<<1, 64, 0, s>>>(c->d_H, ldh, c->d_gv, c->d_y, k);
+    axpy_basis_kernel<<<gridn, KT, 0, s>>>(x, V, ldv, n, c->d_y, k);
+    GRT_HIP(c, hipGetLastError());
+    res->cycles += 1;
+  }
+  res->iters = total;
+  return GRT_OK;
+}
+
 grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_stats* st) {
   auto t0 = std::chrono::steady_clock::now();
   const int n = (int)c->n_beta;
@@ -206,77 +336,64 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
   GRT_TRY(ensure_workspace(c, m));
   hipStream_t s = c->stream;
   const size_t ldv = (size_t)n;
-  cd* V = c->d_V;
-  cd* bvec = V + (size_t)(m + 1) * ldv;  // slot m+1 holds b
-  const int ldh = m + 1;
   const int gridn = (n + KT - 1) / KT;
-  double* d_bn = c->d_scal + 0;
-  double* d_beta = c->d_scal + 1;
-  double* d_hn = c->d_scal + 2;
-  double* d_res = c->d_scal + 3;
-  cd* h1 = c->d_dotpart + (size_t)(m + 2) * c->n_dot_blocks;  // reuse tail as two h vectors
-  cd* h2 = h1 + (m + 1);
-
+  cd* bvec = c->d_V + (size_t)(m + 1) * ldv;  // slot m+1: b
+  cd* rvec = c->d_V + (size_t)(m + 2) * ldv;  // slot m+2: refinement residual
+  cd* evec = c->d_V + (size_t)(m + 3) * ldv;  // slot m+3: refinement correction
   GRT_TRY(rhs_b(c, bvec));
-  GRT_TRY(vec_norm(c, bvec, n, d_bn));
-  double bn = 0.0;
-  GRT_TRY(read_scalar(c, d_bn, &bn));
-  if (!o->use_x0) GRT_HIP(c, hipMemsetAsync(x, 0, sizeof(cd) * n, s));
-  st->iters = 0;
-  st->cycles = 0;
-  st->rel_resid = 0.0;
-  if (!(bn > 0)) {
-    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return GRT_OK;
-  }
-  int total = 0;
-  double rel = 1.0;
-  bool converged = false;
-  while (true) {
-    // r = b - K x into V_0
-    GRT_TRY(apply_K(c, x, V + ldv));  // temp in slot 1
-    sub_vec_kernel<<<gridn, KT, 0, s>>>(bvec, V + ldv, V, n);
-    GRT_TRY(vec_norm(c, V, n, d_beta));
-    double beta = 0.0;
-    GRT_TRY(read_scalar(c, d_beta, &beta));
-    rel = beta / bn;
-    if (rel <= tol) { converged = true; break; }
-    if (total >= maxit) break;
-    scale_kernel<<<gridn, KT, 0, s>>>(V, V, n, d_beta);
-    init_g_kernel<<<1, 1024, 0, s>>>(c->d_gv, m + 1, d_beta);
-    GRT_HIP(c, hipMemsetAsync(c->d_H, 0, sizeof(cd) * (size_t)ldh * (m + 1), s));
-    int k = 0;
-    for (int j = 0; j < m && total < maxit; ++j) {
-      cd* w = V + (size_t)(j + 1) * ldv;
-      GRT_TRY(apply_K(c, V + (size_t)j * ldv, w));
-      cd* hcol = c->d_H + (size_t)j * ldh;
-      for (int pass = 0; pass < 2; ++pass) {
-        cd* hv = pass == 0 ? h1 : h2;
-        dim3 gd(c->n_dot_blocks, j + 1);
-        dots_kernel<<<gd, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, c->n_dot_blocks);
-        reduce_dots_kernel<<<(j + 1 + 63) / 64, 64, 0, s>>>(c->d_dotpart, c->n_dot_blocks, j + 1,
-                                                            hv, 0);
-        update_kernel<<<gridn, KT, 0, s>>>(V, ldv, w, n, hv, j + 1);
-        reduce_dots_kernel<<<(j + 1 + 63) / 64, 64, 0, s>>>(hv, 1, j + 1, hcol, pass);
-      }
-      GRT_TRY(vec_norm(c, w, n, d_hn));
-      scale_kernel<<<gridn, KT, 0, s>>>(w, w, n, d_hn);
-      givens_kernel<<<1, 64, 0, s>>>(c->d_H, ldh, c->d_cs, c->d_sn, c->d_gv, j, d_hn, d_res);
+  // work in normalised variables: b^ = D b, x^ = D x
+  dscale_kernel<<<gridn, KT, 0, s>>>(bvec, c->d_dnorm, bvec, n);
+  if (!o->use_x0)
+    GRT_HIP(c, hipMemsetAsync(x, 0, sizeof(cd) * n, s));
+  else
+    dscale_kernel<<<gridn, KT, 0, s>>>(x, c->d_dnorm, x, n);
+  *st = grt_solve_stats{};
+  CoreResult r;
+  if (o->precision == GRT_FP64) {
+    GRT_TRY(gmres_core(c, apply_K_hat, bvec, x, tol, maxit, m, &r));
+    st->iters = r.iters;
+    st->cycles = r.cycles;
+    st->rel_resid = r.rel;
+    st->refine_steps = 0;
+  } else {
+    // FP64 iterative refinement around the FP32-translation operator:
+    //   r = b - K x (FP64), solve K32 e = r to inner_tol, x += e.
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+    const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
+    double* d_bn = c->d_scal + 4;
+    double* d_rn = c->d_scal + 5;
+    GRT_TRY(vec_norm(c, bvec, n, d_bn));
+    double bn = 0.0;
+    GRT_TRY(read_scalar(c, d_bn, &bn));
+    int total = 0, cycles = 0;
+    double rel = 1.0;
+    bool conv = false;
+    for (int outer = 0; outer <= max_ref; ++outer) {
+      GRT_TRY(apply_K_hat(c, x, rvec));
+      sub_vec_kernel<<<gridn, KT, 0, s>>>(bvec, rvec, rvec, n);
+      GRT_TRY(vec_norm(c, rvec, n, d_rn));
+      double rn = 0.0;
+      GRT_TRY(read_scalar(c, d_rn, &rn));
+      rel = bn > 0 ? rn / bn : 0.0;
+      st->refine_steps = outer;
+      if (rel <= tol) { conv = true; break; }
+      if (outer == max_ref || total >= maxit) break;
+      GRT_HIP(c, hipMemsetAsync(evec, 0, sizeof(cd) * n, s));
+      GRT_TRY(gmres_core(c, apply_K_mixed_hat, rvec, evec, itol, maxit - total, m, &r));
+      total += r.iters;
+      cycles += r.cycles;
+      add_vec_kernel<<<gridn, KT, 0, s>>>(x, evec, n);
       GRT_HIP(c, hipGetLastError());
-      ++total;
-      k = j + 1;
-      double res = 0.0;
-      GRT_TRY(read_scalar(c, d_res, &res));
-      if (res / bn <= tol) break;
     }
-    backsolve_kernel<<<1, 64, 0, s>>>(c->d_H, ldh, c->d_gv, c->d_y, k);
-    axpy_basis_kernel<<<gridn, KT, 0, s>>>(x, V, ldv, n, c->d_y, k);
-    GRT_HIP(c, hipGetLastError());
-    st->cycles += 1;
+    st->iters = total;
+    st->cycles = cycles;
+    st->rel_resid = rel;
+    r.converged = conv;
   }
+  // back to beta = D^{-1} x^
+  dscale_kernel<<<gridn, KT, 0, s>>>(x, c->d_dinv, x, n);
+  GRT_HIP(c, hipGetLastError());
   GRT_HIP(c, hipStreamSynchronize(s));
-  st->iters = total;
-  st->rel_resid = rel;
   st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return converged ? GRT_OK : set_err(c, GRT_ENOCONV, "GMRES did not reach the tolerance");
+  return r.converged ? GRT_OK : set_err(c, GRT_ENOCONV, "GMRES did not reach the tolerance");
 }

@@ -435,6 +435,28 @@ __global__ void mie_kernel(int M, int P, double k2, const double* rad, const dou
   }
 }
 
+// Scaling of the normalised system: d[m][n] = |H_|n|(k2 R_m)|, the size of each
+// outgoing multipole on its own disk boundary (upward recurrence), and 1/d.
+__global__ void dnorm_kernel(int M, int P, double k2, const double* rad, double* dn,
+                             double* dinv) {
+  int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double x = k2 * rad[m];
+  cd hp, hc;
+  hankel01(x, hp, hc);
+  int nb = 2 * P + 1;
+  for (int q = 0; q <= P; ++q) {
+    double a = sqrt(cabs2(hp));
+    dn[(size_t)m * nb + P + q] = a;
+    dn[(size_t)m * nb + P - q] = a;
+    dinv[(size_t)m * nb + P + q] = 1.0 / a;
+    dinv[(size_t)m * nb + P - q] = 1.0 / a;
+    cd hn = (2.0 * (q + 1) / x) * hc - hp;
+    hp = hc;
+    hc = hn;
+  }
+}
+
 // L2L generator of every inclusion: E_j[m] = J_m(k2 rho) e^{i m phi}, m = -L..L,
 // rho e^{i phi} = c_j - (0, 0).
 __global__ void l2l_table_kernel(int M, int L, double k2, const double* cx, const double* cy,
@@ -606,6 +628,11 @@ grt_status setup_build(grt_ctx* c) {
     GRT_HIP(c, hipMalloc(&c->d_mie, sizeof(cd) * c->n_beta));
     mie_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, c->P, g.k[1], c->d_rad, c->d_kp,
                                                       c->d_mie);
+    GRT_HIP(c, hipMalloc(&c->d_dnorm, sizeof(double) * c->n_beta));
+    GRT_HIP(c, hipMalloc(&c->d_dinv, sizeof(double) * c->n_beta));
+    GRT_HIP(c, hipMalloc(&c->d_xtmp, sizeof(cd) * c->n_beta));
+    dnorm_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, c->P, g.k[1], c->d_rad,
+                                                        c->d_dnorm, c->d_dinv);
     int L = g.Q[1] + c->P;
     GRT_HIP(c, hipMalloc(&c->d_l2l, sizeof(cd) * (size_t)c->M * (2 * L + 1)));
     l2l_table_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, L, g.k[1], c->d_cx, c->d_cy,

@@ -40,12 +40,13 @@ class grt_incidence(C.Structure):
 
 class grt_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("restart", C.c_int),
-                ("use_x0", C.c_int)]
+                ("use_x0", C.c_int), ("precision", C.c_int), ("inner_tol", C.c_double),
+                ("max_refine", C.c_int)]
 
 
 class grt_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("rel_resid", C.c_double),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("refine_steps", C.c_int)]
 
 
 class grt_sizes(C.Structure):
@@ -182,10 +183,10 @@ class Context:
         return _VP(t.data_ptr())
 
     # -- operator --------------------------------------------------------------
-    def apply(self, x, y=None):
+    def apply(self, x, y=None, precision=GRT_FP64):
         y = self.new_vec() if y is None else y
         self._enter()
-        self._check(self.lib.grt_apply(self.h, self._vec_ptr(x), self._vec_ptr(y), GRT_FP64))
+        self._check(self.lib.grt_apply(self.h, self._vec_ptr(x), self._vec_ptr(y), precision))
         self._leave()
         return y
 
@@ -210,11 +211,13 @@ class Context:
         self._leave()
         return b
 
-    def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, out=None, check=True):
+    def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, out=None, check=True,
+              precision=GRT_FP64, inner_tol=1e-5, max_refine=10):
         beta = self.new_vec() if out is None else out
         if x0 is not None:
             beta.copy_(x0)
-        opts = grt_solve_opts(tol=tol, maxit=maxit, restart=restart, use_x0=int(x0 is not None))
+        opts = grt_solve_opts(tol=tol, maxit=maxit, restart=restart, use_x0=int(x0 is not None),
+                              precision=precision, inner_tol=inner_tol, max_refine=max_refine)
         stats = grt_solve_stats()
         self._enter()
         st = self.lib.grt_solve(self.h, C.byref(opts), self._vec_ptr(beta), C.byref(stats))

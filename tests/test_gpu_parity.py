@@ -146,3 +146,25 @@ def test_invalid_geometry_rejected(torch_cuda):
     with pytest.raises(GratingError) as ei:
         ctx.set_problem(pb)
     assert ei.value.status == GRT_EGEOM
+
+
+@pytest.mark.parametrize("M,P,seed", [(4, 10, 1), (40, 10, 12), (30, 15, 13), (25, 20, 14)])
+def test_mixed_precision_refinement(torch_cuda, M, P, seed):
+    """FP32 translation + FP64 refinement reaches the FP64 solution to the 1e-9 bar."""
+    from oracle.solver import Reduced
+    from paper_1412_7466_amd.grating import GRT_FP32
+    pb = inputs.tiny_m4() if M == 4 else inputs.small(M, P, seed=seed)
+    red = Reduced(pb)
+    ctx = _ctx(pb)
+    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    y64 = _np(ctx.apply(xd))
+    y32 = _np(ctx.apply(xd, precision=GRT_FP32))
+    e32 = rel(y32, y64)
+    say(f"[gpu] mixed apply M={M} P={P} rel diff vs FP64 {e32:.2e}")
+    assert 0 < e32 < 1e-4
+    beta_o = red.solve_lu()
+    beta, st = ctx.solve(tol=1e-12, restart=150, precision=GRT_FP32, inner_tol=1e-5)
+    say(f"[gpu] mixed M={M} P={P} iters={st.iters} refine={st.refine_steps} "
+        f"resid={st.rel_resid:.2e}")
+    assert st.rel_resid <= 1e-12
+    assert rel(_np(beta), beta_o) < 1e-9
