@@ -89,6 +89,18 @@ def main():
     m2l_ms, launches = ctx.profile_read()
     ctx.profile(False)
     out = ctx.bragg(beta)
+    # the same workload through the mixed-precision path (FP32 translation, FP64 refinement)
+    from paper_1412_7466_amd.grating import GRT_FP32
+    ctx.solve(tol=a.tol, restart=a.restart, precision=GRT_FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        bm, stm = ctx.solve(tol=a.tol, restart=a.restart, precision=GRT_FP32)
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / a.steps
+    mixed = {"solves_per_s": 1.0 / t_mixed, "iters": stm.iters, "refine_steps": stm.refine_steps,
+             "rel_resid": stm.rel_resid,
+             "rel_diff_vs_fp64": float(torch.linalg.norm(bm - beta) / torch.linalg.norm(beta))}
     P, M = pb.P, pb.M
     avg_ms = m2l_ms / max(launches, 1)
     flops = 8.0 * (2 * P + 1) ** 2 * M * M     # Toeplitz contraction per (target, source) pair
@@ -114,6 +126,7 @@ def main():
         "rel_resid": resid[-1],
         "flux_err": out["flux_err"],
         "setup_s": t_setup,
+        "mixed_fp32_fp64": mixed,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
                      "traffic": None, "kernel": f"m2l_kernel<{P}>",

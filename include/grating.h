@@ -181,6 +181,33 @@ grt_status grt_get_mie(grt_ctx* ctx, double* s_host);
 grt_status grt_profile_enable(grt_ctx* ctx, int enable);
 grt_status grt_profile_read(grt_ctx* ctx, double* m2l_ms_total, int64_t* m2l_launches);
 
+/* ---- Batched solves --------------------------------------------------------
+ * Many problems (different inclusion sets, angles or frequencies; the sweeps of
+ * sec. 6) solved together: every GMRES step of the batch is one launch per kernel
+ * over all problems, so small problems share the device instead of each leaving
+ * it mostly idle.  Each problem converges on its own (its own Hessenberg matrix,
+ * rotations and residual) exactly as grt_solve would, in FP64. */
+typedef struct grt_batch grt_batch;
+
+/* Make a batch of n built contexts (all with M >= 1, all on one device).  The
+ * batch borrows the contexts' device data: they must stay alive and unchanged
+ * (no grt_set_problem / grt_build / grt_apply / grt_solve on them) until
+ * grt_batch_destroy.  hip_stream: stream to run on, or NULL for a private one.
+ * GRT_ESTATE if a context is not built, has no inclusions or is on another
+ * device; GRT_EINVAL for n <= 0 or NULL arrays. */
+grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, void* hip_stream);
+grt_status grt_batch_destroy(grt_batch* batch);
+const char* grt_batch_error_message(const grt_batch* batch);
+
+/* Solve every problem of the batch.  beta[i] is a device vector of the i-th
+ * context's n_beta complex entries (its initial guess on entry when
+ * opts->use_x0); stats (host, n entries, may be NULL) receives each problem's
+ * iterations, restarts and final relative residual (seconds is the batch's).
+ * opts->precision must be GRT_FP64 (GRT_EUNSUP otherwise); opts->maxit bounds
+ * the lockstep steps of the whole batch.  GRT_ENOCONV if any problem missed tol. */
+grt_status grt_batch_solve(grt_batch* batch, const grt_solve_opts* opts, void* const* beta,
+                           grt_solve_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

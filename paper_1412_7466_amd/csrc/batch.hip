@@ -1,0 +1,811 @@
+// Batched solves: many problems (geometries of uneven M, angles, frequencies) solved
+// together, each step of GMRES advancing all of them with one launch per kernel.
+//
+// Layout: the coefficient vectors of all problems are concatenated, problem i
+// occupying segments [seg0_i, seg0_i + nseg_i) of SEG entries (zero padded), so that
+// every elementwise and reduction kernel runs once over the whole batch and finds
+// its problem through a segment -> problem table.  The apply kernels run over lists
+// of work items (problem, block x, block y) built once per batch; each item runs
+// the same block-level code as a single-problem launch (translate.h), with the
+// problem's descriptor in device memory.  Problems are grouped by multipole order
+// P (a compile-time parameter of the translation code).
+//
+// The Krylov method is the single-problem one (restarted GMRES, CGS2, Givens, on
+// the normalised operator D K D^{-1}), run in lockstep: every problem has its own
+// Hessenberg matrix, rotations and residual; a problem that has converged keeps its
+// own step count k_i and takes no further updates.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "translate.h"
+
+using namespace grt;
+
+namespace {
+
+constexpr int SEG = 1024;   // entries per segment (256 threads x 4)
+constexpr int BT = 256;
+
+struct InstDesc {
+  DevGeom g;
+  const double *cx, *cy, *htab;
+  const cd *mie, *W1, *W2, *l2l, *f;
+  int M, P, nb, rank, n_g, n_b, Q2;
+  int m2l_chunk, m2l_nchunks, c_chunk, c_nchunks, b_chunk, b_nchunks;
+  cd *pT, *pC, *pB, *pL, *gvec, *tvec, *wvec;
+  int64_t off, nbeta;
+  int seg0, nseg;
+};
+
+struct Item {
+  int inst, x, y;
+};
+
+// ---------------------------------------------------------------------------
+// batched apply kernels
+// ---------------------------------------------------------------------------
+
+template <int P>
+__global__ void __launch_bounds__(M2L_THREADS) m2l_batched(const InstDesc* __restrict__ D,
+                                                           const Item* __restrict__ it,
+                                                           const cd* __restrict__ X) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  m2l_block<P, cd>(q.cx, q.cy, X + q.off, q.pT, q.M, q.m2l_chunk, q.g.k[1], q.g.d, q.g.alpha,
+                   q.g.alpha_inv, q.htab, 0.0, w.x, w.y);
+}
+
+template <int P>
+__global__ void __launch_bounds__(64) cx_batched(const InstDesc* __restrict__ D,
+                                                 const Item* __restrict__ it,
+                                                 const cd* __restrict__ X) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  cx_block<P>(q.g, q.cx, q.cy, X + q.off, q.pC, q.c_chunk, q.htab, w.x, w.y);
+}
+
+__global__ void __launch_bounds__(256) cxr_batched(const InstDesc* __restrict__ D,
+                                                   const Item* __restrict__ it) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  cx_reduce_block(q.g, q.pC, q.c_nchunks, q.gvec, w.x);
+}
+
+// rows [4 x, 4 x + 4) of W (rows x cols, row-major) times v: one wavefront per row.
+__device__ inline void gemv_rows_block(const cd* __restrict__ W, const cd* __restrict__ v, cd* y,
+                                       int rows, int cols, int bx) {
+  int row = bx * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const cd* w = W + (size_t)row * cols;
+  double ar = 0.0, ai = 0.0;
+  for (int k = lane; k < cols; k += 64) {
+    cd a = w[k], b = v[k];
+    ar = fma(a.r, b.r, ar);
+    ar = fma(-a.i, b.i, ar);
+    ai = fma(a.r, b.i, ai);
+    ai = fma(a.i, b.r, ai);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_xor(ar, off, 64);
+    ai += __shfl_xor(ai, off, 64);
+  }
+  if (lane == 0) y[row] = cd{ar, ai};
+}
+
+// t = Sigma^+ U^* g (g = f for the right-hand side), then w = E V t
+__global__ void __launch_bounds__(256) gemv1_batched(const InstDesc* __restrict__ D,
+                                                     const Item* __restrict__ it, int use_f) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  gemv_rows_block(q.W1, use_f ? q.f : q.gvec, q.tvec, q.rank, q.n_g, w.x);
+}
+__global__ void __launch_bounds__(256) gemv2_batched(const InstDesc* __restrict__ D,
+                                                     const Item* __restrict__ it) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  gemv_rows_block(q.W2, q.tvec, q.wvec, q.n_b, q.rank, w.x);
+}
+
+template <int P>
+__global__ void __launch_bounds__(64) bx_batched(const InstDesc* __restrict__ D,
+                                                 const Item* __restrict__ it) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  bx_block<P>(q.g, q.cx, q.cy, q.wvec, q.pB, q.b_chunk, q.htab, w.x, w.y);
+}
+
+__global__ void __launch_bounds__(64) l2l_batched(const InstDesc* __restrict__ D,
+                                                  const Item* __restrict__ it) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  l2l_block(q.M, q.P, q.Q2, q.l2l, q.wvec + q.g.col_off[CB_A2], q.pL, w.x);
+}
+
+// Y = D o (x - s o (T x - B x)) with x = X (already un-normalised) for mode 0, or
+// Y = D o (s o B f) for the right-hand side (mode 1).  Padding entries get 0.
+__global__ void __launch_bounds__(BT) combine_batched(const InstDesc* __restrict__ D,
+                                                      const int* __restrict__ seg2inst,
+                                                      const cd* __restrict__ X,
+                                                      const double* __restrict__ dn, cd* Y,
+                                                      int mode) {
+  const int seg = blockIdx.x;
+  const InstDesc& q = D[seg2inst[seg]];
+  for (int r = 0; r < SEG / BT; ++r) {
+    const int64_t i = (int64_t)seg * SEG + r * BT + threadIdx.x;
+    const int64_t loc = i - q.off;
+    if (loc >= q.nbeta) {
+      Y[i] = cd{0.0, 0.0};
+      continue;
+    }
+    cd b = q.pL[loc];
+    for (int c = 0; c < q.b_nchunks; ++c) b += q.pB[(size_t)c * q.nbeta + loc];
+    cd y;
+    if (mode == 0) {
+      cd t{0, 0};
+      for (int c = 0; c < q.m2l_nchunks; ++c) t += q.pT[(size_t)c * q.nbeta + loc];
+      y = X[i] - q.mie[loc] * (t - b);
+    } else {
+      y = q.mie[loc] * b;
+    }
+    Y[i] = dn[i] * y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched Krylov kernels (concatenated vectors, per-problem reductions)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(BT) ew_scale_kernel(const cd* x, const double* d, cd* y,
+                                                      int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (i < n) y[i] = d[i] * x[i];
+}
+__global__ void __launch_bounds__(BT) ew_sub_kernel(const cd* a, const cd* b, cd* o, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (i < n) o[i] = a[i] - b[i];
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int t = 0; t < BT / 64; ++t) s += red[t];
+  return s;
+}
+
+// partial[seg] = sum over the segment of |x|^2
+__global__ void __launch_bounds__(BT) seg_norm2_kernel(const cd* __restrict__ x, double* partial) {
+  __shared__ double red[BT / 64];
+  double s = 0.0;
+  for (int r = 0; r < SEG / BT; ++r) s += cabs2(x[(int64_t)blockIdx.x * SEG + r * BT + threadIdx.x]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// nrm[i] = sqrt(sum of the segments of problem i)
+__global__ void inst_norm_kernel(const InstDesc* __restrict__ D, int B, const double* partial,
+                                 double* nrm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  double s = 0.0;
+  for (int g = D[i].seg0; g < D[i].seg0 + D[i].nseg; ++g) s += partial[g];
+  nrm[i] = sqrt(s);
+}
+
+// y = x / nrm[problem] (where nrm > 0)
+__global__ void __launch_bounds__(BT) inst_scale_kernel(const int* __restrict__ seg2inst,
+                                                        const cd* x, const double* nrm, cd* y) {
+  const double s = nrm[seg2inst[blockIdx.x]];
+  for (int r = 0; r < SEG / BT; ++r) {
+    int64_t i = (int64_t)blockIdx.x * SEG + r * BT + threadIdx.x;
+    y[i] = s > 0 ? (1.0 / s) * x[i] : x[i];
+  }
+}
+
+// partial[v][seg] = sum over the segment of conj(V_v) w, v = 0..nv-1
+__global__ void __launch_bounds__(BT) seg_dots_kernel(const cd* __restrict__ V, size_t ldv,
+                                                      const cd* __restrict__ w, int nv, int nseg,
+                                                      cd* partial) {
+  __shared__ double red[BT / 64];
+  cd wv[SEG / BT];
+  for (int r = 0; r < SEG / BT; ++r) wv[r] = w[(int64_t)blockIdx.x * SEG + r * BT + threadIdx.x];
+  for (int v = 0; v < nv; ++v) {
+    const cd* a = V + (size_t)v * ldv + (int64_t)blockIdx.x * SEG;
+    double sr = 0.0, si = 0.0;
+    for (int r = 0; r < SEG / BT; ++r) {
+      cd x = a[r * BT + threadIdx.x];
+      sr = fma(x.r, wv[r].r, sr);
+      sr = fma(x.i, wv[r].i, sr);
+      si = fma(x.r, wv[r].i, si);
+      si = fma(-x.i, wv[r].r, si);
+    }
+    sr = block_sum(sr, red);
+    si = block_sum(si, red);
+    if (threadIdx.x == 0) partial[(size_t)v * nseg + blockIdx.x] = cd{sr, si};
+  }
+}
+
+// h[i][v] = sum over problem i's segments of partial[v][.]; H column j += h (pass 1)
+__global__ void inst_dots_kernel(const InstDesc* __restrict__ D, int B, int nv, int nseg,
+                                 const cd* partial, cd* h, int hld, cd* H, int ldh, int j,
+                                 int pass) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B * nv) return;
+  int i = idx / nv, v = idx - i * nv;
+  cd s{0, 0};
+  for (int g = D[i].seg0; g < D[i].seg0 + D[i].nseg; ++g) s += partial[(size_t)v * nseg + g];
+  h[(size_t)i * hld + v] = s;
+  cd* hc = H + (size_t)i * ldh * ldh + (size_t)j * ldh;
+  hc[v] = pass ? hc[v] + s : s;
+}
+
+// w -= sum_v h[problem][v] V_v
+__global__ void __launch_bounds__(BT) seg_update_kernel(const int* __restrict__ seg2inst,
+                                                        const cd* __restrict__ V, size_t ldv,
+                                                        cd* w, int nv, const cd* __restrict__ h,
+                                                        int hld) {
+  const cd* hh = h + (size_t)seg2inst[blockIdx.x] * hld;
+  for (int r = 0; r < SEG / BT; ++r) {
+    int64_t i = (int64_t)blockIdx.x * SEG + r * BT + threadIdx.x;
+    cd acc = w[i];
+    for (int v = 0; v < nv; ++v) {
+      cd hv = hh[v];
+      cd a = V[(size_t)v * ldv + i];
+      acc.r -= hv.r * a.r - hv.i * a.i;
+      acc.i -= hv.r * a.i + hv.i * a.r;
+    }
+    w[i] = acc;
+  }
+}
+
+// Per problem: rotations of column j of its Hessenberg matrix (as in the single
+// solver) and res[i][j] = |g[j+1]|; hn[i] = H[j+1][j].
+__global__ void inst_givens_kernel(int B, const double* nrm, cd* H, int ldh, cd* cs, cd* sn, cd* g,
+                                   int j, double* hn, double* res, int rld) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  cd* Hi = H + (size_t)i * ldh * ldh;
+  cd* csi = cs + (size_t)i * ldh;
+  cd* sni = sn + (size_t)i * ldh;
+  cd* gi = g + (size_t)i * (ldh + 1);
+  double hnorm = nrm[i];
+  hn[i] = hnorm;
+  cd* h = Hi + (size_t)j * ldh;
+  h[j + 1] = cd{hnorm, 0.0};
+  for (int t = 0; t < j; ++t) {
+    cd u = conj(csi[t]) * h[t] + conj(sni[t]) * h[t + 1];
+    h[t + 1] = -(sni[t] * h[t]) + csi[t] * h[t + 1];
+    h[t] = u;
+  }
+  cd a = h[j], b = h[j + 1];
+  double den = sqrt(cabs2(a) + cabs2(b));
+  cd c = den > 0 ? (1.0 / den) * a : cd{1.0, 0.0};
+  cd s = den > 0 ? (1.0 / den) * b : cd{0.0, 0.0};
+  csi[j] = c;
+  sni[j] = s;
+  h[j] = cd{den, 0.0};
+  h[j + 1] = cd{0.0, 0.0};
+  gi[j + 1] = -(s * gi[j]);
+  gi[j] = conj(c) * gi[j];
+  res[(size_t)i * rld + j] = sqrt(cabs2(gi[j + 1]));
+}
+
+__global__ void inst_init_g_kernel(int B, int len, const double* beta, cd* g) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B * len) return;
+  int i = idx / len, t = idx - i * len;
+  g[idx] = (t == 0) ? cd{beta[i], 0.0} : cd{0.0, 0.0};
+}
+
+__global__ void inst_backsolve_kernel(int B, const cd* H, int ldh, const cd* g, const int* kk,
+                                      cd* y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const cd* Hi = H + (size_t)i * ldh * ldh;
+  const cd* gi = g + (size_t)i * (ldh + 1);
+  cd* yi = y + (size_t)i * ldh;
+  int k = kk[i];
+  for (int r = k - 1; r >= 0; --r) {
+    cd s = gi[r];
+    for (int t = r + 1; t < k; ++t) s -= Hi[(size_t)t * ldh + r] * yi[t];
+    cd dd = Hi[(size_t)r * ldh + r];
+    yi[r] = (cabs2(dd) > 0) ? cdiv(s, dd) : cd{0.0, 0.0};
+  }
+}
+
+// x += sum_{v < k[problem]} y[problem][v] V_v
+__global__ void __launch_bounds__(BT) seg_axpy_basis_kernel(const int* __restrict__ seg2inst,
+                                                            cd* x, const cd* __restrict__ V,
+                                                            size_t ldv, const cd* __restrict__ y,
+                                                            int yld, const int* __restrict__ kk) {
+  const int i0 = seg2inst[blockIdx.x];
+  const int k = kk[i0];
+  const cd* yy = y + (size_t)i0 * yld;
+  for (int r = 0; r < SEG / BT; ++r) {
+    int64_t i = (int64_t)blockIdx.x * SEG + r * BT + threadIdx.x;
+    cd acc = x[i];
+    for (int v = 0; v < k; ++v) cmac(acc, yy[v], V[(size_t)v * ldv + i]);
+    x[i] = acc;
+  }
+}
+
+// beta[problem] -> x segments (scatter) and back (gather)
+__global__ void __launch_bounds__(BT) gather_kernel(const cd* src, cd* dst, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+}  // namespace
+
+struct grt_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<grt_ctx*> ctx;
+  int B = 0;
+  std::vector<InstDesc> hd;
+  InstDesc* dd = nullptr;
+  int64_t ntot = 0;
+  int nseg = 0;
+  int* d_seg2inst = nullptr;
+  double *d_dnorm = nullptr, *d_dinv = nullptr;
+  struct Group {
+    int P;
+    Item *m2l = nullptr, *cx = nullptr, *bx = nullptr;
+    int n_m2l = 0, n_cx = 0, n_bx = 0;
+  };
+  std::vector<Group> groups;
+  Item *it_cxr = nullptr, *it_g1 = nullptr, *it_g2 = nullptr, *it_l2l = nullptr;
+  int n_cxr = 0, n_g1 = 0, n_g2 = 0, n_l2l = 0;
+  size_t l2l_smem = 0;
+  // Krylov workspace
+  int m = 0;
+  cd* V = nullptr;        // m + 4 slots of ntot: basis 0..m, iterate, rhs, scratch
+  cd* H = nullptr;        // B x (m+1)^2
+  cd *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h = nullptr;
+  double *res = nullptr, *part = nullptr, *nrm = nullptr, *hn = nullptr, *bn = nullptr;
+  cd* dpart = nullptr;    // (m+1) x nseg
+  int* d_k = nullptr;
+  double* h_pinned = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+static grt_status bset(grt_batch* b, grt_status s, const std::string& m) {
+  if (b) b->err = m;
+  return s;
+}
+#define BHIP(b, call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return bset(b, GRT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+#define BTRY(x)                  \
+  do {                           \
+    grt_status s_ = (x);         \
+    if (s_ != GRT_OK) return s_; \
+  } while (0)
+
+template <typename T>
+static grt_status upload(grt_batch* b, const std::vector<T>& v, T** out) {
+  BHIP(b, hipMalloc(out, sizeof(T) * std::max<size_t>(1, v.size())));
+  if (!v.empty()) BHIP(b, hipMemcpy(*out, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return GRT_OK;
+}
+
+#define BATCH_P_DISPATCH(FN, P, ...)                          \
+  switch (P) {                                                \
+    case 1: FN<1>(__VA_ARGS__); break;                        \
+    case 2: FN<2>(__VA_ARGS__); break;                        \
+    case 3: FN<3>(__VA_ARGS__); break;                        \
+    case 4: FN<4>(__VA_ARGS__); break;                        \
+    case 5: FN<5>(__VA_ARGS__); break;                        \
+    case 6: FN<6>(__VA_ARGS__); break;                        \
+    case 8: FN<8>(__VA_ARGS__); break;                        \
+    case 10: FN<10>(__VA_ARGS__); break;                      \
+    case 12: FN<12>(__VA_ARGS__); break;                      \
+    case 15: FN<15>(__VA_ARGS__); break;                      \
+    case 20: FN<20>(__VA_ARGS__); break;                      \
+    default: return bset(b, GRT_EUNSUP, "P not compiled in"); \
+  }
+
+template <int P>
+static void launch_group_T(grt_batch* b, const grt_batch::Group& gp, const cd* X) {
+  if (gp.n_m2l) m2l_batched<P><<<gp.n_m2l, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2l, X);
+}
+template <int P>
+static void launch_group_C(grt_batch* b, const grt_batch::Group& gp, const cd* X) {
+  if (gp.n_cx) cx_batched<P><<<gp.n_cx, 64, 0, b->stream>>>(b->dd, gp.cx, X);
+}
+template <int P>
+static void launch_group_B(grt_batch* b, const grt_batch::Group& gp) {
+  if (gp.n_bx) bx_batched<P><<<gp.n_bx, 64, 0, b->stream>>>(b->dd, gp.bx);
+}
+
+// layer correction tail for all problems: t = W1 g (or f), w = W2 t, then B and L2L
+static grt_status batch_lowrank(grt_batch* b, int use_f) {
+  hipStream_t s = b->stream;
+  if (b->n_g1) gemv1_batched<<<b->n_g1, 256, 0, s>>>(b->dd, b->it_g1, use_f);
+  if (b->n_g2) gemv2_batched<<<b->n_g2, 256, 0, s>>>(b->dd, b->it_g2);
+  for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_B, gp.P, b, gp);
+  if (b->n_l2l) l2l_batched<<<b->n_l2l, 64, b->l2l_smem, s>>>(b->dd, b->it_l2l);
+  BHIP(b, hipGetLastError());
+  return GRT_OK;
+}
+
+// Y = D K D^{-1} Xh for every problem (Xh, Y concatenated; xtmp scratch)
+static grt_status batch_apply_hat(grt_batch* b, const cd* Xh, cd* Y, cd* xtmp) {
+  hipStream_t s = b->stream;
+  const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
+  ew_scale_kernel<<<gn, BT, 0, s>>>(Xh, b->d_dinv, xtmp, b->ntot);
+  for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_T, gp.P, b, gp, xtmp);
+  for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_C, gp.P, b, gp, xtmp);
+  if (b->n_cxr) cxr_batched<<<b->n_cxr, 256, 0, s>>>(b->dd, b->it_cxr);
+  BTRY(batch_lowrank(b, 0));
+  combine_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, xtmp, b->d_dnorm, Y, 0);
+  BHIP(b, hipGetLastError());
+  return GRT_OK;
+}
+
+static grt_status batch_rhs_hat(grt_batch* b, cd* Y) {
+  BTRY(batch_lowrank(b, 1));
+  combine_batched<<<b->nseg, BT, 0, b->stream>>>(b->dd, b->d_seg2inst, nullptr, b->d_dnorm, Y, 1);
+  BHIP(b, hipGetLastError());
+  return GRT_OK;
+}
+
+static grt_status batch_norms(grt_batch* b, const cd* x, double* nrm_dev) {
+  seg_norm2_kernel<<<b->nseg, BT, 0, b->stream>>>(x, b->part);
+  inst_norm_kernel<<<(b->B + 63) / 64, 64, 0, b->stream>>>(b->dd, b->B, b->part, nrm_dev);
+  BHIP(b, hipGetLastError());
+  return GRT_OK;
+}
+
+static grt_status batch_workspace(grt_batch* b, int m) {
+  if (b->m == m && b->V) return GRT_OK;
+  void* olds[] = {b->V, b->H, b->cs, b->sn, b->g, b->y, b->h, b->res, b->part, b->nrm, b->hn,
+                  b->bn, b->dpart, b->d_k};
+  for (void* p : olds)
+    if (p) hipFree(p);
+  const size_t B = b->B, n = b->ntot, ld = m + 1;
+  BHIP(b, hipMalloc(&b->V, sizeof(cd) * n * (m + 4)));
+  BHIP(b, hipMalloc(&b->H, sizeof(cd) * B * ld * ld));
+  BHIP(b, hipMalloc(&b->cs, sizeof(cd) * B * ld));
+  BHIP(b, hipMalloc(&b->sn, sizeof(cd) * B * ld));
+  BHIP(b, hipMalloc(&b->g, sizeof(cd) * B * (ld + 1)));
+  BHIP(b, hipMalloc(&b->y, sizeof(cd) * B * ld));
+  BHIP(b, hipMalloc(&b->h, sizeof(cd) * B * ld));
+  BHIP(b, hipMalloc(&b->res, sizeof(double) * B * ld));
+  BHIP(b, hipMalloc(&b->part, sizeof(double) * b->nseg));
+  BHIP(b, hipMalloc(&b->nrm, sizeof(double) * B));
+  BHIP(b, hipMalloc(&b->hn, sizeof(double) * B));
+  BHIP(b, hipMalloc(&b->bn, sizeof(double) * B));
+  BHIP(b, hipMalloc(&b->dpart, sizeof(cd) * ld * b->nseg));
+  BHIP(b, hipMalloc(&b->d_k, sizeof(int) * B));
+  if (!b->h_pinned) BHIP(b, hipHostMalloc(&b->h_pinned, sizeof(double) * 3 * B + 64));
+  if (!b->ev[0]) {
+    BHIP(b, hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming));
+    BHIP(b, hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming));
+  }
+  b->m = m;
+  return GRT_OK;
+}
+
+static grt_status read_vec(grt_batch* b, const double* dev, std::vector<double>& out) {
+  out.resize(b->B);
+  BHIP(b, hipMemcpyAsync(b->h_pinned, dev, sizeof(double) * b->B, hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  std::memcpy(out.data(), b->h_pinned, sizeof(double) * b->B);
+  return GRT_OK;
+}
+
+extern "C" {
+
+grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, void* hip_stream) {
+  if (!out || n <= 0 || !ctxs) return GRT_EINVAL;
+  *out = nullptr;
+  grt_batch* b = new (std::nothrow) grt_batch();
+  if (!b) return GRT_ENOMEM;
+  b->B = (int)n;
+  b->ctx.assign(ctxs, ctxs + n);
+  b->device = ctxs[0] ? ctxs[0]->device : 0;
+  for (grt_ctx* c : b->ctx) {
+    if (!c || !c->built || c->M == 0 || c->device != b->device) {
+      delete b;
+      return GRT_ESTATE;
+    }
+  }
+  hipSetDevice(b->device);
+  if (hip_stream) {
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return GRT_EHIP;
+    }
+    b->own_stream = true;
+  }
+  // descriptors and the concatenated layout
+  b->hd.resize(n);
+  int seg = 0;
+  std::vector<int> seg2inst;
+  std::map<int, std::vector<int>> byP;
+  size_t smem = 0;
+  for (int i = 0; i < n; ++i) {
+    grt_ctx* c = b->ctx[i];
+    hipStreamSynchronize(c->stream);
+    InstDesc& q = b->hd[i];
+    q.g = c->g;
+    q.cx = c->d_cx;
+    q.cy = c->d_cy;
+    q.htab = c->d_htab;
+    q.mie = c->d_mie;
+    q.W1 = c->d_W1;
+    q.W2 = c->d_W2;
+    q.l2l = c->d_l2l;
+    q.f = c->d_f;
+    q.M = (int)c->M;
+    q.P = c->P;
+    q.nb = c->nb;
+    q.rank = c->rank;
+    q.n_g = c->n_g;
+    q.n_b = c->n_b;
+    q.Q2 = c->g.Q[1];
+    q.m2l_chunk = c->m2l_chunk;
+    q.m2l_nchunks = c->m2l_nchunks;
+    q.c_chunk = c->c_chunk;
+    q.c_nchunks = c->c_nchunks;
+    q.b_chunk = c->b_chunk;
+    q.b_nchunks = c->b_nchunks;
+    q.pT = c->d_pT;
+    q.pC = c->d_pC;
+    q.pB = c->d_pB;
+    q.pL = c->d_pL;
+    q.gvec = c->d_gvec;
+    q.tvec = c->d_tvec;
+    q.wvec = c->d_wvec;
+    q.nbeta = c->n_beta;
+    q.seg0 = seg;
+    q.nseg = (int)((c->n_beta + SEG - 1) / SEG);
+    q.off = (int64_t)seg * SEG;
+    for (int t = 0; t < q.nseg; ++t) seg2inst.push_back(i);
+    seg += q.nseg;
+    byP[q.P].push_back(i);
+    const int L = q.Q2 + q.P;
+    smem = std::max(smem, sizeof(cd) * (size_t)(2 * L + 1 + 2 * q.Q2 + 1));
+  }
+  b->nseg = seg;
+  b->ntot = (int64_t)seg * SEG;
+  b->l2l_smem = smem;
+  // work items
+  std::vector<Item> cxr, g1, g2, l2l;
+  for (auto& kv : byP) {
+    grt_batch::Group gp;
+    gp.P = kv.first;
+    std::vector<Item> m2l, cxv, bxv;
+    for (int i : kv.second) {
+      const InstDesc& q = b->hd[i];
+      const int nt = 2 * q.g.N + q.g.Nw[1];
+      for (int y = 0; y < q.m2l_nchunks; ++y)
+        for (int x = 0; x < (q.M + 63) / 64; ++x) m2l.push_back({i, x, y});
+      for (int y = 0; y < q.c_nchunks; ++y)
+        for (int x = 0; x < (nt + 63) / 64; ++x) cxv.push_back({i, x, y});
+      for (int y = 0; y < q.b_nchunks; ++y)
+        for (int x = 0; x < (q.M + 63) / 64; ++x) bxv.push_back({i, x, y});
+    }
+    grt_status st;
+    if ((st = upload(b, m2l, &gp.m2l)) != GRT_OK || (st = upload(b, cxv, &gp.cx)) != GRT_OK ||
+        (st = upload(b, bxv, &gp.bx)) != GRT_OK) {
+      delete b;
+      return st;
+    }
+    gp.n_m2l = (int)m2l.size();
+    gp.n_cx = (int)cxv.size();
+    gp.n_bx = (int)bxv.size();
+    b->groups.push_back(gp);
+  }
+  for (int i = 0; i < n; ++i) {
+    const InstDesc& q = b->hd[i];
+    const int nt = 2 * q.g.N + q.g.Nw[1];
+    for (int x = 0; x < (nt + 3) / 4; ++x) cxr.push_back({i, x, 0});
+    for (int x = 0; x < (q.rank + 3) / 4; ++x) g1.push_back({i, x, 0});
+    for (int x = 0; x < (q.n_b + 3) / 4; ++x) g2.push_back({i, x, 0});
+    for (int x = 0; x < q.M; ++x) l2l.push_back({i, x, 0});
+  }
+  // concatenated normalisation
+  std::vector<double> dn(b->ntot, 0.0), di(b->ntot, 0.0);
+  for (int i = 0; i < n; ++i) {
+    grt_ctx* c = b->ctx[i];
+    const InstDesc& q = b->hd[i];
+    hipMemcpy(dn.data() + q.off, c->d_dnorm, sizeof(double) * q.nbeta, hipMemcpyDeviceToHost);
+    hipMemcpy(di.data() + q.off, c->d_dinv, sizeof(double) * q.nbeta, hipMemcpyDeviceToHost);
+  }
+  grt_status st;
+  if ((st = upload(b, cxr, &b->it_cxr)) != GRT_OK || (st = upload(b, g1, &b->it_g1)) != GRT_OK ||
+      (st = upload(b, g2, &b->it_g2)) != GRT_OK || (st = upload(b, l2l, &b->it_l2l)) != GRT_OK ||
+      (st = upload(b, seg2inst, &b->d_seg2inst)) != GRT_OK ||
+      (st = upload(b, b->hd, &b->dd)) != GRT_OK || (st = upload(b, dn, &b->d_dnorm)) != GRT_OK ||
+      (st = upload(b, di, &b->d_dinv)) != GRT_OK) {
+    delete b;
+    return st;
+  }
+  b->n_cxr = (int)cxr.size();
+  b->n_g1 = (int)g1.size();
+  b->n_g2 = (int)g2.size();
+  b->n_l2l = (int)l2l.size();
+  *out = b;
+  return GRT_OK;
+}
+
+grt_status grt_batch_destroy(grt_batch* b) {
+  if (!b) return GRT_OK;
+  hipSetDevice(b->device);
+  if (b->stream) hipStreamSynchronize(b->stream);
+  std::vector<void*> p = {b->dd, b->d_seg2inst, b->d_dnorm, b->d_dinv, b->it_cxr, b->it_g1,
+                          b->it_g2, b->it_l2l, b->V, b->H, b->cs, b->sn, b->g, b->y, b->h,
+                          b->res, b->part, b->nrm, b->hn, b->bn, b->dpart, b->d_k};
+  for (auto& gp : b->groups) {
+    p.push_back(gp.m2l);
+    p.push_back(gp.cx);
+    p.push_back(gp.bx);
+  }
+  for (void* q : p)
+    if (q) hipFree(q);
+  if (b->h_pinned) hipHostFree(b->h_pinned);
+  for (hipEvent_t e : b->ev)
+    if (e) hipEventDestroy(e);
+  if (b->own_stream) hipStreamDestroy(b->stream);
+  delete b;
+  return GRT_OK;
+}
+
+const char* grt_batch_error_message(const grt_batch* b) {
+  return b ? b->err.c_str() : "null batch";
+}
+
+grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* beta,
+                           grt_solve_stats* stats) {
+  if (!b || !o || !beta) return GRT_EINVAL;
+  b->err.clear();
+  if (o->precision != GRT_FP64) return bset(b, GRT_EUNSUP, "batched solves run in GRT_FP64");
+  if (!(o->tol > 0 && o->tol < 1)) return bset(b, GRT_EINVAL, "tol must be in (0, 1)");
+  BHIP(b, hipSetDevice(b->device));
+  auto t0 = std::chrono::steady_clock::now();
+  const int m = std::max(1, std::min(o->restart > 0 ? o->restart : 100, 1000));
+  const int maxit = o->maxit > 0 ? o->maxit : 1000;
+  const double tol = o->tol;
+  BTRY(batch_workspace(b, m));
+  hipStream_t s = b->stream;
+  const int B = b->B, ld = m + 1;
+  const size_t ldv = (size_t)b->ntot;
+  const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
+  cd* V = b->V;
+  cd* X = V + (size_t)(m + 1) * ldv;      // iterate (normalised)
+  cd* Bv = V + (size_t)(m + 2) * ldv;     // right-hand side (normalised)
+  cd* wtmp = V + (size_t)(m + 3) * ldv;   // scratch of the apply
+  // x0 and b
+  BTRY(batch_rhs_hat(b, Bv));
+  BHIP(b, hipMemsetAsync(X, 0, sizeof(cd) * ldv, s));
+  if (o->use_x0) {
+    for (int i = 0; i < B; ++i) {
+      const InstDesc& q = b->hd[i];
+      BHIP(b, hipMemcpyAsync(X + q.off, beta[i], sizeof(cd) * q.nbeta, hipMemcpyDeviceToDevice, s));
+    }
+    ew_scale_kernel<<<gn, BT, 0, s>>>(X, b->d_dnorm, X, b->ntot);
+  }
+  BTRY(batch_norms(b, Bv, b->bn));
+  std::vector<double> bn, beta0;
+  BTRY(read_vec(b, b->bn, bn));
+  std::vector<int> kk(B, 0), iters(B, 0), cycles(B, 0);
+  std::vector<double> rel(B, 1.0);
+  std::vector<char> done(B, 0);
+  int total = 0;
+  while (true) {
+    // R = B - K X into V_0
+    BTRY(batch_apply_hat(b, X, V + ldv, wtmp));
+    ew_sub_kernel<<<gn, BT, 0, s>>>(Bv, V + ldv, V, b->ntot);
+    BTRY(batch_norms(b, V, b->nrm));
+    BTRY(read_vec(b, b->nrm, beta0));
+    bool any = false;
+    for (int i = 0; i < B; ++i) {
+      rel[i] = bn[i] > 0 ? beta0[i] / bn[i] : 0.0;
+      done[i] = rel[i] <= tol;
+      if (!done[i]) any = true;
+    }
+    if (!any || total >= maxit) break;
+    inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, b->nrm, V);
+    inst_init_g_kernel<<<(B * (ld + 1) + 255) / 256, 256, 0, s>>>(B, ld + 1, b->nrm, b->g);
+    BHIP(b, hipMemsetAsync(b->H, 0, sizeof(cd) * (size_t)B * ld * ld, s));
+    std::fill(kk.begin(), kk.end(), -1);
+    for (int i = 0; i < B; ++i)
+      if (done[i]) kk[i] = 0;
+    int steps = 0;
+    // residual estimates of step jj, in the pinned buffer of parity jj & 1
+    double* hbuf[2] = {b->h_pinned + B, b->h_pinned + 2 * B};
+    auto check = [&](int jj) {
+      bool all = true;
+      for (int i = 0; i < B; ++i) {
+        if (kk[i] >= 0) continue;
+        if (hbuf[jj & 1][i] <= tol * bn[i]) kk[i] = jj + 1;
+        else all = false;
+      }
+      return all;
+    };
+    bool all = false;
+    for (int j = 0; j < m && total + j < maxit; ++j) {
+      cd* w = V + (size_t)(j + 1) * ldv;
+      BTRY(batch_apply_hat(b, V + (size_t)j * ldv, w, wtmp));
+      for (int pass = 0; pass < 2; ++pass) {
+        seg_dots_kernel<<<b->nseg, BT, 0, s>>>(V, ldv, w, j + 1, b->nseg, b->dpart);
+        inst_dots_kernel<<<(B * (j + 1) + 255) / 256, 256, 0, s>>>(b->dd, B, j + 1, b->nseg,
+                                                                  b->dpart, b->h, ld, b->H, ld, j,
+                                                                  pass);
+        seg_update_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, ldv, w, j + 1, b->h, ld);
+      }
+      BTRY(batch_norms(b, w, b->nrm));
+      inst_givens_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->nrm, b->H, ld, b->cs, b->sn, b->g, j,
+                                                      b->hn, b->res, ld);
+      inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, w, b->hn, w);
+      BHIP(b, hipGetLastError());
+      BHIP(b, hipMemcpy2DAsync(hbuf[j & 1], sizeof(double), b->res + j, sizeof(double) * ld,
+                               sizeof(double), B, hipMemcpyDeviceToHost, s));
+      BHIP(b, hipEventRecord(b->ev[j & 1], s));
+      steps = j + 1;
+      // the host checks step j-1 while the GPU runs step j
+      if (j >= 1) {
+        BHIP(b, hipEventSynchronize(b->ev[(j - 1) & 1]));
+        if (check(j - 1)) {
+          all = true;
+          break;
+        }
+      }
+    }
+    if (!all && steps > 0) {
+      BHIP(b, hipEventSynchronize(b->ev[(steps - 1) & 1]));
+      check(steps - 1);
+    }
+    for (int i = 0; i < B; ++i)
+      if (kk[i] < 0) kk[i] = steps;
+    total += steps;
+    BHIP(b, hipMemcpyAsync(b->d_k, kk.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+    inst_backsolve_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->H, ld, b->g, b->d_k, b->y);
+    seg_axpy_basis_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, X, V, ldv, b->y, ld, b->d_k);
+    BHIP(b, hipGetLastError());
+    for (int i = 0; i < B; ++i) {
+      iters[i] += kk[i];
+      if (kk[i] > 0) cycles[i] += 1;
+    }
+  }
+  // back to beta = D^{-1} x^, scattered to the callers' vectors
+  ew_scale_kernel<<<gn, BT, 0, s>>>(X, b->d_dinv, X, b->ntot);
+  for (int i = 0; i < B; ++i) {
+    const InstDesc& q = b->hd[i];
+    BHIP(b, hipMemcpyAsync(beta[i], X + q.off, sizeof(cd) * q.nbeta, hipMemcpyDeviceToDevice, s));
+  }
+  BHIP(b, hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool conv = true;
+  for (int i = 0; i < B; ++i) {
+    if (stats) {
+      stats[i] = grt_solve_stats{};
+      stats[i].iters = iters[i];
+      stats[i].cycles = cycles[i];
+      stats[i].rel_resid = rel[i];
+      stats[i].seconds = secs;
+    }
+    if (!(rel[i] <= tol)) conv = false;
+  }
+  return conv ? GRT_OK : bset(b, GRT_ENOCONV, "some problems did not reach the tolerance");
+}
+
+}  // extern "C"

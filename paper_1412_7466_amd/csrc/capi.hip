@@ -24,12 +24,17 @@ grt_status set_err(grt_ctx* c, grt_status s, const std::string& msg) {
 namespace {
 
 void free_all(grt_ctx* c) {
+  if (c->lf) {  // layer-side buffers belong to the shared factors
+    c->d_yw = c->d_colscale = c->d_sv = c->d_htab = nullptr;
+    c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_f = nullptr;
+    c->lf.reset();
+  }
   void* bufs[] = {c->d_cx, c->d_cy, c->d_rad, c->d_kp, c->d_yw, c->d_wcorr, c->d_A,
                   c->d_colscale, c->d_sv, c->d_U, c->d_VH, c->d_W1, c->d_W2, c->d_W3,
                   c->d_mie, c->d_l2l, c->d_f, c->d_pT, c->d_pC, c->d_pB, c->d_pL,
                   c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_cs, c->d_sn, c->d_htab,
                   c->d_gv, c->d_y, c->d_scal, c->d_dotpart, c->d_res, c->d_x32, c->d_pT32,
-                  c->d_pN, c->d_noff, c->d_nlist, c->d_dnorm, c->d_dinv, c->d_xtmp};
+                  c->d_pN, c->d_noff, c->d_nlist, c->d_dnorm, c->d_dinv, c->d_xtmp, c->d_ntgt, c->d_npart};
   for (void* p : bufs)
     if (p) hipFree(p);
   c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal =
@@ -46,6 +51,8 @@ void free_all(grt_ctx* c) {
   c->n_near = 0;
   c->d_dnorm = c->d_dinv = nullptr;
   c->d_xtmp = nullptr;
+  c->d_ntgt = nullptr;
+  c->d_npart = nullptr;
   c->krylov_restart = 0;
   c->built = false;
 }

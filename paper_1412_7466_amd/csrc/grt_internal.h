@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -31,7 +32,20 @@ struct DevGeom {
   const cd* wcorr;              // zeta-correction weights [4][2K+1]: S1, T1, S2, T2
 };
 
+// Device data of the empty layered structure (wall nodes, quadrature corrections,
+// A, its SVD, the pseudo-inverse factor blocks, f) shared by every problem with the
+// same layers, discretization, omega and phi.
+struct LayerFactors {
+  int device = 0;
+  double *yw = nullptr, *colscale = nullptr, *sv = nullptr, *htab = nullptr;
+  cd *wcorr = nullptr, *A = nullptr, *U = nullptr, *VH = nullptr;
+  cd *W1 = nullptr, *W2 = nullptr, *W3 = nullptr, *f = nullptr;
+  int rank = 0;
+  ~LayerFactors();
+};
+
 struct grt_ctx {
+  std::shared_ptr<LayerFactors> lf;  // owns the layer-side buffers below when set
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -85,7 +99,9 @@ struct grt_ctx {
   cf* d_pT32 = nullptr;     // [m2l_nchunks][M][nb]
   cd* d_pN = nullptr;       // [M][nb]
   int* d_noff = nullptr;    // [M+1] CSR offsets
-  int* d_nlist = nullptr;   // [n_near]
+  int* d_nlist = nullptr;   // [n_near] source of each near pair
+  int* d_ntgt = nullptr;    // [n_near] target of each near pair
+  cd* d_npart = nullptr;    // [n_near][nb] per-pair contributions
   int64_t n_near = 0;
   // GMRES workspace
   int krylov_restart = 0;

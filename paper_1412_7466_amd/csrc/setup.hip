@@ -19,6 +19,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "dev_bessel.h"
@@ -533,7 +537,97 @@ static grt_status rocblas_err(grt_ctx* c, const char* what, int st) {
   return set_err(c, GRT_EHIP, std::string(what) + " failed with rocBLAS status " + std::to_string(st));
 }
 
+// ---------------------------------------------------------------------------
+// Sharing of the layer factors.  A, its SVD and the factor blocks depend only on
+// the layered structure, its discretization, omega and phi (not on the
+// inclusions), so problems that agree on those share one set, found through a
+// process-wide cache of weak references (freed with the last context using it).
+// ---------------------------------------------------------------------------
+LayerFactors::~LayerFactors() {
+  hipSetDevice(device);
+  void* p[] = {yw, colscale, sv, htab, wcorr, A, U, VH, W1, W2, W3, f};
+  for (void* q : p)
+    if (q) hipFree(q);
+}
+
+static std::string layer_key(const grt_ctx* c) {
+  const grt_layers& L = c->lay;
+  std::vector<double> v = {L.d, L.h, L.y0, L.n_layer[0], L.n_layer[1], L.n_layer[2], L.pinv_eps,
+                           c->inc.omega, c->inc.phi};
+  std::vector<int> iv = {c->device, L.N, L.Nw[0], L.Nw[1], L.Nw[2], L.Q[0], L.Q[1], L.Q[2], L.Nu,
+                         L.n_rb_lo, L.Nrb, L.zeta_K};
+  std::string k(reinterpret_cast<const char*>(v.data()), v.size() * sizeof(double));
+  k.append(reinterpret_cast<const char*>(iv.data()), iv.size() * sizeof(int));
+  return k;
+}
+
+static std::mutex g_cache_mu;
+static std::map<std::string, std::weak_ptr<LayerFactors>> g_cache;
+
+static void attach_factors(grt_ctx* c, const std::shared_ptr<LayerFactors>& lf) {
+  c->lf = lf;
+  c->d_yw = lf->yw;
+  c->d_colscale = lf->colscale;
+  c->d_sv = lf->sv;
+  c->d_htab = lf->htab;
+  c->d_wcorr = lf->wcorr;
+  c->d_A = lf->A;
+  c->d_U = lf->U;
+  c->d_VH = lf->VH;
+  c->d_W1 = lf->W1;
+  c->d_W2 = lf->W2;
+  c->d_W3 = lf->W3;
+  c->d_f = lf->f;
+  c->rank = lf->rank;
+  int off = 0;
+  for (int l = 0; l < 3; ++l) {
+    c->g.yw[l] = lf->yw + off;
+    off += c->g.Nw[l];
+  }
+  c->g.wcorr = lf->wcorr;
+}
+
+static grt_status build_layers(grt_ctx* c);
+static grt_status build_inclusions(grt_ctx* c);
+
 grt_status setup_build(grt_ctx* c) {
+  const std::string key = layer_key(c);
+  std::shared_ptr<LayerFactors> lf;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) lf = it->second.lock();
+  }
+  if (lf) {
+    attach_factors(c, lf);
+  } else {
+    grt_status st = build_layers(c);
+    if (st != GRT_OK) return st;
+    lf = std::make_shared<LayerFactors>();
+    lf->device = c->device;
+    lf->yw = c->d_yw;
+    lf->colscale = c->d_colscale;
+    lf->sv = c->d_sv;
+    lf->htab = c->d_htab;
+    lf->wcorr = c->d_wcorr;
+    lf->A = c->d_A;
+    lf->U = c->d_U;
+    lf->VH = c->d_VH;
+    lf->W1 = c->d_W1;
+    lf->W2 = c->d_W2;
+    lf->W3 = c->d_W3;
+    lf->f = c->d_f;
+    lf->rank = c->rank;
+    c->lf = lf;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto it = g_cache.begin(); it != g_cache.end();)
+      it = it->second.expired() ? g_cache.erase(it) : std::next(it);
+    g_cache[key] = lf;
+  }
+  return build_inclusions(c);
+}
+
+static grt_status build_layers(grt_ctx* c) {
   hipStream_t s = c->stream;
   DevGeom& g = c->g;
   const int K = g.zeta_K;
@@ -622,8 +716,17 @@ grt_status setup_build(grt_ctx* c) {
                                        c->d_W3);
     GRT_HIP(c, hipGetLastError());
   }
+  GRT_HIP(c, hipMalloc(&c->d_f, sizeof(cd) * c->n_g));
+  rhs_f_kernel<<<(c->n_g + 255) / 256, 256, 0, s>>>(g, g.k[0] * cos(c->inc.phi), c->n_g, c->d_f);
+  GRT_HIP(c, hipGetLastError());
+  GRT_HIP(c, hipStreamSynchronize(s));
+  return GRT_OK;
+}
 
-  // inclusions: Mie diagonal and L2L table
+// Per-problem part: Mie diagonal, normalisation, L2L table.
+static grt_status build_inclusions(grt_ctx* c) {
+  hipStream_t s = c->stream;
+  DevGeom& g = c->g;
   if (c->M > 0) {
     GRT_HIP(c, hipMalloc(&c->d_mie, sizeof(cd) * c->n_beta));
     mie_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, c->P, g.k[1], c->d_rad, c->d_kp,
@@ -639,9 +742,6 @@ grt_status setup_build(grt_ctx* c) {
                                                             c->d_l2l);
     GRT_HIP(c, hipGetLastError());
   }
-  GRT_HIP(c, hipMalloc(&c->d_f, sizeof(cd) * c->n_g));
-  rhs_f_kernel<<<(c->n_g + 255) / 256, 256, 0, s>>>(g, g.k[0] * cos(c->inc.phi), c->n_g, c->d_f);
-  GRT_HIP(c, hipGetLastError());
   GRT_HIP(c, hipStreamSynchronize(s));
   return GRT_OK;
 }

@@ -1,0 +1,502 @@
+// Block-level device code of the apply kernels, shared by the single-problem
+// launches (apply.hip) and the batched launches (batch.hip).  Each *_block
+// function is the body of one workgroup; its block coordinates are parameters so
+// that a batched launch can map a work item (problem, block x, block y) onto it.
+#pragma once
+#include "dev_bessel.h"
+#include "grt_internal.h"
+
+namespace grt {
+
+constexpr int M2L_WAVES = 4;     // waves per block: same 64 targets, sources split 4 ways
+constexpr int M2L_THREADS = 64 * M2L_WAVES;
+constexpr int M2L_TILE = 16;     // sources staged in LDS at a time, per wave
+constexpr int M2L_QB = 4;        // generator orders produced per block of the contraction
+
+__device__ inline __attribute__((always_inline)) void cmac(cf& acc, cf a, cf b) {
+  acc.r = fmaf(a.r, b.r, acc.r);
+  acc.r = fmaf(-a.i, b.i, acc.r);
+  acc.i = fmaf(a.r, b.i, acc.i);
+  acc.i = fmaf(a.i, b.r, acc.i);
+}
+__device__ inline cd to_acc(cd v, cd*) { return v; }
+__device__ inline cf to_acc(cd v, cf*) { return cf{(float)v.r, (float)v.i}; }
+
+// Contribution of one source inclusion (and its copies l = -1, 0, 1) to the incoming
+// coefficients acc[n] of one target, n = -P..P at index n + P:
+//   acc[n] += sum_nu tau_{nu-n} x[nu],  tau_q = sum_l alpha^l H_q(k rho_l) e^{i q phi_l},
+//   rho_l e^{i phi_l} = (dx - l d) + i dy  (Graf's theorem for each copy).
+// The generator is FP64 (H_0, H_1 from the table, upward recurrence, powers of
+// e^{i phi}) and is produced M2L_QB orders at a time; T is the accumulation type
+// (cd: FP64, cf: FP32 with FP32 accumulation).  Each x[nu] is read once per block of
+// orders and feeds up to 2 M2L_QB complex FMAs.  skip0 drops the copy l = 0 (the
+// excluded self term); dead drops everything.  With zsafe > 0 the pair is dropped
+// too when a kept copy has k rho < zsafe (left to the FP64 near-pair pass).
+template <int P, typename T, typename BP, typename TabPtr>
+__device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double dy, double k,
+                                                double d, const cd* wl, bool skip0, bool dead,
+                                                TabPtr tab, double zsafe) {
+  constexpr int NB = 2 * P + 1;
+  constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
+  cd hp[3], hc[3], cc[3], cq[3];
+  double rz2[3];
+  double zz[3];
+  bool near = false;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    double ex = dx - (l - 1) * d;
+    bool off = (skip0 && l == 1) || dead;
+    double r = sqrt(ex * ex + dy * dy);
+    if (off) r = 1.0;
+    double z = k * r;
+    zz[l] = z;
+    if (!off && z < zsafe) near = true;
+    double ir = 1.0 / r;
+    cc[l] = cd{ex * ir, dy * ir};
+    cq[l] = cc[l];
+    rz2[l] = 2.0 / z;
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    bool off = (skip0 && l == 1) || dead || near;
+    cd h0, h1;
+    hankel01_tab(zz[l], tab, h0, h1);
+    cd w = off ? cd{0.0, 0.0} : wl[l];
+    hp[l] = w * h0;
+    hc[l] = w * h1;
+  }
+  {
+    T t0 = to_acc(hp[0] + hp[1] + hp[2], (T*)nullptr);
+#pragma unroll
+    for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
+  }
+#pragma unroll
+  for (int qb = 0; qb < NQB; ++qb) {
+    T tp[M2L_QB], tm[M2L_QB];
+#pragma unroll
+    for (int u = 0; u < M2L_QB; ++u) {
+      const int q = 1 + qb * M2L_QB + u;
+      cd sp{0.0, 0.0}, sm{0.0, 0.0};
+      if (q <= 2 * P) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          double ac = hc[l].r * cq[l].r, bd = hc[l].i * cq[l].i;
+          double ad = hc[l].r * cq[l].i, bc = hc[l].i * cq[l].r;
+          sp.r += ac - bd;
+          sp.i += ad + bc;
+          sm.r += ac + bd;
+          sm.i += bc - ad;
+        }
+        if (q & 1) sm = -sm;  // H_{-q} = (-1)^q H_q
+        if (q < 2 * P) {
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            cd hn = (q * rz2[l]) * hc[l] - hp[l];
+            hp[l] = hc[l];
+            hc[l] = hn;
+            cq[l] = cq[l] * cc[l];
+          }
+        }
+      }
+      tp[u] = to_acc(sp, (T*)nullptr);
+      tm[u] = to_acc(sm, (T*)nullptr);
+    }
+    // x may be re-read here: keeps x[nu] out of registers across blocks of orders
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int nu = 0; nu < NB; ++nu) {
+      bool need = false;
+#pragma unroll
+      for (int u = 0; u < M2L_QB; ++u) {
+        const int q = 1 + qb * M2L_QB + u;
+        if (q <= 2 * P && (nu - q >= 0 || nu + q < NB)) need = true;
+      }
+      if (!need) continue;
+      const T bv = b[nu];
+#pragma unroll
+      for (int u = 0; u < M2L_QB; ++u) {
+        const int q = 1 + qb * M2L_QB + u;
+        if (q > 2 * P) continue;
+        if (nu - q >= 0) cmac(acc[nu - q], tp[u], bv);   // acc[n] += t_q x[n+q]
+        if (nu + q < NB) cmac(acc[nu + q], tm[u], bv);   // acc[n] += t_{-q} x[n-q]
+      }
+    }
+  }
+}
+
+// Translation of the outgoing coefficients of sources [m0, m1) (and of their
+// copies l = -1, 0, 1) into incoming coefficients at 64 targets (one per lane);
+// the block's four waves take a quarter of the sources each, stage them in LDS
+// (every lane then reads the same address: a broadcast) and are summed through
+// LDS at the end.  T = cd: FP64; T = cf: FP32 contraction and accumulation with
+// pairs closer than zsafe left out.
+template <int P, typename T>
+__device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
+                                                          const double* __restrict__ cy,
+                                                          const T* __restrict__ x, T* partial,
+                                                          int M, int chunk, double k, double d,
+                                                          cd alpha, cd alpha_inv,
+                                                          const double* __restrict__ htab,
+                                                          double zsafe, int bx_, int by_) {
+  constexpr int NB = 2 * P + 1;
+  constexpr int TW = sizeof(T) / sizeof(double);  // doubles per complex value (1 or 2)
+  constexpr int STAGE = M2L_WAVES * M2L_TILE * (TW * NB + 2);
+  constexpr int RED = TW * NB * 64;
+  constexpr int BUF = STAGE > RED ? STAGE : RED;
+  __shared__ double smem[BUF];
+  __shared__ double stab[HTAB_SIZE];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  T* sx = reinterpret_cast<T*>(smem) + wv * M2L_TILE * NB;
+  double* scx = smem + TW * M2L_WAVES * M2L_TILE * NB + wv * 2 * M2L_TILE;
+  double* scy = scx + M2L_TILE;
+  const int j = bx_ * 64 + lane;
+  const int m0 = by_ * chunk;
+  const int m1 = min(M, m0 + chunk);
+  const int per = (m1 - m0 + M2L_WAVES - 1) / M2L_WAVES;
+  const int s0 = m0 + wv * per;
+  const int s1 = min(m1, s0 + per);
+  const int ntile = (per + M2L_TILE - 1) / M2L_TILE;  // same for every wave: barriers match
+  for (int t = threadIdx.x; t < HTAB_SIZE; t += M2L_THREADS) stab[t] = htab[t];
+  const bool live = j < M;
+  const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
+  T acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = T{0, 0};
+  const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
+  for (int it = 0; it < ntile; ++it) {
+    const int ts = s0 + it * M2L_TILE;
+    const int cnt = max(0, min(M2L_TILE, s1 - ts));
+    __syncthreads();
+    for (int t = lane; t < cnt * NB; t += 64) sx[t] = x[(size_t)ts * NB + t];
+    for (int t = lane; t < cnt; t += 64) {
+      scx[t] = cx[ts + t];
+      scy[t] = cy[ts + t];
+    }
+    __syncthreads();
+    for (int mm = 0; mm < cnt; ++mm) {
+      const int m = ts + mm;
+      pair_accumulate<P, T>(acc, sx + mm * NB, xj - scx[mm], yj - scy[mm], k, d, wl, j == m,
+                            !live, stab, zsafe);
+    }
+  }
+  // sum the four waves' partial results through LDS: wave 3, then 2, then 1 add into
+  // the buffer in turn, wave 0 adds its own and stores
+  T* red = reinterpret_cast<T*>(smem);
+  for (int src = M2L_WAVES - 1; src >= 1; --src) {
+    __syncthreads();
+    if (wv == src) {
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        T v = acc[n];
+        if (src != M2L_WAVES - 1) {
+          T o = red[n * 64 + lane];
+          v.r += o.r;
+          v.i += o.i;
+        }
+        red[n * 64 + lane] = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (wv == 0 && live) {
+    T* out = partial + ((size_t)by_ * M + j) * NB;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      T o = red[n * 64 + lane];
+      out[n] = T{acc[n].r + o.r, acc[n].i + o.i};
+    }
+  }
+}
+
+// FP64 translation over the near pairs (the pairs the FP32 pass leaves out): one
+// lane per pair (target ntgt[e], source nlist[e]); each pair's contribution goes to
+// its own row of part, summed per target in list order by near_reduce_kernel.
+template <int P>
+__global__ void __launch_bounds__(64) m2l_near_kernel(const double* __restrict__ cx,
+                                                      const double* __restrict__ cy,
+                                                      const cd* __restrict__ x,
+                                                      const int* __restrict__ ntgt,
+                                                      const int* __restrict__ nlist, cd* part,
+                                                      int npairs, double k, double d, cd alpha,
+                                                      cd alpha_inv,
+                                                      const double* __restrict__ htab) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ double stab[HTAB_SIZE];
+  for (int t = threadIdx.x; t < HTAB_SIZE; t += 64) stab[t] = htab[t];
+  __syncthreads();
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  if (e >= npairs) return;
+  const int j = ntgt[e], m = nlist[e];
+  cd acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
+  const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
+  pair_accumulate<P, cd>(acc, x + (size_t)m * NB, cx[j] - cx[m], cy[j] - cy[m], k, d, wl, j == m,
+                         false, stab, 0.0);
+  cd* o = part + (size_t)e * NB;
+#pragma unroll
+  for (int n = 0; n < NB; ++n) o[n] = acc[n];
+}
+
+// out[j][n] = sum over the near pairs of target j (CSR order) of part[e][n]
+static __global__ void near_reduce_kernel(const int* __restrict__ noff, const cd* __restrict__ part,
+                                   int M, int NB, cd* out) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * NB) return;
+  int j = idx / NB, n = idx - j * NB;
+  cd s{0, 0};
+  for (int e = noff[j]; e < noff[j + 1]; ++e) s += part[(size_t)e * NB + n];
+  out[idx] = s;
+}
+
+constexpr int CX_TILE = 32;  // inclusions staged in LDS at a time
+
+// Field of all multipoles (and their copies) at the C targets, one per lane:
+//   target t < N: Gamma_1 node, t < 2N: Gamma_2 node (value, d/dy over 3 copies),
+//   t < 2N + Nw2: middle wall node (value, d/dx, cancelled two-term form
+//   alpha^2 Phi(L-d) - alpha^{-1} Phi(L+2d), Phi the l = 0 field).
+// With F_n = H_n(k r) e^{in theta}: value = sum x[n] F_n and, by
+// (d_x +- i d_y) F_n = -+ k F_{n+-1}, d/dx = (k/2)(A - B), d/dy = (ik/2)(A + B)
+// with A = sum x[n] F_{n-1}, B = sum x[n] F_{n+1}.
+// partial[chunk][t][0..1] = (value, derivative) over the chunk's inclusions.
+template <int P>
+__device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restrict__ cx,
+                                                const double* __restrict__ cy,
+                                                const cd* __restrict__ x, cd* partial, int chunk,
+                                                const double* __restrict__ htab, int bx_, int by_) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ cd sx[CX_TILE * NB];
+  __shared__ double scx[CX_TILE], scy[CX_TILE];
+  __shared__ double stab[HTAB_SIZE];
+  const int nt = 2 * g.N + g.Nw[1];
+  const int t = bx_ * blockDim.x + threadIdx.x;
+  const int m0 = by_ * chunk;
+  const int m1 = min(g.M, m0 + chunk);
+  for (int i = threadIdx.x; i < HTAB_SIZE; i += 64) stab[i] = htab[i];
+  const bool live = t < nt;
+  const int tt = live ? t : 0;
+  double tx[3], ty;
+  cd w[3];
+  const bool wall = tt >= 2 * g.N;
+  if (!wall) {
+    int i = tt % g.N;
+    double x0 = -0.5 * g.d + (i + 0.5) * g.hs;
+    ty = (tt < g.N) ? g.h : -g.h;
+    // copies of the source at x_m + l d are equivalent to targets at x - l d
+    tx[0] = x0 + g.d; w[0] = g.alpha_inv;  // l = -1
+    tx[1] = x0;       w[1] = cd{1.0, 0.0};
+    tx[2] = x0 - g.d; w[2] = g.alpha;      // l = +1
+  } else {
+    ty = g.yw[1][tt - 2 * g.N];
+    tx[0] = -1.5 * g.d; w[0] = g.alpha * g.alpha;
+    tx[1] = 1.5 * g.d;  w[1] = -g.alpha_inv;
+    tx[2] = 1.5 * g.d;  w[2] = cd{0.0, 0.0};  // unused
+  }
+  const int nimg = wall ? 2 : 3;
+  const double k = g.k[1];
+  cd val{0, 0}, A{0, 0}, B{0, 0};
+  for (int ts = m0; ts < m1; ts += CX_TILE) {
+    const int cnt = min(CX_TILE, m1 - ts);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt * NB; i += 64) sx[i] = x[(size_t)ts * NB + i];
+    for (int i = threadIdx.x; i < cnt; i += 64) {
+      scx[i] = cx[ts + i];
+      scy[i] = cy[ts + i];
+    }
+    __syncthreads();
+    for (int mm = 0; mm < cnt; ++mm) {
+      const cd* b = sx + mm * NB;
+#pragma unroll
+      for (int im = 0; im < 3; ++im) {
+        if (im >= nimg) break;
+        double vx = tx[im] - scx[mm], vy = ty - scy[mm];
+        double r = sqrt(vx * vx + vy * vy);
+        double z = k * r;
+        double ir = 1.0 / r;
+        cd e{vx * ir, vy * ir};
+        cd hprev, hcur;
+        hankel01_tab(z, stab, hprev, hcur);
+        cd sv{0, 0}, sa{0, 0}, sb{0, 0};
+        cmac(sv, hprev, b[P]);
+        if (P >= 1) {
+          cmac(sa, hprev, b[P + 1]);
+          cmac(sb, hprev, b[P - 1]);
+        }
+        cd ep = e;
+        double rz2 = 2.0 / z;
+#pragma unroll
+        for (int mo = 1; mo <= P + 1; ++mo) {
+          cd Fp = hcur * ep;                 // F_mo
+          cd Fm = hcur * conj(ep);           // F_{-mo} = (-1)^mo H_mo e^{-i mo theta}
+          if (mo & 1) Fm = -Fm;
+          if (mo <= P) {
+            cmac(sv, Fp, b[P + mo]);
+            cmac(sv, Fm, b[P - mo]);
+          }
+          if (mo + 1 <= P) cmac(sa, Fp, b[P + mo + 1]);
+          if (1 - mo >= -P) cmac(sa, Fm, b[P + 1 - mo]);
+          if (mo - 1 <= P) cmac(sb, Fp, b[P + mo - 1]);
+          if (-mo - 1 >= -P) cmac(sb, Fm, b[P - mo - 1]);
+          if (mo <= P) {
+            cd hn = (mo * rz2) * hcur - hprev;
+            hprev = hcur;
+            hcur = hn;
+            ep = ep * e;
+          }
+        }
+        val += w[im] * sv;
+        A += w[im] * sa;
+        B += w[im] * sb;
+      }
+    }
+  }
+  if (!live) return;
+  cd der = wall ? (0.5 * k) * (A - B) : times_i((0.5 * k) * (A + B));
+  cd* o = partial + ((size_t)by_ * nt + t) * 2;
+  o[0] = val;
+  o[1] = der;
+}
+
+// g (rows Gamma_1 v/n, Gamma_2 v/n, wall-2 v/d) from the chunk partials: one
+// wavefront per target, lanes over chunks, fixed-order tree sum.
+__device__ inline void cx_reduce_block(const DevGeom& g, const cd* partial, int nchunks,
+                                                        cd* gv, int bx_) {
+  const int nt = 2 * g.N + g.Nw[1];
+  const int t = (bx_ * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (t >= nt) return;
+  double vr = 0, vi = 0, dr = 0, di = 0;
+  for (int c = lane; c < nchunks; c += 64) {
+    cd v = partial[((size_t)c * nt + t) * 2];
+    cd dv = partial[((size_t)c * nt + t) * 2 + 1];
+    vr += v.r; vi += v.i; dr += dv.r; di += dv.i;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    vr += __shfl_xor(vr, off, 64);
+    vi += __shfl_xor(vi, off, 64);
+    dr += __shfl_xor(dr, off, 64);
+    di += __shfl_xor(di, off, 64);
+  }
+  if (lane != 0) return;
+  cd v{vr, vi}, dv{dr, di};
+  const int N = g.N;
+  if (t < N) {  // Gamma_1: row is u_1 - u_2, the inclusions live in layer 2
+    gv[g.row_off[RB_G1V] + t] = -v;
+    gv[g.row_off[RB_G1N] + t] = -dv;
+  } else if (t < 2 * N) {
+    gv[g.row_off[RB_G2V] + t - N] = v;
+    gv[g.row_off[RB_G2N] + t - N] = dv;
+  } else {
+    gv[g.row_off[RB_W2V] + t - 2 * N] = v;
+    gv[g.row_off[RB_W2D] + t - 2 * N] = dv;
+  }
+}
+
+// Incoming coefficients at inclusion j from the interface densities (P2L, Graf's
+// theorem for H_0 about c_j):
+//   alpha_j[n] += (i/4) hs alpha^l [G_n sigma - (ik/2)(G_{n-1} + G_{n+1}) mu],
+//   G_n = H_n(k|v|) e^{-in theta_v}, v = node copy - c_j,
+// the mu term being d/dy of the sigma term (gradient identity).  Sources: 2 lines x
+// N nodes x 3 copies = 6N node-copies, chunked over blockIdx.y.  Each G_m is used
+// as soon as it is generated: it feeds acc[m] (sigma) and acc[m -+ 1] (mu).
+template <int P>
+__device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restrict__ cx,
+                                                const double* __restrict__ cy,
+                                                const cd* __restrict__ w, cd* partial, int chunk,
+                                                const double* __restrict__ htab, int bx_, int by_) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ double stab[HTAB_SIZE];
+  for (int i = threadIdx.x; i < HTAB_SIZE; i += 64) stab[i] = htab[i];
+  __syncthreads();
+  const int j = bx_ * blockDim.x + threadIdx.x;
+  const int s0 = by_ * chunk;
+  const int s1 = min(6 * g.N, s0 + chunk);
+  const bool live = j < g.M;
+  const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
+  const double k = g.k[1];
+  cd acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
+  for (int sidx = s0; sidx < s1; ++sidx) {
+    const int line = sidx / (3 * g.N);
+    const int rem = sidx - line * 3 * g.N;
+    const int l = rem / g.N - 1;
+    const int i = rem - (l + 1) * g.N;
+    const double sxp = -0.5 * g.d + (i + 0.5) * g.hs + l * g.d;
+    const double syp = line == 0 ? g.h : -g.h;
+    const cd mu = w[g.col_off[line == 0 ? CB_MU1 : CB_MU2] + i];
+    const cd sg = w[g.col_off[line == 0 ? CB_SIG1 : CB_SIG2] + i];
+    const cd ph = (l == 0) ? cd{1.0, 0.0} : (l > 0 ? g.alpha : g.alpha_inv);
+    const cd pre = times_i((0.25 * g.hs) * ph);        // (i/4) hs alpha^l
+    const cd csig = pre * sg;
+    const cd cmu = pre * times_i((-0.5 * k) * mu);     // -(ik/2) mu (i/4) hs alpha^l
+    const double vx = sxp - xj, vy = syp - yj;
+    const double r = sqrt(vx * vx + vy * vy);
+    const double z = k * r;
+    const double ir = 1.0 / r;
+    const cd e{vx * ir, vy * ir};
+    const cd ec = conj(e);
+    cd hprev, hcur;
+    hankel01_tab(z, stab, hprev, hcur);
+    // order 0: G_0 = H_0 -> acc[0] (sigma), acc[+-1] (mu)
+    cmac(acc[P], csig, hprev);
+    if (P >= 1) {
+      cmac(acc[P + 1], cmu, hprev);
+      cmac(acc[P - 1], cmu, hprev);
+    }
+    cd ep = ec, em = e;
+    const double rz2 = 2.0 / z;
+#pragma unroll
+    for (int m = 1; m <= P + 1; ++m) {
+      const cd Gp = hcur * ep;                                  // G_m = H_m e^{-im theta}
+      const cd Gm = (m & 1) ? -(hcur * em) : hcur * em;        // G_{-m} = (-1)^m H_m e^{im theta}
+      if (m <= P) {
+        cmac(acc[P + m], csig, Gp);
+        cmac(acc[P - m], csig, Gm);
+      }
+      // G_m feeds acc[m - 1] and acc[m + 1]; G_{-m} feeds acc[-m + 1] and acc[-m - 1]
+      if (m - 1 <= P) cmac(acc[P + m - 1], cmu, Gp);
+      if (m + 1 <= P) cmac(acc[P + m + 1], cmu, Gp);
+      if (1 - m >= -P) cmac(acc[P + 1 - m], cmu, Gm);
+      if (-m - 1 >= -P) cmac(acc[P - m - 1], cmu, Gm);
+      if (m <= P) {
+        const cd hn = (m * rz2) * hcur - hprev;
+        hprev = hcur;
+        hcur = hn;
+        ep = ep * ec;
+        em = em * e;
+      }
+    }
+  }
+  if (live) {
+    cd* out = partial + ((size_t)by_ * g.M + j) * NB;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) out[n] = acc[n];
+  }
+}
+
+// L2L: out[j][n] = sum_q a2_q E_j[q - n], E_j[m] = J_m(k2 rho_j) e^{i m phi_j}.
+// One block per inclusion: its E_j row and a2 are staged in LDS.
+__device__ inline void l2l_block(int M, int P, int Q2, const cd* __restrict__ E,
+                                                 const cd* __restrict__ a2, cd* out, int bx_) {
+  extern __shared__ cd l2l_smem[];
+  const int j = bx_;
+  const int NB = 2 * P + 1;
+  const int L = Q2 + P;
+  cd* se = l2l_smem;               // 2L + 1
+  cd* sa = l2l_smem + 2 * L + 1;   // 2 Q2 + 1
+  const cd* e = E + (size_t)j * (2 * L + 1);
+  for (int i = threadIdx.x; i < 2 * L + 1; i += blockDim.x) se[i] = e[i];
+  for (int i = threadIdx.x; i < 2 * Q2 + 1; i += blockDim.x) sa[i] = a2[i];
+  __syncthreads();
+  for (int nn = threadIdx.x; nn < NB; nn += blockDim.x) {
+    const int n = nn - P;
+    cd acc{0, 0};
+    for (int q = -Q2; q <= Q2; ++q) cmac(acc, sa[q + Q2], se[L + q - n]);
+    out[(size_t)j * NB + nn] = acc;
+  }
+}
+
+
+}  // namespace grt

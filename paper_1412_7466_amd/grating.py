@@ -76,6 +76,11 @@ _PROTOS = {
     "grt_get_mie": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "grt_profile_enable": (C.c_int, [_VP, C.c_int]),
     "grt_profile_read": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "grt_batch_create": (C.c_int, [C.POINTER(_VP), C.c_int64, C.POINTER(_VP), _VP]),
+    "grt_batch_destroy": (C.c_int, [_VP]),
+    "grt_batch_error_message": (C.c_char_p, [_VP]),
+    "grt_batch_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), C.POINTER(_VP),
+                                  C.POINTER(grt_solve_stats)]),
 }
 
 _lib = None
@@ -264,6 +269,58 @@ class Context:
         s = np.zeros(2 * self.sizes.n_beta)
         self._check(self.lib.grt_get_mie(self.h, _dptr(s)))
         return s[0::2] + 1j * s[1::2]
+
+
+class Batch:
+    """Lockstep FP64 solves of several built contexts on one GPU (grt_batch_*).
+
+    The contexts must stay alive and untouched while the batch exists."""
+
+    def __init__(self, contexts):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.ctxs = list(contexts)
+        if not self.ctxs:
+            raise ValueError("empty batch")
+        self.device = self.ctxs[0].device
+        self.stream = torch.cuda.Stream(device=self.device)
+        arr = (_VP * len(self.ctxs))(*[c.h for c in self.ctxs])
+        h = _VP()
+        st = self.lib.grt_batch_create(C.byref(h), len(self.ctxs), arr,
+                                       _VP(self.stream.cuda_stream))
+        if st != GRT_OK:
+            raise GratingError(st, "grt_batch_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.grt_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, check=True):
+        """Returns (list of beta vectors, list of grt_solve_stats)."""
+        betas = [c.new_vec() for c in self.ctxs]
+        if x0 is not None:
+            for b, x in zip(betas, x0):
+                b.copy_(x)
+        ptrs = (_VP * len(betas))(*[c._vec_ptr(b) for c, b in zip(self.ctxs, betas)])
+        opts = grt_solve_opts(tol=tol, maxit=maxit, restart=restart, use_x0=int(x0 is not None),
+                              precision=GRT_FP64, inner_tol=0.0, max_refine=0)
+        stats = (grt_solve_stats * len(betas))()
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        st = self.lib.grt_batch_solve(self.h, C.byref(opts), ptrs, stats)
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        if st != GRT_OK and (check or st != GRT_ENOCONV):
+            msg = self.lib.grt_batch_error_message(self.h)
+            raise GratingError(st, msg.decode() if msg else "")
+        return betas, list(stats)
 
 
 def exported_symbols():

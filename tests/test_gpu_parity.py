@@ -168,3 +168,82 @@ def test_mixed_precision_refinement(torch_cuda, M, P, seed):
         f"resid={st.rel_resid:.2e}")
     assert st.rel_resid <= 1e-12
     assert rel(_np(beta), beta_o) < 1e-9
+
+
+def _batch_problems():
+    return [inputs.tiny_m4(),
+            inputs.small(12, 4, seed=21),
+            inputs.small(30, 10, seed=22, phi=0.3),
+            inputs.small(5, 15, omega=12.0, seed=23),
+            inputs.small(67, 6, seed=24, phi=WOOD),
+            inputs.small(20, 10, seed=25)]
+
+
+def test_batched_solve_matches_single_and_oracle(torch_cuda):
+    """Lockstep batched GMRES over problems of different M, P, angle and omega
+    reaches each problem's own solution (oracle LU and the single solver)."""
+    from oracle.solver import Reduced
+    from paper_1412_7466_amd.grating import Batch
+    pbs = _batch_problems()
+    ctxs = [_ctx(pb) for pb in pbs]
+    singles = []
+    for pb, ctx in zip(pbs, ctxs):
+        beta, st = ctx.solve(tol=1e-12, restart=150)
+        singles.append((_np(beta), st.iters))
+    say("[gpu] batch create", len(ctxs))
+    batch = Batch(ctxs)
+    betas, stats = batch.solve(tol=1e-12, restart=150)
+    for pb, ctx, b, st, (bs, its) in zip(pbs, ctxs, betas, stats, singles):
+        red = Reduced(pb)
+        beta_o = red.solve_lu()
+        say(f"[gpu] batch {pb.name} iters={st.iters} (single {its}) resid={st.rel_resid:.2e}")
+        assert st.rel_resid <= 1e-12
+        assert rel(_np(b), beta_o) < 1e-9
+        assert rel(_np(b), bs) < 1e-9
+    # warm start from the solution: converged on entry
+    betas2, stats2 = batch.solve(tol=1e-12, restart=150, x0=betas)
+    assert all(s.iters == 0 for s in stats2)
+    for b2, b in zip(betas2, betas):
+        assert rel(_np(b2), _np(b)) < 1e-15  # x -> D x -> D^{-1} x rounding only
+    batch.close()
+
+
+def test_batched_rejects_bad_input(torch_cuda):
+    from paper_1412_7466_amd.grating import (Batch, Context, GratingError, GRT_ESTATE,
+                                             GRT_EUNSUP, grt_solve_opts, grt_solve_stats,
+                                             _VP)
+    import ctypes as C
+    empty = _ctx(inputs.empty_slab())
+    with pytest.raises(GratingError) as ei:
+        Batch([empty])
+    assert ei.value.status == GRT_ESTATE
+    unbuilt = Context(0)
+    unbuilt.set_problem(inputs.small(3, 2, seed=5))
+    with pytest.raises(GratingError) as ei:
+        Batch([unbuilt])
+    assert ei.value.status == GRT_ESTATE
+    ctx = _ctx(inputs.small(3, 2, seed=5))
+    batch = Batch([ctx])
+    beta = ctx.new_vec()
+    opts = grt_solve_opts(tol=1e-9, maxit=10, restart=10, use_x0=0, precision=1,
+                          inner_tol=1e-5, max_refine=1)
+    ptrs = (_VP * 1)(_VP(beta.data_ptr()))
+    st = batch.lib.grt_batch_solve(batch.h, C.byref(opts), ptrs, (grt_solve_stats * 1)())
+    assert st == GRT_EUNSUP
+
+
+def test_layer_factors_shared_between_contexts(torch_cuda):
+    """Problems with the same layers, omega and phi share one set of layer factors;
+    the survivor keeps working after the first owner is destroyed."""
+    from oracle.solver import Reduced
+    pa = inputs.small(10, 6, seed=31)
+    pb = inputs.small(14, 6, seed=32)
+    pb.disc = pa.disc  # same discretization of the layers
+    ca = _ctx(pa)
+    cb = _ctx(pb)
+    A1, _ = ca.get_A()
+    A2, _ = cb.get_A()
+    assert np.array_equal(A1, A2)
+    ca.close()
+    beta, st = cb.solve(tol=1e-12, restart=150)
+    assert rel(_np(beta), Reduced(pb).solve_lu()) < 1e-9
