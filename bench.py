@@ -58,7 +58,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); "
-              "the multi-GPU design is described in DESIGN.md and is not built", file=sys.stderr)
+              "a sharded solve across GPUs is not built", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1412_7466_amd import inputs

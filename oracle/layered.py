@@ -11,7 +11,7 @@ walls of every layer (eq. bound2) and matching to Rayleigh-Bloch expansions on
 Gamma_u, Gamma_d (eq. bound3).  Stacking these rows gives the rectangular
 matrix A of eq. matA with right-hand side f of eq. Arhs.
 
-Readings taken here (listed in the design doc):
+Readings taken here, where the paper is silent or ambiguous:
   * flat interfaces Gamma_1: y = h, Gamma_2: y = -h, normals +y; jump relations
     (S sigma)_n^{+-} = (-+1/2 + N) sigma, (D mu)^{+-} = (+-1/2 + D) mu, "+" above;
   * value rows of an interface are [I + D_diff, S_diff] on (mu, sigma) and normal

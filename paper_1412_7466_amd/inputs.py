@@ -16,7 +16,7 @@ normal (so the horizontal wavenumber is k_1 sin(phi)), multipole order P.
 Discretization sizes follow the paper's description of its discretization
 (section 3: equispaced interface nodes, Gauss-Legendre wall nodes, J expansions of
 2Q+1 terms, Rayleigh-Bloch modes, artificial lines at +-y0) with the concrete
-rules documented in the design doc.
+rules of derive_discretization below, where the paper gives no numbers.
 """
 from __future__ import annotations
 
