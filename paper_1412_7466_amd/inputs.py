@@ -262,3 +262,71 @@ def empty_slab(omega=10.0, phi=-math.pi / 5, d=1.0, h=0.5, n_layer=STACK, **kw) 
     return Problem(d=d, h=h, n_layer=tuple(n_layer), omega=omega, phi=phi, P=10,
                    x=e, y=e.copy(), radius=e.copy(), n_incl=e.copy(), disc=disc,
                    name="empty")
+
+
+# ----------------------------------------------------------------------------
+# learned warm start: geometry sets, initial weights, synthetic targets
+# ----------------------------------------------------------------------------
+
+WARM_OMEGAS = (20.0,)
+WARM_PHIS = (-math.pi / 5, -math.pi / 12, math.pi / 12, math.pi / 5)
+
+
+def warm_problem(i: int, held_out: bool = False, M_range=(200, 2000), P: int = 15,
+                 omegas=WARM_OMEGAS, phis=WARM_PHIS) -> Problem:
+    """Geometry i of the warm-start training set (seed 50000+i) or of the held-out
+    set (seed 90000+i): the M=1000 workload's rules (d=1, middle layer y in
+    [-1, 1], radii U[0.004, 0.012], indices U[1.5, 3.0], gap 0.002, P=15) with M a
+    seeded uniform integer in M_range and (omega, phi) taken in turn from a small
+    grid.  All problems with the same (omega, phi) get the same discretization
+    (interface nodes from the closest position the packing allows), so they share
+    one factorization of the layered structure."""
+    seed = (90000 if held_out else 50000) + i
+    rng = np.random.Generator(np.random.PCG64(seed + 7_000_000))
+    M = int(rng.integers(M_range[0], M_range[1] + 1))
+    omega = float(omegas[i % len(omegas)])
+    phi = float(phis[(i // len(omegas)) % len(phis)])
+    d, h, r_lo, gap = 1.0, 1.0, 0.004, 0.002
+    x, y, r, n = pack_disks(M, d, h, r_lo, 0.012, 1.5, 3.0, gap, seed)
+    closest = h - (max(gap, 0.02) + r_lo)
+    disc = derive_discretization(d, h, STACK, omega, phi, np.array([closest]), P)
+    return Problem(d=d, h=h, n_layer=STACK, omega=omega, phi=phi, P=P, x=x, y=y, radius=r,
+                   n_incl=n, disc=disc, name=f"warm{'H' if held_out else 'T'}{i}_M{M}",
+                   seed=seed)
+
+
+def nn_shapes(H: int, L: int, p_out: int, F: int = 32, E: int = 8):
+    """Shapes of the warm-start network's weights, in the order of its flat
+    parameter vector (matrices row-major [rows][cols])."""
+    O = 2 * (2 * p_out + 1)
+    s = [(H, F), (H,)]
+    for _ in range(L):
+        s += [(H, H), (H, H), (H, E), (H,), (H, 2 * H), (H,)]
+    s += [(O, H), (O,)]
+    return s
+
+
+def nn_init(H: int, L: int, p_out: int, seed: int = 0, out_scale: float = 0.1):
+    """Seeded initial weights (float32): uniform in +-sqrt(6 / fan_in) for
+    matrices (scaled by out_scale for the output layer), zero biases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = nn_shapes(H, L, p_out)
+    parts = []
+    for i, s in enumerate(shapes):
+        if len(s) == 1:
+            parts.append(np.zeros(s))
+        else:
+            a = math.sqrt(6.0 / s[1]) * (out_scale if i == len(shapes) - 2 else 1.0)
+            parts.append(rng.uniform(-a, a, size=s))
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+
+
+def nn_synthetic_target(M: int, p_out: int, seed: int = 0):
+    """Seeded target t, positive weights w ([M][2(2 p_out + 1)] float32) and a
+    normaliser, for checks of the loss and its gradient."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    O = 2 * (2 * p_out + 1)
+    t = rng.standard_normal((M, O)).astype(np.float32)
+    w = rng.uniform(0.1, 1.0, size=(M, O)).astype(np.float32)
+    w[:, 1::2] = w[:, 0::2]
+    return t, w, float(M * O)
