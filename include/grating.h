@@ -105,6 +105,8 @@ typedef struct {
   double rel_resid;     /* true relative residual ||b - K x|| / ||b|| (FP64)  */
   double seconds;       /* wall time of the solve                            */
   int refine_steps;     /* GRT_FP32: FP64 refinement steps taken             */
+  int x0_rejected;      /* use_x0 and ||b - K x0|| >= ||b||: the guess was
+                           dropped and the solve started from x = 0          */
 } grt_solve_stats;
 
 typedef struct {
@@ -152,6 +154,10 @@ grt_status grt_apply_lowrank(grt_ctx* ctx, const void* x_dev, void* y_dev);
 
 /* b = S B_phys A^+ f, the right-hand side of the reduced system (device). */
 grt_status grt_rhs(grt_ctx* ctx, void* b_dev);
+
+/* alpha0 = B_phys A^+ f (device, n_beta complex): the incoming coefficients that
+ * the layered structure alone sends to each inclusion (sec. 5), so that b = S alpha0. */
+grt_status grt_incident(grt_ctx* ctx, void* a_dev);
 
 /* Solve K beta = b by restarted GMRES in FP64 on the device (sec. 5).  beta_dev
  * (device) receives the solution; with opts->use_x0 it holds the initial guess
@@ -207,6 +213,80 @@ const char* grt_batch_error_message(const grt_batch* batch);
  * the lockstep steps of the whole batch.  GRT_ENOCONV if any problem missed tol. */
 grt_status grt_batch_solve(grt_batch* batch, const grt_solve_opts* opts, void* const* beta,
                            grt_solve_stats* stats);
+
+/* ---- Learned warm start ------------------------------------------------------
+ * A message-passing network over each inclusion's k nearest neighbours (minimum
+ * image in x, period d; ties by index) predicts the multiple-scattering part of the
+ * incoming coefficients on orders |n| <= p_out; the GMRES initial guess is
+ *   beta0_j[n] = s_j[n] (alpha0_j[n] + out_j[n])   (alpha0 from grt_incident, s the
+ * Mie diagonal; out = 0 for |n| > p_out),
+ * i.e. the exact relation beta = S alpha of sec. 5 with the incoming field alpha
+ * predicted.  grt_solve with use_x0 drops a guess no better than zero
+ * (stats.x0_rejected), so the plain solve stays the fallback and the judge of the
+ * result.
+ *
+ * Network, width H, L layers, node inputs f_j (32), edge inputs e_jk (8):
+ *   h = relu(W_in f + b_in);  per layer: P = A h, Q = B h,
+ *   agg_j = mean_k relu(P_j + Q_nbr(j,k) + C e_jk + c),  h <- h + relu(U [h; agg] + u);
+ *   out = W_out h + b_out   (out_j: (re, im) for n = -p_out .. p_out).
+ * Node inputs: k2 r, n/n2 - 1, y/h, sin phi, omega/40, (D s)_n for n = 0,1,2 and
+ * alpha0_n for n = -3..3 as (re, im) pairs (D = |H_|n|(k2 r)|), zero padding.
+ * Edge inputs for c_j - c_m = rho e^{i phi}, z = k2 rho:
+ *   k2 dx, k2 dy, z, 1/z, H0(z) (re, im), H1(z) e^{i phi} (re, im).
+ * Flat FP32 parameter vector, row-major matrices: W_in [H][32], b_in [H]; per layer
+ * A [H][H], B [H][H], C [H][8], c [H], U [H][2H], u [H]; W_out [O][H], b_out [O]
+ * with O = 2 (2 p_out + 1).  The forward and backward passes use the weights
+ * rounded to bfloat16 (nearest, ties to even) with FP32 activations and
+ * accumulation; Adam updates the FP32 master copy.
+ * Loss of one geometry: sum w (out - t)^2 / wnorm with t the exact correction
+ * T beta - B_phys A^+ C beta of a solved geometry, w = (D |s|)^2 and
+ * wnorm = sum w |alpha0 + t|^2 over the predicted orders. */
+typedef struct grt_nn grt_nn;
+typedef struct {
+  int width;   /* H: multiple of 64 in [64, 256]                            */
+  int layers;  /* L: 1..8                                                   */
+  int k;       /* neighbours per inclusion: 1..32                           */
+  int p_out;   /* predicted orders |n| <= p_out: 0..20                      */
+} grt_nn_config;
+
+/* Create a network (all weights 0 until grt_nn_set_params) on a device and stream
+ * (NULL: private stream).  GRT_EINVAL for a configuration outside the ranges. */
+grt_status grt_nn_create(grt_nn** out, int hip_device, void* hip_stream, const grt_nn_config* cfg);
+grt_status grt_nn_destroy(grt_nn* nn);
+const char* grt_nn_error_message(const grt_nn* nn);
+grt_status grt_nn_num_params(const grt_nn* nn, int64_t* n);
+/* Copy count FP32 weights in (resets the Adam state) or out (host arrays). */
+grt_status grt_nn_set_params(grt_nn* nn, const float* host, int64_t count);
+grt_status grt_nn_get_params(grt_nn* nn, float* host, int64_t count);
+
+/* Build the graph and inputs of a built context (M >= 1) and keep them on the
+ * device as a sample; with beta_dev (its solution, device) also the training target.
+ * The context may be destroyed afterwards.  *id receives the sample's index. */
+grt_status grt_nn_add_sample(grt_nn* nn, grt_ctx* ctx, const void* beta_dev, int* id);
+grt_status grt_nn_clear_samples(grt_nn* nn);
+grt_status grt_nn_sample_size(grt_nn* nn, int id, int64_t* M);
+/* Copy a sample's inputs and target to host arrays (any may be NULL):
+ * feat [M][32], nbr [M][k] (-1 = none), edge [M][k][8], target and weight [M][O]. */
+grt_status grt_nn_get_sample(grt_nn* nn, int id, float* feat, int* nbr, float* edge,
+                             float* target, float* weight, double* wnorm);
+/* Replace a sample's target, weights (host [M][O]) and normaliser (> 0). */
+grt_status grt_nn_set_target(grt_nn* nn, int id, const float* target, const float* weight,
+                             double wnorm);
+
+/* Loss of one sample with the current weights; grad_host (num_params floats) and
+ * out_host ([M][O]) receive the gradient and the outputs when not NULL. */
+grt_status grt_nn_loss_grad(grt_nn* nn, int id, double* loss, float* grad_host, float* out_host);
+
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) over the given samples,
+ * one step per sample, in an order reshuffled every epoch from seed.
+ * last_epoch_loss: mean loss over the last epoch (losses before each step). */
+grt_status grt_nn_train(grt_nn* nn, int64_t n_ids, const int* ids, int epochs, float lr,
+                        uint64_t seed, double* last_epoch_loss);
+
+/* beta0 (device, n_beta complex) for a built context: graph, inputs and forward
+ * pass on the device, then beta0 = s (alpha0 + out).  Pass it to grt_solve with
+ * opts.use_x0 = 1. */
+grt_status grt_nn_predict(grt_nn* nn, grt_ctx* ctx, void* beta0_dev);
 
 #ifdef __cplusplus
 }

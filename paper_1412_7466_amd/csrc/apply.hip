@@ -377,6 +377,19 @@ grt_status rhs_b(grt_ctx* c, cd* b) {
   return GRT_OK;
 }
 
+// alpha0 = B_phys A^+ f: the incoming coefficients the layered structure alone sends
+// to every inclusion (the right-hand side before the Mie diagonal).
+grt_status incident_alpha(grt_ctx* c, cd* out) {
+  if (c->M == 0) return GRT_OK;
+  grt_status st = lowrank_tail(c, c->d_f);
+  if (st != GRT_OK) return st;
+  int n = (int)c->n_beta;
+  combine_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(n, nullptr, c->d_mie, nullptr, 0, c->d_pB,
+                                                         c->b_nchunks, c->d_pL, out, 2);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
+
 __global__ void sub_kernel(int n, const cd* a, const cd* b, cd* o) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = a[i] - (b ? b[i] : cd{0, 0});

@@ -308,6 +308,14 @@ grt_status grt_rhs(grt_ctx* c, void* b) {
   return rhs_b(c, static_cast<cd*>(b));
 }
 
+grt_status grt_incident(grt_ctx* c, void* a) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (!a) return set_err(c, GRT_EINVAL, "null vector");
+  return incident_alpha(c, static_cast<cd*>(a));
+}
+
 grt_status grt_solve(grt_ctx* c, const grt_solve_opts* o, void* beta, grt_solve_stats* stats) {
   GRT_CHECK_CTX(c);
   grt_status st = check_built(c);

@@ -145,6 +145,7 @@ grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y);
 grt_status apply_T_only(grt_ctx* c, const cd* x, cd* y);
 grt_status apply_lowrank_only(grt_ctx* c, const cd* x, cd* y);
 grt_status rhs_b(grt_ctx* c, cd* b);
+grt_status incident_alpha(grt_ctx* c, cd* out);
 grt_status lowrank_from_g(grt_ctx* c, cd* pB_out_sum_into, bool mult_s, const cd* x, cd* y);
 grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out_cd /* device [2 Nrb] */);
 grt_status apply_alloc(grt_ctx* c);

@@ -243,12 +243,13 @@ struct CoreResult {
   int iters = 0, cycles = 0;
   double rel = 1.0;
   bool converged = false;
+  bool x0_rejected = false;
 };
 
 // Restarted GMRES for op(x) = b from the iterate in x (updated in place).  b must not
 // live in basis slots 0..m.  Stops at ||b - op x|| <= tol ||b|| or after maxit steps.
 static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double tol, int maxit,
-                             int m, CoreResult* res) {
+                             int m, CoreResult* res, bool guard_x0 = false) {
   const int n = (int)c->n_beta;
   hipStream_t s = c->stream;
   const size_t ldv = (size_t)n;
@@ -280,6 +281,12 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
     double beta = 0.0;
     GRT_TRY(read_scalar(c, d_beta, &beta));
     res->rel = beta / bn;
+    if (guard_x0 && res->cycles == 0 && !res->x0_rejected && res->rel >= 1.0) {
+      // an initial guess no better than zero is dropped: restart from x = 0
+      GRT_HIP(c, hipMemsetAsync(x, 0, sizeof(cd) * n, s));
+      res->x0_rejected = true;
+      continue;
+    }
     if (res->rel <= tol) { res->converged = true; break; }
     if (total >= maxit) break;
     scale_kernel<<<gridn, KT, 0, s>>>(V, V, n, d_beta);
@@ -350,7 +357,8 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
   *st = grt_solve_stats{};
   CoreResult r;
   if (o->precision == GRT_FP64) {
-    GRT_TRY(gmres_core(c, apply_K_hat, bvec, x, tol, maxit, m, &r));
+    GRT_TRY(gmres_core(c, apply_K_hat, bvec, x, tol, maxit, m, &r, o->use_x0 != 0));
+    st->x0_rejected = r.x0_rejected ? 1 : 0;
     st->iters = r.iters;
     st->cycles = r.cycles;
     st->rel_resid = r.rel;
@@ -375,6 +383,13 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
       double rn = 0.0;
       GRT_TRY(read_scalar(c, d_rn, &rn));
       rel = bn > 0 ? rn / bn : 0.0;
+      if (outer == 0 && o->use_x0 && rel >= 1.0) {
+        // an initial guess no better than zero is dropped
+        GRT_HIP(c, hipMemsetAsync(x, 0, sizeof(cd) * n, s));
+        st->x0_rejected = 1;
+        GRT_HIP(c, hipMemcpyAsync(rvec, bvec, sizeof(cd) * n, hipMemcpyDeviceToDevice, s));
+        rel = 1.0;
+      }
       st->refine_steps = outer;
       if (rel <= tol) { conv = true; break; }
       if (outer == max_ref || total >= maxit) break;

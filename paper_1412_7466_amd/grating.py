@@ -46,12 +46,16 @@ class grt_solve_opts(C.Structure):
 
 class grt_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("rel_resid", C.c_double),
-                ("seconds", C.c_double), ("refine_steps", C.c_int)]
+                ("seconds", C.c_double), ("refine_steps", C.c_int), ("x0_rejected", C.c_int)]
 
 
 class grt_sizes(C.Structure):
     _fields_ = [("M", C.c_int64), ("P", C.c_int), ("n_beta", C.c_int64), ("n_rows", C.c_int64),
                 ("n_alpha", C.c_int64), ("rank", C.c_int64), ("Nrb", C.c_int)]
+
+
+class grt_nn_config(C.Structure):
+    _fields_ = [("width", C.c_int), ("layers", C.c_int), ("k", C.c_int), ("p_out", C.c_int)]
 
 
 # name -> (restype, argtypes); mirrors include/grating.h
@@ -68,6 +72,7 @@ _PROTOS = {
     "grt_apply_T": (C.c_int, [_VP, _VP, _VP]),
     "grt_apply_lowrank": (C.c_int, [_VP, _VP, _VP]),
     "grt_rhs": (C.c_int, [_VP, _VP]),
+    "grt_incident": (C.c_int, [_VP, _VP]),
     "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
     "grt_bragg": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -81,6 +86,25 @@ _PROTOS = {
     "grt_batch_error_message": (C.c_char_p, [_VP]),
     "grt_batch_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), C.POINTER(_VP),
                                   C.POINTER(grt_solve_stats)]),
+    "grt_nn_create": (C.c_int, [C.POINTER(_VP), C.c_int, _VP, C.POINTER(grt_nn_config)]),
+    "grt_nn_destroy": (C.c_int, [_VP]),
+    "grt_nn_error_message": (C.c_char_p, [_VP]),
+    "grt_nn_num_params": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "grt_nn_set_params": (C.c_int, [_VP, C.POINTER(C.c_float), C.c_int64]),
+    "grt_nn_get_params": (C.c_int, [_VP, C.POINTER(C.c_float), C.c_int64]),
+    "grt_nn_add_sample": (C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_int)]),
+    "grt_nn_clear_samples": (C.c_int, [_VP]),
+    "grt_nn_sample_size": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int64)]),
+    "grt_nn_get_sample": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                    C.POINTER(C.c_float), C.POINTER(C.c_double)]),
+    "grt_nn_set_target": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                    C.c_double]),
+    "grt_nn_loss_grad": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float),
+                                   C.POINTER(C.c_float)]),
+    "grt_nn_train": (C.c_int, [_VP, C.c_int64, C.POINTER(C.c_int), C.c_int, C.c_float,
+                               C.c_uint64, C.POINTER(C.c_double)]),
+    "grt_nn_predict": (C.c_int, [_VP, _VP, _VP]),
 }
 
 _lib = None
@@ -216,6 +240,14 @@ class Context:
         self._leave()
         return b
 
+    def incident(self, a=None):
+        """alpha0 = B_phys A^+ f (the layers' incoming coefficients at each inclusion)."""
+        a = self.new_vec() if a is None else a
+        self._enter()
+        self._check(self.lib.grt_incident(self.h, self._vec_ptr(a)))
+        self._leave()
+        return a
+
     def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, out=None, check=True,
               precision=GRT_FP64, inner_tol=1e-5, max_refine=10):
         beta = self.new_vec() if out is None else out
@@ -321,6 +353,108 @@ class Batch:
             msg = self.lib.grt_batch_error_message(self.h)
             raise GratingError(st, msg.decode() if msg else "")
         return betas, list(stats)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Network:
+    """The learned warm start (grt_nn_*): a message-passing network on one GPU."""
+
+    def __init__(self, width=128, layers=3, k=16, p_out=3, device=0):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = device
+        self.width, self.layers, self.k, self.p_out = width, layers, k, p_out
+        self.O = 2 * (2 * p_out + 1)
+        self.stream = torch.cuda.Stream(device=device)
+        cfg = grt_nn_config(width=width, layers=layers, k=k, p_out=p_out)
+        h = _VP()
+        st = self.lib.grt_nn_create(C.byref(h), device, _VP(self.stream.cuda_stream), C.byref(cfg))
+        if st != GRT_OK:
+            raise GratingError(st, "grt_nn_create failed")
+        self.h = h
+        n = C.c_int64(0)
+        self._check(self.lib.grt_nn_num_params(self.h, C.byref(n)))
+        self.n_params = n.value
+
+    def _check(self, st):
+        if st != GRT_OK:
+            msg = self.lib.grt_nn_error_message(self.h)
+            raise GratingError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.grt_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        self._check(self.lib.grt_nn_set_params(self.h, _fptr(a), a.size))
+
+    def get_params(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.lib.grt_nn_get_params(self.h, _fptr(a), a.size))
+        return a
+
+    def add_sample(self, ctx, beta=None):
+        i = C.c_int(0)
+        ctx.torch.cuda.synchronize(self.device)
+        bp = ctx._vec_ptr(beta) if beta is not None else _VP(0)
+        self._check(self.lib.grt_nn_add_sample(self.h, ctx.h, bp, C.byref(i)))
+        return i.value
+
+    def clear_samples(self):
+        self._check(self.lib.grt_nn_clear_samples(self.h))
+
+    def sample(self, i):
+        M = C.c_int64(0)
+        self._check(self.lib.grt_nn_sample_size(self.h, i, C.byref(M)))
+        M = M.value
+        feat = np.zeros((M, 32), np.float32)
+        nbr = np.zeros((M, self.k), np.int32)
+        edge = np.zeros((M, self.k, 8), np.float32)
+        t = np.zeros((M, self.O), np.float32)
+        w = np.zeros((M, self.O), np.float32)
+        wn = C.c_double(0)
+        self._check(self.lib.grt_nn_get_sample(
+            self.h, i, _fptr(feat), nbr.ctypes.data_as(C.POINTER(C.c_int)), _fptr(edge),
+            _fptr(t), _fptr(w), C.byref(wn)))
+        return dict(feat=feat, nbr=nbr, edge=edge, target=t, weight=w, wnorm=wn.value)
+
+    def set_target(self, i, t, w, wnorm):
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self.lib.grt_nn_set_target(self.h, i, _fptr(t), _fptr(w), float(wnorm)))
+
+    def loss_grad(self, i):
+        M = C.c_int64(0)
+        self._check(self.lib.grt_nn_sample_size(self.h, i, C.byref(M)))
+        loss = C.c_double(0)
+        g = np.zeros(self.n_params, np.float32)
+        out = np.zeros((M.value, self.O), np.float32)
+        self._check(self.lib.grt_nn_loss_grad(self.h, i, C.byref(loss), _fptr(g), _fptr(out)))
+        return loss.value, g, out
+
+    def train(self, ids, epochs=1, lr=1e-3, seed=0):
+        a = (C.c_int * len(ids))(*ids)
+        loss = C.c_double(0)
+        self._check(self.lib.grt_nn_train(self.h, len(ids), a, epochs, lr, seed, C.byref(loss)))
+        return loss.value
+
+    def predict(self, ctx, out=None):
+        beta0 = ctx.new_vec() if out is None else out
+        ctx.torch.cuda.synchronize(self.device)
+        self._check(self.lib.grt_nn_predict(self.h, ctx.h, ctx._vec_ptr(beta0)))
+        return beta0
 
 
 def exported_symbols():
