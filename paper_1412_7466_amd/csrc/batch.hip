@@ -338,11 +338,13 @@ __global__ void __launch_bounds__(BT) seg_axpy_basis_kernel(const int* __restric
   }
 }
 
-// beta[problem] -> x segments (scatter) and back (gather)
-__global__ void __launch_bounds__(BT) gather_kernel(const cd* src, cd* dst, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-  if (i < n) dst[i] = src[i];
+// x = 0 on the segments of problems whose flag is set
+__global__ void __launch_bounds__(BT) zero_rejected_kernel(const int* __restrict__ seg2inst,
+                                                           const int* __restrict__ flag, cd* x) {
+  if (!flag[seg2inst[blockIdx.x]]) return;
+  for (int r = 0; r < SEG / BT; ++r) x[(int64_t)blockIdx.x * SEG + r * BT + threadIdx.x] = cd{0.0, 0.0};
 }
+
 
 }  // namespace
 
@@ -709,6 +711,8 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
   std::vector<int> kk(B, 0), iters(B, 0), cycles(B, 0);
   std::vector<double> rel(B, 1.0);
   std::vector<char> done(B, 0);
+  std::vector<int> rejected(B, 0);
+  bool guard = o->use_x0 != 0;
   int total = 0;
   while (true) {
     // R = B - K X into V_0
@@ -716,11 +720,26 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
     ew_sub_kernel<<<gn, BT, 0, s>>>(Bv, V + ldv, V, b->ntot);
     BTRY(batch_norms(b, V, b->nrm));
     BTRY(read_vec(b, b->nrm, beta0));
-    bool any = false;
+    bool any = false, reject = false;
     for (int i = 0; i < B; ++i) {
       rel[i] = bn[i] > 0 ? beta0[i] / bn[i] : 0.0;
       done[i] = rel[i] <= tol;
       if (!done[i]) any = true;
+      if (guard && rel[i] >= 1.0) {
+        rejected[i] = 1;
+        reject = true;
+      }
+    }
+    if (guard) {
+      guard = false;
+      if (reject) {
+        // initial guesses no better than zero are dropped: those problems restart
+        // from x = 0 (the residual is then recomputed for the whole batch)
+        BHIP(b, hipMemcpyAsync(b->d_k, rejected.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+        zero_rejected_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, b->d_k, X);
+        BHIP(b, hipGetLastError());
+        continue;
+      }
     }
     if (!any || total >= maxit) break;
     inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, b->nrm, V);
@@ -802,6 +821,7 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
       stats[i].cycles = cycles[i];
       stats[i].rel_resid = rel[i];
       stats[i].seconds = secs;
+      stats[i].x0_rejected = rejected[i];
     }
     if (!(rel[i] <= tol)) conv = false;
   }
