@@ -8,9 +8,15 @@ at M = 1000 (d = 1, middle layer y in [-1, 1], radii U[0.004, 0.012], indices
 U[1.5, 3.0], gap 0.002, omega = 20, phi = -pi/5, P = 15), seeded and synthetic.
 Setup (matrix A, its SVD, Mie, tables) is outside the timed region.
 
-Prints one JSON line.  `roofline` is for the translation kernel (the dominant
-one), timed with HIP events on the library stream during the timed solves;
-`cpu_baseline` times the CPU FP64 oracle on a bounded sample of the same work.
+The plain FP64 solve is timed twice: with the Toeplitz generator of every pair
+evaluated on the fly in the translation kernel, and with it built once into a
+resident table (1.0 GB) that every apply streams.  `value` is the faster of the
+two; `roofline` is for that run's translation kernel (the dominant one), timed
+with HIP events on the library stream during the timed solves, and
+`roofline_on_the_fly` / `roofline_table` give both.  `sweep` compares, on held-out
+geometries of the warm-start set, sequential plain FP64 solves with one batched
+solve, cold and warm-started by the trained network.  `cpu_baseline` times the
+CPU FP64 oracle on a bounded sample of the same work.
 """
 import argparse
 import json
@@ -24,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solves/s at 1e-9 resid, plain FP64 vs mixed+batched+warm-start; matvec %peak"
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
 
 
 def cpu_baseline(pb, iters, n_sample=96):
@@ -47,6 +54,85 @@ def cpu_baseline(pb, iters, n_sample=96):
                        f"layer term (<5% of the work) is not in the sample")}
 
 
+def sweep(a, torch):
+    """Held-out geometries of the warm-start set (one angle): plain FP64 solves one
+    after another against one batched solve, cold and warm-started."""
+    import numpy as np
+    from paper_1412_7466_amd import inputs
+    from paper_1412_7466_amd.grating import Batch, Context, Network
+    wpath = os.path.join(ROOT, "paper_1412_7466_amd", "warm_start.npz")
+    phi = -math.pi / 5
+    pbs = [inputs.warm_problem(i, held_out=True, phis=(phi,)) for i in range(a.sweep_n)]
+    ctxs = []
+    t0 = time.perf_counter()
+    for pb in pbs:
+        c = Context(0)
+        c.set_problem(pb)
+        c.build()
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+
+    def seq(x0s=None):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = []
+        for i, c in enumerate(ctxs):
+            out.append(c.solve(tol=a.tol, restart=a.restart,
+                               x0=None if x0s is None else x0s[i]))
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    seq()
+    plain, t_plain = seq()
+    batch = Batch(ctxs)
+    batch.solve(tol=a.tol, restart=a.restart)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bb, sb = batch.solve(tol=a.tol, restart=a.restart)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    res = {"workload": (f"{a.sweep_n} held-out geometries of the warm-start set: M=1000 rules "
+                        f"with M uniform in [200, 2000], omega=20, phi=-pi/5, P=15, GMRES to "
+                        f"{a.tol:g}"),
+           "M": [pb.M for pb in pbs], "build_s": t_build,
+           "plain_fp64_sequential_solves_per_s": len(ctxs) / t_plain,
+           "batched_fp64_solves_per_s": len(ctxs) / t_batch,
+           "iters_cold": [s.iters for _, s in plain],
+           "batched_max_rel_diff_vs_plain": max(
+               float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
+               for b, (p, _) in zip(bb, plain))}
+    if os.path.exists(wpath):
+        w = np.load(wpath)
+        width, layers, k, p_out = (int(v) for v in w["config"])
+        net = Network(width, layers, k, p_out)
+        net.set_params(w["theta"])
+        for c in ctxs[:1]:
+            net.predict(c)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x0s = [net.predict(c) for c in ctxs]
+        torch.cuda.synchronize()
+        t_pred = time.perf_counter() - t
+        warm, t_warm = seq(x0s)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x0s = [net.predict(c) for c in ctxs]
+        bw, sw = batch.solve(tol=a.tol, restart=a.restart, x0=x0s)
+        torch.cuda.synchronize()
+        t_bw = time.perf_counter() - t
+        res.update({"predict_s": t_pred,
+                    "warm_fp64_sequential_solves_per_s": len(ctxs) / (t_warm + t_pred),
+                    "batched_warm_fp64_solves_per_s": len(ctxs) / t_bw,
+                    "iters_warm": [s.iters for _, s in warm],
+                    "warm_rejected": int(sum(s.x0_rejected for s in sw))})
+        net.close()
+    batch.close()
+    for c in ctxs:
+        c.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +141,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-n", type=int, default=8)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); "
@@ -71,26 +159,63 @@ def main():
     ctx.build()
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    for _ in range(a.warmup):
-        ctx.solve(tol=a.tol, restart=a.restart)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_read()
-    iters = []
-    resid = []
-    torch.cuda.synchronize()
+    P, M = pb.P, pb.M
+    NB = 2 * P + 1
+    flops = 8.0 * NB ** 2 * M * M     # Toeplitz contraction per (target, source) pair
+
+    def timed_solves():
+        for _ in range(a.warmup):
+            ctx.solve(tol=a.tol, restart=a.restart)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        iters, resid = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            beta, st = ctx.solve(tol=a.tol, restart=a.restart)
+            iters.append(st.iters)
+            resid.append(st.rel_resid)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        ms, launches = ctx.profile_read()
+        ctx.profile(False)
+        return beta, iters, resid, elapsed, ms / max(launches, 1), launches
+
+    # 1. generator evaluated on the fly
+    beta_f, iters_f, resid_f, el_f, avg_f, n_f = timed_solves()
+    ach_f = flops / (avg_f * 1e-3) / 1e12
+    roof_f = {"bound": "alu", "achieved": ach_f, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+              "frac": ach_f / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+              "kernel": f"m2l_kernel<{P}>", "avg_launch_ms": avg_f, "launches": n_f,
+              "flops_per_launch": flops}
+    # 2. resident generator table
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        beta, st = ctx.solve(tol=a.tol, restart=a.restart)
-        iters.append(st.iters)
-        resid.append(st.rel_resid)
+    ctx.set_table(True)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    m2l_ms, launches = ctx.profile_read()
-    ctx.profile(False)
+    t_table = time.perf_counter() - t0
+    beta_t, iters_t, resid_t, el_t, avg_t, n_t = timed_solves()
+    tbytes = 16.0 * M * M * (4 * P + 1)            # generator table, one read per pair
+    xbytes = 16.0 * M * NB                        # coefficients in
+    nchunk = ctx.sizes.m2l_chunks
+    obytes = 16.0 * nchunk * M * NB               # one partial result per source chunk out
+    bytes_t = tbytes + xbytes + obytes
+    gbs = bytes_t / (avg_t * 1e-3) / 1e9
+    roof_t = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": f"m2l_table_kernel<{P}>",
+              "avg_launch_ms": avg_t, "launches": n_t, "bytes_per_launch": bytes_t,
+              "flops_per_launch": flops, "tflops": flops / (avg_t * 1e-3) / 1e12}
+    use_table = el_t < el_f
+    beta = beta_t if use_table else beta_f
+    iters, resid = (iters_t, resid_t) if use_table else (iters_f, resid_f)
+    elapsed = el_t if use_table else el_f
     out = ctx.bragg(beta)
-    # the same workload through the mixed-precision path (FP32 translation, FP64 refinement)
+    diff_tf = float(torch.linalg.norm(beta_t - beta_f) / torch.linalg.norm(beta_f))
+    # 3. the same workload through the mixed-precision path (FP32 translation on the fly,
+    #    FP64 refinement; its FP64 residuals use the table when it is on)
     from paper_1412_7466_amd.grating import GRT_FP32
+    if not use_table:
+        ctx.set_table(False)
     ctx.solve(tol=a.tol, restart=a.restart, precision=GRT_FP32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -101,10 +226,7 @@ def main():
     mixed = {"solves_per_s": 1.0 / t_mixed, "iters": stm.iters, "refine_steps": stm.refine_steps,
              "rel_resid": stm.rel_resid,
              "rel_diff_vs_fp64": float(torch.linalg.norm(bm - beta) / torch.linalg.norm(beta))}
-    P, M = pb.P, pb.M
-    avg_ms = m2l_ms / max(launches, 1)
-    flops = 8.0 * (2 * P + 1) ** 2 * M * M     # Toeplitz contraction per (target, source) pair
-    achieved = flops / (avg_ms * 1e-3) / 1e12
+    ctx.set_table(False)
     res = {
         "metric": METRIC,
         "value": a.steps / elapsed,
@@ -120,19 +242,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "m1000_fp64: plain FP64 method, M=1000, P=15, omega=20, d=1, "
                                "middle layer y in [-1,1], one angle phi=-pi/5, GMRES to 1e-9",
-                   "M": M, "P": P, "n_unknowns": M * (2 * P + 1), "tol": a.tol,
-                   "restart": a.restart, "seed": pb.seed},
+                   "M": M, "P": P, "n_unknowns": M * NB, "tol": a.tol,
+                   "restart": a.restart, "seed": pb.seed,
+                   "translation": "resident table" if use_table else "on the fly"},
         "gmres_iters": iters[-1],
         "rel_resid": resid[-1],
         "flux_err": out["flux_err"],
         "setup_s": t_setup,
+        "table_build_s": t_table,
+        "fp64_on_the_fly_solves_per_s": a.steps / el_f,
+        "fp64_table_solves_per_s": a.steps / el_t,
+        "table_vs_on_the_fly_rel_diff": diff_tf,
         "mixed_fp32_fp64": mixed,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": None, "kernel": f"m2l_kernel<{P}>",
-                     "avg_launch_ms": avg_ms, "launches": launches,
-                     "flops_per_launch": flops},
+        "roofline": roof_t if use_table else roof_f,
+        "roofline_on_the_fly": roof_f,
+        "roofline_table": roof_t,
     }
+    if not a.no_sweep:
+        res["sweep"] = sweep(a, torch)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(pb, iters[-1])
     print(json.dumps(res), flush=True)

@@ -117,6 +117,8 @@ typedef struct {
   int64_t n_alpha;  /* columns of A                                          */
   int64_t rank;     /* singular values kept by the pseudo-inverse            */
   int Nrb;
+  int m2l_chunks;   /* source chunks of the translation launch (one partial
+                       result of n_beta entries each)                         */
 } grt_sizes;
 
 /* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
@@ -145,6 +147,20 @@ grt_status grt_query(const grt_ctx* ctx, grt_sizes* out);
  * Hankel generator itself is FP64); the remaining near pairs, the layer
  * correction and the preconditioner stay FP64. */
 grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision);
+
+/* Resident translation table (FP64 applies).  The Toeplitz generator of every
+ * (target, source) pair, tau_q = sum_l alpha^l H_q(k2 rho_l) e^{i q phi_l} (sec. 4.2,
+ * eq. repre3_mod), does not depend on beta, so it can be built once per problem
+ * (M * Mpad * (4P+1) complex FP64, Mpad = M rounded up to 64: 1.0 GB at M = 1000,
+ * P = 15) and streamed by every apply instead of re-evaluating the Hankel functions.
+ * enable = 1 builds it now (if built) and after every later grt_build; 0 frees it
+ * and the apply evaluates the generator on the fly again.  Results agree with the
+ * on-the-fly apply to rounding.  GRT_ENOMEM if it does not fit in free device
+ * memory with 1 GiB to spare (the context stays usable, without the table).
+ * The mixed-precision apply and batched solves always evaluate on the fly. */
+grt_status grt_set_table(grt_ctx* ctx, int enable);
+/* Bytes the table of the current problem takes. */
+grt_status grt_table_bytes(const grt_ctx* ctx, int64_t* bytes);
 
 /* Diagnostic parts of the apply: y = T x (translation among inclusions and their
  * near copies, sec. 4.2 / eq. repre3_mod) and y = B_phys A^+ C x (the low-rank

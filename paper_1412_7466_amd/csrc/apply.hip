@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <string>
 
 #include "dev_bessel.h"
 #include "grt_internal.h"
@@ -36,6 +37,25 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restri
                                                           double zsafe) {
   m2l_block<P, T>(cx, cy, x, partial, M, chunk, k, d, alpha, alpha_inv, htab, zsafe, blockIdx.x,
                   blockIdx.y);
+}
+
+template <int P>
+__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(P <= 15 ? 2 : 1, P <= 15 ? 2 : 1))) m2l_table_kernel(const cd* __restrict__ table,
+                                                                const cd* __restrict__ x,
+                                                                cd* partial, int M, int Mpad,
+                                                                int chunk) {
+  m2l_table_block<P>(table, x, partial, M, Mpad, chunk, blockIdx.x, blockIdx.y);
+}
+
+template <int P>
+__global__ void __launch_bounds__(64) table_build_kernel(const double* __restrict__ cx,
+                                                         const double* __restrict__ cy, int M,
+                                                         int Mpad, int chunk, double k, double d,
+                                                         cd alpha, cd alpha_inv,
+                                                         const double* __restrict__ htab,
+                                                         cd* table) {
+  table_build_block<P>(cx, cy, M, Mpad, chunk, k, d, alpha, alpha_inv, htab, table, blockIdx.x,
+                       blockIdx.y);
 }
 
 template <int P>
@@ -104,10 +124,23 @@ void launch_m2l(grt_ctx* c, const cd* x) {
   dim3 grid((unsigned)((c->M + 63) / 64), c->m2l_nchunks);
   hipEvent_t* ev = prof_pair(c);
   if (ev) hipEventRecord(ev[0], c->stream);
-  m2l_kernel<P, cd><<<grid, M2L_THREADS, 0, c->stream>>>(
-      c->d_cx, c->d_cy, x, c->d_pT, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
-      c->g.alpha_inv, c->d_htab, 0.0);
+  if (c->d_table)
+    m2l_table_kernel<P><<<grid, M2L_THREADS, 0, c->stream>>>(c->d_table, x, c->d_pT, (int)c->M,
+                                                             c->table_mpad, c->m2l_chunk);
+  else
+    m2l_kernel<P, cd><<<grid, M2L_THREADS, 0, c->stream>>>(
+        c->d_cx, c->d_cy, x, c->d_pT, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
+        c->g.alpha_inv, c->d_htab, 0.0);
   if (ev) hipEventRecord(ev[1], c->stream);
+}
+
+template <int P>
+void launch_table_build(grt_ctx* c) {
+  const int chunk = 16;
+  dim3 grid((unsigned)((c->M + 63) / 64), (unsigned)((c->M + chunk - 1) / chunk));
+  table_build_kernel<P><<<grid, 64, 0, c->stream>>>(c->d_cx, c->d_cy, (int)c->M, c->table_mpad,
+                                                     chunk, c->g.k[1], c->g.d, c->g.alpha,
+                                                     c->g.alpha_inv, c->d_htab, c->d_table);
 }
 
 template <int P>
@@ -374,6 +407,35 @@ grt_status rhs_b(grt_ctx* c, cd* b) {
   combine_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(n, nullptr, c->d_mie, nullptr, 0, c->d_pB,
                                                          c->b_nchunks, c->d_pL, b, 3);
   GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
+
+// Resident translation table: allocate (zeroed: rows of targets >= M stay zero) and
+// fill it, or free it.
+size_t table_bytes(const grt_ctx* c) {
+  const size_t mpad = (size_t)((c->M + 63) / 64) * 64;
+  return mpad * (size_t)c->M * (size_t)(4 * c->P + 1) * sizeof(cd);
+}
+
+grt_status table_set(grt_ctx* c, bool on) {
+  if (c->d_table) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->d_table);
+    c->d_table = nullptr;
+  }
+  if (!on || c->M == 0) return GRT_OK;
+  const size_t bytes = table_bytes(c);
+  size_t free_b = 0, total_b = 0;
+  GRT_HIP(c, hipMemGetInfo(&free_b, &total_b));
+  if (bytes + ((size_t)1 << 30) > free_b)
+    return set_err(c, GRT_ENOMEM, "translation table of " + std::to_string(bytes >> 20) +
+                                      " MiB does not fit in free device memory");
+  c->table_mpad = (int)(((c->M + 63) / 64) * 64);
+  GRT_HIP(c, hipMalloc(&c->d_table, bytes));
+  GRT_HIP(c, hipMemsetAsync(c->d_table, 0, bytes, c->stream));
+  GRT_P_DISPATCH(launch_table_build, c->P, c);
+  GRT_HIP(c, hipGetLastError());
+  GRT_HIP(c, hipStreamSynchronize(c->stream));
   return GRT_OK;
 }
 

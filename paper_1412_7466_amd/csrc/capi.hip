@@ -34,7 +34,8 @@ void free_all(grt_ctx* c) {
                   c->d_mie, c->d_l2l, c->d_f, c->d_pT, c->d_pC, c->d_pB, c->d_pL,
                   c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_cs, c->d_sn, c->d_htab,
                   c->d_gv, c->d_y, c->d_scal, c->d_dotpart, c->d_res, c->d_x32, c->d_pT32,
-                  c->d_pN, c->d_noff, c->d_nlist, c->d_dnorm, c->d_dinv, c->d_xtmp, c->d_ntgt, c->d_npart};
+                  c->d_pN, c->d_noff, c->d_nlist, c->d_dnorm, c->d_dinv, c->d_xtmp, c->d_ntgt, c->d_npart,
+                  c->d_table};
   for (void* p : bufs)
     if (p) hipFree(p);
   c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal =
@@ -53,6 +54,7 @@ void free_all(grt_ctx* c) {
   c->d_xtmp = nullptr;
   c->d_ntgt = nullptr;
   c->d_npart = nullptr;
+  c->d_table = nullptr;
   c->krylov_restart = 0;
   c->built = false;
 }
@@ -250,7 +252,25 @@ grt_status grt_build(grt_ctx* c) {
   if (st != GRT_OK) return st;
   st = apply_alloc(c);
   if (st != GRT_OK) return st;
+  if (c->want_table) {
+    st = table_set(c, true);
+    if (st != GRT_OK) return st;
+  }
   c->built = true;
+  return GRT_OK;
+}
+
+grt_status grt_set_table(grt_ctx* c, int enable) {
+  GRT_CHECK_CTX(c);
+  c->want_table = enable != 0;
+  if (!c->built) return GRT_OK;
+  return table_set(c, c->want_table);
+}
+
+grt_status grt_table_bytes(const grt_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return GRT_EINVAL;
+  if (!c->have_problem) return GRT_ESTATE;
+  *bytes = (int64_t)table_bytes(c);
   return GRT_OK;
 }
 
@@ -264,6 +284,7 @@ grt_status grt_query(const grt_ctx* c, grt_sizes* out) {
   out->n_alpha = c->g.n_alpha;
   out->rank = c->built ? c->rank : 0;
   out->Nrb = c->g.Nrb;
+  out->m2l_chunks = c->built ? c->m2l_nchunks : 0;
   return GRT_OK;
 }
 

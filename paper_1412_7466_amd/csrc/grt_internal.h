@@ -103,6 +103,10 @@ struct grt_ctx {
   int* d_ntgt = nullptr;    // [n_near] target of each near pair
   cd* d_npart = nullptr;    // [n_near][nb] per-pair contributions
   int64_t n_near = 0;
+  // resident translation table (FP64 apply only; see table_set)
+  bool want_table = false;
+  cd* d_table = nullptr;    // [M][4P+1][Mpad]
+  int table_mpad = 0;
   // GMRES workspace
   int krylov_restart = 0;
   cd* d_V = nullptr;        // [restart+1][n_beta]
@@ -149,6 +153,8 @@ grt_status incident_alpha(grt_ctx* c, cd* out);
 grt_status lowrank_from_g(grt_ctx* c, cd* pB_out_sum_into, bool mult_s, const cd* x, cd* y);
 grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out_cd /* device [2 Nrb] */);
 grt_status apply_alloc(grt_ctx* c);
+grt_status table_set(grt_ctx* c, bool on);
+size_t table_bytes(const grt_ctx* c);
 
 // krylov (krylov.hip)
 grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_stats* st);

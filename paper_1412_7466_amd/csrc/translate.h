@@ -22,21 +22,18 @@ __device__ inline __attribute__((always_inline)) void cmac(cf& acc, cf a, cf b) 
 __device__ inline cd to_acc(cd v, cd*) { return v; }
 __device__ inline cf to_acc(cd v, cf*) { return cf{(float)v.r, (float)v.i}; }
 
-// Contribution of one source inclusion (and its copies l = -1, 0, 1) to the incoming
-// coefficients acc[n] of one target, n = -P..P at index n + P:
-//   acc[n] += sum_nu tau_{nu-n} x[nu],  tau_q = sum_l alpha^l H_q(k rho_l) e^{i q phi_l},
-//   rho_l e^{i phi_l} = (dx - l d) + i dy  (Graf's theorem for each copy).
-// The generator is FP64 (H_0, H_1 from the table, upward recurrence, powers of
-// e^{i phi}) and is produced M2L_QB orders at a time; T is the accumulation type
-// (cd: FP64, cf: FP32 with FP32 accumulation).  Each x[nu] is read once per block of
-// orders and feeds up to 2 M2L_QB complex FMAs.  skip0 drops the copy l = 0 (the
-// excluded self term); dead drops everything.  With zsafe > 0 the pair is dropped
-// too when a kept copy has k rho < zsafe (left to the FP64 near-pair pass).
-template <int P, typename T, typename BP, typename TabPtr>
-__device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double dy, double k,
-                                                double d, const cd* wl, bool skip0, bool dead,
-                                                TabPtr tab, double zsafe) {
-  constexpr int NB = 2 * P + 1;
+// Toeplitz generator of one (target, source) pair, FP64:
+//   tau_q = sum_l alpha^l H_q(k rho_l) e^{i q phi_l},  rho_l e^{i phi_l} = (dx - l d) + i dy,
+// for the copies l = -1, 0, 1 (Graf's theorem for each copy), q = -2P..2P.  H_0, H_1
+// come from the table, H_q from the upward recurrence and e^{i q phi} from powers.
+// emit0(tau_0) is called first, then emit(qb, tp, tm) for each block of M2L_QB
+// orders with tp[u] = tau_q, tm[u] = tau_{-q}, q = 1 + qb M2L_QB + u (zero past 2P).
+// skip0 drops the copy l = 0 (the excluded self term); dead drops everything; with
+// zsafe > 0 the pair is dropped too when a kept copy has k rho < zsafe.
+template <int P, typename TabPtr, typename F0, typename F>
+__device__ __forceinline__ void pair_generate(double dx, double dy, double k, double d,
+                                              const cd* wl, bool skip0, bool dead, TabPtr tab,
+                                              double zsafe, F0&& emit0, F&& emit) {
   constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
   cd hp[3], hc[3], cc[3], cq[3];
   double rz2[3];
@@ -65,14 +62,10 @@ __device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double 
     hp[l] = w * h0;
     hc[l] = w * h1;
   }
-  {
-    T t0 = to_acc(hp[0] + hp[1] + hp[2], (T*)nullptr);
-#pragma unroll
-    for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
-  }
+  emit0(hp[0] + hp[1] + hp[2]);
 #pragma unroll
   for (int qb = 0; qb < NQB; ++qb) {
-    T tp[M2L_QB], tm[M2L_QB];
+    cd tp[M2L_QB], tm[M2L_QB];
 #pragma unroll
     for (int u = 0; u < M2L_QB; ++u) {
       const int q = 1 + qb * M2L_QB + u;
@@ -98,30 +91,66 @@ __device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double 
           }
         }
       }
-      tp[u] = to_acc(sp, (T*)nullptr);
-      tm[u] = to_acc(sm, (T*)nullptr);
+      tp[u] = sp;
+      tm[u] = sm;
     }
-    // x may be re-read here: keeps x[nu] out of registers across blocks of orders
-    asm volatile("" ::: "memory");
+    emit(qb, tp, tm);
+  }
+}
+
+// acc[n] += sum over the block's orders q of tau_q x[n+q] + tau_{-q} x[n-q]
+// (n = -P..P at index n + P); each x[nu] is read once per block and feeds up to
+// 2 M2L_QB complex FMAs.
+template <int P, typename T, typename BP>
+__device__ __forceinline__ void contract_block(T* acc, BP b, int qb, const T* tp, const T* tm) {
+  constexpr int NB = 2 * P + 1;
+  // x may be re-read here: keeps x[nu] out of registers across blocks of orders
+  asm volatile("" ::: "memory");
 #pragma unroll
-    for (int nu = 0; nu < NB; ++nu) {
-      bool need = false;
+  for (int nu = 0; nu < NB; ++nu) {
+    bool need = false;
 #pragma unroll
-      for (int u = 0; u < M2L_QB; ++u) {
-        const int q = 1 + qb * M2L_QB + u;
-        if (q <= 2 * P && (nu - q >= 0 || nu + q < NB)) need = true;
-      }
-      if (!need) continue;
-      const T bv = b[nu];
+    for (int u = 0; u < M2L_QB; ++u) {
+      const int q = 1 + qb * M2L_QB + u;
+      if (q <= 2 * P && (nu - q >= 0 || nu + q < NB)) need = true;
+    }
+    if (!need) continue;
+    const T bv = b[nu];
 #pragma unroll
-      for (int u = 0; u < M2L_QB; ++u) {
-        const int q = 1 + qb * M2L_QB + u;
-        if (q > 2 * P) continue;
-        if (nu - q >= 0) cmac(acc[nu - q], tp[u], bv);   // acc[n] += t_q x[n+q]
-        if (nu + q < NB) cmac(acc[nu + q], tm[u], bv);   // acc[n] += t_{-q} x[n-q]
-      }
+    for (int u = 0; u < M2L_QB; ++u) {
+      const int q = 1 + qb * M2L_QB + u;
+      if (q > 2 * P) continue;
+      if (nu - q >= 0) cmac(acc[nu - q], tp[u], bv);   // acc[n] += t_q x[n+q]
+      if (nu + q < NB) cmac(acc[nu + q], tm[u], bv);   // acc[n] += t_{-q} x[n-q]
     }
   }
+}
+
+// Contribution of one source inclusion (and its copies) to the incoming
+// coefficients acc[n] of one target: acc[n] += sum_nu tau_{nu-n} x[nu], with the
+// generator computed on the fly.  T is the accumulation type (cd: FP64, cf: FP32
+// with FP32 accumulation; the generator is FP64 either way).
+template <int P, typename T, typename BP, typename TabPtr>
+__device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double dy, double k,
+                                                double d, const cd* wl, bool skip0, bool dead,
+                                                TabPtr tab, double zsafe) {
+  constexpr int NB = 2 * P + 1;
+  pair_generate<P>(
+      dx, dy, k, d, wl, skip0, dead, tab, zsafe,
+      [&](cd t0) {
+        const T t = to_acc(t0, (T*)nullptr);
+#pragma unroll
+        for (int n = 0; n < NB; ++n) cmac(acc[n], t, b[n]);
+      },
+      [&](int qb, const cd* tp, const cd* tm) {
+        T a[M2L_QB], c[M2L_QB];
+#pragma unroll
+        for (int u = 0; u < M2L_QB; ++u) {
+          a[u] = to_acc(tp[u], (T*)nullptr);
+          c[u] = to_acc(tm[u], (T*)nullptr);
+        }
+        contract_block<P, T>(acc, b, qb, a, c);
+      });
 }
 
 // Translation of the outgoing coefficients of sources [m0, m1) (and of their
@@ -206,6 +235,134 @@ __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
       T o = red[n * 64 + lane];
       out[n] = T{acc[n].r + o.r, acc[n].i + o.i};
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Resident translation table.  The generator tau^{(jm)} does not depend on the
+// coefficients, so for one geometry it can be built once and streamed by every
+// apply: table[(m NQ + q + 2P) Mpad + j] = tau_q of target j, source m, NQ = 4P+1,
+// Mpad = M rounded up to 64 (zero rows for j >= M).  Consecutive targets are
+// consecutive in memory, so the 64 lanes of a wave read one 1 KB line per order.
+// ---------------------------------------------------------------------------
+
+// One lane per target, sources [by_ chunk, (by_+1) chunk).
+template <int P>
+__device__ __forceinline__ void table_build_block(const double* __restrict__ cx,
+                                                  const double* __restrict__ cy, int M, int Mpad,
+                                                  int chunk, double k, double d, cd alpha,
+                                                  cd alpha_inv, const double* __restrict__ htab,
+                                                  cd* table, int bx_, int by_) {
+  constexpr int NQ = 4 * P + 1;
+  __shared__ double stab[HTAB_SIZE];
+  for (int t = threadIdx.x; t < HTAB_SIZE; t += blockDim.x) stab[t] = htab[t];
+  __syncthreads();
+  const int j = bx_ * 64 + (threadIdx.x & 63);
+  if (j >= M) return;
+  const int m0 = by_ * chunk, m1 = min(M, m0 + chunk);
+  const double xj = cx[j], yj = cy[j];
+  const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
+  for (int m = m0; m < m1; ++m) {
+    cd* col = table + (size_t)m * NQ * Mpad + j;
+    pair_generate<P>(
+        xj - cx[m], yj - cy[m], k, d, wl, j == m, false, stab, 0.0,
+        [&](cd t0) { col[(size_t)(2 * P) * Mpad] = t0; },
+        [&](int qb, const cd* tp, const cd* tm) {
+#pragma unroll
+          for (int u = 0; u < M2L_QB; ++u) {
+            const int q = 1 + qb * M2L_QB + u;
+            if (q > 2 * P) continue;
+            col[(size_t)(2 * P + q) * Mpad] = tp[u];
+            col[(size_t)(2 * P - q) * Mpad] = tm[u];
+          }
+        });
+  }
+}
+
+// Same result as m2l_block in FP64, with the generator read from the resident
+// table (the next block of orders is loaded while the current one is contracted).
+template <int P>
+__device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
+                                                const cd* __restrict__ x, cd* partial, int M,
+                                                int Mpad, int chunk, int bx_, int by_) {
+  constexpr int NB = 2 * P + 1;
+  constexpr int NQ = 4 * P + 1;
+  constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
+  constexpr int STAGE = 2 * M2L_WAVES * M2L_TILE * NB;
+  constexpr int RED = 2 * NB * 64;
+  constexpr int BUF = STAGE > RED ? STAGE : RED;
+  __shared__ double smem[BUF];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  cd* sx = reinterpret_cast<cd*>(smem) + wv * M2L_TILE * NB;
+  const int j = bx_ * 64 + lane;  // < Mpad: table rows of dead lanes are zero
+  const int m0 = by_ * chunk;
+  const int m1 = min(M, m0 + chunk);
+  const int per = (m1 - m0 + M2L_WAVES - 1) / M2L_WAVES;
+  const int s0 = m0 + wv * per;
+  const int s1 = min(m1, s0 + per);
+  const int ntile = (per + M2L_TILE - 1) / M2L_TILE;
+  cd acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = cd{0, 0};
+  for (int it = 0; it < ntile; ++it) {
+    const int ts = s0 + it * M2L_TILE;
+    const int cnt = max(0, min(M2L_TILE, s1 - ts));
+    __syncthreads();
+    for (int t = lane; t < cnt * NB; t += 64) sx[t] = x[(size_t)ts * NB + t];
+    __syncthreads();
+    for (int mm = 0; mm < cnt; ++mm) {
+      const cd* b = sx + mm * NB;
+      const cd* col = table + (size_t)(ts + mm) * NQ * Mpad + j;
+      {
+        const cd t0 = col[(size_t)(2 * P) * Mpad];
+#pragma unroll
+        for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
+      }
+      cd np[M2L_QB], nm[M2L_QB];
+#pragma unroll
+      for (int u = 0; u < M2L_QB; ++u) {
+        const int q = 1 + u;
+        np[u] = q <= 2 * P ? col[(size_t)(2 * P + q) * Mpad] : cd{0, 0};
+        nm[u] = q <= 2 * P ? col[(size_t)(2 * P - q) * Mpad] : cd{0, 0};
+      }
+#pragma unroll
+      for (int qb = 0; qb < NQB; ++qb) {
+        cd tp[M2L_QB], tm[M2L_QB];
+#pragma unroll
+        for (int u = 0; u < M2L_QB; ++u) {
+          tp[u] = np[u];
+          tm[u] = nm[u];
+        }
+        if (qb + 1 < NQB) {
+#pragma unroll
+          for (int u = 0; u < M2L_QB; ++u) {
+            const int q = 1 + (qb + 1) * M2L_QB + u;
+            np[u] = q <= 2 * P ? col[(size_t)(2 * P + q) * Mpad] : cd{0, 0};
+            nm[u] = q <= 2 * P ? col[(size_t)(2 * P - q) * Mpad] : cd{0, 0};
+          }
+        }
+        contract_block<P, cd>(acc, b, qb, tp, tm);
+      }
+    }
+  }
+  cd* red = reinterpret_cast<cd*>(smem);
+  for (int src = M2L_WAVES - 1; src >= 1; --src) {
+    __syncthreads();
+    if (wv == src) {
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        cd v = acc[n];
+        if (src != M2L_WAVES - 1) v += red[n * 64 + lane];
+        red[n * 64 + lane] = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (wv == 0 && j < M) {
+    cd* out = partial + ((size_t)by_ * M + j) * NB;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) out[n] = acc[n] + red[n * 64 + lane];
   }
 }
 

@@ -51,7 +51,8 @@ class grt_solve_stats(C.Structure):
 
 class grt_sizes(C.Structure):
     _fields_ = [("M", C.c_int64), ("P", C.c_int), ("n_beta", C.c_int64), ("n_rows", C.c_int64),
-                ("n_alpha", C.c_int64), ("rank", C.c_int64), ("Nrb", C.c_int)]
+                ("n_alpha", C.c_int64), ("rank", C.c_int64), ("Nrb", C.c_int),
+                ("m2l_chunks", C.c_int)]
 
 
 class grt_nn_config(C.Structure):
@@ -73,6 +74,8 @@ _PROTOS = {
     "grt_apply_lowrank": (C.c_int, [_VP, _VP, _VP]),
     "grt_rhs": (C.c_int, [_VP, _VP]),
     "grt_incident": (C.c_int, [_VP, _VP]),
+    "grt_set_table": (C.c_int, [_VP, C.c_int]),
+    "grt_table_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
     "grt_bragg": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -239,6 +242,17 @@ class Context:
         self._check(self.lib.grt_rhs(self.h, self._vec_ptr(b)))
         self._leave()
         return b
+
+    def set_table(self, enable=True):
+        """Build (or free) the resident translation table of the FP64 apply."""
+        self._enter()
+        self._check(self.lib.grt_set_table(self.h, int(enable)))
+        self._leave()
+
+    def table_bytes(self):
+        n = C.c_int64(0)
+        self._check(self.lib.grt_table_bytes(self.h, C.byref(n)))
+        return n.value
 
     def incident(self, a=None):
         """alpha0 = B_phys A^+ f (the layers' incoming coefficients at each inclusion)."""

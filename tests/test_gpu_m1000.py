@@ -83,3 +83,19 @@ def test_m1000_solve_mixed(m1000):
     say(f"[gpu] m1000 mixed iters={st.iters} refine={st.refine_steps} "
         f"resid={st.rel_resid:.2e} {st.seconds:.3f}s")
     _check_solution(ctx, beta, gold, "mixed")
+
+
+def test_m1000_resident_table(m1000):
+    """Same bars with the resident translation table (1 GB at this size)."""
+    torch, ctx, gold = m1000
+    ctx.set_table(True)
+    try:
+        x = torch.tensor(gold["probe"], dtype=torch.complex128, device="cuda:0")
+        e = rel(ctx.apply(x).cpu().numpy(), gold["K_probe"])
+        say(f"[gpu] m1000 table: K probe rel err {e:.2e}")
+        assert e < 1e-9
+        beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000)
+        say(f"[gpu] m1000 table FP64 iters={st.iters} resid={st.rel_resid:.2e} {st.seconds:.3f}s")
+        _check_solution(ctx, beta, gold, "FP64 table")
+    finally:
+        ctx.set_table(False)

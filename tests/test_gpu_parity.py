@@ -247,3 +247,25 @@ def test_layer_factors_shared_between_contexts(torch_cuda):
     ca.close()
     beta, st = cb.solve(tol=1e-12, restart=150)
     assert rel(_np(beta), Reduced(pb).solve_lu()) < 1e-9
+
+
+@pytest.mark.parametrize("M,P,seed", [(67, 4, 6), (20, 10, 8), (12, 15, 9), (30, 20, 14)])
+def test_resident_table_matches_oracle(torch_cuda, M, P, seed):
+    """The FP64 apply streaming the resident generator table equals the oracle (and
+    the on-the-fly apply to rounding); switching it off restores the on-the-fly path."""
+    from oracle.solver import Reduced
+    pb = inputs.small(M, P, seed=seed)
+    red = Reduced(pb)
+    ctx = _ctx(pb)
+    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    y_fly = _np(ctx.apply_T(xd))
+    ctx.set_table(True)
+    say(f"[gpu] table M={M} P={P}: {ctx.table_bytes()} bytes")
+    y_tab = _np(ctx.apply_T(xd))
+    assert rel(y_tab, red.T_apply(xh)) < 1e-12
+    assert rel(y_tab, y_fly) < 1e-13
+    assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+    beta, st = ctx.solve(tol=1e-12, restart=150)
+    assert rel(_np(beta), red.solve_lu()) < 1e-9
+    ctx.set_table(False)
+    assert np.array_equal(_np(ctx.apply_T(xd)), y_fly)
