@@ -182,18 +182,20 @@ def main():
         ctx.profile(False)
         return beta, iters, resid, elapsed, ms / max(launches, 1), launches
 
-    # 1. generator evaluated on the fly
+    # 1. generator evaluated on the fly (launch shape chosen by the autotuner)
+    tune_f = ctx.autotune()
     beta_f, iters_f, resid_f, el_f, avg_f, n_f = timed_solves()
     ach_f = flops / (avg_f * 1e-3) / 1e12
     roof_f = {"bound": "alu", "achieved": ach_f, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
               "frac": ach_f / FP64_VALU_PEAK_TFLOPS, "traffic": None,
               "kernel": f"m2l_kernel<{P}>", "avg_launch_ms": avg_f, "launches": n_f,
-              "flops_per_launch": flops}
+              "flops_per_launch": flops, "autotune_chunks_ms": tune_f}
     # 2. resident generator table
     t0 = time.perf_counter()
     ctx.set_table(True)
     torch.cuda.synchronize()
     t_table = time.perf_counter() - t0
+    tune_t = ctx.autotune()
     beta_t, iters_t, resid_t, el_t, avg_t, n_t = timed_solves()
     tbytes = 16.0 * M * M * (4 * P + 1)            # generator table, one read per pair
     xbytes = 16.0 * M * NB                        # coefficients in
@@ -204,7 +206,8 @@ def main():
     roof_t = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": f"m2l_table_kernel<{P}>",
               "avg_launch_ms": avg_t, "launches": n_t, "bytes_per_launch": bytes_t,
-              "flops_per_launch": flops, "tflops": flops / (avg_t * 1e-3) / 1e12}
+              "flops_per_launch": flops, "tflops": flops / (avg_t * 1e-3) / 1e12,
+              "autotune_chunks_ms": tune_t}
     use_table = el_t < el_f
     beta = beta_t if use_table else beta_f
     iters, resid = (iters_t, resid_t) if use_table else (iters_f, resid_f)

@@ -159,6 +159,14 @@ grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision
  * memory with 1 GiB to spare (the context stays usable, without the table).
  * The mixed-precision apply and batched solves always evaluate on the fly. */
 grt_status grt_set_table(grt_ctx* ctx, int enable);
+/* Launch-shape autotuner of the translation kernel: times the launch for source
+ * chunk counts giving 256 .. 8192 work-groups, in the current mode (on the fly or
+ * resident table), and keeps the fastest for every later apply of this context
+ * (results change only by the order of the chunk sums).  Up to cap measured
+ * (chunk count, ms per launch) pairs go to chunks[] / ms[] (host); *n receives
+ * their number.  Without a call the split aims at two work-groups per SIMD. */
+grt_status grt_autotune(grt_ctx* ctx, int cap, int* n, int* chunks, double* ms);
+
 /* Bytes the table of the current problem takes. */
 grt_status grt_table_bytes(const grt_ctx* ctx, int64_t* bytes);
 

@@ -272,6 +272,17 @@ bool supported_P(int P) {
   }
 }
 
+// Split nsrc sources into chunks so that tiles x chunks covers about want_waves
+// work-groups (at least min_chunk sources per chunk).
+static void split_work(int64_t nsrc, int64_t tiles, int64_t want_waves, int64_t min_chunk,
+                       int& chunk, int& nchunks) {
+  int64_t nc = std::max<int64_t>(1, (want_waves + tiles - 1) / tiles);
+  nc = std::min<int64_t>(nc, std::max<int64_t>(1, (nsrc + min_chunk - 1) / min_chunk));
+  int64_t ch = (nsrc + nc - 1) / nc;
+  chunk = (int)ch;
+  nchunks = (int)((nsrc + ch - 1) / ch);
+}
+
 grt_status apply_alloc(grt_ctx* c) {
   const int64_t M = c->M;
   // vectors of the low-rank path: also needed without inclusions (Bragg amplitudes)
@@ -281,20 +292,19 @@ grt_status apply_alloc(grt_ctx* c) {
   if (M == 0) return GRT_OK;
   // Work split: every kernel gets enough (target tile, source chunk) blocks to
   // give each of the 1024 SIMDs about two waves; partial sums per chunk are
-  // added in a fixed order afterwards (deterministic results).
-  auto split = [](int64_t nsrc, int64_t tiles, int64_t want_waves, int64_t min_chunk,
-                  int& chunk, int& nchunks) {
-    int64_t nc = std::max<int64_t>(1, (want_waves + tiles - 1) / tiles);
-    nc = std::min<int64_t>(nc, std::max<int64_t>(1, (nsrc + min_chunk - 1) / min_chunk));
-    int64_t ch = (nsrc + nc - 1) / nc;
-    chunk = (int)ch;
-    nchunks = (int)((nsrc + ch - 1) / ch);
-  };
+  // added in a fixed order afterwards (deterministic results).  The translation's
+  // split can be re-chosen by measurement (autotune_m2l); its partial buffers are
+  // sized for the largest candidate.
   const int nt = 2 * c->g.N + c->g.Nw[1];
-  split(M, (M + 63) / 64, 2048 / M2L_WAVES, 4 * M2L_WAVES, c->m2l_chunk, c->m2l_nchunks);
-  split(M, (nt + 63) / 64, 2048, 4, c->c_chunk, c->c_nchunks);
-  split(6 * (int64_t)c->g.N, (M + 63) / 64, 1024, 16, c->b_chunk, c->b_nchunks);
-  GRT_HIP(c, hipMalloc(&c->d_pT, sizeof(cd) * (size_t)c->m2l_nchunks * c->n_beta));
+  split_work(M, (M + 63) / 64, 2048 / M2L_WAVES, 4 * M2L_WAVES, c->m2l_chunk, c->m2l_nchunks);
+  {
+    int ch, nc;
+    split_work(M, (M + 63) / 64, M2L_TUNE_MAX_WAVES / M2L_WAVES, 4 * M2L_WAVES, ch, nc);
+    c->m2l_nchunks_cap = std::max(nc, c->m2l_nchunks);
+  }
+  split_work(M, (nt + 63) / 64, 2048, 4, c->c_chunk, c->c_nchunks);
+  split_work(6 * (int64_t)c->g.N, (M + 63) / 64, 1024, 16, c->b_chunk, c->b_nchunks);
+  GRT_HIP(c, hipMalloc(&c->d_pT, sizeof(cd) * (size_t)c->m2l_nchunks_cap * c->n_beta));
   GRT_HIP(c, hipMalloc(&c->d_pC, sizeof(cd) * (size_t)c->c_nchunks * nt * 2));
   GRT_HIP(c, hipMalloc(&c->d_pB, sizeof(cd) * (size_t)c->b_nchunks * c->n_beta));
   GRT_HIP(c, hipMalloc(&c->d_pL, sizeof(cd) * (size_t)c->n_beta));
@@ -305,7 +315,7 @@ grt_status apply_alloc(grt_ctx* c) {
     const int q = 2 * c->P;
     c->zsafe = 1.1 * 2.0 * std::exp((std::lgamma((double)q) - std::log(M_PI * 1e30)) / q);
     GRT_HIP(c, hipMalloc(&c->d_x32, sizeof(cf) * (size_t)c->n_beta));
-    GRT_HIP(c, hipMalloc(&c->d_pT32, sizeof(cf) * (size_t)c->m2l_nchunks * c->n_beta));
+    GRT_HIP(c, hipMalloc(&c->d_pT32, sizeof(cf) * (size_t)c->m2l_nchunks_cap * c->n_beta));
     GRT_HIP(c, hipMalloc(&c->d_pN, sizeof(cd) * (size_t)c->n_beta));
     GRT_HIP(c, hipMalloc(&c->d_noff, sizeof(int) * (size_t)(M + 1)));
     int* cnt = nullptr;
@@ -436,6 +446,62 @@ grt_status table_set(grt_ctx* c, bool on) {
   GRT_P_DISPATCH(launch_table_build, c->P, c);
   GRT_HIP(c, hipGetLastError());
   GRT_HIP(c, hipStreamSynchronize(c->stream));
+  return GRT_OK;
+}
+
+// Measure the translation launch for several source-chunk counts (work-group
+// counts from 256 to M2L_TUNE_MAX_WAVES) in the current mode (on the fly or resident
+// table) and keep the fastest.  Reports up to cap (chunks, ms per launch) pairs.
+grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, double* ms_out) {
+  if (c->M == 0) {
+    if (n_out) *n_out = 0;
+    return GRT_OK;
+  }
+  hipStream_t s = c->stream;
+  const int64_t M = c->M;
+  hipEvent_t e0, e1;
+  GRT_HIP(c, hipEventCreate(&e0));
+  GRT_HIP(c, hipEventCreate(&e1));
+  const bool prof = c->prof;
+  c->prof = false;
+  GRT_HIP(c, hipMemsetAsync(c->d_xtmp, 0, sizeof(cd) * (size_t)c->n_beta, s));
+  int best_chunk = c->m2l_chunk, best_n = c->m2l_nchunks, count = 0;
+  double best_ms = 1e300;
+  int last_nc = -1;
+  for (int64_t waves = 256; waves <= M2L_TUNE_MAX_WAVES; waves *= 2) {
+    int ch, nc;
+    split_work(M, (M + 63) / 64, waves / M2L_WAVES, 4 * M2L_WAVES, ch, nc);
+    if (nc == last_nc || nc > c->m2l_nchunks_cap) continue;
+    last_nc = nc;
+    c->m2l_chunk = ch;
+    c->m2l_nchunks = nc;
+    for (int r = 0; r < 2; ++r) GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
+    GRT_HIP(c, hipEventRecord(e0, s));
+    const int reps = 5;
+    for (int r = 0; r < reps; ++r) GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
+    GRT_HIP(c, hipEventRecord(e1, s));
+    GRT_HIP(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    GRT_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+    const double per = ms / reps;
+    if (count < cap) {
+      if (chunks_out) chunks_out[count] = nc;
+      if (ms_out) ms_out[count] = per;
+    }
+    ++count;
+    if (per < best_ms) {
+      best_ms = per;
+      best_chunk = ch;
+      best_n = nc;
+    }
+  }
+  c->m2l_chunk = best_chunk;
+  c->m2l_nchunks = best_n;
+  c->prof = prof;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  GRT_HIP(c, hipGetLastError());
+  if (n_out) *n_out = std::min(count, cap);
   return GRT_OK;
 }
 

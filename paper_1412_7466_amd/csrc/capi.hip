@@ -32,8 +32,8 @@ void free_all(grt_ctx* c) {
   void* bufs[] = {c->d_cx, c->d_cy, c->d_rad, c->d_kp, c->d_yw, c->d_wcorr, c->d_A,
                   c->d_colscale, c->d_sv, c->d_U, c->d_VH, c->d_W1, c->d_W2, c->d_W3,
                   c->d_mie, c->d_l2l, c->d_f, c->d_pT, c->d_pC, c->d_pB, c->d_pL,
-                  c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_cs, c->d_sn, c->d_htab,
-                  c->d_gv, c->d_y, c->d_scal, c->d_dotpart, c->d_res, c->d_x32, c->d_pT32,
+                  c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_htab,
+                  c->d_y, c->d_scal, c->d_dotpart, c->d_x32, c->d_pT32,
                   c->d_pN, c->d_noff, c->d_nlist, c->d_dnorm, c->d_dinv, c->d_xtmp, c->d_ntgt, c->d_npart,
                   c->d_table};
   for (void* p : bufs)
@@ -42,8 +42,7 @@ void free_all(grt_ctx* c) {
       c->d_htab = nullptr;
   c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_mie = c->d_l2l =
       c->d_f = c->d_pT = c->d_pC = c->d_pB = c->d_pL = c->d_gvec = c->d_tvec = c->d_wvec =
-          c->d_V = c->d_H = c->d_cs = c->d_sn = c->d_gv = c->d_y = c->d_dotpart = nullptr;
-  c->d_res = nullptr;
+          c->d_V = c->d_H = c->d_y = c->d_dotpart = nullptr;
   c->d_x32 = nullptr;
   c->d_pT32 = nullptr;
   c->d_pN = nullptr;
@@ -100,6 +99,7 @@ grt_status grt_destroy(grt_ctx* c) {
   for (hipEvent_t e : c->ev_res)
     if (e) hipEventDestroy(e);
   if (c->h_pinned) hipHostFree(c->h_pinned);
+  if (c->h_H) hipHostFree(c->h_H);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
   return GRT_OK;
@@ -327,6 +327,14 @@ grt_status grt_rhs(grt_ctx* c, void* b) {
   if (st != GRT_OK) return st;
   if (!b) return set_err(c, GRT_EINVAL, "null vector");
   return rhs_b(c, static_cast<cd*>(b));
+}
+
+grt_status grt_autotune(grt_ctx* c, int cap, int* n, int* chunks, double* ms) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (cap < 0 || (cap > 0 && (!chunks || !ms))) return set_err(c, GRT_EINVAL, "bad arrays");
+  return autotune_m2l(c, cap, n, chunks, ms);
 }
 
 grt_status grt_incident(grt_ctx* c, void* a) {

@@ -84,6 +84,7 @@ struct grt_ctx {
   double* d_htab = nullptr; // H_0, H_1 interpolation table (HTAB_SIZE doubles)
   // apply workspace
   int m2l_chunk = 16, m2l_nchunks = 0;
+  int m2l_nchunks_cap = 0;  // partial buffers hold this many chunks
   int c_chunk = 64, c_nchunks = 0;
   int b_chunk = 64, b_nchunks = 0;
   cd* d_pT = nullptr;       // [m2l_nchunks][M][nb]
@@ -111,16 +112,13 @@ struct grt_ctx {
   int krylov_restart = 0;
   cd* d_V = nullptr;        // [restart+1][n_beta]
   cd* d_H = nullptr;        // [restart+1][restart] (column j contiguous: H[j*(restart+1)+i])
-  cd* d_cs = nullptr;
-  cd* d_sn = nullptr;
-  cd* d_gv = nullptr;       // [restart+1]
   cd* d_y = nullptr;
   double* d_scal = nullptr; // scratch scalars
   cd* d_dotpart = nullptr;  // [restart+1][n_dot_blocks]
   int n_dot_blocks = 0;
-  double* d_res = nullptr;   // residual estimate of every Arnoldi step
   hipEvent_t ev_res[2] = {nullptr, nullptr};
   double* h_pinned = nullptr;
+  cd* h_H = nullptr;        // pinned host mirror of H and the least-squares solution
   // kernel timing (HIP events around every translation-kernel launch)
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;  // pairs: start, stop
@@ -154,6 +152,8 @@ grt_status lowrank_from_g(grt_ctx* c, cd* pB_out_sum_into, bool mult_s, const cd
 grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out_cd /* device [2 Nrb] */);
 grt_status apply_alloc(grt_ctx* c);
 grt_status table_set(grt_ctx* c, bool on);
+grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, double* ms_out);
+constexpr int M2L_TUNE_MAX_WAVES = 8192;
 size_t table_bytes(const grt_ctx* c);
 
 // krylov (krylov.hip)

@@ -1,8 +1,11 @@
 // Restarted GMRES on the device for K beta = b (paper sec. 5: the preconditioned
 // Schur system is solved iteratively by GMRES; sec. 6 reports its relative residual
 // as the "GMRES error").  FP64 throughout: classical Gram-Schmidt applied twice
-// (CGS2) for the Arnoldi basis, complex Givens rotations for the Hessenberg least
-// squares, all on the device; the host only reads one residual estimate per step.
+// (CGS2) for the Arnoldi basis on the device; each new Hessenberg column (j+2
+// numbers) is copied to pinned host memory, where the complex Givens rotations,
+// the residual estimate and, at the end of a cycle, the triangular solve run,
+// one Arnoldi step behind the device so the GPU queue never drains.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -113,76 +116,42 @@ __global__ void axpy_basis_kernel(cd* x, const cd* __restrict__ V, size_t ldv, i
   x[i] = acc;
 }
 
-// ||w|| from the norm partials; then column j of H gets the rotations of columns
-// 0..j-1 and a new rotation that zeroes H[j+1][j]; g is rotated alongside.  With
-// c = a/den, s = b/den the rotation [[conj c, conj s], [-s, c]] maps (a, b) to
-// (den, 0).  res = |g[j+1]|, the residual norm of the current iterate.
-__global__ void givens_kernel(cd* H, int ldh, cd* cs, cd* sn, cd* g, int j, const double* npart,
-                              int nblk, double* hnext, double* res) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// w /= ||w|| with ||w|| from the norm partials (every block redoes the short sum in
+// the same order); block 0 also stores it as H[j+1][j].
+__global__ void __launch_bounds__(KT) norm_scale_kernel(cd* w, int n, const double* npart, int nblk,
+                                                         cd* hsub) {
   double s2 = 0.0;
   for (int b = 0; b < nblk; ++b) s2 += npart[b];
-  double hn = sqrt(s2);
-  *hnext = hn;
-  cd* h = H + (size_t)j * ldh;
-  h[j + 1] = cd{hn, 0.0};
-  for (int i = 0; i < j; ++i) {
-    cd t = conj(cs[i]) * h[i] + conj(sn[i]) * h[i + 1];
-    h[i + 1] = -(sn[i] * h[i]) + cs[i] * h[i + 1];
-    h[i] = t;
-  }
-  cd a = h[j], b = h[j + 1];
-  double den = sqrt(cabs2(a) + cabs2(b));
-  cd c = den > 0 ? (1.0 / den) * a : cd{1.0, 0.0};
-  cd s = den > 0 ? (1.0 / den) * b : cd{0.0, 0.0};
-  cs[j] = c;
-  sn[j] = s;
-  h[j] = cd{den, 0.0};
-  h[j + 1] = cd{0.0, 0.0};
-  g[j + 1] = -(s * g[j]);
-  g[j] = conj(c) * g[j];
-  res[j] = sqrt(cabs2(g[j + 1]));
-}
-
-// back substitution R y = g for the leading k x k triangle
-__global__ void backsolve_kernel(const cd* H, int ldh, const cd* g, cd* y, int k) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = k - 1; i >= 0; --i) {
-    cd s = g[i];
-    for (int t = i + 1; t < k; ++t) s -= H[(size_t)t * ldh + i] * y[t];
-    cd d = H[(size_t)i * ldh + i];
-    y[i] = (cabs2(d) > 0) ? cdiv(s, d) : cd{0.0, 0.0};
-  }
-}
-
-__global__ void init_g_kernel(cd* g, int len, const double* beta) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < len) g[i] = (i == 0) ? cd{*beta, 0.0} : cd{0.0, 0.0};
+  const double hn = sqrt(s2);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hsub = cd{hn, 0.0};
+  int i = blockIdx.x * KT + threadIdx.x;
+  if (i >= n) return;
+  if (hn > 0) w[i] = (1.0 / hn) * w[i];
 }
 
 }  // namespace
 
 static grt_status ensure_workspace(grt_ctx* c, int m) {
   if (c->krylov_restart == m && c->d_V) return GRT_OK;
-  hipFree(c->d_V); hipFree(c->d_H); hipFree(c->d_cs); hipFree(c->d_sn); hipFree(c->d_gv);
-  hipFree(c->d_y); hipFree(c->d_scal); hipFree(c->d_dotpart); hipFree(c->d_res);
+  hipFree(c->d_V); hipFree(c->d_H);
+  hipFree(c->d_y); hipFree(c->d_scal); hipFree(c->d_dotpart);
   const size_t n = (size_t)c->n_beta;
   c->n_dot_blocks = (int)std::min<size_t>(16, (n + KT * 4 - 1) / (KT * 4));
   if (c->n_dot_blocks < 1) c->n_dot_blocks = 1;
   GRT_HIP(c, hipMalloc(&c->d_V, sizeof(cd) * n * (m + 4)));
   GRT_HIP(c, hipMalloc(&c->d_H, sizeof(cd) * (size_t)(m + 1) * (m + 1)));
-  GRT_HIP(c, hipMalloc(&c->d_cs, sizeof(cd) * (m + 1)));
-  GRT_HIP(c, hipMalloc(&c->d_sn, sizeof(cd) * (m + 1)));
-  GRT_HIP(c, hipMalloc(&c->d_gv, sizeof(cd) * (m + 2)));
   GRT_HIP(c, hipMalloc(&c->d_y, sizeof(cd) * (m + 1)));
   GRT_HIP(c, hipMalloc(&c->d_scal, sizeof(double) * (16 + c->n_dot_blocks)));
-  GRT_HIP(c, hipMalloc(&c->d_res, sizeof(double) * (m + 1)));
   if (!c->ev_res[0]) {
     GRT_HIP(c, hipEventCreateWithFlags(&c->ev_res[0], hipEventDisableTiming));
     GRT_HIP(c, hipEventCreateWithFlags(&c->ev_res[1], hipEventDisableTiming));
   }
   GRT_HIP(c, hipMalloc(&c->d_dotpart, sizeof(cd) * ((size_t)(m + 2) * c->n_dot_blocks + 2 * (size_t)(m + 2))));
   if (!c->h_pinned) GRT_HIP(c, hipHostMalloc(&c->h_pinned, sizeof(double) * 16));
+  if (c->h_H) hipHostFree(c->h_H);
+  c->h_H = nullptr;
+  // host mirror of the Hessenberg columns, then y: (m+1)^2 + (m+1) complex
+  GRT_HIP(c, hipHostMalloc(&c->h_H, sizeof(cd) * ((size_t)(m + 1) * (m + 1) + (m + 1))));
   c->krylov_restart = m;
   return GRT_OK;
 }
@@ -254,15 +223,11 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
   hipStream_t s = c->stream;
   const size_t ldv = (size_t)n;
   cd* V = c->d_V;
-  const int ldh = m + 1;
   const int gridn = (n + KT - 1) / KT;
   const int nblk = c->n_dot_blocks;
   double* d_bn = c->d_scal + 0;
   double* d_beta = c->d_scal + 1;
-  double* d_hn = c->d_scal + 2;
   double* d_npart = c->d_scal + 16;
-  double* d_res = c->d_res;
-  double* h_res = c->h_pinned + 8;
   GRT_TRY(vec_norm(c, bvec, n, d_bn));
   double bn = 0.0;
   GRT_TRY(read_scalar(c, d_bn, &bn));
@@ -273,6 +238,33 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
     return GRT_OK;
   }
   int total = 0;
+  const int ldh = m + 1;
+  cd* hH = c->h_H;                            // host mirror of H (column j at hH + j ldh)
+  cd* hy = c->h_H + (size_t)ldh * ldh;        // least-squares solution
+  std::vector<cd> cs(m + 1), sn(m + 1), g(m + 2);
+  // Column jj of H arrived on the host: rotate it by the previous rotations, make
+  // the rotation [[conj c, conj s], [-s, c]] (c = a/den, s = b/den) that zeroes
+  // H[jj+1][jj], rotate g alongside; |g[jj+1]| is the residual norm of the
+  // iterate that uses the first jj+1 basis vectors.
+  auto givens = [&](int jj) {
+    cd* h = hH + (size_t)jj * ldh;
+    for (int i = 0; i < jj; ++i) {
+      cd t = conj(cs[i]) * h[i] + conj(sn[i]) * h[i + 1];
+      h[i + 1] = -(sn[i] * h[i]) + cs[i] * h[i + 1];
+      h[i] = t;
+    }
+    cd a = h[jj], b = h[jj + 1];
+    double den = std::sqrt(cabs2(a) + cabs2(b));
+    cd cc = den > 0 ? (1.0 / den) * a : cd{1.0, 0.0};
+    cd ss = den > 0 ? (1.0 / den) * b : cd{0.0, 0.0};
+    cs[jj] = cc;
+    sn[jj] = ss;
+    h[jj] = cd{den, 0.0};
+    h[jj + 1] = cd{0.0, 0.0};
+    g[jj + 1] = -(ss * g[jj]);
+    g[jj] = conj(cc) * g[jj];
+    return std::sqrt(cabs2(g[jj + 1]));
+  };
   while (true) {
     // r = b - op x into V_0
     GRT_TRY(op(c, x, V + ldv));  // temp in slot 1
@@ -290,13 +282,15 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
     if (res->rel <= tol) { res->converged = true; break; }
     if (total >= maxit) break;
     scale_kernel<<<gridn, KT, 0, s>>>(V, V, n, d_beta);
-    init_g_kernel<<<1, 1024, 0, s>>>(c->d_gv, m + 1, d_beta);
-    // Arnoldi steps.  The host never waits on the step it just queued: the
-    // residual estimate of step j is checked after step j+1 has been queued, so
-    // at most one step is computed past convergence (and discarded: the
-    // least-squares solve uses columns 0..k-1 only, which that step leaves intact).
+    std::fill(g.begin(), g.end(), cd{0.0, 0.0});
+    g[0] = cd{beta, 0.0};
+    // Arnoldi steps.  The host never waits on the step it just queued: column j
+    // of H is copied back and rotated after step j+1 has been queued, so at most
+    // one step is computed past convergence (and discarded: the least-squares
+    // solve uses columns 0..k-1 only, which that step leaves intact).
     int k = 0;
     int queued = 0;
+    bool conv = false;
     for (int j = 0; j < m && total + queued < maxit; ++j) {
       cd* w = V + (size_t)(j + 1) * ldv;
       GRT_TRY(op(c, V + (size_t)j * ldv, w));
@@ -307,27 +301,35 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
         update_kernel<<<gridn, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, nblk, j + 1, hcol, pass);
       }
       norm2_kernel<<<nblk, KT, 0, s>>>(w, n, d_npart, nblk);
-      givens_kernel<<<1, 64, 0, s>>>(c->d_H, ldh, c->d_cs, c->d_sn, c->d_gv, j, d_npart, nblk,
-                                     d_hn, d_res);
-      scale_kernel<<<gridn, KT, 0, s>>>(w, w, n, d_hn);
+      norm_scale_kernel<<<gridn, KT, 0, s>>>(w, n, d_npart, nblk, hcol + j + 1);
       GRT_HIP(c, hipGetLastError());
-      GRT_HIP(c, hipMemcpyAsync(h_res + (j & 1), d_res + j, sizeof(double),
+      GRT_HIP(c, hipMemcpyAsync(hH + (size_t)j * ldh, hcol, sizeof(cd) * (j + 2),
                                 hipMemcpyDeviceToHost, s));
       GRT_HIP(c, hipEventRecord(c->ev_res[j & 1], s));
       ++queued;
       if (j >= 1) {
         GRT_HIP(c, hipEventSynchronize(c->ev_res[(j - 1) & 1]));
-        if (h_res[(j - 1) & 1] / bn <= tol) { k = j; break; }
+        if (givens(j - 1) / bn <= tol) { k = j; conv = true; break; }
       }
       k = j + 1;
     }
-    if (k == queued) {  // the last queued step has not been checked yet
+    if (!conv && k == queued && k > 0) {  // the last queued step has not been checked yet
       GRT_HIP(c, hipEventSynchronize(c->ev_res[(k - 1) & 1]));
+      givens(k - 1);
     }
     total += k;
-    backsolve_kernel<<<1, 64, 0, s>>>(c->d_H, ldh, c->d_gv, c->d_y, k);
+    // back substitution R y = g on the leading k x k triangle (host), then x += V y
+    for (int i = k - 1; i >= 0; --i) {
+      cd acc = g[i];
+      for (int t = i + 1; t < k; ++t) acc -= hH[(size_t)t * ldh + i] * hy[t];
+      cd dd = hH[(size_t)i * ldh + i];
+      hy[i] = (cabs2(dd) > 0) ? cdiv(acc, dd) : cd{0.0, 0.0};
+    }
+    GRT_HIP(c, hipMemcpyAsync(c->d_y, hy, sizeof(cd) * k, hipMemcpyHostToDevice, s));
     axpy_basis_kernel<<<gridn, KT, 0, s>>>(x, V, ldv, n, c->d_y, k);
     GRT_HIP(c, hipGetLastError());
+    // the host y buffer is rewritten next cycle: wait for the copy to land
+    GRT_HIP(c, hipStreamSynchronize(s));
     res->cycles += 1;
   }
   res->iters = total;

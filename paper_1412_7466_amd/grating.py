@@ -76,6 +76,8 @@ _PROTOS = {
     "grt_incident": (C.c_int, [_VP, _VP]),
     "grt_set_table": (C.c_int, [_VP, C.c_int]),
     "grt_table_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "grt_autotune": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                               C.POINTER(C.c_double)]),
     "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
     "grt_bragg": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -248,6 +250,18 @@ class Context:
         self._enter()
         self._check(self.lib.grt_set_table(self.h, int(enable)))
         self._leave()
+
+    def autotune(self, cap=16):
+        """Time the translation launch for several chunk counts and keep the
+        fastest; returns [(chunks, ms per launch)]."""
+        n = C.c_int(0)
+        ch = (C.c_int * cap)()
+        ms = (C.c_double * cap)()
+        self._enter()
+        self._check(self.lib.grt_autotune(self.h, cap, C.byref(n), ch, ms))
+        self._leave()
+        self.sizes = self.query()
+        return [(ch[i], ms[i]) for i in range(n.value)]
 
     def table_bytes(self):
         n = C.c_int64(0)

@@ -269,3 +269,21 @@ def test_resident_table_matches_oracle(torch_cuda, M, P, seed):
     assert rel(_np(beta), red.solve_lu()) < 1e-9
     ctx.set_table(False)
     assert np.array_equal(_np(ctx.apply_T(xd)), y_fly)
+
+
+@pytest.mark.parametrize("M,P,seed,table", [(67, 4, 6, False), (150, 10, 16, True)])
+def test_autotune_keeps_parity(torch_cuda, M, P, seed, table):
+    """The launch shape the autotuner picks changes only the order of the chunk sums."""
+    from oracle.solver import Reduced
+    pb = inputs.small(M, P, seed=seed)
+    red = Reduced(pb)
+    ctx = _ctx(pb)
+    if table:
+        ctx.set_table(True)
+    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    tuned = ctx.autotune()
+    say(f"[gpu] autotune M={M} P={P} table={table}: {tuned} -> {ctx.sizes.m2l_chunks} chunks")
+    assert len(tuned) >= 1
+    assert ctx.sizes.m2l_chunks in [c for c, _ in tuned]
+    assert rel(_np(ctx.apply_T(xd)), red.T_apply(xh)) < 1e-12
+    assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
