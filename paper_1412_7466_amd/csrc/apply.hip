@@ -303,7 +303,7 @@ grt_status apply_alloc(grt_ctx* c) {
     c->m2l_nchunks_cap = std::max(nc, c->m2l_nchunks);
   }
   split_work(M, (nt + 63) / 64, 2048, 4, c->c_chunk, c->c_nchunks);
-  split_work(6 * (int64_t)c->g.N, (M + 63) / 64, 1024, 16, c->b_chunk, c->b_nchunks);
+  split_work(2 * (int64_t)c->g.N, (M + 63) / 64, 1024, 8, c->b_chunk, c->b_nchunks);
   GRT_HIP(c, hipMalloc(&c->d_pT, sizeof(cd) * (size_t)c->m2l_nchunks_cap * c->n_beta));
   GRT_HIP(c, hipMalloc(&c->d_pC, sizeof(cd) * (size_t)c->c_nchunks * nt * 2));
   GRT_HIP(c, hipMalloc(&c->d_pB, sizeof(cd) * (size_t)c->b_nchunks * c->n_beta));

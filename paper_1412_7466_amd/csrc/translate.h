@@ -450,7 +450,7 @@ __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restr
     tx[1] = 1.5 * g.d;  w[1] = -g.alpha_inv;
     tx[2] = 1.5 * g.d;  w[2] = cd{0.0, 0.0};  // unused
   }
-  const int nimg = wall ? 2 : 3;
+  if (wall) w[2] = cd{0.0, 0.0};  // two-term form: the third position is not used
   const double k = g.k[1];
   cd val{0, 0}, A{0, 0}, B{0, 0};
   for (int ts = m0; ts < m1; ts += CX_TILE) {
@@ -464,47 +464,60 @@ __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restr
     __syncthreads();
     for (int mm = 0; mm < cnt; ++mm) {
       const cd* b = sx + mm * NB;
+      // the copies' (or wall terms') weights are folded into H_0, H_1, so one sum
+      // F_n = sum_im w_im H_n(k r_im) e^{i n theta_im} serves all three positions
+      cd hp[3], hc[3], e[3], ep[3];
+      double rz2[3];
 #pragma unroll
       for (int im = 0; im < 3; ++im) {
-        if (im >= nimg) break;
-        double vx = tx[im] - scx[mm], vy = ty - scy[mm];
-        double r = sqrt(vx * vx + vy * vy);
-        double z = k * r;
-        double ir = 1.0 / r;
-        cd e{vx * ir, vy * ir};
-        cd hprev, hcur;
-        hankel01_tab(z, stab, hprev, hcur);
-        cd sv{0, 0}, sa{0, 0}, sb{0, 0};
-        cmac(sv, hprev, b[P]);
-        if (P >= 1) {
-          cmac(sa, hprev, b[P + 1]);
-          cmac(sb, hprev, b[P - 1]);
-        }
-        cd ep = e;
-        double rz2 = 2.0 / z;
+        const double vx = tx[im] - scx[mm], vy = ty - scy[mm];
+        const double r = sqrt(vx * vx + vy * vy);
+        const double z = k * r;
+        const double ir = 1.0 / r;
+        e[im] = cd{vx * ir, vy * ir};
+        ep[im] = e[im];
+        rz2[im] = 2.0 / z;
+        cd h0, h1;
+        hankel01_tab(z, stab, h0, h1);
+        hp[im] = w[im] * h0;
+        hc[im] = w[im] * h1;
+      }
+      const cd F0 = hp[0] + hp[1] + hp[2];
+      cmac(val, F0, b[P]);
+      if (P >= 1) {
+        cmac(A, F0, b[P + 1]);
+        cmac(B, F0, b[P - 1]);
+      }
 #pragma unroll
-        for (int mo = 1; mo <= P + 1; ++mo) {
-          cd Fp = hcur * ep;                 // F_mo
-          cd Fm = hcur * conj(ep);           // F_{-mo} = (-1)^mo H_mo e^{-i mo theta}
-          if (mo & 1) Fm = -Fm;
-          if (mo <= P) {
-            cmac(sv, Fp, b[P + mo]);
-            cmac(sv, Fm, b[P - mo]);
-          }
-          if (mo + 1 <= P) cmac(sa, Fp, b[P + mo + 1]);
-          if (1 - mo >= -P) cmac(sa, Fm, b[P + 1 - mo]);
-          if (mo - 1 <= P) cmac(sb, Fp, b[P + mo - 1]);
-          if (-mo - 1 >= -P) cmac(sb, Fm, b[P - mo - 1]);
-          if (mo <= P) {
-            cd hn = (mo * rz2) * hcur - hprev;
-            hprev = hcur;
-            hcur = hn;
-            ep = ep * e;
+      for (int mo = 1; mo <= P + 1; ++mo) {
+        cd Fp{0, 0}, Fm{0, 0};  // F_mo and F_{-mo} = (-1)^mo sum H_mo e^{-i mo theta}
+#pragma unroll
+        for (int im = 0; im < 3; ++im) {
+          const double ac = hc[im].r * ep[im].r, bd = hc[im].i * ep[im].i;
+          const double ad = hc[im].r * ep[im].i, bc = hc[im].i * ep[im].r;
+          Fp.r += ac - bd;
+          Fp.i += ad + bc;
+          Fm.r += ac + bd;
+          Fm.i += bc - ad;
+        }
+        if (mo & 1) Fm = -Fm;
+        if (mo <= P) {
+          cmac(val, Fp, b[P + mo]);
+          cmac(val, Fm, b[P - mo]);
+        }
+        if (mo + 1 <= P) cmac(A, Fp, b[P + mo + 1]);
+        if (1 - mo >= -P) cmac(A, Fm, b[P + 1 - mo]);
+        if (mo - 1 <= P) cmac(B, Fp, b[P + mo - 1]);
+        if (-mo - 1 >= -P) cmac(B, Fm, b[P - mo - 1]);
+        if (mo <= P) {
+#pragma unroll
+          for (int im = 0; im < 3; ++im) {
+            const cd hn = (mo * rz2[im]) * hc[im] - hp[im];
+            hp[im] = hc[im];
+            hc[im] = hn;
+            ep[im] = ep[im] * e[im];
           }
         }
-        val += w[im] * sv;
-        A += w[im] * sa;
-        B += w[im] * sb;
       }
     }
   }
@@ -552,62 +565,81 @@ __device__ inline void cx_reduce_block(const DevGeom& g, const cd* partial, int 
 
 // Incoming coefficients at inclusion j from the interface densities (P2L, Graf's
 // theorem for H_0 about c_j):
-//   alpha_j[n] += (i/4) hs alpha^l [G_n sigma - (ik/2)(G_{n-1} + G_{n+1}) mu],
-//   G_n = H_n(k|v|) e^{-in theta_v}, v = node copy - c_j,
+//   alpha_j[n] += (i/4) hs sum_l alpha^l [G^l_n sigma - (ik/2)(G^l_{n-1} + G^l_{n+1}) mu],
+//   G^l_n = H_n(k|v_l|) e^{-in theta_l}, v_l = node + l d e_x - c_j,
 // the mu term being d/dy of the sigma term (gradient identity).  Sources: 2 lines x
-// N nodes x 3 copies = 6N node-copies, chunked over blockIdx.y.  Each G_m is used
-// as soon as it is generated: it feeds acc[m] (sigma) and acc[m -+ 1] (mu).
+// N nodes, chunked over blockIdx.y; the three copies of a node share its densities,
+// so their generators are summed (weights alpha^l folded into H_0, H_1) before the
+// contraction.  Each order m of the sum feeds acc[m] (sigma) and acc[m -+ 1] (mu).
 template <int P>
 __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restrict__ cx,
-                                                const double* __restrict__ cy,
-                                                const cd* __restrict__ w, cd* partial, int chunk,
-                                                const double* __restrict__ htab, int bx_, int by_) {
+                                         const double* __restrict__ cy,
+                                         const cd* __restrict__ w, cd* partial, int chunk,
+                                         const double* __restrict__ htab, int bx_, int by_) {
   constexpr int NB = 2 * P + 1;
   __shared__ double stab[HTAB_SIZE];
   for (int i = threadIdx.x; i < HTAB_SIZE; i += 64) stab[i] = htab[i];
   __syncthreads();
   const int j = bx_ * blockDim.x + threadIdx.x;
   const int s0 = by_ * chunk;
-  const int s1 = min(6 * g.N, s0 + chunk);
+  const int s1 = min(2 * g.N, s0 + chunk);
   const bool live = j < g.M;
   const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
   const double k = g.k[1];
+  const cd wl[3] = {g.alpha_inv, cd{1.0, 0.0}, g.alpha};
   cd acc[NB];
 #pragma unroll
   for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
   for (int sidx = s0; sidx < s1; ++sidx) {
-    const int line = sidx / (3 * g.N);
-    const int rem = sidx - line * 3 * g.N;
-    const int l = rem / g.N - 1;
-    const int i = rem - (l + 1) * g.N;
-    const double sxp = -0.5 * g.d + (i + 0.5) * g.hs + l * g.d;
+    const int line = sidx / g.N;
+    const int i = sidx - line * g.N;
+    const double sx0 = -0.5 * g.d + (i + 0.5) * g.hs;
     const double syp = line == 0 ? g.h : -g.h;
     const cd mu = w[g.col_off[line == 0 ? CB_MU1 : CB_MU2] + i];
     const cd sg = w[g.col_off[line == 0 ? CB_SIG1 : CB_SIG2] + i];
-    const cd ph = (l == 0) ? cd{1.0, 0.0} : (l > 0 ? g.alpha : g.alpha_inv);
-    const cd pre = times_i((0.25 * g.hs) * ph);        // (i/4) hs alpha^l
+    const cd pre = times_i(cd{0.25 * g.hs, 0.0});     // (i/4) hs
     const cd csig = pre * sg;
-    const cd cmu = pre * times_i((-0.5 * k) * mu);     // -(ik/2) mu (i/4) hs alpha^l
-    const double vx = sxp - xj, vy = syp - yj;
-    const double r = sqrt(vx * vx + vy * vy);
-    const double z = k * r;
-    const double ir = 1.0 / r;
-    const cd e{vx * ir, vy * ir};
-    const cd ec = conj(e);
-    cd hprev, hcur;
-    hankel01_tab(z, stab, hprev, hcur);
-    // order 0: G_0 = H_0 -> acc[0] (sigma), acc[+-1] (mu)
-    cmac(acc[P], csig, hprev);
-    if (P >= 1) {
-      cmac(acc[P + 1], cmu, hprev);
-      cmac(acc[P - 1], cmu, hprev);
+    const cd cmu = pre * times_i((-0.5 * k) * mu);     // -(ik/2) mu (i/4) hs
+    cd hp[3], hc[3], ec[3], ep[3];
+    double rz2[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double vx = sx0 + (l - 1) * g.d - xj, vy = syp - yj;
+      const double r = sqrt(vx * vx + vy * vy);
+      const double z = k * r;
+      const double ir = 1.0 / r;
+      ec[l] = cd{vx * ir, -vy * ir};  // e^{-i theta}
+      ep[l] = ec[l];
+      rz2[l] = 2.0 / z;
+      cd h0, h1;
+      hankel01_tab(z, stab, h0, h1);
+      hp[l] = wl[l] * h0;
+      hc[l] = wl[l] * h1;
+      // one copy after another: keeps the table reads of the copies from being
+      // scheduled together (register peak)
+      asm volatile("" ::: "memory");
     }
-    cd ep = ec, em = e;
-    const double rz2 = 2.0 / z;
+    // order 0: G_0 -> acc[0] (sigma), acc[+-1] (mu)
+    const cd G0 = hp[0] + hp[1] + hp[2];
+    cmac(acc[P], csig, G0);
+    if (P >= 1) {
+      cmac(acc[P + 1], cmu, G0);
+      cmac(acc[P - 1], cmu, G0);
+    }
 #pragma unroll
     for (int m = 1; m <= P + 1; ++m) {
-      const cd Gp = hcur * ep;                                  // G_m = H_m e^{-im theta}
-      const cd Gm = (m & 1) ? -(hcur * em) : hcur * em;        // G_{-m} = (-1)^m H_m e^{im theta}
+      // G_m = sum H_m e^{-im theta}, G_{-m} = (-1)^m sum H_m e^{im theta}
+      cd Gp{0, 0}, Gm{0, 0};
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const double ac = hc[l].r * ep[l].r, bd = hc[l].i * ep[l].i;
+        const double ad = hc[l].r * ep[l].i, bc = hc[l].i * ep[l].r;
+        Gp.r += ac - bd;
+        Gp.i += ad + bc;
+        Gm.r += ac + bd;
+        Gm.i += bc - ad;
+      }
+      if (m & 1) Gm = -Gm;
       if (m <= P) {
         cmac(acc[P + m], csig, Gp);
         cmac(acc[P - m], csig, Gm);
@@ -618,11 +650,13 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
       if (1 - m >= -P) cmac(acc[P + 1 - m], cmu, Gm);
       if (-m - 1 >= -P) cmac(acc[P - m - 1], cmu, Gm);
       if (m <= P) {
-        const cd hn = (m * rz2) * hcur - hprev;
-        hprev = hcur;
-        hcur = hn;
-        ep = ep * ec;
-        em = em * e;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const cd hn = (m * rz2[l]) * hc[l] - hp[l];
+          hp[l] = hc[l];
+          hc[l] = hn;
+          ep[l] = ep[l] * ec[l];
+        }
       }
     }
   }
@@ -633,8 +667,6 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
   }
 }
 
-// L2L: out[j][n] = sum_q a2_q E_j[q - n], E_j[m] = J_m(k2 rho_j) e^{i m phi_j}.
-// One block per inclusion: its E_j row and a2 are staged in LDS.
 __device__ inline void l2l_block(int M, int P, int Q2, const cd* __restrict__ E,
                                                  const cd* __restrict__ a2, cd* out, int bx_) {
   extern __shared__ cd l2l_smem[];
