@@ -31,6 +31,73 @@ sys.path.insert(0, ROOT)
 METRIC = "solves/s at 1e-9 resid, plain FP64 vs mixed+batched+warm-start; matvec %peak"
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "m2l_table_traffic_m1000.md")
+KERNEL_SOURCES = ["translate.h", "apply.hip", "dev_bessel.h", "dev_common.h"]
+
+
+def kernel_source_hash():
+    """sha256 over the sources the translation kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_7466_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    when there is none or the kernel sources changed since it was taken."""
+    import re
+    if not os.path.exists(TRAFFIC_MD):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_MD).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel") != kernel or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def record_traffic(fetch_db, write_db, kernel, copy_bytes, commands):
+    """Write the counter summary: FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the
+    kernel, each scaled by what the same counter reads for the plain device copy of
+    copy_bytes bytes in the same run."""
+    import sqlite3
+    import statistics
+
+    def per_dispatch(db, counter):
+        """(median over the kernel's dispatches, largest copy dispatch) of a counter."""
+        con = sqlite3.connect(db)
+        cur = con.execute("select * from counters_collection")
+        cols = [d[0] for d in cur.description]
+        name_c = next(c for c in ("kernel_name", "name") if c in cols)
+        rows = [dict(zip(cols, r)) for r in cur.fetchall()]
+        rows = [r for r in rows if r.get("counter_name") == counter]
+        kern = [r["value"] for r in rows if kernel.split("<")[0] in r[name_c]]
+        copy = [r["value"] for r in rows if "copy" in r[name_c].lower()]
+        return statistics.median(kern), max(copy)
+    kf, cf = per_dispatch(fetch_db, "FETCH_SIZE")
+    kw, cw = per_dispatch(write_db, "WRITE_SIZE")
+    sf = copy_bytes / (cf * 1024.0)
+    sw = copy_bytes / (cw * 1024.0)
+    rec = {"kernel": kernel, "source_sha256": kernel_source_hash(),
+           "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
+           "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": sf, "write_scale": sw,
+           "hbm_bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw}
+    with open(TRAFFIC_MD, "w") as f:
+        f.write("# HBM traffic of the resident-table translation kernel, M=1000, P=15\n\n")
+        f.write("Two rocprofv3 counter runs of the benchmark (table mode, default launch shape) "
+                "with a plain device copy of known size appended; each counter is scaled by "
+                "what it reads for the copy.\n\nCommands (repository root, one MI355X):\n\n")
+        for cmd in commands:
+            f.write(f"```\n{cmd}\n```\n\n")
+        f.write(f"FETCH_SIZE {kf:.1f} KiB per dispatch (copy of {copy_bytes} B: {cf:.1f} KiB); "
+                f"WRITE_SIZE {kw:.1f} KiB per dispatch (copy: {cw:.1f} KiB).\n\n")
+        f.write("```json\n" + json.dumps(rec) + "\n```\n")
+    return rec
 
 
 def cpu_baseline(pb, iters, n_sample=96):
@@ -142,8 +209,21 @@ def main():
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="end with a plain device copy of this size (counter calibration)")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write the traffic summary from two counter runs and exit")
     ap.add_argument("--sweep-n", type=int, default=8)
     a = ap.parse_args()
+    if a.traffic_record:
+        cmds = [f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc {c} --kernel-include-regex "
+                f"'m2l_table_kernel|copyBuffer' -d $REPO/gpurun_out/pmc_{c.lower()} -o run -- "
+                f"python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-sweep "
+                f"--no-autotune --copy-probe-mib 1024" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+        print(json.dumps(record_traffic(a.traffic_record[0], a.traffic_record[1],
+                                        "m2l_table_kernel<15>", 1024 * 1024 * 1024, cmds)))
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); "
               "a sharded solve across GPUs is not built", file=sys.stderr)
@@ -183,7 +263,7 @@ def main():
         return beta, iters, resid, elapsed, ms / max(launches, 1), launches
 
     # 1. generator evaluated on the fly (launch shape chosen by the autotuner)
-    tune_f = ctx.autotune()
+    tune_f = None if a.no_autotune else ctx.autotune()
     beta_f, iters_f, resid_f, el_f, avg_f, n_f = timed_solves()
     ach_f = flops / (avg_f * 1e-3) / 1e12
     roof_f = {"bound": "alu", "achieved": ach_f, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -195,7 +275,7 @@ def main():
     ctx.set_table(True)
     torch.cuda.synchronize()
     t_table = time.perf_counter() - t0
-    tune_t = ctx.autotune()
+    tune_t = None if a.no_autotune else ctx.autotune()
     beta_t, iters_t, resid_t, el_t, avg_t, n_t = timed_solves()
     tbytes = 16.0 * M * M * (4 * P + 1)            # generator table, one read per pair
     xbytes = 16.0 * M * NB                        # coefficients in
@@ -204,7 +284,8 @@ def main():
     bytes_t = tbytes + xbytes + obytes
     gbs = bytes_t / (avg_t * 1e-3) / 1e9
     roof_t = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": f"m2l_table_kernel<{P}>",
+              "frac": gbs / HBM_PEAK_GBS, "traffic": committed_traffic(f"m2l_table_kernel<{P}>"),
+              "kernel": f"m2l_table_kernel<{P}>",
               "avg_launch_ms": avg_t, "launches": n_t, "bytes_per_launch": bytes_t,
               "flops_per_launch": flops, "tflops": flops / (avg_t * 1e-3) / 1e12,
               "autotune_chunks_ms": tune_t}
@@ -263,6 +344,12 @@ def main():
     }
     if not a.no_sweep:
         res["sweep"] = sweep(a, torch)
+    if a.copy_probe_mib > 0:
+        src = torch.ones(a.copy_probe_mib * 131072, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(pb, iters[-1])
     print(json.dumps(res), flush=True)

@@ -97,6 +97,10 @@ typedef struct {
                       well-separated inclusions runs in FP32 (FP32 accumulate)  */
   double inner_tol;/* GRT_FP32: relative tolerance of each inner solve (0: 1e-5) */
   int max_refine;  /* GRT_FP32: most refinement steps (0: 10)                */
+  int use_graph;   /* 1: every apply of K is replayed from a HIP graph captured
+                      once per operator (dropped when the table, the launch
+                      shape or the problem changes); ignored while kernel
+                      timing (grt_profile_enable) is on.  Same results.        */
 } grt_solve_opts;
 
 typedef struct {

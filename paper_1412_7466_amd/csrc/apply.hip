@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(64) table_build_kernel(const double* __restric
 }
 
 template <int P>
-__global__ void __launch_bounds__(64) cx_kernel(DevGeom g, const double* __restrict__ cx,
+__global__ void __launch_bounds__(64 * CX_WAVES) cx_kernel(DevGeom g, const double* __restrict__ cx,
                                                 const double* __restrict__ cy,
                                                 const cd* __restrict__ x, cd* partial, int chunk,
                                                 const double* __restrict__ htab) {
@@ -72,36 +72,66 @@ __global__ void __launch_bounds__(256) cx_reduce_kernel(DevGeom g, const cd* par
 }
 
 template <int P>
-__global__ void __launch_bounds__(64) bx_kernel(DevGeom g, const double* __restrict__ cx,
+__global__ void __launch_bounds__(64 * BX_WAVES) bx_kernel(DevGeom g, const double* __restrict__ cx,
                                                 const double* __restrict__ cy,
                                                 const cd* __restrict__ w, cd* partial, int chunk,
                                                 const double* __restrict__ htab) {
   bx_block<P>(g, cx, cy, w, partial, chunk, htab, blockIdx.x, blockIdx.y);
 }
 
-__global__ void __launch_bounds__(64) l2l_kernel(int M, int P, int Q2, const cd* __restrict__ E,
+__global__ void __launch_bounds__(256) l2l_kernel(int M, int P, int Q2, const cd* __restrict__ E,
                                                  const cd* __restrict__ a2, cd* out) {
   l2l_block(M, P, Q2, E, a2, out, blockIdx.x);
 }
 
-// y = x - s o (sum_c pT[c] - sum_c pB[c] - pL); any of the parts may be absent.
-__global__ void combine_kernel(int nbeta, const cd* x, const cd* s, const cd* pT, int nT,
-                               const cd* pB, int nB, const cd* pL, cd* y, int mode) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbeta) return;
-  cd t{0, 0}, b{0, 0};
-  for (int c = 0; c < nT; ++c) t += pT[(size_t)c * nbeta + i];
-  for (int c = 0; c < nB; ++c) b += pB[(size_t)c * nbeta + i];
+// Sum of the partial results of entry i: each block takes 64 entries, its four
+// waves a quarter of the chunks each, added in a fixed order through LDS.
+constexpr int CMB_ENTRIES = 64;
+template <typename TT>
+__device__ __forceinline__ cd chunk_sum(const TT* part, int nch, size_t stride, int64_t i, int grp,
+                                        bool live) {
+  cd acc{0, 0};
+  if (live)
+    for (int c = grp; c < nch; c += 4) {
+      const TT v = part[(size_t)c * stride + i];
+      acc.r += v.r;
+      acc.i += v.i;
+    }
+  return acc;
+}
+
+__device__ __forceinline__ cd group_total(cd v, cd* red, int lane, int grp) {
+  red[grp * CMB_ENTRIES + lane] = v;
+  __syncthreads();
+  cd t = red[lane];
+  for (int g2 = 1; g2 < 4; ++g2) t += red[g2 * CMB_ENTRIES + lane];
+  __syncthreads();
+  return t;
+}
+
+// y = x - s o (sum_c pT[c] - sum_c pB[c] - pL)   (mode 0, full K)
+// y = sum_c pT[c]                                (mode 1, T x)
+// y = sum_c pB[c] + pL                           (mode 2, B_phys A^+ C x, or alpha0)
+// y = s o (sum_c pB[c] + pL)                     (mode 3, right-hand side)
+// then y *= oscale when given.  Any of the parts may be absent.
+__global__ void __launch_bounds__(256) combine_kernel(int nbeta, const cd* x, const cd* s,
+                                                      const cd* pT, int nT, const cd* pB, int nB,
+                                                      const cd* pL, cd* y, int mode,
+                                                      const double* oscale) {
+  __shared__ cd red[4 * CMB_ENTRIES];
+  const int lane = threadIdx.x & (CMB_ENTRIES - 1), grp = threadIdx.x / CMB_ENTRIES;
+  const int64_t i = (int64_t)blockIdx.x * CMB_ENTRIES + lane;
+  const bool live = i < nbeta;
+  const cd t = group_total(chunk_sum(pT, nT, nbeta, i, grp, live), red, lane, grp);
+  cd b = group_total(chunk_sum(pB, nB, nbeta, i, grp, live), red, lane, grp);
+  if (grp != 0 || !live) return;
   if (pL) b += pL[i];
-  if (mode == 0) {  // full K
-    y[i] = x[i] - s[i] * (t - b);
-  } else if (mode == 1) {  // T x only
-    y[i] = t;
-  } else if (mode == 2) {  // B A^+ C x only
-    y[i] = b;
-  } else {  // rhs: s o (B part)
-    y[i] = s[i] * b;
-  }
+  cd v;
+  if (mode == 0) v = x[i] - s[i] * (t - b);
+  else if (mode == 1) v = t;
+  else if (mode == 2) v = b;
+  else v = s[i] * b;
+  y[i] = oscale ? oscale[i] * v : v;
 }
 
 // Event pair for timing one translation launch (when profiling is on).
@@ -172,19 +202,21 @@ __global__ void to_f32_kernel(const cd* x, cf* y, int n) {
 }
 
 // y = x - s o ((sum_c pT32[c] + pN) - sum_c pB[c] - pL): the mixed-precision apply.
-__global__ void combine_mixed_kernel(int nbeta, const cd* x, const cd* s, const cf* pT, int nT,
-                                     const cd* pN, const cd* pB, int nB, const cd* pL, cd* y) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbeta) return;
-  cd t = pN[i];
-  for (int c = 0; c < nT; ++c) {
-    cf v = pT[(size_t)c * nbeta + i];
-    t.r += v.r;
-    t.i += v.i;
-  }
-  cd b = pL[i];
-  for (int c = 0; c < nB; ++c) b += pB[(size_t)c * nbeta + i];
-  y[i] = x[i] - s[i] * (t - b);
+__global__ void __launch_bounds__(256) combine_mixed_kernel(int nbeta, const cd* x, const cd* s,
+                                                            const cf* pT, int nT, const cd* pN,
+                                                            const cd* pB, int nB, const cd* pL,
+                                                            cd* y, const double* oscale) {
+  __shared__ cd red[4 * CMB_ENTRIES];
+  const int lane = threadIdx.x & (CMB_ENTRIES - 1), grp = threadIdx.x / CMB_ENTRIES;
+  const int64_t i = (int64_t)blockIdx.x * CMB_ENTRIES + lane;
+  const bool live = i < nbeta;
+  cd t = group_total(chunk_sum(pT, nT, nbeta, i, grp, live), red, lane, grp);
+  cd b = group_total(chunk_sum(pB, nB, nbeta, i, grp, live), red, lane, grp);
+  if (grp != 0 || !live) return;
+  t += pN[i];
+  b += pL[i];
+  const cd v = x[i] - s[i] * (t - b);
+  y[i] = oscale ? oscale[i] * v : v;
 }
 
 // Near-pair lists: pairs (j, m) with some kept copy at k rho < zsafe.
@@ -234,14 +266,14 @@ template <int P>
 void launch_cx(grt_ctx* c, const cd* x) {
   const int nt = 2 * c->g.N + c->g.Nw[1];
   dim3 grid((nt + 63) / 64, c->c_nchunks);
-  cx_kernel<P><<<grid, 64, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, x, c->d_pC, c->c_chunk,
+  cx_kernel<P><<<grid, 64 * CX_WAVES, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, x, c->d_pC, c->c_chunk,
                                             c->d_htab);
 }
 
 template <int P>
 void launch_bx(grt_ctx* c, const cd* w) {
   dim3 grid((unsigned)((c->M + 63) / 64), c->b_nchunks);
-  bx_kernel<P><<<grid, 64, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, w, c->d_pB, c->b_chunk,
+  bx_kernel<P><<<grid, 64 * BX_WAVES, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, w, c->d_pB, c->b_chunk,
                                            c->d_htab);
 }
 
@@ -302,8 +334,9 @@ grt_status apply_alloc(grt_ctx* c) {
     split_work(M, (M + 63) / 64, M2L_TUNE_MAX_WAVES / M2L_WAVES, 4 * M2L_WAVES, ch, nc);
     c->m2l_nchunks_cap = std::max(nc, c->m2l_nchunks);
   }
-  split_work(M, (nt + 63) / 64, 2048, 4, c->c_chunk, c->c_nchunks);
-  split_work(2 * (int64_t)c->g.N, (M + 63) / 64, 1024, 8, c->b_chunk, c->b_nchunks);
+  split_work(M, (nt + 63) / 64, 2048 / CX_WAVES, 4 * CX_WAVES, c->c_chunk, c->c_nchunks);
+  split_work(2 * (int64_t)c->g.N, (M + 63) / 64, 2048 / BX_WAVES, 2 * BX_WAVES, c->b_chunk,
+             c->b_nchunks);
   GRT_HIP(c, hipMalloc(&c->d_pT, sizeof(cd) * (size_t)c->m2l_nchunks_cap * c->n_beta));
   GRT_HIP(c, hipMalloc(&c->d_pC, sizeof(cd) * (size_t)c->c_nchunks * nt * 2));
   GRT_HIP(c, hipMalloc(&c->d_pB, sizeof(cd) * (size_t)c->b_nchunks * c->n_beta));
@@ -348,10 +381,9 @@ static grt_status lowrank_tail(grt_ctx* c, const cd* gvec) {
   launch_gemv_rows(s, c->d_W2, c->d_tvec, c->d_wvec, c->n_b, c->rank);
   GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec);
   {
-    const int L = c->g.Q[1] + c->P;
-    size_t sh = sizeof(cd) * (size_t)(2 * L + 1 + 2 * c->g.Q[1] + 1);
-    l2l_kernel<<<(unsigned)c->M, 64, sh, s>>>((int)c->M, c->P, c->g.Q[1], c->d_l2l,
-                                             c->d_wvec + c->g.col_off[CB_A2], c->d_pL);
+    const size_t sh = sizeof(cd) * (size_t)(2 * c->g.Q[1] + 1);
+    l2l_kernel<<<(unsigned)((c->M + L2L_TARGETS - 1) / L2L_TARGETS), 256, sh, s>>>(
+        (int)c->M, c->P, c->g.Q[1], c->d_l2l, c->d_wvec + c->g.col_off[CB_A2], c->d_pL);
   }
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
@@ -365,7 +397,8 @@ static grt_status cx_apply(grt_ctx* c, const cd* x) {
   return GRT_OK;
 }
 
-static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode) {
+static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode,
+                            const double* oscale = nullptr) {
   if (c->M == 0) return GRT_OK;
   hipStream_t s = c->stream;
   bool needT = (mode == 0 || mode == 1);
@@ -378,18 +411,20 @@ static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode) {
     if (st != GRT_OK) return st;
   }
   int n = (int)c->n_beta;
-  combine_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, x, c->d_mie, c->d_pT, needT ? c->m2l_nchunks : 0,
-                                                 c->d_pB, needB ? c->b_nchunks : 0,
-                                                 needB ? c->d_pL : nullptr, y, mode);
+  combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
+      n, x, c->d_mie, c->d_pT, needT ? c->m2l_nchunks : 0, c->d_pB, needB ? c->b_nchunks : 0,
+      needB ? c->d_pL : nullptr, y, mode, oscale);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
 
-grt_status apply_K(grt_ctx* c, const cd* x, cd* y) { return run_apply(c, x, y, 0); }
+grt_status apply_K(grt_ctx* c, const cd* x, cd* y, const double* oscale) {
+  return run_apply(c, x, y, 0, oscale);
+}
 
 // K32 x: FP32 translation between well-separated pairs, FP64 for near pairs, the
 // layer correction and the preconditioner.
-grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y) {
+grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y, const double* oscale) {
   if (c->M == 0) return GRT_OK;
   hipStream_t s = c->stream;
   const int n = (int)c->n_beta;
@@ -400,9 +435,9 @@ grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y) {
   if (st != GRT_OK) return st;
   st = lowrank_tail(c, c->d_gvec);
   if (st != GRT_OK) return st;
-  combine_mixed_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, x, c->d_mie, c->d_pT32, c->m2l_nchunks,
-                                                       c->d_pN, c->d_pB, c->b_nchunks, c->d_pL,
-                                                       y);
+  combine_mixed_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
+      n, x, c->d_mie, c->d_pT32, c->m2l_nchunks, c->d_pN, c->d_pB, c->b_nchunks, c->d_pL, y,
+      oscale);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
@@ -414,8 +449,8 @@ grt_status rhs_b(grt_ctx* c, cd* b) {
   grt_status st = lowrank_tail(c, c->d_f);
   if (st != GRT_OK) return st;
   int n = (int)c->n_beta;
-  combine_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(n, nullptr, c->d_mie, nullptr, 0, c->d_pB,
-                                                         c->b_nchunks, c->d_pL, b, 3);
+  combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, c->stream>>>(
+      n, nullptr, c->d_mie, nullptr, 0, c->d_pB, c->b_nchunks, c->d_pL, b, 3, nullptr);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
@@ -428,6 +463,7 @@ size_t table_bytes(const grt_ctx* c) {
 }
 
 grt_status table_set(grt_ctx* c, bool on) {
+  graph_reset(c);
   if (c->d_table) {
     hipStreamSynchronize(c->stream);
     hipFree(c->d_table);
@@ -498,6 +534,7 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, double
   c->m2l_chunk = best_chunk;
   c->m2l_nchunks = best_n;
   c->prof = prof;
+  graph_reset(c);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   GRT_HIP(c, hipGetLastError());
@@ -512,8 +549,8 @@ grt_status incident_alpha(grt_ctx* c, cd* out) {
   grt_status st = lowrank_tail(c, c->d_f);
   if (st != GRT_OK) return st;
   int n = (int)c->n_beta;
-  combine_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(n, nullptr, c->d_mie, nullptr, 0, c->d_pB,
-                                                         c->b_nchunks, c->d_pL, out, 2);
+  combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, c->stream>>>(
+      n, nullptr, c->d_mie, nullptr, 0, c->d_pB, c->b_nchunks, c->d_pL, out, 2, nullptr);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }

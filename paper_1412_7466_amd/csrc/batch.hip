@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l_batched(const InstDesc* __res
 }
 
 template <int P>
-__global__ void __launch_bounds__(64) cx_batched(const InstDesc* __restrict__ D,
+__global__ void __launch_bounds__(64 * CX_WAVES) cx_batched(const InstDesc* __restrict__ D,
                                                  const Item* __restrict__ it,
                                                  const cd* __restrict__ X) {
   const Item w = it[blockIdx.x];
@@ -84,19 +84,32 @@ __device__ inline void gemv_rows_block(const cd* __restrict__ W, const cd* __res
   int lane = threadIdx.x & 63;
   if (row >= rows) return;
   const cd* w = W + (size_t)row * cols;
-  double ar = 0.0, ai = 0.0;
-  for (int k = lane; k < cols; k += 64) {
-    cd a = w[k], b = v[k];
-    ar = fma(a.r, b.r, ar);
-    ar = fma(-a.i, b.i, ar);
-    ai = fma(a.r, b.i, ai);
-    ai = fma(a.i, b.r, ai);
+  // four independent partial sums: four row segments in flight per lane
+  double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+  int k = lane;
+  for (; k + 192 < cols; k += 256) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const cd a = w[k + 64 * u], b = v[k + 64 * u];
+      ar[u] = fma(a.r, b.r, ar[u]);
+      ar[u] = fma(-a.i, b.i, ar[u]);
+      ai[u] = fma(a.r, b.i, ai[u]);
+      ai[u] = fma(a.i, b.r, ai[u]);
+    }
   }
+  for (; k < cols; k += 64) {
+    const cd a = w[k], b = v[k];
+    ar[0] = fma(a.r, b.r, ar[0]);
+    ar[0] = fma(-a.i, b.i, ar[0]);
+    ai[0] = fma(a.r, b.i, ai[0]);
+    ai[0] = fma(a.i, b.r, ai[0]);
+  }
+  double sr = (ar[0] + ar[1]) + (ar[2] + ar[3]), si = (ai[0] + ai[1]) + (ai[2] + ai[3]);
   for (int off = 32; off > 0; off >>= 1) {
-    ar += __shfl_xor(ar, off, 64);
-    ai += __shfl_xor(ai, off, 64);
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
   }
-  if (lane == 0) y[row] = cd{ar, ai};
+  if (lane == 0) y[row] = cd{sr, si};
 }
 
 // t = Sigma^+ U^* g (g = f for the right-hand side), then w = E V t
@@ -114,14 +127,14 @@ __global__ void __launch_bounds__(256) gemv2_batched(const InstDesc* __restrict_
 }
 
 template <int P>
-__global__ void __launch_bounds__(64) bx_batched(const InstDesc* __restrict__ D,
+__global__ void __launch_bounds__(64 * BX_WAVES) bx_batched(const InstDesc* __restrict__ D,
                                                  const Item* __restrict__ it) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
   bx_block<P>(q.g, q.cx, q.cy, q.wvec, q.pB, q.b_chunk, q.htab, w.x, w.y);
 }
 
-__global__ void __launch_bounds__(64) l2l_batched(const InstDesc* __restrict__ D,
+__global__ void __launch_bounds__(256) l2l_batched(const InstDesc* __restrict__ D,
                                                   const Item* __restrict__ it) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
@@ -427,11 +440,11 @@ static void launch_group_T(grt_batch* b, const grt_batch::Group& gp, const cd* X
 }
 template <int P>
 static void launch_group_C(grt_batch* b, const grt_batch::Group& gp, const cd* X) {
-  if (gp.n_cx) cx_batched<P><<<gp.n_cx, 64, 0, b->stream>>>(b->dd, gp.cx, X);
+  if (gp.n_cx) cx_batched<P><<<gp.n_cx, 64 * CX_WAVES, 0, b->stream>>>(b->dd, gp.cx, X);
 }
 template <int P>
 static void launch_group_B(grt_batch* b, const grt_batch::Group& gp) {
-  if (gp.n_bx) bx_batched<P><<<gp.n_bx, 64, 0, b->stream>>>(b->dd, gp.bx);
+  if (gp.n_bx) bx_batched<P><<<gp.n_bx, 64 * BX_WAVES, 0, b->stream>>>(b->dd, gp.bx);
 }
 
 // layer correction tail for all problems: t = W1 g (or f), w = W2 t, then B and L2L
@@ -440,7 +453,7 @@ static grt_status batch_lowrank(grt_batch* b, int use_f) {
   if (b->n_g1) gemv1_batched<<<b->n_g1, 256, 0, s>>>(b->dd, b->it_g1, use_f);
   if (b->n_g2) gemv2_batched<<<b->n_g2, 256, 0, s>>>(b->dd, b->it_g2);
   for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_B, gp.P, b, gp);
-  if (b->n_l2l) l2l_batched<<<b->n_l2l, 64, b->l2l_smem, s>>>(b->dd, b->it_l2l);
+  if (b->n_l2l) l2l_batched<<<b->n_l2l, 256, b->l2l_smem, s>>>(b->dd, b->it_l2l);
   BHIP(b, hipGetLastError());
   return GRT_OK;
 }
@@ -583,8 +596,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     for (int t = 0; t < q.nseg; ++t) seg2inst.push_back(i);
     seg += q.nseg;
     byP[q.P].push_back(i);
-    const int L = q.Q2 + q.P;
-    smem = std::max(smem, sizeof(cd) * (size_t)(2 * L + 1 + 2 * q.Q2 + 1));
+    smem = std::max(smem, sizeof(cd) * (size_t)(2 * q.Q2 + 1));
   }
   b->nseg = seg;
   b->ntot = (int64_t)seg * SEG;
@@ -622,7 +634,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     for (int x = 0; x < (nt + 3) / 4; ++x) cxr.push_back({i, x, 0});
     for (int x = 0; x < (q.rank + 3) / 4; ++x) g1.push_back({i, x, 0});
     for (int x = 0; x < (q.n_b + 3) / 4; ++x) g2.push_back({i, x, 0});
-    for (int x = 0; x < q.M; ++x) l2l.push_back({i, x, 0});
+    for (int x = 0; x < (q.M + L2L_TARGETS - 1) / L2L_TARGETS; ++x) l2l.push_back({i, x, 0});
   }
   // concatenated normalisation
   std::vector<double> dn(b->ntot, 0.0), di(b->ntot, 0.0);

@@ -24,6 +24,7 @@ grt_status set_err(grt_ctx* c, grt_status s, const std::string& msg) {
 namespace {
 
 void free_all(grt_ctx* c) {
+  graph_reset(c);
   if (c->lf) {  // layer-side buffers belong to the shared factors
     c->d_yw = c->d_colscale = c->d_sv = c->d_htab = nullptr;
     c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_f = nullptr;
@@ -54,6 +55,7 @@ void free_all(grt_ctx* c) {
   c->d_ntgt = nullptr;
   c->d_npart = nullptr;
   c->d_table = nullptr;
+  c->d_wtmp = nullptr;
   c->krylov_restart = 0;
   c->built = false;
 }

@@ -119,6 +119,8 @@ struct grt_ctx {
   hipEvent_t ev_res[2] = {nullptr, nullptr};
   double* h_pinned = nullptr;
   cd* h_H = nullptr;        // pinned host mirror of H and the least-squares solution
+  cd* d_wtmp = nullptr;     // output of every apply in the solver (a slot of d_V)
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // captured applies: K, mixed K
   // kernel timing (HIP events around every translation-kernel launch)
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;  // pairs: start, stop
@@ -142,13 +144,13 @@ void launch_gemv_rows(hipStream_t s, const cd* W, const cd* x, cd* y, int rows, 
 
 // apply (apply.hip)
 bool supported_P(int P);
-grt_status apply_K(grt_ctx* c, const cd* x, cd* y);
-grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y);
+// y = K x (then y *= oscale elementwise when oscale is given)
+grt_status apply_K(grt_ctx* c, const cd* x, cd* y, const double* oscale = nullptr);
+grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y, const double* oscale = nullptr);
 grt_status apply_T_only(grt_ctx* c, const cd* x, cd* y);
 grt_status apply_lowrank_only(grt_ctx* c, const cd* x, cd* y);
 grt_status rhs_b(grt_ctx* c, cd* b);
 grt_status incident_alpha(grt_ctx* c, cd* out);
-grt_status lowrank_from_g(grt_ctx* c, cd* pB_out_sum_into, bool mult_s, const cd* x, cd* y);
 grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out_cd /* device [2 Nrb] */);
 grt_status apply_alloc(grt_ctx* c);
 grt_status table_set(grt_ctx* c, bool on);
@@ -157,4 +159,5 @@ constexpr int M2L_TUNE_MAX_WAVES = 8192;
 size_t table_bytes(const grt_ctx* c);
 
 // krylov (krylov.hip)
+void graph_reset(grt_ctx* c);   // drop captured applies (their configuration changed)
 grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_stats* st);

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "grt_internal.h"
@@ -116,20 +117,32 @@ __global__ void axpy_basis_kernel(cd* x, const cd* __restrict__ V, size_t ldv, i
   x[i] = acc;
 }
 
-// w /= ||w|| with ||w|| from the norm partials (every block redoes the short sum in
-// the same order); block 0 also stores it as H[j+1][j].
-__global__ void __launch_bounds__(KT) norm_scale_kernel(cd* w, int n, const double* npart, int nblk,
-                                                         cd* hsub) {
+// vout = w / ||w|| with ||w|| from the norm partials (every block redoes the short
+// sum in the same order); block 0 also stores it as H[j+1][j].  xpre = dinv o vout
+// (the unnormalised input of the next apply).
+__global__ void __launch_bounds__(KT) norm_scale_kernel(const cd* w, cd* vout, int n,
+                                                         const double* npart, int nblk, cd* hsub,
+                                                         const double* dinv, cd* xpre) {
   double s2 = 0.0;
   for (int b = 0; b < nblk; ++b) s2 += npart[b];
   const double hn = sqrt(s2);
   if (blockIdx.x == 0 && threadIdx.x == 0) *hsub = cd{hn, 0.0};
   int i = blockIdx.x * KT + threadIdx.x;
   if (i >= n) return;
-  if (hn > 0) w[i] = (1.0 / hn) * w[i];
+  const cd v = hn > 0 ? (1.0 / hn) * w[i] : w[i];
+  vout[i] = v;
+  xpre[i] = dinv[i] * v;
 }
 
 }  // namespace
+
+void graph_reset(grt_ctx* c) {
+  for (hipGraphExec_t& g : c->graph_exec)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
 
 static grt_status ensure_workspace(grt_ctx* c, int m) {
   if (c->krylov_restart == m && c->d_V) return GRT_OK;
@@ -138,7 +151,9 @@ static grt_status ensure_workspace(grt_ctx* c, int m) {
   const size_t n = (size_t)c->n_beta;
   c->n_dot_blocks = (int)std::min<size_t>(16, (n + KT * 4 - 1) / (KT * 4));
   if (c->n_dot_blocks < 1) c->n_dot_blocks = 1;
-  GRT_HIP(c, hipMalloc(&c->d_V, sizeof(cd) * n * (m + 4)));
+  graph_reset(c);  // captured applies point into the workspace
+  GRT_HIP(c, hipMalloc(&c->d_V, sizeof(cd) * n * (m + 5)));
+  c->d_wtmp = c->d_V + n * (m + 4);
   GRT_HIP(c, hipMalloc(&c->d_H, sizeof(cd) * (size_t)(m + 1) * (m + 1)));
   GRT_HIP(c, hipMalloc(&c->d_y, sizeof(cd) * (m + 1)));
   GRT_HIP(c, hipMalloc(&c->d_scal, sizeof(double) * (16 + c->n_dot_blocks)));
@@ -183,7 +198,7 @@ __global__ void add_vec_kernel(cd* x, const cd* e, int n) {
   if (i < n) x[i] = x[i] + e[i];
 }
 
-typedef grt_status (*KOp)(grt_ctx*, const cd*, cd*);
+typedef grt_status (*KOp)(grt_ctx*, const cd*, cd*, const double*);
 
 // y = d o x (elementwise; y may alias x)
 __global__ void dscale_kernel(const cd* x, const double* d, cd* y, int n) {
@@ -193,19 +208,39 @@ __global__ void dscale_kernel(const cd* x, const double* d, cd* y, int n) {
 
 // The normalised operators D K D^{-1} (D = |H_|n|(k2 R_m)|, a diagonal similarity
 // that keeps the reduced system well conditioned when high-order coefficients are
-// tiny): scale the input by D^{-1}, apply, scale the output by D.
-static grt_status apply_hat(grt_ctx* c, KOp op, const cd* xh, cd* y) {
-  const int n = (int)c->n_beta;
-  const int gridn = (n + KT - 1) / KT;
-  dscale_kernel<<<gridn, KT, 0, c->stream>>>(xh, c->d_dinv, c->d_xtmp, n);
-  grt_status st = op(c, c->d_xtmp, y);
-  if (st != GRT_OK) return st;
-  dscale_kernel<<<gridn, KT, 0, c->stream>>>(y, c->d_dnorm, y, n);
+// tiny).  Every apply reads D^{-1} x from d_xtmp and writes D K D^{-1} x to d_wtmp,
+// fixed buffers, so with use_graph the kernel sequence of one apply is captured once
+// as a HIP graph (per operator) and replayed; the graphs are dropped whenever the
+// apply's configuration changes (graph_reset).
+static grt_status apply_step(grt_ctx* c, KOp op, bool use_graph) {
+  if (!use_graph || c->prof) return op(c, c->d_xtmp, c->d_wtmp, c->d_dnorm);
+  hipGraphExec_t* ge = (op == apply_K) ? &c->graph_exec[0] : &c->graph_exec[1];
+  if (!*ge) {
+    hipGraph_t gr = nullptr;
+    GRT_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    grt_status st = op(c, c->d_xtmp, c->d_wtmp, c->d_dnorm);
+    hipError_t e = hipStreamEndCapture(c->stream, &gr);
+    if (st != GRT_OK || e != hipSuccess) {
+      if (gr) hipGraphDestroy(gr);
+      return st != GRT_OK ? st
+                          : set_err(c, GRT_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(ge, gr, nullptr, nullptr, 0);
+    hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+      *ge = nullptr;
+      return set_err(c, GRT_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+  }
+  GRT_HIP(c, hipGraphLaunch(*ge, c->stream));
   return GRT_OK;
 }
-static grt_status apply_K_hat(grt_ctx* c, const cd* x, cd* y) { return apply_hat(c, apply_K, x, y); }
-static grt_status apply_K_mixed_hat(grt_ctx* c, const cd* x, cd* y) {
-  return apply_hat(c, apply_K_mixed, x, y);
+
+// d_wtmp = D K D^{-1} xh
+static grt_status apply_hat(grt_ctx* c, KOp op, const cd* xh, bool use_graph) {
+  const int n = (int)c->n_beta;
+  dscale_kernel<<<(n + KT - 1) / KT, KT, 0, c->stream>>>(xh, c->d_dinv, c->d_xtmp, n);
+  return apply_step(c, op, use_graph);
 }
 
 struct CoreResult {
@@ -218,7 +253,7 @@ struct CoreResult {
 // Restarted GMRES for op(x) = b from the iterate in x (updated in place).  b must not
 // live in basis slots 0..m.  Stops at ||b - op x|| <= tol ||b|| or after maxit steps.
 static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double tol, int maxit,
-                             int m, CoreResult* res, bool guard_x0 = false) {
+                             int m, CoreResult* res, bool guard_x0, bool use_graph) {
   const int n = (int)c->n_beta;
   hipStream_t s = c->stream;
   const size_t ldv = (size_t)n;
@@ -267,8 +302,8 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
   };
   while (true) {
     // r = b - op x into V_0
-    GRT_TRY(op(c, x, V + ldv));  // temp in slot 1
-    sub_vec_kernel<<<gridn, KT, 0, s>>>(bvec, V + ldv, V, n);
+    GRT_TRY(apply_hat(c, op, x, use_graph));
+    sub_vec_kernel<<<gridn, KT, 0, s>>>(bvec, c->d_wtmp, V, n);
     GRT_TRY(vec_norm(c, V, n, d_beta));
     double beta = 0.0;
     GRT_TRY(read_scalar(c, d_beta, &beta));
@@ -292,8 +327,12 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
     int queued = 0;
     bool conv = false;
     for (int j = 0; j < m && total + queued < maxit; ++j) {
-      cd* w = V + (size_t)(j + 1) * ldv;
-      GRT_TRY(op(c, V + (size_t)j * ldv, w));
+      cd* w = c->d_wtmp;  // the new direction; normalised into V_{j+1} below
+      // from the second step on, the previous step left D^{-1} V_j in d_xtmp
+      if (j == 0)
+        GRT_TRY(apply_hat(c, op, V, use_graph));
+      else
+        GRT_TRY(apply_step(c, op, use_graph));
       cd* hcol = c->d_H + (size_t)j * ldh;
       for (int pass = 0; pass < 2; ++pass) {
         dim3 gd(nblk, j + 1);
@@ -301,7 +340,8 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
         update_kernel<<<gridn, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, nblk, j + 1, hcol, pass);
       }
       norm2_kernel<<<nblk, KT, 0, s>>>(w, n, d_npart, nblk);
-      norm_scale_kernel<<<gridn, KT, 0, s>>>(w, n, d_npart, nblk, hcol + j + 1);
+      norm_scale_kernel<<<gridn, KT, 0, s>>>(w, V + (size_t)(j + 1) * ldv, n, d_npart, nblk,
+                                             hcol + j + 1, c->d_dinv, c->d_xtmp);
       GRT_HIP(c, hipGetLastError());
       GRT_HIP(c, hipMemcpyAsync(hH + (size_t)j * ldh, hcol, sizeof(cd) * (j + 2),
                                 hipMemcpyDeviceToHost, s));
@@ -343,6 +383,7 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
   const int maxit = o->maxit > 0 ? o->maxit : 1000;
   const double tol = o->tol > 0 ? o->tol : 1e-9;
   GRT_TRY(ensure_workspace(c, m));
+  const bool graph = o->use_graph != 0;
   hipStream_t s = c->stream;
   const size_t ldv = (size_t)n;
   const int gridn = (n + KT - 1) / KT;
@@ -359,7 +400,7 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
   *st = grt_solve_stats{};
   CoreResult r;
   if (o->precision == GRT_FP64) {
-    GRT_TRY(gmres_core(c, apply_K_hat, bvec, x, tol, maxit, m, &r, o->use_x0 != 0));
+    GRT_TRY(gmres_core(c, apply_K, bvec, x, tol, maxit, m, &r, o->use_x0 != 0, graph));
     st->x0_rejected = r.x0_rejected ? 1 : 0;
     st->iters = r.iters;
     st->cycles = r.cycles;
@@ -379,8 +420,8 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
     double rel = 1.0;
     bool conv = false;
     for (int outer = 0; outer <= max_ref; ++outer) {
-      GRT_TRY(apply_K_hat(c, x, rvec));
-      sub_vec_kernel<<<gridn, KT, 0, s>>>(bvec, rvec, rvec, n);
+      GRT_TRY(apply_hat(c, apply_K, x, graph));
+      sub_vec_kernel<<<gridn, KT, 0, s>>>(bvec, c->d_wtmp, rvec, n);
       GRT_TRY(vec_norm(c, rvec, n, d_rn));
       double rn = 0.0;
       GRT_TRY(read_scalar(c, d_rn, &rn));
@@ -396,7 +437,7 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
       if (rel <= tol) { conv = true; break; }
       if (outer == max_ref || total >= maxit) break;
       GRT_HIP(c, hipMemsetAsync(evec, 0, sizeof(cd) * n, s));
-      GRT_TRY(gmres_core(c, apply_K_mixed_hat, rvec, evec, itol, maxit - total, m, &r));
+      GRT_TRY(gmres_core(c, apply_K_mixed, rvec, evec, itol, maxit - total, m, &r, false, graph));
       total += r.iters;
       cycles += r.cycles;
       add_vec_kernel<<<gridn, KT, 0, s>>>(x, evec, n);

@@ -504,19 +504,32 @@ __global__ void __launch_bounds__(256) gemv_rows_kernel(const cd* __restrict__ W
   int lane = threadIdx.x & 63;
   if (wave >= rows) return;
   const cd* w = W + (size_t)wave * cols;
-  double ar = 0.0, ai = 0.0;
-  for (int k = lane; k < cols; k += 64) {
-    cd a = w[k], b = x[k];
-    ar = fma(a.r, b.r, ar);
-    ar = fma(-a.i, b.i, ar);
-    ai = fma(a.r, b.i, ai);
-    ai = fma(a.i, b.r, ai);
+  // four independent partial sums: four row segments in flight per lane
+  double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+  int k = lane;
+  for (; k + 192 < cols; k += 256) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const cd a = w[k + 64 * u], b = x[k + 64 * u];
+      ar[u] = fma(a.r, b.r, ar[u]);
+      ar[u] = fma(-a.i, b.i, ar[u]);
+      ai[u] = fma(a.r, b.i, ai[u]);
+      ai[u] = fma(a.i, b.r, ai[u]);
+    }
   }
+  for (; k < cols; k += 64) {
+    const cd a = w[k], b = x[k];
+    ar[0] = fma(a.r, b.r, ar[0]);
+    ar[0] = fma(-a.i, b.i, ar[0]);
+    ai[0] = fma(a.r, b.i, ai[0]);
+    ai[0] = fma(a.i, b.r, ai[0]);
+  }
+  double sr = (ar[0] + ar[1]) + (ar[2] + ar[3]), si = (ai[0] + ai[1]) + (ai[2] + ai[3]);
   for (int off = 32; off > 0; off >>= 1) {
-    ar += __shfl_xor(ar, off, 64);
-    ai += __shfl_xor(ai, off, 64);
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
   }
-  if (lane == 0) y[wave] = cd{ar, ai};
+  if (lane == 0) y[wave] = cd{sr, si};
 }
 
 // One thread per interval of the H_0, H_1 interpolation table.

@@ -73,12 +73,15 @@ __device__ __forceinline__ void pair_generate(double dx, double dy, double k, do
       if (q <= 2 * P) {
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
-          double ac = hc[l].r * cq[l].r, bd = hc[l].i * cq[l].i;
-          double ad = hc[l].r * cq[l].i, bc = hc[l].i * cq[l].r;
-          sp.r += ac - bd;
-          sp.i += ad + bc;
-          sm.r += ac + bd;
-          sm.i += bc - ad;
+          // sp += hc cq, sm += hc conj(cq), as FMAs
+          sp.r = fma(hc[l].r, cq[l].r, sp.r);
+          sp.r = fma(-hc[l].i, cq[l].i, sp.r);
+          sp.i = fma(hc[l].r, cq[l].i, sp.i);
+          sp.i = fma(hc[l].i, cq[l].r, sp.i);
+          sm.r = fma(hc[l].r, cq[l].r, sm.r);
+          sm.r = fma(hc[l].i, cq[l].i, sm.r);
+          sm.i = fma(hc[l].i, cq[l].r, sm.i);
+          sm.i = fma(-hc[l].r, cq[l].i, sm.i);
         }
         if (q & 1) sm = -sm;  // H_{-q} = (-1)^q H_q
         if (q < 2 * P) {
@@ -279,6 +282,12 @@ __device__ __forceinline__ void table_build_block(const double* __restrict__ cx,
   }
 }
 
+// Streaming read of one table entry: each entry is used exactly once per apply, so
+// it is loaded non-temporally (it should not displace the reused data in the caches).
+__device__ __forceinline__ cd ld_stream(const cd* p) {
+  return cd{__builtin_nontemporal_load(&p->r), __builtin_nontemporal_load(&p->i)};
+}
+
 // Same result as m2l_block in FP64, with the generator read from the resident
 // table (the next block of orders is loaded while the current one is contracted).
 template <int P>
@@ -315,7 +324,7 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
       const cd* b = sx + mm * NB;
       const cd* col = table + (size_t)(ts + mm) * NQ * Mpad + j;
       {
-        const cd t0 = col[(size_t)(2 * P) * Mpad];
+        const cd t0 = ld_stream(col + (size_t)(2 * P) * Mpad);
 #pragma unroll
         for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
       }
@@ -323,8 +332,8 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
 #pragma unroll
       for (int u = 0; u < M2L_QB; ++u) {
         const int q = 1 + u;
-        np[u] = q <= 2 * P ? col[(size_t)(2 * P + q) * Mpad] : cd{0, 0};
-        nm[u] = q <= 2 * P ? col[(size_t)(2 * P - q) * Mpad] : cd{0, 0};
+        np[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P + q) * Mpad) : cd{0, 0};
+        nm[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P - q) * Mpad) : cd{0, 0};
       }
 #pragma unroll
       for (int qb = 0; qb < NQB; ++qb) {
@@ -338,8 +347,8 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
 #pragma unroll
           for (int u = 0; u < M2L_QB; ++u) {
             const int q = 1 + (qb + 1) * M2L_QB + u;
-            np[u] = q <= 2 * P ? col[(size_t)(2 * P + q) * Mpad] : cd{0, 0};
-            nm[u] = q <= 2 * P ? col[(size_t)(2 * P - q) * Mpad] : cd{0, 0};
+            np[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P + q) * Mpad) : cd{0, 0};
+            nm[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P - q) * Mpad) : cd{0, 0};
           }
         }
         contract_block<P, cd>(acc, b, qb, tp, tm);
@@ -407,7 +416,8 @@ static __global__ void near_reduce_kernel(const int* __restrict__ noff, const cd
   out[idx] = s;
 }
 
-constexpr int CX_TILE = 32;  // inclusions staged in LDS at a time
+constexpr int CX_WAVES = 4;   // waves per block: same 64 targets, sources split 4 ways
+constexpr int CX_TILE = 8;    // inclusions staged in LDS at a time, per wave
 
 // Field of all multipoles (and their copies) at the C targets, one per lane:
 //   target t < N: Gamma_1 node, t < 2N: Gamma_2 node (value, d/dy over 3 copies),
@@ -416,21 +426,34 @@ constexpr int CX_TILE = 32;  // inclusions staged in LDS at a time
 // With F_n = H_n(k r) e^{in theta}: value = sum x[n] F_n and, by
 // (d_x +- i d_y) F_n = -+ k F_{n+-1}, d/dx = (k/2)(A - B), d/dy = (ik/2)(A + B)
 // with A = sum x[n] F_{n-1}, B = sum x[n] F_{n+1}.
-// partial[chunk][t][0..1] = (value, derivative) over the chunk's inclusions.
+// partial[chunk][t][0..1] = (value, derivative) over the chunk's inclusions.  A block
+// has CX_WAVES waves on the same 64 targets, each taking a share of the chunk's
+// sources; the H_0/H_1 table is staged once per block and the waves' sums are added
+// through LDS in a fixed order.
 template <int P>
 __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restrict__ cx,
-                                                const double* __restrict__ cy,
-                                                const cd* __restrict__ x, cd* partial, int chunk,
-                                                const double* __restrict__ htab, int bx_, int by_) {
+                                         const double* __restrict__ cy,
+                                         const cd* __restrict__ x, cd* partial, int chunk,
+                                         const double* __restrict__ htab, int bx_, int by_) {
   constexpr int NB = 2 * P + 1;
-  __shared__ cd sx[CX_TILE * NB];
-  __shared__ double scx[CX_TILE], scy[CX_TILE];
+  __shared__ cd sx_all[CX_WAVES * CX_TILE * NB];
+  __shared__ double sc_all[CX_WAVES * 2 * CX_TILE];
   __shared__ double stab[HTAB_SIZE];
+  __shared__ cd red[CX_WAVES * 64 * 3];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  cd* sx = sx_all + wv * CX_TILE * NB;
+  double* scx = sc_all + wv * 2 * CX_TILE;
+  double* scy = scx + CX_TILE;
   const int nt = 2 * g.N + g.Nw[1];
-  const int t = bx_ * blockDim.x + threadIdx.x;
-  const int m0 = by_ * chunk;
-  const int m1 = min(g.M, m0 + chunk);
-  for (int i = threadIdx.x; i < HTAB_SIZE; i += 64) stab[i] = htab[i];
+  const int t = bx_ * 64 + lane;
+  const int c0 = by_ * chunk;
+  const int c1 = min(g.M, c0 + chunk);
+  const int per = (c1 - c0 + CX_WAVES - 1) / CX_WAVES;
+  const int m0 = c0 + wv * per;
+  const int m1 = min(c1, m0 + per);
+  const int ntile = (per + CX_TILE - 1) / CX_TILE;  // same for every wave: barriers match
+  for (int i = threadIdx.x; i < HTAB_SIZE; i += blockDim.x) stab[i] = htab[i];
   const bool live = t < nt;
   const int tt = live ? t : 0;
   double tx[3], ty;
@@ -453,11 +476,12 @@ __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restr
   if (wall) w[2] = cd{0.0, 0.0};  // two-term form: the third position is not used
   const double k = g.k[1];
   cd val{0, 0}, A{0, 0}, B{0, 0};
-  for (int ts = m0; ts < m1; ts += CX_TILE) {
-    const int cnt = min(CX_TILE, m1 - ts);
+  for (int it = 0; it < ntile; ++it) {
+    const int ts = m0 + it * CX_TILE;
+    const int cnt = max(0, min(CX_TILE, m1 - ts));
     __syncthreads();
-    for (int i = threadIdx.x; i < cnt * NB; i += 64) sx[i] = x[(size_t)ts * NB + i];
-    for (int i = threadIdx.x; i < cnt; i += 64) {
+    for (int i = lane; i < cnt * NB; i += 64) sx[i] = x[(size_t)ts * NB + i];
+    for (int i = lane; i < cnt; i += 64) {
       scx[i] = cx[ts + i];
       scy[i] = cy[ts + i];
     }
@@ -493,12 +517,14 @@ __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restr
         cd Fp{0, 0}, Fm{0, 0};  // F_mo and F_{-mo} = (-1)^mo sum H_mo e^{-i mo theta}
 #pragma unroll
         for (int im = 0; im < 3; ++im) {
-          const double ac = hc[im].r * ep[im].r, bd = hc[im].i * ep[im].i;
-          const double ad = hc[im].r * ep[im].i, bc = hc[im].i * ep[im].r;
-          Fp.r += ac - bd;
-          Fp.i += ad + bc;
-          Fm.r += ac + bd;
-          Fm.i += bc - ad;
+          Fp.r = fma(hc[im].r, ep[im].r, Fp.r);
+          Fp.r = fma(-hc[im].i, ep[im].i, Fp.r);
+          Fp.i = fma(hc[im].r, ep[im].i, Fp.i);
+          Fp.i = fma(hc[im].i, ep[im].r, Fp.i);
+          Fm.r = fma(hc[im].r, ep[im].r, Fm.r);
+          Fm.r = fma(hc[im].i, ep[im].i, Fm.r);
+          Fm.i = fma(hc[im].i, ep[im].r, Fm.i);
+          Fm.i = fma(-hc[im].r, ep[im].i, Fm.i);
         }
         if (mo & 1) Fm = -Fm;
         if (mo <= P) {
@@ -521,7 +547,16 @@ __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restr
       }
     }
   }
-  if (!live) return;
+  red[(wv * 64 + lane) * 3 + 0] = val;
+  red[(wv * 64 + lane) * 3 + 1] = A;
+  red[(wv * 64 + lane) * 3 + 2] = B;
+  __syncthreads();
+  if (wv != 0 || !live) return;
+  for (int v = 1; v < CX_WAVES; ++v) {
+    val += red[(v * 64 + lane) * 3 + 0];
+    A += red[(v * 64 + lane) * 3 + 1];
+    B += red[(v * 64 + lane) * 3 + 2];
+  }
   cd der = wall ? (0.5 * k) * (A - B) : times_i((0.5 * k) * (A + B));
   cd* o = partial + ((size_t)by_ * nt + t) * 2;
   o[0] = val;
@@ -571,6 +606,7 @@ __device__ inline void cx_reduce_block(const DevGeom& g, const cd* partial, int 
 // N nodes, chunked over blockIdx.y; the three copies of a node share its densities,
 // so their generators are summed (weights alpha^l folded into H_0, H_1) before the
 // contraction.  Each order m of the sum feeds acc[m] (sigma) and acc[m -+ 1] (mu).
+constexpr int BX_WAVES = 4;  // waves per block: same 64 targets, nodes split 4 ways
 template <int P>
 __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restrict__ cx,
                                          const double* __restrict__ cy,
@@ -578,11 +614,17 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
                                          const double* __restrict__ htab, int bx_, int by_) {
   constexpr int NB = 2 * P + 1;
   __shared__ double stab[HTAB_SIZE];
-  for (int i = threadIdx.x; i < HTAB_SIZE; i += 64) stab[i] = htab[i];
+  __shared__ cd red[NB * 64];
+  for (int i = threadIdx.x; i < HTAB_SIZE; i += blockDim.x) stab[i] = htab[i];
   __syncthreads();
-  const int j = bx_ * blockDim.x + threadIdx.x;
-  const int s0 = by_ * chunk;
-  const int s1 = min(2 * g.N, s0 + chunk);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int j = bx_ * 64 + lane;
+  const int c0 = by_ * chunk;
+  const int c1 = min(2 * g.N, c0 + chunk);
+  const int per = (c1 - c0 + BX_WAVES - 1) / BX_WAVES;
+  const int s0 = c0 + wv * per;
+  const int s1 = min(c1, s0 + per);
   const bool live = j < g.M;
   const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
   const double k = g.k[1];
@@ -632,12 +674,14 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
       cd Gp{0, 0}, Gm{0, 0};
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
-        const double ac = hc[l].r * ep[l].r, bd = hc[l].i * ep[l].i;
-        const double ad = hc[l].r * ep[l].i, bc = hc[l].i * ep[l].r;
-        Gp.r += ac - bd;
-        Gp.i += ad + bc;
-        Gm.r += ac + bd;
-        Gm.i += bc - ad;
+        Gp.r = fma(hc[l].r, ep[l].r, Gp.r);
+        Gp.r = fma(-hc[l].i, ep[l].i, Gp.r);
+        Gp.i = fma(hc[l].r, ep[l].i, Gp.i);
+        Gp.i = fma(hc[l].i, ep[l].r, Gp.i);
+        Gm.r = fma(hc[l].r, ep[l].r, Gm.r);
+        Gm.r = fma(hc[l].i, ep[l].i, Gm.r);
+        Gm.i = fma(hc[l].i, ep[l].r, Gm.i);
+        Gm.i = fma(-hc[l].r, ep[l].i, Gm.i);
       }
       if (m & 1) Gm = -Gm;
       if (m <= P) {
@@ -660,31 +704,48 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
       }
     }
   }
-  if (live) {
+  // the waves' sums through LDS: wave 3, then 2, then 1 add into the buffer in
+  // turn, wave 0 adds its own and stores
+  for (int src = BX_WAVES - 1; src >= 1; --src) {
+    __syncthreads();
+    if (wv == src) {
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        cd v = acc[n];
+        if (src != BX_WAVES - 1) v += red[n * 64 + lane];
+        red[n * 64 + lane] = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (wv == 0 && live) {
     cd* out = partial + ((size_t)by_ * g.M + j) * NB;
 #pragma unroll
-    for (int n = 0; n < NB; ++n) out[n] = acc[n];
+    for (int n = 0; n < NB; ++n) out[n] = acc[n] + red[n * 64 + lane];
   }
 }
 
+// L2L of the middle-layer J expansion (coefficients a2, orders -Q2..Q2) to the
+// incoming coefficients of four targets per 256-thread block, one wave per target,
+// one lane per order n:
+//   out[j][n] = sum_q a2_q E_j[q - n],  E_j[m] = J_m(k2 rho_j) e^{i m phi_j},
+// E_j stored at offset L = Q2 + P.  a2 is staged in LDS (extern shared, 2 Q2 + 1).
+constexpr int L2L_TARGETS = 4;
 __device__ inline void l2l_block(int M, int P, int Q2, const cd* __restrict__ E,
-                                                 const cd* __restrict__ a2, cd* out, int bx_) {
+                                 const cd* __restrict__ a2, cd* out, int bx_) {
   extern __shared__ cd l2l_smem[];
-  const int j = bx_;
   const int NB = 2 * P + 1;
   const int L = Q2 + P;
-  cd* se = l2l_smem;               // 2L + 1
-  cd* sa = l2l_smem + 2 * L + 1;   // 2 Q2 + 1
-  const cd* e = E + (size_t)j * (2 * L + 1);
-  for (int i = threadIdx.x; i < 2 * L + 1; i += blockDim.x) se[i] = e[i];
-  for (int i = threadIdx.x; i < 2 * Q2 + 1; i += blockDim.x) sa[i] = a2[i];
+  for (int i = threadIdx.x; i < 2 * Q2 + 1; i += blockDim.x) l2l_smem[i] = a2[i];
   __syncthreads();
-  for (int nn = threadIdx.x; nn < NB; nn += blockDim.x) {
-    const int n = nn - P;
-    cd acc{0, 0};
-    for (int q = -Q2; q <= Q2; ++q) cmac(acc, sa[q + Q2], se[L + q - n]);
-    out[(size_t)j * NB + nn] = acc;
-  }
+  const int j = bx_ * L2L_TARGETS + (threadIdx.x >> 6);
+  const int nn = threadIdx.x & 63;
+  if (j >= M || nn >= NB) return;
+  const int n = nn - P;
+  const cd* e = E + (size_t)j * (2 * L + 1) + L - n;
+  cd acc{0, 0};
+  for (int q = -Q2; q <= Q2; ++q) cmac(acc, l2l_smem[q + Q2], e[q]);
+  out[(size_t)j * NB + nn] = acc;
 }
 
 

@@ -41,7 +41,7 @@ class grt_incidence(C.Structure):
 class grt_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("restart", C.c_int),
                 ("use_x0", C.c_int), ("precision", C.c_int), ("inner_tol", C.c_double),
-                ("max_refine", C.c_int)]
+                ("max_refine", C.c_int), ("use_graph", C.c_int)]
 
 
 class grt_solve_stats(C.Structure):
@@ -277,12 +277,13 @@ class Context:
         return a
 
     def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, out=None, check=True,
-              precision=GRT_FP64, inner_tol=1e-5, max_refine=10):
+              precision=GRT_FP64, inner_tol=1e-5, max_refine=10, graph=False):
         beta = self.new_vec() if out is None else out
         if x0 is not None:
             beta.copy_(x0)
         opts = grt_solve_opts(tol=tol, maxit=maxit, restart=restart, use_x0=int(x0 is not None),
-                              precision=precision, inner_tol=inner_tol, max_refine=max_refine)
+                              precision=precision, inner_tol=inner_tol, max_refine=max_refine,
+                              use_graph=int(graph))
         stats = grt_solve_stats()
         self._enter()
         st = self.lib.grt_solve(self.h, C.byref(opts), self._vec_ptr(beta), C.byref(stats))

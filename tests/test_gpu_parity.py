@@ -287,3 +287,33 @@ def test_autotune_keeps_parity(torch_cuda, M, P, seed, table):
     assert ctx.sizes.m2l_chunks in [c for c, _ in tuned]
     assert rel(_np(ctx.apply_T(xd)), red.T_apply(xh)) < 1e-12
     assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+
+
+def test_graph_replayed_solves_match_eager(torch_cuda):
+    """Solves whose applies replay a captured HIP graph equal the eager solves, on
+    every replay, with eager work and synchronisations between the replays, across a
+    change of translation mode (which drops and re-captures the graph) and for the
+    mixed-precision operator."""
+    from oracle.solver import Reduced
+    from paper_1412_7466_amd.grating import GRT_FP32
+    pb = inputs.small(40, 10, seed=12)
+    red = Reduced(pb)
+    ctx = _ctx(pb)
+    xh, xd = _randvec(torch_cuda, red.G.n_beta, 12, 10)
+    beta_o = red.solve_lu()
+    for table in (False, True, False):
+        ctx.set_table(table)
+        b_eager, s_eager = ctx.solve(tol=1e-12, restart=150)
+        y_eager = _np(ctx.apply(xd))
+        for rep in range(3):
+            b_g, s_g = ctx.solve(tol=1e-12, restart=150, graph=True)
+            torch_cuda.cuda.synchronize()
+            assert s_g.iters == s_eager.iters
+            assert rel(_np(b_g), _np(b_eager)) < 1e-14, (table, rep)
+            assert rel(_np(ctx.apply(xd)), y_eager) == 0.0   # eager work between replays
+        assert rel(_np(b_g), beta_o) < 1e-9
+    bm, sm = ctx.solve(tol=1e-12, restart=150, precision=GRT_FP32)
+    for rep in range(2):
+        bg, sg = ctx.solve(tol=1e-12, restart=150, precision=GRT_FP32, graph=True)
+        assert sg.iters == sm.iters and sg.refine_steps == sm.refine_steps
+        assert rel(_np(bg), _np(bm)) < 1e-14
