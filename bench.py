@@ -76,17 +76,21 @@ def record_traffic(fetch_db, write_db, kernel, copy_bytes, commands):
         rows = [dict(zip(cols, r)) for r in cur.fetchall()]
         rows = [r for r in rows if r.get("counter_name") == counter]
         kern = [r["value"] for r in rows if kernel.split("<")[0] in r[name_c]]
-        copy = [r["value"] for r in rows if "copy" in r[name_c].lower()]
-        return statistics.median(kern), max(copy)
+        copy = [r for r in rows if "copy" in r[name_c].lower()]
+        big = max(copy, key=lambda r: r["value"])
+        per_dispatch.copy_us = (big["end"] - big["start"]) / 1e3
+        return statistics.median(kern), big["value"]
     kf, cf = per_dispatch(fetch_db, "FETCH_SIZE")
     kw, cw = per_dispatch(write_db, "WRITE_SIZE")
+    copy_gbs = 2.0 * copy_bytes / (per_dispatch.copy_us * 1e-6) / 1e9
     sf = copy_bytes / (cf * 1024.0)
     sw = copy_bytes / (cw * 1024.0)
     rec = {"kernel": kernel, "source_sha256": kernel_source_hash(),
            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
            "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": sf, "write_scale": sw,
-           "hbm_bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw}
+           "hbm_bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw,
+           "copy_read_write_GBps": copy_gbs}
     with open(TRAFFIC_MD, "w") as f:
         f.write("# HBM traffic of the resident-table translation kernel, M=1000, P=15\n\n")
         f.write("Two rocprofv3 counter runs of the benchmark (table mode, default launch shape) "
@@ -95,7 +99,8 @@ def record_traffic(fetch_db, write_db, kernel, copy_bytes, commands):
         for cmd in commands:
             f.write(f"```\n{cmd}\n```\n\n")
         f.write(f"FETCH_SIZE {kf:.1f} KiB per dispatch (copy of {copy_bytes} B: {cf:.1f} KiB); "
-                f"WRITE_SIZE {kw:.1f} KiB per dispatch (copy: {cw:.1f} KiB).\n\n")
+                f"WRITE_SIZE {kw:.1f} KiB per dispatch (copy: {cw:.1f} KiB).  The copy itself "
+                f"moved {2 * copy_bytes} B (read + write) at {copy_gbs:.0f} GB/s.\n\n")
         f.write("```json\n" + json.dumps(rec) + "\n```\n")
     return rec
 
@@ -289,6 +294,18 @@ def main():
               "avg_launch_ms": avg_t, "launches": n_t, "bytes_per_launch": bytes_t,
               "flops_per_launch": flops, "tflops": flops / (avg_t * 1e-3) / 1e12,
               "autotune_chunks_ms": tune_t}
+    # the same table contracted with two lanes per target (for comparison)
+    ctx.set_table(2)
+    if not a.no_autotune:
+        ctx.autotune()
+    _, _, _, el_t1, avg_t1, n_t1 = timed_solves()
+    gbs1 = bytes_t / (avg_t1 * 1e-3) / 1e9
+    roof_t1 = {"bound": "hbm", "achieved": gbs1, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": gbs1 / HBM_PEAK_GBS, "kernel": f"m2l_table2_kernel<{P}>",
+               "avg_launch_ms": avg_t1, "launches": n_t1, "solves_per_s": a.steps / el_t1}
+    ctx.set_table(1)
+    if tune_t is not None:
+        ctx.autotune()
     use_table = el_t < el_f
     beta = beta_t if use_table else beta_f
     iters, resid = (iters_t, resid_t) if use_table else (iters_f, resid_f)
@@ -341,6 +358,7 @@ def main():
         "roofline": roof_t if use_table else roof_f,
         "roofline_on_the_fly": roof_f,
         "roofline_table": roof_t,
+        "roofline_table_two_lanes": roof_t1,
     }
     if not a.no_sweep:
         res["sweep"] = sweep(a, torch)

@@ -157,12 +157,15 @@ grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision
  * eq. repre3_mod), does not depend on beta, so it can be built once per problem
  * (M * Mpad * (4P+1) complex FP64, Mpad = M rounded up to 64: 1.0 GB at M = 1000,
  * P = 15) and streamed by every apply instead of re-evaluating the Hankel functions.
- * enable = 1 builds it now (if built) and after every later grt_build; 0 frees it
- * and the apply evaluates the generator on the fly again.  Results agree with the
- * on-the-fly apply to rounding.  GRT_ENOMEM if it does not fit in free device
- * memory with 1 GiB to spare (the context stays usable, without the table).
- * The mixed-precision apply and batched solves always evaluate on the fly. */
-grt_status grt_set_table(grt_ctx* ctx, int enable);
+ * mode 1 builds it now (if built) and after every later grt_build, and contracts it
+ * with one lane per target; mode 2 is the same table contracted with two lanes per
+ * target (each lane half of the 2P+1 outputs, using the reflection symmetry of the
+ * Toeplitz product: more waves per SIMD, but twice the load instructions; kept for
+ * comparison); 0 frees it and the apply evaluates the generator on the fly again.  Results agree with the on-the-fly apply to rounding.
+ * GRT_ENOMEM if it does not fit in free device memory with 1 GiB to spare (the
+ * context stays usable, without the table).  The mixed-precision apply and batched
+ * solves always evaluate on the fly. */
+grt_status grt_set_table(grt_ctx* ctx, int mode);
 /* Launch-shape autotuner of the translation kernel: times the launch for source
  * chunk counts giving 256 .. 8192 work-groups, in the current mode (on the fly or
  * resident table), and keeps the fastest for every later apply of this context

@@ -40,11 +40,19 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restri
 }
 
 template <int P>
-__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(P <= 15 ? 2 : 1, P <= 15 ? 2 : 1))) m2l_table_kernel(const cd* __restrict__ table,
+__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(P <= 15 ? 2 : 1, 8))) m2l_table_kernel(const cd* __restrict__ table,
                                                                 const cd* __restrict__ x,
                                                                 cd* partial, int M, int Mpad,
                                                                 int chunk) {
   m2l_table_block<P>(table, x, partial, M, Mpad, chunk, blockIdx.x, blockIdx.y);
+}
+
+template <int P>
+__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(P <= 15 ? 3 : 1, 8))) m2l_table2_kernel(const cd* __restrict__ table,
+                                                                 const cd* __restrict__ x,
+                                                                 cd* partial, int M, int Mpad,
+                                                                 int chunk) {
+  m2l_table2_block<P>(table, x, partial, M, Mpad, chunk, blockIdx.x, blockIdx.y);
 }
 
 template <int P>
@@ -154,7 +162,11 @@ void launch_m2l(grt_ctx* c, const cd* x) {
   dim3 grid((unsigned)((c->M + 63) / 64), c->m2l_nchunks);
   hipEvent_t* ev = prof_pair(c);
   if (ev) hipEventRecord(ev[0], c->stream);
-  if (c->d_table)
+  if (c->d_table && c->table_lanes == 2) {
+    dim3 grid2((unsigned)((c->M + 31) / 32), c->m2l_nchunks);
+    m2l_table2_kernel<P><<<grid2, M2L_THREADS, 0, c->stream>>>(c->d_table, x, c->d_pT, (int)c->M,
+                                                               c->table_mpad, c->m2l_chunk);
+  } else if (c->d_table)
     m2l_table_kernel<P><<<grid, M2L_THREADS, 0, c->stream>>>(c->d_table, x, c->d_pT, (int)c->M,
                                                              c->table_mpad, c->m2l_chunk);
   else

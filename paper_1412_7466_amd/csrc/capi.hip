@@ -262,9 +262,11 @@ grt_status grt_build(grt_ctx* c) {
   return GRT_OK;
 }
 
-grt_status grt_set_table(grt_ctx* c, int enable) {
+grt_status grt_set_table(grt_ctx* c, int mode) {
   GRT_CHECK_CTX(c);
-  c->want_table = enable != 0;
+  if (mode < 0 || mode > 2) return set_err(c, GRT_EINVAL, "table mode must be 0, 1 or 2");
+  c->want_table = mode != 0;
+  c->table_lanes = mode == 2 ? 2 : 1;
   if (!c->built) return GRT_OK;
   return table_set(c, c->want_table);
 }

@@ -108,6 +108,7 @@ struct grt_ctx {
   bool want_table = false;
   cd* d_table = nullptr;    // [M][4P+1][Mpad]
   int table_mpad = 0;
+  int table_lanes = 1;      // lanes per target in the table kernel (1 or 2)
   // GMRES workspace
   int krylov_restart = 0;
   cd* d_V = nullptr;        // [restart+1][n_beta]

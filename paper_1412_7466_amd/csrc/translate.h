@@ -12,6 +12,12 @@ constexpr int M2L_WAVES = 4;     // waves per block: same 64 targets, sources sp
 constexpr int M2L_THREADS = 64 * M2L_WAVES;
 constexpr int M2L_TILE = 16;     // sources staged in LDS at a time, per wave
 constexpr int M2L_QB = 4;        // generator orders produced per block of the contraction
+#ifndef M2L_TNUG
+#define M2L_TNUG 2               // coefficients read ahead in the table kernel's contraction
+#endif
+#ifndef M2L_TDIST
+#define M2L_TDIST 2              // blocks of table orders in flight in the table kernel
+#endif
 
 __device__ inline __attribute__((always_inline)) void cmac(cf& acc, cf a, cf b) {
   acc.r = fmaf(a.r, b.r, acc.r);
@@ -104,7 +110,7 @@ __device__ __forceinline__ void pair_generate(double dx, double dy, double k, do
 // acc[n] += sum over the block's orders q of tau_q x[n+q] + tau_{-q} x[n-q]
 // (n = -P..P at index n + P); each x[nu] is read once per block and feeds up to
 // 2 M2L_QB complex FMAs.
-template <int P, typename T, typename BP>
+template <int P, typename T, typename BP, int NUG = 1 << 20>
 __device__ __forceinline__ void contract_block(T* acc, BP b, int qb, const T* tp, const T* tm) {
   constexpr int NB = 2 * P + 1;
   // x may be re-read here: keeps x[nu] out of registers across blocks of orders
@@ -119,6 +125,8 @@ __device__ __forceinline__ void contract_block(T* acc, BP b, int qb, const T* tp
     }
     if (!need) continue;
     const T bv = b[nu];
+    // with NUG set, at most NUG coefficients are read ahead of their use
+    if (nu % NUG == NUG - 1) asm volatile("" ::: "memory");
 #pragma unroll
     for (int u = 0; u < M2L_QB; ++u) {
       const int q = 1 + qb * M2L_QB + u;
@@ -178,7 +186,7 @@ __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
   __shared__ double smem[BUF];
   __shared__ double stab[HTAB_SIZE];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   T* sx = reinterpret_cast<T*>(smem) + wv * M2L_TILE * NB;
   double* scx = smem + TW * M2L_WAVES * M2L_TILE * NB + wv * 2 * M2L_TILE;
   double* scy = scx + M2L_TILE;
@@ -302,7 +310,7 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
   constexpr int BUF = STAGE > RED ? STAGE : RED;
   __shared__ double smem[BUF];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   cd* sx = reinterpret_cast<cd*>(smem) + wv * M2L_TILE * NB;
   const int j = bx_ * 64 + lane;  // < Mpad: table rows of dead lanes are zero
   const int m0 = by_ * chunk;
@@ -314,6 +322,8 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
   cd acc[NB];
 #pragma unroll
   for (int n = 0; n < NB; ++n) acc[n] = cd{0, 0};
+  // table row of order q for source m: a wave-uniform base plus the lane's target
+  auto row = [&](const cd* col, int q) { return ld_stream(col + (size_t)(2 * P + q) * Mpad + j); };
   for (int it = 0; it < ntile; ++it) {
     const int ts = s0 + it * M2L_TILE;
     const int cnt = max(0, min(M2L_TILE, s1 - ts));
@@ -322,36 +332,40 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
     __syncthreads();
     for (int mm = 0; mm < cnt; ++mm) {
       const cd* b = sx + mm * NB;
-      const cd* col = table + (size_t)(ts + mm) * NQ * Mpad + j;
+      const cd* col = table + (size_t)(ts + mm) * NQ * Mpad;
       {
-        const cd t0 = ld_stream(col + (size_t)(2 * P) * Mpad);
+        const cd t0 = row(col, 0);
 #pragma unroll
         for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
       }
-      cd np[M2L_QB], nm[M2L_QB];
+      // blocks of orders in flight: the current one and the next M2L_TDIST - 1
+      cd np[M2L_TDIST][M2L_QB], nm[M2L_TDIST][M2L_QB];
 #pragma unroll
-      for (int u = 0; u < M2L_QB; ++u) {
-        const int q = 1 + u;
-        np[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P + q) * Mpad) : cd{0, 0};
-        nm[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P - q) * Mpad) : cd{0, 0};
-      }
+      for (int d = 0; d < M2L_TDIST; ++d)
+#pragma unroll
+        for (int u = 0; u < M2L_QB; ++u) {
+          const int q = 1 + d * M2L_QB + u;
+          np[d][u] = q <= 2 * P ? row(col, q) : cd{0, 0};
+          nm[d][u] = q <= 2 * P ? row(col, -q) : cd{0, 0};
+        }
 #pragma unroll
       for (int qb = 0; qb < NQB; ++qb) {
+        constexpr int D = M2L_TDIST;
         cd tp[M2L_QB], tm[M2L_QB];
 #pragma unroll
         for (int u = 0; u < M2L_QB; ++u) {
-          tp[u] = np[u];
-          tm[u] = nm[u];
+          tp[u] = np[qb % D][u];
+          tm[u] = nm[qb % D][u];
         }
-        if (qb + 1 < NQB) {
+        if (qb + D < NQB) {
 #pragma unroll
           for (int u = 0; u < M2L_QB; ++u) {
-            const int q = 1 + (qb + 1) * M2L_QB + u;
-            np[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P + q) * Mpad) : cd{0, 0};
-            nm[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P - q) * Mpad) : cd{0, 0};
+            const int q = 1 + (qb + D) * M2L_QB + u;
+            np[qb % D][u] = q <= 2 * P ? row(col, q) : cd{0, 0};
+            nm[qb % D][u] = q <= 2 * P ? row(col, -q) : cd{0, 0};
           }
         }
-        contract_block<P, cd>(acc, b, qb, tp, tm);
+        contract_block<P, cd, const cd*, M2L_TNUG>(acc, b, qb, tp, tm);
       }
     }
   }
@@ -372,6 +386,149 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
     cd* out = partial + ((size_t)by_ * M + j) * NB;
 #pragma unroll
     for (int n = 0; n < NB; ++n) out[n] = acc[n] + red[n * 64 + lane];
+  }
+}
+
+// Half contraction for the two-lanes-per-target table kernel: outputs n = -P..0
+// only (local index 0..P), acc[n] += sum over the block's orders of
+// tau_q x[n+q] + tau_{-q} x[n-q].
+constexpr int NU_GROUP = 2;  // coefficients read from LDS per group in the half contraction
+constexpr int T2_TILE = 8;   // sources staged per wave in the two-lanes table kernel
+template <int P, typename BP>
+__device__ __forceinline__ void contract_block_half(cd* acc, BP b, int qb, const cd* tp,
+                                                    const cd* tm) {
+  constexpr int NB = 2 * P + 1;
+  constexpr int NH = P + 1;
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int nu = 0; nu < NB; ++nu) {
+    bool need = false;
+#pragma unroll
+    for (int u = 0; u < M2L_QB; ++u) {
+      const int q = 1 + qb * M2L_QB + u;
+      if (q <= 2 * P && ((nu - q >= 0 && nu - q < NH) || nu + q < NH)) need = true;
+    }
+    if (!need) continue;
+    const cd bv = b[nu];
+    // a few coefficients in flight at a time: the LDS reads are not all hoisted
+    if (nu % NU_GROUP == NU_GROUP - 1) asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < M2L_QB; ++u) {
+      const int q = 1 + qb * M2L_QB + u;
+      if (q > 2 * P) continue;
+      if (nu - q >= 0 && nu - q < NH) cmac(acc[nu - q], tp[u], bv);
+      if (nu + q < NH) cmac(acc[nu + q], tm[u], bv);
+    }
+  }
+}
+
+// Resident-table translation with two lanes per target.  The Toeplitz contraction
+// is symmetric under reflection: with tau'_q = tau_{-q} and x'[nu] = x[-nu], the
+// outputs n = 0..P equal the outputs -n of the same contraction on (tau', x').  So
+// lane 2i computes n = -P..0 of target i and lane 2i+1 the same formula on the
+// reflected table entries and coefficients (lane-dependent addresses, identical
+// instructions), each holding P+1 accumulators instead of 2P+1; the two lanes read
+// the same table lines.  32 targets per wave, four waves splitting the sources.
+template <int P>
+__device__ __forceinline__ void m2l_table2_block(const cd* __restrict__ table,
+                                                 const cd* __restrict__ x, cd* partial, int M,
+                                                 int Mpad, int chunk, int bx_, int by_) {
+  constexpr int NB = 2 * P + 1;
+  constexpr int NH = P + 1;
+  constexpr int NQ = 4 * P + 1;
+  constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
+  constexpr int STAGE = 2 * M2L_WAVES * T2_TILE * 2 * NB;  // forward and reflected copies
+  constexpr int RED = 2 * NH * 64;
+  constexpr int BUF = STAGE > RED ? STAGE : RED;
+  __shared__ double smem[BUF];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const bool h = lane & 1;                // 0: n = -P..0, 1: n = 0..P (reflected)
+  cd* sx = reinterpret_cast<cd*>(smem) + wv * T2_TILE * 2 * NB;
+  const int j = bx_ * 32 + (lane >> 1);  // < Mpad: table rows of dead targets are zero
+  const int m0 = by_ * chunk;
+  const int m1 = min(M, m0 + chunk);
+  const int per = (m1 - m0 + M2L_WAVES - 1) / M2L_WAVES;
+  const int s0 = m0 + wv * per;
+  const int s1 = min(m1, s0 + per);
+  const int ntile = (per + T2_TILE - 1) / T2_TILE;
+  cd acc[NH];
+#pragma unroll
+  for (int n = 0; n < NH; ++n) acc[n] = cd{0, 0};
+  for (int it = 0; it < ntile; ++it) {
+    const int ts = s0 + it * T2_TILE;
+    const int cnt = max(0, min(T2_TILE, s1 - ts));
+    __syncthreads();
+    // each source staged forwards (x[nu], even lanes) and reflected (x[NB-1-nu], odd
+    // lanes), so every lane reads at constant offsets from its own base
+    for (int t = lane; t < cnt * NB; t += 64) {
+      const int mm = t / NB, nu = t - mm * NB;
+      const cd v = x[(size_t)ts * NB + t];
+      sx[mm * 2 * NB + nu] = v;
+      sx[mm * 2 * NB + NB + (NB - 1 - nu)] = v;
+    }
+    __syncthreads();
+    for (int mm = 0; mm < cnt; ++mm) {
+      const cd* b = sx + mm * 2 * NB + h * NB;
+      // both lanes of a target load the same two rows (+q, -q): row offsets are
+      // wave-uniform, and the odd lane swaps their roles
+      const cd* col = table + (size_t)(ts + mm) * NQ * Mpad;
+      {
+        const cd t0 = ld_stream(col + (size_t)(2 * P) * Mpad + j);
+#pragma unroll
+        for (int n = 0; n < NH; ++n) cmac(acc[n], t0, b[n]);
+      }
+      cd np[M2L_QB], nm[M2L_QB];
+#pragma unroll
+      for (int u = 0; u < M2L_QB; ++u) {
+        const int q = 1 + u;
+        np[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P + q) * Mpad + j) : cd{0, 0};
+        nm[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P - q) * Mpad + j) : cd{0, 0};
+      }
+#pragma unroll
+      for (int qb = 0; qb < NQB; ++qb) {
+        cd tp[M2L_QB], tm[M2L_QB];
+#pragma unroll
+        for (int u = 0; u < M2L_QB; ++u) {
+          tp[u] = h ? nm[u] : np[u];
+          tm[u] = h ? np[u] : nm[u];
+        }
+        if (qb + 1 < NQB) {
+#pragma unroll
+          for (int u = 0; u < M2L_QB; ++u) {
+            const int q = 1 + (qb + 1) * M2L_QB + u;
+            np[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P + q) * Mpad + j) : cd{0, 0};
+            nm[u] = q <= 2 * P ? ld_stream(col + (size_t)(2 * P - q) * Mpad + j) : cd{0, 0};
+          }
+        }
+        contract_block_half<P, const cd*>(acc, b, qb, tp, tm);
+      }
+    }
+  }
+  cd* red = reinterpret_cast<cd*>(smem);
+  for (int src = M2L_WAVES - 1; src >= 1; --src) {
+    __syncthreads();
+    if (wv == src) {
+#pragma unroll
+      for (int n = 0; n < NH; ++n) {
+        cd v = acc[n];
+        if (src != M2L_WAVES - 1) v += red[n * 64 + lane];
+        red[n * 64 + lane] = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (wv == 0 && j < M) {
+    cd* out = partial + ((size_t)by_ * M + j) * NB;
+#pragma unroll
+    for (int n = 0; n < NH; ++n) {
+      const cd v = acc[n] + red[n * 64 + lane];
+      // even lane: n - P in -P..0; odd lane: -(n - P) in 0..P (its n = P is 0: skipped)
+      if (h == 0)
+        out[n] = v;
+      else if (n < P)
+        out[2 * P - n] = v;
+    }
   }
 }
 

@@ -120,6 +120,12 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime: load it first so that this library binds to
+    # the same one (streams and device memory are shared with torch).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not built: run `python -m paper_1412_7466_amd.build`")
     lib = C.CDLL(path)
@@ -245,10 +251,11 @@ class Context:
         self._leave()
         return b
 
-    def set_table(self, enable=True):
-        """Build (or free) the resident translation table of the FP64 apply."""
+    def set_table(self, mode=1):
+        """Resident translation table of the FP64 apply: 0 off (generator on the
+        fly), 1 on (one lane per target), 2 on (two lanes per target)."""
         self._enter()
-        self._check(self.lib.grt_set_table(self.h, int(enable)))
+        self._check(self.lib.grt_set_table(self.h, int(mode)))
         self._leave()
 
     def autotune(self, cap=16):

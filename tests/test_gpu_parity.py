@@ -259,11 +259,15 @@ def test_resident_table_matches_oracle(torch_cuda, M, P, seed):
     ctx = _ctx(pb)
     xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
     y_fly = _np(ctx.apply_T(xd))
-    ctx.set_table(True)
+    ctx.set_table(2)   # two lanes per target (reflection symmetry)
+    y_tab1 = _np(ctx.apply_T(xd))
+    assert rel(y_tab1, red.T_apply(xh)) < 1e-12
+    ctx.set_table(1)   # one lane per target
     say(f"[gpu] table M={M} P={P}: {ctx.table_bytes()} bytes")
     y_tab = _np(ctx.apply_T(xd))
     assert rel(y_tab, red.T_apply(xh)) < 1e-12
     assert rel(y_tab, y_fly) < 1e-13
+    assert rel(y_tab, y_tab1) < 1e-13
     assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
     beta, st = ctx.solve(tol=1e-12, restart=150)
     assert rel(_np(beta), red.solve_lu()) < 1e-9
