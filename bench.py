@@ -205,6 +205,46 @@ def sweep(a, torch):
     return res
 
 
+def small_sweep(a, torch, n=32, M_range=(20, 100)):
+    """Many small problems (one angle, shared layer factors): one after another
+    against one batched solve."""
+    from paper_1412_7466_amd import inputs
+    from paper_1412_7466_amd.grating import Batch, Context
+    pbs = [inputs.warm_problem(1000 + i, held_out=True, M_range=M_range, phis=(-math.pi / 5,))
+           for i in range(n)]
+    ctxs = []
+    for pb in pbs:
+        c = Context(0)
+        c.set_problem(pb)
+        c.build()
+        ctxs.append(c)
+    for c in ctxs:
+        c.solve(tol=a.tol, restart=a.restart)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = [c.solve(tol=a.tol, restart=a.restart) for c in ctxs]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    batch = Batch(ctxs)
+    batch.solve(tol=a.tol, restart=a.restart)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bb, sb = batch.solve(tol=a.tol, restart=a.restart)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    res = {"workload": (f"{n} geometries of the warm-start rules with M uniform in "
+                        f"[{M_range[0]}, {M_range[1]}], omega=20, phi=-pi/5, P=15, GMRES to {a.tol:g}"),
+           "plain_fp64_sequential_solves_per_s": n / t_plain,
+           "batched_fp64_solves_per_s": n / t_batch,
+           "batched_max_rel_diff_vs_plain": max(
+               float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
+               for b, (p, _) in zip(bb, plain))}
+    batch.close()
+    for c in ctxs:
+        c.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +334,15 @@ def main():
               "avg_launch_ms": avg_t, "launches": n_t, "bytes_per_launch": bytes_t,
               "flops_per_launch": flops, "tflops": flops / (avg_t * 1e-3) / 1e12,
               "autotune_chunks_ms": tune_t}
+    # the same solves with every apply replayed from a captured HIP graph
+    ctx.solve(tol=a.tol, restart=a.restart, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        beta_g, st_g = ctx.solve(tol=a.tol, restart=a.restart, graph=True)
+    torch.cuda.synchronize()
+    el_g = time.perf_counter() - t0
+    graph_diff = float(torch.linalg.norm(beta_g - beta_t) / torch.linalg.norm(beta_t))
     # the same table contracted with two lanes per target (for comparison)
     ctx.set_table(2)
     if not a.no_autotune:
@@ -306,10 +355,11 @@ def main():
     ctx.set_table(1)
     if tune_t is not None:
         ctx.autotune()
-    use_table = el_t < el_f
+    use_table = min(el_t, el_g) < el_f
+    use_graph = use_table and el_g < el_t
     beta = beta_t if use_table else beta_f
     iters, resid = (iters_t, resid_t) if use_table else (iters_f, resid_f)
-    elapsed = el_t if use_table else el_f
+    elapsed = (el_g if use_graph else el_t) if use_table else el_f
     out = ctx.bragg(beta)
     diff_tf = float(torch.linalg.norm(beta_t - beta_f) / torch.linalg.norm(beta_f))
     # 3. the same workload through the mixed-precision path (FP32 translation on the fly,
@@ -345,7 +395,9 @@ def main():
                                "middle layer y in [-1,1], one angle phi=-pi/5, GMRES to 1e-9",
                    "M": M, "P": P, "n_unknowns": M * NB, "tol": a.tol,
                    "restart": a.restart, "seed": pb.seed,
-                   "translation": "resident table" if use_table else "on the fly"},
+                   "translation": ("resident table" + (", applies replayed from a HIP graph"
+                                                       if use_graph else "")
+                                   if use_table else "on the fly")},
         "gmres_iters": iters[-1],
         "rel_resid": resid[-1],
         "flux_err": out["flux_err"],
@@ -353,6 +405,8 @@ def main():
         "table_build_s": t_table,
         "fp64_on_the_fly_solves_per_s": a.steps / el_f,
         "fp64_table_solves_per_s": a.steps / el_t,
+        "fp64_table_graph_solves_per_s": a.steps / el_g,
+        "graph_vs_eager_rel_diff": graph_diff,
         "table_vs_on_the_fly_rel_diff": diff_tf,
         "mixed_fp32_fp64": mixed,
         "roofline": roof_t if use_table else roof_f,
@@ -362,6 +416,7 @@ def main():
     }
     if not a.no_sweep:
         res["sweep"] = sweep(a, torch)
+        res["sweep_small"] = small_sweep(a, torch)
     if a.copy_probe_mib > 0:
         src = torch.ones(a.copy_probe_mib * 131072, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)

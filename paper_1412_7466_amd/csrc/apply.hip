@@ -88,8 +88,8 @@ __global__ void __launch_bounds__(64 * BX_WAVES) bx_kernel(DevGeom g, const doub
 }
 
 __global__ void __launch_bounds__(256) l2l_kernel(int M, int P, int Q2, const cd* __restrict__ E,
-                                                 const cd* __restrict__ a2, cd* out) {
-  l2l_block(M, P, Q2, E, a2, out, blockIdx.x);
+                                                  const cd* __restrict__ a2, cd* out, int ntb) {
+  l2l_block(M, P, Q2, E, a2, out, blockIdx.x, ntb);
 }
 
 // Sum of the partial results of entry i: each block takes 64 entries, its four
@@ -393,9 +393,10 @@ static grt_status lowrank_tail(grt_ctx* c, const cd* gvec) {
   launch_gemv_rows(s, c->d_W2, c->d_tvec, c->d_wvec, c->n_b, c->rank);
   GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec);
   {
-    const size_t sh = sizeof(cd) * (size_t)(2 * c->g.Q[1] + 1);
-    l2l_kernel<<<(unsigned)((c->M + L2L_TARGETS - 1) / L2L_TARGETS), 256, sh, s>>>(
-        (int)c->M, c->P, c->g.Q[1], c->d_l2l, c->d_wvec + c->g.col_off[CB_A2], c->d_pL);
+    const int ntb = l2l_targets_per_block(c->P, c->g.Q[1]);
+    const size_t sh = l2l_lds_bytes(c->P, c->g.Q[1], ntb);
+    l2l_kernel<<<(unsigned)((c->M + ntb - 1) / ntb), 256, sh, s>>>(
+        (int)c->M, c->P, c->g.Q[1], c->d_l2l, c->d_wvec + c->g.col_off[CB_A2], c->d_pL, ntb);
   }
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;

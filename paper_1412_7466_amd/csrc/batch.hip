@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) l2l_batched(const InstDesc* __restrict__ 
                                                   const Item* __restrict__ it) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
-  l2l_block(q.M, q.P, q.Q2, q.l2l, q.wvec + q.g.col_off[CB_A2], q.pL, w.x);
+  l2l_block(q.M, q.P, q.Q2, q.l2l, q.wvec + q.g.col_off[CB_A2], q.pL, w.x, w.y);
 }
 
 // Y = D o (x - s o (T x - B x)) with x = X (already un-normalised) for mode 0, or
@@ -596,7 +596,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     for (int t = 0; t < q.nseg; ++t) seg2inst.push_back(i);
     seg += q.nseg;
     byP[q.P].push_back(i);
-    smem = std::max(smem, sizeof(cd) * (size_t)(2 * q.Q2 + 1));
+    smem = std::max(smem, l2l_lds_bytes(q.P, q.Q2, l2l_targets_per_block(q.P, q.Q2)));
   }
   b->nseg = seg;
   b->ntot = (int64_t)seg * SEG;
@@ -634,7 +634,10 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     for (int x = 0; x < (nt + 3) / 4; ++x) cxr.push_back({i, x, 0});
     for (int x = 0; x < (q.rank + 3) / 4; ++x) g1.push_back({i, x, 0});
     for (int x = 0; x < (q.n_b + 3) / 4; ++x) g2.push_back({i, x, 0});
-    for (int x = 0; x < (q.M + L2L_TARGETS - 1) / L2L_TARGETS; ++x) l2l.push_back({i, x, 0});
+    {
+      const int ntb = l2l_targets_per_block(q.P, q.Q2);  // carried in the item's y
+      for (int x = 0; x < (q.M + ntb - 1) / ntb; ++x) l2l.push_back({i, x, ntb});
+    }
   }
   // concatenated normalisation
   std::vector<double> dn(b->ntot, 0.0), di(b->ntot, 0.0);

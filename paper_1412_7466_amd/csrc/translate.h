@@ -883,26 +883,43 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
 }
 
 // L2L of the middle-layer J expansion (coefficients a2, orders -Q2..Q2) to the
-// incoming coefficients of four targets per 256-thread block, one wave per target,
-// one lane per order n:
+// incoming coefficients of ntb (at most L2L_TARGETS) targets per 256-thread block:
 //   out[j][n] = sum_q a2_q E_j[q - n],  E_j[m] = J_m(k2 rho_j) e^{i m phi_j},
-// E_j stored at offset L = Q2 + P.  a2 is staged in LDS (extern shared, 2 Q2 + 1).
-constexpr int L2L_TARGETS = 4;
+// E_j stored at offset L = Q2 + P.  a2 and the block's E rows are staged in LDS
+// (extern shared: 2 Q2 + 1 + ntb (2L + 1) complex, see l2l_targets_per_block); one
+// thread per (target, n), consecutive n reading consecutive LDS entries.
+constexpr int L2L_TARGETS = 8;
+constexpr size_t L2L_LDS_BUDGET = 60 * 1024;
+// targets per block so that the staged rows fit the LDS budget
+__host__ __device__ inline int l2l_targets_per_block(int P, int Q2) {
+  const size_t row = sizeof(cd) * (size_t)(2 * (Q2 + P) + 1);
+  const size_t fixed = sizeof(cd) * (size_t)(2 * Q2 + 1);
+  int n = fixed + row <= L2L_LDS_BUDGET ? (int)((L2L_LDS_BUDGET - fixed) / row) : 1;
+  return n < 1 ? 1 : (n > L2L_TARGETS ? L2L_TARGETS : n);
+}
+__host__ __device__ inline size_t l2l_lds_bytes(int P, int Q2, int ntb) {
+  return sizeof(cd) * (size_t)(2 * Q2 + 1 + ntb * (2 * (Q2 + P) + 1));
+}
 __device__ inline void l2l_block(int M, int P, int Q2, const cd* __restrict__ E,
-                                 const cd* __restrict__ a2, cd* out, int bx_) {
+                                 const cd* __restrict__ a2, cd* out, int bx_, int ntb) {
   extern __shared__ cd l2l_smem[];
   const int NB = 2 * P + 1;
   const int L = Q2 + P;
-  for (int i = threadIdx.x; i < 2 * Q2 + 1; i += blockDim.x) l2l_smem[i] = a2[i];
+  const int row = 2 * L + 1;
+  cd* sa = l2l_smem;
+  cd* se = l2l_smem + 2 * Q2 + 1;
+  const int j0 = bx_ * ntb;
+  const int nt = min(ntb, M - j0);
+  for (int i = threadIdx.x; i < 2 * Q2 + 1; i += blockDim.x) sa[i] = a2[i];
+  for (int i = threadIdx.x; i < nt * row; i += blockDim.x) se[i] = E[(size_t)j0 * row + i];
   __syncthreads();
-  const int j = bx_ * L2L_TARGETS + (threadIdx.x >> 6);
-  const int nn = threadIdx.x & 63;
-  if (j >= M || nn >= NB) return;
-  const int n = nn - P;
-  const cd* e = E + (size_t)j * (2 * L + 1) + L - n;
-  cd acc{0, 0};
-  for (int q = -Q2; q <= Q2; ++q) cmac(acc, l2l_smem[q + Q2], e[q]);
-  out[(size_t)j * NB + nn] = acc;
+  for (int t = threadIdx.x; t < nt * NB; t += blockDim.x) {
+    const int jj = t / NB, nn = t - jj * NB;
+    const cd* e = se + jj * row + L - (nn - P);
+    cd acc{0, 0};
+    for (int q = -Q2; q <= Q2; ++q) cmac(acc, sa[q + Q2], e[q]);
+    out[(size_t)(j0 + jj) * NB + nn] = acc;
+  }
 }
 
 
