@@ -105,7 +105,7 @@ def record_traffic(fetch_db, write_db, kernel, copy_bytes, commands):
     return rec
 
 
-def cpu_baseline(pb, iters, n_sample=96):
+def cpu_baseline(pb, iters, n_sample=320):
     """Oracle T-apply on a sample of target rows, extrapolated to whole solves."""
     import numpy as np
     from oracle.common import Geometry
@@ -232,10 +232,17 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
     bb, sb = batch.solve(tol=a.tol, restart=a.restart)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t
+    batch.solve(tol=a.tol, restart=a.restart, graph=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    batch.solve(tol=a.tol, restart=a.restart, graph=True)
+    torch.cuda.synchronize()
+    t_bgraph = time.perf_counter() - t
     res = {"workload": (f"{n} geometries of the warm-start rules with M uniform in "
                         f"[{M_range[0]}, {M_range[1]}], omega=20, phi=-pi/5, P=15, GMRES to {a.tol:g}"),
            "plain_fp64_sequential_solves_per_s": n / t_plain,
            "batched_fp64_solves_per_s": n / t_batch,
+           "batched_graph_fp64_solves_per_s": n / t_bgraph,
            "batched_max_rel_diff_vs_plain": max(
                float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
                for b, (p, _) in zip(bb, plain))}

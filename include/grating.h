@@ -241,7 +241,9 @@ const char* grt_batch_error_message(const grt_batch* batch);
  * opts->use_x0); stats (host, n entries, may be NULL) receives each problem's
  * iterations, restarts and final relative residual (seconds is the batch's).
  * opts->precision must be GRT_FP64 (GRT_EUNSUP otherwise); opts->maxit bounds
- * the lockstep steps of the whole batch.  GRT_ENOCONV if any problem missed tol. */
+ * the lockstep steps of the whole batch; with opts->use_graph the batch's apply
+ * (every kernel launch for all problems) is captured once as a HIP graph and
+ * replayed at every step.  GRT_ENOCONV if any problem missed tol. */
 grt_status grt_batch_solve(grt_batch* batch, const grt_solve_opts* opts, void* const* beta,
                            grt_solve_stats* stats);
 

@@ -385,7 +385,9 @@ struct grt_batch {
   size_t l2l_smem = 0;
   // Krylov workspace
   int m = 0;
-  cd* V = nullptr;        // m + 4 slots of ntot: basis 0..m, iterate, rhs, scratch
+  cd* V = nullptr;        // m + 5 slots of ntot: basis 0..m, iterate, rhs, apply in, out
+  cd *xtmp = nullptr, *wout = nullptr;   // slots m+3, m+4: the apply's fixed buffers
+  hipGraphExec_t graph = nullptr;       // captured batch_apply_core
   cd* H = nullptr;        // B x (m+1)^2
   cd *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h = nullptr;
   double *res = nullptr, *part = nullptr, *nrm = nullptr, *hn = nullptr, *bn = nullptr;
@@ -458,17 +460,43 @@ static grt_status batch_lowrank(grt_batch* b, int use_f) {
   return GRT_OK;
 }
 
-// Y = D K D^{-1} Xh for every problem (Xh, Y concatenated; xtmp scratch)
-static grt_status batch_apply_hat(grt_batch* b, const cd* Xh, cd* Y, cd* xtmp) {
+// wout = D K D^{-1} x for every problem, x = D^{-1} xh already in xtmp (both fixed
+// buffers of the batch, so the whole launch sequence can be captured once as a HIP
+// graph and replayed; see batch_apply).
+static grt_status batch_apply_core(grt_batch* b) {
   hipStream_t s = b->stream;
-  const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
-  ew_scale_kernel<<<gn, BT, 0, s>>>(Xh, b->d_dinv, xtmp, b->ntot);
-  for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_T, gp.P, b, gp, xtmp);
-  for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_C, gp.P, b, gp, xtmp);
+  for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_T, gp.P, b, gp, b->xtmp);
+  for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_C, gp.P, b, gp, b->xtmp);
   if (b->n_cxr) cxr_batched<<<b->n_cxr, 256, 0, s>>>(b->dd, b->it_cxr);
   BTRY(batch_lowrank(b, 0));
-  combine_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, xtmp, b->d_dnorm, Y, 0);
+  combine_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, b->xtmp, b->d_dnorm, b->wout, 0);
   BHIP(b, hipGetLastError());
+  return GRT_OK;
+}
+
+// wout = D K D^{-1} xh (xh concatenated), the core replayed from a graph if asked
+static grt_status batch_apply(grt_batch* b, const cd* xh, bool use_graph) {
+  hipStream_t s = b->stream;
+  const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
+  ew_scale_kernel<<<gn, BT, 0, s>>>(xh, b->d_dinv, b->xtmp, b->ntot);
+  if (!use_graph) return batch_apply_core(b);
+  if (!b->graph) {
+    hipGraph_t gr = nullptr;
+    BHIP(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    grt_status st = batch_apply_core(b);
+    hipError_t e = hipStreamEndCapture(s, &gr);
+    if (st != GRT_OK || e != hipSuccess) {
+      if (gr) hipGraphDestroy(gr);
+      return st != GRT_OK ? st : bset(b, GRT_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
+    hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+      b->graph = nullptr;
+      return bset(b, GRT_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+  }
+  BHIP(b, hipGraphLaunch(b->graph, s));
   return GRT_OK;
 }
 
@@ -493,7 +521,13 @@ static grt_status batch_workspace(grt_batch* b, int m) {
   for (void* p : olds)
     if (p) hipFree(p);
   const size_t B = b->B, n = b->ntot, ld = m + 1;
-  BHIP(b, hipMalloc(&b->V, sizeof(cd) * n * (m + 4)));
+  if (b->graph) {  // the captured apply points into the old workspace
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  BHIP(b, hipMalloc(&b->V, sizeof(cd) * n * (m + 5)));
+  b->xtmp = b->V + n * (m + 3);
+  b->wout = b->V + n * (m + 4);
   BHIP(b, hipMalloc(&b->H, sizeof(cd) * B * ld * ld));
   BHIP(b, hipMalloc(&b->cs, sizeof(cd) * B * ld));
   BHIP(b, hipMalloc(&b->sn, sizeof(cd) * B * ld));
@@ -678,6 +712,7 @@ grt_status grt_batch_destroy(grt_batch* b) {
   }
   for (void* q : p)
     if (q) hipFree(q);
+  if (b->graph) hipGraphExecDestroy(b->graph);
   if (b->h_pinned) hipHostFree(b->h_pinned);
   for (hipEvent_t e : b->ev)
     if (e) hipEventDestroy(e);
@@ -709,7 +744,7 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
   cd* V = b->V;
   cd* X = V + (size_t)(m + 1) * ldv;      // iterate (normalised)
   cd* Bv = V + (size_t)(m + 2) * ldv;     // right-hand side (normalised)
-  cd* wtmp = V + (size_t)(m + 3) * ldv;   // scratch of the apply
+  const bool use_graph = o->use_graph != 0;
   // x0 and b
   BTRY(batch_rhs_hat(b, Bv));
   BHIP(b, hipMemsetAsync(X, 0, sizeof(cd) * ldv, s));
@@ -731,8 +766,8 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
   int total = 0;
   while (true) {
     // R = B - K X into V_0
-    BTRY(batch_apply_hat(b, X, V + ldv, wtmp));
-    ew_sub_kernel<<<gn, BT, 0, s>>>(Bv, V + ldv, V, b->ntot);
+    BTRY(batch_apply(b, X, use_graph));
+    ew_sub_kernel<<<gn, BT, 0, s>>>(Bv, b->wout, V, b->ntot);
     BTRY(batch_norms(b, V, b->nrm));
     BTRY(read_vec(b, b->nrm, beta0));
     bool any = false, reject = false;
@@ -777,8 +812,8 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
     };
     bool all = false;
     for (int j = 0; j < m && total + j < maxit; ++j) {
-      cd* w = V + (size_t)(j + 1) * ldv;
-      BTRY(batch_apply_hat(b, V + (size_t)j * ldv, w, wtmp));
+      cd* w = b->wout;  // the new directions; normalised into V_{j+1} below
+      BTRY(batch_apply(b, V + (size_t)j * ldv, use_graph));
       for (int pass = 0; pass < 2; ++pass) {
         seg_dots_kernel<<<b->nseg, BT, 0, s>>>(V, ldv, w, j + 1, b->nseg, b->dpart);
         inst_dots_kernel<<<(B * (j + 1) + 255) / 256, 256, 0, s>>>(b->dd, B, j + 1, b->nseg,
@@ -789,7 +824,7 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
       BTRY(batch_norms(b, w, b->nrm));
       inst_givens_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->nrm, b->H, ld, b->cs, b->sn, b->g, j,
                                                       b->hn, b->res, ld);
-      inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, w, b->hn, w);
+      inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, w, b->hn, V + (size_t)(j + 1) * ldv);
       BHIP(b, hipGetLastError());
       BHIP(b, hipMemcpy2DAsync(hbuf[j & 1], sizeof(double), b->res + j, sizeof(double) * ld,
                                sizeof(double), B, hipMemcpyDeviceToHost, s));

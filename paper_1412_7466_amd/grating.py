@@ -372,7 +372,7 @@ class Batch:
         except Exception:
             pass
 
-    def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, check=True):
+    def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, check=True, graph=False):
         """Returns (list of beta vectors, list of grt_solve_stats)."""
         betas = [c.new_vec() for c in self.ctxs]
         if x0 is not None:
@@ -380,7 +380,8 @@ class Batch:
                 b.copy_(x)
         ptrs = (_VP * len(betas))(*[c._vec_ptr(b) for c, b in zip(self.ctxs, betas)])
         opts = grt_solve_opts(tol=tol, maxit=maxit, restart=restart, use_x0=int(x0 is not None),
-                              precision=GRT_FP64, inner_tol=0.0, max_refine=0)
+                              precision=GRT_FP64, inner_tol=0.0, max_refine=0,
+                              use_graph=int(graph))
         stats = (grt_solve_stats * len(betas))()
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         st = self.lib.grt_batch_solve(self.h, C.byref(opts), ptrs, stats)

@@ -200,6 +200,15 @@ def test_batched_solve_matches_single_and_oracle(torch_cuda):
         assert st.rel_resid <= 1e-12
         assert rel(_np(b), beta_o) < 1e-9
         assert rel(_np(b), bs) < 1e-9
+    # the same batch with its apply replayed from a captured graph, three times, with
+    # eager work between the replays: identical results every time
+    for rep in range(3):
+        bg, sg = batch.solve(tol=1e-12, restart=150, graph=True)
+        torch_cuda.cuda.synchronize()
+        for b, b2, st, st2 in zip(betas, bg, stats, sg):
+            assert st2.iters == st.iters
+            assert rel(_np(b2), _np(b)) < 1e-14, rep
+        ctxs[0].apply(betas[0])
     # warm start from the solution: converged on entry
     betas2, stats2 = batch.solve(tol=1e-12, restart=150, x0=betas)
     assert all(s.iters == 0 for s in stats2)
