@@ -123,6 +123,8 @@ typedef struct {
   int Nrb;
   int m2l_chunks;   /* source chunks of the translation launch (one partial
                        result of n_beta entries each)                         */
+  int cx_chunks;    /* source chunks of the C x launch                       */
+  int bx_chunks;    /* node chunks of the B_phys w (P2L) launch              */
 } grt_sizes;
 
 /* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
@@ -132,7 +134,8 @@ grt_status grt_destroy(grt_ctx* ctx);
 const char* grt_error_message(const grt_ctx* ctx);
 
 /* Copy and validate the problem (sec. 2).  GRT_EGEOM if two disks overlap under
- * the minimum image in x or a disk crosses an interface. */
+ * the minimum image in x, a disk crosses an interface or a centre lies outside the
+ * cell |x| <= d/2 (the near copies l = -1, 0, 1 of sec. 4.2 assume one cell). */
 grt_status grt_set_problem(grt_ctx* ctx, const grt_layers* lay, const grt_inclusions* inc,
                            const grt_incidence* wave);
 
@@ -166,12 +169,15 @@ grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision
  * context stays usable, without the table).  The mixed-precision apply and batched
  * solves always evaluate on the fly. */
 grt_status grt_set_table(grt_ctx* ctx, int mode);
-/* Launch-shape autotuner of the translation kernel: times the launch for source
- * chunk counts giving 256 .. 8192 work-groups, in the current mode (on the fly or
- * resident table), and keeps the fastest for every later apply of this context
- * (results change only by the order of the chunk sums).  Up to cap measured
- * (chunk count, ms per launch) pairs go to chunks[] / ms[] (host); *n receives
- * their number.  Without a call the split aims at two work-groups per SIMD. */
+/* Launch-shape autotuner: times the translation launch for source chunk counts
+ * giving 256 .. 8192 work-groups, in the current mode (on the fly or resident
+ * table), then the C x and B_phys w launches (each with the pass that adds its
+ * per-chunk partial results) for 1 .. 64 sources per wave, and keeps the fastest
+ * of each for every later apply of this context (results change only by the
+ * order of the chunk sums; grt_query reports the chosen chunk counts).  Up to cap
+ * measured (chunk count, ms per launch) pairs of the translation go to chunks[] /
+ * ms[] (host); *n receives their number.  Without a call every split aims at two
+ * work-groups per SIMD. */
 grt_status grt_autotune(grt_ctx* ctx, int cap, int* n, int* chunks, double* ms);
 
 /* Bytes the table of the current problem takes. */

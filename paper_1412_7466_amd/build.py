@@ -22,7 +22,7 @@ SOURCES = ["capi.hip", "setup.hip", "apply.hip", "krylov.hip", "batch.hip", "nn.
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-mllvm", "-pragma-unroll-threshold=200000",
+         "-mllvm", "-pragma-unroll-threshold=200000", "-Werror=return-type",
          "-I", os.path.join(HERE, "..", "include"), "-I", CSRC]
 
 

@@ -349,9 +349,19 @@ grt_status apply_alloc(grt_ctx* c) {
   split_work(M, (nt + 63) / 64, 2048 / CX_WAVES, 4 * CX_WAVES, c->c_chunk, c->c_nchunks);
   split_work(2 * (int64_t)c->g.N, (M + 63) / 64, 2048 / BX_WAVES, 2 * BX_WAVES, c->b_chunk,
              c->b_nchunks);
+  // the coupling launches' candidates (autotune_coupling) go down to CX_TUNE_MIN_PER
+  // and BX_TUNE_MIN_PER sources per wave, within CX_TUNE_MAX_CHUNKS and
+  // BX_TUNE_MAX_CHUNKS partial results (the P2L partials are n_beta entries each)
+  c->c_nchunks_cap = std::max<int>(
+      c->c_nchunks, (int)std::min<int64_t>(CX_TUNE_MAX_CHUNKS, (M + CX_WAVES * CX_TUNE_MIN_PER - 1) /
+                                                                   (CX_WAVES * CX_TUNE_MIN_PER)));
+  c->b_nchunks_cap = std::max<int>(
+      c->b_nchunks,
+      (int)std::min<int64_t>(BX_TUNE_MAX_CHUNKS, (2 * (int64_t)c->g.N + BX_WAVES * BX_TUNE_MIN_PER - 1) /
+                                                     (BX_WAVES * BX_TUNE_MIN_PER)));
   GRT_HIP(c, hipMalloc(&c->d_pT, sizeof(cd) * (size_t)c->m2l_nchunks_cap * c->n_beta));
-  GRT_HIP(c, hipMalloc(&c->d_pC, sizeof(cd) * (size_t)c->c_nchunks * nt * 2));
-  GRT_HIP(c, hipMalloc(&c->d_pB, sizeof(cd) * (size_t)c->b_nchunks * c->n_beta));
+  GRT_HIP(c, hipMalloc(&c->d_pC, sizeof(cd) * (size_t)c->c_nchunks_cap * nt * 2));
+  GRT_HIP(c, hipMalloc(&c->d_pB, sizeof(cd) * (size_t)c->b_nchunks_cap * c->n_beta));
   GRT_HIP(c, hipMalloc(&c->d_pL, sizeof(cd) * (size_t)c->n_beta));
   // mixed-precision path: FP32 copy of x, FP32 partials, near-pair lists and results.
   // zsafe: the smallest k2*rho with (2P-1)! (2/z)^{2P} / pi <= 1e30, the large-order
@@ -552,6 +562,91 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, double
   hipEventDestroy(e1);
   GRT_HIP(c, hipGetLastError());
   if (n_out) *n_out = std::min(count, cap);
+  return GRT_OK;
+}
+
+// Launch shapes of the coupling kernels, chosen by measurement: for each candidate
+// number of sources per wave (chunk = waves per block x that number, so the waves of
+// a block get equal shares) time the kernel together with the pass that adds its
+// per-chunk partial results (cx_reduce for C x; the combine, which reads the P2L
+// partials, for B_phys w), and keep the fastest.  Inputs are zero: the kernels' cost
+// does not depend on the values.
+grt_status autotune_coupling(grt_ctx* c) {
+  if (c->M == 0) return GRT_OK;
+  hipStream_t s = c->stream;
+  const int64_t M = c->M;
+  const int nt = 2 * c->g.N + c->g.Nw[1];
+  const int n = (int)c->n_beta;
+  cd* ytmp = nullptr;
+  GRT_HIP(c, hipMalloc(&ytmp, sizeof(cd) * (size_t)n));
+  hipEvent_t e0, e1;
+  GRT_HIP(c, hipEventCreate(&e0));
+  GRT_HIP(c, hipEventCreate(&e1));
+  GRT_HIP(c, hipMemsetAsync(c->d_xtmp, 0, sizeof(cd) * (size_t)n, s));
+  GRT_HIP(c, hipMemsetAsync(c->d_wvec, 0, sizeof(cd) * (size_t)c->n_b, s));
+  // launch() enqueues one candidate and returns its status
+  auto time_it = [&](auto&& launch) -> double {
+    for (int r = 0; r < 2; ++r)
+      if (launch() != GRT_OK) return -1.0;
+    hipEventRecord(e0, s);
+    const int reps = 6;
+    for (int r = 0; r < reps; ++r) launch();
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    return ms / reps;
+  };
+  static const int per_wave[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 48, 64};
+  {  // C x
+    int best_ch = c->c_chunk, best_nc = c->c_nchunks, last = -1;
+    double best = 1e300;
+    for (int p : per_wave) {
+      const int ch = CX_WAVES * p;
+      const int nc = (int)((M + ch - 1) / ch);
+      if (p < CX_TUNE_MIN_PER || nc == last || nc > c->c_nchunks_cap) continue;
+      last = nc;
+      c->c_chunk = ch;
+      c->c_nchunks = nc;
+      const double ms = time_it([&]() -> grt_status {
+        GRT_P_DISPATCH(launch_cx, c->P, c, c->d_xtmp);
+        cx_reduce_kernel<<<(nt + 3) / 4, 256, 0, s>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
+        return GRT_OK;
+      });
+      if (ms < 0) break;
+      if (ms < best) { best = ms; best_ch = ch; best_nc = nc; }
+    }
+    c->c_chunk = best_ch;
+    c->c_nchunks = best_nc;
+  }
+  {  // B_phys w (P2L) with the combine that reads its partials
+    int best_ch = c->b_chunk, best_nc = c->b_nchunks, last = -1;
+    double best = 1e300;
+    const int64_t ns = 2 * (int64_t)c->g.N;
+    for (int p : per_wave) {
+      const int ch = BX_WAVES * p;
+      const int nc = (int)((ns + ch - 1) / ch);
+      if (p < BX_TUNE_MIN_PER || nc == last || nc > c->b_nchunks_cap) continue;
+      last = nc;
+      c->b_chunk = ch;
+      c->b_nchunks = nc;
+      const double ms = time_it([&]() -> grt_status {
+        GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec);
+        combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
+            n, c->d_xtmp, c->d_mie, c->d_pT, 0, c->d_pB, c->b_nchunks, c->d_pL, ytmp, 2, nullptr);
+        return GRT_OK;
+      });
+      if (ms < 0) break;
+      if (ms < best) { best = ms; best_ch = ch; best_nc = nc; }
+    }
+    c->b_chunk = best_ch;
+    c->b_nchunks = best_nc;
+  }
+  graph_reset(c);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(ytmp);
+  GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
 

@@ -152,6 +152,8 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
       return set_err(c, GRT_EINVAL, "non-finite or non-positive inclusion data");
     if (std::fabs(c->hy[m]) + c->hr[m] >= L.h)
       return set_err(c, GRT_EGEOM, "inclusion " + std::to_string(m) + " touches an interface");
+    if (std::fabs(c->hx[m]) > 0.5 * L.d)
+      return set_err(c, GRT_EGEOM, "inclusion " + std::to_string(m) + " lies outside the cell |x| <= d/2");
   }
   // minimum-image overlap check on a cell grid
   if (M > 1) {
@@ -289,6 +291,8 @@ grt_status grt_query(const grt_ctx* c, grt_sizes* out) {
   out->rank = c->built ? c->rank : 0;
   out->Nrb = c->g.Nrb;
   out->m2l_chunks = c->built ? c->m2l_nchunks : 0;
+  out->cx_chunks = c->built ? c->c_nchunks : 0;
+  out->bx_chunks = c->built ? c->b_nchunks : 0;
   return GRT_OK;
 }
 
@@ -338,7 +342,9 @@ grt_status grt_autotune(grt_ctx* c, int cap, int* n, int* chunks, double* ms) {
   grt_status st = check_built(c);
   if (st != GRT_OK) return st;
   if (cap < 0 || (cap > 0 && (!chunks || !ms))) return set_err(c, GRT_EINVAL, "bad arrays");
-  return autotune_m2l(c, cap, n, chunks, ms);
+  st = autotune_m2l(c, cap, n, chunks, ms);
+  if (st != GRT_OK) return st;
+  return autotune_coupling(c);
 }
 
 grt_status grt_incident(grt_ctx* c, void* a) {

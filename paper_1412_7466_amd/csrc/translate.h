@@ -574,6 +574,10 @@ static __global__ void near_reduce_kernel(const int* __restrict__ noff, const cd
 }
 
 constexpr int CX_WAVES = 4;   // waves per block: same 64 targets, sources split 4 ways
+constexpr int CX_TUNE_MIN_PER = 1;  // fewest sources per wave among the tuner's candidates
+constexpr int BX_TUNE_MIN_PER = 2;
+constexpr int CX_TUNE_MAX_CHUNKS = 1024;  // most partial results among the candidates
+constexpr int BX_TUNE_MAX_CHUNKS = 128;
 constexpr int CX_TILE = 8;    // inclusions staged in LDS at a time, per wave
 
 // Field of all multipoles (and their copies) at the C targets, one per lane:

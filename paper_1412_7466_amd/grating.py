@@ -52,7 +52,7 @@ class grt_solve_stats(C.Structure):
 class grt_sizes(C.Structure):
     _fields_ = [("M", C.c_int64), ("P", C.c_int), ("n_beta", C.c_int64), ("n_rows", C.c_int64),
                 ("n_alpha", C.c_int64), ("rank", C.c_int64), ("Nrb", C.c_int),
-                ("m2l_chunks", C.c_int)]
+                ("m2l_chunks", C.c_int), ("cx_chunks", C.c_int), ("bx_chunks", C.c_int)]
 
 
 class grt_nn_config(C.Structure):
@@ -260,7 +260,9 @@ class Context:
 
     def autotune(self, cap=16):
         """Time the translation launch for several chunk counts and keep the
-        fastest; returns [(chunks, ms per launch)]."""
+        fastest, then the same for the C x and B_phys w launches; returns the
+        translation's [(chunks, ms per launch)] (the chosen coupling chunk counts
+        are in self.sizes)."""
         n = C.c_int(0)
         ch = (C.c_int * cap)()
         ms = (C.c_double * cap)()

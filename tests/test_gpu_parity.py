@@ -146,6 +146,14 @@ def test_invalid_geometry_rejected(torch_cuda):
     with pytest.raises(GratingError) as ei:
         ctx.set_problem(pb)
     assert ei.value.status == GRT_EGEOM
+    # a centre outside the cell |x| <= d/2 (the near copies assume one cell)
+    pb = inputs.small(4, 4, seed=3)
+    pb.x = pb.x.copy()
+    pb.x[2] = 0.5 * pb.d + 1e-9
+    with pytest.raises(GratingError) as ei:
+        ctx.set_problem(pb)
+    assert ei.value.status == GRT_EGEOM
+    ctx.close()
 
 
 @pytest.mark.parametrize("M,P,seed", [(4, 10, 1), (40, 10, 12), (30, 15, 13), (25, 20, 14)])
@@ -295,8 +303,10 @@ def test_autotune_keeps_parity(torch_cuda, M, P, seed, table):
         ctx.set_table(True)
     xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
     tuned = ctx.autotune()
-    say(f"[gpu] autotune M={M} P={P} table={table}: {tuned} -> {ctx.sizes.m2l_chunks} chunks")
+    say(f"[gpu] autotune M={M} P={P} table={table}: {tuned} -> {ctx.sizes.m2l_chunks} chunks, "
+        f"C x {ctx.sizes.cx_chunks}, B_phys w {ctx.sizes.bx_chunks}")
     assert len(tuned) >= 1
+    assert ctx.sizes.cx_chunks >= 1 and ctx.sizes.bx_chunks >= 1
     assert ctx.sizes.m2l_chunks in [c for c, _ in tuned]
     assert rel(_np(ctx.apply_T(xd)), red.T_apply(xh)) < 1e-12
     assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
