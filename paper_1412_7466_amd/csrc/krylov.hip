@@ -16,6 +16,21 @@
 namespace {
 
 constexpr int KT = 256;
+constexpr int NBLK_MAX = 16;  // most partial sums per dot product (ensure_workspace)
+
+// sum_{b < nblk} p[b * stride] in the order b = 0, 1, ...; all loads are issued
+// before the first add (nblk <= NBLK_MAX), so the sum costs one memory latency
+template <typename T>
+__device__ __forceinline__ T sum_partials(const T* p, size_t stride, int nblk) {
+  T v[NBLK_MAX];
+#pragma unroll
+  for (int b = 0; b < NBLK_MAX; ++b) v[b] = b < nblk ? p[(size_t)b * stride] : T{};
+  T s = v[0];
+#pragma unroll
+  for (int b = 1; b < NBLK_MAX; ++b)
+    if (b < nblk) s += v[b];
+  return s;
+}
 
 // partial[v][blk] = sum_{i in slice blk} conj(V_v[i]) w[i]
 __global__ void __launch_bounds__(KT) dots_kernel(const cd* __restrict__ V, size_t ldv,
@@ -54,8 +69,7 @@ __global__ void __launch_bounds__(KT) update_kernel(const cd* __restrict__ V, si
                                                      int nblk, int nvec, cd* hcol, int pass) {
   __shared__ cd h[1024];
   for (int v = threadIdx.x; v < nvec; v += KT) {
-    cd s{0, 0};
-    for (int b = 0; b < nblk; ++b) s += partial[(size_t)v * nblk + b];
+    const cd s = sum_partials(partial + (size_t)v * nblk, 1, nblk);
     h[v] = s;
     if (blockIdx.x == 0) hcol[v] = pass ? hcol[v] + s : s;
   }
@@ -123,9 +137,7 @@ __global__ void axpy_basis_kernel(cd* x, const cd* __restrict__ V, size_t ldv, i
 __global__ void __launch_bounds__(KT) norm_scale_kernel(const cd* w, cd* vout, int n,
                                                          const double* npart, int nblk, cd* hsub,
                                                          const double* dinv, cd* xpre) {
-  double s2 = 0.0;
-  for (int b = 0; b < nblk; ++b) s2 += npart[b];
-  const double hn = sqrt(s2);
+  const double hn = sqrt(sum_partials(npart, 1, nblk));
   if (blockIdx.x == 0 && threadIdx.x == 0) *hsub = cd{hn, 0.0};
   int i = blockIdx.x * KT + threadIdx.x;
   if (i >= n) return;
@@ -149,7 +161,7 @@ static grt_status ensure_workspace(grt_ctx* c, int m) {
   hipFree(c->d_V); hipFree(c->d_H);
   hipFree(c->d_y); hipFree(c->d_scal); hipFree(c->d_dotpart);
   const size_t n = (size_t)c->n_beta;
-  c->n_dot_blocks = (int)std::min<size_t>(16, (n + KT * 4 - 1) / (KT * 4));
+  c->n_dot_blocks = (int)std::min<size_t>(NBLK_MAX, (n + KT * 4 - 1) / (KT * 4));
   if (c->n_dot_blocks < 1) c->n_dot_blocks = 1;
   graph_reset(c);  // captured applies point into the workspace
   GRT_HIP(c, hipMalloc(&c->d_V, sizeof(cd) * n * (m + 5)));
