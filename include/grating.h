@@ -246,10 +246,15 @@ const char* grt_batch_error_message(const grt_batch* batch);
  * context's n_beta complex entries (its initial guess on entry when
  * opts->use_x0); stats (host, n entries, may be NULL) receives each problem's
  * iterations, restarts and final relative residual (seconds is the batch's).
- * opts->precision must be GRT_FP64 (GRT_EUNSUP otherwise); opts->maxit bounds
- * the lockstep steps of the whole batch; with opts->use_graph the batch's apply
- * (every kernel launch for all problems) is captured once as a HIP graph and
- * replayed at every step.  GRT_ENOCONV if any problem missed tol. */
+ * opts->precision GRT_FP64: lockstep GMRES on every problem in FP64.  GRT_FP32:
+ * lockstep FP64 iterative refinement (as in grt_solve: the residual b - K x in FP64,
+ * then GMRES on the operator with the FP32 translation of well-separated pairs to
+ * opts->inner_tol, at most opts->max_refine times); a problem whose FP64 residual
+ * meets tol takes no further corrections, and stats report its inner iterations
+ * and refinement steps.  opts->maxit bounds the lockstep steps of the whole batch;
+ * with opts->use_graph the batch's apply (every kernel launch for all problems; one
+ * graph per precision) is captured once as a HIP graph and replayed at every step.
+ * GRT_ENOCONV if any problem missed tol; GRT_EINVAL for another precision. */
 grt_status grt_batch_solve(grt_batch* batch, const grt_solve_opts* opts, void* const* beta,
                            grt_solve_stats* stats);
 

@@ -41,6 +41,13 @@ struct InstDesc {
   cd *pT, *pC, *pB, *pL, *gvec, *tvec, *wvec;
   int64_t off, nbeta;
   int seg0, nseg;
+  // mixed precision (GRT_FP32): FP32 partials of the well-separated pairs, near-pair
+  // CSR lists with their FP64 per-pair results and sums (the problem's own buffers)
+  cf* pT32;
+  cd *npart, *pN;
+  const int *noff, *nlist, *ntgt;
+  int n_near;
+  double zsafe;
 };
 
 struct Item {
@@ -68,6 +75,42 @@ __global__ void __launch_bounds__(64 * CX_WAVES) cx_batched(const InstDesc* __re
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
   cx_block<P>(q.g, q.cx, q.cy, X + q.off, q.pC, q.c_chunk, q.htab, w.x, w.y);
+}
+
+// FP32 translation of the well-separated pairs (near pairs, k2 rho < zsafe, skipped)
+template <int P>
+__global__ void __launch_bounds__(M2L_THREADS) m2l32_batched(const InstDesc* __restrict__ D,
+                                                             const Item* __restrict__ it,
+                                                             const cf* __restrict__ X32) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  m2l_block<P, cf>(q.cx, q.cy, X32 + q.off, q.pT32, q.M, q.m2l_chunk, q.g.k[1], q.g.d, q.g.alpha,
+                   q.g.alpha_inv, q.htab, q.zsafe, w.x, w.y);
+}
+
+// the near pairs [64 x, 64 x + 64) of a problem in FP64, one lane per pair
+template <int P>
+__global__ void __launch_bounds__(64) near_batched(const InstDesc* __restrict__ D,
+                                                   const Item* __restrict__ it,
+                                                   const cd* __restrict__ X) {
+  __shared__ double stab[HTAB_SIZE];
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  for (int t = threadIdx.x; t < HTAB_SIZE; t += 64) stab[t] = q.htab[t];
+  __syncthreads();
+  const int e = w.x * 64 + threadIdx.x;
+  if (e < q.n_near)
+    near_pair<P>(q.cx, q.cy, X + q.off, q.ntgt, q.nlist, q.npart, e, q.g.k[1], q.g.d, q.g.alpha,
+                 q.g.alpha_inv, stab);
+}
+
+// per-target sums of the near-pair results, entries [256 x, 256 x + 256) of a problem
+__global__ void __launch_bounds__(256) nred_batched(const InstDesc* __restrict__ D,
+                                                   const Item* __restrict__ it) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  const int idx = w.x * 256 + threadIdx.x;
+  if (idx < q.M * q.nb) near_reduce_entry(q.noff, q.npart, q.nb, q.pN, idx);
 }
 
 __global__ void __launch_bounds__(256) cxr_batched(const InstDesc* __restrict__ D,
@@ -171,9 +214,45 @@ __global__ void __launch_bounds__(BT) combine_batched(const InstDesc* __restrict
   }
 }
 
+// The mixed-precision apply, Y = D o (x - s o ((T32 x + T_near x) - B x)): FP32
+// partials of the well-separated pairs plus the FP64 near-pair sums.
+__global__ void __launch_bounds__(BT) combine_mixed_batched(const InstDesc* __restrict__ D,
+                                                            const int* __restrict__ seg2inst,
+                                                            const cd* __restrict__ X,
+                                                            const double* __restrict__ dn, cd* Y) {
+  const int seg = blockIdx.x;
+  const InstDesc& q = D[seg2inst[seg]];
+  for (int r = 0; r < SEG / BT; ++r) {
+    const int64_t i = (int64_t)seg * SEG + r * BT + threadIdx.x;
+    const int64_t loc = i - q.off;
+    if (loc >= q.nbeta) {
+      Y[i] = cd{0.0, 0.0};
+      continue;
+    }
+    cd b = q.pL[loc];
+    for (int c = 0; c < q.b_nchunks; ++c) b += q.pB[(size_t)c * q.nbeta + loc];
+    cd t = q.pN[loc];
+    for (int c = 0; c < q.m2l_nchunks; ++c) {
+      const cf v = q.pT32[(size_t)c * q.nbeta + loc];
+      t.r += v.r;
+      t.i += v.i;
+    }
+    Y[i] = dn[i] * (X[i] - q.mie[loc] * (t - b));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // batched Krylov kernels (concatenated vectors, per-problem reductions)
 // ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(BT) ew_to32_kernel(const cd* x, cf* y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (i < n) y[i] = cf{(float)x[i].r, (float)x[i].i};
+}
+__global__ void __launch_bounds__(BT) ew_add_kernel(cd* x, const cd* e, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (i < n) x[i] += e[i];
+}
 
 __global__ void __launch_bounds__(BT) ew_scale_kernel(const cd* x, const double* d, cd* y,
                                                       int64_t n) {
@@ -376,18 +455,20 @@ struct grt_batch {
   double *d_dnorm = nullptr, *d_dinv = nullptr;
   struct Group {
     int P;
-    Item *m2l = nullptr, *cx = nullptr, *bx = nullptr;
-    int n_m2l = 0, n_cx = 0, n_bx = 0;
+    Item *m2l = nullptr, *cx = nullptr, *bx = nullptr, *nr = nullptr;
+    int n_m2l = 0, n_cx = 0, n_bx = 0, n_nr = 0;
   };
   std::vector<Group> groups;
-  Item *it_cxr = nullptr, *it_g1 = nullptr, *it_g2 = nullptr, *it_l2l = nullptr;
-  int n_cxr = 0, n_g1 = 0, n_g2 = 0, n_l2l = 0;
+  Item *it_cxr = nullptr, *it_g1 = nullptr, *it_g2 = nullptr, *it_l2l = nullptr, *it_nred = nullptr;
+  int n_cxr = 0, n_g1 = 0, n_g2 = 0, n_l2l = 0, n_nred = 0;
+  cf* x32 = nullptr;      // FP32 copy of the apply's input (mixed precision)
   size_t l2l_smem = 0;
   // Krylov workspace
   int m = 0;
-  cd* V = nullptr;        // m + 5 slots of ntot: basis 0..m, iterate, rhs, apply in, out
+  cd* V = nullptr;        // m + 7 slots of ntot: basis 0..m, iterate, rhs, apply in, out,
+                          // refinement residual and correction
   cd *xtmp = nullptr, *wout = nullptr;   // slots m+3, m+4: the apply's fixed buffers
-  hipGraphExec_t graph = nullptr;       // captured batch_apply_core
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // captured batch_apply_core: FP64, mixed
   cd* H = nullptr;        // B x (m+1)^2
   cd *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h = nullptr;
   double *res = nullptr, *part = nullptr, *nrm = nullptr, *hn = nullptr, *bn = nullptr;
@@ -448,6 +529,11 @@ template <int P>
 static void launch_group_B(grt_batch* b, const grt_batch::Group& gp) {
   if (gp.n_bx) bx_batched<P><<<gp.n_bx, 64 * BX_WAVES, 0, b->stream>>>(b->dd, gp.bx);
 }
+template <int P>
+static void launch_group_T32(grt_batch* b, const grt_batch::Group& gp) {
+  if (gp.n_m2l) m2l32_batched<P><<<gp.n_m2l, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2l, b->x32);
+  if (gp.n_nr) near_batched<P><<<gp.n_nr, 64, 0, b->stream>>>(b->dd, gp.nr, b->xtmp);
+}
 
 // layer correction tail for all problems: t = W1 g (or f), w = W2 t, then B and L2L
 static grt_status batch_lowrank(grt_batch* b, int use_f) {
@@ -463,40 +549,55 @@ static grt_status batch_lowrank(grt_batch* b, int use_f) {
 // wout = D K D^{-1} x for every problem, x = D^{-1} xh already in xtmp (both fixed
 // buffers of the batch, so the whole launch sequence can be captured once as a HIP
 // graph and replayed; see batch_apply).
-static grt_status batch_apply_core(grt_batch* b) {
+// With mixed: the translation of well-separated pairs in FP32 (FP32 copy of x, FP32
+// accumulation) and of near pairs in FP64; C x, A^+ and B_phys w in FP64 as always.
+static grt_status batch_apply_core(grt_batch* b, bool mixed) {
   hipStream_t s = b->stream;
-  for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_T, gp.P, b, gp, b->xtmp);
+  if (mixed) {
+    const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
+    ew_to32_kernel<<<gn, BT, 0, s>>>(b->xtmp, b->x32, b->ntot);
+    for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_T32, gp.P, b, gp);
+    if (b->n_nred) nred_batched<<<b->n_nred, 256, 0, s>>>(b->dd, b->it_nred);
+  } else {
+    for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_T, gp.P, b, gp, b->xtmp);
+  }
   for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_C, gp.P, b, gp, b->xtmp);
   if (b->n_cxr) cxr_batched<<<b->n_cxr, 256, 0, s>>>(b->dd, b->it_cxr);
   BTRY(batch_lowrank(b, 0));
-  combine_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, b->xtmp, b->d_dnorm, b->wout, 0);
+  if (mixed)
+    combine_mixed_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, b->xtmp, b->d_dnorm,
+                                                 b->wout);
+  else
+    combine_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, b->xtmp, b->d_dnorm, b->wout, 0);
   BHIP(b, hipGetLastError());
   return GRT_OK;
 }
 
-// wout = D K D^{-1} xh (xh concatenated), the core replayed from a graph if asked
-static grt_status batch_apply(grt_batch* b, const cd* xh, bool use_graph) {
+// wout = D K D^{-1} xh (xh concatenated; K the mixed-precision operator if mixed),
+// the core replayed from a graph if asked
+static grt_status batch_apply(grt_batch* b, const cd* xh, bool use_graph, bool mixed) {
   hipStream_t s = b->stream;
   const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
   ew_scale_kernel<<<gn, BT, 0, s>>>(xh, b->d_dinv, b->xtmp, b->ntot);
-  if (!use_graph) return batch_apply_core(b);
-  if (!b->graph) {
+  if (!use_graph) return batch_apply_core(b, mixed);
+  hipGraphExec_t& ge = b->graph[mixed ? 1 : 0];
+  if (!ge) {
     hipGraph_t gr = nullptr;
     BHIP(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    grt_status st = batch_apply_core(b);
+    grt_status st = batch_apply_core(b, mixed);
     hipError_t e = hipStreamEndCapture(s, &gr);
     if (st != GRT_OK || e != hipSuccess) {
       if (gr) hipGraphDestroy(gr);
       return st != GRT_OK ? st : bset(b, GRT_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
     }
-    e = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
     hipGraphDestroy(gr);
     if (e != hipSuccess) {
-      b->graph = nullptr;
+      ge = nullptr;
       return bset(b, GRT_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
   }
-  BHIP(b, hipGraphLaunch(b->graph, s));
+  BHIP(b, hipGraphLaunch(ge, s));
   return GRT_OK;
 }
 
@@ -521,11 +622,12 @@ static grt_status batch_workspace(grt_batch* b, int m) {
   for (void* p : olds)
     if (p) hipFree(p);
   const size_t B = b->B, n = b->ntot, ld = m + 1;
-  if (b->graph) {  // the captured apply points into the old workspace
-    hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-  }
-  BHIP(b, hipMalloc(&b->V, sizeof(cd) * n * (m + 5)));
+  for (hipGraphExec_t& ge : b->graph)  // the captured applies point into the old workspace
+    if (ge) {
+      hipGraphExecDestroy(ge);
+      ge = nullptr;
+    }
+  BHIP(b, hipMalloc(&b->V, sizeof(cd) * n * (m + 7)));
   b->xtmp = b->V + n * (m + 3);
   b->wout = b->V + n * (m + 4);
   BHIP(b, hipMalloc(&b->H, sizeof(cd) * B * ld * ld));
@@ -555,6 +657,129 @@ static grt_status read_vec(grt_batch* b, const double* dev, std::vector<double>&
   BHIP(b, hipMemcpyAsync(b->h_pinned, dev, sizeof(double) * b->B, hipMemcpyDeviceToHost, b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
   std::memcpy(out.data(), b->h_pinned, sizeof(double) * b->B);
+  return GRT_OK;
+}
+
+// Per-problem outcome of a lockstep GMRES run.
+struct LockstepResult {
+  std::vector<int> iters, cycles, rejected;
+  std::vector<double> rel;
+  int steps = 0;  // lockstep Arnoldi steps taken (the longest problem's count)
+  explicit LockstepResult(int B) : iters(B, 0), cycles(B, 0), rejected(B, 0), rel(B, 1.0) {}
+};
+
+// Restarted GMRES for all problems in lockstep on D K D^{-1} X = Bv (K the mixed
+// operator if mixed): X (normalised, in place) from its current value.  A problem
+// stops updating once its residual estimate reaches tol ||Bv_i|| (a problem with
+// Bv_i = 0 is done at once).  With guard, an initial X_i no better than zero is
+// dropped and that problem restarts from zero.
+static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, double tol,
+                              int maxit, int m, bool guard, bool use_graph, LockstepResult& r) {
+  hipStream_t s = b->stream;
+  const int B = b->B, ld = m + 1;
+  const size_t ldv = (size_t)b->ntot;
+  cd* V = b->V;
+  BTRY(batch_norms(b, Bv, b->bn));
+  std::vector<double> bn, beta0;
+  BTRY(read_vec(b, b->bn, bn));
+  std::vector<int> kk(B, 0);
+  std::vector<char> done(B, 0);
+  int total = 0;
+  while (true) {
+    // R = B - K X into V_0
+    BTRY(batch_apply(b, X, use_graph, mixed));
+    {
+      const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
+      ew_sub_kernel<<<gn, BT, 0, s>>>(Bv, b->wout, V, b->ntot);
+    }
+    BTRY(batch_norms(b, V, b->nrm));
+    BTRY(read_vec(b, b->nrm, beta0));
+    bool any = false, reject = false;
+    for (int i = 0; i < B; ++i) {
+      r.rel[i] = bn[i] > 0 ? beta0[i] / bn[i] : 0.0;
+      done[i] = r.rel[i] <= tol;
+      if (!done[i]) any = true;
+      if (guard && r.rel[i] >= 1.0) {
+        r.rejected[i] = 1;
+        reject = true;
+      }
+    }
+    if (guard) {
+      guard = false;
+      if (reject) {
+        // initial guesses no better than zero are dropped: those problems restart
+        // from x = 0 (the residual is then recomputed for the whole batch)
+        BHIP(b, hipMemcpyAsync(b->d_k, r.rejected.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+        zero_rejected_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, b->d_k, X);
+        BHIP(b, hipGetLastError());
+        continue;
+      }
+    }
+    if (!any || total >= maxit) break;
+    inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, b->nrm, V);
+    inst_init_g_kernel<<<(B * (ld + 1) + 255) / 256, 256, 0, s>>>(B, ld + 1, b->nrm, b->g);
+    BHIP(b, hipMemsetAsync(b->H, 0, sizeof(cd) * (size_t)B * ld * ld, s));
+    std::fill(kk.begin(), kk.end(), -1);
+    for (int i = 0; i < B; ++i)
+      if (done[i]) kk[i] = 0;
+    int steps = 0;
+    // residual estimates of step jj, in the pinned buffer of parity jj & 1
+    double* hbuf[2] = {b->h_pinned + B, b->h_pinned + 2 * B};
+    auto check = [&](int jj) {
+      bool all = true;
+      for (int i = 0; i < B; ++i) {
+        if (kk[i] >= 0) continue;
+        if (hbuf[jj & 1][i] <= tol * bn[i]) kk[i] = jj + 1;
+        else all = false;
+      }
+      return all;
+    };
+    bool all = false;
+    for (int j = 0; j < m && total + j < maxit; ++j) {
+      cd* w = b->wout;  // the new directions; normalised into V_{j+1} below
+      BTRY(batch_apply(b, V + (size_t)j * ldv, use_graph, mixed));
+      for (int pass = 0; pass < 2; ++pass) {
+        seg_dots_kernel<<<b->nseg, BT, 0, s>>>(V, ldv, w, j + 1, b->nseg, b->dpart);
+        inst_dots_kernel<<<(B * (j + 1) + 255) / 256, 256, 0, s>>>(b->dd, B, j + 1, b->nseg,
+                                                                  b->dpart, b->h, ld, b->H, ld, j,
+                                                                  pass);
+        seg_update_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, ldv, w, j + 1, b->h, ld);
+      }
+      BTRY(batch_norms(b, w, b->nrm));
+      inst_givens_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->nrm, b->H, ld, b->cs, b->sn, b->g, j,
+                                                      b->hn, b->res, ld);
+      inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, w, b->hn, V + (size_t)(j + 1) * ldv);
+      BHIP(b, hipGetLastError());
+      BHIP(b, hipMemcpy2DAsync(hbuf[j & 1], sizeof(double), b->res + j, sizeof(double) * ld,
+                               sizeof(double), B, hipMemcpyDeviceToHost, s));
+      BHIP(b, hipEventRecord(b->ev[j & 1], s));
+      steps = j + 1;
+      // the host checks step j-1 while the GPU runs step j
+      if (j >= 1) {
+        BHIP(b, hipEventSynchronize(b->ev[(j - 1) & 1]));
+        if (check(j - 1)) {
+          all = true;
+          break;
+        }
+      }
+    }
+    if (!all && steps > 0) {
+      BHIP(b, hipEventSynchronize(b->ev[(steps - 1) & 1]));
+      check(steps - 1);
+    }
+    for (int i = 0; i < B; ++i)
+      if (kk[i] < 0) kk[i] = steps;
+    total += steps;
+    BHIP(b, hipMemcpyAsync(b->d_k, kk.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+    inst_backsolve_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->H, ld, b->g, b->d_k, b->y);
+    seg_axpy_basis_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, X, V, ldv, b->y, ld, b->d_k);
+    BHIP(b, hipGetLastError());
+    for (int i = 0; i < B; ++i) {
+      r.iters[i] += kk[i];
+      if (kk[i] > 0) r.cycles[i] += 1;
+    }
+  }
+  r.steps = total;
   return GRT_OK;
 }
 
@@ -624,6 +849,14 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     q.tvec = c->d_tvec;
     q.wvec = c->d_wvec;
     q.nbeta = c->n_beta;
+    q.pT32 = c->d_x32 ? c->d_pT32 : nullptr;
+    q.npart = c->d_npart;
+    q.pN = c->d_pN;
+    q.noff = c->d_noff;
+    q.nlist = c->d_nlist;
+    q.ntgt = c->d_ntgt;
+    q.n_near = (int)c->n_near;
+    q.zsafe = c->zsafe;
     q.seg0 = seg;
     q.nseg = (int)((c->n_beta + SEG - 1) / SEG);
     q.off = (int64_t)seg * SEG;
@@ -636,14 +869,15 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
   b->ntot = (int64_t)seg * SEG;
   b->l2l_smem = smem;
   // work items
-  std::vector<Item> cxr, g1, g2, l2l;
+  std::vector<Item> cxr, g1, g2, l2l, nred;
   for (auto& kv : byP) {
     grt_batch::Group gp;
     gp.P = kv.first;
-    std::vector<Item> m2l, cxv, bxv;
+    std::vector<Item> m2l, cxv, bxv, nr;
     for (int i : kv.second) {
       const InstDesc& q = b->hd[i];
       const int nt = 2 * q.g.N + q.g.Nw[1];
+      for (int x = 0; x < (q.n_near + 63) / 64; ++x) nr.push_back({i, x, 0});
       for (int y = 0; y < q.m2l_nchunks; ++y)
         for (int x = 0; x < (q.M + 63) / 64; ++x) m2l.push_back({i, x, y});
       for (int y = 0; y < q.c_nchunks; ++y)
@@ -653,10 +887,13 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     }
     grt_status st;
     if ((st = upload(b, m2l, &gp.m2l)) != GRT_OK || (st = upload(b, cxv, &gp.cx)) != GRT_OK ||
-        (st = upload(b, bxv, &gp.bx)) != GRT_OK) {
-      delete b;
+        (st = upload(b, bxv, &gp.bx)) != GRT_OK || (st = upload(b, nr, &gp.nr)) != GRT_OK) {
+      for (void* q : {(void*)gp.m2l, (void*)gp.cx, (void*)gp.bx, (void*)gp.nr})
+        if (q) hipFree(q);
+      grt_batch_destroy(b);
       return st;
     }
+    gp.n_nr = (int)nr.size();
     gp.n_m2l = (int)m2l.size();
     gp.n_cx = (int)cxv.size();
     gp.n_bx = (int)bxv.size();
@@ -668,6 +905,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     for (int x = 0; x < (nt + 3) / 4; ++x) cxr.push_back({i, x, 0});
     for (int x = 0; x < (q.rank + 3) / 4; ++x) g1.push_back({i, x, 0});
     for (int x = 0; x < (q.n_b + 3) / 4; ++x) g2.push_back({i, x, 0});
+    for (int x = 0; x < (q.M * q.nb + 255) / 256; ++x) nred.push_back({i, x, 0});
     {
       const int ntb = l2l_targets_per_block(q.P, q.Q2);  // carried in the item's y
       for (int x = 0; x < (q.M + ntb - 1) / ntb; ++x) l2l.push_back({i, x, ntb});
@@ -685,15 +923,21 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
   if ((st = upload(b, cxr, &b->it_cxr)) != GRT_OK || (st = upload(b, g1, &b->it_g1)) != GRT_OK ||
       (st = upload(b, g2, &b->it_g2)) != GRT_OK || (st = upload(b, l2l, &b->it_l2l)) != GRT_OK ||
       (st = upload(b, seg2inst, &b->d_seg2inst)) != GRT_OK ||
+      (st = upload(b, nred, &b->it_nred)) != GRT_OK ||
       (st = upload(b, b->hd, &b->dd)) != GRT_OK || (st = upload(b, dn, &b->d_dnorm)) != GRT_OK ||
       (st = upload(b, di, &b->d_dinv)) != GRT_OK) {
-    delete b;
+    grt_batch_destroy(b);
     return st;
   }
   b->n_cxr = (int)cxr.size();
   b->n_g1 = (int)g1.size();
   b->n_g2 = (int)g2.size();
   b->n_l2l = (int)l2l.size();
+  b->n_nred = (int)nred.size();
+  if (hipMalloc(&b->x32, sizeof(cf) * (size_t)b->ntot) != hipSuccess) {
+    grt_batch_destroy(b);
+    return GRT_ENOMEM;
+  }
   *out = b;
   return GRT_OK;
 }
@@ -703,16 +947,19 @@ grt_status grt_batch_destroy(grt_batch* b) {
   hipSetDevice(b->device);
   if (b->stream) hipStreamSynchronize(b->stream);
   std::vector<void*> p = {b->dd, b->d_seg2inst, b->d_dnorm, b->d_dinv, b->it_cxr, b->it_g1,
-                          b->it_g2, b->it_l2l, b->V, b->H, b->cs, b->sn, b->g, b->y, b->h,
-                          b->res, b->part, b->nrm, b->hn, b->bn, b->dpart, b->d_k};
+                          b->it_g2, b->it_l2l, b->it_nred, b->x32, b->V, b->H, b->cs, b->sn,
+                          b->g, b->y, b->h, b->res, b->part, b->nrm, b->hn, b->bn, b->dpart,
+                          b->d_k};
   for (auto& gp : b->groups) {
     p.push_back(gp.m2l);
     p.push_back(gp.cx);
     p.push_back(gp.bx);
+    p.push_back(gp.nr);
   }
   for (void* q : p)
     if (q) hipFree(q);
-  if (b->graph) hipGraphExecDestroy(b->graph);
+  for (hipGraphExec_t ge : b->graph)
+    if (ge) hipGraphExecDestroy(ge);
   if (b->h_pinned) hipHostFree(b->h_pinned);
   for (hipEvent_t e : b->ev)
     if (e) hipEventDestroy(e);
@@ -729,7 +976,8 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
                            grt_solve_stats* stats) {
   if (!b || !o || !beta) return GRT_EINVAL;
   b->err.clear();
-  if (o->precision != GRT_FP64) return bset(b, GRT_EUNSUP, "batched solves run in GRT_FP64");
+  if (o->precision != GRT_FP64 && o->precision != GRT_FP32)
+    return bset(b, GRT_EINVAL, "precision must be GRT_FP64 or GRT_FP32");
   if (!(o->tol > 0 && o->tol < 1)) return bset(b, GRT_EINVAL, "tol must be in (0, 1)");
   BHIP(b, hipSetDevice(b->device));
   auto t0 = std::chrono::steady_clock::now();
@@ -738,12 +986,11 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
   const double tol = o->tol;
   BTRY(batch_workspace(b, m));
   hipStream_t s = b->stream;
-  const int B = b->B, ld = m + 1;
+  const int B = b->B;
   const size_t ldv = (size_t)b->ntot;
   const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
-  cd* V = b->V;
-  cd* X = V + (size_t)(m + 1) * ldv;      // iterate (normalised)
-  cd* Bv = V + (size_t)(m + 2) * ldv;     // right-hand side (normalised)
+  cd* X = b->V + (size_t)(m + 1) * ldv;   // iterate (normalised)
+  cd* Bv = b->V + (size_t)(m + 2) * ldv;  // right-hand side (normalised)
   const bool use_graph = o->use_graph != 0;
   // x0 and b
   BTRY(batch_rhs_hat(b, Bv));
@@ -755,104 +1002,72 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
     }
     ew_scale_kernel<<<gn, BT, 0, s>>>(X, b->d_dnorm, X, b->ntot);
   }
-  BTRY(batch_norms(b, Bv, b->bn));
-  std::vector<double> bn, beta0;
-  BTRY(read_vec(b, b->bn, bn));
-  std::vector<int> kk(B, 0), iters(B, 0), cycles(B, 0);
-  std::vector<double> rel(B, 1.0);
-  std::vector<char> done(B, 0);
-  std::vector<int> rejected(B, 0);
-  bool guard = o->use_x0 != 0;
-  int total = 0;
-  while (true) {
-    // R = B - K X into V_0
-    BTRY(batch_apply(b, X, use_graph));
-    ew_sub_kernel<<<gn, BT, 0, s>>>(Bv, b->wout, V, b->ntot);
-    BTRY(batch_norms(b, V, b->nrm));
-    BTRY(read_vec(b, b->nrm, beta0));
-    bool any = false, reject = false;
-    for (int i = 0; i < B; ++i) {
-      rel[i] = bn[i] > 0 ? beta0[i] / bn[i] : 0.0;
-      done[i] = rel[i] <= tol;
-      if (!done[i]) any = true;
-      if (guard && rel[i] >= 1.0) {
-        rejected[i] = 1;
-        reject = true;
-      }
-    }
-    if (guard) {
-      guard = false;
-      if (reject) {
-        // initial guesses no better than zero are dropped: those problems restart
-        // from x = 0 (the residual is then recomputed for the whole batch)
-        BHIP(b, hipMemcpyAsync(b->d_k, rejected.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
-        zero_rejected_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, b->d_k, X);
-        BHIP(b, hipGetLastError());
-        continue;
-      }
-    }
-    if (!any || total >= maxit) break;
-    inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, b->nrm, V);
-    inst_init_g_kernel<<<(B * (ld + 1) + 255) / 256, 256, 0, s>>>(B, ld + 1, b->nrm, b->g);
-    BHIP(b, hipMemsetAsync(b->H, 0, sizeof(cd) * (size_t)B * ld * ld, s));
-    std::fill(kk.begin(), kk.end(), -1);
-    for (int i = 0; i < B; ++i)
-      if (done[i]) kk[i] = 0;
-    int steps = 0;
-    // residual estimates of step jj, in the pinned buffer of parity jj & 1
-    double* hbuf[2] = {b->h_pinned + B, b->h_pinned + 2 * B};
-    auto check = [&](int jj) {
-      bool all = true;
+  LockstepResult r(B);
+  std::vector<int> refine(B, 0);
+  if (o->precision == GRT_FP64) {
+    BTRY(batch_gmres(b, false, Bv, X, tol, maxit, m, o->use_x0 != 0, use_graph, r));
+  } else {
+    // FP64 iterative refinement around the mixed-precision operator, for all
+    // problems in lockstep: R = B - K X (FP64), solve K32 E = R to inner_tol, X += E.
+    // A problem whose FP64 residual meets tol gets R = 0, so the inner solve leaves
+    // it alone.
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+    const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
+    cd* R = b->V + (size_t)(m + 5) * ldv;
+    cd* E = b->V + (size_t)(m + 6) * ldv;
+    std::vector<double> bn, rn;
+    BTRY(batch_norms(b, Bv, b->bn));
+    BTRY(read_vec(b, b->bn, bn));
+    std::vector<int> flag(B, 0);
+    bool guard = o->use_x0 != 0;
+    int total = 0;
+    for (int outer = 0; outer <= max_ref; ++outer) {
+      BTRY(batch_apply(b, X, use_graph, false));
+      ew_sub_kernel<<<gn, BT, 0, s>>>(Bv, b->wout, R, b->ntot);
+      BTRY(batch_norms(b, R, b->nrm));
+      BTRY(read_vec(b, b->nrm, rn));
+      bool any = false, reject = false;
       for (int i = 0; i < B; ++i) {
-        if (kk[i] >= 0) continue;
-        if (hbuf[jj & 1][i] <= tol * bn[i]) kk[i] = jj + 1;
-        else all = false;
-      }
-      return all;
-    };
-    bool all = false;
-    for (int j = 0; j < m && total + j < maxit; ++j) {
-      cd* w = b->wout;  // the new directions; normalised into V_{j+1} below
-      BTRY(batch_apply(b, V + (size_t)j * ldv, use_graph));
-      for (int pass = 0; pass < 2; ++pass) {
-        seg_dots_kernel<<<b->nseg, BT, 0, s>>>(V, ldv, w, j + 1, b->nseg, b->dpart);
-        inst_dots_kernel<<<(B * (j + 1) + 255) / 256, 256, 0, s>>>(b->dd, B, j + 1, b->nseg,
-                                                                  b->dpart, b->h, ld, b->H, ld, j,
-                                                                  pass);
-        seg_update_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, ldv, w, j + 1, b->h, ld);
-      }
-      BTRY(batch_norms(b, w, b->nrm));
-      inst_givens_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->nrm, b->H, ld, b->cs, b->sn, b->g, j,
-                                                      b->hn, b->res, ld);
-      inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, w, b->hn, V + (size_t)(j + 1) * ldv);
-      BHIP(b, hipGetLastError());
-      BHIP(b, hipMemcpy2DAsync(hbuf[j & 1], sizeof(double), b->res + j, sizeof(double) * ld,
-                               sizeof(double), B, hipMemcpyDeviceToHost, s));
-      BHIP(b, hipEventRecord(b->ev[j & 1], s));
-      steps = j + 1;
-      // the host checks step j-1 while the GPU runs step j
-      if (j >= 1) {
-        BHIP(b, hipEventSynchronize(b->ev[(j - 1) & 1]));
-        if (check(j - 1)) {
-          all = true;
-          break;
+        r.rel[i] = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+        if (guard && r.rel[i] >= 1.0) {
+          r.rejected[i] = 1;
+          reject = true;
         }
       }
-    }
-    if (!all && steps > 0) {
-      BHIP(b, hipEventSynchronize(b->ev[(steps - 1) & 1]));
-      check(steps - 1);
-    }
-    for (int i = 0; i < B; ++i)
-      if (kk[i] < 0) kk[i] = steps;
-    total += steps;
-    BHIP(b, hipMemcpyAsync(b->d_k, kk.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
-    inst_backsolve_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->H, ld, b->g, b->d_k, b->y);
-    seg_axpy_basis_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, X, V, ldv, b->y, ld, b->d_k);
-    BHIP(b, hipGetLastError());
-    for (int i = 0; i < B; ++i) {
-      iters[i] += kk[i];
-      if (kk[i] > 0) cycles[i] += 1;
+      if (guard) {
+        guard = false;
+        if (reject) {
+          // initial guesses no better than zero are dropped (residual recomputed)
+          BHIP(b, hipMemcpyAsync(b->d_k, r.rejected.data(), sizeof(int) * B,
+                                 hipMemcpyHostToDevice, s));
+          zero_rejected_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, b->d_k, X);
+          BHIP(b, hipGetLastError());
+          --outer;
+          continue;
+        }
+      }
+      for (int i = 0; i < B; ++i) {
+        flag[i] = r.rel[i] <= tol;
+        if (!flag[i]) {
+          any = true;
+          refine[i] = outer;
+        }
+      }
+      if (!any || outer == max_ref || total >= maxit) break;
+      BHIP(b, hipMemcpyAsync(b->d_k, flag.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+      zero_rejected_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, b->d_k, R);
+      BHIP(b, hipMemsetAsync(E, 0, sizeof(cd) * ldv, s));
+      LockstepResult ri(B);
+      BTRY(batch_gmres(b, true, R, E, itol, maxit - total, m, false, use_graph, ri));
+      total += ri.steps;
+      for (int i = 0; i < B; ++i) {
+        r.iters[i] += ri.iters[i];
+        r.cycles[i] += ri.cycles[i];
+      }
+      ew_add_kernel<<<gn, BT, 0, s>>>(X, E, b->ntot);
+      BHIP(b, hipGetLastError());
+      for (int i = 0; i < B; ++i)
+        if (!flag[i]) refine[i] = outer + 1;
     }
   }
   // back to beta = D^{-1} x^, scattered to the callers' vectors
@@ -867,13 +1082,14 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
   for (int i = 0; i < B; ++i) {
     if (stats) {
       stats[i] = grt_solve_stats{};
-      stats[i].iters = iters[i];
-      stats[i].cycles = cycles[i];
-      stats[i].rel_resid = rel[i];
+      stats[i].iters = r.iters[i];
+      stats[i].cycles = r.cycles[i];
+      stats[i].rel_resid = r.rel[i];
       stats[i].seconds = secs;
-      stats[i].x0_rejected = rejected[i];
+      stats[i].refine_steps = refine[i];
+      stats[i].x0_rejected = r.rejected[i];
     }
-    if (!(rel[i] <= tol)) conv = false;
+    if (!(r.rel[i] <= tol)) conv = false;
   }
   return conv ? GRT_OK : bset(b, GRT_ENOCONV, "some problems did not reach the tolerance");
 }

@@ -535,21 +535,17 @@ __device__ __forceinline__ void m2l_table2_block(const cd* __restrict__ table,
 // FP64 translation over the near pairs (the pairs the FP32 pass leaves out): one
 // lane per pair (target ntgt[e], source nlist[e]); each pair's contribution goes to
 // its own row of part, summed per target in list order by near_reduce_kernel.
+// One near pair e of the CSR list (target ntgt[e], source nlist[e]) in FP64:
+// part[e][n] = sum over the three copies of T(j <- m) x_m (stab: the H_0/H_1 table,
+// already in LDS).
 template <int P>
-__global__ void __launch_bounds__(64) m2l_near_kernel(const double* __restrict__ cx,
-                                                      const double* __restrict__ cy,
-                                                      const cd* __restrict__ x,
-                                                      const int* __restrict__ ntgt,
-                                                      const int* __restrict__ nlist, cd* part,
-                                                      int npairs, double k, double d, cd alpha,
-                                                      cd alpha_inv,
-                                                      const double* __restrict__ htab) {
+__device__ __forceinline__ void near_pair(const double* __restrict__ cx,
+                                          const double* __restrict__ cy,
+                                          const cd* __restrict__ x, const int* __restrict__ ntgt,
+                                          const int* __restrict__ nlist, cd* part, int e,
+                                          double k, double d, cd alpha, cd alpha_inv,
+                                          const double* stab) {
   constexpr int NB = 2 * P + 1;
-  __shared__ double stab[HTAB_SIZE];
-  for (int t = threadIdx.x; t < HTAB_SIZE; t += 64) stab[t] = htab[t];
-  __syncthreads();
-  const int e = blockIdx.x * 64 + threadIdx.x;
-  if (e >= npairs) return;
   const int j = ntgt[e], m = nlist[e];
   cd acc[NB];
 #pragma unroll
@@ -562,15 +558,37 @@ __global__ void __launch_bounds__(64) m2l_near_kernel(const double* __restrict__
   for (int n = 0; n < NB; ++n) o[n] = acc[n];
 }
 
-// out[j][n] = sum over the near pairs of target j (CSR order) of part[e][n]
-static __global__ void near_reduce_kernel(const int* __restrict__ noff, const cd* __restrict__ part,
-                                   int M, int NB, cd* out) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= M * NB) return;
-  int j = idx / NB, n = idx - j * NB;
+template <int P>
+__global__ void __launch_bounds__(64) m2l_near_kernel(const double* __restrict__ cx,
+                                                      const double* __restrict__ cy,
+                                                      const cd* __restrict__ x,
+                                                      const int* __restrict__ ntgt,
+                                                      const int* __restrict__ nlist, cd* part,
+                                                      int npairs, double k, double d, cd alpha,
+                                                      cd alpha_inv,
+                                                      const double* __restrict__ htab) {
+  __shared__ double stab[HTAB_SIZE];
+  for (int t = threadIdx.x; t < HTAB_SIZE; t += 64) stab[t] = htab[t];
+  __syncthreads();
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  if (e < npairs) near_pair<P>(cx, cy, x, ntgt, nlist, part, e, k, d, alpha, alpha_inv, stab);
+}
+
+// out[idx] for idx = j NB + n: the sum over the near pairs of target j (CSR order) of
+// part[e][n]
+__device__ __forceinline__ void near_reduce_entry(const int* __restrict__ noff,
+                                                  const cd* __restrict__ part, int NB, cd* out,
+                                                  int idx) {
+  const int j = idx / NB, n = idx - j * NB;
   cd s{0, 0};
   for (int e = noff[j]; e < noff[j + 1]; ++e) s += part[(size_t)e * NB + n];
   out[idx] = s;
+}
+
+static __global__ void near_reduce_kernel(const int* __restrict__ noff, const cd* __restrict__ part,
+                                          int M, int NB, cd* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < M * NB) near_reduce_entry(noff, part, NB, out, idx);
 }
 
 constexpr int CX_WAVES = 4;   // waves per block: same 64 targets, sources split 4 ways

@@ -374,16 +374,18 @@ class Batch:
         except Exception:
             pass
 
-    def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, check=True, graph=False):
-        """Returns (list of beta vectors, list of grt_solve_stats)."""
+    def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, check=True, graph=False,
+              precision=None, inner_tol=0.0, max_refine=0):
+        """Returns (list of beta vectors, list of grt_solve_stats).  precision
+        GRT_FP32: FP32 translation inside lockstep FP64 refinement."""
         betas = [c.new_vec() for c in self.ctxs]
         if x0 is not None:
             for b, x in zip(betas, x0):
                 b.copy_(x)
         ptrs = (_VP * len(betas))(*[c._vec_ptr(b) for c, b in zip(self.ctxs, betas)])
         opts = grt_solve_opts(tol=tol, maxit=maxit, restart=restart, use_x0=int(x0 is not None),
-                              precision=GRT_FP64, inner_tol=0.0, max_refine=0,
-                              use_graph=int(graph))
+                              precision=GRT_FP64 if precision is None else precision,
+                              inner_tol=inner_tol, max_refine=max_refine, use_graph=int(graph))
         stats = (grt_solve_stats * len(betas))()
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         st = self.lib.grt_batch_solve(self.h, C.byref(opts), ptrs, stats)

@@ -227,7 +227,7 @@ def test_batched_solve_matches_single_and_oracle(torch_cuda):
 
 def test_batched_rejects_bad_input(torch_cuda):
     from paper_1412_7466_amd.grating import (Batch, Context, GratingError, GRT_ESTATE,
-                                             GRT_EUNSUP, grt_solve_opts, grt_solve_stats,
+                                             GRT_EINVAL, grt_solve_opts, grt_solve_stats,
                                              _VP)
     import ctypes as C
     empty = _ctx(inputs.empty_slab())
@@ -242,11 +242,45 @@ def test_batched_rejects_bad_input(torch_cuda):
     ctx = _ctx(inputs.small(3, 2, seed=5))
     batch = Batch([ctx])
     beta = ctx.new_vec()
-    opts = grt_solve_opts(tol=1e-9, maxit=10, restart=10, use_x0=0, precision=1,
+    opts = grt_solve_opts(tol=1e-9, maxit=10, restart=10, use_x0=0, precision=7,
                           inner_tol=1e-5, max_refine=1)
     ptrs = (_VP * 1)(_VP(beta.data_ptr()))
     st = batch.lib.grt_batch_solve(batch.h, C.byref(opts), ptrs, (grt_solve_stats * 1)())
-    assert st == GRT_EUNSUP
+    assert st == GRT_EINVAL
+
+
+def test_batched_mixed_precision_refinement(torch_cuda):
+    """Lockstep FP64 refinement around the FP32 translation, over problems of
+    different M, P, angle and omega: every problem reaches its oracle solution to the
+    1e-9 bar with an FP64 residual at tol, the same as the single mixed solver; the
+    graph-replayed mixed apply gives the same results; a warm start from the
+    solution takes no correction."""
+    from oracle.solver import Reduced
+    from paper_1412_7466_amd.grating import Batch, GRT_FP32
+    pbs = _batch_problems()
+    ctxs = [_ctx(pb) for pb in pbs]
+    batch = Batch(ctxs)
+    betas, stats = batch.solve(tol=1e-11, restart=150, precision=GRT_FP32, inner_tol=1e-5)
+    for pb, ctx, b, st in zip(pbs, ctxs, betas, stats):
+        beta_o = Reduced(pb).solve_lu()
+        bs, ss = ctx.solve(tol=1e-11, restart=150, precision=GRT_FP32, inner_tol=1e-5)
+        say(f"[gpu] batch mixed {pb.name} iters={st.iters} refine={st.refine_steps} "
+            f"(single {ss.iters}, {ss.refine_steps}) resid={st.rel_resid:.2e}")
+        assert st.rel_resid <= 1e-11
+        assert st.refine_steps >= 1
+        assert rel(_np(b), beta_o) < 1e-9
+        assert rel(_np(b), _np(bs)) < 1e-9
+    for rep in range(2):
+        bg, sg = batch.solve(tol=1e-11, restart=150, precision=GRT_FP32, inner_tol=1e-5,
+                             graph=True)
+        torch_cuda.cuda.synchronize()
+        for b, b2, st, st2 in zip(betas, bg, stats, sg):
+            assert st2.iters == st.iters and st2.refine_steps == st.refine_steps
+            assert rel(_np(b2), _np(b)) < 1e-14, rep
+        ctxs[0].apply(betas[0])
+    betas2, stats2 = batch.solve(tol=1e-11, restart=150, precision=GRT_FP32, x0=betas)
+    assert all(s2.iters == 0 and s2.refine_steps == 0 for s2 in stats2)
+    batch.close()
 
 
 def test_layer_factors_shared_between_contexts(torch_cuda):
