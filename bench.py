@@ -15,8 +15,10 @@ two; `roofline` is for that run's translation kernel (the dominant one), timed
 with HIP events on the library stream during the timed solves, and
 `roofline_on_the_fly` / `roofline_table` give both.  `sweep` compares, on held-out
 geometries of the warm-start set, sequential plain FP64 solves with one batched
-solve, cold and warm-started by the trained network.  `cpu_baseline` times the
-CPU FP64 oracle on a bounded sample of the same work.
+solve, in FP64 and in mixed precision (FP32 translation, FP64 refinement), cold and
+warm-started by the trained network (mixed + batched + warm-start against plain
+FP64, prediction time included).  `cpu_baseline` times the CPU FP64 oracle on a
+bounded sample of the same work.
 """
 import argparse
 import json
@@ -131,7 +133,7 @@ def sweep(a, torch):
     after another against one batched solve, cold and warm-started."""
     import numpy as np
     from paper_1412_7466_amd import inputs
-    from paper_1412_7466_amd.grating import Batch, Context, Network
+    from paper_1412_7466_amd.grating import Batch, Context, Network, GRT_FP32
     wpath = os.path.join(ROOT, "paper_1412_7466_amd", "warm_start.npz")
     phi = -math.pi / 5
     pbs = [inputs.warm_problem(i, held_out=True, phis=(phi,)) for i in range(a.sweep_n)]
@@ -164,13 +166,32 @@ def sweep(a, torch):
     bb, sb = batch.solve(tol=a.tol, restart=a.restart)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t
+
+    def batched_mixed(x0s_fn=None):
+        """one batched solve in mixed precision (FP32 translation, FP64 refinement),
+        applies replayed from a captured graph; x0s_fn's prediction time included"""
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x0s = None if x0s_fn is None else x0s_fn()
+        out = batch.solve(tol=a.tol, restart=a.restart, precision=GRT_FP32, graph=True, x0=x0s)
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    batched_mixed()
+    (bm, sm), t_bmixed = batched_mixed()
     res = {"workload": (f"{a.sweep_n} held-out geometries of the warm-start set: M=1000 rules "
                         f"with M uniform in [200, 2000], omega=20, phi=-pi/5, P=15, GMRES to "
                         f"{a.tol:g}"),
            "M": [pb.M for pb in pbs], "build_s": t_build,
            "plain_fp64_sequential_solves_per_s": len(ctxs) / t_plain,
            "batched_fp64_solves_per_s": len(ctxs) / t_batch,
+           "batched_mixed_solves_per_s": len(ctxs) / t_bmixed,
            "iters_cold": [s.iters for _, s in plain],
+           "iters_batched_mixed": [s.iters for s in sm],
+           "refine_steps_batched_mixed": [s.refine_steps for s in sm],
+           "batched_mixed_max_rel_diff_vs_plain": max(
+               float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
+               for b, (p, _) in zip(bm, plain)),
            "batched_max_rel_diff_vs_plain": max(
                float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
                for b, (p, _) in zip(bb, plain))}
@@ -193,11 +214,18 @@ def sweep(a, torch):
         bw, sw = batch.solve(tol=a.tol, restart=a.restart, x0=x0s)
         torch.cuda.synchronize()
         t_bw = time.perf_counter() - t
+        (bmw, smw), t_bmw = batched_mixed(lambda: [net.predict(c) for c in ctxs])
         res.update({"predict_s": t_pred,
                     "warm_fp64_sequential_solves_per_s": len(ctxs) / (t_warm + t_pred),
                     "batched_warm_fp64_solves_per_s": len(ctxs) / t_bw,
+                    "mixed_batched_warm_solves_per_s": len(ctxs) / t_bmw,
                     "iters_warm": [s.iters for _, s in warm],
-                    "warm_rejected": int(sum(s.x0_rejected for s in sw))})
+                    "iters_mixed_batched_warm": [s.iters for s in smw],
+                    "warm_rejected": int(sum(s.x0_rejected for s in sw)),
+                    "mixed_batched_warm_max_rel_diff_vs_plain": max(
+                        float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
+                        for b, (p, _) in zip(bmw, plain)),
+                    "mixed_batched_warm_vs_plain_fp64": t_plain / t_bmw})
         net.close()
     batch.close()
     for c in ctxs:
@@ -209,7 +237,7 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
     """Many small problems (one angle, shared layer factors): one after another
     against one batched solve."""
     from paper_1412_7466_amd import inputs
-    from paper_1412_7466_amd.grating import Batch, Context
+    from paper_1412_7466_amd.grating import Batch, Context, GRT_FP32
     pbs = [inputs.warm_problem(1000 + i, held_out=True, M_range=M_range, phis=(-math.pi / 5,))
            for i in range(n)]
     ctxs = []
@@ -238,11 +266,21 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
     batch.solve(tol=a.tol, restart=a.restart, graph=True)
     torch.cuda.synchronize()
     t_bgraph = time.perf_counter() - t
+    batch.solve(tol=a.tol, restart=a.restart, graph=True, precision=GRT_FP32)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bm, _ = batch.solve(tol=a.tol, restart=a.restart, graph=True, precision=GRT_FP32)
+    torch.cuda.synchronize()
+    t_bmixed = time.perf_counter() - t
     res = {"workload": (f"{n} geometries of the warm-start rules with M uniform in "
                         f"[{M_range[0]}, {M_range[1]}], omega=20, phi=-pi/5, P=15, GMRES to {a.tol:g}"),
            "plain_fp64_sequential_solves_per_s": n / t_plain,
            "batched_fp64_solves_per_s": n / t_batch,
            "batched_graph_fp64_solves_per_s": n / t_bgraph,
+           "batched_graph_mixed_solves_per_s": n / t_bmixed,
+           "batched_mixed_max_rel_diff_vs_plain": max(
+               float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
+               for b, (p, _) in zip(bm, plain)),
            "batched_max_rel_diff_vs_plain": max(
                float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
                for b, (p, _) in zip(bb, plain))}
