@@ -290,6 +290,92 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
     return res
 
 
+def batch_config(a, torch, n):
+    """A sample of the batched mixed-precision workload (M log-uniform in [200, 4000],
+    P in {10, 15, 20}, omega in {10, 20, 40}, angles in [-pi/3, pi/3]) on six
+    (omega, phi) cells: plain FP64 solves one after another (generator on the fly)
+    against one batched solve in FP64 and in mixed precision, cold and warm-started.
+    Some instances at omega = 40 converge very slowly (strongly coupled resonant
+    scattering), so the solves run with restart 400 and at most 2000 lockstep steps,
+    and the number of instances that reached the tolerance is reported."""
+    import numpy as np
+    from paper_1412_7466_amd import inputs
+    from paper_1412_7466_amd.grating import Batch, Context, Network, GRT_FP32
+    cells = [(0, 0), (1, 5), (2, 10), (0, 15), (1, 12), (2, 3)]
+    pbs = [inputs.batch_problem(i, cells) for i in range(n)]
+    t0 = time.perf_counter()
+    ctxs = []
+    for pb in pbs:
+        c = Context(0)
+        c.set_problem(pb)
+        c.build()
+        ctxs.append(c)
+        print(f"[bench] batch workload: built {pb.name}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    kw = dict(tol=a.tol, restart=max(a.restart, 400), maxit=2000, check=False)
+    ctxs[0].solve(**kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = [c.solve(**kw) for c in ctxs]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    print("[bench] batch workload: sequential solves done", file=sys.stderr, flush=True)
+    batch = Batch(ctxs)
+
+    def timed(x0_fn=None, **extra):
+        batch.solve(graph=True, **kw, **extra)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x0 = None if x0_fn is None else x0_fn()
+        out = batch.solve(graph=True, x0=x0, **kw, **extra)
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    (bf, sf), t_bf = timed()
+    (bm, sm), t_bm = timed(precision=GRT_FP32)
+    print("[bench] batch workload: batched solves done", file=sys.stderr, flush=True)
+
+    def diff(bs):
+        return max(float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
+                   for b, (p, _) in zip(bs, plain))
+
+    res = {"workload": (f"{n} instances of the batched workload: M log-uniform in [200, 4000], "
+                        f"P in {{10, 15, 20}}, omega in {{10, 20, 40}} x angles in [-pi/3, pi/3] "
+                        f"(6 cells), d=1, middle layer y in [-1, 1], GMRES to {a.tol:g}"),
+           "M": [pb.M for pb in pbs], "P": [pb.P for pb in pbs],
+           "omega": [pb.omega for pb in pbs], "build_s": t_build,
+           "plain_fp64_sequential_solves_per_s": n / t_plain,
+           "batched_fp64_solves_per_s": n / t_bf,
+           "batched_mixed_solves_per_s": n / t_bm,
+           "restart": kw["restart"], "maxit": kw["maxit"],
+           "iters_plain": [st.iters for _, st in plain],
+           "iters_batched_mixed": [st.iters for st in sm],
+           "converged_plain": int(sum(st.rel_resid <= a.tol for _, st in plain)),
+           "converged_batched_fp64": int(sum(st.rel_resid <= a.tol for st in sf)),
+           "converged_batched_mixed": int(sum(st.rel_resid <= a.tol for st in sm)),
+           "batched_fp64_max_rel_diff_vs_plain": diff(bf),
+           "batched_mixed_max_rel_diff_vs_plain": diff(bm)}
+    wpath = os.path.join(ROOT, "paper_1412_7466_amd", "warm_start.npz")
+    if os.path.exists(wpath):
+        w = np.load(wpath)
+        width, layers, k, p_out = (int(v) for v in w["config"])
+        net = Network(width, layers, k, p_out)
+        net.set_params(w["theta"])
+        (bw, sw), t_bw = timed(precision=GRT_FP32, x0_fn=lambda: [net.predict(c) for c in ctxs])
+        res.update({"mixed_batched_warm_solves_per_s": n / t_bw,
+                    "mixed_batched_warm_vs_plain_fp64": t_plain / t_bw,
+                    "iters_mixed_batched_warm": [st.iters for st in sw],
+                    "converged_mixed_batched_warm": int(sum(st.rel_resid <= a.tol for st in sw)),
+                    "warm_rejected": int(sum(st.x0_rejected for st in sw)),
+                    "mixed_batched_warm_max_rel_diff_vs_plain": diff(bw)})
+        net.close()
+    batch.close()
+    for c in ctxs:
+        c.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +391,8 @@ def main():
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the traffic summary from two counter runs and exit")
     ap.add_argument("--sweep-n", type=int, default=8)
+    ap.add_argument("--batch-workload", type=int, default=0,
+                    help="also run this many instances of the batched workload (slow setup)")
     a = ap.parse_args()
     if a.traffic_record:
         cmds = [f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc {c} --kernel-include-regex "
@@ -464,6 +552,8 @@ def main():
     if not a.no_sweep:
         res["sweep"] = sweep(a, torch)
         res["sweep_small"] = small_sweep(a, torch)
+    if a.batch_workload > 0:
+        res["batch_workload"] = batch_config(a, torch, a.batch_workload)
     if a.copy_probe_mib > 0:
         src = torch.ones(a.copy_probe_mib * 131072, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)

@@ -48,6 +48,9 @@ struct InstDesc {
   const int *noff, *nlist, *ntgt;
   int n_near;
   double zsafe;
+  // 0 once the lockstep solver has no further use for this problem's applies: every
+  // apply kernel then skips its work items and the combine writes zeros
+  int active;
 };
 
 struct Item {
@@ -64,6 +67,7 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l_batched(const InstDesc* __res
                                                            const cd* __restrict__ X) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   m2l_block<P, cd>(q.cx, q.cy, X + q.off, q.pT, q.M, q.m2l_chunk, q.g.k[1], q.g.d, q.g.alpha,
                    q.g.alpha_inv, q.htab, 0.0, w.x, w.y);
 }
@@ -74,6 +78,7 @@ __global__ void __launch_bounds__(64 * CX_WAVES) cx_batched(const InstDesc* __re
                                                  const cd* __restrict__ X) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   cx_block<P>(q.g, q.cx, q.cy, X + q.off, q.pC, q.c_chunk, q.htab, w.x, w.y);
 }
 
@@ -84,6 +89,7 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l32_batched(const InstDesc* __r
                                                              const cf* __restrict__ X32) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   m2l_block<P, cf>(q.cx, q.cy, X32 + q.off, q.pT32, q.M, q.m2l_chunk, q.g.k[1], q.g.d, q.g.alpha,
                    q.g.alpha_inv, q.htab, q.zsafe, w.x, w.y);
 }
@@ -96,6 +102,7 @@ __global__ void __launch_bounds__(64) near_batched(const InstDesc* __restrict__ 
   __shared__ double stab[HTAB_SIZE];
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   for (int t = threadIdx.x; t < HTAB_SIZE; t += 64) stab[t] = q.htab[t];
   __syncthreads();
   const int e = w.x * 64 + threadIdx.x;
@@ -109,6 +116,7 @@ __global__ void __launch_bounds__(256) nred_batched(const InstDesc* __restrict__
                                                    const Item* __restrict__ it) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   const int idx = w.x * 256 + threadIdx.x;
   if (idx < q.M * q.nb) near_reduce_entry(q.noff, q.npart, q.nb, q.pN, idx);
 }
@@ -117,6 +125,7 @@ __global__ void __launch_bounds__(256) cxr_batched(const InstDesc* __restrict__ 
                                                    const Item* __restrict__ it) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   cx_reduce_block(q.g, q.pC, q.c_nchunks, q.gvec, w.x);
 }
 
@@ -160,12 +169,14 @@ __global__ void __launch_bounds__(256) gemv1_batched(const InstDesc* __restrict_
                                                      const Item* __restrict__ it, int use_f) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   gemv_rows_block(q.W1, use_f ? q.f : q.gvec, q.tvec, q.rank, q.n_g, w.x);
 }
 __global__ void __launch_bounds__(256) gemv2_batched(const InstDesc* __restrict__ D,
                                                      const Item* __restrict__ it) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   gemv_rows_block(q.W2, q.tvec, q.wvec, q.n_b, q.rank, w.x);
 }
 
@@ -174,6 +185,7 @@ __global__ void __launch_bounds__(64 * BX_WAVES) bx_batched(const InstDesc* __re
                                                  const Item* __restrict__ it) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   bx_block<P>(q.g, q.cx, q.cy, q.wvec, q.pB, q.b_chunk, q.htab, w.x, w.y);
 }
 
@@ -181,6 +193,7 @@ __global__ void __launch_bounds__(256) l2l_batched(const InstDesc* __restrict__ 
                                                   const Item* __restrict__ it) {
   const Item w = it[blockIdx.x];
   const InstDesc& q = D[w.inst];
+  if (!q.active) return;
   l2l_block(q.M, q.P, q.Q2, q.l2l, q.wvec + q.g.col_off[CB_A2], q.pL, w.x, w.y);
 }
 
@@ -196,7 +209,7 @@ __global__ void __launch_bounds__(BT) combine_batched(const InstDesc* __restrict
   for (int r = 0; r < SEG / BT; ++r) {
     const int64_t i = (int64_t)seg * SEG + r * BT + threadIdx.x;
     const int64_t loc = i - q.off;
-    if (loc >= q.nbeta) {
+    if (loc >= q.nbeta || (mode == 0 && !q.active)) {
       Y[i] = cd{0.0, 0.0};
       continue;
     }
@@ -225,7 +238,7 @@ __global__ void __launch_bounds__(BT) combine_mixed_batched(const InstDesc* __re
   for (int r = 0; r < SEG / BT; ++r) {
     const int64_t i = (int64_t)seg * SEG + r * BT + threadIdx.x;
     const int64_t loc = i - q.off;
-    if (loc >= q.nbeta) {
+    if (loc >= q.nbeta || !q.active) {
       Y[i] = cd{0.0, 0.0};
       continue;
     }
@@ -430,6 +443,12 @@ __global__ void __launch_bounds__(BT) seg_axpy_basis_kernel(const int* __restric
   }
 }
 
+// D[i].active = flags[i]
+__global__ void set_active_kernel(InstDesc* D, const int* __restrict__ flags, int B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B) D[i].active = flags[i];
+}
+
 // x = 0 on the segments of problems whose flag is set
 __global__ void __launch_bounds__(BT) zero_rejected_kernel(const int* __restrict__ seg2inst,
                                                            const int* __restrict__ flag, cd* x) {
@@ -474,6 +493,8 @@ struct grt_batch {
   double *res = nullptr, *part = nullptr, *nrm = nullptr, *hn = nullptr, *bn = nullptr;
   cd* dpart = nullptr;    // (m+1) x nseg
   int* d_k = nullptr;
+  int* d_act = nullptr;         // staging of the active flags
+  std::vector<int> act;         // the flags as last sent to the descriptors
   double* h_pinned = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
@@ -652,6 +673,17 @@ static grt_status batch_workspace(grt_batch* b, int m) {
   return GRT_OK;
 }
 
+// Send the problems' active flags to the descriptors (only if they changed).
+static grt_status set_active(grt_batch* b, const std::vector<int>& flags) {
+  if (flags == b->act) return GRT_OK;
+  BHIP(b, hipMemcpyAsync(b->d_act, flags.data(), sizeof(int) * b->B, hipMemcpyHostToDevice,
+                         b->stream));
+  set_active_kernel<<<(b->B + 63) / 64, 64, 0, b->stream>>>(b->dd, b->d_act, b->B);
+  BHIP(b, hipGetLastError());
+  b->act = flags;
+  return GRT_OK;
+}
+
 static grt_status read_vec(grt_batch* b, const double* dev, std::vector<double>& out) {
   out.resize(b->B);
   BHIP(b, hipMemcpyAsync(b->h_pinned, dev, sizeof(double) * b->B, hipMemcpyDeviceToHost, b->stream));
@@ -684,9 +716,12 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
   BTRY(read_vec(b, b->bn, bn));
   std::vector<int> kk(B, 0);
   std::vector<char> done(B, 0);
+  const std::vector<int> all_on(B, 1);
+  std::vector<int> act(B, 1);
   int total = 0;
   while (true) {
-    // R = B - K X into V_0
+    // R = B - K X into V_0 (for every problem)
+    BTRY(set_active(b, all_on));
     BTRY(batch_apply(b, X, use_graph, mixed));
     {
       const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
@@ -720,8 +755,12 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
     inst_init_g_kernel<<<(B * (ld + 1) + 255) / 256, 256, 0, s>>>(B, ld + 1, b->nrm, b->g);
     BHIP(b, hipMemsetAsync(b->H, 0, sizeof(cd) * (size_t)B * ld * ld, s));
     std::fill(kk.begin(), kk.end(), -1);
-    for (int i = 0; i < B; ++i)
+    for (int i = 0; i < B; ++i) {
       if (done[i]) kk[i] = 0;
+      act[i] = !done[i];
+    }
+    // problems already at tol take no Arnoldi steps: their applies are skipped
+    BTRY(set_active(b, act));
     int steps = 0;
     // residual estimates of step jj, in the pinned buffer of parity jj & 1
     double* hbuf[2] = {b->h_pinned + B, b->h_pinned + 2 * B};
@@ -754,13 +793,16 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
                                sizeof(double), B, hipMemcpyDeviceToHost, s));
       BHIP(b, hipEventRecord(b->ev[j & 1], s));
       steps = j + 1;
-      // the host checks step j-1 while the GPU runs step j
+      // the host checks step j-1 while the GPU runs step j; problems found converged
+      // are skipped from step j+1 on (their solution uses columns < kk only)
       if (j >= 1) {
         BHIP(b, hipEventSynchronize(b->ev[(j - 1) & 1]));
         if (check(j - 1)) {
           all = true;
           break;
         }
+        for (int i = 0; i < B; ++i) act[i] = kk[i] < 0;
+        BTRY(set_active(b, act));
       }
     }
     if (!all && steps > 0) {
@@ -780,6 +822,7 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
     }
   }
   r.steps = total;
+  BTRY(set_active(b, all_on));
   return GRT_OK;
 }
 
@@ -857,6 +900,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     q.ntgt = c->d_ntgt;
     q.n_near = (int)c->n_near;
     q.zsafe = c->zsafe;
+    q.active = 1;
     q.seg0 = seg;
     q.nseg = (int)((c->n_beta + SEG - 1) / SEG);
     q.off = (int64_t)seg * SEG;
@@ -934,7 +978,9 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
   b->n_g2 = (int)g2.size();
   b->n_l2l = (int)l2l.size();
   b->n_nred = (int)nred.size();
-  if (hipMalloc(&b->x32, sizeof(cf) * (size_t)b->ntot) != hipSuccess) {
+  b->act.assign(n, 1);
+  if (hipMalloc(&b->d_act, sizeof(int) * (size_t)n) != hipSuccess ||
+      hipMalloc(&b->x32, sizeof(cf) * (size_t)b->ntot) != hipSuccess) {
     grt_batch_destroy(b);
     return GRT_ENOMEM;
   }
@@ -947,7 +993,7 @@ grt_status grt_batch_destroy(grt_batch* b) {
   hipSetDevice(b->device);
   if (b->stream) hipStreamSynchronize(b->stream);
   std::vector<void*> p = {b->dd, b->d_seg2inst, b->d_dnorm, b->d_dinv, b->it_cxr, b->it_g1,
-                          b->it_g2, b->it_l2l, b->it_nred, b->x32, b->V, b->H, b->cs, b->sn,
+                          b->it_g2, b->it_l2l, b->it_nred, b->x32, b->d_act, b->V, b->H, b->cs, b->sn,
                           b->g, b->y, b->h, b->res, b->part, b->nrm, b->hn, b->bn, b->dpart,
                           b->d_k};
   for (auto& gp : b->groups) {

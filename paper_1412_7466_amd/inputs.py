@@ -295,6 +295,36 @@ def warm_problem(i: int, held_out: bool = False, M_range=(200, 2000), P: int = 1
                    seed=seed)
 
 
+BATCH_OMEGAS = (10.0, 20.0, 40.0)
+BATCH_PHIS = tuple(-math.pi / 3 + a * (2 * math.pi / 3) / 15 for a in range(16))
+BATCH_PS = (10, 15, 20)
+
+
+def batch_problem(i: int, cells=None) -> Problem:
+    """Instance i of the batched mixed-precision workload (seed 120000+i): the
+    M=1000 workload's rules (d=1, middle layer y in [-1, 1], radii U[0.004, 0.012],
+    indices U[1.5, 3.0], gap 0.002) with M log-uniform in [200, 4000] and P uniform
+    in {10, 15, 20}, at the (omega, phi) cell i mod len(cells) of the grid
+    omega in {10, 20, 40} x 16 angles equally spaced in [-pi/3, pi/3] (cells: list of
+    (omega index, phi index), default the whole grid in the order omega fastest).
+    Problems of one cell share their discretization, hence one factorization of the
+    layered structure."""
+    if cells is None:
+        cells = [(w, a) for a in range(len(BATCH_PHIS)) for w in range(len(BATCH_OMEGAS))]
+    wi, ai = cells[i % len(cells)]
+    omega, phi = BATCH_OMEGAS[wi], BATCH_PHIS[ai]
+    seed = 120000 + i
+    rng = np.random.Generator(np.random.PCG64(seed + 7_000_000))
+    M = int(round(math.exp(rng.uniform(math.log(200), math.log(4000)))))
+    P = int(BATCH_PS[int(rng.integers(0, len(BATCH_PS)))])
+    d, h, r_lo, gap = 1.0, 1.0, 0.004, 0.002
+    x, y, r, n = pack_disks(M, d, h, r_lo, 0.012, 1.5, 3.0, gap, seed)
+    closest = h - (max(gap, 0.02) + r_lo)
+    disc = derive_discretization(d, h, STACK, omega, phi, np.array([closest]), P)
+    return Problem(d=d, h=h, n_layer=STACK, omega=omega, phi=phi, P=P, x=x, y=y, radius=r,
+                   n_incl=n, disc=disc, name=f"batch{i}_M{M}_P{P}", seed=seed)
+
+
 def nn_shapes(H: int, L: int, p_out: int, F: int = 32, E: int = 8):
     """Shapes of the warm-start network's weights, in the order of its flat
     parameter vector (matrices row-major [rows][cols])."""
