@@ -287,9 +287,18 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// The Krylov kernels below skip the segments of inactive problems (their results are
+// no longer used) and report zero for them.
+
 // partial[seg] = sum over the segment of |x|^2
-__global__ void __launch_bounds__(BT) seg_norm2_kernel(const cd* __restrict__ x, double* partial) {
+__global__ void __launch_bounds__(BT) seg_norm2_kernel(const InstDesc* __restrict__ D,
+                                                       const int* __restrict__ seg2inst,
+                                                       const cd* __restrict__ x, double* partial) {
   __shared__ double red[BT / 64];
+  if (!D[seg2inst[blockIdx.x]].active) {
+    if (threadIdx.x == 0) partial[blockIdx.x] = 0.0;
+    return;
+  }
   double s = 0.0;
   for (int r = 0; r < SEG / BT; ++r) s += cabs2(x[(int64_t)blockIdx.x * SEG + r * BT + threadIdx.x]);
   s = block_sum(s, red);
@@ -307,8 +316,10 @@ __global__ void inst_norm_kernel(const InstDesc* __restrict__ D, int B, const do
 }
 
 // y = x / nrm[problem] (where nrm > 0)
-__global__ void __launch_bounds__(BT) inst_scale_kernel(const int* __restrict__ seg2inst,
+__global__ void __launch_bounds__(BT) inst_scale_kernel(const InstDesc* __restrict__ D,
+                                                        const int* __restrict__ seg2inst,
                                                         const cd* x, const double* nrm, cd* y) {
+  if (!D[seg2inst[blockIdx.x]].active) return;
   const double s = nrm[seg2inst[blockIdx.x]];
   for (int r = 0; r < SEG / BT; ++r) {
     int64_t i = (int64_t)blockIdx.x * SEG + r * BT + threadIdx.x;
@@ -316,14 +327,23 @@ __global__ void __launch_bounds__(BT) inst_scale_kernel(const int* __restrict__ 
   }
 }
 
-// partial[v][seg] = sum over the segment of conj(V_v) w, v = 0..nv-1
-__global__ void __launch_bounds__(BT) seg_dots_kernel(const cd* __restrict__ V, size_t ldv,
+// partial[v][seg] = sum over the segment of conj(V_v) w, v = 0..nv-1; block (seg, y)
+// takes v in [y DOT_VB, y DOT_VB + DOT_VB)
+constexpr int DOT_VB = 8;
+__global__ void __launch_bounds__(BT) seg_dots_kernel(const InstDesc* __restrict__ D,
+                                                      const int* __restrict__ seg2inst,
+                                                      const cd* __restrict__ V, size_t ldv,
                                                       const cd* __restrict__ w, int nv, int nseg,
                                                       cd* partial) {
   __shared__ double red[BT / 64];
+  const int v0 = blockIdx.y * DOT_VB, v1 = min(nv, v0 + DOT_VB);
+  if (!D[seg2inst[blockIdx.x]].active) {
+    for (int v = v0 + threadIdx.x; v < v1; v += BT) partial[(size_t)v * nseg + blockIdx.x] = cd{0, 0};
+    return;
+  }
   cd wv[SEG / BT];
   for (int r = 0; r < SEG / BT; ++r) wv[r] = w[(int64_t)blockIdx.x * SEG + r * BT + threadIdx.x];
-  for (int v = 0; v < nv; ++v) {
+  for (int v = v0; v < v1; ++v) {
     const cd* a = V + (size_t)v * ldv + (int64_t)blockIdx.x * SEG;
     double sr = 0.0, si = 0.0;
     for (int r = 0; r < SEG / BT; ++r) {
@@ -354,10 +374,12 @@ __global__ void inst_dots_kernel(const InstDesc* __restrict__ D, int B, int nv, 
 }
 
 // w -= sum_v h[problem][v] V_v
-__global__ void __launch_bounds__(BT) seg_update_kernel(const int* __restrict__ seg2inst,
+__global__ void __launch_bounds__(BT) seg_update_kernel(const InstDesc* __restrict__ D,
+                                                        const int* __restrict__ seg2inst,
                                                         const cd* __restrict__ V, size_t ldv,
                                                         cd* w, int nv, const cd* __restrict__ h,
                                                         int hld) {
+  if (!D[seg2inst[blockIdx.x]].active) return;
   const cd* hh = h + (size_t)seg2inst[blockIdx.x] * hld;
   for (int r = 0; r < SEG / BT; ++r) {
     int64_t i = (int64_t)blockIdx.x * SEG + r * BT + threadIdx.x;
@@ -630,7 +652,7 @@ static grt_status batch_rhs_hat(grt_batch* b, cd* Y) {
 }
 
 static grt_status batch_norms(grt_batch* b, const cd* x, double* nrm_dev) {
-  seg_norm2_kernel<<<b->nseg, BT, 0, b->stream>>>(x, b->part);
+  seg_norm2_kernel<<<b->nseg, BT, 0, b->stream>>>(b->dd, b->d_seg2inst, x, b->part);
   inst_norm_kernel<<<(b->B + 63) / 64, 64, 0, b->stream>>>(b->dd, b->B, b->part, nrm_dev);
   BHIP(b, hipGetLastError());
   return GRT_OK;
@@ -751,7 +773,7 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
       }
     }
     if (!any || total >= maxit) break;
-    inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, b->nrm, V);
+    inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, V, b->nrm, V);
     inst_init_g_kernel<<<(B * (ld + 1) + 255) / 256, 256, 0, s>>>(B, ld + 1, b->nrm, b->g);
     BHIP(b, hipMemsetAsync(b->H, 0, sizeof(cd) * (size_t)B * ld * ld, s));
     std::fill(kk.begin(), kk.end(), -1);
@@ -778,16 +800,17 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
       cd* w = b->wout;  // the new directions; normalised into V_{j+1} below
       BTRY(batch_apply(b, V + (size_t)j * ldv, use_graph, mixed));
       for (int pass = 0; pass < 2; ++pass) {
-        seg_dots_kernel<<<b->nseg, BT, 0, s>>>(V, ldv, w, j + 1, b->nseg, b->dpart);
+        seg_dots_kernel<<<dim3(b->nseg, (j + 1 + DOT_VB - 1) / DOT_VB), BT, 0, s>>>(
+            b->dd, b->d_seg2inst, V, ldv, w, j + 1, b->nseg, b->dpart);
         inst_dots_kernel<<<(B * (j + 1) + 255) / 256, 256, 0, s>>>(b->dd, B, j + 1, b->nseg,
                                                                   b->dpart, b->h, ld, b->H, ld, j,
                                                                   pass);
-        seg_update_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, V, ldv, w, j + 1, b->h, ld);
+        seg_update_kernel<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, V, ldv, w, j + 1, b->h, ld);
       }
       BTRY(batch_norms(b, w, b->nrm));
       inst_givens_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->nrm, b->H, ld, b->cs, b->sn, b->g, j,
                                                       b->hn, b->res, ld);
-      inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, w, b->hn, V + (size_t)(j + 1) * ldv);
+      inst_scale_kernel<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, w, b->hn, V + (size_t)(j + 1) * ldv);
       BHIP(b, hipGetLastError());
       BHIP(b, hipMemcpy2DAsync(hbuf[j & 1], sizeof(double), b->res + j, sizeof(double) * ld,
                                sizeof(double), B, hipMemcpyDeviceToHost, s));
@@ -1066,7 +1089,6 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
     BTRY(read_vec(b, b->bn, bn));
     std::vector<int> flag(B, 0);
     bool guard = o->use_x0 != 0;
-    int total = 0;
     for (int outer = 0; outer <= max_ref; ++outer) {
       BTRY(batch_apply(b, X, use_graph, false));
       ew_sub_kernel<<<gn, BT, 0, s>>>(Bv, b->wout, R, b->ntot);
@@ -1092,28 +1114,29 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
           continue;
         }
       }
+      // a problem takes no further correction once its FP64 residual meets tol or
+      // it has used its own maxit inner iterations
+      int budget = 0;
       for (int i = 0; i < B; ++i) {
-        flag[i] = r.rel[i] <= tol;
+        flag[i] = r.rel[i] <= tol || r.iters[i] >= maxit;
         if (!flag[i]) {
           any = true;
-          refine[i] = outer;
+          budget = std::max(budget, maxit - r.iters[i]);
         }
       }
-      if (!any || outer == max_ref || total >= maxit) break;
+      if (!any || outer == max_ref) break;
       BHIP(b, hipMemcpyAsync(b->d_k, flag.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
       zero_rejected_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, b->d_k, R);
       BHIP(b, hipMemsetAsync(E, 0, sizeof(cd) * ldv, s));
       LockstepResult ri(B);
-      BTRY(batch_gmres(b, true, R, E, itol, maxit - total, m, false, use_graph, ri));
-      total += ri.steps;
+      BTRY(batch_gmres(b, true, R, E, itol, budget, m, false, use_graph, ri));
       for (int i = 0; i < B; ++i) {
         r.iters[i] += ri.iters[i];
         r.cycles[i] += ri.cycles[i];
+        if (!flag[i]) refine[i] += 1;
       }
       ew_add_kernel<<<gn, BT, 0, s>>>(X, E, b->ntot);
       BHIP(b, hipGetLastError());
-      for (int i = 0; i < B; ++i)
-        if (!flag[i]) refine[i] = outer + 1;
     }
   }
   // back to beta = D^{-1} x^, scattered to the callers' vectors
