@@ -227,6 +227,25 @@ def sweep(a, torch):
                         for b, (p, _) in zip(bmw, plain)),
                     "mixed_batched_warm_vs_plain_fp64": t_plain / t_bmw})
         net.close()
+    # the same FP64 solves with every problem's resident translation table, one after
+    # another and batched (a new batch: the contexts changed)
+    batch.close()
+    for c in ctxs:
+        c.set_table(1)
+    seq()
+    plain_t, t_plain_t = seq()
+    batch = Batch(ctxs)
+    batch.solve(tol=a.tol, restart=a.restart, graph=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bt, _ = batch.solve(tol=a.tol, restart=a.restart, graph=True)
+    torch.cuda.synchronize()
+    t_batch_t = time.perf_counter() - t
+    res.update({"plain_fp64_table_sequential_solves_per_s": len(ctxs) / t_plain_t,
+                "batched_fp64_table_graph_solves_per_s": len(ctxs) / t_batch_t,
+                "batched_table_max_rel_diff_vs_plain": max(
+                    float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
+                    for b, (p, _) in zip(bt, plain))})
     batch.close()
     for c in ctxs:
         c.close()

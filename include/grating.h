@@ -166,8 +166,10 @@ grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision
  * Toeplitz product: more waves per SIMD, but twice the load instructions; kept for
  * comparison); 0 frees it and the apply evaluates the generator on the fly again.  Results agree with the on-the-fly apply to rounding.
  * GRT_ENOMEM if it does not fit in free device memory with 1 GiB to spare (the
- * context stays usable, without the table).  The mixed-precision apply and batched
- * solves always evaluate on the fly. */
+ * context stays usable, without the table).  The mixed-precision apply always
+ * evaluates on the fly; batched FP64 solves stream the table of every context that
+ * has one when the batch is created (changing the mode afterwards makes
+ * grt_batch_solve return GRT_ESTATE). */
 grt_status grt_set_table(grt_ctx* ctx, int mode);
 /* Launch-shape autotuner: times the translation launch for source chunk counts
  * giving 256 .. 8192 work-groups, in the current mode (on the fly or resident
@@ -233,9 +235,11 @@ grt_status grt_profile_read(grt_ctx* ctx, double* m2l_ms_total, int64_t* m2l_lau
 typedef struct grt_batch grt_batch;
 
 /* Make a batch of n built contexts (all with M >= 1, all on one device).  The
- * batch borrows the contexts' device data: they must stay alive and unchanged
- * (no grt_set_problem / grt_build / grt_apply / grt_solve on them) until
- * grt_batch_destroy.  hip_stream: stream to run on, or NULL for a private one.
+ * batch borrows the contexts' device data: they must stay alive until
+ * grt_batch_destroy; grt_apply / grt_solve on them share their scratch buffers, so
+ * they must not overlap a batch solve; after grt_set_problem, grt_build or a change
+ * of table mode on one of them grt_batch_solve returns GRT_ESTATE (make a new
+ * batch).  hip_stream: stream to run on, or NULL for a private one.
  * GRT_ESTATE if a context is not built, has no inclusions or is on another
  * device; GRT_EINVAL for n <= 0 or NULL arrays. */
 grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, void* hip_stream);

@@ -487,6 +487,7 @@ size_t table_bytes(const grt_ctx* c) {
 
 grt_status table_set(grt_ctx* c, bool on) {
   graph_reset(c);
+  ++c->gen;
   if (c->d_table) {
     hipStreamSynchronize(c->stream);
     hipFree(c->d_table);

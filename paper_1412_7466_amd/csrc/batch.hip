@@ -48,6 +48,9 @@ struct InstDesc {
   const int *noff, *nlist, *ntgt;
   int n_near;
   double zsafe;
+  // resident translation table of the FP64 apply (null: generator on the fly)
+  const cd* table;
+  int mpad;
   // 0 once the lockstep solver has no further use for this problem's applies: every
   // apply kernel then skips its work items and the combine writes zeros
   int active;
@@ -80,6 +83,17 @@ __global__ void __launch_bounds__(64 * CX_WAVES) cx_batched(const InstDesc* __re
   const InstDesc& q = D[w.inst];
   if (!q.active) return;
   cx_block<P>(q.g, q.cx, q.cy, X + q.off, q.pC, q.c_chunk, q.htab, w.x, w.y);
+}
+
+// FP64 translation from the problem's resident table
+template <int P>
+__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(P <= 15 ? 2 : 1, 8)))
+m2lt_batched(const InstDesc* __restrict__ D, const Item* __restrict__ it,
+             const cd* __restrict__ X) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  if (!q.active) return;
+  m2l_table_block<P>(q.table, X + q.off, q.pT, q.M, q.mpad, q.m2l_chunk, w.x, w.y);
 }
 
 // FP32 translation of the well-separated pairs (near pairs, k2 rho < zsafe, skipped)
@@ -496,9 +510,13 @@ struct grt_batch {
   double *d_dnorm = nullptr, *d_dinv = nullptr;
   struct Group {
     int P;
-    Item *m2l = nullptr, *cx = nullptr, *bx = nullptr, *nr = nullptr;
-    int n_m2l = 0, n_cx = 0, n_bx = 0, n_nr = 0;
+    // m2l: translation items of every problem (the mixed apply's FP32 launch); m2lf /
+    // m2lt: those of the problems without / with a resident table (FP64 apply)
+    Item *m2l = nullptr, *m2lf = nullptr, *m2lt = nullptr, *cx = nullptr, *bx = nullptr,
+         *nr = nullptr;
+    int n_m2l = 0, n_m2lf = 0, n_m2lt = 0, n_cx = 0, n_bx = 0, n_nr = 0;
   };
+  std::vector<uint64_t> gen;  // the contexts' generations at creation
   std::vector<Group> groups;
   Item *it_cxr = nullptr, *it_g1 = nullptr, *it_g2 = nullptr, *it_l2l = nullptr, *it_nred = nullptr;
   int n_cxr = 0, n_g1 = 0, n_g2 = 0, n_l2l = 0, n_nred = 0;
@@ -562,7 +580,8 @@ static grt_status upload(grt_batch* b, const std::vector<T>& v, T** out) {
 
 template <int P>
 static void launch_group_T(grt_batch* b, const grt_batch::Group& gp, const cd* X) {
-  if (gp.n_m2l) m2l_batched<P><<<gp.n_m2l, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2l, X);
+  if (gp.n_m2lf) m2l_batched<P><<<gp.n_m2lf, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2lf, X);
+  if (gp.n_m2lt) m2lt_batched<P><<<gp.n_m2lt, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2lt, X);
 }
 template <int P>
 static void launch_group_C(grt_batch* b, const grt_batch::Group& gp, const cd* X) {
@@ -923,6 +942,8 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     q.ntgt = c->d_ntgt;
     q.n_near = (int)c->n_near;
     q.zsafe = c->zsafe;
+    q.table = c->d_table;
+    q.mpad = c->table_mpad;
     q.active = 1;
     q.seg0 = seg;
     q.nseg = (int)((c->n_beta + SEG - 1) / SEG);
@@ -940,13 +961,16 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
   for (auto& kv : byP) {
     grt_batch::Group gp;
     gp.P = kv.first;
-    std::vector<Item> m2l, cxv, bxv, nr;
+    std::vector<Item> m2l, m2lf, m2lt, cxv, bxv, nr;
     for (int i : kv.second) {
       const InstDesc& q = b->hd[i];
       const int nt = 2 * q.g.N + q.g.Nw[1];
       for (int x = 0; x < (q.n_near + 63) / 64; ++x) nr.push_back({i, x, 0});
       for (int y = 0; y < q.m2l_nchunks; ++y)
-        for (int x = 0; x < (q.M + 63) / 64; ++x) m2l.push_back({i, x, y});
+        for (int x = 0; x < (q.M + 63) / 64; ++x) {
+          m2l.push_back({i, x, y});
+          (q.table ? m2lt : m2lf).push_back({i, x, y});
+        }
       for (int y = 0; y < q.c_nchunks; ++y)
         for (int x = 0; x < (nt + 63) / 64; ++x) cxv.push_back({i, x, y});
       for (int y = 0; y < q.b_nchunks; ++y)
@@ -954,14 +978,18 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     }
     grt_status st;
     if ((st = upload(b, m2l, &gp.m2l)) != GRT_OK || (st = upload(b, cxv, &gp.cx)) != GRT_OK ||
-        (st = upload(b, bxv, &gp.bx)) != GRT_OK || (st = upload(b, nr, &gp.nr)) != GRT_OK) {
-      for (void* q : {(void*)gp.m2l, (void*)gp.cx, (void*)gp.bx, (void*)gp.nr})
+        (st = upload(b, bxv, &gp.bx)) != GRT_OK || (st = upload(b, nr, &gp.nr)) != GRT_OK ||
+        (st = upload(b, m2lf, &gp.m2lf)) != GRT_OK || (st = upload(b, m2lt, &gp.m2lt)) != GRT_OK) {
+      for (void* q : {(void*)gp.m2l, (void*)gp.m2lf, (void*)gp.m2lt, (void*)gp.cx, (void*)gp.bx,
+                      (void*)gp.nr})
         if (q) hipFree(q);
       grt_batch_destroy(b);
       return st;
     }
     gp.n_nr = (int)nr.size();
     gp.n_m2l = (int)m2l.size();
+    gp.n_m2lf = (int)m2lf.size();
+    gp.n_m2lt = (int)m2lt.size();
     gp.n_cx = (int)cxv.size();
     gp.n_bx = (int)bxv.size();
     b->groups.push_back(gp);
@@ -1002,6 +1030,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
   b->n_l2l = (int)l2l.size();
   b->n_nred = (int)nred.size();
   b->act.assign(n, 1);
+  for (grt_ctx* c : b->ctx) b->gen.push_back(c->gen);
   if (hipMalloc(&b->d_act, sizeof(int) * (size_t)n) != hipSuccess ||
       hipMalloc(&b->x32, sizeof(cf) * (size_t)b->ntot) != hipSuccess) {
     grt_batch_destroy(b);
@@ -1021,6 +1050,8 @@ grt_status grt_batch_destroy(grt_batch* b) {
                           b->d_k};
   for (auto& gp : b->groups) {
     p.push_back(gp.m2l);
+    p.push_back(gp.m2lf);
+    p.push_back(gp.m2lt);
     p.push_back(gp.cx);
     p.push_back(gp.bx);
     p.push_back(gp.nr);
@@ -1048,6 +1079,10 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
   if (o->precision != GRT_FP64 && o->precision != GRT_FP32)
     return bset(b, GRT_EINVAL, "precision must be GRT_FP64 or GRT_FP32");
   if (!(o->tol > 0 && o->tol < 1)) return bset(b, GRT_EINVAL, "tol must be in (0, 1)");
+  for (int i = 0; i < b->B; ++i)
+    if (b->ctx[i]->gen != b->gen[i])
+      return bset(b, GRT_ESTATE, "context " + std::to_string(i) +
+                                     " changed (problem, build or table) since the batch was made");
   BHIP(b, hipSetDevice(b->device));
   auto t0 = std::chrono::steady_clock::now();
   const int m = std::max(1, std::min(o->restart > 0 ? o->restart : 100, 1000));

@@ -25,6 +25,7 @@ namespace {
 
 void free_all(grt_ctx* c) {
   graph_reset(c);
+  ++c->gen;
   if (c->lf) {  // layer-side buffers belong to the shared factors
     c->d_yw = c->d_colscale = c->d_sv = c->d_htab = nullptr;
     c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_f = nullptr;

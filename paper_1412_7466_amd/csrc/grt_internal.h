@@ -105,6 +105,8 @@ struct grt_ctx {
   cd* d_npart = nullptr;    // [n_near][nb] per-pair contributions
   int64_t n_near = 0;
   // resident translation table (FP64 apply only; see table_set)
+  uint64_t gen = 0;          // bumped whenever device buffers are freed or replaced (a
+                             // batch built on this context checks it before solving)
   bool want_table = false;
   cd* d_table = nullptr;    // [M][4P+1][Mpad]
   int table_mpad = 0;

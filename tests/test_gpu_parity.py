@@ -198,6 +198,10 @@ def test_batched_solve_matches_single_and_oracle(torch_cuda):
     for pb, ctx in zip(pbs, ctxs):
         beta, st = ctx.solve(tol=1e-12, restart=150)
         singles.append((_np(beta), st.iters))
+    # two problems with a resident translation table: their batched FP64 applies
+    # stream it, the others evaluate the generator on the fly
+    ctxs[1].set_table(True)
+    ctxs[4].set_table(True)
     say("[gpu] batch create", len(ctxs))
     batch = Batch(ctxs)
     betas, stats = batch.solve(tol=1e-12, restart=150)
@@ -222,6 +226,12 @@ def test_batched_solve_matches_single_and_oracle(torch_cuda):
     assert all(s.iters == 0 for s in stats2)
     for b2, b in zip(betas2, betas):
         assert rel(_np(b2), _np(b)) < 1e-15  # x -> D x -> D^{-1} x rounding only
+    # a context whose table is freed after the batch was made is refused
+    from paper_1412_7466_amd.grating import GratingError, GRT_ESTATE
+    ctxs[4].set_table(False)
+    with pytest.raises(GratingError) as ei:
+        batch.solve(tol=1e-12, restart=150)
+    assert ei.value.status == GRT_ESTATE
     batch.close()
 
 
