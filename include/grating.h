@@ -123,6 +123,9 @@ typedef struct {
   int Nrb;
   int m2l_chunks;   /* source chunks of the translation launch (one partial
                        result of n_beta entries each)                         */
+  int m2l_split;    /* 1, or 2: the FP64 translation with the generator on the
+                       fly runs as two launches, each forming half of the
+                       2P+1 outputs (and recomputing the generator)           */
   int cx_chunks;    /* source chunks of the C x launch                       */
   int bx_chunks;    /* node chunks of the B_phys w (P2L) launch              */
 } grt_sizes;
@@ -173,14 +176,24 @@ grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision
 grt_status grt_set_table(grt_ctx* ctx, int mode);
 /* Launch-shape autotuner: times the translation launch for source chunk counts
  * giving 256 .. 8192 work-groups, in the current mode (on the fly or resident
- * table), then the C x and B_phys w launches (each with the pass that adds its
- * per-chunk partial results) for 1 .. 64 sources per wave, and keeps the fastest
- * of each for every later apply of this context (results change only by the
- * order of the chunk sums; grt_query reports the chosen chunk counts).  Up to cap
- * measured (chunk count, ms per launch) pairs of the translation go to chunks[] /
- * ms[] (host); *n receives their number.  Without a call every split aims at two
- * work-groups per SIMD. */
-grt_status grt_autotune(grt_ctx* ctx, int cap, int* n, int* chunks, double* ms);
+ * table; on the fly also split over two launches, each forming half of the
+ * outputs with half the accumulators per lane), then the C x and B_phys w launches
+ * (each with the pass that adds its per-chunk partial results) for 1 .. 64 sources
+ * per wave, and keeps the fastest of each for every later apply of this context
+ * (results change only by the order of the chunk sums; grt_query reports the
+ * choices).  Up to cap measured (chunk count, split, ms per launch) triples of the
+ * translation go to chunks[] / splits[] / ms[] (host; splits may be NULL); *n
+ * receives their number.  Without a call every split aims at two work-groups per
+ * SIMD, in one launch. */
+grt_status grt_autotune(grt_ctx* ctx, int cap, int* n, int* chunks, int* splits, double* ms);
+
+/* Set the translation's launch shape by hand (what grt_autotune would choose):
+ * about m2l_chunks source chunks (1 .. the number grt_autotune may try, at most M;
+ * the chunk length is rounded up, so grt_query may report fewer) and m2l_split 1
+ * or 2 (2: the on-the-fly FP64 translation as two launches, each forming half of
+ * the outputs; ignored with the resident table and in mixed precision).  Results
+ * change only by the order of the chunk sums.  GRT_EINVAL outside those ranges. */
+grt_status grt_set_launch(grt_ctx* ctx, int m2l_chunks, int m2l_split);
 
 /* Bytes the table of the current problem takes. */
 grt_status grt_table_bytes(const grt_ctx* ctx, int64_t* bytes);

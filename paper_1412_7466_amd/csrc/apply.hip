@@ -39,6 +39,21 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l_kernel(const double* __restri
                   blockIdx.y);
 }
 
+// Outputs [LO, LO + NH) only (index n + P): the on-the-fly translation split over two
+// launches, each recomputing the generator, so that a lane holds half the
+// accumulators (FP64) and two waves fit on a SIMD.
+template <int P, int LO, int NH>
+__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(M2L_HALF_MINW, 8))) m2l_half_kernel(const double* __restrict__ cx,
+                                                               const double* __restrict__ cy,
+                                                               const cd* __restrict__ x,
+                                                               cd* partial, int M, int chunk,
+                                                               double k, double d, cd alpha,
+                                                               cd alpha_inv,
+                                                               const double* __restrict__ htab) {
+  m2l_block<P, cd, LO, NH>(cx, cy, x, partial, M, chunk, k, d, alpha, alpha_inv, htab, 0.0,
+                           blockIdx.x, blockIdx.y);
+}
+
 template <int P>
 __global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(P <= 15 ? 2 : 1, 8))) m2l_table_kernel(const cd* __restrict__ table,
                                                                 const cd* __restrict__ x,
@@ -166,10 +181,18 @@ void launch_m2l(grt_ctx* c, const cd* x) {
     dim3 grid2((unsigned)((c->M + 31) / 32), c->m2l_nchunks);
     m2l_table2_kernel<P><<<grid2, M2L_THREADS, 0, c->stream>>>(c->d_table, x, c->d_pT, (int)c->M,
                                                                c->table_mpad, c->m2l_chunk);
-  } else if (c->d_table)
+  } else if (c->d_table) {
     m2l_table_kernel<P><<<grid, M2L_THREADS, 0, c->stream>>>(c->d_table, x, c->d_pT, (int)c->M,
                                                              c->table_mpad, c->m2l_chunk);
-  else
+  } else if (c->m2l_split == 2) {
+    constexpr int NB = 2 * P + 1, H0 = (NB + 1) / 2;
+    m2l_half_kernel<P, 0, H0><<<grid, M2L_THREADS, 0, c->stream>>>(
+        c->d_cx, c->d_cy, x, c->d_pT, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
+        c->g.alpha_inv, c->d_htab);
+    m2l_half_kernel<P, H0, NB - H0><<<grid, M2L_THREADS, 0, c->stream>>>(
+        c->d_cx, c->d_cy, x, c->d_pT, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
+        c->g.alpha_inv, c->d_htab);
+  } else
     m2l_kernel<P, cd><<<grid, M2L_THREADS, 0, c->stream>>>(
         c->d_cx, c->d_cy, x, c->d_pT, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
         c->g.alpha_inv, c->d_htab, 0.0);
@@ -512,7 +535,8 @@ grt_status table_set(grt_ctx* c, bool on) {
 // Measure the translation launch for several source-chunk counts (work-group
 // counts from 256 to M2L_TUNE_MAX_WAVES) in the current mode (on the fly or resident
 // table) and keep the fastest.  Reports up to cap (chunks, ms per launch) pairs.
-grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, double* ms_out) {
+grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* splits_out,
+                        double* ms_out) {
   if (c->M == 0) {
     if (n_out) *n_out = 0;
     return GRT_OK;
@@ -525,38 +549,46 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, double
   const bool prof = c->prof;
   c->prof = false;
   GRT_HIP(c, hipMemsetAsync(c->d_xtmp, 0, sizeof(cd) * (size_t)c->n_beta, s));
-  int best_chunk = c->m2l_chunk, best_n = c->m2l_nchunks, count = 0;
+  int best_chunk = c->m2l_chunk, best_n = c->m2l_nchunks, best_split = c->m2l_split, count = 0;
   double best_ms = 1e300;
-  int last_nc = -1;
-  for (int64_t waves = 256; waves <= M2L_TUNE_MAX_WAVES; waves *= 2) {
-    int ch, nc;
-    split_work(M, (M + 63) / 64, waves / M2L_WAVES, 4 * M2L_WAVES, ch, nc);
-    if (nc == last_nc || nc > c->m2l_nchunks_cap) continue;
-    last_nc = nc;
-    c->m2l_chunk = ch;
-    c->m2l_nchunks = nc;
-    for (int r = 0; r < 2; ++r) GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
-    GRT_HIP(c, hipEventRecord(e0, s));
-    const int reps = 5;
-    for (int r = 0; r < reps; ++r) GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
-    GRT_HIP(c, hipEventRecord(e1, s));
-    GRT_HIP(c, hipEventSynchronize(e1));
-    float ms = 0.f;
-    GRT_HIP(c, hipEventElapsedTime(&ms, e0, e1));
-    const double per = ms / reps;
-    if (count < cap) {
-      if (chunks_out) chunks_out[count] = nc;
-      if (ms_out) ms_out[count] = per;
-    }
-    ++count;
-    if (per < best_ms) {
-      best_ms = per;
-      best_chunk = ch;
-      best_n = nc;
+  // the split into two launches applies to the FP64 generator on the fly only
+  const int max_split = c->d_table ? 1 : 2;
+  for (int split = 1; split <= max_split; ++split) {
+    int last_nc = -1;
+    for (int64_t waves = 256; waves <= M2L_TUNE_MAX_WAVES; waves *= 2) {
+      int ch, nc;
+      split_work(M, (M + 63) / 64, waves / M2L_WAVES, 4 * M2L_WAVES, ch, nc);
+      if (nc == last_nc || nc > c->m2l_nchunks_cap) continue;
+      last_nc = nc;
+      c->m2l_chunk = ch;
+      c->m2l_nchunks = nc;
+      c->m2l_split = split;
+      for (int r = 0; r < 2; ++r) GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
+      GRT_HIP(c, hipEventRecord(e0, s));
+      const int reps = 5;
+      for (int r = 0; r < reps; ++r) GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
+      GRT_HIP(c, hipEventRecord(e1, s));
+      GRT_HIP(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      GRT_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / reps;
+      if (count < cap) {
+        if (chunks_out) chunks_out[count] = nc;
+        if (splits_out) splits_out[count] = split;
+        if (ms_out) ms_out[count] = per;
+      }
+      ++count;
+      if (per < best_ms) {
+        best_ms = per;
+        best_chunk = ch;
+        best_n = nc;
+        best_split = split;
+      }
     }
   }
   c->m2l_chunk = best_chunk;
   c->m2l_nchunks = best_n;
+  c->m2l_split = best_split;
   c->prof = prof;
   graph_reset(c);
   hipEventDestroy(e0);

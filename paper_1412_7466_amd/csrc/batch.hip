@@ -51,6 +51,7 @@ struct InstDesc {
   // resident translation table of the FP64 apply (null: generator on the fly)
   const cd* table;
   int mpad;
+  int split;  // 2: FP64 on-the-fly translation as two half-output launches
   // 0 once the lockstep solver has no further use for this problem's applies: every
   // apply kernel then skips its work items and the combine writes zeros
   int active;
@@ -83,6 +84,18 @@ __global__ void __launch_bounds__(64 * CX_WAVES) cx_batched(const InstDesc* __re
   const InstDesc& q = D[w.inst];
   if (!q.active) return;
   cx_block<P>(q.g, q.cx, q.cy, X + q.off, q.pC, q.c_chunk, q.htab, w.x, w.y);
+}
+
+// FP64 translation on the fly, outputs [LO, LO + NH) only (the split launch shape)
+template <int P, int LO, int NH>
+__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(M2L_HALF_MINW, 8)))
+m2lh_batched(const InstDesc* __restrict__ D, const Item* __restrict__ it,
+             const cd* __restrict__ X) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  if (!q.active) return;
+  m2l_block<P, cd, LO, NH>(q.cx, q.cy, X + q.off, q.pT, q.M, q.m2l_chunk, q.g.k[1], q.g.d,
+                           q.g.alpha, q.g.alpha_inv, q.htab, 0.0, w.x, w.y);
 }
 
 // FP64 translation from the problem's resident table
@@ -511,10 +524,11 @@ struct grt_batch {
   struct Group {
     int P;
     // m2l: translation items of every problem (the mixed apply's FP32 launch); m2lf /
-    // m2lt: those of the problems without / with a resident table (FP64 apply)
-    Item *m2l = nullptr, *m2lf = nullptr, *m2lt = nullptr, *cx = nullptr, *bx = nullptr,
-         *nr = nullptr;
-    int n_m2l = 0, n_m2lf = 0, n_m2lt = 0, n_cx = 0, n_bx = 0, n_nr = 0;
+    // m2lh / m2lt: those of the problems on the fly in one launch / on the fly split
+    // over two half-output launches / with a resident table (FP64 apply)
+    Item *m2l = nullptr, *m2lf = nullptr, *m2lh = nullptr, *m2lt = nullptr, *cx = nullptr,
+         *bx = nullptr, *nr = nullptr;
+    int n_m2l = 0, n_m2lf = 0, n_m2lh = 0, n_m2lt = 0, n_cx = 0, n_bx = 0, n_nr = 0;
   };
   std::vector<uint64_t> gen;  // the contexts' generations at creation
   std::vector<Group> groups;
@@ -581,6 +595,11 @@ static grt_status upload(grt_batch* b, const std::vector<T>& v, T** out) {
 template <int P>
 static void launch_group_T(grt_batch* b, const grt_batch::Group& gp, const cd* X) {
   if (gp.n_m2lf) m2l_batched<P><<<gp.n_m2lf, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2lf, X);
+  if (gp.n_m2lh) {
+    constexpr int NB = 2 * P + 1, H0 = (NB + 1) / 2;
+    m2lh_batched<P, 0, H0><<<gp.n_m2lh, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2lh, X);
+    m2lh_batched<P, H0, NB - H0><<<gp.n_m2lh, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2lh, X);
+  }
   if (gp.n_m2lt) m2lt_batched<P><<<gp.n_m2lt, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2lt, X);
 }
 template <int P>
@@ -944,6 +963,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     q.zsafe = c->zsafe;
     q.table = c->d_table;
     q.mpad = c->table_mpad;
+    q.split = c->d_table ? 1 : c->m2l_split;
     q.active = 1;
     q.seg0 = seg;
     q.nseg = (int)((c->n_beta + SEG - 1) / SEG);
@@ -961,7 +981,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
   for (auto& kv : byP) {
     grt_batch::Group gp;
     gp.P = kv.first;
-    std::vector<Item> m2l, m2lf, m2lt, cxv, bxv, nr;
+    std::vector<Item> m2l, m2lf, m2lh, m2lt, cxv, bxv, nr;
     for (int i : kv.second) {
       const InstDesc& q = b->hd[i];
       const int nt = 2 * q.g.N + q.g.Nw[1];
@@ -969,7 +989,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
       for (int y = 0; y < q.m2l_nchunks; ++y)
         for (int x = 0; x < (q.M + 63) / 64; ++x) {
           m2l.push_back({i, x, y});
-          (q.table ? m2lt : m2lf).push_back({i, x, y});
+          (q.table ? m2lt : q.split == 2 ? m2lh : m2lf).push_back({i, x, y});
         }
       for (int y = 0; y < q.c_nchunks; ++y)
         for (int x = 0; x < (nt + 63) / 64; ++x) cxv.push_back({i, x, y});
@@ -979,9 +999,10 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     grt_status st;
     if ((st = upload(b, m2l, &gp.m2l)) != GRT_OK || (st = upload(b, cxv, &gp.cx)) != GRT_OK ||
         (st = upload(b, bxv, &gp.bx)) != GRT_OK || (st = upload(b, nr, &gp.nr)) != GRT_OK ||
-        (st = upload(b, m2lf, &gp.m2lf)) != GRT_OK || (st = upload(b, m2lt, &gp.m2lt)) != GRT_OK) {
-      for (void* q : {(void*)gp.m2l, (void*)gp.m2lf, (void*)gp.m2lt, (void*)gp.cx, (void*)gp.bx,
-                      (void*)gp.nr})
+        (st = upload(b, m2lf, &gp.m2lf)) != GRT_OK || (st = upload(b, m2lh, &gp.m2lh)) != GRT_OK ||
+        (st = upload(b, m2lt, &gp.m2lt)) != GRT_OK) {
+      for (void* q : {(void*)gp.m2l, (void*)gp.m2lf, (void*)gp.m2lh, (void*)gp.m2lt, (void*)gp.cx,
+                      (void*)gp.bx, (void*)gp.nr})
         if (q) hipFree(q);
       grt_batch_destroy(b);
       return st;
@@ -989,6 +1010,7 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
     gp.n_nr = (int)nr.size();
     gp.n_m2l = (int)m2l.size();
     gp.n_m2lf = (int)m2lf.size();
+    gp.n_m2lh = (int)m2lh.size();
     gp.n_m2lt = (int)m2lt.size();
     gp.n_cx = (int)cxv.size();
     gp.n_bx = (int)bxv.size();
@@ -1051,6 +1073,7 @@ grt_status grt_batch_destroy(grt_batch* b) {
   for (auto& gp : b->groups) {
     p.push_back(gp.m2l);
     p.push_back(gp.m2lf);
+    p.push_back(gp.m2lh);
     p.push_back(gp.m2lt);
     p.push_back(gp.cx);
     p.push_back(gp.bx);

@@ -292,6 +292,7 @@ grt_status grt_query(const grt_ctx* c, grt_sizes* out) {
   out->rank = c->built ? c->rank : 0;
   out->Nrb = c->g.Nrb;
   out->m2l_chunks = c->built ? c->m2l_nchunks : 0;
+  out->m2l_split = c->built ? c->m2l_split : 0;
   out->cx_chunks = c->built ? c->c_nchunks : 0;
   out->bx_chunks = c->built ? c->b_nchunks : 0;
   return GRT_OK;
@@ -338,12 +339,29 @@ grt_status grt_rhs(grt_ctx* c, void* b) {
   return rhs_b(c, static_cast<cd*>(b));
 }
 
-grt_status grt_autotune(grt_ctx* c, int cap, int* n, int* chunks, double* ms) {
+grt_status grt_set_launch(grt_ctx* c, int m2l_chunks, int m2l_split) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_built(c);
+  if (st != GRT_OK) return st;
+  if (m2l_split != 1 && m2l_split != 2) return set_err(c, GRT_EINVAL, "split must be 1 or 2");
+  if (c->M == 0) return GRT_OK;
+  if (m2l_chunks < 1 || m2l_chunks > c->m2l_nchunks_cap || m2l_chunks > c->M)
+    return set_err(c, GRT_EINVAL, "chunk count must be in [1, " +
+                                      std::to_string(std::min<int64_t>(c->m2l_nchunks_cap, c->M)) + "]");
+  const int64_t ch = (c->M + m2l_chunks - 1) / m2l_chunks;
+  c->m2l_chunk = (int)ch;
+  c->m2l_nchunks = (int)((c->M + ch - 1) / ch);
+  c->m2l_split = m2l_split;
+  graph_reset(c);
+  return GRT_OK;
+}
+
+grt_status grt_autotune(grt_ctx* c, int cap, int* n, int* chunks, int* splits, double* ms) {
   GRT_CHECK_CTX(c);
   grt_status st = check_built(c);
   if (st != GRT_OK) return st;
   if (cap < 0 || (cap > 0 && (!chunks || !ms))) return set_err(c, GRT_EINVAL, "bad arrays");
-  st = autotune_m2l(c, cap, n, chunks, ms);
+  st = autotune_m2l(c, cap, n, chunks, splits, ms);
   if (st != GRT_OK) return st;
   return autotune_coupling(c);
 }

@@ -85,6 +85,7 @@ struct grt_ctx {
   // apply workspace
   int m2l_chunk = 16, m2l_nchunks = 0;
   int m2l_nchunks_cap = 0;  // partial buffers hold this many chunks
+  int m2l_split = 1;        // on-the-fly FP64 translation over 1 or 2 launches (halves of n)
   int c_chunk = 64, c_nchunks = 0, c_nchunks_cap = 0;
   int b_chunk = 64, b_nchunks = 0, b_nchunks_cap = 0;
   cd* d_pT = nullptr;       // [m2l_nchunks][M][nb]
@@ -157,7 +158,8 @@ grt_status incident_alpha(grt_ctx* c, cd* out);
 grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out_cd /* device [2 Nrb] */);
 grt_status apply_alloc(grt_ctx* c);
 grt_status table_set(grt_ctx* c, bool on);
-grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, double* ms_out);
+grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* splits_out,
+                        double* ms_out);
 grt_status autotune_coupling(grt_ctx* c);
 constexpr int M2L_TUNE_MAX_WAVES = 8192;
 size_t table_bytes(const grt_ctx* c);

@@ -12,6 +12,10 @@ constexpr int M2L_WAVES = 4;     // waves per block: same 64 targets, sources sp
 constexpr int M2L_THREADS = 64 * M2L_WAVES;
 constexpr int M2L_TILE = 16;     // sources staged in LDS at a time, per wave
 constexpr int M2L_QB = 4;        // generator orders produced per block of the contraction
+#ifndef M2L_HALF_MINW
+#define M2L_HALF_MINW 2  // waves per SIMD asked of the register allocator for the split
+                         // (half-output) translation kernels
+#endif
 #ifndef M2L_TNUG
 #define M2L_TNUG 2               // coefficients read ahead in the table kernel's contraction
 #endif
@@ -107,10 +111,10 @@ __device__ __forceinline__ void pair_generate(double dx, double dy, double k, do
   }
 }
 
-// acc[n] += sum over the block's orders q of tau_q x[n+q] + tau_{-q} x[n-q]
-// (n = -P..P at index n + P); each x[nu] is read once per block and feeds up to
-// 2 M2L_QB complex FMAs.
-template <int P, typename T, typename BP, int NUG = 1 << 20>
+// acc[n - LO] += sum over the block's orders q of tau_q x[n+q] + tau_{-q} x[n-q] for
+// the outputs n in [LO, LO + NH) (n = -P..P at index n + P; by default all of them);
+// each x[nu] is read once per block and feeds up to 2 M2L_QB complex FMAs.
+template <int P, typename T, typename BP, int NUG = 1 << 20, int LO = 0, int NH = 2 * P + 1>
 __device__ __forceinline__ void contract_block(T* acc, BP b, int qb, const T* tp, const T* tm) {
   constexpr int NB = 2 * P + 1;
   // x may be re-read here: keeps x[nu] out of registers across blocks of orders
@@ -121,7 +125,8 @@ __device__ __forceinline__ void contract_block(T* acc, BP b, int qb, const T* tp
 #pragma unroll
     for (int u = 0; u < M2L_QB; ++u) {
       const int q = 1 + qb * M2L_QB + u;
-      if (q <= 2 * P && (nu - q >= 0 || nu + q < NB)) need = true;
+      if (q <= 2 * P && ((nu - q >= LO && nu - q < LO + NH) || (nu + q >= LO && nu + q < LO + NH)))
+        need = true;
     }
     if (!need) continue;
     const T bv = b[nu];
@@ -131,27 +136,26 @@ __device__ __forceinline__ void contract_block(T* acc, BP b, int qb, const T* tp
     for (int u = 0; u < M2L_QB; ++u) {
       const int q = 1 + qb * M2L_QB + u;
       if (q > 2 * P) continue;
-      if (nu - q >= 0) cmac(acc[nu - q], tp[u], bv);   // acc[n] += t_q x[n+q]
-      if (nu + q < NB) cmac(acc[nu + q], tm[u], bv);   // acc[n] += t_{-q} x[n-q]
+      if (nu - q >= LO && nu - q < LO + NH) cmac(acc[nu - q - LO], tp[u], bv);  // t_q x[n+q]
+      if (nu + q >= LO && nu + q < LO + NH) cmac(acc[nu + q - LO], tm[u], bv);  // t_{-q} x[n-q]
     }
   }
 }
 
 // Contribution of one source inclusion (and its copies) to the incoming
-// coefficients acc[n] of one target: acc[n] += sum_nu tau_{nu-n} x[nu], with the
-// generator computed on the fly.  T is the accumulation type (cd: FP64, cf: FP32
-// with FP32 accumulation; the generator is FP64 either way).
-template <int P, typename T, typename BP, typename TabPtr>
+// coefficients acc[n - LO] of one target, n in [LO, LO + NH): acc[n] += sum_nu
+// tau_{nu-n} x[nu], with the generator computed on the fly.  T is the accumulation
+// type (cd: FP64, cf: FP32 with FP32 accumulation; the generator is FP64 either way).
+template <int P, typename T, typename BP, typename TabPtr, int LO = 0, int NH = 2 * P + 1>
 __device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double dy, double k,
                                                 double d, const cd* wl, bool skip0, bool dead,
                                                 TabPtr tab, double zsafe) {
-  constexpr int NB = 2 * P + 1;
   pair_generate<P>(
       dx, dy, k, d, wl, skip0, dead, tab, zsafe,
       [&](cd t0) {
         const T t = to_acc(t0, (T*)nullptr);
 #pragma unroll
-        for (int n = 0; n < NB; ++n) cmac(acc[n], t, b[n]);
+        for (int n = 0; n < NH; ++n) cmac(acc[n], t, b[n + LO]);
       },
       [&](int qb, const cd* tp, const cd* tm) {
         T a[M2L_QB], c[M2L_QB];
@@ -160,7 +164,7 @@ __device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double 
           a[u] = to_acc(tp[u], (T*)nullptr);
           c[u] = to_acc(tm[u], (T*)nullptr);
         }
-        contract_block<P, T>(acc, b, qb, a, c);
+        contract_block<P, T, BP, 1 << 20, LO, NH>(acc, b, qb, a, c);
       });
 }
 
@@ -169,8 +173,10 @@ __device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double 
 // the block's four waves take a quarter of the sources each, stage them in LDS
 // (every lane then reads the same address: a broadcast) and are summed through
 // LDS at the end.  T = cd: FP64; T = cf: FP32 contraction and accumulation with
-// pairs closer than zsafe left out.
-template <int P, typename T>
+// pairs closer than zsafe left out.  Only the outputs n in [LO, LO + NH) (index
+// n + P) are formed and stored: a launch may split them over two blocks, each
+// recomputing the generator, to halve the accumulators a lane holds.
+template <int P, typename T, int LO = 0, int NH = 2 * P + 1>
 __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
                                                           const double* __restrict__ cy,
                                                           const T* __restrict__ x, T* partial,
@@ -181,7 +187,7 @@ __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
   constexpr int NB = 2 * P + 1;
   constexpr int TW = sizeof(T) / sizeof(double);  // doubles per complex value (1 or 2)
   constexpr int STAGE = M2L_WAVES * M2L_TILE * (TW * NB + 2);
-  constexpr int RED = TW * NB * 64;
+  constexpr int RED = TW * NH * 64;
   constexpr int BUF = STAGE > RED ? STAGE : RED;
   __shared__ double smem[BUF];
   __shared__ double stab[HTAB_SIZE];
@@ -200,9 +206,9 @@ __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
   for (int t = threadIdx.x; t < HTAB_SIZE; t += M2L_THREADS) stab[t] = htab[t];
   const bool live = j < M;
   const double xj = live ? cx[j] : 0.0, yj = live ? cy[j] : 0.0;
-  T acc[NB];
+  T acc[NH];
 #pragma unroll
-  for (int n = 0; n < NB; ++n) acc[n] = T{0, 0};
+  for (int n = 0; n < NH; ++n) acc[n] = T{0, 0};
   const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
   for (int it = 0; it < ntile; ++it) {
     const int ts = s0 + it * M2L_TILE;
@@ -216,8 +222,8 @@ __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
     __syncthreads();
     for (int mm = 0; mm < cnt; ++mm) {
       const int m = ts + mm;
-      pair_accumulate<P, T>(acc, sx + mm * NB, xj - scx[mm], yj - scy[mm], k, d, wl, j == m,
-                            !live, stab, zsafe);
+      pair_accumulate<P, T, const T*, const double*, LO, NH>(
+          acc, sx + mm * NB, xj - scx[mm], yj - scy[mm], k, d, wl, j == m, !live, stab, zsafe);
     }
   }
   // sum the four waves' partial results through LDS: wave 3, then 2, then 1 add into
@@ -227,7 +233,7 @@ __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
     __syncthreads();
     if (wv == src) {
 #pragma unroll
-      for (int n = 0; n < NB; ++n) {
+      for (int n = 0; n < NH; ++n) {
         T v = acc[n];
         if (src != M2L_WAVES - 1) {
           T o = red[n * 64 + lane];
@@ -240,9 +246,9 @@ __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
   }
   __syncthreads();
   if (wv == 0 && live) {
-    T* out = partial + ((size_t)by_ * M + j) * NB;
+    T* out = partial + ((size_t)by_ * M + j) * NB + LO;
 #pragma unroll
-    for (int n = 0; n < NB; ++n) {
+    for (int n = 0; n < NH; ++n) {
       T o = red[n * 64 + lane];
       out[n] = T{acc[n].r + o.r, acc[n].i + o.i};
     }

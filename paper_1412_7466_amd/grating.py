@@ -52,7 +52,8 @@ class grt_solve_stats(C.Structure):
 class grt_sizes(C.Structure):
     _fields_ = [("M", C.c_int64), ("P", C.c_int), ("n_beta", C.c_int64), ("n_rows", C.c_int64),
                 ("n_alpha", C.c_int64), ("rank", C.c_int64), ("Nrb", C.c_int),
-                ("m2l_chunks", C.c_int), ("cx_chunks", C.c_int), ("bx_chunks", C.c_int)]
+                ("m2l_chunks", C.c_int), ("m2l_split", C.c_int), ("cx_chunks", C.c_int),
+                ("bx_chunks", C.c_int)]
 
 
 class grt_nn_config(C.Structure):
@@ -76,8 +77,9 @@ _PROTOS = {
     "grt_incident": (C.c_int, [_VP, _VP]),
     "grt_set_table": (C.c_int, [_VP, C.c_int]),
     "grt_table_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "grt_set_launch": (C.c_int, [_VP, C.c_int, C.c_int]),
     "grt_autotune": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                               C.POINTER(C.c_double)]),
+                               C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
     "grt_bragg": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -258,19 +260,28 @@ class Context:
         self._check(self.lib.grt_set_table(self.h, int(mode)))
         self._leave()
 
-    def autotune(self, cap=16):
-        """Time the translation launch for several chunk counts and keep the
-        fastest, then the same for the C x and B_phys w launches; returns the
-        translation's [(chunks, ms per launch)] (the chosen coupling chunk counts
-        are in self.sizes)."""
-        n = C.c_int(0)
-        ch = (C.c_int * cap)()
-        ms = (C.c_double * cap)()
+    def set_launch(self, m2l_chunks, m2l_split=1):
+        """Translation launch shape by hand: about m2l_chunks source chunks, split 1
+        or 2 (two launches, half of the outputs each)."""
         self._enter()
-        self._check(self.lib.grt_autotune(self.h, cap, C.byref(n), ch, ms))
+        self._check(self.lib.grt_set_launch(self.h, int(m2l_chunks), int(m2l_split)))
         self._leave()
         self.sizes = self.query()
-        return [(ch[i], ms[i]) for i in range(n.value)]
+
+    def autotune(self, cap=32):
+        """Time the translation launch for several chunk counts (and, on the fly,
+        split over two launches or not) and keep the fastest, then the same for the
+        C x and B_phys w launches; returns the translation's [(chunks, split, ms per
+        launch)] (the choices are in self.sizes)."""
+        n = C.c_int(0)
+        ch = (C.c_int * cap)()
+        sp = (C.c_int * cap)()
+        ms = (C.c_double * cap)()
+        self._enter()
+        self._check(self.lib.grt_autotune(self.h, cap, C.byref(n), ch, sp, ms))
+        self._leave()
+        self.sizes = self.query()
+        return [(ch[i], sp[i], ms[i]) for i in range(n.value)]
 
     def table_bytes(self):
         n = C.c_int64(0)

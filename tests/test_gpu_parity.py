@@ -202,6 +202,9 @@ def test_batched_solve_matches_single_and_oracle(torch_cuda):
     # stream it, the others evaluate the generator on the fly
     ctxs[1].set_table(True)
     ctxs[4].set_table(True)
+    # two with the on-the-fly translation split over two half-output launches
+    ctxs[2].set_launch(2, 2)
+    ctxs[5].set_launch(1, 2)
     say("[gpu] batch create", len(ctxs))
     batch = Batch(ctxs)
     betas, stats = batch.solve(tol=1e-12, restart=150)
@@ -347,13 +350,43 @@ def test_autotune_keeps_parity(torch_cuda, M, P, seed, table):
         ctx.set_table(True)
     xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
     tuned = ctx.autotune()
-    say(f"[gpu] autotune M={M} P={P} table={table}: {tuned} -> {ctx.sizes.m2l_chunks} chunks, "
+    say(f"[gpu] autotune M={M} P={P} table={table}: {tuned} -> {ctx.sizes.m2l_chunks} chunks "
+        f"split {ctx.sizes.m2l_split}, "
         f"C x {ctx.sizes.cx_chunks}, B_phys w {ctx.sizes.bx_chunks}")
     assert len(tuned) >= 1
     assert ctx.sizes.cx_chunks >= 1 and ctx.sizes.bx_chunks >= 1
-    assert ctx.sizes.m2l_chunks in [c for c, _ in tuned]
+    assert (ctx.sizes.m2l_chunks, ctx.sizes.m2l_split) in [(c, sp) for c, sp, _ in tuned]
+    assert ctx.sizes.m2l_split in ((1,) if table else (1, 2))
     assert rel(_np(ctx.apply_T(xd)), red.T_apply(xh)) < 1e-12
     assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+
+
+@pytest.mark.parametrize("M,P,seed", [(67, 4, 71), (30, 10, 72), (40, 15, 73), (25, 20, 74)])
+def test_split_translation_matches(torch_cuda, M, P, seed):
+    """The on-the-fly translation split over two launches (half of the outputs each)
+    gives the one-launch result bit for bit (each output sums the same terms in the
+    same order) and matches the oracle; likewise after a change of chunk count."""
+    from oracle.solver import Reduced
+    pb = inputs.small(M, P, seed=seed)
+    red = Reduced(pb)
+    ctx = _ctx(pb)
+    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    for chunks in (1, 2):
+        ctx.set_launch(chunks, 1)
+        y1 = _np(ctx.apply_T(xd))
+        ctx.set_launch(chunks, 2)
+        assert ctx.sizes.m2l_split == 2
+        y2 = _np(ctx.apply_T(xd))
+        say(f"[gpu] split M={M} P={P} chunks={ctx.sizes.m2l_chunks}: "
+            f"max |diff| {np.max(np.abs(y2 - y1)):.1e}")
+        assert np.array_equal(y1, y2)
+        assert rel(y2, red.T_apply(xh)) < 1e-12
+        assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+    from paper_1412_7466_amd.grating import GratingError, GRT_EINVAL
+    with pytest.raises(GratingError) as ei:
+        ctx.set_launch(1, 3)
+    assert ei.value.status == GRT_EINVAL
+    ctx.close()
 
 
 def test_graph_replayed_solves_match_eager(torch_cuda):
