@@ -174,8 +174,9 @@ grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision
  * has one when the batch is created (changing the mode afterwards makes
  * grt_batch_solve return GRT_ESTATE). */
 grt_status grt_set_table(grt_ctx* ctx, int mode);
-/* Launch-shape autotuner: times the translation launch for source chunk counts
- * giving 256 .. 8192 work-groups, in the current mode (on the fly or resident
+/* Launch-shape autotuner: times the translation launch, with the pass that adds
+ * its per-chunk partial results, for source chunk counts giving 256 .. 16384
+ * wavefronts, in the current mode (on the fly or resident
  * table; on the fly also split over two launches, each forming half of the
  * outputs with half the accumulators per lane), then the C x and B_phys w launches
  * (each with the pass that adds its per-chunk partial results) for 1 .. 64 sources

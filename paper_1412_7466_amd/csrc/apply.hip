@@ -532,9 +532,10 @@ grt_status table_set(grt_ctx* c, bool on) {
   return GRT_OK;
 }
 
-// Measure the translation launch for several source-chunk counts (work-group
-// counts from 256 to M2L_TUNE_MAX_WAVES) in the current mode (on the fly or resident
-// table) and keep the fastest.  Reports up to cap (chunks, ms per launch) pairs.
+// Measure the translation launch, with the pass that adds its partial results, for
+// several source-chunk counts (work-group counts from 256 to M2L_TUNE_MAX_WAVES) in
+// the current mode (on the fly: also split over two launches; or resident table) and
+// keep the fastest.  Reports up to cap (chunks, split, ms) triples.
 grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* splits_out,
                         double* ms_out) {
   if (c->M == 0) {
@@ -546,6 +547,8 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* s
   hipEvent_t e0, e1;
   GRT_HIP(c, hipEventCreate(&e0));
   GRT_HIP(c, hipEventCreate(&e1));
+  cd* ytmp = nullptr;
+  GRT_HIP(c, hipMalloc(&ytmp, sizeof(cd) * (size_t)c->n_beta));
   const bool prof = c->prof;
   c->prof = false;
   GRT_HIP(c, hipMemsetAsync(c->d_xtmp, 0, sizeof(cd) * (size_t)c->n_beta, s));
@@ -563,10 +566,21 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* s
       c->m2l_chunk = ch;
       c->m2l_nchunks = nc;
       c->m2l_split = split;
-      for (int r = 0; r < 2; ++r) GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
+      // each candidate is timed with the pass that adds its partial results (the
+      // combine reads one partial per chunk)
+      const int n = (int)c->n_beta;
+      for (int r = 0; r < 2; ++r) {
+        GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
+        combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
+            n, c->d_xtmp, c->d_mie, c->d_pT, c->m2l_nchunks, c->d_pB, 0, nullptr, ytmp, 1, nullptr);
+      }
       GRT_HIP(c, hipEventRecord(e0, s));
       const int reps = 5;
-      for (int r = 0; r < reps; ++r) GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
+      for (int r = 0; r < reps; ++r) {
+        GRT_P_DISPATCH(launch_m2l, c->P, c, c->d_xtmp);
+        combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
+            n, c->d_xtmp, c->d_mie, c->d_pT, c->m2l_nchunks, c->d_pB, 0, nullptr, ytmp, 1, nullptr);
+      }
       GRT_HIP(c, hipEventRecord(e1, s));
       GRT_HIP(c, hipEventSynchronize(e1));
       float ms = 0.f;
@@ -593,6 +607,7 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* s
   graph_reset(c);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  hipFree(ytmp);
   GRT_HIP(c, hipGetLastError());
   if (n_out) *n_out = std::min(count, cap);
   return GRT_OK;

@@ -161,7 +161,7 @@ grt_status table_set(grt_ctx* c, bool on);
 grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* splits_out,
                         double* ms_out);
 grt_status autotune_coupling(grt_ctx* c);
-constexpr int M2L_TUNE_MAX_WAVES = 8192;
+constexpr int M2L_TUNE_MAX_WAVES = 16384;
 size_t table_bytes(const grt_ctx* c);
 
 // krylov (krylov.hip)
