@@ -196,6 +196,13 @@ grt_status grt_autotune(grt_ctx* ctx, int cap, int* n, int* chunks, int* splits,
  * change only by the order of the chunk sums.  GRT_EINVAL outside those ranges. */
 grt_status grt_set_launch(grt_ctx* ctx, int m2l_chunks, int m2l_split);
 
+/* on = 1: the FP64 apply runs C x, A^+ and B_phys w (bound by FP64 arithmetic) on a
+ * second stream of the context, concurrently with the translation T x (bound by HBM
+ * in table mode), joining before the combine; every later apply, solve and captured
+ * graph of this context does so.  Results are identical (the same kernels with the
+ * same inputs).  on = 0: one stream (the default).  GRT_EINVAL for other values. */
+grt_status grt_set_overlap(grt_ctx* ctx, int on);
+
 /* Bytes the table of the current problem takes. */
 grt_status grt_table_bytes(const grt_ctx* ctx, int64_t* bytes);
 

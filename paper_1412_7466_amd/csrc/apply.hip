@@ -298,18 +298,18 @@ __global__ void near_fill_kernel(const double* cx, const double* cy, int M, doub
 }
 
 template <int P>
-void launch_cx(grt_ctx* c, const cd* x) {
+void launch_cx(grt_ctx* c, const cd* x, hipStream_t st) {
   const int nt = 2 * c->g.N + c->g.Nw[1];
   dim3 grid((nt + 63) / 64, c->c_nchunks);
-  cx_kernel<P><<<grid, 64 * CX_WAVES, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, x, c->d_pC, c->c_chunk,
-                                            c->d_htab);
+  cx_kernel<P><<<grid, 64 * CX_WAVES, 0, st>>>(c->g, c->d_cx, c->d_cy, x, c->d_pC, c->c_chunk,
+                                               c->d_htab);
 }
 
 template <int P>
-void launch_bx(grt_ctx* c, const cd* w) {
+void launch_bx(grt_ctx* c, const cd* w, hipStream_t st) {
   dim3 grid((unsigned)((c->M + 63) / 64), c->b_nchunks);
-  bx_kernel<P><<<grid, 64 * BX_WAVES, 0, c->stream>>>(c->g, c->d_cx, c->d_cy, w, c->d_pB, c->b_chunk,
-                                           c->d_htab);
+  bx_kernel<P><<<grid, 64 * BX_WAVES, 0, st>>>(c->g, c->d_cx, c->d_cy, w, c->d_pB, c->b_chunk,
+                                               c->d_htab);
 }
 
 #define GRT_P_DISPATCH(FN, P, ...)                        \
@@ -420,11 +420,11 @@ grt_status apply_alloc(grt_ctx* c) {
 }
 
 // w = A^+ g on the prefix entries B reads, then alpha^L into pB (partials) and pL.
-static grt_status lowrank_tail(grt_ctx* c, const cd* gvec) {
-  hipStream_t s = c->stream;
+static grt_status lowrank_tail(grt_ctx* c, const cd* gvec, hipStream_t s = nullptr) {
+  if (!s) s = c->stream;
   launch_gemv_rows(s, c->d_W1, gvec, c->d_tvec, c->rank, c->n_g);
   launch_gemv_rows(s, c->d_W2, c->d_tvec, c->d_wvec, c->n_b, c->rank);
-  GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec);
+  GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec, s);
   {
     const int ntb = l2l_targets_per_block(c->P, c->g.Q[1]);
     const size_t sh = l2l_lds_bytes(c->P, c->g.Q[1], ntb);
@@ -435,10 +435,11 @@ static grt_status lowrank_tail(grt_ctx* c, const cd* gvec) {
   return GRT_OK;
 }
 
-static grt_status cx_apply(grt_ctx* c, const cd* x) {
+static grt_status cx_apply(grt_ctx* c, const cd* x, hipStream_t s = nullptr) {
+  if (!s) s = c->stream;
   const int nt = 2 * c->g.N + c->g.Nw[1];
-  GRT_P_DISPATCH(launch_cx, c->P, c, x);
-  cx_reduce_kernel<<<(nt + 3) / 4, 256, 0, c->stream>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
+  GRT_P_DISPATCH(launch_cx, c->P, c, x, s);
+  cx_reduce_kernel<<<(nt + 3) / 4, 256, 0, s>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
@@ -449,12 +450,26 @@ static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode,
   hipStream_t s = c->stream;
   bool needT = (mode == 0 || mode == 1);
   bool needB = (mode == 0 || mode == 2);
-  if (needT) GRT_P_DISPATCH(launch_m2l, c->P, c, x);
-  if (needB) {
-    grt_status st = cx_apply(c, x);
+  if (needT && needB && c->overlap && c->stream2) {
+    // C x, A^+ and B_phys w (ALU-bound) on the second stream, concurrently with the
+    // translation; the combine waits for both
+    GRT_HIP(c, hipEventRecord(c->ev_fork, s));
+    GRT_HIP(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+    grt_status st = cx_apply(c, x, c->stream2);
     if (st != GRT_OK) return st;
-    st = lowrank_tail(c, c->d_gvec);
+    st = lowrank_tail(c, c->d_gvec, c->stream2);
     if (st != GRT_OK) return st;
+    GRT_HIP(c, hipEventRecord(c->ev_join, c->stream2));
+    GRT_P_DISPATCH(launch_m2l, c->P, c, x);
+    GRT_HIP(c, hipStreamWaitEvent(s, c->ev_join, 0));
+  } else {
+    if (needT) GRT_P_DISPATCH(launch_m2l, c->P, c, x);
+    if (needB) {
+      grt_status st = cx_apply(c, x);
+      if (st != GRT_OK) return st;
+      st = lowrank_tail(c, c->d_gvec);
+      if (st != GRT_OK) return st;
+    }
   }
   int n = (int)c->n_beta;
   combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
@@ -657,7 +672,7 @@ grt_status autotune_coupling(grt_ctx* c) {
       c->c_chunk = ch;
       c->c_nchunks = nc;
       const double ms = time_it([&]() -> grt_status {
-        GRT_P_DISPATCH(launch_cx, c->P, c, c->d_xtmp);
+        GRT_P_DISPATCH(launch_cx, c->P, c, c->d_xtmp, s);
         cx_reduce_kernel<<<(nt + 3) / 4, 256, 0, s>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
         return GRT_OK;
       });
@@ -679,7 +694,7 @@ grt_status autotune_coupling(grt_ctx* c) {
       c->b_chunk = ch;
       c->b_nchunks = nc;
       const double ms = time_it([&]() -> grt_status {
-        GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec);
+        GRT_P_DISPATCH(launch_bx, c->P, c, c->d_wvec, s);
         combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
             n, c->d_xtmp, c->d_mie, c->d_pT, 0, c->d_pB, c->b_nchunks, c->d_pL, ytmp, 2, nullptr);
         return GRT_OK;

@@ -103,6 +103,12 @@ grt_status grt_destroy(grt_ctx* c) {
     if (e) hipEventDestroy(e);
   if (c->h_pinned) hipHostFree(c->h_pinned);
   if (c->h_H) hipHostFree(c->h_H);
+  if (c->stream2) {
+    hipStreamSynchronize(c->stream2);
+    hipStreamDestroy(c->stream2);
+  }
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
   return GRT_OK;
@@ -337,6 +343,20 @@ grt_status grt_rhs(grt_ctx* c, void* b) {
   if (st != GRT_OK) return st;
   if (!b) return set_err(c, GRT_EINVAL, "null vector");
   return rhs_b(c, static_cast<cd*>(b));
+}
+
+grt_status grt_set_overlap(grt_ctx* c, int on) {
+  GRT_CHECK_CTX(c);
+  if (on != 0 && on != 1) return set_err(c, GRT_EINVAL, "overlap must be 0 or 1");
+  GRT_HIP(c, hipSetDevice(c->device));
+  if (on && !c->stream2) {
+    GRT_HIP(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+    GRT_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    GRT_HIP(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
+  c->overlap = on != 0;
+  graph_reset(c);
+  return GRT_OK;
 }
 
 grt_status grt_set_launch(grt_ctx* c, int m2l_chunks, int m2l_split) {

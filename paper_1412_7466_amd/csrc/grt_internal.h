@@ -49,6 +49,10 @@ struct grt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // second stream of the FP64 apply: C x, A^+ and B_phys w concurrently with T x
+  bool overlap = false;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   // problem (host copies)
   bool have_problem = false, built = false;

@@ -78,6 +78,7 @@ _PROTOS = {
     "grt_set_table": (C.c_int, [_VP, C.c_int]),
     "grt_table_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "grt_set_launch": (C.c_int, [_VP, C.c_int, C.c_int]),
+    "grt_set_overlap": (C.c_int, [_VP, C.c_int]),
     "grt_autotune": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
@@ -267,6 +268,12 @@ class Context:
         self._check(self.lib.grt_set_launch(self.h, int(m2l_chunks), int(m2l_split)))
         self._leave()
         self.sizes = self.query()
+
+    def set_overlap(self, on):
+        """Run C x, A^+ and B_phys w on a second stream, concurrently with T x."""
+        self._enter()
+        self._check(self.lib.grt_set_overlap(self.h, int(bool(on))))
+        self._leave()
 
     def autotune(self, cap=32):
         """Time the translation launch for several chunk counts (and, on the fly,

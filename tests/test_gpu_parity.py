@@ -389,6 +389,35 @@ def test_split_translation_matches(torch_cuda, M, P, seed):
     ctx.close()
 
 
+def test_overlapped_apply_matches(torch_cuda):
+    """The FP64 apply with C x, A^+ and B_phys w on a second stream (concurrent with the
+    translation) gives the one-stream result bit for bit, eager and replayed from a
+    captured graph, on the fly and with the resident table."""
+    from oracle.solver import Reduced
+    pb = inputs.small(40, 10, seed=81)
+    red = Reduced(pb)
+    ctx = _ctx(pb)
+    xh, xd = _randvec(torch_cuda, red.G.n_beta, 81, 10)
+    for table in (False, True):
+        ctx.set_table(table)
+        ctx.set_overlap(False)
+        y0 = _np(ctx.apply(xd))
+        b0, s0 = ctx.solve(tol=1e-12, restart=150)
+        ctx.set_overlap(True)
+        y1 = _np(ctx.apply(xd))
+        assert np.array_equal(y0, y1)
+        assert rel(y1, red.K_apply(xh)) < 1e-9
+        for rep in range(3):
+            b1, s1 = ctx.solve(tol=1e-12, restart=150, graph=True)
+            torch_cuda.cuda.synchronize()
+            assert s1.iters == s0.iters
+            assert np.array_equal(_np(b1), _np(b0)), (table, rep)
+            ctx.apply(xd)
+        say(f"[gpu] overlap table={table}: iters {s0.iters}, identical")
+    ctx.set_overlap(False)
+    ctx.close()
+
+
 def test_graph_replayed_solves_match_eager(torch_cuda):
     """Solves whose applies replay a captured HIP graph equal the eager solves, on
     every replay, with eager work and synchronisations between the replays, across a
