@@ -97,7 +97,8 @@ def record_traffic(fetch_db, write_db, kernel, copy_bytes, commands):
         f.write("# HBM traffic of the resident-table translation kernel, M=1000, P=15\n\n")
         f.write("Two rocprofv3 counter runs of the benchmark (table mode, default launch shape) "
                 "with a plain device copy of known size appended; each counter is scaled by "
-                "what it reads for the copy.\n\nCommands (repository root, one MI355X):\n\n")
+                "what it reads for the copy.\n\nCommands (repository root, one MI355X):\n\n"
+                "($REPO is the repository root, $OUT any output directory.)\n\n")
         for cmd in commands:
             f.write(f"```\n{cmd}\n```\n\n")
         f.write(f"FETCH_SIZE {kf:.1f} KiB per dispatch (copy of {copy_bytes} B: {cf:.1f} KiB); "
@@ -420,7 +421,7 @@ def main():
     a = ap.parse_args()
     if a.traffic_record:
         cmds = [f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc {c} --kernel-include-regex "
-                f"'m2l_table_kernel|copyBuffer' -d $REPO/gpurun_out/pmc_{c.lower()} -o run -- "
+                f"'m2l_table_kernel|copyBuffer' -d $OUT/pmc_{c.lower()} -o run -- "
                 f"python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-sweep "
                 f"--no-autotune --copy-probe-mib 1024" for c in ("FETCH_SIZE", "WRITE_SIZE")]
         print(json.dumps(record_traffic(a.traffic_record[0], a.traffic_record[1],

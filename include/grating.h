@@ -291,8 +291,8 @@ grt_status grt_batch_solve(grt_batch* batch, const grt_solve_opts* opts, void* c
  * Mie diagonal; out = 0 for |n| > p_out),
  * i.e. the exact relation beta = S alpha of sec. 5 with the incoming field alpha
  * predicted.  grt_solve with use_x0 drops a guess no better than zero
- * (stats.x0_rejected), so the plain solve stays the fallback and the judge of the
- * result.
+ * (stats.x0_rejected), so the plain solve stays the fallback, and GMRES to the
+ * requested residual decides the accuracy of the result.
  *
  * Network, width H, L layers, node inputs f_j (32), edge inputs e_jk (8):
  *   h = relu(W_in f + b_in);  per layer: P = A h, Q = B h,

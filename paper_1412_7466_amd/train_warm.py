@@ -1,7 +1,7 @@
 """Train the learned warm start on solves the library itself generates, then
 measure it on held-out geometries.
 
-    python -m paper_1412_7466_amd.train_warm --out gpurun_out/warm_start.npz
+    python -m paper_1412_7466_amd.train_warm --out warm_start.npz
 
 1. Training set: geometries inputs.warm_problem(i) (the M=1000 workload's rules
    with M uniform in [M_lo, M_hi], (omega, phi) from a small grid sharing one
@@ -44,7 +44,7 @@ def main(argv=None):
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--p-out", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--out", default="gpurun_out/warm_start.npz")
+    ap.add_argument("--out", default="warm_start.npz")
     a = ap.parse_args(argv)
 
     import torch
