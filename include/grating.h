@@ -123,9 +123,10 @@ typedef struct {
   int Nrb;
   int m2l_chunks;   /* source chunks of the translation launch (one partial
                        result of n_beta entries each)                         */
-  int m2l_split;    /* 1, or 2: the FP64 translation with the generator on the
-                       fly runs as two launches, each forming half of the
-                       2P+1 outputs (and recomputing the generator)           */
+  int m2l_split;    /* variant of the FP64 translation: on the fly, 1 launch or
+                       2 (each forming half of the 2P+1 outputs, recomputing
+                       the generator); with the resident table, 1 or 2 lanes
+                       per target                                             */
   int cx_chunks;    /* source chunks of the C x launch                       */
   int bx_chunks;    /* node chunks of the B_phys w (P2L) launch              */
 } grt_sizes;
@@ -176,9 +177,10 @@ grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision
 grt_status grt_set_table(grt_ctx* ctx, int mode);
 /* Launch-shape autotuner: times the translation launch, with the pass that adds
  * its per-chunk partial results, for source chunk counts giving 256 .. 16384
- * wavefronts, in the current mode (on the fly or resident
- * table; on the fly also split over two launches, each forming half of the
- * outputs with half the accumulators per lane), then the C x and B_phys w launches
+ * wavefronts, in the current mode (on the fly or resident table) and in its two
+ * variants (on the fly: one launch, or two each forming half of the outputs with
+ * half the accumulators per lane; table: one or two lanes per target, the latter
+ * as grt_set_table(ctx, 2)), then the C x and B_phys w launches
  * (each with the pass that adds its per-chunk partial results) for 1 .. 64 sources
  * per wave, and keeps the fastest of each for every later apply of this context
  * (results change only by the order of the chunk sums; grt_query reports the
@@ -190,10 +192,11 @@ grt_status grt_autotune(grt_ctx* ctx, int cap, int* n, int* chunks, int* splits,
 
 /* Set the translation's launch shape by hand (what grt_autotune would choose):
  * about m2l_chunks source chunks (1 .. the number grt_autotune may try, at most M;
- * the chunk length is rounded up, so grt_query may report fewer) and m2l_split 1
- * or 2 (2: the on-the-fly FP64 translation as two launches, each forming half of
- * the outputs; ignored with the resident table and in mixed precision).  Results
- * change only by the order of the chunk sums.  GRT_EINVAL outside those ranges. */
+ * the chunk length is rounded up, so grt_query may report fewer) and the variant
+ * m2l_split of the current mode, 1 or 2 (on the fly: 2 = two launches, each forming
+ * half of the outputs; resident table: 2 = two lanes per target; mixed precision
+ * ignores it).  Results change only by the order of the chunk sums.  GRT_EINVAL
+ * outside those ranges. */
 grt_status grt_set_launch(grt_ctx* ctx, int m2l_chunks, int m2l_split);
 
 /* on = 1: the FP64 apply runs C x, A^+ and B_phys w (bound by FP64 arithmetic) on a

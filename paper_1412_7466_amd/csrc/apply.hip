@@ -567,11 +567,13 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* s
   const bool prof = c->prof;
   c->prof = false;
   GRT_HIP(c, hipMemsetAsync(c->d_xtmp, 0, sizeof(cd) * (size_t)c->n_beta, s));
-  int best_chunk = c->m2l_chunk, best_n = c->m2l_nchunks, best_split = c->m2l_split, count = 0;
+  // the variant: on the fly, one launch or two half-output launches (m2l_split);
+  // with the resident table, one or two lanes per target (table_lanes)
+  const bool table = c->d_table != nullptr;
+  int best_chunk = c->m2l_chunk, best_n = c->m2l_nchunks,
+      best_split = table ? c->table_lanes : c->m2l_split, count = 0;
   double best_ms = 1e300;
-  // the split into two launches applies to the FP64 generator on the fly only
-  const int max_split = c->d_table ? 1 : 2;
-  for (int split = 1; split <= max_split; ++split) {
+  for (int split = 1; split <= 2; ++split) {
     int last_nc = -1;
     for (int64_t waves = 256; waves <= M2L_TUNE_MAX_WAVES; waves *= 2) {
       int ch, nc;
@@ -580,7 +582,10 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* s
       last_nc = nc;
       c->m2l_chunk = ch;
       c->m2l_nchunks = nc;
-      c->m2l_split = split;
+      if (table)
+        c->table_lanes = split;
+      else
+        c->m2l_split = split;
       // each candidate is timed with the pass that adds its partial results (the
       // combine reads one partial per chunk)
       const int n = (int)c->n_beta;
@@ -617,7 +622,10 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* s
   }
   c->m2l_chunk = best_chunk;
   c->m2l_nchunks = best_n;
-  c->m2l_split = best_split;
+  if (table)
+    c->table_lanes = best_split;
+  else
+    c->m2l_split = best_split;
   c->prof = prof;
   graph_reset(c);
   hipEventDestroy(e0);

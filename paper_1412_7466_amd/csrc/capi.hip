@@ -298,7 +298,7 @@ grt_status grt_query(const grt_ctx* c, grt_sizes* out) {
   out->rank = c->built ? c->rank : 0;
   out->Nrb = c->g.Nrb;
   out->m2l_chunks = c->built ? c->m2l_nchunks : 0;
-  out->m2l_split = c->built ? c->m2l_split : 0;
+  out->m2l_split = !c->built ? 0 : c->d_table ? c->table_lanes : c->m2l_split;
   out->cx_chunks = c->built ? c->c_nchunks : 0;
   out->bx_chunks = c->built ? c->b_nchunks : 0;
   return GRT_OK;
@@ -371,7 +371,10 @@ grt_status grt_set_launch(grt_ctx* c, int m2l_chunks, int m2l_split) {
   const int64_t ch = (c->M + m2l_chunks - 1) / m2l_chunks;
   c->m2l_chunk = (int)ch;
   c->m2l_nchunks = (int)((c->M + ch - 1) / ch);
-  c->m2l_split = m2l_split;
+  if (c->d_table)
+    c->table_lanes = m2l_split;
+  else
+    c->m2l_split = m2l_split;
   graph_reset(c);
   return GRT_OK;
 }

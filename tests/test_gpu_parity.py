@@ -356,7 +356,7 @@ def test_autotune_keeps_parity(torch_cuda, M, P, seed, table):
     assert len(tuned) >= 1
     assert ctx.sizes.cx_chunks >= 1 and ctx.sizes.bx_chunks >= 1
     assert (ctx.sizes.m2l_chunks, ctx.sizes.m2l_split) in [(c, sp) for c, sp, _ in tuned]
-    assert ctx.sizes.m2l_split in ((1,) if table else (1, 2))
+    assert ctx.sizes.m2l_split in (1, 2)
     assert rel(_np(ctx.apply_T(xd)), red.T_apply(xh)) < 1e-12
     assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
 
