@@ -406,19 +406,18 @@ __global__ void __launch_bounds__(BT) seg_update_kernel(const InstDesc* __restri
                                                         const cd* __restrict__ V, size_t ldv,
                                                         cd* w, int nv, const cd* __restrict__ h,
                                                         int hld) {
+  // block (seg, r): entries [seg SEG + r BT, seg SEG + (r+1) BT), one per thread
   if (!D[seg2inst[blockIdx.x]].active) return;
   const cd* hh = h + (size_t)seg2inst[blockIdx.x] * hld;
-  for (int r = 0; r < SEG / BT; ++r) {
-    int64_t i = (int64_t)blockIdx.x * SEG + r * BT + threadIdx.x;
-    cd acc = w[i];
-    for (int v = 0; v < nv; ++v) {
-      cd hv = hh[v];
-      cd a = V[(size_t)v * ldv + i];
-      acc.r -= hv.r * a.r - hv.i * a.i;
-      acc.i -= hv.r * a.i + hv.i * a.r;
-    }
-    w[i] = acc;
+  const int64_t i = (int64_t)blockIdx.x * SEG + blockIdx.y * BT + threadIdx.x;
+  cd acc = w[i];
+  for (int v = 0; v < nv; ++v) {
+    cd hv = hh[v];
+    cd a = V[(size_t)v * ldv + i];
+    acc.r -= hv.r * a.r - hv.i * a.i;
+    acc.i -= hv.r * a.i + hv.i * a.r;
   }
+  w[i] = acc;
 }
 
 // Per problem: rotations of column j of its Hessenberg matrix (as in the single
@@ -481,15 +480,14 @@ __global__ void __launch_bounds__(BT) seg_axpy_basis_kernel(const int* __restric
                                                             cd* x, const cd* __restrict__ V,
                                                             size_t ldv, const cd* __restrict__ y,
                                                             int yld, const int* __restrict__ kk) {
+  // block (seg, r): entries [seg SEG + r BT, seg SEG + (r+1) BT), one per thread
   const int i0 = seg2inst[blockIdx.x];
   const int k = kk[i0];
   const cd* yy = y + (size_t)i0 * yld;
-  for (int r = 0; r < SEG / BT; ++r) {
-    int64_t i = (int64_t)blockIdx.x * SEG + r * BT + threadIdx.x;
-    cd acc = x[i];
-    for (int v = 0; v < k; ++v) cmac(acc, yy[v], V[(size_t)v * ldv + i]);
-    x[i] = acc;
-  }
+  const int64_t i = (int64_t)blockIdx.x * SEG + blockIdx.y * BT + threadIdx.x;
+  cd acc = x[i];
+  for (int v = 0; v < k; ++v) cmac(acc, yy[v], V[(size_t)v * ldv + i]);
+  x[i] = acc;
 }
 
 // D[i].active = flags[i]
@@ -843,7 +841,8 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
         inst_dots_kernel<<<(B * (j + 1) + 255) / 256, 256, 0, s>>>(b->dd, B, j + 1, b->nseg,
                                                                   b->dpart, b->h, ld, b->H, ld, j,
                                                                   pass);
-        seg_update_kernel<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, V, ldv, w, j + 1, b->h, ld);
+        seg_update_kernel<<<dim3(b->nseg, SEG / BT), BT, 0, s>>>(b->dd, b->d_seg2inst, V, ldv, w,
+                                                                 j + 1, b->h, ld);
       }
       BTRY(batch_norms(b, w, b->nrm));
       inst_givens_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->nrm, b->H, ld, b->cs, b->sn, b->g, j,
@@ -875,7 +874,8 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
     total += steps;
     BHIP(b, hipMemcpyAsync(b->d_k, kk.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
     inst_backsolve_kernel<<<(B + 63) / 64, 64, 0, s>>>(B, b->H, ld, b->g, b->d_k, b->y);
-    seg_axpy_basis_kernel<<<b->nseg, BT, 0, s>>>(b->d_seg2inst, X, V, ldv, b->y, ld, b->d_k);
+    seg_axpy_basis_kernel<<<dim3(b->nseg, SEG / BT), BT, 0, s>>>(b->d_seg2inst, X, V, ldv, b->y,
+                                                                 ld, b->d_k);
     BHIP(b, hipGetLastError());
     for (int i = 0; i < B; ++i) {
       r.iters[i] += kk[i];
