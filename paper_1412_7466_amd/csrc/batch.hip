@@ -224,6 +224,29 @@ __global__ void __launch_bounds__(256) l2l_batched(const InstDesc* __restrict__ 
   l2l_block(q.M, q.P, q.Q2, q.l2l, q.wvec + q.g.col_off[CB_A2], q.pL, w.x, w.y);
 }
 
+// sum_{c < n} part[c stride + i] as four interleaved partial sums (c mod 4), so that
+// four loads are in flight; fixed order
+template <typename TT>
+__device__ __forceinline__ cd chunks_sum(const TT* __restrict__ part, int n, size_t stride,
+                                         int64_t i) {
+  cd s[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  int c = 0;
+  for (; c + 3 < n; c += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const TT v = part[(size_t)(c + u) * stride + i];
+      s[u].r += v.r;
+      s[u].i += v.i;
+    }
+  }
+  for (; c < n; ++c) {
+    const TT v = part[(size_t)c * stride + i];
+    s[0].r += v.r;
+    s[0].i += v.i;
+  }
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 // Y = D o (x - s o (T x - B x)) with x = X (already un-normalised) for mode 0, or
 // Y = D o (s o B f) for the right-hand side (mode 1).  Padding entries get 0.
 __global__ void __launch_bounds__(BT) combine_batched(const InstDesc* __restrict__ D,
@@ -240,12 +263,10 @@ __global__ void __launch_bounds__(BT) combine_batched(const InstDesc* __restrict
       Y[i] = cd{0.0, 0.0};
       continue;
     }
-    cd b = q.pL[loc];
-    for (int c = 0; c < q.b_nchunks; ++c) b += q.pB[(size_t)c * q.nbeta + loc];
+    const cd b = q.pL[loc] + chunks_sum(q.pB, q.b_nchunks, q.nbeta, loc);
     cd y;
     if (mode == 0) {
-      cd t{0, 0};
-      for (int c = 0; c < q.m2l_nchunks; ++c) t += q.pT[(size_t)c * q.nbeta + loc];
+      const cd t = chunks_sum(q.pT, q.m2l_nchunks, q.nbeta, loc);
       y = X[i] - q.mie[loc] * (t - b);
     } else {
       y = q.mie[loc] * b;
@@ -269,14 +290,8 @@ __global__ void __launch_bounds__(BT) combine_mixed_batched(const InstDesc* __re
       Y[i] = cd{0.0, 0.0};
       continue;
     }
-    cd b = q.pL[loc];
-    for (int c = 0; c < q.b_nchunks; ++c) b += q.pB[(size_t)c * q.nbeta + loc];
-    cd t = q.pN[loc];
-    for (int c = 0; c < q.m2l_nchunks; ++c) {
-      const cf v = q.pT32[(size_t)c * q.nbeta + loc];
-      t.r += v.r;
-      t.i += v.i;
-    }
+    const cd b = q.pL[loc] + chunks_sum(q.pB, q.b_nchunks, q.nbeta, loc);
+    const cd t = q.pN[loc] + chunks_sum(q.pT32, q.m2l_nchunks, q.nbeta, loc);
     Y[i] = dn[i] * (X[i] - q.mie[loc] * (t - b));
   }
 }
