@@ -64,9 +64,12 @@ __global__ void __launch_bounds__(KT) dots_kernel(const cd* __restrict__ V, size
 // h[v] = sum_b partial[v][b] (fixed order), then w[i] -= sum_v h[v] V_v[i].
 // Every block redoes the small reduction; block 0 also stores h into the
 // Hessenberg column (pass 0) or adds it (pass 1: the re-orthogonalisation).
+// With npart given, block b also stores npart[b] = sum of |w_new[i]|^2 over its
+// entries, the partial sums of the new direction's norm.
 __global__ void __launch_bounds__(KT) update_kernel(const cd* __restrict__ V, size_t ldv, cd* w,
                                                      int n, const cd* __restrict__ partial,
-                                                     int nblk, int nvec, cd* hcol, int pass) {
+                                                     int nblk, int nvec, cd* hcol, int pass,
+                                                     double* npart) {
   __shared__ cd h[1024];
   for (int v = threadIdx.x; v < nvec; v += KT) {
     const cd s = sum_partials(partial + (size_t)v * nblk, 1, nblk);
@@ -75,15 +78,42 @@ __global__ void __launch_bounds__(KT) update_kernel(const cd* __restrict__ V, si
   }
   __syncthreads();
   int i = blockIdx.x * KT + threadIdx.x;
-  if (i >= n) return;
-  cd acc = w[i];
-  for (int v = 0; v < nvec; ++v) {
-    cd hv = h[v];
-    cd a = V[(size_t)v * ldv + i];
-    acc.r -= hv.r * a.r - hv.i * a.i;
-    acc.i -= hv.r * a.i + hv.i * a.r;
+  double s2 = 0.0;
+  if (i < n) {
+    cd acc = w[i];
+    for (int v = 0; v < nvec; ++v) {
+      cd hv = h[v];
+      cd a = V[(size_t)v * ldv + i];
+      acc.r -= hv.r * a.r - hv.i * a.i;
+      acc.i -= hv.r * a.i + hv.i * a.r;
+    }
+    w[i] = acc;
+    s2 = cabs2(acc);
   }
-  w[i] = acc;
+  if (!npart) return;  // uniform over the block
+  for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+  __shared__ double r[KT / 64];
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = s2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int t = 0; t < KT / 64; ++t) a += r[t];
+    npart[blockIdx.x] = a;
+  }
+}
+
+// sum_{b < np} p[b] in a fixed order (strided per thread, butterfly over the wave,
+// waves in order); every thread of every block gets the same value.
+__device__ __forceinline__ double block_sum(const double* p, int np) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < np; b += KT) s += p[b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  __shared__ double r[KT / 64];
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double a = 0.0;
+  for (int t = 0; t < KT / 64; ++t) a += r[t];
+  return a;
 }
 
 // sum |w|^2 partials
@@ -131,13 +161,13 @@ __global__ void axpy_basis_kernel(cd* x, const cd* __restrict__ V, size_t ldv, i
   x[i] = acc;
 }
 
-// vout = w / ||w|| with ||w|| from the norm partials (every block redoes the short
-// sum in the same order); block 0 also stores it as H[j+1][j].  xpre = dinv o vout
-// (the unnormalised input of the next apply).
+// vout = w / ||w|| with ||w|| from the np norm partials (every block redoes the
+// short sum in the same order); block 0 also stores it as H[j+1][j].  xpre = dinv o
+// vout (the unnormalised input of the next apply).
 __global__ void __launch_bounds__(KT) norm_scale_kernel(const cd* w, cd* vout, int n,
-                                                         const double* npart, int nblk, cd* hsub,
+                                                         const double* npart, int np, cd* hsub,
                                                          const double* dinv, cd* xpre) {
-  const double hn = sqrt(sum_partials(npart, 1, nblk));
+  const double hn = sqrt(block_sum(npart, np));
   if (blockIdx.x == 0 && threadIdx.x == 0) *hsub = cd{hn, 0.0};
   int i = blockIdx.x * KT + threadIdx.x;
   if (i >= n) return;
@@ -168,7 +198,10 @@ static grt_status ensure_workspace(grt_ctx* c, int m) {
   c->d_wtmp = c->d_V + n * (m + 4);
   GRT_HIP(c, hipMalloc(&c->d_H, sizeof(cd) * (size_t)(m + 1) * (m + 1)));
   GRT_HIP(c, hipMalloc(&c->d_y, sizeof(cd) * (m + 1)));
-  GRT_HIP(c, hipMalloc(&c->d_scal, sizeof(double) * (16 + c->n_dot_blocks)));
+  // scalars, then the norm partials: n_dot_blocks of them from norm2_kernel, or one
+  // per KT entries from the update pass
+  GRT_HIP(c, hipMalloc(&c->d_scal, sizeof(double) * (16 + std::max<size_t>(c->n_dot_blocks,
+                                                                           (n + KT - 1) / KT))));
   if (!c->ev_res[0]) {
     GRT_HIP(c, hipEventCreateWithFlags(&c->ev_res[0], hipEventDisableTiming));
     GRT_HIP(c, hipEventCreateWithFlags(&c->ev_res[1], hipEventDisableTiming));
@@ -349,10 +382,11 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
       for (int pass = 0; pass < 2; ++pass) {
         dim3 gd(nblk, j + 1);
         dots_kernel<<<gd, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, nblk);
-        update_kernel<<<gridn, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, nblk, j + 1, hcol, pass);
+        // the second pass also leaves the partial sums of |w|^2
+        update_kernel<<<gridn, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, nblk, j + 1, hcol, pass,
+                                           pass ? d_npart : nullptr);
       }
-      norm2_kernel<<<nblk, KT, 0, s>>>(w, n, d_npart, nblk);
-      norm_scale_kernel<<<gridn, KT, 0, s>>>(w, V + (size_t)(j + 1) * ldv, n, d_npart, nblk,
+      norm_scale_kernel<<<gridn, KT, 0, s>>>(w, V + (size_t)(j + 1) * ldv, n, d_npart, gridn,
                                              hcol + j + 1, c->d_dinv, c->d_xtmp);
       GRT_HIP(c, hipGetLastError());
       GRT_HIP(c, hipMemcpyAsync(hH + (size_t)j * ldh, hcol, sizeof(cd) * (j + 2),
