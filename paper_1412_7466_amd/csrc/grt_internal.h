@@ -127,6 +127,7 @@ struct grt_ctx {
   hipEvent_t ev_res[2] = {nullptr, nullptr};
   double* h_pinned = nullptr;
   cd* h_H = nullptr;        // pinned host mirror of H and the least-squares solution
+  cd* h_H_dev = nullptr;    // the same memory's device address (kernels write H columns)
   cd* d_wtmp = nullptr;     // output of every apply in the solver (a slot of d_V)
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // captured applies: K, mixed K
   // kernel timing (HIP events around every translation-kernel launch)

@@ -162,13 +162,21 @@ __global__ void axpy_basis_kernel(cd* x, const cd* __restrict__ V, size_t ldv, i
 }
 
 // vout = w / ||w|| with ||w|| from the np norm partials (every block redoes the
-// short sum in the same order); block 0 also stores it as H[j+1][j].  xpre = dinv o
+// short sum in the same order); block 0 also stores it as H[j+1][j] = hcol[j+1] and
+// copies the finished column hcol[0..j+1] to the host mirror hhost.  xpre = dinv o
 // vout (the unnormalised input of the next apply).
 __global__ void __launch_bounds__(KT) norm_scale_kernel(const cd* w, cd* vout, int n,
-                                                         const double* npart, int np, cd* hsub,
-                                                         const double* dinv, cd* xpre) {
+                                                         const double* npart, int np, cd* hcol,
+                                                         int j, cd* hhost, const double* dinv,
+                                                         cd* xpre) {
   const double hn = sqrt(block_sum(npart, np));
-  if (blockIdx.x == 0 && threadIdx.x == 0) *hsub = cd{hn, 0.0};
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t <= j; t += KT) hhost[t] = hcol[t];
+    if (threadIdx.x == 0) {
+      hcol[j + 1] = cd{hn, 0.0};
+      hhost[j + 1] = cd{hn, 0.0};
+    }
+  }
   int i = blockIdx.x * KT + threadIdx.x;
   if (i >= n) return;
   const cd v = hn > 0 ? (1.0 / hn) * w[i] : w[i];
@@ -210,8 +218,13 @@ static grt_status ensure_workspace(grt_ctx* c, int m) {
   if (!c->h_pinned) GRT_HIP(c, hipHostMalloc(&c->h_pinned, sizeof(double) * 16));
   if (c->h_H) hipHostFree(c->h_H);
   c->h_H = nullptr;
+  c->h_H_dev = nullptr;
   // host mirror of the Hessenberg columns, then y: (m+1)^2 + (m+1) complex
-  GRT_HIP(c, hipHostMalloc(&c->h_H, sizeof(cd) * ((size_t)(m + 1) * (m + 1) + (m + 1))));
+  // (coherent, so that the columns the normalisation kernel writes there are read by
+  // the host once the step's event has completed)
+  GRT_HIP(c, hipHostMalloc(&c->h_H, sizeof(cd) * ((size_t)(m + 1) * (m + 1) + (m + 1)),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+  GRT_HIP(c, hipHostGetDevicePointer((void**)&c->h_H_dev, c->h_H, 0));
   c->krylov_restart = m;
   return GRT_OK;
 }
@@ -386,11 +399,11 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
         update_kernel<<<gridn, KT, 0, s>>>(V, ldv, w, n, c->d_dotpart, nblk, j + 1, hcol, pass,
                                            pass ? d_npart : nullptr);
       }
+      // the normalisation also puts column j of H (j+2 numbers) into the host mirror
       norm_scale_kernel<<<gridn, KT, 0, s>>>(w, V + (size_t)(j + 1) * ldv, n, d_npart, gridn,
-                                             hcol + j + 1, c->d_dinv, c->d_xtmp);
+                                             hcol, j, c->h_H_dev + (size_t)j * ldh, c->d_dinv,
+                                             c->d_xtmp);
       GRT_HIP(c, hipGetLastError());
-      GRT_HIP(c, hipMemcpyAsync(hH + (size_t)j * ldh, hcol, sizeof(cd) * (j + 2),
-                                hipMemcpyDeviceToHost, s));
       GRT_HIP(c, hipEventRecord(c->ev_res[j & 1], s));
       ++queued;
       if (j >= 1) {
