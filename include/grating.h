@@ -236,6 +236,27 @@ grt_status grt_solve(grt_ctx* ctx, const grt_solve_opts* opts, void* beta_dev,
 grt_status grt_bragg(grt_ctx* ctx, const void* beta_dev, int64_t cap, int* orders, double* c,
                      double* d, double* R, double* T, double* flux_err);
 
+/* The total field at n_pts points (host xy[2 i], xy[2 i + 1]) for the solution beta
+ * (device, [M][2P+1]; ignored when M = 0), written to host u[2 i], u[2 i + 1] (re, im).
+ * The representation of sec. 3 (eqs. repre1-repre3) and sec. 5 (eq. repre3_mod): in
+ * each truncated layer the three near copies of the interface layer potentials (the
+ * trapezoid sums over the nodes the method solves with), the layer's J expansion,
+ * and in the middle layer the outgoing multipoles of every disk and of its copies
+ * l = -1, 0, 1; above y0 and below -y0 the Rayleigh-Bloch expansions with c_n, d_n
+ * (eqs. rad1, rad2); the incident plane wave in the top layer (y > h); inside a disk
+ * or one of its near copies the interior expansion sum_n gamma_n J_n(k_p r) e^{in theta}
+ * (sec. 4.1) with gamma_n from continuity with the field arriving at the disk.  The
+ * representation is evaluated in the unit cell |x| <= d/2 and carried to other x by
+ * quasi-periodicity, u(x + l d) = alpha^l u(x) (sec. 2).  A point with |y| = h
+ * exactly belongs to the middle layer.  The node sums lose
+ * accuracy within a few node spacings (d/N) of an interface and are not the field on
+ * it.  Allocates device scratch (O(n_alpha rank + M (2P+1) + n_pts)) and synchronises
+ * the context stream.  GRT_EINVAL for null arrays or coordinates that are not finite
+ * or exceed 1e6 in size,
+ * GRT_ESTATE before grt_build. */
+grt_status grt_eval_field(grt_ctx* ctx, const void* beta_dev, int64_t n_pts, const double* xy,
+                          double* u);
+
 /* Copy the equilibrated matrix A (column-major [n_alpha][n_rows] complex) and its
  * column scales to host buffers (diagnostics / tests). */
 grt_status grt_get_A(grt_ctx* ctx, double* A_host, double* colscale_host);
@@ -265,7 +286,9 @@ typedef struct grt_batch grt_batch;
  * of table mode on one of them grt_batch_solve returns GRT_ESTATE (make a new
  * batch).  hip_stream: stream to run on, or NULL for a private one.
  * GRT_ESTATE if a context is not built, has no inclusions or is on another
- * device; GRT_EINVAL for n <= 0 or NULL arrays. */
+ * device; GRT_EINVAL for n <= 0, NULL arrays or a context listed twice (every
+ * instance writes its own context's scratch buffers during a lockstep step, so the
+ * contexts of one batch must be distinct). */
 grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, void* hip_stream);
 grt_status grt_batch_destroy(grt_batch* batch);
 const char* grt_batch_error_message(const grt_batch* batch);

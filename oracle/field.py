@@ -166,12 +166,29 @@ def _inclusions(G, beta, tx, ty, skip=None):
     return u, ux, uy
 
 
+def interior_coefficients(red, beta):
+    """gamma_m[n] of the field inside disk m, sum_n gamma_n J_n(k_p r) e^{in theta}
+    (sec. 4.1): continuity at r = R with the exterior sum_n (a_n J_n(k2 r) + beta_n
+    H_n(k2 r)) e^{in theta}, where a = T beta + B_phys A^+ (f - C beta) is the field
+    arriving at the disk (sec. 5)."""
+    G = red.G
+    P = G.P
+    n = np.arange(-P, P + 1)[None, :]
+    a = red.T_apply(beta) - red.lowrank_apply(beta) + red.B @ red.pinv.apply(red.f)
+    a = a.reshape(G.M, 2 * P + 1)
+    b = np.asarray(beta).reshape(G.M, 2 * P + 1)
+    R = G.rad[:, None]
+    ext = a * sp.jv(n, G.k2 * R) + b * sp.hankel1(n, G.k2 * R)
+    return ext / sp.jv(n, G.kp[:, None] * R)
+
+
 class Field:
     """Field of one solved problem: beta (inclusions) and alpha = A^+ (f - C beta)."""
 
     def __init__(self, red, beta, n_fine=16384):
         G = self.G = red.G
         self.beta = np.zeros(0) if G.M == 0 else np.asarray(beta)
+        self.gamma = interior_coefficients(red, self.beta) if G.M else None
         al = red.alpha_vec(self.beta)
         c = G.col
         self.mu1, self.sig1 = al[c["mu1"]], al[c["sig1"]]
@@ -217,11 +234,50 @@ class Field:
         E = np.exp(1j * (G.kapn[None, :] * tx + kn[None, :] * yy))
         return E @ coef, (1j * G.kapn[None, :] * E) @ coef, (1j * kn[None, :] * E) @ coef
 
-    def total(self, tx, ty):
-        """Total field (value only) at points of any layer, outside the inclusions."""
+    def inside(self, tx, ty):
+        """(inside, value): which points lie in a disk or one of its near copies
+        (x_m + l d, l = -1, 0, 1), and the interior field there (the copy's field is
+        alpha^l times the disk's, by quasi-periodicity)."""
         G = self.G
         tx = np.atleast_1d(np.asarray(tx, float))
         ty = np.atleast_1d(np.asarray(ty, float))
+        ins = np.zeros(len(tx), bool)
+        val = np.zeros(len(tx), complex)
+        n = np.arange(-G.P, G.P + 1)[None, :]
+        for m in range(G.M):
+            for l in (-1, 0, 1):
+                vx = tx - G.cx[m] - l * G.d
+                vy = ty - G.cy[m]
+                sel = (np.hypot(vx, vy) < G.rad[m]) & ~ins
+                if np.any(sel):
+                    J = incoming(n, G.kp[m], vx[sel][:, None], vy[sel][:, None])
+                    val[sel] = G.alpha ** l * (J @ self.gamma[m])
+                    ins |= sel
+        return ins, val
+
+    def total(self, tx, ty):
+        """Total field (value only) at points of any layer, inclusions included.  The
+        representation holds in the unit cell |x| <= d/2; elsewhere the field follows
+        from quasi-periodicity, u(x + l d) = alpha^l u(x) (sec. 2, eq. bound2)."""
+        G = self.G
+        tx = np.atleast_1d(np.asarray(tx, float))
+        ty = np.atleast_1d(np.asarray(ty, float))
+        cell = np.floor(tx / G.d + 0.5)
+        if np.any(cell != 0):
+            return G.alpha ** cell * self.total(tx - cell * G.d, ty)
+        out = np.zeros(len(tx), complex)
+        if G.M:
+            ins, val = self.inside(tx, ty)
+            out[ins] = val[ins]
+            if np.all(ins):
+                return out
+            rest = ~ins
+            out[rest] = self._outside(tx[rest], ty[rest])
+            return out
+        return self._outside(tx, ty)
+
+    def _outside(self, tx, ty):
+        G = self.G
         out = np.zeros(len(tx), complex)
         for sel, fn in ((ty > G.y0, lambda x, y: self.rayleigh(True, x, y)[0]
                          + G.u_inc(x, y)),

@@ -97,22 +97,26 @@ def dense_T(G):
 
 
 class TranslationTable:
-    """Matrix-free application of T from a stored generator table (large M)."""
+    """Matrix-free application of T from a stored generator table (large M).
 
-    def __init__(self, G, chunk=64):
+    rows: the target inclusions whose rows of T are kept (default all); apply then
+    returns alpha^T for those targets only."""
+
+    def __init__(self, G, chunk=64, rows=None):
         self.G = G
         M = G.M
-        self.tau = np.empty((M, M, 4 * G.P + 1), complex)
-        for a in range(0, M, chunk):
-            js = np.arange(a, min(M, a + chunk))
-            self.tau[js] = generator(G, js)
+        self.rows = np.arange(M) if rows is None else np.asarray(rows)
+        self.tau = np.empty((len(self.rows), M, 4 * G.P + 1), complex)
+        for a in range(0, len(self.rows), chunk):
+            js = self.rows[a:a + chunk]
+            self.tau[a:a + len(js)] = generator(G, js)
 
     def apply(self, beta):
         """alpha^T[j, n] = sum_m sum_q tau[j, m, q] beta[m, n + q]."""
         G = self.G
         P = G.P
         b = np.asarray(beta).reshape(G.M, 2 * P + 1)
-        out = np.zeros_like(b)
+        out = np.zeros((len(self.rows), 2 * P + 1), complex)
         for qi in range(4 * P + 1):
             q = qi - 2 * P
             n_lo = max(-P, -P - q)

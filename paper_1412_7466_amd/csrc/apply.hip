@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "dev_bessel.h"
 #include "grt_internal.h"
@@ -737,6 +738,23 @@ grt_status incident_alpha(grt_ctx* c, cd* out) {
 __global__ void sub_kernel(int n, const cd* a, const cd* b, cd* o) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = a[i] - (b ? b[i] : cd{0, 0});
+}
+
+// Every entry of alpha = A^+ (f - C beta): t = W1 g, alpha = (E V) t with E V built
+// into W for all n_alpha entries.
+grt_status alpha_full(grt_ctx* c, const cd* beta, cd* out, cd* W) {
+  hipStream_t s = c->stream;
+  if (c->M > 0) {
+    grt_status st = cx_apply(c, beta);
+    if (st != GRT_OK) return st;
+  }
+  sub_kernel<<<(c->n_g + 255) / 256, 256, 0, s>>>(c->n_g, c->d_f, c->M > 0 ? c->d_gvec : nullptr,
+                                                   c->d_gvec);
+  launch_gemv_rows(s, c->d_W1, c->d_gvec, c->d_tvec, c->rank, c->n_g);
+  launch_build_Wv(s, c, 0, c->g.n_alpha, W);
+  launch_gemv_rows(s, W, c->d_tvec, out, c->g.n_alpha, c->rank);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
 }
 
 // c and d blocks of alpha = A^+ (f - C beta) into out[0 .. 2 Nrb).

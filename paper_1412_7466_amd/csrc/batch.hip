@@ -918,6 +918,16 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
       return GRT_ESTATE;
     }
   }
+  // every instance writes its context's scratch buffers (partials, coupling
+  // vectors) during a lockstep apply, so one context may appear only once
+  {
+    std::vector<grt_ctx*> sorted(b->ctx);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) {
+      delete b;
+      return GRT_EINVAL;
+    }
+  }
   hipSetDevice(b->device);
   if (hip_stream) {
     b->stream = reinterpret_cast<hipStream_t>(hip_stream);

@@ -150,6 +150,8 @@ grt_status set_err(grt_ctx* c, grt_status s, const std::string& msg);
 // setup (setup.hip)
 grt_status setup_build(grt_ctx* c);
 void launch_gemv_rows(hipStream_t s, const cd* W, const cd* x, cd* y, int rows, int cols);
+// W[i][k] = E[i0 + i] conj(V^H[k][i0 + i]) for i < rows, k < rank: rows of E V
+void launch_build_Wv(hipStream_t s, const grt_ctx* c, int i0, int rows, cd* W);
 
 // apply (apply.hip)
 bool supported_P(int P);
@@ -161,6 +163,9 @@ grt_status apply_lowrank_only(grt_ctx* c, const cd* x, cd* y);
 grt_status rhs_b(grt_ctx* c, cd* b);
 grt_status incident_alpha(grt_ctx* c, cd* out);
 grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out_cd /* device [2 Nrb] */);
+// every entry of alpha = A^+ (f - C beta), unscaled (device [n_alpha]); W: device
+// scratch of n_alpha * rank entries
+grt_status alpha_full(grt_ctx* c, const cd* beta, cd* out, cd* W);
 grt_status apply_alloc(grt_ctx* c);
 grt_status table_set(grt_ctx* c, bool on);
 grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* splits_out,

@@ -540,6 +540,11 @@ __global__ void htab_kernel(double* tab) {
 
 }  // namespace
 
+void launch_build_Wv(hipStream_t s, const grt_ctx* c, int i0, int rows, cd* W) {
+  dim3 g((c->rank + 255) / 256, rows);
+  build_Wv_kernel<<<g, 256, 0, s>>>(c->d_VH, c->g.n_alpha, c->d_colscale, i0, rows, c->rank, W);
+}
+
 void launch_gemv_rows(hipStream_t s, const cd* W, const cd* x, cd* y, int rows, int cols) {
   if (rows <= 0) return;
   int blocks = (rows + 3) / 4;

@@ -85,6 +85,8 @@ _PROTOS = {
     "grt_bragg": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                             C.POINTER(C.c_double)]),
+    "grt_eval_field": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double)]),
     "grt_get_A": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "grt_get_mie": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "grt_profile_enable": (C.c_int, [_VP, C.c_int]),
@@ -334,6 +336,18 @@ class Context:
         self._leave()
         return dict(orders=np.array(orders[:]), c=c[0::2] + 1j * c[1::2], d=d[0::2] + 1j * d[1::2],
                     R=R, T=T, flux_err=flux.value)
+
+    def eval_field(self, beta, xy):
+        """Total field at the points xy ([n, 2] float64, host) for the solution beta
+        (device tensor, or None without inclusions): complex128 numpy array [n]."""
+        import numpy as np
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        out = np.zeros(2 * len(xy))
+        self._enter()
+        self._check(self.lib.grt_eval_field(self.h, self._vec_ptr(beta) if beta is not None
+                                            else None, len(xy), _dptr(xy), _dptr(out)))
+        self._leave()
+        return out[0::2] + 1j * out[1::2]
 
     def get_A(self):
         s = self.sizes

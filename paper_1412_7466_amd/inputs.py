@@ -249,6 +249,13 @@ def m1000(phi=-math.pi / 5, **kw) -> Problem:
                         20.0, phi, 15, **kw)
 
 
+def m1000_p20(phi=-math.pi / 5, **kw) -> Problem:
+    """The M=1000 geometry (seed 2) at multipole order P=20 (41 coefficients per
+    disk, generator orders up to 40)."""
+    return make_problem("m1000_p20", 1.0, 1.0, 1000, 0.004, 0.012, 1.5, 3.0, 0.002, 2,
+                        20.0, phi, 20, **kw)
+
+
 def small(M, P, omega=10.0, seed=7, phi=-math.pi / 5, d=1.0, h=0.5, **kw) -> Problem:
     """Small test geometry with m1000's size and index distributions, scaled."""
     return make_problem(f"small_M{M}_P{P}", d, h, M, 0.02, 0.04, 1.5, 3.0, 0.01, seed,

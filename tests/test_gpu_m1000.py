@@ -1,11 +1,13 @@
-"""Full-size parity: the M=1000, P=15 workload the benchmark times, against the
-CPU FP64 oracle's stored solution (tests/golden/m1000_oracle.npz, written by
+"""Full-size parity: the M=1000 workload the benchmark times (P=15) and the same
+geometry at P=20, against the CPU FP64 oracle's stored results
+(tests/golden/m1000_oracle.npz and m1000_p20_oracle.npz, written by
 tests/golden/make_m1000_oracle.py from oracle/ only).
 
-Same launch configuration as the benchmark (the work split is a function of M
-and the discretization only).  Bars: K applied to a fixed probe vector 1e-9
-relative; beta and the propagating Bragg amplitudes 1e-9 relative; flux error
-below 1e-9.
+Same launch configuration as the benchmark (the work split is a function of M and
+the discretization only).  Every comparison is per order in the normalised basis
+(tests/parity.py): T applied to the stored probe x = D^-1 u to 1e-12 of each order's
+size, K to 1e-9; beta to 1e-9 per order plus 1e-10 of the largest order; each
+propagating Bragg amplitude to 1e-9; flux error below 1e-9.
 """
 import os
 import sys
@@ -14,10 +16,11 @@ import numpy as np
 import pytest
 
 from paper_1412_7466_amd import inputs
+from parity import check_amplitudes, check_orders
 
 pytestmark = pytest.mark.gpu
 
-GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "m1000_oracle.npz")
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def say(*a):
@@ -25,77 +28,97 @@ def say(*a):
     sys.stdout.flush()
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
-
-
-@pytest.fixture(scope="module")
-def m1000():
+def _load(case):
     import torch
     if not torch.cuda.is_available():
         pytest.fail("no GPU visible")
     from paper_1412_7466_amd.grating import Context
-    gold = np.load(GOLD)
-    pb = inputs.m1000()
+    gold = np.load(os.path.join(GOLD, f"{case}_oracle.npz"))
+    pb = getattr(inputs, case)()
     assert str(gold["digest"]) == pb.digest(), "inputs changed: regenerate the golden file"
-    say(f"[gpu] m1000 build M={pb.M} P={pb.P} N={pb.disc.N}")
+    say(f"[gpu] {case} build M={pb.M} P={pb.P} N={pb.disc.N}")
     ctx = Context(0)
     ctx.set_problem(pb)
     ctx.build()
-    return torch, ctx, gold
+    return torch, ctx, gold, pb
 
 
-def test_m1000_apply(m1000):
-    torch, ctx, gold = m1000
+@pytest.fixture(scope="module")
+def m1000():
+    torch, ctx, gold, pb = _load("m1000")
+    yield torch, ctx, gold, pb
+    ctx.close()
+
+
+def _check_apply(torch, ctx, gold, pb, tag):
     x = torch.tensor(gold["probe"], dtype=torch.complex128, device="cuda:0")
+    D = gold["D"]
+    yT = ctx.apply_T(x).cpu().numpy()
+    check_orders(yT, gold["T_probe"], D, pb.P, 1e-12, tag=f"{tag} T probe")
     y = ctx.apply(x).cpu().numpy()
-    e = rel(y, gold["K_probe"])
-    say(f"[gpu] m1000 K probe rel err {e:.2e}")
-    assert e < 1e-9
+    check_orders(y, gold["K_probe"], D, pb.P, 1e-9, tag=f"{tag} K probe")
 
 
-def _check_solution(ctx, beta, gold, tag):
-    b = beta.cpu().numpy()
-    e = rel(b, gold["beta"])
+def _check_solution(ctx, beta, gold, pb, tag):
+    check_orders(beta.cpu().numpy(), gold["beta"], gold["D"], pb.P, 1e-9, 1e-10,
+                 tag=f"{tag} beta")
     og = ctx.bragg(beta)
     p1, p3 = gold["prop1"], gold["prop3"]
     vg = np.concatenate([og["c"][p1], og["d"][p3]])
     vo = np.concatenate([gold["c"][p1], gold["d"][p3]])
-    eb = rel(vg, vo)
-    say(f"[gpu] m1000 {tag}: beta rel err {e:.2e}  Bragg rel err {eb:.2e}  "
-        f"flux {og['flux_err']:.2e}")
-    assert e < 1e-9
-    assert eb < 1e-9
+    check_amplitudes(vg, vo, 1e-9, tag=f"{tag} Bragg")
+    say(f"[gpu] {tag}: flux {og['flux_err']:.2e}")
     assert og["flux_err"] < 1e-9
 
 
+def test_m1000_apply(m1000):
+    torch, ctx, gold, pb = m1000
+    _check_apply(torch, ctx, gold, pb, "m1000")
+
+
 def test_m1000_solve_fp64(m1000):
-    torch, ctx, gold = m1000
+    torch, ctx, gold, pb = m1000
     beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000)
     say(f"[gpu] m1000 FP64 iters={st.iters} resid={st.rel_resid:.2e} {st.seconds:.3f}s")
-    _check_solution(ctx, beta, gold, "FP64")
+    _check_solution(ctx, beta, gold, pb, "m1000 FP64")
 
 
 def test_m1000_solve_mixed(m1000):
     from paper_1412_7466_amd.grating import GRT_FP32
-    torch, ctx, gold = m1000
+    torch, ctx, gold, pb = m1000
     beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000, precision=GRT_FP32)
     say(f"[gpu] m1000 mixed iters={st.iters} refine={st.refine_steps} "
         f"resid={st.rel_resid:.2e} {st.seconds:.3f}s")
-    _check_solution(ctx, beta, gold, "mixed")
+    _check_solution(ctx, beta, gold, pb, "m1000 mixed")
 
 
 def test_m1000_resident_table(m1000):
     """Same bars with the resident translation table (1 GB at this size)."""
-    torch, ctx, gold = m1000
+    torch, ctx, gold, pb = m1000
     ctx.set_table(True)
     try:
-        x = torch.tensor(gold["probe"], dtype=torch.complex128, device="cuda:0")
-        e = rel(ctx.apply(x).cpu().numpy(), gold["K_probe"])
-        say(f"[gpu] m1000 table: K probe rel err {e:.2e}")
-        assert e < 1e-9
+        _check_apply(torch, ctx, gold, pb, "m1000 table")
         beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000)
         say(f"[gpu] m1000 table FP64 iters={st.iters} resid={st.rel_resid:.2e} {st.seconds:.3f}s")
-        _check_solution(ctx, beta, gold, "FP64 table")
+        _check_solution(ctx, beta, gold, pb, "m1000 FP64 table")
     finally:
         ctx.set_table(False)
+
+
+def test_m1000_p20():
+    """P=20 at M=1000: generator orders up to 40, the one-lane kernels' accumulators
+    no longer fit in registers (split on-the-fly launch, two-lane table kernel)."""
+    if not os.path.exists(os.path.join(GOLD, "m1000_p20_oracle.npz")):
+        pytest.skip("tests/golden/m1000_p20_oracle.npz not generated")
+    torch, ctx, gold, pb = _load("m1000_p20")
+    try:
+        _check_apply(torch, ctx, gold, pb, "m1000_p20")
+        ctx.set_launch(16, 2)
+        _check_apply(torch, ctx, gold, pb, "m1000_p20 split")
+        beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000)
+        say(f"[gpu] m1000_p20 FP64 iters={st.iters} resid={st.rel_resid:.2e} {st.seconds:.3f}s")
+        _check_solution(ctx, beta, gold, pb, "m1000_p20 FP64")
+        ctx.set_table(2)
+        _check_apply(torch, ctx, gold, pb, "m1000_p20 table 2 lanes")
+    finally:
+        ctx.close()

@@ -1,8 +1,12 @@
 """Parity of the HIP library (through the C ABI) with the CPU FP64 oracle.
 
-Tolerance: 1e-9 relative on coefficient vectors and Bragg amplitudes (the bar of
-the method's FP64 path); pieces computed without the pseudo-inverse (Mie
-diagonal, matrix A, translation T) are held to 1e-12.
+Every coefficient vector is compared order by order in the basis normalised by
+D = |H_|n|(k2 r)| (tests/parity.py): probes are x = D^-1 u with u of unit size in
+every order, and each order of the output is held to its own size.  Bars: 1e-12 for
+pieces computed without the pseudo-inverse (Mie diagonal, matrix A, translation T);
+1e-9 for K, the low-rank term, the right-hand side, solutions (plus 1e-10 of the
+largest order, the accuracy a 1e-12 residual fixes) and each propagating Bragg
+amplitude.
 """
 import math
 import sys
@@ -11,6 +15,7 @@ import numpy as np
 import pytest
 
 from paper_1412_7466_amd import inputs
+from parity import check_amplitudes, check_orders, dscale, probe
 
 pytestmark = pytest.mark.gpu
 
@@ -49,12 +54,15 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _randvec(torch, n, seed, P):
-    rng = np.random.default_rng(seed)
-    nb = 2 * P + 1
-    v = (rng.standard_normal((n // nb, nb)) + 1j * rng.standard_normal((n // nb, nb)))
-    v *= 0.5 ** np.abs(np.arange(-P, P + 1))[None, :]
-    return v.reshape(-1), torch.tensor(v.reshape(-1), dtype=torch.complex128, device="cuda:0")
+def _probe(torch, pb, seed):
+    xh = probe(pb, seed)
+    return xh, torch.tensor(xh, dtype=torch.complex128, device="cuda:0")
+
+
+def _check_bragg(og, oo, tag):
+    vg = np.concatenate([og["c"][oo["prop1"]], og["d"][oo["prop3"]]])
+    vo = np.concatenate([oo["c"][oo["prop1"]], oo["d"][oo["prop3"]]])
+    check_amplitudes(vg, vo, 1e-9, tag=tag)
 
 
 def test_tiny_pieces_and_solve(torch_cuda, tiny_oracle):
@@ -65,36 +73,37 @@ def test_tiny_pieces_and_solve(torch_cuda, tiny_oracle):
     assert ctx.sizes.n_rows == G.n_rows and ctx.sizes.n_alpha == G.n_alpha
     # Mie diagonal
     s = ctx.get_mie()
-    assert rel(s, red.s) < 1e-13
+    # per order 1e-11: for |n| >> k r the two terms of the numerator of s_n agree to
+    # leading order and cancel (by about 40x at n = 10 here), so the device Bessel
+    # values' ~3e-14 relative error appears magnified in s_10 ~ 1e-23
+    check_orders(s, red.s, np.ones(G.n_beta), G.P, 1e-11, tag="tiny Mie")
     # equilibrated A and its column scales
     A, E = ctx.get_A()
     assert np.max(np.abs(E / red.pinv.E - 1)) < 1e-12
     Ao = red.A * red.pinv.E[None, :]
     assert np.max(np.abs(A - Ao)) < 1e-12
     # translation and low-rank parts
-    xh, xd = _randvec(torch, G.n_beta, 1, G.P)
+    xh, xd = _probe(torch, pb, 1)
     yT = _np(ctx.apply_T(xd))
-    assert rel(yT, red.T_apply(xh)) < 1e-12
+    D = dscale(pb)
+    check_orders(yT, red.T_apply(xh), D, G.P, 1e-12, tag="tiny T")
     yL = _np(ctx.apply_lowrank(xd))
-    assert rel(yL, red.lowrank_apply(xh)) < 1e-9
+    check_orders(yL, red.lowrank_apply(xh), D, G.P, 1e-9, tag="tiny lowrank")
     yK = _np(ctx.apply(xd))
-    assert rel(yK, red.K_apply(xh)) < 1e-9
+    check_orders(yK, red.K_apply(xh), D, G.P, 1e-9, tag="tiny K")
     b = _np(ctx.rhs())
-    assert rel(b, red.rhs()) < 1e-9
+    check_orders(b, red.rhs(), D, G.P, 1e-9, 1e-12, tag="tiny rhs")
     # solve
     beta_o = red.solve_lu()
     beta, st = ctx.solve(tol=1e-12, restart=100)
     say(f"[gpu] tiny iters={st.iters} resid={st.rel_resid:.2e}")
     assert st.rel_resid <= 1e-12
-    assert rel(_np(beta), beta_o) < 1e-9
+    check_orders(_np(beta), beta_o, D, G.P, 1e-9, 1e-10, tag="tiny beta")
     # Bragg amplitudes
     og = ctx.bragg(beta)
     oo = red.bragg(beta_o)
     assert np.array_equal(og["orders"], oo["orders"])
-    sel1, sel3 = oo["prop1"], oo["prop3"]
-    vg = np.concatenate([og["c"][sel1], og["d"][sel3]])
-    vo = np.concatenate([oo["c"][sel1], oo["d"][sel3]])
-    assert rel(vg, vo) < 1e-9
+    _check_bragg(og, oo, "tiny")
     assert og["flux_err"] < 1e-10
 
 
@@ -106,18 +115,17 @@ def test_small_solves(torch_cuda, M, P, seed, phi):
     pb = inputs.small(M, P, seed=seed, phi=phi)
     red = Reduced(pb)
     ctx = _ctx(pb)
-    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
-    assert rel(_np(ctx.apply_T(xd)), red.T_apply(xh)) < 1e-12
-    assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+    xh, xd = _probe(torch_cuda, pb, seed)
+    D = dscale(pb)
+    check_orders(_np(ctx.apply_T(xd)), red.T_apply(xh), D, P, 1e-12, tag=f"{pb.name} T")
+    check_orders(_np(ctx.apply(xd)), red.K_apply(xh), D, P, 1e-9, tag=f"{pb.name} K")
     beta_o = red.solve_lu()
     beta, st = ctx.solve(tol=1e-12, restart=150)
     say(f"[gpu] M={M} P={P} iters={st.iters} resid={st.rel_resid:.2e}")
-    assert rel(_np(beta), beta_o) < 1e-9
+    check_orders(_np(beta), beta_o, D, P, 1e-9, 1e-10, tag=f"{pb.name} beta")
     og = ctx.bragg(beta)
     oo = red.bragg(beta_o)
-    vg = np.concatenate([og["c"][oo["prop1"]], og["d"][oo["prop3"]]])
-    vo = np.concatenate([oo["c"][oo["prop1"]], oo["d"][oo["prop3"]]])
-    assert rel(vg, vo) < 1e-9
+    _check_bragg(og, oo, pb.name)
     assert og["flux_err"] < 1e-9
 
 
@@ -132,7 +140,7 @@ def test_empty_slab(torch_cuda, phi):
     assert abs(og["flux_err"]) < 1e-11
     vg = np.concatenate([og["c"][oo["prop1"]], og["d"][oo["prop3"]]])
     vo = np.concatenate([oo["c"][oo["prop1"]], oo["d"][oo["prop3"]]])
-    assert rel(vg, vo) < 1e-10
+    check_amplitudes(vg, vo, 1e-10, tag="empty slab")
 
 
 def test_invalid_geometry_rejected(torch_cuda):
@@ -164,18 +172,18 @@ def test_mixed_precision_refinement(torch_cuda, M, P, seed):
     pb = inputs.tiny_m4() if M == 4 else inputs.small(M, P, seed=seed)
     red = Reduced(pb)
     ctx = _ctx(pb)
-    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    xh, xd = _probe(torch_cuda, pb, seed)
+    D = dscale(pb)
     y64 = _np(ctx.apply(xd))
     y32 = _np(ctx.apply(xd, precision=GRT_FP32))
-    e32 = rel(y32, y64)
-    say(f"[gpu] mixed apply M={M} P={P} rel diff vs FP64 {e32:.2e}")
-    assert 0 < e32 < 1e-4
+    e32 = check_orders(y32, y64, D, P, 1e-4, tag=f"{pb.name} mixed apply vs FP64")
+    assert e32 > 0
     beta_o = red.solve_lu()
     beta, st = ctx.solve(tol=1e-12, restart=150, precision=GRT_FP32, inner_tol=1e-5)
     say(f"[gpu] mixed M={M} P={P} iters={st.iters} refine={st.refine_steps} "
         f"resid={st.rel_resid:.2e}")
     assert st.rel_resid <= 1e-12
-    assert rel(_np(beta), beta_o) < 1e-9
+    check_orders(_np(beta), beta_o, D, P, 1e-9, 1e-10, tag=f"{pb.name} mixed beta")
 
 
 def _batch_problems():
@@ -213,22 +221,25 @@ def test_batched_solve_matches_single_and_oracle(torch_cuda):
         beta_o = red.solve_lu()
         say(f"[gpu] batch {pb.name} iters={st.iters} (single {its}) resid={st.rel_resid:.2e}")
         assert st.rel_resid <= 1e-12
-        assert rel(_np(b), beta_o) < 1e-9
-        assert rel(_np(b), bs) < 1e-9
+        D = dscale(pb)
+        check_orders(_np(b), beta_o, D, pb.P, 1e-9, 1e-10, tag=f"batch {pb.name} vs oracle")
+        check_orders(_np(b), bs, D, pb.P, 1e-9, 1e-10, tag=f"batch {pb.name} vs single")
     # the same batch with its apply replayed from a captured graph, three times, with
     # eager work between the replays: identical results every time
     for rep in range(3):
         bg, sg = batch.solve(tol=1e-12, restart=150, graph=True)
         torch_cuda.cuda.synchronize()
-        for b, b2, st, st2 in zip(betas, bg, stats, sg):
+        for pb, b, b2, st, st2 in zip(pbs, betas, bg, stats, sg):
             assert st2.iters == st.iters
-            assert rel(_np(b2), _np(b)) < 1e-14, rep
+            check_orders(_np(b2), _np(b), dscale(pb), pb.P, 1e-13, 1e-14,
+                         tag=f"batch graph replay {rep}")
         ctxs[0].apply(betas[0])
     # warm start from the solution: converged on entry
     betas2, stats2 = batch.solve(tol=1e-12, restart=150, x0=betas)
     assert all(s.iters == 0 for s in stats2)
-    for b2, b in zip(betas2, betas):
-        assert rel(_np(b2), _np(b)) < 1e-15  # x -> D x -> D^{-1} x rounding only
+    for pb, b2, b in zip(pbs, betas2, betas):
+        # x -> D x -> D^{-1} x rounding only
+        check_orders(_np(b2), _np(b), dscale(pb), pb.P, 1e-15, tag="batch warm on entry")
     # a context whose table is freed after the batch was made is refused
     from paper_1412_7466_amd.grating import GratingError, GRT_ESTATE
     ctxs[4].set_table(False)
@@ -281,15 +292,17 @@ def test_batched_mixed_precision_refinement(torch_cuda):
             f"(single {ss.iters}, {ss.refine_steps}) resid={st.rel_resid:.2e}")
         assert st.rel_resid <= 1e-11
         assert st.refine_steps >= 1
-        assert rel(_np(b), beta_o) < 1e-9
-        assert rel(_np(b), _np(bs)) < 1e-9
+        D = dscale(pb)
+        check_orders(_np(b), beta_o, D, pb.P, 1e-9, 1e-10, tag=f"batch mixed {pb.name}")
+        check_orders(_np(b), _np(bs), D, pb.P, 1e-9, 1e-10, tag=f"batch mixed {pb.name} vs single")
     for rep in range(2):
         bg, sg = batch.solve(tol=1e-11, restart=150, precision=GRT_FP32, inner_tol=1e-5,
                              graph=True)
         torch_cuda.cuda.synchronize()
-        for b, b2, st, st2 in zip(betas, bg, stats, sg):
+        for pb, b, b2, st, st2 in zip(pbs, betas, bg, stats, sg):
             assert st2.iters == st.iters and st2.refine_steps == st.refine_steps
-            assert rel(_np(b2), _np(b)) < 1e-14, rep
+            check_orders(_np(b2), _np(b), dscale(pb), pb.P, 1e-13, 1e-14,
+                         tag=f"batch mixed graph replay {rep}")
         ctxs[0].apply(betas[0])
     betas2, stats2 = batch.solve(tol=1e-11, restart=150, precision=GRT_FP32, x0=betas)
     assert all(s2.iters == 0 and s2.refine_steps == 0 for s2 in stats2)
@@ -310,7 +323,8 @@ def test_layer_factors_shared_between_contexts(torch_cuda):
     assert np.array_equal(A1, A2)
     ca.close()
     beta, st = cb.solve(tol=1e-12, restart=150)
-    assert rel(_np(beta), Reduced(pb).solve_lu()) < 1e-9
+    check_orders(_np(beta), Reduced(pb).solve_lu(), dscale(pb), pb.P, 1e-9, 1e-10,
+                 tag="shared factors")
 
 
 @pytest.mark.parametrize("M,P,seed", [(67, 4, 6), (20, 10, 8), (12, 15, 9), (30, 20, 14)])
@@ -321,20 +335,21 @@ def test_resident_table_matches_oracle(torch_cuda, M, P, seed):
     pb = inputs.small(M, P, seed=seed)
     red = Reduced(pb)
     ctx = _ctx(pb)
-    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    xh, xd = _probe(torch_cuda, pb, seed)
     y_fly = _np(ctx.apply_T(xd))
     ctx.set_table(2)   # two lanes per target (reflection symmetry)
     y_tab1 = _np(ctx.apply_T(xd))
-    assert rel(y_tab1, red.T_apply(xh)) < 1e-12
+    D = dscale(pb)
+    check_orders(y_tab1, red.T_apply(xh), D, P, 1e-12, tag=f"{pb.name} table 2 lanes")
     ctx.set_table(1)   # one lane per target
     say(f"[gpu] table M={M} P={P}: {ctx.table_bytes()} bytes")
     y_tab = _np(ctx.apply_T(xd))
-    assert rel(y_tab, red.T_apply(xh)) < 1e-12
-    assert rel(y_tab, y_fly) < 1e-13
-    assert rel(y_tab, y_tab1) < 1e-13
-    assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+    check_orders(y_tab, red.T_apply(xh), D, P, 1e-12, tag=f"{pb.name} table")
+    check_orders(y_tab, y_fly, D, P, 1e-13, tag=f"{pb.name} table vs on the fly")
+    check_orders(y_tab, y_tab1, D, P, 1e-13, tag=f"{pb.name} table 1 vs 2 lanes")
+    check_orders(_np(ctx.apply(xd)), red.K_apply(xh), D, P, 1e-9, tag=f"{pb.name} table K")
     beta, st = ctx.solve(tol=1e-12, restart=150)
-    assert rel(_np(beta), red.solve_lu()) < 1e-9
+    check_orders(_np(beta), red.solve_lu(), D, P, 1e-9, 1e-10, tag=f"{pb.name} table beta")
     ctx.set_table(False)
     assert np.array_equal(_np(ctx.apply_T(xd)), y_fly)
 
@@ -348,7 +363,7 @@ def test_autotune_keeps_parity(torch_cuda, M, P, seed, table):
     ctx = _ctx(pb)
     if table:
         ctx.set_table(True)
-    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    xh, xd = _probe(torch_cuda, pb, seed)
     tuned = ctx.autotune()
     say(f"[gpu] autotune M={M} P={P} table={table}: {tuned} -> {ctx.sizes.m2l_chunks} chunks "
         f"split {ctx.sizes.m2l_split}, "
@@ -357,8 +372,9 @@ def test_autotune_keeps_parity(torch_cuda, M, P, seed, table):
     assert ctx.sizes.cx_chunks >= 1 and ctx.sizes.bx_chunks >= 1
     assert (ctx.sizes.m2l_chunks, ctx.sizes.m2l_split) in [(c, sp) for c, sp, _ in tuned]
     assert ctx.sizes.m2l_split in (1, 2)
-    assert rel(_np(ctx.apply_T(xd)), red.T_apply(xh)) < 1e-12
-    assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+    D = dscale(pb)
+    check_orders(_np(ctx.apply_T(xd)), red.T_apply(xh), D, P, 1e-12, tag="autotuned T")
+    check_orders(_np(ctx.apply(xd)), red.K_apply(xh), D, P, 1e-9, tag="autotuned K")
 
 
 @pytest.mark.parametrize("M,P,seed", [(67, 4, 71), (30, 10, 72), (40, 15, 73), (25, 20, 74)])
@@ -370,7 +386,7 @@ def test_split_translation_matches(torch_cuda, M, P, seed):
     pb = inputs.small(M, P, seed=seed)
     red = Reduced(pb)
     ctx = _ctx(pb)
-    xh, xd = _randvec(torch_cuda, red.G.n_beta, seed, P)
+    xh, xd = _probe(torch_cuda, pb, seed)
     for chunks in (1, 2):
         ctx.set_launch(chunks, 1)
         y1 = _np(ctx.apply_T(xd))
@@ -380,8 +396,8 @@ def test_split_translation_matches(torch_cuda, M, P, seed):
         say(f"[gpu] split M={M} P={P} chunks={ctx.sizes.m2l_chunks}: "
             f"max |diff| {np.max(np.abs(y2 - y1)):.1e}")
         assert np.array_equal(y1, y2)
-        assert rel(y2, red.T_apply(xh)) < 1e-12
-        assert rel(_np(ctx.apply(xd)), red.K_apply(xh)) < 1e-9
+        check_orders(y2, red.T_apply(xh), dscale(pb), P, 1e-12, tag="split T")
+        check_orders(_np(ctx.apply(xd)), red.K_apply(xh), dscale(pb), P, 1e-9, tag="split K")
     from paper_1412_7466_amd.grating import GratingError, GRT_EINVAL
     with pytest.raises(GratingError) as ei:
         ctx.set_launch(1, 3)
@@ -397,7 +413,7 @@ def test_overlapped_apply_matches(torch_cuda):
     pb = inputs.small(40, 10, seed=81)
     red = Reduced(pb)
     ctx = _ctx(pb)
-    xh, xd = _randvec(torch_cuda, red.G.n_beta, 81, 10)
+    xh, xd = _probe(torch_cuda, pb, 81)
     for table in (False, True):
         ctx.set_table(table)
         ctx.set_overlap(False)
@@ -406,7 +422,7 @@ def test_overlapped_apply_matches(torch_cuda):
         ctx.set_overlap(True)
         y1 = _np(ctx.apply(xd))
         assert np.array_equal(y0, y1)
-        assert rel(y1, red.K_apply(xh)) < 1e-9
+        check_orders(y1, red.K_apply(xh), dscale(pb), 10, 1e-9, tag="overlap K")
         for rep in range(3):
             b1, s1 = ctx.solve(tol=1e-12, restart=150, graph=True)
             torch_cuda.cuda.synchronize()
@@ -428,7 +444,7 @@ def test_graph_replayed_solves_match_eager(torch_cuda):
     pb = inputs.small(40, 10, seed=12)
     red = Reduced(pb)
     ctx = _ctx(pb)
-    xh, xd = _randvec(torch_cuda, red.G.n_beta, 12, 10)
+    xh, xd = _probe(torch_cuda, pb, 12)
     beta_o = red.solve_lu()
     for table in (False, True, False):
         ctx.set_table(table)
@@ -438,11 +454,12 @@ def test_graph_replayed_solves_match_eager(torch_cuda):
             b_g, s_g = ctx.solve(tol=1e-12, restart=150, graph=True)
             torch_cuda.cuda.synchronize()
             assert s_g.iters == s_eager.iters
-            assert rel(_np(b_g), _np(b_eager)) < 1e-14, (table, rep)
-            assert rel(_np(ctx.apply(xd)), y_eager) == 0.0   # eager work between replays
-        assert rel(_np(b_g), beta_o) < 1e-9
+            check_orders(_np(b_g), _np(b_eager), dscale(pb), 10, 1e-13, 1e-14,
+                         tag=f"graph replay table={table} rep={rep}")
+            assert np.array_equal(_np(ctx.apply(xd)), y_eager)   # eager work between replays
+        check_orders(_np(b_g), beta_o, dscale(pb), 10, 1e-9, 1e-10, tag="graph replay vs oracle")
     bm, sm = ctx.solve(tol=1e-12, restart=150, precision=GRT_FP32)
     for rep in range(2):
         bg, sg = ctx.solve(tol=1e-12, restart=150, precision=GRT_FP32, graph=True)
         assert sg.iters == sm.iters and sg.refine_steps == sm.refine_steps
-        assert rel(_np(bg), _np(bm)) < 1e-14
+        check_orders(_np(bg), _np(bm), dscale(pb), 10, 1e-13, 1e-14, tag="mixed graph replay")

@@ -201,3 +201,29 @@ def test_pinv_rule_and_eps_sweep():
                 jumps[(rule, eps)] = np.max(np.abs(A[0] - B[0])) / np.max(np.abs(A[0]))
     for rule in ("truncate", "cap"):
         assert jumps[(rule, 1e-11)] < jumps[(rule, 1e-9)], jumps
+
+
+def test_field_continuous_across_disk_boundaries(tiny_fine):
+    """Inside each disk the field is sum_n gamma_n J_n(k_p r) e^{in theta} (sec. 4.1);
+    on the boundary it meets the middle layer's representation in value and radial
+    derivative (TM, equal mu), at points between any quadrature nodes."""
+    red, beta, F = tiny_fine
+    G = red.G
+    n = np.arange(-G.P, G.P + 1)
+    th = np.linspace(0, 2 * np.pi, 9, endpoint=False) + 0.1
+    for m in range(G.M):
+        R = G.rad[m]
+        tx = G.cx[m] + R * np.cos(th)
+        ty = G.cy[m] + R * np.sin(th)
+        u, ux, uy = F.layer(1, tx, ty)
+        ur = ux * np.cos(th) + uy * np.sin(th)
+        e = np.exp(1j * np.outer(th, n))
+        kp = G.kp[m]
+        u_in = (e * sp.jv(n, kp * R)) @ F.gamma[m]
+        ur_in = (e * kp * sp.jvp(n, kp * R)) @ F.gamma[m]
+        # the local expansions are truncated at |n| <= P = 10 here, at their outer radius
+        assert np.max(np.abs(u_in - u)) < 1e-10 * np.max(np.abs(u)), m
+        assert np.max(np.abs(ur_in - ur)) < 1e-9 * np.max(np.abs(ur)), m
+        # Field.total picks the interior just inside the boundary
+        ins, val = F.inside(G.cx[m] + 0.999 * R * np.cos(th), G.cy[m] + 0.999 * R * np.sin(th))
+        assert np.all(ins)

@@ -145,6 +145,9 @@ def test_translation_paths_agree():
     ref = T @ x
     tab = TranslationTable(G, chunk=3)
     assert np.linalg.norm(tab.apply(x) - ref) < 1e-13 * np.linalg.norm(ref)
+    sub = TranslationTable(G, chunk=2, rows=[4, 1, 6])
+    assert np.allclose(sub.apply(x).reshape(3, -1),
+                       ref.reshape(G.M, -1)[[4, 1, 6]], rtol=1e-13, atol=0)
     rows = apply_T_rows(G, x, [1, 4])
     nb = 2 * G.P + 1
     assert np.allclose(rows[0], ref[nb:2 * nb], rtol=1e-13, atol=0)
