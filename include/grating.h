@@ -271,6 +271,34 @@ grt_status grt_get_mie(grt_ctx* ctx, double* s_host);
 grt_status grt_profile_enable(grt_ctx* ctx, int enable);
 grt_status grt_profile_read(grt_ctx* ctx, double* m2l_ms_total, int64_t* m2l_launches);
 
+/* ---- Translation without allocation ------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  y = T x, the same
+ * translation as grt_apply_T (sec. 4.2, eq. repre3_mod: the three near copies
+ * l = -1, 0, 1 of every inclusion, phased by alpha^l, excluding (j, j, 0)), but with
+ * no context: the caller passes the geometry as device arrays and the call makes no
+ * allocation.  Its per-chunk partial sums go to a fixed scratch array that the
+ * library holds on each device for the life of the process
+ * (GRT_NOALLOC_SCRATCH_BYTES = 64 MiB); the chunk count is chosen as in grt_apply_T
+ * and lowered until the partials fit, so M (2P+1) may be at most 4,194,304 (one
+ * partial result); larger problems get GRT_EINVAL.
+ *   M: inclusions, centres cx_dev[M], cy_dev[M] (device FP64) inside one cell
+ *      |x| <= d/2 (not checked; grt_set_problem checks it on the context path);
+ *   P: multipole order (1-6, 8, 10, 12, 15 or 20; others GRT_EUNSUP);
+ *   k2: wavenumber of the middle layer (> 0); d: period (> 0);
+ *   alpha = alpha_re + i alpha_im: the Bloch phase e^{i kappa d} (|alpha| = 1 to 1e-12);
+ *   x_dev, y_dev: device complex FP64 [M][2P+1] (n = -P..P at n + P), not aliased.
+ * Work is enqueued on hip_stream (a hipStream_t on the current device; NULL: the null
+ * stream) and is asynchronous.  The first call on a device fills that device's
+ * H_0 / H_1 table with a synchronous copy, so it must not be made under stream
+ * capture (GRT_ESTATE then); later calls may be captured.  Calls that overlap on one
+ * device share its scratch array and race: order them (one stream, or events).
+ * Results equal grt_apply_T's up to the order of the partial sums. */
+#define GRT_NOALLOC_SCRATCH_BYTES (64ll << 20)
+grt_status grt_apply_T_noalloc(int64_t M, int P, double k2, double d, double alpha_re,
+                               double alpha_im, const double* cx_dev, const double* cy_dev,
+                               const void* x_dev, void* y_dev, void* hip_stream);
+
 /* ---- Batched solves --------------------------------------------------------
  * Many problems (different inclusion sets, angles or frequencies; the sweeps of
  * sec. 6) solved together: every GMRES step of the batch is one launch per kernel

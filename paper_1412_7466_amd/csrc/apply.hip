@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -770,5 +771,117 @@ grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out) {
   launch_gemv_rows(s, c->d_W1, c->d_gvec, c->d_tvec, c->rank, c->n_g);
   launch_gemv_rows(s, c->d_W3, c->d_tvec, out, 2 * c->g.Nrb, c->rank);
   GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// y = T x without a context and without any allocation by the call.  The per-chunk
+// partial sums of the translation go to `scratch`, a file-scope device array of
+// fixed size, and the H_0 / H_1 table to `noalloc_htab`; both exist on every device
+// the library runs on for the life of the process.  Host code never passes the
+// arrays' names to a kernel (on the host they are stand-ins, not device addresses):
+// the first call on a device looks up their device addresses there with
+// hipGetSymbolAddress and keeps them per device.
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static __device__ __align__(256) double noalloc_htab[HTAB_SIZE];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+struct NoallocDevice {
+  cd* scratch = nullptr;
+  double* htab = nullptr;
+};
+std::mutex g_noalloc_mu;
+NoallocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+
+// Device addresses of this device's arrays; on the first call on the device also
+// fills its H_0 / H_1 table (a synchronous copy of host-built coefficients).
+grt_status noalloc_device(int dev, hipStream_t s, NoallocDevice& out) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  NoallocDevice& nd = g_noalloc[dev];
+  if (nd.scratch) {
+    out = nd;
+    return GRT_OK;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return GRT_EHIP;
+  if (cap != hipStreamCaptureStatusNone) return GRT_ESTATE;  // first call must not be captured
+  void* ps = nullptr;
+  void* ph = nullptr;
+  if (hipGetSymbolAddress(&ps, HIP_SYMBOL(scratch)) != hipSuccess || !ps) return GRT_EHIP;
+  if (hipGetSymbolAddress(&ph, HIP_SYMBOL(noalloc_htab)) != hipSuccess || !ph) return GRT_EHIP;
+  std::vector<double> tab(HTAB_SIZE);
+  for (int k = 0; k < HTAB_NI; ++k) htab_interval(k, tab.data() + (size_t)k * HTAB_STRIDE);
+  if (hipMemcpy(ph, tab.data(), sizeof(double) * HTAB_SIZE, hipMemcpyHostToDevice) != hipSuccess)
+    return GRT_EHIP;
+  nd.scratch = static_cast<cd*>(ps);
+  nd.htab = static_cast<double*>(ph);
+  out = nd;
+  return GRT_OK;
+}
+
+template <int P>
+void launch_m2l_noalloc(hipStream_t s, const double* cx, const double* cy, const cd* x, cd* part,
+                        int M, int chunk, int nchunks, double k, double d, cd alpha,
+                        const double* htab) {
+  dim3 grid((unsigned)((M + 63) / 64), (unsigned)nchunks);
+  const cd alpha_inv{alpha.r, -alpha.i};  // |alpha| = 1
+  m2l_kernel<P, cd><<<grid, M2L_THREADS, 0, s>>>(cx, cy, x, part, M, chunk, k, d, alpha,
+                                                  alpha_inv, htab, 0.0);
+}
+
+#define GRT_P_DISPATCH_NOCTX(FN, P, ...)                \
+  switch (P) {                                          \
+    case 1: FN<1>(__VA_ARGS__); break;                  \
+    case 2: FN<2>(__VA_ARGS__); break;                  \
+    case 3: FN<3>(__VA_ARGS__); break;                  \
+    case 4: FN<4>(__VA_ARGS__); break;                  \
+    case 5: FN<5>(__VA_ARGS__); break;                  \
+    case 6: FN<6>(__VA_ARGS__); break;                  \
+    case 8: FN<8>(__VA_ARGS__); break;                  \
+    case 10: FN<10>(__VA_ARGS__); break;                \
+    case 12: FN<12>(__VA_ARGS__); break;                \
+    case 15: FN<15>(__VA_ARGS__); break;                \
+    case 20: FN<20>(__VA_ARGS__); break;                \
+    default: return GRT_EUNSUP;                         \
+  }
+
+}  // namespace
+
+extern "C" grt_status grt_apply_T_noalloc(int64_t M, int P, double k2, double d, double alpha_re,
+                                          double alpha_im, const double* cx_dev,
+                                          const double* cy_dev, const void* x_dev, void* y_dev,
+                                          void* hip_stream) {
+  if (M < 1 || M > (int64_t)1 << 30 || P < 1 || !(k2 > 0) || !(d > 0) || !cx_dev || !cy_dev ||
+      !x_dev || !y_dev || x_dev == y_dev || !std::isfinite(alpha_re) || !std::isfinite(alpha_im) ||
+      std::fabs(std::hypot(alpha_re, alpha_im) - 1.0) > 1e-12)
+    return GRT_EINVAL;
+  if (!supported_P(P)) return GRT_EUNSUP;
+  const int64_t nbeta = M * (2 * P + 1);
+  const int64_t max_chunks = (int64_t)(NOALLOC_SCRATCH_BYTES / (sizeof(cd) * (size_t)nbeta));
+  if (max_chunks < 1) return GRT_EINVAL;  // one partial result does not fit
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return GRT_EHIP;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  NoallocDevice nd;
+  grt_status st = noalloc_device(dev, s, nd);
+  if (st != GRT_OK) return st;
+  // the default launch shape of the context path, limited by what the scratch holds
+  int chunk = 0, nchunks = 0;
+  split_work(M, (M + 63) / 64, 2048 / M2L_WAVES, 4 * M2L_WAVES, chunk, nchunks);
+  if (nchunks > max_chunks) {
+    chunk = (int)((M + max_chunks - 1) / max_chunks);
+    nchunks = (int)((M + chunk - 1) / chunk);
+  }
+  const cd* x = static_cast<const cd*>(x_dev);
+  cd* y = static_cast<cd*>(y_dev);
+  GRT_P_DISPATCH_NOCTX(launch_m2l_noalloc, P, s, cx_dev, cy_dev, x, nd.scratch, (int)M, chunk,
+                       nchunks, k2, d, cd{alpha_re, alpha_im}, nd.htab);
+  const int n = (int)nbeta;
+  combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
+      n, nullptr, nullptr, nd.scratch, nchunks, nullptr, 0, nullptr, y, 1, nullptr);
+  if (hipGetLastError() != hipSuccess) return GRT_EHIP;
   return GRT_OK;
 }

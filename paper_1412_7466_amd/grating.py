@@ -91,6 +91,8 @@ _PROTOS = {
     "grt_get_mie": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "grt_profile_enable": (C.c_int, [_VP, C.c_int]),
     "grt_profile_read": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "grt_apply_T_noalloc": (C.c_int, [C.c_int64, C.c_int, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, _VP, _VP, _VP, _VP, _VP]),
     "grt_batch_create": (C.c_int, [C.POINTER(_VP), C.c_int64, C.POINTER(_VP), _VP]),
     "grt_batch_destroy": (C.c_int, [_VP]),
     "grt_batch_error_message": (C.c_char_p, [_VP]),
@@ -371,6 +373,29 @@ class Context:
         s = np.zeros(2 * self.sizes.n_beta)
         self._check(self.lib.grt_get_mie(self.h, _dptr(s)))
         return s[0::2] + 1j * s[1::2]
+
+
+def apply_T_noalloc(P, k2, d, alpha, cx, cy, x, y):
+    """y = T x through grt_apply_T_noalloc (no context, no allocation by the call).
+
+    cx, cy: float64 device tensors [M]; x, y: complex128 device tensors [M (2P+1)],
+    all contiguous on the current device; alpha: complex Bloch phase.  Enqueued on
+    torch's current stream."""
+    import torch
+    lib = load_library()
+    M = cx.numel()
+    for t in (cx, cy, x, y):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("device tensors must be contiguous CUDA tensors")
+    if cy.numel() != M or x.numel() != M * (2 * P + 1) or y.numel() != x.numel():
+        raise ValueError("sizes do not match M and P")
+    s = torch.cuda.current_stream(x.device).cuda_stream
+    st = lib.grt_apply_T_noalloc(M, P, float(k2), float(d), float(alpha.real),
+                                 float(alpha.imag), _VP(cx.data_ptr()), _VP(cy.data_ptr()),
+                                 _VP(x.data_ptr()), _VP(y.data_ptr()), _VP(s))
+    if st != GRT_OK:
+        raise GratingError(st, "grt_apply_T_noalloc failed")
+    return y
 
 
 class Batch:

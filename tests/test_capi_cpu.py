@@ -37,3 +37,22 @@ def test_null_context_rejected(lib):
     assert lib.grt_apply(None, None, None, 0) == grating.GRT_EINVAL
     assert lib.grt_create(None, 0, None) == grating.GRT_EINVAL
     assert lib.grt_error_message(None) == b"null context"
+
+
+def test_noalloc_rejects_bad_arguments_on_host(lib):
+    """grt_apply_T_noalloc checks its arguments before touching a device."""
+    f = lib.grt_apply_T_noalloc
+    p = C.c_void_p(16)   # never dereferenced: every call below fails its host checks
+    ok = dict(M=4, P=10, k2=10.0, d=1.0, ar=1.0, ai=0.0)
+
+    def call(**kw):
+        a = {**ok, **kw}
+        return f(a["M"], a["P"], a["k2"], a["d"], a["ar"], a["ai"], p, p, p, C.c_void_p(32), None)
+
+    assert call(M=0) == grating.GRT_EINVAL
+    assert call(k2=-1.0) == grating.GRT_EINVAL
+    assert call(ar=2.0) == grating.GRT_EINVAL              # |alpha| must be 1
+    assert call(P=7) == grating.GRT_EUNSUP                 # P not compiled in
+    assert call(M=200_000, P=20) == grating.GRT_EINVAL     # one partial exceeds the scratch
+    assert f(4, 10, 10.0, 1.0, 1.0, 0.0, None, p, p, C.c_void_p(32), None) == grating.GRT_EINVAL
+    assert f(4, 10, 10.0, 1.0, 1.0, 0.0, p, p, p, p, None) == grating.GRT_EINVAL   # x aliases y
