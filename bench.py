@@ -164,18 +164,24 @@ def record_flops(db, commands):
                 vals[c] = statistics.median(v)
         inst = (2 * vals.get("SQ_INSTS_VALU_FMA_F64", 0) + vals.get("SQ_INSTS_VALU_ADD_F64", 0)
                 + vals.get("SQ_INSTS_VALU_MUL_F64", 0)) * 64
+        # SQ_INSTS_VALU_FLOPS_FP64 adds each wave instruction's flops (FMA = 2) once,
+        # not per lane: x 64 lanes (it equals the instruction-count estimate)
+        counted = 64 * vals.get("SQ_INSTS_VALU_FLOPS_FP64", inst / 64)
         kern[k] = {"counters_median_per_dispatch": vals,
-                   "flops_fp64_per_dispatch": vals.get("SQ_INSTS_VALU_FLOPS_FP64", inst),
+                   "flops_fp64_per_dispatch": counted,
                    "flops_fp64_from_instructions": inst,
+                   "flops_fp32_per_dispatch": 64 * vals.get("SQ_INSTS_VALU_FLOPS_FP32", 0),
                    "algorithmic_flops": algo,
-                   "counted_over_algorithmic": vals.get("SQ_INSTS_VALU_FLOPS_FP64", inst) / algo,
+                   "counted_over_algorithmic": counted / algo,
                    "dispatches": len({r.get("dispatch_id", i) for i, r in enumerate(rk)})}
     rec = {"source_sha256": kernel_source_hash(), "kernels": kern}
     with open(FLOPS_MD, "w") as f:
         f.write("# FP64 instruction counters of the translation kernels, M=1000, P=15\n\n"
                 "One rocprofv3 counter run of the benchmark (every translation mode, default "
-                "launch shapes).  SQ_INSTS_VALU_FLOPS_FP64 counts the FP64 flops the VALU "
-                "executed (FMA = 2); the algorithmic count is the Toeplitz contraction, "
+                "launch shapes).  SQ_INSTS_VALU_FLOPS_FP64 adds the FP64 flops of each wave "
+                "instruction (FMA = 2) once, so it is multiplied by the 64 lanes of a wave; it "
+                "equals (2 FMA + ADD + MUL) x 64 from the instruction counts.  The algorithmic "
+                "count is the Toeplitz contraction, "
                 "8 (2P+1)^2 flops per (target, source) pair, M^2 pairs per launch.  A counted "
                 "figure above it is the generator arithmetic (Hankel functions, recurrence, "
                 "phases) the on-the-fly kernels also do.\n\nCommand (repository root, one "
