@@ -469,19 +469,105 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
     return res
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3   # dense FP32 matrix-core peak of the MI355X
+
+
+def block_translation(a, torch):
+    """S T of R incidence angles at once on the FP32 matrix cores, on the large block
+    geometry (d=4, omega=40, P=20, radii U[0.005, 0.01]): the context is built for the
+    translation only (no layer factorisation of the R angles).  Timed with HIP events
+    on the context's stream; sampled targets of sampled angles checked against the
+    oracle (test infrastructure) one by one."""
+    import numpy as np
+    from paper_1412_7466_amd import inputs
+    from paper_1412_7466_amd.grating import Context
+    M, R = a.block_M, a.block_workload
+    pb, phis = inputs.large_block(M=M, R=R)
+    P = pb.P
+    nb = 2 * P + 1
+    ctx = Context(0)
+    ctx.set_problem(pb, phis=list(phis))
+    t0 = time.perf_counter()
+    ctx.build_translation()
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    k2 = pb.omega * pb.n_layer[1]
+    n = np.abs(np.arange(-P, P + 1))
+    import scipy.special as sp
+    D = np.abs(sp.hankel1(n[None, :], k2 * np.asarray(pb.radius)[:, None])).reshape(-1)
+    rng = np.random.default_rng(3)
+    x = torch.empty(R * D.size, dtype=torch.complex128, device="cuda:0")
+    for r in range(R):
+        u = rng.standard_normal(D.size) + 1j * rng.standard_normal(D.size)
+        x[r * D.size:(r + 1) * D.size] = torch.from_numpy(u / D)
+    y = ctx.apply_ST_block(x)          # warm-up (allocates the packed buffers)
+    torch.cuda.synchronize()
+    s = ctx.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = a.block_reps
+    ev[0].record(s)
+    for _ in range(reps):
+        ctx.apply_ST_block(x, y)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    # algorithmic: 8 (2P+1)^2 flops per (target, source, copy) per angle, 3M^2 - M
+    # pair-images; issued: the padded GEMM the kernel runs (rows to 16-tiles, the K
+    # steps of each (source, copy) to 4, angles to 64)
+    algo = 8.0 * nb * nb * (3.0 * M * M - M) * R
+    mt, ns, rp = (nb + 15) // 16, (nb + 3) // 4, ((R + 63) // 64) * 64
+    issued = 8.0 * (mt * 16) * (ns * 4) * 3.0 * M * M * rp
+    tf = algo / (ms * 1e-3) / 1e12
+    # oracle check of sampled targets of sampled angles
+    from oracle.common import Geometry
+    from oracle.multiple import apply_T_rows, mie_coefficients
+    import dataclasses
+    rows = np.array([0, M // 2, M - 1])
+    sel = (rows[:, None] * nb + np.arange(nb)[None, :]).reshape(-1)
+    worst = 0.0
+    for r in sorted({0, R // 2, R - 1}):
+        G = Geometry(dataclasses.replace(pb, phi=float(phis[r])))
+        xr = x[r * D.size:(r + 1) * D.size].cpu().numpy()
+        ref = (mie_coefficients(G.k2, G.kp[rows], G.rad[rows], P) *
+               apply_T_rows(G, xr, rows)).reshape(-1)
+        yr = y[r * D.size:(r + 1) * D.size].cpu().numpy()[sel]
+        e = np.abs(D[sel] * (yr - ref)).reshape(-1, nb).max(0)
+        sc = np.abs(D[sel] * ref).reshape(-1, nb).max(0)
+        worst = max(worst, float((e / np.maximum(sc, 1e-6 * sc.max())).max()))
+    ctx.close()
+    return {"workload": f"large block: M={M}, d=4, middle layer y in [-2,2], radii "
+                        f"U[0.005,0.01], omega=40, P={P}, {R} angles in [-pi/3,pi/3], "
+                        f"S T of every angle per apply (FP32 matrix cores)",
+            "M": M, "P": P, "R": R, "translation_build_s": t_build,
+            "ms_per_block_apply": ms, "applies_timed": reps,
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tf / FP32_MFMA_PEAK_TFLOPS,
+                         "flops_per_launch": algo,
+                         "what": "algorithmic 8 (2P+1)^2 (3M^2 - M) R (every near copy "
+                                 "of every pair, every angle)",
+                         "issued_mfma_flops_per_launch": issued,
+                         "issued_tflops": issued / (ms * 1e-3) / 1e12,
+                         "issued_frac": issued / (ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS},
+            "oracle_check": {"sample": "targets 0, M/2, M-1 of angles 0, R/2, R-1",
+                             "worst_per_order_rel_err": worst,
+                             "bar": "FP32: 1e-5 of each order's size (floor 1e-6 of the "
+                                    "largest)"}}
+
+
 def batch_config(a, torch, n):
-    """A sample of the batched mixed-precision workload (M log-uniform in [200, 4000],
-    P in {10, 15, 20}, omega in {10, 20, 40}, angles in [-pi/3, pi/3]) on six
-    (omega, phi) cells: plain FP64 solves one after another (generator on the fly)
-    against one batched solve in FP64 and in mixed precision, cold and warm-started.
-    Some instances at omega = 40 converge very slowly (strongly coupled resonant
-    scattering), so the solves run with restart 400 and at most 2000 lockstep steps,
-    and the number of instances that reached the tolerance is reported."""
+    """The first n instances of the batched mixed-precision workload (instance i: seed
+    3000 + i, M log-uniform in [200, 4000], (omega, P) = (10, 10), (20, 15), (40, 20) by
+    i mod 3, angle (i div 3) mod 16 of 16 in [-pi/3, pi/3]; n = 48 covers every
+    (omega, angle) cell once): plain FP64 solves one after another against one batched
+    solve in FP64 and in mixed precision, cold and warm-started.  At omega = 40 the
+    GMRES iteration count grows about linearly with M (a third of M), so the Krylov
+    dimension must reach it: restart 1500, at most 3000 steps.  Reports converged
+    counts, the differences to the plain solves and, for the instances with a stored
+    oracle solution (tests/golden/batch_oracle.npz), the error against it."""
     import numpy as np
     from paper_1412_7466_amd import inputs
     from paper_1412_7466_amd.grating import Batch, Context, Network, GRT_FP32
-    cells = [(0, 0), (1, 5), (2, 10), (0, 15), (1, 12), (2, 3)]
-    pbs = [inputs.batch_problem(i, cells) for i in range(n)]
+    pbs = [inputs.batch_problem(i) for i in range(n)]
     t0 = time.perf_counter()
     ctxs = []
     for pb in pbs:
@@ -493,11 +579,13 @@ def batch_config(a, torch, n):
         print(f"[bench] batch workload: built and tuned {pb.name}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
-    kw = dict(tol=a.tol, restart=max(a.restart, 400), maxit=2000, check=False)
+    kw = dict(tol=a.tol, restart=1500, maxit=3000, check=False)
     ctxs[0].solve(**kw)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    plain = [c.solve(**kw) for c in ctxs]
+    plain = []
+    for c in ctxs:
+        plain.append(c.solve(**kw))
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t
     print("[bench] batch workload: sequential solves done", file=sys.stderr, flush=True)
@@ -513,20 +601,42 @@ def batch_config(a, torch, n):
         return out, time.perf_counter() - t
 
     (bf, sf), t_bf = timed()
+    print("[bench] batch workload: batched FP64 solves done", file=sys.stderr, flush=True)
     (bm, sm), t_bm = timed(precision=GRT_FP32)
-    print("[bench] batch workload: batched solves done", file=sys.stderr, flush=True)
+    print("[bench] batch workload: batched mixed solves done", file=sys.stderr, flush=True)
 
     def diff(bs, sts):
-        """largest relative difference to the plain solution over the instances that
-        reached the tolerance in both runs"""
-        d = [float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
-             for b, st, (p, sp) in zip(bs, sts, plain)
-             if st.rel_resid <= a.tol and sp.rel_resid <= a.tol]
+        """largest relative difference to the plain solution (normalised basis) over
+        the instances that reached the tolerance in both runs"""
+        d = []
+        for c, b, st, (p, sp) in zip(ctxs, bs, sts, plain):
+            if st.rel_resid <= a.tol and sp.rel_resid <= a.tol:
+                D = torch.from_numpy(np.abs(_dnorm(c.pb))).to(b.device)
+                d.append(float(torch.linalg.norm(D * (b - p)) / torch.linalg.norm(D * p)))
         return max(d) if d else None
 
-    res = {"workload": (f"{n} instances of the batched workload: M log-uniform in [200, 4000], "
-                        f"P in {{10, 15, 20}}, omega in {{10, 20, 40}} x angles in [-pi/3, pi/3] "
-                        f"(6 cells), d=1, middle layer y in [-1, 1], GMRES to {a.tol:g}"),
+    gold = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batch_oracle.npz")
+    if os.path.exists(gpath):
+        gold = dict(np.load(gpath))
+
+    def oracle_errs(bs):
+        """error of the instances with a stored oracle solution"""
+        out = {}
+        if gold is None:
+            return out
+        for i in gold["instances"]:
+            i = int(i)
+            if i >= n or str(gold[f"i{i}_digest"]) != pbs[i].digest():
+                continue
+            g = {k: gold[f"i{i}_{k}"] for k in ("beta", "D", "c", "d", "prop1", "prop3")}
+            out[f"instance_{i}"] = oracle_error(bs[i], ctxs[i], g)
+        return out
+
+    res = {"workload": (f"first {n} instances of the batched workload (R24 rules: seed 3000+i, "
+                        f"M log-uniform in [200, 4000], (omega, P) in {{(10,10), (20,15), "
+                        f"(40,20)}} by i mod 3, 16 angles in [-pi/3, pi/3]), d=1, middle layer "
+                        f"y in [-1, 1], GMRES to {a.tol:g}"),
            "M": [pb.M for pb in pbs], "P": [pb.P for pb in pbs],
            "omega": [pb.omega for pb in pbs], "build_s": t_build,
            "plain_fp64_sequential_solves_per_s": n / t_plain,
@@ -539,7 +649,9 @@ def batch_config(a, torch, n):
            "converged_batched_fp64": int(sum(st.rel_resid <= a.tol for st in sf)),
            "converged_batched_mixed": int(sum(st.rel_resid <= a.tol for st in sm)),
            "batched_fp64_max_rel_diff_vs_plain": diff(bf, sf),
-           "batched_mixed_max_rel_diff_vs_plain": diff(bm, sm)}
+           "batched_mixed_max_rel_diff_vs_plain": diff(bm, sm),
+           "err_vs_oracle_plain": oracle_errs([p for p, _ in plain]),
+           "err_vs_oracle_batched_mixed": oracle_errs(bm)}
     wpath = os.path.join(ROOT, "paper_1412_7466_amd", "warm_start.npz")
     if os.path.exists(wpath):
         w = np.load(wpath)
@@ -552,12 +664,22 @@ def batch_config(a, torch, n):
                     "iters_mixed_batched_warm": [st.iters for st in sw],
                     "converged_mixed_batched_warm": int(sum(st.rel_resid <= a.tol for st in sw)),
                     "warm_rejected": int(sum(st.x0_rejected for st in sw)),
-                    "mixed_batched_warm_max_rel_diff_vs_plain": diff(bw, sw)})
+                    "mixed_batched_warm_max_rel_diff_vs_plain": diff(bw, sw),
+                    "err_vs_oracle_mixed_batched_warm": oracle_errs(bw)})
         net.close()
     batch.close()
     for c in ctxs:
         c.close()
     return res
+
+
+def _dnorm(pb):
+    """D = |H_|n|(k2 r)| of a problem (the basis the solver's residuals are taken in)."""
+    import numpy as np
+    import scipy.special as sp
+    n = np.abs(np.arange(-pb.P, pb.P + 1))
+    k2 = pb.omega * pb.n_layer[1]
+    return np.abs(sp.hankel1(n[None, :], k2 * np.asarray(pb.radius)[:, None])).reshape(-1)
 
 
 def main():
@@ -577,6 +699,11 @@ def main():
     ap.add_argument("--sweep-n", type=int, default=8)
     ap.add_argument("--batch-workload", type=int, default=0,
                     help="also run this many instances of the batched workload (slow setup)")
+    ap.add_argument("--block-workload", type=int, default=0, metavar="R",
+                    help="also time S T of R angles at once on the FP32 matrix cores "
+                         "(large block geometry, translation-only build)")
+    ap.add_argument("--block-M", type=int, default=10000)
+    ap.add_argument("--block-reps", type=int, default=2)
     ap.add_argument("--flops-record", metavar="PMC_DB",
                     help="write the FP64 counter summary from one counter run and exit")
     a = ap.parse_args()
@@ -788,6 +915,8 @@ def main():
         res["sweep_small"] = small_sweep(a, torch)
     if a.batch_workload > 0:
         res["batch_workload"] = batch_config(a, torch, a.batch_workload)
+    if a.block_workload > 0:
+        res["block_translation"] = block_translation(a, torch)
     if a.copy_probe_mib > 0:
         src = torch.ones(a.copy_probe_mib * 131072, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)

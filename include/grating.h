@@ -18,7 +18,7 @@
  *    next call on ctx).
  *  - Coefficient vectors (beta, K beta, right-hand side) are complex FP64,
  *    interleaved (re, im), laid out [M][2P+1] with the order n = -P..P at index
- *    n + P.  They live in DEVICE memory owned by the caller, on the context's
+ *    n + P; a context with n_rhs >= 2 incidence angles stacks them [n_rhs][M][2P+1].  They live in DEVICE memory owned by the caller, on the context's
  *    device, contiguous; the library never frees caller memory.
  *  - Host arrays passed to grt_set_problem are copied; the caller keeps them.
  *  - Work is enqueued on the context stream.  grt_apply and grt_rhs are
@@ -79,11 +79,17 @@ typedef struct {
 
 /* Plane wave of frequency omega (k_l = omega * n_l), angle phi from the downward
  * normal (horizontal wavenumber k_1 sin phi), TM polarisation; multipole order P
- * (2P+1 coefficients per inclusion). */
+ * (2P+1 coefficients per inclusion).  Several right-hand sides: n_rhs >= 2 angles
+ * phis[0 .. n_rhs) (host, copied; phi is then ignored) on the same geometry and
+ * frequency, each with its own Bloch phase e^{i k_1 sin(phis[r]) d} (sec. 2) and so
+ * its own layer factorisation; every coefficient vector of such a context is
+ * angle-major, [n_rhs][M][2P+1].  n_rhs 0 or 1: the single angle phi. */
 typedef struct {
   double omega;
   double phi;
   int P;
+  int64_t n_rhs;
+  const double* phis;
 } grt_incidence;
 
 typedef struct {
@@ -129,6 +135,7 @@ typedef struct {
                        per target                                             */
   int cx_chunks;    /* source chunks of the C x launch                       */
   int bx_chunks;    /* node chunks of the B_phys w (P2L) launch              */
+  int64_t n_rhs;    /* right-hand sides (angles); vectors hold n_rhs * n_beta  */
 } grt_sizes;
 
 /* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
@@ -148,15 +155,28 @@ grt_status grt_set_problem(grt_ctx* ctx, const grt_layers* lay, const grt_inclus
  * truncated pseudo-inverse factors (eq. applypA), the L2L table and f (eq. Arhs). */
 grt_status grt_build(grt_ctx* ctx);
 
+/* Build only what the translation needs (sec. 4.1 Mie diagonal S, the normalisation
+ * D = |H_|n|(k2 r)|, the H_0/H_1 table, the translation's workspace), not the layered
+ * structure (no A, no SVD).  Afterwards grt_apply_ST_block (any n_rhs), grt_apply_T
+ * (n_rhs = 1), grt_set_launch and grt_query work; every call that needs the layers
+ * returns GRT_ESTATE until grt_build (which then builds the rest from scratch).  For
+ * uses of the translation alone, e.g. timing it at sizes where factorising the layers
+ * of every angle would take far longer than the applies. */
+grt_status grt_build_translation(grt_ctx* ctx);
+
 grt_status grt_query(const grt_ctx* ctx, grt_sizes* out);
 
 /* y = K x with K = I - S T + S B_phys A^+ C, the left-preconditioned Schur
- * operator of sec. 5 (B_phys = -B of the paper).  x, y: device [M][2P+1] complex
- * FP64, may not alias.  precision GRT_FP64: everything in FP64.  GRT_FP32: the
- * translation T between inclusion pairs whose scaled distance k2*rho keeps every
- * H_q, q <= 2P, inside the FP32 range runs in FP32 with FP32 accumulation (the
- * Hankel generator itself is FP64); the remaining near pairs, the layer
- * correction and the preconditioner stay FP64. */
+ * operator of sec. 5 (B_phys = -B of the paper).  x, y: device [n_rhs][M][2P+1]
+ * complex FP64 (each angle's own K), may not alias.  precision GRT_FP64:
+ * everything in FP64.  GRT_FP32 with one right-hand side: the translation T between
+ * inclusion pairs whose scaled distance k2*rho keeps every H_q, q <= 2P, inside the
+ * FP32 range runs in FP32 with FP32 accumulation (the Hankel generator itself is
+ * FP64); the remaining near pairs, the layer correction and the preconditioner stay
+ * FP64.  GRT_FP32 with n_rhs >= 2: S T of all angles at once as one complex GEMM on
+ * the FP32 matrix cores (grt_apply_ST_block), every pair included (in the basis
+ * normalised by D = |H_|n|(k2 r)| its entries are at most of order one); the layer
+ * correction of each angle in FP64. */
 grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision);
 
 /* Resident translation table (FP64 applies).  The Toeplitz generator of every
@@ -215,6 +235,16 @@ grt_status grt_table_bytes(const grt_ctx* ctx, int64_t* bytes);
 grt_status grt_apply_T(grt_ctx* ctx, const void* x_dev, void* y_dev);
 grt_status grt_apply_lowrank(grt_ctx* ctx, const void* x_dev, void* y_dev);
 
+/* y_r = S T_r x_r for every right-hand side r (any n_rhs >= 1), the translation of
+ * sec. 4.2 with the Bloch phase alpha_r = e^{i kappa_r d} of each angle on the near
+ * copies (eq. repre3_mod), computed as one complex GEMM per target on the FP32
+ * matrix cores (v_mfma_f32_16x16x4f32): A_j[n, (m, l, nu)] = D_j[n] s_j[n]
+ * tau^{(jml)}_{nu - n} / D_m[nu] generated in FP64 from the Hankel recurrence and
+ * rounded to FP32, B[(m, l, nu), r] = alpha_r^l (D x_r)_m[nu] in FP32, FP32
+ * accumulation.  Same layout as grt_apply; allocates its packed buffers on the
+ * first call (M (2P+1) R_64 complex FP32 each, R_64 = n_rhs rounded up to 64). */
+grt_status grt_apply_ST_block(grt_ctx* ctx, const void* x_dev, void* y_dev);
+
 /* b = S B_phys A^+ f, the right-hand side of the reduced system (device). */
 grt_status grt_rhs(grt_ctx* ctx, void* b_dev);
 
@@ -224,20 +254,27 @@ grt_status grt_incident(grt_ctx* ctx, void* a_dev);
 
 /* Solve K beta = b by restarted GMRES in FP64 on the device (sec. 5).  beta_dev
  * (device) receives the solution; with opts->use_x0 it holds the initial guess
- * on entry.  GRT_ENOCONV if tol is not reached (beta and stats still written). */
+ * on entry.  GRT_ENOCONV if tol is not reached (beta and stats still written).
+ * n_rhs >= 2: every angle's system, [n_rhs][M][2P+1], solved in lockstep as one
+ * batch (each angle keeps its own Krylov space: the operators differ by the Bloch
+ * phase); stats must then hold n_rhs entries (or be NULL); GRT_FP32 runs the FP64
+ * refinement of every angle around inner solves whose translation is the FP32
+ * matrix-core block product of all angles. */
 grt_status grt_solve(grt_ctx* ctx, const grt_solve_opts* opts, void* beta_dev,
                      grt_solve_stats* stats);
 
-/* Bragg amplitudes (sec. 2 eq. rad1/rad2, sec. 6): from beta (device) form
+/* Bragg amplitudes (sec. 2 eq. rad1/rad2, sec. 6) of right-hand side rhs (0 ..
+ * n_rhs - 1): from beta (device, that angle's [M][2P+1] vector) form
  * alpha = A^+ (f - C beta) and return, for each of the Nrb orders (host arrays of
  * length >= Nrb): orders[i], c[2i..2i+1], d[2i..2i+1] (re, im), the reflected and
  * transmitted energy fractions R[i], T[i] (zero for evanescent orders) and the
- * flux error |sum R + sum T - 1|. */
-grt_status grt_bragg(grt_ctx* ctx, const void* beta_dev, int64_t cap, int* orders, double* c,
-                     double* d, double* R, double* T, double* flux_err);
+ * flux error |sum R + sum T - 1|.  GRT_EINVAL for rhs out of range. */
+grt_status grt_bragg(grt_ctx* ctx, int64_t rhs, const void* beta_dev, int64_t cap, int* orders,
+                     double* c, double* d, double* R, double* T, double* flux_err);
 
-/* The total field at n_pts points (host xy[2 i], xy[2 i + 1]) for the solution beta
- * (device, [M][2P+1]; ignored when M = 0), written to host u[2 i], u[2 i + 1] (re, im).
+/* The total field of right-hand side rhs at n_pts points (host xy[2 i], xy[2 i + 1])
+ * for its solution beta (device, that angle's [M][2P+1] vector; ignored when M = 0),
+ * written to host u[2 i], u[2 i + 1] (re, im).
  * The representation of sec. 3 (eqs. repre1-repre3) and sec. 5 (eq. repre3_mod): in
  * each truncated layer the three near copies of the interface layer potentials (the
  * trapezoid sums over the nodes the method solves with), the layer's J expansion,
@@ -254,11 +291,11 @@ grt_status grt_bragg(grt_ctx* ctx, const void* beta_dev, int64_t cap, int* order
  * the context stream.  GRT_EINVAL for null arrays or coordinates that are not finite
  * or exceed 1e6 in size,
  * GRT_ESTATE before grt_build. */
-grt_status grt_eval_field(grt_ctx* ctx, const void* beta_dev, int64_t n_pts, const double* xy,
-                          double* u);
+grt_status grt_eval_field(grt_ctx* ctx, int64_t rhs, const void* beta_dev, int64_t n_pts,
+                          const double* xy, double* u);
 
 /* Copy the equilibrated matrix A (column-major [n_alpha][n_rows] complex) and its
- * column scales to host buffers (diagnostics / tests). */
+ * column scales to host buffers (diagnostics / tests; the first angle's). */
 grt_status grt_get_A(grt_ctx* ctx, double* A_host, double* colscale_host);
 
 /* Copy the Mie diagonal [M][2P+1] complex to a host buffer (diagnostics / tests). */
@@ -314,7 +351,8 @@ typedef struct grt_batch grt_batch;
  * of table mode on one of them grt_batch_solve returns GRT_ESTATE (make a new
  * batch).  hip_stream: stream to run on, or NULL for a private one.
  * GRT_ESTATE if a context is not built, has no inclusions or is on another
- * device; GRT_EINVAL for n <= 0, NULL arrays or a context listed twice (every
+ * device; GRT_EINVAL for n <= 0, NULL arrays, a context with n_rhs >= 2 (grt_solve
+ * batches its angles itself) or a context listed twice (every
  * instance writes its own context's scratch buffers during a lockstep step, so the
  * contexts of one batch must be distinct). */
 grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, void* hip_stream);
@@ -382,7 +420,8 @@ grt_status grt_nn_num_params(const grt_nn* nn, int64_t* n);
 grt_status grt_nn_set_params(grt_nn* nn, const float* host, int64_t count);
 grt_status grt_nn_get_params(grt_nn* nn, float* host, int64_t count);
 
-/* Build the graph and inputs of a built context (M >= 1) and keep them on the
+/* Build the graph and inputs of a built context (M >= 1, one angle: GRT_EUNSUP for
+ * n_rhs >= 2) and keep them on the
  * device as a sample; with beta_dev (its solution, device) also the training target.
  * The context may be destroyed afterwards.  *id receives the sample's index. */
 grt_status grt_nn_add_sample(grt_nn* nn, grt_ctx* ctx, const void* beta_dev, int* id);

@@ -564,6 +564,10 @@ struct grt_batch {
   std::vector<int> act;         // the flags as last sent to the descriptors
   double* h_pinned = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // angles of one geometry (a context with several right-hand sides): the mixed
+  // apply translates all of them at once on the owner's FP32 matrix-core product
+  grt_ctx* block_owner = nullptr;
+  int64_t block_stride = 0;   // distance between consecutive instances' vectors
 };
 
 static grt_status bset(grt_batch* b, grt_status s, const std::string& m) {
@@ -640,6 +644,30 @@ static grt_status batch_lowrank(grt_batch* b, int use_f) {
   return GRT_OK;
 }
 
+// The mixed apply of a block of angles, Y = D x - Yb + D s B x, with Yb = D S T D^{-1}
+// (D x) from the matrix-core product (column r = instance r).
+__global__ void __launch_bounds__(BT) combine_block_batched(const InstDesc* __restrict__ D,
+                                                            const int* __restrict__ seg2inst,
+                                                            const cd* __restrict__ X,
+                                                            const double* __restrict__ dn,
+                                                            const cf* __restrict__ Yb, int Rp,
+                                                            cd* Y) {
+  const int seg = blockIdx.x;
+  const int inst = seg2inst[seg];
+  const InstDesc& q = D[inst];
+  for (int r = 0; r < SEG / BT; ++r) {
+    const int64_t i = (int64_t)seg * SEG + r * BT + threadIdx.x;
+    const int64_t loc = i - q.off;
+    if (loc >= q.nbeta || !q.active) {
+      Y[i] = cd{0.0, 0.0};
+      continue;
+    }
+    const cd b = q.pL[loc] + chunks_sum(q.pB, q.b_nchunks, q.nbeta, loc);
+    const cf t = Yb[(size_t)loc * Rp + inst];
+    Y[i] = dn[i] * (X[i] + q.mie[loc] * b) - cd{t.r, t.i};
+  }
+}
+
 // wout = D K D^{-1} x for every problem, x = D^{-1} xh already in xtmp (both fixed
 // buffers of the batch, so the whole launch sequence can be captured once as a HIP
 // graph and replayed; see batch_apply).
@@ -647,6 +675,18 @@ static grt_status batch_lowrank(grt_batch* b, int use_f) {
 // accumulation) and of near pairs in FP64; C x, A^+ and B_phys w in FP64 as always.
 static grt_status batch_apply_core(grt_batch* b, bool mixed) {
   hipStream_t s = b->stream;
+  if (mixed && b->block_owner) {
+    grt_ctx* o = b->block_owner;
+    grt_status st = block_product(o, b->xtmp, b->block_stride, o->d_dnorm, b->B, s);
+    if (st != GRT_OK) return bset(b, st, "block translation: " + o->err);
+    for (auto& gp : b->groups) BATCH_P_DISPATCH(launch_group_C, gp.P, b, gp, b->xtmp);
+    if (b->n_cxr) cxr_batched<<<b->n_cxr, 256, 0, s>>>(b->dd, b->it_cxr);
+    BTRY(batch_lowrank(b, 0));
+    combine_block_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, b->xtmp, b->d_dnorm,
+                                                 o->d_blkY, o->blk_Rp, b->wout);
+    BHIP(b, hipGetLastError());
+    return GRT_OK;
+  }
   if (mixed) {
     const unsigned gn = (unsigned)((b->ntot + BT - 1) / BT);
     ew_to32_kernel<<<gn, BT, 0, s>>>(b->xtmp, b->x32, b->ntot);
@@ -902,9 +942,27 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
   return GRT_OK;
 }
 
-extern "C" {
+static grt_status batch_create_impl(grt_batch** out, int64_t n, grt_ctx* const* ctxs,
+                                    void* hip_stream);
 
-grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, void* hip_stream) {
+grt_status batch_create_internal(grt_batch** out, int64_t n, grt_ctx* const* ctxs,
+                                 void* hip_stream) {
+  return batch_create_impl(out, n, ctxs, hip_stream);
+}
+
+grt_status batch_set_block(grt_batch* b, grt_ctx* owner) {
+  if (!b || !owner || (int64_t)b->B != owner->n_rhs) return GRT_EINVAL;
+  const int64_t stride = b->B > 1 ? b->hd[1].off - b->hd[0].off : 0;
+  for (int i = 0; i < b->B; ++i)
+    if (b->hd[i].off != i * stride || b->hd[i].M != b->hd[0].M || b->hd[i].P != b->hd[0].P)
+      return bset(b, GRT_EINVAL, "block instances must share the geometry and the layout");
+  b->block_owner = owner;
+  b->block_stride = stride;
+  return GRT_OK;
+}
+
+static grt_status batch_create_impl(grt_batch** out, int64_t n, grt_ctx* const* ctxs,
+                                    void* hip_stream) {
   if (!out || n <= 0 || !ctxs) return GRT_EINVAL;
   *out = nullptr;
   grt_batch* b = new (std::nothrow) grt_batch();
@@ -1085,6 +1143,15 @@ grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, vo
   }
   *out = b;
   return GRT_OK;
+}
+
+extern "C" {
+
+grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, void* hip_stream) {
+  if (!out || n <= 0 || !ctxs) return GRT_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (ctxs[i] && ctxs[i]->n_rhs > 1) return GRT_EINVAL;   // its solves batch its angles
+  return batch_create_impl(out, n, ctxs, hip_stream);
 }
 
 grt_status grt_batch_destroy(grt_batch* b) {

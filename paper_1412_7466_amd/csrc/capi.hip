@@ -26,6 +26,16 @@ namespace {
 void free_all(grt_ctx* c) {
   graph_reset(c);
   ++c->gen;
+  if (c->rhs_batch) {
+    grt_batch_destroy(c->rhs_batch);
+    c->rhs_batch = nullptr;
+  }
+  for (void* p : {(void*)c->d_blkX, (void*)c->d_blkY, (void*)c->d_blkph, (void*)c->d_blkw})
+    if (p) hipFree(p);
+  c->d_blkX = c->d_blkY = nullptr;
+  c->d_blkph = nullptr;
+  c->d_blkw = nullptr;
+  c->blk_Rp = 0;
   if (c->lf) {  // layer-side buffers belong to the shared factors
     c->d_yw = c->d_colscale = c->d_sv = c->d_htab = nullptr;
     c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_f = nullptr;
@@ -59,9 +69,20 @@ void free_all(grt_ctx* c) {
   c->d_wtmp = nullptr;
   c->krylov_restart = 0;
   c->built = false;
+  c->trans_built = false;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+// context of right-hand side r (r = 0: this one)
+grt_ctx* rhs_ctx(grt_ctx* c, int64_t r) { return r == 0 ? c : c->rhs[(size_t)r - 1]; }
+
+void destroy_rhs(grt_ctx* c, size_t keep) {
+  while (c->rhs.size() > keep) {
+    grt_destroy(c->rhs.back());
+    c->rhs.pop_back();
+  }
+}
 
 }  // namespace
 
@@ -98,6 +119,7 @@ grt_status grt_destroy(grt_ctx* c) {
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
   free_all(c);
+  destroy_rhs(c, 0);
   for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
   for (hipEvent_t e : c->ev_res)
     if (e) hipEventDestroy(e);
@@ -140,8 +162,15 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
   if (L.Nu < 1 || L.Nrb < 1 || L.Nrb > 100000) return set_err(c, GRT_EINVAL, "bad Nu / Nrb");
   if (!(L.pinv_eps > 0 && L.pinv_eps < 1)) return set_err(c, GRT_EINVAL, "pinv_eps must be in (0, 1)");
   if (!finite_pos(wave->omega)) return set_err(c, GRT_EINVAL, "omega must be > 0");
-  if (!std::isfinite(wave->phi) || std::fabs(wave->phi) >= M_PI / 2)
-    return set_err(c, GRT_EINVAL, "|phi| must be < pi/2");
+  const int64_t R = wave->n_rhs > 1 ? wave->n_rhs : 1;
+  if (wave->n_rhs < 0 || R > 65536) return set_err(c, GRT_EINVAL, "n_rhs must be in [0, 65536]");
+  if (R > 1 && !wave->phis) return set_err(c, GRT_EINVAL, "n_rhs > 1 needs phis");
+  const double phi0 = R > 1 ? wave->phis[0] : wave->phi;
+  for (int64_t r = 0; r < R; ++r) {
+    const double ph = R > 1 ? wave->phis[r] : wave->phi;
+    if (!std::isfinite(ph) || std::fabs(ph) >= M_PI / 2)
+      return set_err(c, GRT_EINVAL, "|phi| must be < pi/2");
+  }
   if (wave->P < 1 || wave->P > 40) return set_err(c, GRT_EINVAL, "P must be in [1, 40]");
   if (!supported_P(wave->P)) return set_err(c, GRT_EUNSUP, "multipole order P not compiled in");
   const int64_t M = inc->M;
@@ -196,6 +225,9 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
   }
   c->lay = L;
   c->inc = *wave;
+  c->inc.phi = phi0;
+  c->inc.n_rhs = 0;
+  c->inc.phis = nullptr;
   c->M = M;
   c->P = wave->P;
   c->nb = 2 * wave->P + 1;
@@ -212,7 +244,7 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
     g.Nw[l] = L.Nw[l];
     g.Q[l] = L.Q[l];
   }
-  g.kappa = g.k[0] * std::sin(wave->phi);
+  g.kappa = g.k[0] * std::sin(phi0);
   g.alpha = cd{std::cos(g.kappa * L.d), std::sin(g.kappa * L.d)};
   g.alpha_inv = cd{g.alpha.r, -g.alpha.i};
   g.N = L.N;
@@ -237,15 +269,33 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
   g.n_alpha = g.col_off[CB_COUNT];
   c->n_g = g.row_off[RB_W1V];
   c->n_b = g.col_off[CB_A1];
+  // the other angles: contexts of their own on the same device and stream
+  c->n_rhs = R;
+  c->phis.clear();
+  if (R > 1) c->phis.assign(wave->phis, wave->phis + R);
+  destroy_rhs(c, (size_t)(R - 1));
+  for (int64_t r = 1; r < R; ++r) {
+    if ((size_t)r > c->rhs.size()) {
+      grt_ctx* sub = nullptr;
+      grt_status st = grt_create(&sub, c->device, c->stream);
+      if (st != GRT_OK) return set_err(c, st, "creating the context of an angle failed");
+      sub->want_table = c->want_table;
+      sub->table_lanes = c->table_lanes;
+      c->rhs.push_back(sub);
+    }
+    grt_incidence w1 = *wave;
+    w1.phi = wave->phis[r];
+    w1.n_rhs = 0;
+    w1.phis = nullptr;
+    grt_status st = grt_set_problem(c->rhs[(size_t)r - 1], lay, inc, &w1);
+    if (st != GRT_OK) return set_err(c, st, std::string("angle ") + std::to_string(r) + ": " +
+                                                c->rhs[(size_t)r - 1]->err);
+  }
   c->have_problem = true;
   return GRT_OK;
 }
 
-grt_status grt_build(grt_ctx* c) {
-  GRT_CHECK_CTX(c);
-  if (!c->have_problem) return set_err(c, GRT_ESTATE, "set_problem first");
-  GRT_HIP(c, hipSetDevice(c->device));
-  if (c->built) return GRT_OK;
+static grt_status upload_inclusions(grt_ctx* c) {
   const int64_t M = c->M;
   if (M > 0) {
     std::vector<double> kp(M);
@@ -259,13 +309,44 @@ grt_status grt_build(grt_ctx* c) {
     GRT_HIP(c, hipMemcpy(c->d_rad, c->hr.data(), sizeof(double) * M, hipMemcpyHostToDevice));
     GRT_HIP(c, hipMemcpy(c->d_kp, kp.data(), sizeof(double) * M, hipMemcpyHostToDevice));
   }
-  grt_status st = setup_build(c);
+  return GRT_OK;
+}
+
+grt_status grt_build_translation(grt_ctx* c) {
+  GRT_CHECK_CTX(c);
+  if (!c->have_problem) return set_err(c, GRT_ESTATE, "set_problem first");
+  GRT_HIP(c, hipSetDevice(c->device));
+  if (c->built || c->trans_built) return GRT_OK;
+  grt_status st = upload_inclusions(c);
+  if (st == GRT_OK) st = setup_translation(c);
+  if (st == GRT_OK) st = apply_alloc(c);
+  if (st != GRT_OK) {
+    free_all(c);
+    return st;
+  }
+  c->trans_built = true;
+  return GRT_OK;
+}
+
+grt_status grt_build(grt_ctx* c) {
+  GRT_CHECK_CTX(c);
+  if (!c->have_problem) return set_err(c, GRT_ESTATE, "set_problem first");
+  GRT_HIP(c, hipSetDevice(c->device));
+  if (c->built) return GRT_OK;
+  if (c->trans_built) free_all(c);   // start again with the layered structure
+  grt_status st = upload_inclusions(c);
+  if (st != GRT_OK) return st;
+  st = setup_build(c);
   if (st != GRT_OK) return st;
   st = apply_alloc(c);
   if (st != GRT_OK) return st;
   if (c->want_table) {
     st = table_set(c, true);
     if (st != GRT_OK) return st;
+  }
+  for (grt_ctx* sub : c->rhs) {
+    st = grt_build(sub);
+    if (st != GRT_OK) return set_err(c, st, "building an angle: " + sub->err);
   }
   c->built = true;
   return GRT_OK;
@@ -274,6 +355,10 @@ grt_status grt_build(grt_ctx* c) {
 grt_status grt_set_table(grt_ctx* c, int mode) {
   GRT_CHECK_CTX(c);
   if (mode < 0 || mode > 2) return set_err(c, GRT_EINVAL, "table mode must be 0, 1 or 2");
+  for (grt_ctx* sub : c->rhs) {
+    grt_status st = grt_set_table(sub, mode);
+    if (st != GRT_OK) return set_err(c, st, "angle: " + sub->err);
+  }
   c->want_table = mode != 0;
   c->table_lanes = mode == 2 ? 2 : 1;
   if (!c->built) return GRT_OK;
@@ -297,16 +382,64 @@ grt_status grt_query(const grt_ctx* c, grt_sizes* out) {
   out->n_alpha = c->g.n_alpha;
   out->rank = c->built ? c->rank : 0;
   out->Nrb = c->g.Nrb;
-  out->m2l_chunks = c->built ? c->m2l_nchunks : 0;
+  out->m2l_chunks = (c->built || c->trans_built) ? c->m2l_nchunks : 0;
   out->m2l_split = !c->built ? 0 : c->d_table ? c->table_lanes : c->m2l_split;
   out->cx_chunks = c->built ? c->c_nchunks : 0;
   out->bx_chunks = c->built ? c->b_nchunks : 0;
+  out->n_rhs = c->n_rhs;
   return GRT_OK;
 }
 
 static grt_status check_built(grt_ctx* c) {
-  if (!c->built) return set_err(c, GRT_ESTATE, "build first");
+  if (!c->built)
+    return set_err(c, GRT_ESTATE, c->trans_built ? "translation-only build: grt_build first"
+                                                 : "build first");
   GRT_HIP(c, hipSetDevice(c->device));
+  return GRT_OK;
+}
+
+// Calls that need only the translation data (grt_build or grt_build_translation).
+static grt_status check_translation(grt_ctx* c) {
+  if (!c->built && !c->trans_built) return set_err(c, GRT_ESTATE, "build first");
+  GRT_HIP(c, hipSetDevice(c->device));
+  return GRT_OK;
+}
+
+extern "C++" {
+// Run fn(context of angle r, offset of its vectors) for every right-hand side.
+template <typename F>
+static grt_status for_each_rhs(grt_ctx* c, F fn) {
+  for (int64_t r = 0; r < c->n_rhs; ++r) {
+    grt_ctx* cr = rhs_ctx(c, r);
+    grt_status st = fn(cr, r * c->n_beta);
+    if (st != GRT_OK) return cr == c ? st : set_err(c, st, "angle " + std::to_string(r) + ": " + cr->err);
+  }
+  return GRT_OK;
+}
+}  // extern "C++"
+
+// Phases alpha_r of every angle and the block buffers for them.
+static grt_status block_ready(grt_ctx* c) {
+  std::vector<cd> al((size_t)c->n_rhs);
+  for (int64_t r = 0; r < c->n_rhs; ++r) al[(size_t)r] = rhs_ctx(c, r)->g.alpha;
+  return block_prepare(c, (int)c->n_rhs, al.data());
+}
+
+// y_r = K_r x_r for every angle with the translation of all angles at once on the
+// FP32 matrix cores; the layer correction of each angle in FP64.
+static grt_status apply_K_block(grt_ctx* c, const cd* x, cd* y) {
+  const int R = (int)c->n_rhs;
+  grt_status st = block_ready(c);
+  if (st != GRT_OK) return st;
+  if (!c->d_blkw) GRT_HIP(c, hipMalloc(&c->d_blkw, sizeof(cd) * (size_t)c->n_beta * R));
+  st = block_product(c, x, c->n_beta, c->d_dnorm, R, c->stream);
+  if (st != GRT_OK) return st;
+  st = for_each_rhs(c, [&](grt_ctx* cr, int64_t off) {
+    return apply_lowrank_only(cr, x + off, c->d_blkw + off);
+  });
+  if (st != GRT_OK) return st;
+  block_combine(c, x, c->d_blkw, R, y, c->stream);
+  GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
 
@@ -315,18 +448,42 @@ grt_status grt_apply(grt_ctx* c, const void* x, void* y, int precision) {
   grt_status st = check_built(c);
   if (st != GRT_OK) return st;
   if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
-  if (precision == GRT_FP64) return apply_K(c, static_cast<const cd*>(x), static_cast<cd*>(y));
-  if (precision == GRT_FP32)
-    return apply_K_mixed(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+  const cd* xc = static_cast<const cd*>(x);
+  cd* yc = static_cast<cd*>(y);
+  if (precision == GRT_FP64)
+    return for_each_rhs(c, [&](grt_ctx* cr, int64_t off) { return apply_K(cr, xc + off, yc + off); });
+  if (precision == GRT_FP32) {
+    if (c->n_rhs > 1 && c->M > 0) return apply_K_block(c, xc, yc);
+    return apply_K_mixed(c, xc, yc);
+  }
   return set_err(c, GRT_EINVAL, "precision must be GRT_FP64 or GRT_FP32");
 }
 
 grt_status grt_apply_T(grt_ctx* c, const void* x, void* y) {
   GRT_CHECK_CTX(c);
-  grt_status st = check_built(c);
+  grt_status st = check_translation(c);
+  if (st != GRT_OK) return st;
+  if (!c->built && c->n_rhs > 1)
+    return set_err(c, GRT_ESTATE, "translation-only build with several angles: use grt_apply_ST_block");
+  if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
+  const cd* xc = static_cast<const cd*>(x);
+  cd* yc = static_cast<cd*>(y);
+  return for_each_rhs(c, [&](grt_ctx* cr, int64_t off) { return apply_T_only(cr, xc + off, yc + off); });
+}
+
+grt_status grt_apply_ST_block(grt_ctx* c, const void* x, void* y) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_translation(c);
   if (st != GRT_OK) return st;
   if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
-  return apply_T_only(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+  if (c->M == 0) return GRT_OK;
+  st = block_ready(c);
+  if (st != GRT_OK) return st;
+  st = block_product(c, static_cast<const cd*>(x), c->n_beta, c->d_dnorm, (int)c->n_rhs, c->stream);
+  if (st != GRT_OK) return st;
+  block_unpack(c, (int)c->n_rhs, static_cast<cd*>(y), c->stream);
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
 }
 
 grt_status grt_apply_lowrank(grt_ctx* c, const void* x, void* y) {
@@ -334,7 +491,11 @@ grt_status grt_apply_lowrank(grt_ctx* c, const void* x, void* y) {
   grt_status st = check_built(c);
   if (st != GRT_OK) return st;
   if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
-  return apply_lowrank_only(c, static_cast<const cd*>(x), static_cast<cd*>(y));
+  const cd* xc = static_cast<const cd*>(x);
+  cd* yc = static_cast<cd*>(y);
+  return for_each_rhs(c, [&](grt_ctx* cr, int64_t off) {
+    return apply_lowrank_only(cr, xc + off, yc + off);
+  });
 }
 
 grt_status grt_rhs(grt_ctx* c, void* b) {
@@ -342,7 +503,8 @@ grt_status grt_rhs(grt_ctx* c, void* b) {
   grt_status st = check_built(c);
   if (st != GRT_OK) return st;
   if (!b) return set_err(c, GRT_EINVAL, "null vector");
-  return rhs_b(c, static_cast<cd*>(b));
+  cd* bc = static_cast<cd*>(b);
+  return for_each_rhs(c, [&](grt_ctx* cr, int64_t off) { return rhs_b(cr, bc + off); });
 }
 
 grt_status grt_set_overlap(grt_ctx* c, int on) {
@@ -356,12 +518,16 @@ grt_status grt_set_overlap(grt_ctx* c, int on) {
   }
   c->overlap = on != 0;
   graph_reset(c);
+  for (grt_ctx* sub : c->rhs) {
+    grt_status st = grt_set_overlap(sub, on);
+    if (st != GRT_OK) return set_err(c, st, "angle: " + sub->err);
+  }
   return GRT_OK;
 }
 
 grt_status grt_set_launch(grt_ctx* c, int m2l_chunks, int m2l_split) {
   GRT_CHECK_CTX(c);
-  grt_status st = check_built(c);
+  grt_status st = check_translation(c);
   if (st != GRT_OK) return st;
   if (m2l_split != 1 && m2l_split != 2) return set_err(c, GRT_EINVAL, "split must be 1 or 2");
   if (c->M == 0) return GRT_OK;
@@ -376,6 +542,12 @@ grt_status grt_set_launch(grt_ctx* c, int m2l_chunks, int m2l_split) {
   else
     c->m2l_split = m2l_split;
   graph_reset(c);
+  ++c->gen;   // a batch made earlier holds the old launch shape
+  for (grt_ctx* sub : c->rhs) {
+    if (!sub->built) continue;
+    grt_status st2 = grt_set_launch(sub, m2l_chunks, m2l_split);
+    if (st2 != GRT_OK) return set_err(c, st2, "angle: " + sub->err);
+  }
   return GRT_OK;
 }
 
@@ -386,7 +558,23 @@ grt_status grt_autotune(grt_ctx* c, int cap, int* n, int* chunks, int* splits, d
   if (cap < 0 || (cap > 0 && (!chunks || !ms))) return set_err(c, GRT_EINVAL, "bad arrays");
   st = autotune_m2l(c, cap, n, chunks, splits, ms);
   if (st != GRT_OK) return st;
-  return autotune_coupling(c);
+  st = autotune_coupling(c);
+  if (st != GRT_OK) return st;
+  // the other angles share the geometry: they take the same launch shapes
+  for (grt_ctx* sub : c->rhs) {
+    sub->m2l_chunk = c->m2l_chunk;
+    sub->m2l_nchunks = c->m2l_nchunks;
+    sub->m2l_split = c->m2l_split;
+    sub->table_lanes = c->table_lanes;
+    sub->c_chunk = c->c_chunk;
+    sub->c_nchunks = c->c_nchunks;
+    sub->b_chunk = c->b_chunk;
+    sub->b_nchunks = c->b_nchunks;
+    graph_reset(sub);
+    ++sub->gen;
+  }
+  ++c->gen;
+  return GRT_OK;
 }
 
 grt_status grt_incident(grt_ctx* c, void* a) {
@@ -394,7 +582,45 @@ grt_status grt_incident(grt_ctx* c, void* a) {
   grt_status st = check_built(c);
   if (st != GRT_OK) return st;
   if (!a) return set_err(c, GRT_EINVAL, "null vector");
-  return incident_alpha(c, static_cast<cd*>(a));
+  cd* ac = static_cast<cd*>(a);
+  return for_each_rhs(c, [&](grt_ctx* cr, int64_t off) { return incident_alpha(cr, ac + off); });
+}
+
+// Every angle of a context with several right-hand sides: one lockstep batch over the
+// angles' contexts (FP32 precision translates all angles at once on the matrix cores).
+static grt_status solve_block(grt_ctx* c, const grt_solve_opts* o, cd* beta,
+                              grt_solve_stats* stats) {
+  const int64_t R = c->n_rhs;
+  std::vector<grt_ctx*> list((size_t)R);
+  std::vector<void*> ptrs((size_t)R);
+  for (int64_t r = 0; r < R; ++r) {
+    list[(size_t)r] = rhs_ctx(c, r);
+    ptrs[(size_t)r] = beta + r * c->n_beta;
+  }
+  std::vector<grt_solve_stats> tmp((size_t)R);
+  grt_solve_stats* sp = stats ? stats : tmp.data();
+  grt_status st = GRT_OK;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (!c->rhs_batch) {
+      st = batch_create_internal(&c->rhs_batch, R, list.data(), c->stream);
+      if (st != GRT_OK) return set_err(c, st, "batch of the angles could not be made");
+      st = batch_set_block(c->rhs_batch, c);
+      if (st != GRT_OK) return set_err(c, st, grt_batch_error_message(c->rhs_batch));
+    }
+    if (o->precision == GRT_FP32) {
+      st = block_ready(c);
+      if (st != GRT_OK) return st;
+    }
+    st = grt_batch_solve(c->rhs_batch, o, ptrs.data(), sp);
+    if (st == GRT_ESTATE && attempt == 0) {   // an angle changed since the batch was made
+      grt_batch_destroy(c->rhs_batch);
+      c->rhs_batch = nullptr;
+      continue;
+    }
+    break;
+  }
+  if (st != GRT_OK) set_err(c, st, grt_batch_error_message(c->rhs_batch));
+  return st;
 }
 
 grt_status grt_solve(grt_ctx* c, const grt_solve_opts* o, void* beta, grt_solve_stats* stats) {
@@ -408,9 +634,10 @@ grt_status grt_solve(grt_ctx* c, const grt_solve_opts* o, void* beta, grt_solve_
   grt_solve_stats tmp{};
   grt_solve_stats* sp = stats ? stats : &tmp;
   if (c->M == 0) {
-    *sp = grt_solve_stats{};
+    for (int64_t r = 0; r < (stats ? c->n_rhs : 1); ++r) sp[r] = grt_solve_stats{};
     return GRT_OK;
   }
+  if (c->n_rhs > 1) return solve_block(c, o, static_cast<cd*>(beta), stats);
   return gmres_solve(c, o, static_cast<cd*>(beta), sp);
 }
 
@@ -434,11 +661,17 @@ __global__ void bragg_finish_kernel(DevGeom g, double k1cos, const cd* cdv, doub
 }
 }  // namespace
 
-grt_status grt_bragg(grt_ctx* c, const void* beta, int64_t cap, int* orders, double* cc,
-                     double* dd, double* R, double* T, double* flux_err) {
-  GRT_CHECK_CTX(c);
-  grt_status st = check_built(c);
+grt_status grt_bragg(grt_ctx* c0, int64_t rhs, const void* beta, int64_t cap, int* orders,
+                     double* cc, double* dd, double* R, double* T, double* flux_err) {
+  GRT_CHECK_CTX(c0);
+  grt_status st = check_built(c0);
   if (st != GRT_OK) return st;
+  if (rhs < 0 || rhs >= c0->n_rhs) return set_err(c0, GRT_EINVAL, "rhs out of range");
+  grt_ctx* c = rhs_ctx(c0, rhs);
+  if (c != c0) {
+    st = grt_bragg(c, 0, beta, cap, orders, cc, dd, R, T, flux_err);
+    return st == GRT_OK ? st : set_err(c0, st, c->err);
+  }
   const int Nrb = c->g.Nrb;
   if (cap < Nrb || !orders || !cc || !dd || !R || !T || !flux_err)
     return set_err(c, GRT_EINVAL, "output arrays too small or null");

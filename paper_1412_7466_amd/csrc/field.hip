@@ -252,10 +252,17 @@ __global__ void incoming_kernel(int n, const cd* t, const cd* l, const cd* a0, c
 
 }  // namespace
 
-extern "C" grt_status grt_eval_field(grt_ctx* c, const void* beta_dev, int64_t n_pts,
-                                     const double* xy_host, double* u_host) {
-  if (!c) return GRT_EINVAL;
-  if (!c->built) return set_err(c, GRT_ESTATE, "grt_eval_field before grt_build");
+extern "C" grt_status grt_eval_field(grt_ctx* c0, int64_t rhs, const void* beta_dev,
+                                     int64_t n_pts, const double* xy_host, double* u_host) {
+  if (!c0) return GRT_EINVAL;
+  if (!c0->built) return set_err(c0, GRT_ESTATE, "grt_eval_field before grt_build");
+  if (rhs < 0 || rhs >= c0->n_rhs) return set_err(c0, GRT_EINVAL, "rhs out of range");
+  if (rhs > 0) {
+    grt_ctx* cr = c0->rhs[(size_t)rhs - 1];
+    const grt_status st = grt_eval_field(cr, 0, beta_dev, n_pts, xy_host, u_host);
+    return st == GRT_OK ? st : set_err(c0, st, cr->err);
+  }
+  grt_ctx* c = c0;
   if (n_pts < 0 || n_pts > ((int64_t)1 << 30)) return set_err(c, GRT_EINVAL, "bad point count");
   if (n_pts == 0) return GRT_OK;
   if (!xy_host || !u_host) return set_err(c, GRT_EINVAL, "null point or output array");

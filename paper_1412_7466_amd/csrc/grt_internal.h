@@ -44,8 +44,23 @@ struct LayerFactors {
   ~LayerFactors();
 };
 
+struct grt_batch;
+
 struct grt_ctx {
   std::shared_ptr<LayerFactors> lf;  // owns the layer-side buffers below when set
+  // several right-hand sides (incidence angles) on one geometry: this context holds
+  // the first angle, rhs[r - 1] the others (contexts of their own, same device and
+  // stream); solves of all angles run as one lockstep batch
+  int64_t n_rhs = 1;
+  std::vector<double> phis;
+  std::vector<grt_ctx*> rhs;
+  grt_batch* rhs_batch = nullptr;
+  // block translation on matrix cores (FP32): packed inputs, outputs, phases
+  cf* d_blkX = nullptr;     // [M][NBK][blk_Rp]
+  cf* d_blkY = nullptr;     // [M][nb][blk_Rp]
+  cf* d_blkph = nullptr;    // [blk_Rp]
+  int blk_Rp = 0;
+  cd* d_blkw = nullptr;     // [n_rhs][n_beta] low-rank terms of a block apply
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -56,6 +71,7 @@ struct grt_ctx {
   std::string err;
   // problem (host copies)
   bool have_problem = false, built = false;
+  bool trans_built = false;   // grt_build_translation: translation data only, no layers
   grt_layers lay{};
   grt_incidence inc{};
   int64_t M = 0;
@@ -149,6 +165,7 @@ grt_status set_err(grt_ctx* c, grt_status s, const std::string& msg);
 
 // setup (setup.hip)
 grt_status setup_build(grt_ctx* c);
+grt_status setup_translation(grt_ctx* c);   // translation-only build (no layers)
 void launch_gemv_rows(hipStream_t s, const cd* W, const cd* x, cd* y, int rows, int cols);
 // W[i][k] = E[i0 + i] conj(V^H[k][i0 + i]) for i < rows, k < rank: rows of E V
 void launch_build_Wv(hipStream_t s, const grt_ctx* c, int i0, int rows, cd* W);
@@ -173,6 +190,20 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* s
 grt_status autotune_coupling(grt_ctx* c);
 constexpr int M2L_TUNE_MAX_WAVES = 16384;
 size_t table_bytes(const grt_ctx* c);
+
+// block translation of several right-hand sides on FP32 matrix cores (block.hip)
+int block_nbk(int P);
+grt_status block_prepare(grt_ctx* c, int R, const cd* alphas_host);
+grt_status block_product(grt_ctx* c, const cd* x, int64_t ldx, const double* dn, int R,
+                         hipStream_t s);
+void block_combine(grt_ctx* c, const cd* x, const cd* w, int R, cd* y, hipStream_t s);
+void block_unpack(grt_ctx* c, int R, cd* y, hipStream_t s);
+// batch.hip: make the batch's mixed apply use the block translation of `owner` (all
+// instances: one geometry, the owner's angles in order)
+grt_status batch_set_block(grt_batch* b, grt_ctx* owner);
+// grt_batch_create without its refusal of contexts that hold several angles
+grt_status batch_create_internal(grt_batch** out, int64_t n, grt_ctx* const* ctxs,
+                                 void* hip_stream);
 
 // krylov (krylov.hip)
 void graph_reset(grt_ctx* c);   // drop captured applies (their configuration changed)

@@ -645,6 +645,15 @@ grt_status setup_build(grt_ctx* c) {
   return build_inclusions(c);
 }
 
+// Only what the translation needs: the H_0 / H_1 table (the context's own) and the
+// inclusion data (Mie diagonal, normalisation).  No layered structure.
+grt_status setup_translation(grt_ctx* c) {
+  GRT_HIP(c, hipMalloc(&c->d_htab, sizeof(double) * HTAB_SIZE));
+  htab_kernel<<<1, 64, 0, c->stream>>>(c->d_htab);
+  GRT_HIP(c, hipGetLastError());
+  return build_inclusions(c);
+}
+
 static grt_status build_layers(grt_ctx* c) {
   hipStream_t s = c->stream;
   DevGeom& g = c->g;

@@ -35,7 +35,8 @@ class grt_inclusions(C.Structure):
 
 
 class grt_incidence(C.Structure):
-    _fields_ = [("omega", C.c_double), ("phi", C.c_double), ("P", C.c_int)]
+    _fields_ = [("omega", C.c_double), ("phi", C.c_double), ("P", C.c_int),
+                ("n_rhs", C.c_int64), ("phis", C.POINTER(C.c_double))]
 
 
 class grt_solve_opts(C.Structure):
@@ -53,7 +54,7 @@ class grt_sizes(C.Structure):
     _fields_ = [("M", C.c_int64), ("P", C.c_int), ("n_beta", C.c_int64), ("n_rows", C.c_int64),
                 ("n_alpha", C.c_int64), ("rank", C.c_int64), ("Nrb", C.c_int),
                 ("m2l_chunks", C.c_int), ("m2l_split", C.c_int), ("cx_chunks", C.c_int),
-                ("bx_chunks", C.c_int)]
+                ("bx_chunks", C.c_int), ("n_rhs", C.c_int64)]
 
 
 class grt_nn_config(C.Structure):
@@ -69,9 +70,11 @@ _PROTOS = {
     "grt_set_problem": (C.c_int, [_VP, C.POINTER(grt_layers), C.POINTER(grt_inclusions),
                                   C.POINTER(grt_incidence)]),
     "grt_build": (C.c_int, [_VP]),
+    "grt_build_translation": (C.c_int, [_VP]),
     "grt_query": (C.c_int, [_VP, C.POINTER(grt_sizes)]),
     "grt_apply": (C.c_int, [_VP, _VP, _VP, C.c_int]),
     "grt_apply_T": (C.c_int, [_VP, _VP, _VP]),
+    "grt_apply_ST_block": (C.c_int, [_VP, _VP, _VP]),
     "grt_apply_lowrank": (C.c_int, [_VP, _VP, _VP]),
     "grt_rhs": (C.c_int, [_VP, _VP]),
     "grt_incident": (C.c_int, [_VP, _VP]),
@@ -82,10 +85,10 @@ _PROTOS = {
     "grt_autotune": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
-    "grt_bragg": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
+    "grt_bragg": (C.c_int, [_VP, C.c_int64, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                             C.POINTER(C.c_double)]),
-    "grt_eval_field": (C.c_int, [_VP, _VP, C.c_int64, C.POINTER(C.c_double),
+    "grt_eval_field": (C.c_int, [_VP, C.c_int64, _VP, C.c_int64, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),
     "grt_get_A": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "grt_get_mie": (C.c_int, [_VP, C.POINTER(C.c_double)]),
@@ -194,7 +197,9 @@ class Context:
             pass
 
     # -- problem ---------------------------------------------------------------
-    def set_problem(self, pb):
+    def set_problem(self, pb, phis=None):
+        """phis: several incidence angles (right-hand sides) on this geometry; vectors
+        are then [len(phis)][M][2P+1] (flat)."""
         dd = pb.disc
         lay = grt_layers(d=pb.d, h=pb.h, y0=dd.y0, n_layer=(C.c_double * 3)(*pb.n_layer),
                          N=dd.N, Nw=(C.c_int * 3)(*dd.Nw), Q=(C.c_int * 3)(*dd.Q), Nu=dd.Nu,
@@ -204,7 +209,13 @@ class Context:
                       for a in (pb.x, pb.y, pb.radius, pb.n_incl)]
         inc = grt_inclusions(M=pb.M, x=_dptr(self._arrs[0]), y=_dptr(self._arrs[1]),
                              radius=_dptr(self._arrs[2]), n_incl=_dptr(self._arrs[3]))
-        wave = grt_incidence(omega=pb.omega, phi=pb.phi, P=pb.P)
+        if phis is not None and len(phis) > 1:
+            self._phis = np.ascontiguousarray(phis, dtype=np.float64)
+            wave = grt_incidence(omega=pb.omega, phi=float(self._phis[0]), P=pb.P,
+                                 n_rhs=len(self._phis), phis=_dptr(self._phis))
+        else:
+            wave = grt_incidence(omega=pb.omega, phi=pb.phi if phis is None else float(phis[0]),
+                                 P=pb.P, n_rhs=0, phis=None)
         self._check(self.lib.grt_set_problem(self.h, C.byref(lay), C.byref(inc), C.byref(wave)))
         self.pb = pb
         self.sizes = self.query()
@@ -215,18 +226,31 @@ class Context:
         self._leave()
         self.sizes = self.query()
 
+    def build_translation(self):
+        """Translation data only (no layered structure): apply_ST_block, apply_T."""
+        self._enter()
+        self._check(self.lib.grt_build_translation(self.h))
+        self._leave()
+        self.sizes = self.query()
+
     def query(self):
         s = grt_sizes()
         self._check(self.lib.grt_query(self.h, C.byref(s)))
         return s
 
-    def new_vec(self):
-        return self.torch.zeros(int(self.sizes.n_beta), dtype=self.torch.complex128,
-                                device=f"cuda:{self.device}")
+    @property
+    def n_rhs(self):
+        return max(1, int(self.sizes.n_rhs))
 
-    def _vec_ptr(self, t):
-        if t.dtype != self.torch.complex128 or not t.is_contiguous() or t.numel() != self.sizes.n_beta:
-            raise ValueError("expected a contiguous complex128 vector of length n_beta")
+    def new_vec(self, one=False):
+        """Zero vector of every right-hand side ([n_rhs][n_beta] flat), or of one."""
+        n = int(self.sizes.n_beta) * (1 if one else self.n_rhs)
+        return self.torch.zeros(n, dtype=self.torch.complex128, device=f"cuda:{self.device}")
+
+    def _vec_ptr(self, t, one=False):
+        n = int(self.sizes.n_beta) * (1 if one else self.n_rhs)
+        if t.dtype != self.torch.complex128 or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"expected a contiguous complex128 vector of length {n}")
         return _VP(t.data_ptr())
 
     # -- operator --------------------------------------------------------------
@@ -241,6 +265,14 @@ class Context:
         y = self.new_vec() if y is None else y
         self._enter()
         self._check(self.lib.grt_apply_T(self.h, self._vec_ptr(x), self._vec_ptr(y)))
+        self._leave()
+        return y
+
+    def apply_ST_block(self, x, y=None):
+        """y_r = S T_r x_r on the FP32 matrix cores for every right-hand side."""
+        y = self.new_vec() if y is None else y
+        self._enter()
+        self._check(self.lib.grt_apply_ST_block(self.h, self._vec_ptr(x), self._vec_ptr(y)))
         self._leave()
         return y
 
@@ -315,15 +347,17 @@ class Context:
         opts = grt_solve_opts(tol=tol, maxit=maxit, restart=restart, use_x0=int(x0 is not None),
                               precision=precision, inner_tol=inner_tol, max_refine=max_refine,
                               use_graph=int(graph))
-        stats = grt_solve_stats()
+        R = self.n_rhs
+        stats = (grt_solve_stats * R)()
         self._enter()
-        st = self.lib.grt_solve(self.h, C.byref(opts), self._vec_ptr(beta), C.byref(stats))
+        st = self.lib.grt_solve(self.h, C.byref(opts), self._vec_ptr(beta), stats)
         self._leave()
         if check or st != GRT_ENOCONV:
             self._check(st)
-        return beta, stats
+        return beta, (stats[0] if R == 1 else list(stats))
 
-    def bragg(self, beta=None):
+    def bragg(self, beta=None, rhs=0):
+        """Bragg amplitudes of right-hand side rhs; beta: that angle's vector [n_beta]."""
         n = int(self.sizes.Nrb)
         orders = (C.c_int * n)()
         c = np.zeros(2 * n)
@@ -331,22 +365,22 @@ class Context:
         R = np.zeros(n)
         T = np.zeros(n)
         flux = C.c_double(0)
-        bp = self._vec_ptr(beta) if beta is not None else _VP(0)
+        bp = self._vec_ptr(beta, one=True) if beta is not None else _VP(0)
         self._enter()
-        self._check(self.lib.grt_bragg(self.h, bp, n, orders, _dptr(c), _dptr(d), _dptr(R),
+        self._check(self.lib.grt_bragg(self.h, rhs, bp, n, orders, _dptr(c), _dptr(d), _dptr(R),
                                        _dptr(T), C.byref(flux)))
         self._leave()
         return dict(orders=np.array(orders[:]), c=c[0::2] + 1j * c[1::2], d=d[0::2] + 1j * d[1::2],
                     R=R, T=T, flux_err=flux.value)
 
-    def eval_field(self, beta, xy):
+    def eval_field(self, beta, xy, rhs=0):
         """Total field at the points xy ([n, 2] float64, host) for the solution beta
         (device tensor, or None without inclusions): complex128 numpy array [n]."""
         import numpy as np
         xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         out = np.zeros(2 * len(xy))
         self._enter()
-        self._check(self.lib.grt_eval_field(self.h, self._vec_ptr(beta) if beta is not None
+        self._check(self.lib.grt_eval_field(self.h, rhs, self._vec_ptr(beta, one=True) if beta is not None
                                             else None, len(xy), _dptr(xy), _dptr(out)))
         self._leave()
         return out[0::2] + 1j * out[1::2]

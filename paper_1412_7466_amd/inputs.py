@@ -256,6 +256,17 @@ def m1000_p20(phi=-math.pi / 5, **kw) -> Problem:
                         20.0, phi, 20, **kw)
 
 
+def large_block(M=10000, R=256, seed=4, **kw):
+    """Large single geometry with many incidence angles as one block of right-hand
+    sides: d=4, middle layer y in [-2, 2], M disks with radii U[0.005, 0.01] and
+    indices U[1.5, 3.0], gap 0.002, seed 4, omega=40, P=20; the R angles equally
+    spaced in [-pi/3, pi/3].  Returns (problem at the first angle, angles)."""
+    phis = np.linspace(-math.pi / 3, math.pi / 3, R)
+    pb = make_problem(f"large_block_M{M}", 4.0, 2.0, M, 0.005, 0.01, 1.5, 3.0, 0.002, seed,
+                      40.0, float(phis[0]), 20, **kw)
+    return pb, phis
+
+
 def small(M, P, omega=10.0, seed=7, phi=-math.pi / 5, d=1.0, h=0.5, **kw) -> Problem:
     """Small test geometry with m1000's size and index distributions, scaled."""
     return make_problem(f"small_M{M}_P{P}", d, h, M, 0.02, 0.04, 1.5, 3.0, 0.01, seed,
@@ -308,22 +319,23 @@ BATCH_PS = (10, 15, 20)
 
 
 def batch_problem(i: int, cells=None) -> Problem:
-    """Instance i of the batched mixed-precision workload (seed 120000+i): the
-    M=1000 workload's rules (d=1, middle layer y in [-1, 1], radii U[0.004, 0.012],
-    indices U[1.5, 3.0], gap 0.002) with M log-uniform in [200, 4000] and P uniform
-    in {10, 15, 20}, at the (omega, phi) cell i mod len(cells) of the grid
-    omega in {10, 20, 40} x 16 angles equally spaced in [-pi/3, pi/3] (cells: list of
-    (omega index, phi index), default the whole grid in the order omega fastest).
-    Problems of one cell share their discretization, hence one factorization of the
-    layered structure."""
+    """Instance i of the batched mixed-precision workload (seed 3000+i): the M=1000
+    workload's rules (d=1, middle layer y in [-1, 1], radii U[0.004, 0.012], indices
+    U[1.5, 3.0], gap 0.002) with M log-uniform in [200, 4000], at the (omega, phi) cell
+    i mod len(cells) of the grid omega in {10, 20, 40} x 16 angles equally spaced in
+    [-pi/3, pi/3] (cells: list of (omega index, phi index); default the whole grid with
+    omega fastest, so instance i has omega index i mod 3 and angle index (i div 3) mod
+    16).  The multipole order goes with the frequency as in the single-problem
+    workloads: P = 10, 15, 20 at omega = 10, 20, 40.  Problems of one cell share their
+    discretization, hence one factorization of the layered structure."""
     if cells is None:
         cells = [(w, a) for a in range(len(BATCH_PHIS)) for w in range(len(BATCH_OMEGAS))]
     wi, ai = cells[i % len(cells)]
     omega, phi = BATCH_OMEGAS[wi], BATCH_PHIS[ai]
-    seed = 120000 + i
+    P = int(BATCH_PS[wi])
+    seed = 3000 + i
     rng = np.random.Generator(np.random.PCG64(seed + 7_000_000))
     M = int(round(math.exp(rng.uniform(math.log(200), math.log(4000)))))
-    P = int(BATCH_PS[int(rng.integers(0, len(BATCH_PS)))])
     d, h, r_lo, gap = 1.0, 1.0, 0.004, 0.002
     x, y, r, n = pack_disks(M, d, h, r_lo, 0.012, 1.5, 3.0, gap, seed)
     closest = h - (max(gap, 0.02) + r_lo)

@@ -30,8 +30,9 @@ def test_batch_problem_distribution_and_determinism():
     pbs = [inputs.batch_problem(i, cells) for i in range(12)]
     for i, pb in enumerate(pbs):
         assert 200 <= pb.M <= 4000
-        assert pb.P in inputs.BATCH_PS
         wi, ai = cells[i % len(cells)]
+        assert pb.P == inputs.BATCH_PS[wi]          # P goes with omega
+        assert pb.seed == 3000 + i
         assert pb.omega == inputs.BATCH_OMEGAS[wi]
         assert pb.phi == inputs.BATCH_PHIS[ai]
         assert abs(pb.phi) <= math.pi / 3 + 1e-15
@@ -48,6 +49,8 @@ def test_batch_problem_distribution_and_determinism():
     assert abs(ph[0] + math.pi / 3) < 1e-15 and abs(ph[-1] - math.pi / 3) < 1e-12
     full = [inputs.batch_problem(i) for i in range(3)]
     assert [p.omega for p in full] == [10.0, 20.0, 40.0]
+    assert [p.P for p in full] == [10, 15, 20]
+    assert inputs.batch_problem(3).phi == inputs.BATCH_PHIS[1]
 
 
 def test_problems_of_one_cell_share_the_discretization():
