@@ -5,7 +5,8 @@
 // incoming coefficients of the layers alone (sec. 5), s the Mie diagonal (sec. 4.1).
 //
 // Network (width H, L layers, F = 32 node inputs, E = 8 edge inputs, O = 2(2 p_out+1)
-// outputs; weights in bfloat16, activations and accumulation in FP32):
+// outputs; weights in bfloat16, activations and accumulation in FP32, every GEMM on
+// the FP32 matrix cores):
 //   h0 = relu(W_in f + b_in)
 //   per layer: P = A h, Q = B h;  msg_jk = relu(P_j + Q_nbr(j,k) + C e_jk + c)
 //              agg_j = mean_k msg_jk;  h <- h + relu(U [h; agg] + u)
@@ -43,44 +44,48 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 
 enum { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_BIAS_RESID = 3 };
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // C[i][j] = alpha sum_k A(i,k) B(k,j) + beta C[i][j], A(i,k) = A[i sai + k sak],
-// B(k,j) = B[k sbk + j sbn]; 16x16 output tile per 256-thread block, K staged in
-// LDS 16 at a time.  Epilogues: EPI_BIAS C = AB + bias[j]; EPI_BIAS_RELU also
-// D = relu(C); EPI_BIAS_RESID also D = R + relu(C).
+// B(k,j) = B[k sbk + j sbn], on the matrix cores: one wave per 16x16 output tile,
+// v_mfma_f32_16x16x4f32 over K in steps of 4 (lane l holds A(i0 + l % 16, k0 + l / 16)
+// and B(k0 + l / 16, j0 + l % 16); the accumulator rows 4 (l / 16) + v, column l % 16).
+// B in bfloat16 (the weights) is widened to FP32 exactly, so the products and the
+// FP32 accumulation see the rounded weights and full FP32 activations.  Epilogues:
+// EPI_BIAS C = AB + bias[j]; EPI_BIAS_RELU also D = relu(C); EPI_BIAS_RESID also
+// D = R + relu(C).
 template <typename TBv, int EPI>
-__global__ void __launch_bounds__(256) gemm_kernel(int Mr, int Nc, int Kd, const float* __restrict__ A,
-                                                   int64_t sai, int64_t sak, const TBv* __restrict__ B,
-                                                   int64_t sbk, int64_t sbn, float* C, int64_t ldc,
-                                                   float alpha, float beta, const TBv* __restrict__ bias,
-                                                   float* D, int64_t ldd, const float* R, int64_t ldr) {
-  __shared__ float As[16][17];
-  __shared__ float Bs[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+__global__ void __launch_bounds__(64) gemm_kernel(int Mr, int Nc, int Kd, const float* __restrict__ A,
+                                                  int64_t sai, int64_t sak, const TBv* __restrict__ B,
+                                                  int64_t sbk, int64_t sbn, float* C, int64_t ldc,
+                                                  float alpha, float beta, const TBv* __restrict__ bias,
+                                                  float* D, int64_t ldd, const float* R, int64_t ldr) {
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
   const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
-  float acc = 0.f;
-  for (int k0 = 0; k0 < Kd; k0 += 16) {
-    {
-      const int ai = i0 + ty, ak = k0 + tx;
-      As[ty][tx] = (ai < Mr && ak < Kd) ? A[ai * sai + ak * sak] : 0.f;
-      const int bk = k0 + ty, bj = j0 + tx;
-      Bs[ty][tx] = (bk < Kd && bj < Nc) ? ld_val(B[bk * sbk + bj * sbn]) : 0.f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) acc = fmaf(As[ty][kk], Bs[kk][tx], acc);
-    __syncthreads();
+  const int ai = i0 + li, bj = j0 + li;
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < Kd; k0 += 4) {
+    const int k = k0 + lk;
+    const float a = (ai < Mr && k < Kd) ? A[ai * sai + k * sak] : 0.f;
+    const float b = (k < Kd && bj < Nc) ? ld_val(B[k * sbk + bj * sbn]) : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
   }
-  const int i = i0 + ty, j = j0 + tx;
-  if (i >= Mr || j >= Nc) return;
-  if (EPI == EPI_PLAIN) {
-    float v = alpha * acc;
-    if (beta != 0.f) v += beta * C[i * ldc + j];
-    C[i * ldc + j] = v;
-  } else {
-    const float pre = acc + ld_val(bias[j]);
-    C[i * ldc + j] = pre;
-    if (EPI == EPI_BIAS_RELU) D[i * ldd + j] = fmaxf(pre, 0.f);
-    if (EPI == EPI_BIAS_RESID) D[i * ldd + j] = R[i * ldr + j] + fmaxf(pre, 0.f);
+  const int j = j0 + li;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + 4 * lk + v;
+    if (i >= Mr || j >= Nc) continue;
+    if (EPI == EPI_PLAIN) {
+      float w = alpha * acc[v];
+      if (beta != 0.f) w += beta * C[i * ldc + j];
+      C[i * ldc + j] = w;
+    } else {
+      const float pre = acc[v] + ld_val(bias[j]);
+      C[i * ldc + j] = pre;
+      if (EPI == EPI_BIAS_RELU) D[i * ldd + j] = fmaxf(pre, 0.f);
+      if (EPI == EPI_BIAS_RESID) D[i * ldd + j] = R[i * ldr + j] + fmaxf(pre, 0.f);
+    }
   }
 }
 
@@ -492,7 +497,7 @@ void gemm(hipStream_t s, int Mr, int Nc, int Kd, const float* A, int64_t sai, in
           const float* R = nullptr, int64_t ldr = 0) {
   if (Mr <= 0 || Nc <= 0) return;
   dim3 grid(blocks_for(Nc, 16), blocks_for(Mr, 16));
-  gemm_kernel<TBv, EPI><<<grid, 256, 0, s>>>(Mr, Nc, Kd, A, sai, sak, B, sbk, sbn, C, ldc, alpha, beta,
+  gemm_kernel<TBv, EPI><<<grid, 64, 0, s>>>(Mr, Nc, Kd, A, sai, sak, B, sbk, sbn, C, ldc, alpha, beta,
                                              bias, D, ldd, R, ldr);
 }
 

@@ -286,19 +286,19 @@ def empty_slab(omega=10.0, phi=-math.pi / 5, d=1.0, h=0.5, n_layer=STACK, **kw) 
 # learned warm start: geometry sets, initial weights, synthetic targets
 # ----------------------------------------------------------------------------
 
-WARM_OMEGAS = (20.0,)
-WARM_PHIS = (-math.pi / 5, -math.pi / 12, math.pi / 12, math.pi / 5)
+WARM_OMEGAS = (10.0, 20.0, 30.0, 40.0)
+WARM_PHIS = (-math.pi / 3, -math.pi / 9, math.pi / 9, math.pi / 3)
 
 
-def warm_problem(i: int, held_out: bool = False, M_range=(200, 2000), P: int = 15,
+def warm_problem(i: int, held_out: bool = False, M_range=(200, 2000), P: int = 20,
                  omegas=WARM_OMEGAS, phis=WARM_PHIS) -> Problem:
     """Geometry i of the warm-start training set (seed 50000+i) or of the held-out
-    set (seed 90000+i): the M=1000 workload's rules (d=1, middle layer y in
-    [-1, 1], radii U[0.004, 0.012], indices U[1.5, 3.0], gap 0.002, P=15) with M a
-    seeded uniform integer in M_range and (omega, phi) taken in turn from a small
-    grid.  All problems with the same (omega, phi) get the same discretization
-    (interface nodes from the closest position the packing allows), so they share
-    one factorization of the layered structure."""
+    set (seed 90000+i): the M=1000 workload's rules (d=1, middle layer y in [-1, 1],
+    radii U[0.004, 0.012], indices U[1.5, 3.0], gap 0.002) with M a seeded uniform
+    integer in M_range, P = 20, and (omega, phi) taken in turn from a grid over
+    omega in [10, 40] and phi in [-pi/3, pi/3] (omega fastest).  All problems with the
+    same (omega, phi) get the same discretization (interface nodes from the closest
+    position the packing allows), so they share one factorization of the layers."""
     seed = (90000 if held_out else 50000) + i
     rng = np.random.Generator(np.random.PCG64(seed + 7_000_000))
     M = int(rng.integers(M_range[0], M_range[1] + 1))

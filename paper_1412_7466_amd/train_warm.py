@@ -4,9 +4,11 @@ measure it on held-out geometries.
     python -m paper_1412_7466_amd.train_warm --out warm_start.npz
 
 1. Training set: geometries inputs.warm_problem(i) (the M=1000 workload's rules
-   with M uniform in [M_lo, M_hi], (omega, phi) from a small grid sharing one
-   factorization of the layers per pair), each solved by FP64 GMRES to 1e-10; the
-   network's inputs and exact target are kept on the GPU (grt_nn_add_sample).
+   with M uniform in [M_lo, M_hi], P = 20, (omega, phi) from a 4 x 4 grid over
+   omega in [10, 40] and phi in [-pi/3, pi/3], each grid cell sharing one
+   factorization of the layers), each solved by FP64 GMRES to 1e-10; the network's
+   inputs and exact target (every order |n| <= p_out = P by default) are kept on the
+   GPU (grt_nn_add_sample).
 2. Adam on the GPU (grt_nn_train), one geometry per step.
 3. Held-out geometries (other seeds): FP64 GMRES to 1e-9 from x0 = 0 and from the
    network's guess (prediction time included), iterations and time for both, and
@@ -33,8 +35,8 @@ def log(*a):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n-train", type=int, default=256)
-    ap.add_argument("--n-held", type=int, default=32)
+    ap.add_argument("--n-train", type=int, default=1024)
+    ap.add_argument("--n-held", type=int, default=128)
     ap.add_argument("--M-lo", type=int, default=200)
     ap.add_argument("--M-hi", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=60)
@@ -42,7 +44,8 @@ def main(argv=None):
     ap.add_argument("--width", type=int, default=128)
     ap.add_argument("--layers", type=int, default=3)
     ap.add_argument("--k", type=int, default=16)
-    ap.add_argument("--p-out", type=int, default=3)
+    ap.add_argument("--p-out", type=int, default=20)
+    ap.add_argument("--restart", type=int, default=800)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default="warm_start.npz")
     a = ap.parse_args(argv)
@@ -69,7 +72,7 @@ def main(argv=None):
     for i in range(a.n_train):
         pb = inputs.warm_problem(i, M_range=(a.M_lo, a.M_hi))
         ctx = build(pb)
-        beta, st = ctx.solve(tol=1e-10, restart=200, maxit=2000)
+        beta, st = ctx.solve(tol=1e-10, restart=a.restart, maxit=3000)
         ids.append(net.add_sample(ctx, beta))
         train_iters.append(st.iters)
         if ctx is not anchors[(pb.omega, pb.phi)]:
@@ -97,12 +100,12 @@ def main(argv=None):
         ctx = build(pb)
         torch.cuda.synchronize()
         tc = time.perf_counter()
-        bc, sc = ctx.solve(tol=1e-9, restart=200, maxit=2000)
+        bc, sc = ctx.solve(tol=1e-9, restart=a.restart, maxit=3000)
         torch.cuda.synchronize()
         tc = time.perf_counter() - tc
         tw = time.perf_counter()
         x0 = net.predict(ctx)
-        bw, sw = ctx.solve(tol=1e-9, restart=200, maxit=2000, x0=x0)
+        bw, sw = ctx.solve(tol=1e-9, restart=a.restart, maxit=3000, x0=x0)
         torch.cuda.synchronize()
         tw = time.perf_counter() - tw
         # normalised error of the guesses against the cold solution
