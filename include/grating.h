@@ -47,7 +47,7 @@ typedef enum {
   GRT_EUNSUP = -7   /* unsupported option                                             */
 } grt_status;
 
-typedef enum { GRT_FP64 = 0, GRT_FP32 = 1 } grt_precision;
+typedef enum { GRT_FP64 = 0, GRT_FP32 = 1, GRT_FP32_RELAXED = 2 } grt_precision;
 
 typedef struct grt_ctx grt_ctx;
 
@@ -100,8 +100,18 @@ typedef struct {
   int precision;   /* GRT_FP64: GMRES on K in FP64.  GRT_FP32: FP64 iterative
                       refinement r = b - K x, x += e, with e from GMRES (FP64
                       orthogonalisation) on K32, whose translation between
-                      well-separated inclusions runs in FP32 (FP32 accumulate)  */
-  double inner_tol;/* GRT_FP32: relative tolerance of each inner solve (0: 1e-5) */
+                      well-separated inclusions runs in FP32 (FP32 accumulate).
+                      GRT_FP32_RELAXED: one FP64 GMRES on K whose Arnoldi
+                      applies switch to K32 once the residual estimate is
+                      below inner_tol (relaxed inexact Krylov: an apply error
+                      of relative size e is harmless once the residual is
+                      below tol / e; Bouras and Fraysse 2005, Simoncini and
+                      Szyld 2003); every restart and the final check take the
+                      FP64 residual b - K x, so a solve that stops has met tol
+                      in FP64                                                 */
+  double inner_tol;/* GRT_FP32: relative tolerance of each inner solve (0: 1e-5).
+                      GRT_FP32_RELAXED: relative residual below which the
+                      applies use K32 (0: 1e3 tol, at most 1e-2)              */
   int max_refine;  /* GRT_FP32: most refinement steps (0: 10)                */
   int use_graph;   /* 1: every apply of K is replayed from a HIP graph captured
                       once per operator (dropped when the table, the launch
@@ -117,6 +127,8 @@ typedef struct {
   int refine_steps;     /* GRT_FP32: FP64 refinement steps taken             */
   int x0_rejected;      /* use_x0 and ||b - K x0|| >= ||b||: the guess was
                            dropped and the solve started from x = 0          */
+  int fp32_applies;     /* applies of K32 (GRT_FP32: every inner step;
+                           GRT_FP32_RELAXED: the Arnoldi steps past the switch) */
 } grt_solve_stats;
 
 typedef struct {
@@ -190,11 +202,24 @@ grt_status grt_apply(grt_ctx* ctx, const void* x_dev, void* y_dev, int precision
  * Toeplitz product: more waves per SIMD, but twice the load instructions; kept for
  * comparison); 0 frees it and the apply evaluates the generator on the fly again.  Results agree with the on-the-fly apply to rounding.
  * GRT_ENOMEM if it does not fit in free device memory with 1 GiB to spare (the
- * context stays usable, without the table).  The mixed-precision apply always
- * evaluates on the fly; batched FP64 solves stream the table of every context that
- * has one when the batch is created (changing the mode afterwards makes
+ * context stays usable, without the table).  The mixed-precision apply has a table
+ * of its own (grt_set_table32); batched FP64 solves stream the table of every
+ * context that has one when the batch is created (changing the mode afterwards makes
  * grt_batch_solve return GRT_ESTATE). */
 grt_status grt_set_table(grt_ctx* ctx, int mode);
+/* Resident FP32 table of the mixed-precision apply (GRT_FP32 and GRT_FP32_RELAXED
+ * solves and grt_apply with GRT_FP32, one angle).  The same generator as
+ * grt_set_table, rounded to FP32, for the well-separated pairs only: a pair with a
+ * kept copy at k2 rho below the FP32-safe distance is zero in the table and stays
+ * in the FP64 near-pair pass.  M * Mpad * (4P+1) complex FP32 (half the FP64
+ * table's bytes), streamed by every mixed apply instead of evaluating the Hankel
+ * functions; the contraction and its accumulation are FP32 as on the fly, so the
+ * result differs from the on-the-fly mixed apply by FP32 rounding only.  on = 1
+ * builds it now (if built) and after every later grt_build; 0 frees it.
+ * GRT_ENOMEM as grt_set_table; GRT_EUNSUP for a context with several angles (their
+ * FP32 translation is the matrix-core block product).  Batched mixed solves use the
+ * tables of the contexts that have one when the batch is created. */
+grt_status grt_set_table32(grt_ctx* ctx, int on);
 /* Launch-shape autotuner: times the translation launch, with the pass that adds
  * its per-chunk partial results, for source chunk counts giving 256 .. 16384
  * wavefronts, in the current mode (on the fly or resident table) and in its two

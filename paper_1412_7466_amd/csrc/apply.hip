@@ -72,6 +72,26 @@ __global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_e
   m2l_table2_block<P>(table, x, partial, M, Mpad, chunk, blockIdx.x, blockIdx.y);
 }
 
+// FP32 translation of the well-separated pairs from the resident FP32 table
+template <int P>
+__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(3, 8))) m2l_table32_kernel(const cf* __restrict__ table,
+                                                                  const cf* __restrict__ x,
+                                                                  cf* partial, int M, int Mpad,
+                                                                  int chunk) {
+  m2l_table_block<P, cf>(table, x, partial, M, Mpad, chunk, blockIdx.x, blockIdx.y);
+}
+
+template <int P>
+__global__ void __launch_bounds__(64) table32_build_kernel(const double* __restrict__ cx,
+                                                           const double* __restrict__ cy, int M,
+                                                           int Mpad, int chunk, double k,
+                                                           double d, cd alpha, cd alpha_inv,
+                                                           const double* __restrict__ htab,
+                                                           double zsafe, cf* table) {
+  table_build_block<P, cf>(cx, cy, M, Mpad, chunk, k, d, alpha, alpha_inv, htab, table,
+                           blockIdx.x, blockIdx.y, zsafe);
+}
+
 template <int P>
 __global__ void __launch_bounds__(64) table_build_kernel(const double* __restrict__ cx,
                                                          const double* __restrict__ cy, int M,
@@ -211,13 +231,26 @@ void launch_table_build(grt_ctx* c) {
 }
 
 template <int P>
+void launch_table32_build(grt_ctx* c) {
+  const int chunk = 16;
+  dim3 grid((unsigned)((c->M + 63) / 64), (unsigned)((c->M + chunk - 1) / chunk));
+  table32_build_kernel<P><<<grid, 64, 0, c->stream>>>(
+      c->d_cx, c->d_cy, (int)c->M, c->table32_mpad, chunk, c->g.k[1], c->g.d, c->g.alpha,
+      c->g.alpha_inv, c->d_htab, c->zsafe, c->d_table32);
+}
+
+template <int P>
 void launch_m2l32(grt_ctx* c, const cf* x32) {
   dim3 grid((unsigned)((c->M + 63) / 64), c->m2l_nchunks);
   hipEvent_t* ev = prof_pair(c);
   if (ev) hipEventRecord(ev[0], c->stream);
-  m2l_kernel<P, cf><<<grid, M2L_THREADS, 0, c->stream>>>(
-      c->d_cx, c->d_cy, x32, c->d_pT32, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d, c->g.alpha,
-      c->g.alpha_inv, c->d_htab, c->zsafe);
+  if (c->d_table32)
+    m2l_table32_kernel<P><<<grid, M2L_THREADS, 0, c->stream>>>(
+        c->d_table32, x32, c->d_pT32, (int)c->M, c->table32_mpad, c->m2l_chunk);
+  else
+    m2l_kernel<P, cf><<<grid, M2L_THREADS, 0, c->stream>>>(
+        c->d_cx, c->d_cy, x32, c->d_pT32, (int)c->M, c->m2l_chunk, c->g.k[1], c->g.d,
+        c->g.alpha, c->g.alpha_inv, c->d_htab, c->zsafe);
   if (ev) hipEventRecord(ev[1], c->stream);
 }
 
@@ -485,19 +518,36 @@ grt_status apply_K(grt_ctx* c, const cd* x, cd* y, const double* oscale) {
   return run_apply(c, x, y, 0, oscale);
 }
 
-// K32 x: FP32 translation between well-separated pairs, FP64 for near pairs, the
-// layer correction and the preconditioner.
+// K32 x: FP32 translation between well-separated pairs (generator on the fly, or
+// from the resident FP32 table), FP64 for near pairs, the layer correction and the
+// preconditioner.  With the two-stream option the FP64 layer correction runs on the
+// second stream alongside the translation.
 grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y, const double* oscale) {
   if (c->M == 0) return GRT_OK;
   hipStream_t s = c->stream;
   const int n = (int)c->n_beta;
+  const bool ovl = c->overlap && c->stream2;
+  grt_status st = GRT_OK;
+  if (ovl) {
+    GRT_HIP(c, hipEventRecord(c->ev_fork, s));
+    GRT_HIP(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+    st = cx_apply(c, x, c->stream2);
+    if (st != GRT_OK) return st;
+    st = lowrank_tail(c, c->d_gvec, c->stream2);
+    if (st != GRT_OK) return st;
+    GRT_HIP(c, hipEventRecord(c->ev_join, c->stream2));
+  }
   to_f32_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, c->d_x32, n);
   GRT_P_DISPATCH(launch_m2l32, c->P, c, c->d_x32);
   GRT_P_DISPATCH(launch_near, c->P, c, x);
-  grt_status st = cx_apply(c, x);
-  if (st != GRT_OK) return st;
-  st = lowrank_tail(c, c->d_gvec);
-  if (st != GRT_OK) return st;
+  if (ovl) {
+    GRT_HIP(c, hipStreamWaitEvent(s, c->ev_join, 0));
+  } else {
+    st = cx_apply(c, x);
+    if (st != GRT_OK) return st;
+    st = lowrank_tail(c, c->d_gvec);
+    if (st != GRT_OK) return st;
+  }
   combine_mixed_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
       n, x, c->d_mie, c->d_pT32, c->m2l_nchunks, c->d_pN, c->d_pB, c->b_nchunks, c->d_pL, y,
       oscale);
@@ -544,6 +594,37 @@ grt_status table_set(grt_ctx* c, bool on) {
   GRT_HIP(c, hipMalloc(&c->d_table, bytes));
   GRT_HIP(c, hipMemsetAsync(c->d_table, 0, bytes, c->stream));
   GRT_P_DISPATCH(launch_table_build, c->P, c);
+  GRT_HIP(c, hipGetLastError());
+  GRT_HIP(c, hipStreamSynchronize(c->stream));
+  return GRT_OK;
+}
+
+// Resident FP32 table of the well-separated pairs (the mixed-precision apply's
+// translation): allocate, zero and fill it, or free it.
+size_t table32_bytes(const grt_ctx* c) {
+  const size_t mpad = (size_t)((c->M + 63) / 64) * 64;
+  return mpad * (size_t)c->M * (size_t)(4 * c->P + 1) * sizeof(cf);
+}
+
+grt_status table32_set(grt_ctx* c, bool on) {
+  graph_reset(c);
+  ++c->gen;
+  if (c->d_table32) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->d_table32);
+    c->d_table32 = nullptr;
+  }
+  if (!on || c->M == 0) return GRT_OK;
+  const size_t bytes = table32_bytes(c);
+  size_t free_b = 0, total_b = 0;
+  GRT_HIP(c, hipMemGetInfo(&free_b, &total_b));
+  if (bytes + ((size_t)1 << 30) > free_b)
+    return set_err(c, GRT_ENOMEM, "FP32 translation table of " + std::to_string(bytes >> 20) +
+                                      " MiB does not fit in free device memory");
+  c->table32_mpad = (int)(((c->M + 63) / 64) * 64);
+  GRT_HIP(c, hipMalloc(&c->d_table32, bytes));
+  GRT_HIP(c, hipMemsetAsync(c->d_table32, 0, bytes, c->stream));
+  GRT_P_DISPATCH(launch_table32_build, c->P, c);
   GRT_HIP(c, hipGetLastError());
   GRT_HIP(c, hipStreamSynchronize(c->stream));
   return GRT_OK;

@@ -51,6 +51,9 @@ struct InstDesc {
   // resident translation table of the FP64 apply (null: generator on the fly)
   const cd* table;
   int mpad;
+  // resident FP32 table of the well-separated pairs (mixed apply; null: on the fly)
+  const cf* table32;
+  int mpad32;
   int split;  // 2: FP64 on-the-fly translation as two half-output launches
   // 0 once the lockstep solver has no further use for this problem's applies: every
   // apply kernel then skips its work items and the combine writes zeros
@@ -119,6 +122,17 @@ __global__ void __launch_bounds__(M2L_THREADS) m2l32_batched(const InstDesc* __r
   if (!q.active) return;
   m2l_block<P, cf>(q.cx, q.cy, X32 + q.off, q.pT32, q.M, q.m2l_chunk, q.g.k[1], q.g.d, q.g.alpha,
                    q.g.alpha_inv, q.htab, q.zsafe, w.x, w.y);
+}
+
+// FP32 translation of the well-separated pairs from the problem's FP32 table
+template <int P>
+__global__ void __launch_bounds__(M2L_THREADS) __attribute__((amdgpu_waves_per_eu(3, 8))) m2lt32_batched(const InstDesc* __restrict__ D,
+                                                              const Item* __restrict__ it,
+                                                              const cf* __restrict__ X32) {
+  const Item w = it[blockIdx.x];
+  const InstDesc& q = D[w.inst];
+  if (!q.active) return;
+  m2l_table_block<P, cf>(q.table32, X32 + q.off, q.pT32, q.M, q.mpad32, q.m2l_chunk, w.x, w.y);
 }
 
 // the near pairs [64 x, 64 x + 64) of a problem in FP64, one lane per pair
@@ -536,12 +550,14 @@ struct grt_batch {
   double *d_dnorm = nullptr, *d_dinv = nullptr;
   struct Group {
     int P;
-    // m2l: translation items of every problem (the mixed apply's FP32 launch); m2lf /
-    // m2lh / m2lt: those of the problems on the fly in one launch / on the fly split
-    // over two half-output launches / with a resident table (FP64 apply)
-    Item *m2l = nullptr, *m2lf = nullptr, *m2lh = nullptr, *m2lt = nullptr, *cx = nullptr,
-         *bx = nullptr, *nr = nullptr;
-    int n_m2l = 0, n_m2lf = 0, n_m2lh = 0, n_m2lt = 0, n_cx = 0, n_bx = 0, n_nr = 0;
+    // m2l / m2lt32: translation items of the problems without / with an FP32 table
+    // (the mixed apply's FP32 launches); m2lf / m2lh / m2lt: those of the problems on
+    // the fly in one launch / on the fly split over two half-output launches / with a
+    // resident table (FP64 apply)
+    Item *m2l = nullptr, *m2lt32 = nullptr, *m2lf = nullptr, *m2lh = nullptr, *m2lt = nullptr,
+         *cx = nullptr, *bx = nullptr, *nr = nullptr;
+    int n_m2l = 0, n_m2lt32 = 0, n_m2lf = 0, n_m2lh = 0, n_m2lt = 0, n_cx = 0, n_bx = 0,
+        n_nr = 0;
   };
   std::vector<uint64_t> gen;  // the contexts' generations at creation
   std::vector<Group> groups;
@@ -630,6 +646,8 @@ static void launch_group_B(grt_batch* b, const grt_batch::Group& gp) {
 template <int P>
 static void launch_group_T32(grt_batch* b, const grt_batch::Group& gp) {
   if (gp.n_m2l) m2l32_batched<P><<<gp.n_m2l, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2l, b->x32);
+  if (gp.n_m2lt32)
+    m2lt32_batched<P><<<gp.n_m2lt32, M2L_THREADS, 0, b->stream>>>(b->dd, gp.m2lt32, b->x32);
   if (gp.n_nr) near_batched<P><<<gp.n_nr, 64, 0, b->stream>>>(b->dd, gp.nr, b->xtmp);
 }
 
@@ -817,9 +835,13 @@ struct LockstepResult {
 // operator if mixed): X (normalised, in place) from its current value.  A problem
 // stops updating once its residual estimate reaches tol ||Bv_i|| (a problem with
 // Bv_i = 0 is done at once).  With guard, an initial X_i no better than zero is
-// dropped and that problem restarts from zero.
+// dropped and that problem restarts from zero.  With relax > 0 (relaxed inexact
+// GMRES, FP64 operator): an Arnoldi step applies the mixed operator once every
+// problem still iterating has a residual estimate at most relax ||Bv_i||; the
+// residuals at the restarts stay FP64.
 static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, double tol,
-                              int maxit, int m, bool guard, bool use_graph, LockstepResult& r) {
+                              int maxit, int m, bool guard, bool use_graph, LockstepResult& r,
+                              double relax = 0.0, int* fast_steps = nullptr) {
   hipStream_t s = b->stream;
   const int B = b->B, ld = m + 1;
   const size_t ldv = (size_t)b->ntot;
@@ -887,9 +909,15 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
       return all;
     };
     bool all = false;
+    // the largest relative residual estimate among the problems still iterating
+    double est = 0.0;
+    for (int i = 0; i < B; ++i)
+      if (!done[i]) est = std::max(est, r.rel[i]);
     for (int j = 0; j < m && total + j < maxit; ++j) {
       cd* w = b->wout;  // the new directions; normalised into V_{j+1} below
-      BTRY(batch_apply(b, V + (size_t)j * ldv, use_graph, mixed));
+      const bool fast = mixed || (relax > 0 && est <= relax);
+      if (fast && !mixed && fast_steps) ++*fast_steps;
+      BTRY(batch_apply(b, V + (size_t)j * ldv, use_graph, fast));
       for (int pass = 0; pass < 2; ++pass) {
         seg_dots_kernel<<<dim3(b->nseg, (j + 1 + DOT_VB - 1) / DOT_VB), BT, 0, s>>>(
             b->dd, b->d_seg2inst, V, ldv, w, j + 1, b->nseg, b->dpart);
@@ -916,7 +944,11 @@ static grt_status batch_gmres(grt_batch* b, bool mixed, const cd* Bv, cd* X, dou
           all = true;
           break;
         }
-        for (int i = 0; i < B; ++i) act[i] = kk[i] < 0;
+        est = 0.0;
+        for (int i = 0; i < B; ++i) {
+          act[i] = kk[i] < 0;
+          if (act[i] && bn[i] > 0) est = std::max(est, hbuf[(j - 1) & 1][i] / bn[i]);
+        }
         BTRY(set_active(b, act));
       }
     }
@@ -1046,6 +1078,8 @@ static grt_status batch_create_impl(grt_batch** out, int64_t n, grt_ctx* const* 
     q.zsafe = c->zsafe;
     q.table = c->d_table;
     q.mpad = c->table_mpad;
+    q.table32 = c->d_table32;
+    q.mpad32 = c->table32_mpad;
     q.split = c->d_table ? 1 : c->m2l_split;
     q.active = 1;
     q.seg0 = seg;
@@ -1064,14 +1098,14 @@ static grt_status batch_create_impl(grt_batch** out, int64_t n, grt_ctx* const* 
   for (auto& kv : byP) {
     grt_batch::Group gp;
     gp.P = kv.first;
-    std::vector<Item> m2l, m2lf, m2lh, m2lt, cxv, bxv, nr;
+    std::vector<Item> m2l, m2lt32, m2lf, m2lh, m2lt, cxv, bxv, nr;
     for (int i : kv.second) {
       const InstDesc& q = b->hd[i];
       const int nt = 2 * q.g.N + q.g.Nw[1];
       for (int x = 0; x < (q.n_near + 63) / 64; ++x) nr.push_back({i, x, 0});
       for (int y = 0; y < q.m2l_nchunks; ++y)
         for (int x = 0; x < (q.M + 63) / 64; ++x) {
-          m2l.push_back({i, x, y});
+          (q.table32 ? m2lt32 : m2l).push_back({i, x, y});
           (q.table ? m2lt : q.split == 2 ? m2lh : m2lf).push_back({i, x, y});
         }
       for (int y = 0; y < q.c_nchunks; ++y)
@@ -1083,15 +1117,17 @@ static grt_status batch_create_impl(grt_batch** out, int64_t n, grt_ctx* const* 
     if ((st = upload(b, m2l, &gp.m2l)) != GRT_OK || (st = upload(b, cxv, &gp.cx)) != GRT_OK ||
         (st = upload(b, bxv, &gp.bx)) != GRT_OK || (st = upload(b, nr, &gp.nr)) != GRT_OK ||
         (st = upload(b, m2lf, &gp.m2lf)) != GRT_OK || (st = upload(b, m2lh, &gp.m2lh)) != GRT_OK ||
-        (st = upload(b, m2lt, &gp.m2lt)) != GRT_OK) {
-      for (void* q : {(void*)gp.m2l, (void*)gp.m2lf, (void*)gp.m2lh, (void*)gp.m2lt, (void*)gp.cx,
-                      (void*)gp.bx, (void*)gp.nr})
+        (st = upload(b, m2lt, &gp.m2lt)) != GRT_OK ||
+        (st = upload(b, m2lt32, &gp.m2lt32)) != GRT_OK) {
+      for (void* q : {(void*)gp.m2l, (void*)gp.m2lt32, (void*)gp.m2lf, (void*)gp.m2lh,
+                      (void*)gp.m2lt, (void*)gp.cx, (void*)gp.bx, (void*)gp.nr})
         if (q) hipFree(q);
       grt_batch_destroy(b);
       return st;
     }
     gp.n_nr = (int)nr.size();
     gp.n_m2l = (int)m2l.size();
+    gp.n_m2lt32 = (int)m2lt32.size();
     gp.n_m2lf = (int)m2lf.size();
     gp.n_m2lh = (int)m2lh.size();
     gp.n_m2lt = (int)m2lt.size();
@@ -1164,6 +1200,7 @@ grt_status grt_batch_destroy(grt_batch* b) {
                           b->d_k};
   for (auto& gp : b->groups) {
     p.push_back(gp.m2l);
+    p.push_back(gp.m2lt32);
     p.push_back(gp.m2lf);
     p.push_back(gp.m2lh);
     p.push_back(gp.m2lt);
@@ -1191,8 +1228,8 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
                            grt_solve_stats* stats) {
   if (!b || !o || !beta) return GRT_EINVAL;
   b->err.clear();
-  if (o->precision != GRT_FP64 && o->precision != GRT_FP32)
-    return bset(b, GRT_EINVAL, "precision must be GRT_FP64 or GRT_FP32");
+  if (o->precision != GRT_FP64 && o->precision != GRT_FP32 && o->precision != GRT_FP32_RELAXED)
+    return bset(b, GRT_EINVAL, "precision must be GRT_FP64, GRT_FP32 or GRT_FP32_RELAXED");
   if (!(o->tol > 0 && o->tol < 1)) return bset(b, GRT_EINVAL, "tol must be in (0, 1)");
   for (int i = 0; i < b->B; ++i)
     if (b->ctx[i]->gen != b->gen[i])
@@ -1223,8 +1260,13 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
   }
   LockstepResult r(B);
   std::vector<int> refine(B, 0);
-  if (o->precision == GRT_FP64) {
-    BTRY(batch_gmres(b, false, Bv, X, tol, maxit, m, o->use_x0 != 0, use_graph, r));
+  int fast_steps = 0;
+  if (o->precision == GRT_FP64 || o->precision == GRT_FP32_RELAXED) {
+    const double sw = o->precision == GRT_FP64 ? 0.0
+                      : o->inner_tol > 0      ? o->inner_tol
+                                              : std::min(1e-2, 1e3 * tol);
+    BTRY(batch_gmres(b, false, Bv, X, tol, maxit, m, o->use_x0 != 0, use_graph, r, sw,
+                     &fast_steps));
   } else {
     // FP64 iterative refinement around the mixed-precision operator, for all
     // problems in lockstep: R = B - K X (FP64), solve K32 E = R to inner_tol, X += E.
@@ -1307,6 +1349,9 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
       stats[i].seconds = secs;
       stats[i].refine_steps = refine[i];
       stats[i].x0_rejected = r.rejected[i];
+      // lockstep: the relaxed switch is taken for the whole batch at once
+      stats[i].fp32_applies = o->precision == GRT_FP32 ? r.iters[i] + r.cycles[i]
+                                                       : std::min(fast_steps, r.iters[i]);
     }
     if (!(r.rel[i] <= tol)) conv = false;
   }

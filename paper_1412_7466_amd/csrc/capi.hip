@@ -47,7 +47,7 @@ void free_all(grt_ctx* c) {
                   c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_htab,
                   c->d_y, c->d_scal, c->d_dotpart, c->d_x32, c->d_pT32,
                   c->d_pN, c->d_noff, c->d_nlist, c->d_dnorm, c->d_dinv, c->d_xtmp, c->d_ntgt, c->d_npart,
-                  c->d_table};
+                  c->d_table, c->d_table32};
   for (void* p : bufs)
     if (p) hipFree(p);
   c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal =
@@ -66,6 +66,7 @@ void free_all(grt_ctx* c) {
   c->d_ntgt = nullptr;
   c->d_npart = nullptr;
   c->d_table = nullptr;
+  c->d_table32 = nullptr;
   c->d_wtmp = nullptr;
   c->krylov_restart = 0;
   c->built = false;
@@ -344,6 +345,10 @@ grt_status grt_build(grt_ctx* c) {
     st = table_set(c, true);
     if (st != GRT_OK) return st;
   }
+  if (c->want_table32) {
+    st = table32_set(c, true);
+    if (st != GRT_OK) return st;
+  }
   for (grt_ctx* sub : c->rhs) {
     st = grt_build(sub);
     if (st != GRT_OK) return set_err(c, st, "building an angle: " + sub->err);
@@ -363,6 +368,17 @@ grt_status grt_set_table(grt_ctx* c, int mode) {
   c->table_lanes = mode == 2 ? 2 : 1;
   if (!c->built) return GRT_OK;
   return table_set(c, c->want_table);
+}
+
+grt_status grt_set_table32(grt_ctx* c, int on) {
+  GRT_CHECK_CTX(c);
+  if (on != 0 && on != 1) return set_err(c, GRT_EINVAL, "on must be 0 or 1");
+  if (c->have_problem && c->n_rhs > 1 && on)
+    return set_err(c, GRT_EUNSUP, "with several angles the FP32 translation is the "
+                                  "matrix-core block product (no table)");
+  c->want_table32 = on != 0;
+  if (!c->built) return GRT_OK;
+  return table32_set(c, c->want_table32);
 }
 
 grt_status grt_table_bytes(const grt_ctx* c, int64_t* bytes) {
@@ -607,7 +623,7 @@ static grt_status solve_block(grt_ctx* c, const grt_solve_opts* o, cd* beta,
       st = batch_set_block(c->rhs_batch, c);
       if (st != GRT_OK) return set_err(c, st, grt_batch_error_message(c->rhs_batch));
     }
-    if (o->precision == GRT_FP32) {
+    if (o->precision != GRT_FP64) {
       st = block_ready(c);
       if (st != GRT_OK) return st;
     }
@@ -629,8 +645,8 @@ grt_status grt_solve(grt_ctx* c, const grt_solve_opts* o, void* beta, grt_solve_
   if (st != GRT_OK) return st;
   if (!o || !beta) return set_err(c, GRT_EINVAL, "null argument");
   if (!(o->tol > 0 && o->tol < 1)) return set_err(c, GRT_EINVAL, "tol must be in (0, 1)");
-  if (o->precision != GRT_FP64 && o->precision != GRT_FP32)
-    return set_err(c, GRT_EINVAL, "precision must be GRT_FP64 or GRT_FP32");
+  if (o->precision != GRT_FP64 && o->precision != GRT_FP32 && o->precision != GRT_FP32_RELAXED)
+    return set_err(c, GRT_EINVAL, "precision must be GRT_FP64, GRT_FP32 or GRT_FP32_RELAXED");
   grt_solve_stats tmp{};
   grt_solve_stats* sp = stats ? stats : &tmp;
   if (c->M == 0) {

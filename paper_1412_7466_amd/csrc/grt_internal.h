@@ -132,6 +132,10 @@ struct grt_ctx {
   cd* d_table = nullptr;    // [M][4P+1][Mpad]
   int table_mpad = 0;
   int table_lanes = 1;      // lanes per target in the table kernel (1 or 2)
+  // resident FP32 table of the well-separated pairs (mixed-precision apply only)
+  bool want_table32 = false;
+  cf* d_table32 = nullptr;  // [M][4P+1][Mpad], near pairs zero
+  int table32_mpad = 0;
   // GMRES workspace
   int krylov_restart = 0;
   cd* d_V = nullptr;        // [restart+1][n_beta]
@@ -185,6 +189,8 @@ grt_status bragg_alpha(grt_ctx* c, const cd* beta, cd* out_cd /* device [2 Nrb] 
 grt_status alpha_full(grt_ctx* c, const cd* beta, cd* out, cd* W);
 grt_status apply_alloc(grt_ctx* c);
 grt_status table_set(grt_ctx* c, bool on);
+grt_status table32_set(grt_ctx* c, bool on);
+size_t table32_bytes(const grt_ctx* c);
 grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* splits_out,
                         double* ms_out);
 grt_status autotune_coupling(grt_ctx* c);

@@ -303,6 +303,7 @@ static grt_status apply_hat(grt_ctx* c, KOp op, const cd* xh, bool use_graph) {
 
 struct CoreResult {
   int iters = 0, cycles = 0;
+  int fast_applies = 0;
   double rel = 1.0;
   bool converged = false;
   bool x0_rejected = false;
@@ -310,8 +311,12 @@ struct CoreResult {
 
 // Restarted GMRES for op(x) = b from the iterate in x (updated in place).  b must not
 // live in basis slots 0..m.  Stops at ||b - op x|| <= tol ||b|| or after maxit steps.
+// With fast set (relaxed inexact GMRES), an Arnoldi step whose latest residual
+// estimate is at most fast_rel ||b|| applies fast instead of op; the residual at
+// every restart, and so the stopping test, is always op's.
 static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double tol, int maxit,
-                             int m, CoreResult* res, bool guard_x0, bool use_graph) {
+                             int m, CoreResult* res, bool guard_x0, bool use_graph,
+                             KOp fast = nullptr, double fast_rel = 0.0) {
   const int n = (int)c->n_beta;
   hipStream_t s = c->stream;
   const size_t ldv = (size_t)n;
@@ -384,13 +389,17 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
     int k = 0;
     int queued = 0;
     bool conv = false;
+    double est = res->rel;  // latest residual estimate known on the host (relative)
     for (int j = 0; j < m && total + queued < maxit; ++j) {
       cd* w = c->d_wtmp;  // the new direction; normalised into V_{j+1} below
+      const bool use_fast = fast && est <= fast_rel;
+      const KOp opj = use_fast ? fast : op;
+      if (use_fast) ++res->fast_applies;
       // from the second step on, the previous step left D^{-1} V_j in d_xtmp
       if (j == 0)
-        GRT_TRY(apply_hat(c, op, V, use_graph));
+        GRT_TRY(apply_hat(c, opj, V, use_graph));
       else
-        GRT_TRY(apply_step(c, op, use_graph));
+        GRT_TRY(apply_step(c, opj, use_graph));
       cd* hcol = c->d_H + (size_t)j * ldh;
       for (int pass = 0; pass < 2; ++pass) {
         dim3 gd(nblk, j + 1);
@@ -408,7 +417,8 @@ static grt_status gmres_core(grt_ctx* c, KOp op, const cd* bvec, cd* x, double t
       ++queued;
       if (j >= 1) {
         GRT_HIP(c, hipEventSynchronize(c->ev_res[(j - 1) & 1]));
-        if (givens(j - 1) / bn <= tol) { k = j; conv = true; break; }
+        est = givens(j - 1) / bn;
+        if (est <= tol) { k = j; conv = true; break; }
       }
       k = j + 1;
     }
@@ -458,13 +468,17 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
     dscale_kernel<<<gridn, KT, 0, s>>>(x, c->d_dnorm, x, n);
   *st = grt_solve_stats{};
   CoreResult r;
-  if (o->precision == GRT_FP64) {
-    GRT_TRY(gmres_core(c, apply_K, bvec, x, tol, maxit, m, &r, o->use_x0 != 0, graph));
+  if (o->precision == GRT_FP64 || o->precision == GRT_FP32_RELAXED) {
+    const bool relax = o->precision == GRT_FP32_RELAXED;
+    const double sw = o->inner_tol > 0 ? o->inner_tol : std::min(1e-2, 1e3 * tol);
+    GRT_TRY(gmres_core(c, apply_K, bvec, x, tol, maxit, m, &r, o->use_x0 != 0, graph,
+                       relax ? apply_K_mixed : nullptr, sw));
     st->x0_rejected = r.x0_rejected ? 1 : 0;
     st->iters = r.iters;
     st->cycles = r.cycles;
     st->rel_resid = r.rel;
     st->refine_steps = 0;
+    st->fp32_applies = r.fast_applies;
   } else {
     // FP64 iterative refinement around the FP32-translation operator:
     //   r = b - K x (FP64), solve K32 e = r to inner_tol, x += e.
@@ -498,6 +512,7 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
       GRT_HIP(c, hipMemsetAsync(evec, 0, sizeof(cd) * n, s));
       GRT_TRY(gmres_core(c, apply_K_mixed, rvec, evec, itol, maxit - total, m, &r, false, graph));
       total += r.iters;
+      st->fp32_applies += r.iters + r.cycles;
       cycles += r.cycles;
       add_vec_kernel<<<gridn, KT, 0, s>>>(x, evec, n);
       GRT_HIP(c, hipGetLastError());

@@ -263,13 +263,16 @@ __device__ __forceinline__ void m2l_block(const double* __restrict__ cx,
 // consecutive in memory, so the 64 lanes of a wave read one 1 KB line per order.
 // ---------------------------------------------------------------------------
 
-// One lane per target, sources [by_ chunk, (by_+1) chunk).
-template <int P>
+// One lane per target, sources [by_ chunk, (by_+1) chunk).  T = cd: the FP64 table
+// of every pair; T = cf with zsafe > 0: the FP32 table of the mixed-precision apply,
+// whose near pairs (a kept copy at k rho < zsafe, done in FP64 elsewhere) are zero.
+template <int P, typename T = cd>
 __device__ __forceinline__ void table_build_block(const double* __restrict__ cx,
                                                   const double* __restrict__ cy, int M, int Mpad,
                                                   int chunk, double k, double d, cd alpha,
                                                   cd alpha_inv, const double* __restrict__ htab,
-                                                  cd* table, int bx_, int by_) {
+                                                  T* table, int bx_, int by_,
+                                                  double zsafe = 0.0) {
   constexpr int NQ = 4 * P + 1;
   __shared__ double stab[HTAB_SIZE];
   for (int t = threadIdx.x; t < HTAB_SIZE; t += blockDim.x) stab[t] = htab[t];
@@ -280,17 +283,17 @@ __device__ __forceinline__ void table_build_block(const double* __restrict__ cx,
   const double xj = cx[j], yj = cy[j];
   const cd wl[3] = {alpha_inv, cd{1.0, 0.0}, alpha};
   for (int m = m0; m < m1; ++m) {
-    cd* col = table + (size_t)m * NQ * Mpad + j;
+    T* col = table + (size_t)m * NQ * Mpad + j;
     pair_generate<P>(
-        xj - cx[m], yj - cy[m], k, d, wl, j == m, false, stab, 0.0,
-        [&](cd t0) { col[(size_t)(2 * P) * Mpad] = t0; },
+        xj - cx[m], yj - cy[m], k, d, wl, j == m, false, stab, zsafe,
+        [&](cd t0) { col[(size_t)(2 * P) * Mpad] = to_acc(t0, (T*)nullptr); },
         [&](int qb, const cd* tp, const cd* tm) {
 #pragma unroll
           for (int u = 0; u < M2L_QB; ++u) {
             const int q = 1 + qb * M2L_QB + u;
             if (q > 2 * P) continue;
-            col[(size_t)(2 * P + q) * Mpad] = tp[u];
-            col[(size_t)(2 * P - q) * Mpad] = tm[u];
+            col[(size_t)(2 * P + q) * Mpad] = to_acc(tp[u], (T*)nullptr);
+            col[(size_t)(2 * P - q) * Mpad] = to_acc(tm[u], (T*)nullptr);
           }
         });
   }
@@ -301,23 +304,29 @@ __device__ __forceinline__ void table_build_block(const double* __restrict__ cx,
 __device__ __forceinline__ cd ld_stream(const cd* p) {
   return cd{__builtin_nontemporal_load(&p->r), __builtin_nontemporal_load(&p->i)};
 }
+__device__ __forceinline__ cf ld_stream(const cf* p) {
+  return cf{__builtin_nontemporal_load(&p->r), __builtin_nontemporal_load(&p->i)};
+}
 
-// Same result as m2l_block in FP64, with the generator read from the resident
-// table (the next block of orders is loaded while the current one is contracted).
-template <int P>
-__device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
-                                                const cd* __restrict__ x, cd* partial, int M,
+// Same result as m2l_block, with the generator read from the resident table (the
+// next block of orders is loaded while the current one is contracted).  T = cd: the
+// FP64 apply; T = cf: the FP32 table, coefficients and accumulation of the
+// mixed-precision apply (near pairs are zero in that table).
+template <int P, typename T = cd>
+__device__ __forceinline__ void m2l_table_block(const T* __restrict__ table,
+                                                const T* __restrict__ x, T* partial, int M,
                                                 int Mpad, int chunk, int bx_, int by_) {
   constexpr int NB = 2 * P + 1;
   constexpr int NQ = 4 * P + 1;
   constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
-  constexpr int STAGE = 2 * M2L_WAVES * M2L_TILE * NB;
-  constexpr int RED = 2 * NB * 64;
+  constexpr int TW = sizeof(T) / sizeof(double);  // doubles per complex value (1 or 2)
+  constexpr int STAGE = TW * M2L_WAVES * M2L_TILE * NB;
+  constexpr int RED = TW * NB * 64;
   constexpr int BUF = STAGE > RED ? STAGE : RED;
   __shared__ double smem[BUF];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  cd* sx = reinterpret_cast<cd*>(smem) + wv * M2L_TILE * NB;
+  T* sx = reinterpret_cast<T*>(smem) + wv * M2L_TILE * NB;
   const int j = bx_ * 64 + lane;  // < Mpad: table rows of dead lanes are zero
   const int m0 = by_ * chunk;
   const int m1 = min(M, m0 + chunk);
@@ -325,11 +334,11 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
   const int s0 = m0 + wv * per;
   const int s1 = min(m1, s0 + per);
   const int ntile = (per + M2L_TILE - 1) / M2L_TILE;
-  cd acc[NB];
+  T acc[NB];
 #pragma unroll
-  for (int n = 0; n < NB; ++n) acc[n] = cd{0, 0};
+  for (int n = 0; n < NB; ++n) acc[n] = T{0, 0};
   // table row of order q for source m: a wave-uniform base plus the lane's target
-  auto row = [&](const cd* col, int q) { return ld_stream(col + (size_t)(2 * P + q) * Mpad + j); };
+  auto row = [&](const T* col, int q) { return ld_stream(col + (size_t)(2 * P + q) * Mpad + j); };
   for (int it = 0; it < ntile; ++it) {
     const int ts = s0 + it * M2L_TILE;
     const int cnt = max(0, min(M2L_TILE, s1 - ts));
@@ -337,27 +346,27 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
     for (int t = lane; t < cnt * NB; t += 64) sx[t] = x[(size_t)ts * NB + t];
     __syncthreads();
     for (int mm = 0; mm < cnt; ++mm) {
-      const cd* b = sx + mm * NB;
-      const cd* col = table + (size_t)(ts + mm) * NQ * Mpad;
+      const T* b = sx + mm * NB;
+      const T* col = table + (size_t)(ts + mm) * NQ * Mpad;
       {
-        const cd t0 = row(col, 0);
+        const T t0 = row(col, 0);
 #pragma unroll
         for (int n = 0; n < NB; ++n) cmac(acc[n], t0, b[n]);
       }
       // blocks of orders in flight: the current one and the next M2L_TDIST - 1
-      cd np[M2L_TDIST][M2L_QB], nm[M2L_TDIST][M2L_QB];
+      T np[M2L_TDIST][M2L_QB], nm[M2L_TDIST][M2L_QB];
 #pragma unroll
       for (int d = 0; d < M2L_TDIST; ++d)
 #pragma unroll
         for (int u = 0; u < M2L_QB; ++u) {
           const int q = 1 + d * M2L_QB + u;
-          np[d][u] = q <= 2 * P ? row(col, q) : cd{0, 0};
-          nm[d][u] = q <= 2 * P ? row(col, -q) : cd{0, 0};
+          np[d][u] = q <= 2 * P ? row(col, q) : T{0, 0};
+          nm[d][u] = q <= 2 * P ? row(col, -q) : T{0, 0};
         }
 #pragma unroll
       for (int qb = 0; qb < NQB; ++qb) {
         constexpr int D = M2L_TDIST;
-        cd tp[M2L_QB], tm[M2L_QB];
+        T tp[M2L_QB], tm[M2L_QB];
 #pragma unroll
         for (int u = 0; u < M2L_QB; ++u) {
           tp[u] = np[qb % D][u];
@@ -367,31 +376,38 @@ __device__ __forceinline__ void m2l_table_block(const cd* __restrict__ table,
 #pragma unroll
           for (int u = 0; u < M2L_QB; ++u) {
             const int q = 1 + (qb + D) * M2L_QB + u;
-            np[qb % D][u] = q <= 2 * P ? row(col, q) : cd{0, 0};
-            nm[qb % D][u] = q <= 2 * P ? row(col, -q) : cd{0, 0};
+            np[qb % D][u] = q <= 2 * P ? row(col, q) : T{0, 0};
+            nm[qb % D][u] = q <= 2 * P ? row(col, -q) : T{0, 0};
           }
         }
-        contract_block<P, cd, const cd*, M2L_TNUG>(acc, b, qb, tp, tm);
+        contract_block<P, T, const T*, M2L_TNUG>(acc, b, qb, tp, tm);
       }
     }
   }
-  cd* red = reinterpret_cast<cd*>(smem);
+  T* red = reinterpret_cast<T*>(smem);
   for (int src = M2L_WAVES - 1; src >= 1; --src) {
     __syncthreads();
     if (wv == src) {
 #pragma unroll
       for (int n = 0; n < NB; ++n) {
-        cd v = acc[n];
-        if (src != M2L_WAVES - 1) v += red[n * 64 + lane];
+        T v = acc[n];
+        if (src != M2L_WAVES - 1) {
+          const T o = red[n * 64 + lane];
+          v.r += o.r;
+          v.i += o.i;
+        }
         red[n * 64 + lane] = v;
       }
     }
   }
   __syncthreads();
   if (wv == 0 && j < M) {
-    cd* out = partial + ((size_t)by_ * M + j) * NB;
+    T* out = partial + ((size_t)by_ * M + j) * NB;
 #pragma unroll
-    for (int n = 0; n < NB; ++n) out[n] = acc[n] + red[n * 64 + lane];
+    for (int n = 0; n < NB; ++n) {
+      const T o = red[n * 64 + lane];
+      out[n] = T{acc[n].r + o.r, acc[n].i + o.i};
+    }
   }
 }
 

@@ -19,7 +19,7 @@ GRT_OK, GRT_EINVAL, GRT_EGEOM, GRT_ENOMEM, GRT_EHIP, GRT_ENOCONV, GRT_ESTATE, GR
     0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "GRT_OK", -1: "GRT_EINVAL", -2: "GRT_EGEOM", -3: "GRT_ENOMEM", -4: "GRT_EHIP",
                 -5: "GRT_ENOCONV", -6: "GRT_ESTATE", -7: "GRT_EUNSUP"}
-GRT_FP64, GRT_FP32 = 0, 1
+GRT_FP64, GRT_FP32, GRT_FP32_RELAXED = 0, 1, 2
 
 
 class grt_layers(C.Structure):
@@ -47,7 +47,8 @@ class grt_solve_opts(C.Structure):
 
 class grt_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("rel_resid", C.c_double),
-                ("seconds", C.c_double), ("refine_steps", C.c_int), ("x0_rejected", C.c_int)]
+                ("seconds", C.c_double), ("refine_steps", C.c_int), ("x0_rejected", C.c_int),
+                ("fp32_applies", C.c_int)]
 
 
 class grt_sizes(C.Structure):
@@ -79,6 +80,7 @@ _PROTOS = {
     "grt_rhs": (C.c_int, [_VP, _VP]),
     "grt_incident": (C.c_int, [_VP, _VP]),
     "grt_set_table": (C.c_int, [_VP, C.c_int]),
+    "grt_set_table32": (C.c_int, [_VP, C.c_int]),
     "grt_table_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "grt_set_launch": (C.c_int, [_VP, C.c_int, C.c_int]),
     "grt_set_overlap": (C.c_int, [_VP, C.c_int]),
@@ -297,6 +299,13 @@ class Context:
         self._check(self.lib.grt_set_table(self.h, int(mode)))
         self._leave()
 
+    def set_table32(self, on=True):
+        """Resident FP32 table of the well-separated pairs for the mixed-precision
+        apply (GRT_FP32 / GRT_FP32_RELAXED solves); False frees it."""
+        self._enter()
+        self._check(self.lib.grt_set_table32(self.h, int(bool(on))))
+        self._leave()
+
     def set_launch(self, m2l_chunks, m2l_split=1):
         """Translation launch shape by hand: about m2l_chunks source chunks, split 1
         or 2 (two launches, half of the outputs each)."""
@@ -340,7 +349,12 @@ class Context:
         return a
 
     def solve(self, tol=1e-9, maxit=1000, restart=200, x0=None, out=None, check=True,
-              precision=GRT_FP64, inner_tol=1e-5, max_refine=10, graph=False):
+              precision=GRT_FP64, inner_tol=0.0, max_refine=10, graph=False):
+        """GMRES to tol (FP64 residual).  precision GRT_FP32: FP64 refinement around
+        inner solves on the mixed operator (inner_tol 0: 1e-5); GRT_FP32_RELAXED: one
+        FP64 GMRES whose applies switch to the mixed operator below inner_tol (0:
+        1e3 tol, at most 1e-2).  Returns (beta, stats) (lists of stats with several
+        angles)."""
         beta = self.new_vec() if out is None else out
         if x0 is not None:
             beta.copy_(x0)

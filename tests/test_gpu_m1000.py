@@ -92,6 +92,22 @@ def test_m1000_solve_mixed(m1000):
     _check_solution(ctx, beta, gold, pb, "m1000 mixed")
 
 
+def test_m1000_solve_relaxed_fp32_table(m1000):
+    """Relaxed mixed precision with the FP32 table of the well-separated pairs: FP64
+    GMRES whose applies switch to the FP32 translation below 1e3 tol."""
+    from paper_1412_7466_amd.grating import GRT_FP32_RELAXED
+    torch, ctx, gold, pb = m1000
+    ctx.set_table32(True)
+    try:
+        beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000, precision=GRT_FP32_RELAXED)
+        say(f"[gpu] m1000 relaxed iters={st.iters} fp32 applies={st.fp32_applies} "
+            f"resid={st.rel_resid:.2e} {st.seconds:.3f}s")
+        assert st.fp32_applies > 0
+        _check_solution(ctx, beta, gold, pb, "m1000 relaxed")
+    finally:
+        ctx.set_table32(False)
+
+
 def test_m1000_resident_table(m1000):
     """Same bars with the resident translation table (1 GB at this size)."""
     torch, ctx, gold, pb = m1000
@@ -122,3 +138,32 @@ def test_m1000_p20():
         _check_apply(torch, ctx, gold, pb, "m1000_p20 table 2 lanes")
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("inst", [9, 25, 29])
+def test_batched_workload_instances(inst):
+    """Instances of the batched workload with a stored oracle LU solution
+    (tests/golden/batch_oracle.npz): omega = 10, 20 and 40 at P = 10, 15 and 20.  The
+    omega = 40 instance checks the high-frequency rules (N, Q, Nw from k3 = 80)."""
+    import torch
+    from paper_1412_7466_amd.grating import Context
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    gold = np.load(os.path.join(GOLD, "batch_oracle.npz"))
+    pb = inputs.batch_problem(inst)
+    assert str(gold[f"i{inst}_digest"]) == pb.digest(), "inputs changed: regenerate"
+    say(f"[gpu] batch instance {inst}: M={pb.M} P={pb.P} omega={pb.omega}")
+    ctx = Context(0)
+    ctx.set_problem(pb)
+    ctx.build()
+    beta, st = ctx.solve(tol=1e-12, restart=600, maxit=2000)
+    say(f"[gpu] instance {inst}: iters {st.iters} resid {st.rel_resid:.2e}")
+    check_orders(beta.cpu().numpy(), gold[f"i{inst}_beta"], gold[f"i{inst}_D"], pb.P, 1e-9,
+                 1e-10, tag=f"batch instance {inst} beta")
+    og = ctx.bragg(beta)
+    p1, p3 = gold[f"i{inst}_prop1"], gold[f"i{inst}_prop3"]
+    check_amplitudes(np.concatenate([og["c"][p1], og["d"][p3]]),
+                     np.concatenate([gold[f"i{inst}_c"][p1], gold[f"i{inst}_d"][p3]]), 1e-9,
+                     tag=f"batch instance {inst} Bragg")
+    assert og["flux_err"] < 1e-9
+    ctx.close()

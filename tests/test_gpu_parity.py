@@ -186,6 +186,41 @@ def test_mixed_precision_refinement(torch_cuda, M, P, seed):
     check_orders(_np(beta), beta_o, D, P, 1e-9, 1e-10, tag=f"{pb.name} mixed beta")
 
 
+@pytest.mark.parametrize("M,P,seed", [(40, 10, 12), (30, 15, 13), (25, 20, 14)])
+def test_fp32_table_and_relaxed_solve(torch_cuda, M, P, seed):
+    """The resident FP32 table of the well-separated pairs reproduces the on-the-fly
+    mixed apply (the same FP32 generator values and contraction), and the relaxed
+    solve (FP64 GMRES whose applies switch to the mixed operator) reaches the
+    oracle's solution to the 1e-9 bar with its FP64 residual."""
+    from oracle.solver import Reduced
+    from paper_1412_7466_amd.grating import GRT_FP32, GRT_FP32_RELAXED
+    pb = inputs.small(M, P, seed=seed)
+    ctx = _ctx(pb)
+    xh, xd = _probe(torch_cuda, pb, seed)
+    D = dscale(pb)
+    y64 = _np(ctx.apply(xd))
+    yf = _np(ctx.apply(xd, precision=GRT_FP32))
+    ctx.set_table32(True)
+    yt = _np(ctx.apply(xd, precision=GRT_FP32))
+    check_orders(yt, yf, D, P, 1e-6, tag=f"{pb.name} FP32 table vs on the fly")
+    check_orders(yt, y64, D, P, 1e-4, tag=f"{pb.name} FP32 table vs FP64")
+    beta_o = Reduced(pb).solve_lu()
+    b64, s64 = ctx.solve(tol=1e-12, restart=150)
+    # switch at 1e-3: far earlier than the FP32 error allows for 1e-12, so the
+    # restarts' FP64 residuals have to finish the job
+    for sw in (0.0, 1e-3):
+        beta, st = ctx.solve(tol=1e-12, restart=150, precision=GRT_FP32_RELAXED, inner_tol=sw)
+        say(f"[gpu] relaxed M={M} P={P} switch={sw:g}: iters={st.iters} (FP64 {s64.iters}) "
+            f"cycles={st.cycles} fp32 applies={st.fp32_applies} resid={st.rel_resid:.2e}")
+        assert st.rel_resid <= 1e-12
+        if sw > 0:
+            assert st.fp32_applies > 0
+        check_orders(_np(beta), beta_o, D, P, 1e-9, 1e-10, tag=f"{pb.name} relaxed beta")
+    ctx.set_table32(False)
+    yf2 = _np(ctx.apply(xd, precision=GRT_FP32))
+    check_orders(yf2, yf, D, P, 1e-15, tag=f"{pb.name} table freed: on the fly again")
+
+
 def _batch_problems():
     return [inputs.tiny_m4(),
             inputs.small(12, 4, seed=21),
@@ -246,6 +281,33 @@ def test_batched_solve_matches_single_and_oracle(torch_cuda):
     with pytest.raises(GratingError) as ei:
         batch.solve(tol=1e-12, restart=150)
     assert ei.value.status == GRT_ESTATE
+    batch.close()
+
+
+def test_batched_relaxed_with_fp32_tables(torch_cuda):
+    """Lockstep relaxed solves (FP64 GMRES whose applies switch to the mixed operator
+    for the whole batch) with FP32 tables on some problems reach every problem's
+    oracle solution; the plain mixed (refinement) batch agrees too."""
+    from oracle.solver import Reduced
+    from paper_1412_7466_amd.grating import Batch, GRT_FP32, GRT_FP32_RELAXED
+    pbs = _batch_problems()
+    ctxs = [_ctx(pb) for pb in pbs]
+    ctxs[1].set_table32(True)
+    ctxs[2].set_table32(True)
+    ctxs[4].set_table32(True)
+    batch = Batch(ctxs)
+    for prec, sw in ((GRT_FP32_RELAXED, 1e-4), (GRT_FP32_RELAXED, 0.0), (GRT_FP32, 0.0)):
+        betas, stats = batch.solve(tol=1e-12, restart=150, precision=prec, inner_tol=sw,
+                                   graph=True)
+        for pb, b, st in zip(pbs, betas, stats):
+            say(f"[gpu] batch precision {prec} switch {sw:g} {pb.name}: iters={st.iters} "
+                f"fp32 applies={st.fp32_applies} resid={st.rel_resid:.2e}")
+            assert st.rel_resid <= 1e-12
+            beta_o = Reduced(pb).solve_lu()
+            check_orders(_np(b), beta_o, dscale(pb), pb.P, 1e-9, 1e-10,
+                         tag=f"batch relaxed {pb.name}")
+        if sw > 0:
+            assert max(st.fp32_applies for st in stats) > 0
     batch.close()
 
 
