@@ -300,14 +300,33 @@ def relaxed_m1000(a, torch, ctx, beta, err, use_graph, use_overlap, M, P, NB, fl
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     ctx.set_overlap(bool(use_overlap))
-    kw = dict(tol=a.tol, restart=a.restart, precision=GRT_FP32_RELAXED, graph=bool(use_graph))
-    ctx.solve(**kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        br, st = ctx.solve(**kw)
-    torch.cuda.synchronize()
-    t_rel = (time.perf_counter() - t0) / a.steps
+    # the switch point: the default 1e3 tol (an FP32 apply error of 1e-6 relative is
+    # then harmless by the relaxation bound), and earlier switches, each checked
+    # against the oracle
+    by_switch = {}
+    best = None
+    for sw in (0.0, 1e-5, 1e-4, 1e-3):
+        kw = dict(tol=a.tol, restart=a.restart, precision=GRT_FP32_RELAXED,
+                  graph=bool(use_graph), inner_tol=sw)
+        ctx.solve(**kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            b_sw, st_sw = ctx.solve(**kw)
+        torch.cuda.synchronize()
+        t_sw = (time.perf_counter() - t0) / a.steps
+        e_sw = err(b_sw)
+        key = "default" if sw == 0.0 else f"{sw:g}"
+        by_switch[key] = {"solves_per_s": 1.0 / t_sw, "iters": st_sw.iters,
+                          "cycles": st_sw.cycles, "fp32_applies": st_sw.fp32_applies,
+                          "rel_resid": st_sw.rel_resid, "err_vs_oracle": e_sw}
+        ok = e_sw is None or e_sw["meets_1e-9"]
+        if ok and (best is None or t_sw < best[0]):
+            best = (t_sw, key, b_sw, st_sw)
+    if best is None:   # none met the bar: report the default
+        d = by_switch["default"]
+        best = (1.0 / d["solves_per_s"], "default", b_sw, st_sw)
+    t_rel, best_key, br, st = best
     # the FP32 table kernel alone: applies of the mixed operator with kernel timing
     ctx.set_overlap(False)
     x = ctx.rhs()
@@ -328,7 +347,8 @@ def relaxed_m1000(a, torch, ctx, beta, err, use_graph, use_overlap, M, P, NB, fl
     ctx.set_table32(False)
     return {"solves_per_s": 1.0 / t_rel, "iters": st.iters, "fp32_applies": st.fp32_applies,
             "cycles": st.cycles, "rel_resid": st.rel_resid,
-            "switch_below": min(1e-2, 1e3 * a.tol), "graph": bool(use_graph),
+            "switch": best_key, "default_switch_below": min(1e-2, 1e3 * a.tol),
+            "by_switch": by_switch, "graph": bool(use_graph),
             "two_streams": bool(use_overlap), "table32_build_s": t_build,
             "rel_diff_vs_fp64": float(torch.linalg.norm(br - beta) / torch.linalg.norm(beta)),
             "err_vs_oracle": err(br),
@@ -769,7 +789,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--tol", type=float, default=1e-9)
+    # 1e-10: a residual below the metric's 1e-9 for which beta and the Bragg
+    # amplitudes also meet 1e-9 against the oracle (at 1e-9 the error is about 1e-9)
+    ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
@@ -952,6 +974,19 @@ def main():
     #    translation (resident FP32 table of the well-separated pairs) below 1e3 tol;
     #    same graph / two-stream options as the best FP64 configuration
     relaxed = relaxed_m1000(a, torch, ctx, beta, err, use_graph, use_overlap, M, P, NB, flops)
+    # 5. the best FP64 configuration at the metric's own residual, 1e-9 (context: its
+    #    error against the oracle is about 1e-9)
+    ctx.set_overlap(bool(use_overlap))
+    kw9 = dict(tol=1e-9, restart=a.restart, graph=bool(use_graph))
+    ctx.solve(**kw9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        b9, st9 = ctx.solve(**kw9)
+    torch.cuda.synchronize()
+    at_1e9 = {"solves_per_s": a.steps / (time.perf_counter() - t0), "iters": st9.iters,
+              "rel_resid": st9.rel_resid, "err_vs_oracle": err(b9)}
+    ctx.set_overlap(False)
     ctx.set_table(False)
     res = {
         "metric": METRIC,
@@ -967,7 +1002,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "m1000_fp64: plain FP64 method, M=1000, P=15, omega=20, d=1, "
-                               "middle layer y in [-1,1], one angle phi=-pi/5, GMRES to 1e-9",
+                               f"middle layer y in [-1,1], one angle phi=-pi/5, GMRES to "
+                               f"{a.tol:g}",
                    "M": M, "P": P, "n_unknowns": M * NB, "tol": a.tol,
                    "restart": a.restart, "seed": pb.seed,
                    "translation": ("resident table" + (", applies replayed from a HIP graph"
@@ -992,6 +1028,7 @@ def main():
         "table_vs_on_the_fly_rel_diff": diff_tf,
         "mixed_fp32_fp64": mixed,
         "mixed_relaxed_fp32_table": relaxed,
+        "fp64_best_at_tol_1e-9": at_1e9,
         "roofline": roof_t if use_table else roof_f,
         "roofline_on_the_fly": roof_f,
         "roofline_table": roof_t,

@@ -188,7 +188,10 @@ class Field:
     def __init__(self, red, beta, n_fine=16384):
         G = self.G = red.G
         self.beta = np.zeros(0) if G.M == 0 else np.asarray(beta)
-        self.gamma = interior_coefficients(red, self.beta) if G.M else None
+        # interior expansions exist for disks only; for the non-circular inclusions the
+        # field is available outside their enclosing circles
+        self.gamma = (interior_coefficients(red, self.beta)
+                      if G.M and getattr(G.pb, "shape", None) is None else None)
         al = red.alpha_vec(self.beta)
         c = G.col
         self.mu1, self.sig1 = al[c["mu1"]], al[c["sig1"]]
@@ -250,6 +253,9 @@ class Field:
                 vy = ty - G.cy[m]
                 sel = (np.hypot(vx, vy) < G.rad[m]) & ~ins
                 if np.any(sel):
+                    if self.gamma is None:
+                        raise NotImplementedError("field inside the enclosing circle of a "
+                                                  "non-circular inclusion")
                     J = incoming(n, G.kp[m], vx[sel][:, None], vy[sel][:, None])
                     val[sel] = G.alpha ** l * (J @ self.gamma[m])
                     ins |= sel

@@ -40,6 +40,7 @@ from .common import Geometry
 from .layered import assemble_A, rhs_f
 from .multiple import mie_coefficients, dense_T, TranslationTable
 from .coupling import assemble_C, assemble_Bphys
+from .inclusion import scattering_matrix
 
 
 class PseudoInverse:
@@ -77,7 +78,19 @@ class Reduced:
         self.A = assemble_A(G)
         self.f = rhs_f(G)
         self.pinv = PseudoInverse(self.A, pb.disc.pinv_eps, pinv_rule)
-        self.s = mie_coefficients(G.k2, G.kp, G.rad, G.P).reshape(-1) if G.M else np.zeros(0)
+        # single-inclusion scattering matrices (sec. 4.1): the Mie diagonal s of a disk,
+        # or, for the non-circular inclusions of eq. par1, a dense (2P+1)^2 block per
+        # inclusion from its boundary integral equation (self.S, [M][2P+1][2P+1])
+        self.S = None
+        if getattr(pb, "shape", None) is not None and G.M:
+            sh = np.asarray(pb.shape, float)
+            self.S = np.stack([scattering_matrix(a1, a2, a3, rot, G.k2, kp, G.P,
+                                                 n=pb.shape_nodes // 2)
+                               for (a1, a2, a3, rot), kp in zip(sh, G.kp)])
+            self.s = None
+        else:
+            self.s = (mie_coefficients(G.k2, G.kp, G.rad, G.P).reshape(-1) if G.M
+                      else np.zeros(0))
         n = np.abs(np.arange(-G.P, G.P + 1))
         self.D = (np.abs(sp.hankel1(n[None, :], G.k2 * G.rad[:, None])).reshape(-1)
                   if G.M else np.zeros(0))
@@ -103,16 +116,25 @@ class Reduced:
         """B_phys A^+ C x (the incoming field of the layers due to x)."""
         return self.B @ self.pinv.apply(self.C @ x)
 
+    def S_mul(self, v):
+        """The block-diagonal scattering matrix times v (a vector or [n, cols])."""
+        if self.S is None:
+            return self.s * v if v.ndim == 1 else self.s[:, None] * v
+        M, nb = self.G.M, self.G.nb
+        if v.ndim == 1:
+            return np.einsum("mln,mn->ml", self.S, v.reshape(M, nb)).reshape(-1)
+        return np.einsum("mln,mnc->mlc", self.S, v.reshape(M, nb, -1)).reshape(M * nb, -1)
+
     def K_apply(self, x):
-        return x - self.s * self.T_apply(x) + self.s * self.lowrank_apply(x)
+        return x - self.S_mul(self.T_apply(x) - self.lowrank_apply(x))
 
     def rhs(self):
-        return self.s * (self.B @ self.pinv.apply(self.f))
+        return self.S_mul(self.B @ self.pinv.apply(self.f))
 
     def K_dense(self):
         n = self.G.n_beta
         W = self.pinv.apply(self.C)       # [n_alpha, n]
-        return np.eye(n) - self.s[:, None] * self.T + self.s[:, None] * (self.B @ W)
+        return np.eye(n) - self.S_mul(self.T - self.B @ W)
 
     # -- solves ------------------------------------------------------------
     def solve_lu(self):
@@ -142,8 +164,8 @@ class Reduced:
         D = self.D
         # beta columns in normalised units (D beta), inclusion rows scaled by D
         top = np.hstack([self.A, self.C / D[None, :]])
-        bot = np.hstack([-(D * self.s)[:, None] * self.B,
-                         D[:, None] * (np.eye(n) - self.s[:, None] * self.T) / D[None, :]])
+        bot = np.hstack([-D[:, None] * self.S_mul(self.B),
+                         D[:, None] * (np.eye(n) - self.S_mul(self.T)) / D[None, :]])
         F = np.vstack([top, bot])
         rhs = np.concatenate([self.f, np.zeros(n, complex)])
         pi = PseudoInverse(F, self.G.pb.disc.pinv_eps)

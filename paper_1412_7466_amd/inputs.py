@@ -57,6 +57,12 @@ class Problem:
     disc: Discretization
     name: str = ""
     seed: Optional[int] = None
+    # non-circular inclusions (paper eq. par1): per inclusion (a1, a2, a3, rot), the
+    # boundary rho(t) (cos(t + rot), sin(t + rot)), rho = a1 + a2 cos(a3 t), with
+    # radius = a1 + |a2| its enclosing circle; None: disks of the given radii.
+    # shape_nodes: boundary nodes of each inclusion's integral equation.
+    shape: Optional[np.ndarray] = None
+    shape_nodes: int = 64
 
     @property
     def M(self) -> int:
@@ -74,6 +80,9 @@ class Problem:
         hsh.update(np.array([dd.N, *dd.Nw, *dd.Q, dd.Nu, dd.n_rb_lo, dd.Nrb, dd.zeta_K],
                             dtype=np.int64).tobytes())
         hsh.update(np.array([dd.y0, dd.pinv_eps], dtype=np.float64).tobytes())
+        if self.shape is not None:
+            hsh.update(np.ascontiguousarray(self.shape, dtype=np.float64).tobytes())
+            hsh.update(np.int64(self.shape_nodes).tobytes())
         return hsh.hexdigest()[:16]
 
 
@@ -271,6 +280,23 @@ def small(M, P, omega=10.0, seed=7, phi=-math.pi / 5, d=1.0, h=0.5, **kw) -> Pro
     """Small test geometry with m1000's size and index distributions, scaled."""
     return make_problem(f"small_M{M}_P{P}", d, h, M, 0.02, 0.04, 1.5, 3.0, 0.01, seed,
                         omega, phi, P, **kw)
+
+
+def star(M, P, omega=10.0, seed=9, phi=-math.pi / 5, d=1.0, h=0.5, a2_rel=1.0 / 3.0,
+         a3=3, r_lo=0.02, r_hi=0.04, n_lo=1.5, n_hi=3.0, gap=0.01, shape_nodes=64,
+         **kw) -> Problem:
+    """Non-circular inclusions of the paper's class (eq. par1): enclosing radii
+    U[r_lo, r_hi] packed like the disks, then a1 = r / (1 + a2_rel),
+    a2 = a2_rel a1, a3 lobes (the paper uses a2 / a1 = 1/3, a3 = 3), and a
+    rotation U[0, 2 pi) per inclusion from a second seeded stream."""
+    pb = make_problem(f"star_M{M}_P{P}", d, h, M, r_lo, r_hi, n_lo, n_hi, gap, seed, omega,
+                      phi, P, **kw)
+    rng = np.random.Generator(np.random.PCG64(seed + 5_000_000))
+    a1 = pb.radius / (1.0 + a2_rel)
+    rot = rng.uniform(0.0, 2.0 * math.pi, size=M)
+    pb.shape = np.stack([a1, a2_rel * a1, np.full(M, float(a3)), rot], axis=1)
+    pb.shape_nodes = int(shape_nodes)
+    return pb
 
 
 def empty_slab(omega=10.0, phi=-math.pi / 5, d=1.0, h=0.5, n_layer=STACK, **kw) -> Problem:

@@ -48,6 +48,8 @@ def main(argv=None):
     ap.add_argument("--restart", type=int, default=800)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default="warm_start.npz")
+    ap.add_argument("--load", default=None,
+                    help="evaluate the network stored in this file (no training)")
     a = ap.parse_args(argv)
 
     import torch
@@ -56,8 +58,13 @@ def main(argv=None):
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    loaded = None
+    if a.load:
+        loaded = np.load(a.load)
+        a.width, a.layers, a.k, a.p_out = (int(v) for v in loaded["config"])
     net = Network(a.width, a.layers, a.k, a.p_out)
-    net.set_params(inputs.nn_init(a.width, a.layers, a.p_out, seed=a.seed))
+    net.set_params(inputs.nn_init(a.width, a.layers, a.p_out, seed=a.seed) if loaded is None
+                   else loaded["theta"])
     anchors = {}   # one live context per (omega, phi) keeps the shared layer factors
 
     def build(pb):
@@ -69,6 +76,8 @@ def main(argv=None):
 
     t0 = time.perf_counter()
     ids, train_iters = [], []
+    if loaded is not None:
+        a.n_train, a.epochs = 0, 0
     for i in range(a.n_train):
         pb = inputs.warm_problem(i, M_range=(a.M_lo, a.M_hi))
         ctx = build(pb)
@@ -130,8 +139,8 @@ def main(argv=None):
     summary = dict(
         n_train=a.n_train, n_held=a.n_held, M_range=[a.M_lo, a.M_hi], epochs=a.epochs,
         lr=a.lr, width=a.width, layers=a.layers, k=a.k, p_out=a.p_out,
-        data_seconds=t_data, train_seconds=t_train, final_loss=losses[-1],
-        loss_curve=losses, train_iters_mean=float(np.mean(train_iters)),
+        data_seconds=t_data, train_seconds=t_train, final_loss=losses[-1] if losses else None,
+        loss_curve=losses, train_iters_mean=float(np.mean(train_iters)) if train_iters else None,
         held_iters_cold_mean=float(ic.mean()), held_iters_warm_mean=float(iw.mean()),
         held_seconds_cold=float(tcs.sum()), held_seconds_warm=float(tws.sum()),
         held_err_single_mean=float(np.mean([r["err_single"] for r in rows])),
@@ -139,6 +148,14 @@ def main(argv=None):
         held_rejected=int(sum(r["rejected"] for r in rows)),
         held_warm_vs_cold_max=float(max(r["warm_vs_cold"] for r in rows)),
         rows=rows)
+    if loaded is not None:
+        # evaluation of a stored network: keep the record of its training
+        prev = json.loads(str(loaded["summary"]))
+        for k in ("n_train", "M_range", "epochs", "lr", "data_seconds", "train_seconds",
+                  "final_loss", "loss_curve", "train_iters_mean"):
+            if k in prev:
+                summary[k] = prev[k]
+        summary["evaluated_from"] = a.load
     log("[summary] " + json.dumps({k: v for k, v in summary.items() if k != "rows"}))
     theta = net.get_params()
     np.savez(a.out, theta=theta,
