@@ -363,6 +363,53 @@ def relaxed_m1000(a, torch, ctx, beta, err, use_graph, use_overlap, M, P, NB, fl
                                                "coefficients in + chunk partials out"}}}
 
 
+def shapes_m1000(a, torch):
+    """Non-circular inclusions (paper eq. par1, three lobes, a2/a1 = 1/3, turned at
+    random) on the M=1000 workload's packing: build time (including every inclusion's
+    integral equation), plain FP64 and relaxed mixed solves/s in the headline's
+    configuration, and the error against the stored oracle solution."""
+    import numpy as np
+    from paper_1412_7466_amd import inputs
+    from paper_1412_7466_amd.grating import Context, GRT_FP32_RELAXED
+    pb = inputs.star_m1000()
+    gold = None
+    gpath = os.path.join(ROOT, "tests", "golden", "star_m1000_oracle.npz")
+    if os.path.exists(gpath):
+        gold = dict(np.load(gpath))
+        if str(gold["digest"]) != pb.digest():
+            gold = None
+    ctx = Context(0)
+    ctx.set_problem(pb)
+    t0 = time.perf_counter()
+    ctx.build()
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    ctx.set_table(True)
+    ctx.set_table32(True)
+    ctx.set_overlap(True)
+    if not a.no_autotune:
+        ctx.autotune()
+    out = {"workload": (f"star_m1000: the m1000 packing (M=1000, P=15, omega=20) with "
+                        f"three-lobed inclusions of eq. par1 (a2/a1 = 1/3, random rotations), "
+                        f"{pb.shape_nodes} boundary nodes each, GMRES to {a.tol:g}"),
+           "build_s": t_build}
+    for key, kw in (("fp64", {}), ("relaxed_mixed", {"precision": GRT_FP32_RELAXED})):
+        kw = dict(tol=a.tol, restart=a.restart, graph=True, **kw)
+        ctx.solve(**kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            beta, st = ctx.solve(**kw)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / a.steps
+        og = ctx.bragg(beta)
+        out[key] = {"solves_per_s": 1.0 / el, "iters": st.iters, "fp32_applies": st.fp32_applies,
+                    "rel_resid": st.rel_resid, "flux_err": float(og["flux_err"]),
+                    "err_vs_oracle": oracle_error(beta, ctx, gold) if gold is not None else None}
+    ctx.close()
+    return out
+
+
 def sweep(a, torch):
     """Held-out geometries of the warm-start set (one grid cell: omega = 20, one angle):
     plain FP64 solves one after another against one batched solve, first with the
@@ -796,6 +843,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-shapes", action="store_true",
+                    help="skip the non-circular inclusion workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="end with a plain device copy of this size (counter calibration)")
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -1037,6 +1086,8 @@ def main():
     if not a.no_sweep:
         res["sweep"] = sweep(a, torch)
         res["sweep_small"] = small_sweep(a, torch)
+    if not a.no_shapes:
+        res["shapes_m1000"] = shapes_m1000(a, torch)
     if a.batch_workload > 0:
         res["batch_workload"] = batch_config(a, torch, a.batch_workload)
     if a.block_workload > 0:

@@ -71,10 +71,24 @@ typedef struct {
   double pinv_eps;
 } grt_layers;
 
-/* M disks (paper sec. 4, 5): centres (x, y), radius and refractive index. */
+/* M inclusions (paper sec. 4, 5): centres (x, y), radius and refractive index.
+ * shape NULL: disks of that radius (the Mie diagonal scattering matrix of sec. 4.1).
+ * shape non-NULL: non-circular inclusions of the paper's class (eq. par1), host
+ * [M][4] = (a1, a2, a3, rot) per inclusion, boundary rho(t) (cos(t + rot),
+ * sin(t + rot)), rho = a1 + a2 cos(a3 t), with a1 > 0, |a2| < a1, a3 an integer in
+ * [1, 64]; radius[m] must be its enclosing circle a1 + |a2| (it serves the packing
+ * checks, the near-pair rule and the normalisation D); shape_nodes (even, 16..512;
+ * 0: 64) boundary nodes of each inclusion's integral equation (eqs. intg1, intg2),
+ * solved at build time for the dense (2P+1)^2 scattering matrix (formula for s_ln;
+ * copies turned by rot need no separate treatment: each inclusion is solved as
+ * given).  Shapes need P <= 20 and one angle; the block translation, field
+ * evaluation and the warm-start network take disks only (GRT_EUNSUP); single and
+ * batched solves, FP64 and mixed, take both. */
 typedef struct {
   int64_t M;
   const double *x, *y, *radius, *n_incl;
+  const double* shape;
+  int shape_nodes;
 } grt_inclusions;
 
 /* Plane wave of frequency omega (k_l = omega * n_l), angle phi from the downward
@@ -220,6 +234,13 @@ grt_status grt_set_table(grt_ctx* ctx, int mode);
  * FP32 translation is the matrix-core block product).  Batched mixed solves use the
  * tables of the contexts that have one when the batch is created. */
 grt_status grt_set_table32(grt_ctx* ctx, int on);
+
+/* The block-diagonal scattering matrix of sec. 4.1 (after grt_build or
+ * grt_build_translation): out_dev (device, [M][2P+1][2P+1] complex FP64, caller
+ * owned; block m row l = outgoing order l, column n = incoming order n, index + P)
+ * receives the dense blocks of non-circular inclusions or the Mie diagonal of
+ * disks. */
+grt_status grt_scattering_blocks(grt_ctx* ctx, void* out_dev);
 /* Launch-shape autotuner: times the translation launch, with the pass that adds
  * its per-chunk partial results, for source chunk counts giving 256 .. 16384
  * wavefronts, in the current mode (on the fly or resident table) and in its two

@@ -158,6 +158,7 @@ __device__ __forceinline__ cd group_total(cd v, cd* red, int lane, int grp) {
 // y = sum_c pT[c]                                (mode 1, T x)
 // y = sum_c pB[c] + pL                           (mode 2, B_phys A^+ C x, or alpha0)
 // y = s o (sum_c pB[c] + pL)                     (mode 3, right-hand side)
+// y = sum_c pT[c] - sum_c pB[c] - pL             (mode 4: w of y = x - S w, dense S)
 // then y *= oscale when given.  Any of the parts may be absent.
 __global__ void __launch_bounds__(256) combine_kernel(int nbeta, const cd* x, const cd* s,
                                                       const cd* pT, int nT, const cd* pB, int nB,
@@ -175,6 +176,7 @@ __global__ void __launch_bounds__(256) combine_kernel(int nbeta, const cd* x, co
   if (mode == 0) v = x[i] - s[i] * (t - b);
   else if (mode == 1) v = t;
   else if (mode == 2) v = b;
+  else if (mode == 4) v = t - b;
   else v = s[i] * b;
   y[i] = oscale ? oscale[i] * v : v;
 }
@@ -285,7 +287,8 @@ __global__ void __launch_bounds__(256) combine_mixed_kernel(int nbeta, const cd*
   if (grp != 0 || !live) return;
   t += pN[i];
   b += pL[i];
-  const cd v = x[i] - s[i] * (t - b);
+  // without s: the vector w of y = x - S w (dense scattering matrices)
+  const cd v = s ? x[i] - s[i] * (t - b) : t - b;
   y[i] = oscale ? oscale[i] * v : v;
 }
 
@@ -507,9 +510,13 @@ static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode,
     }
   }
   int n = (int)c->n_beta;
+  // non-circular inclusions: w = T x - B x first, then y = x - S w with the blocks
+  const bool dense = c->d_sblk && mode == 0;
   combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
       n, x, c->d_mie, c->d_pT, needT ? c->m2l_nchunks : 0, c->d_pB, needB ? c->b_nchunks : 0,
-      needB ? c->d_pL : nullptr, y, mode, oscale);
+      needB ? c->d_pL : nullptr, dense ? c->d_wS : y, dense ? 4 : mode,
+      dense ? nullptr : oscale);
+  if (dense) launch_sblock_apply(c, x, c->d_wS, y, 0, oscale, s);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
@@ -548,9 +555,11 @@ grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y, const double* oscale) {
     st = lowrank_tail(c, c->d_gvec);
     if (st != GRT_OK) return st;
   }
+  const bool dense = c->d_sblk != nullptr;
   combine_mixed_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
-      n, x, c->d_mie, c->d_pT32, c->m2l_nchunks, c->d_pN, c->d_pB, c->b_nchunks, c->d_pL, y,
-      oscale);
+      n, x, dense ? nullptr : c->d_mie, c->d_pT32, c->m2l_nchunks, c->d_pN, c->d_pB,
+      c->b_nchunks, c->d_pL, dense ? c->d_wS : y, dense ? nullptr : oscale);
+  if (dense) launch_sblock_apply(c, x, c->d_wS, y, 0, oscale, s);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
@@ -562,8 +571,11 @@ grt_status rhs_b(grt_ctx* c, cd* b) {
   grt_status st = lowrank_tail(c, c->d_f);
   if (st != GRT_OK) return st;
   int n = (int)c->n_beta;
+  const bool dense = c->d_sblk != nullptr;
   combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, c->stream>>>(
-      n, nullptr, c->d_mie, nullptr, 0, c->d_pB, c->b_nchunks, c->d_pL, b, 3, nullptr);
+      n, nullptr, c->d_mie, nullptr, 0, c->d_pB, c->b_nchunks, c->d_pL, dense ? c->d_wS : b,
+      dense ? 2 : 3, nullptr);
+  if (dense) launch_sblock_apply(c, nullptr, c->d_wS, b, 1, nullptr, c->stream);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }

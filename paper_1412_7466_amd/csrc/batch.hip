@@ -54,6 +54,10 @@ struct InstDesc {
   // resident FP32 table of the well-separated pairs (mixed apply; null: on the fly)
   const cf* table32;
   int mpad32;
+  // non-circular inclusions: dense scattering-matrix blocks [M][2P+1][2P+1] and the
+  // problem's w vector of y = x - S w (null: the Mie diagonal)
+  const cd* sblk;
+  cd* wS;
   int split;  // 2: FP64 on-the-fly translation as two half-output launches
   // 0 once the lockstep solver has no further use for this problem's applies: every
   // apply kernel then skips its work items and the combine writes zeros
@@ -281,11 +285,43 @@ __global__ void __launch_bounds__(BT) combine_batched(const InstDesc* __restrict
     cd y;
     if (mode == 0) {
       const cd t = chunks_sum(q.pT, q.m2l_nchunks, q.nbeta, loc);
+      if (q.sblk) {   // dense blocks: w here, y in sblock_batched
+        q.wS[loc] = t - b;
+        continue;
+      }
       y = X[i] - q.mie[loc] * (t - b);
     } else {
+      if (q.sblk) {
+        q.wS[loc] = b;
+        continue;
+      }
       y = q.mie[loc] * b;
     }
     Y[i] = dn[i] * y;
+  }
+}
+
+// Second pass for the problems with dense scattering-matrix blocks:
+// Y = D o (x - S w) (mode 0) or Y = D o (S w) (mode 1), w from the combine.
+__global__ void __launch_bounds__(BT) sblock_batched(const InstDesc* __restrict__ D,
+                                                     const int* __restrict__ seg2inst,
+                                                     const cd* __restrict__ X,
+                                                     const double* __restrict__ dn, cd* Y,
+                                                     int mode) {
+  const int seg = blockIdx.x;
+  const InstDesc& q = D[seg2inst[seg]];
+  if (!q.sblk || (mode == 0 && !q.active)) return;
+  const int nb = q.nb;
+  for (int r = 0; r < SEG / BT; ++r) {
+    const int64_t i = (int64_t)seg * SEG + r * BT + threadIdx.x;
+    const int64_t loc = i - q.off;
+    if (loc >= q.nbeta) continue;
+    const int64_t j = loc / nb;
+    const cd* row = q.sblk + (size_t)loc * nb;
+    const cd* wj = q.wS + (size_t)j * nb;
+    cd acc{0.0, 0.0};
+    for (int n = 0; n < nb; ++n) cmac(acc, row[n], wj[n]);
+    Y[i] = dn[i] * (mode == 0 ? X[i] - acc : acc);
   }
 }
 
@@ -306,6 +342,10 @@ __global__ void __launch_bounds__(BT) combine_mixed_batched(const InstDesc* __re
     }
     const cd b = q.pL[loc] + chunks_sum(q.pB, q.b_nchunks, q.nbeta, loc);
     const cd t = q.pN[loc] + chunks_sum(q.pT32, q.m2l_nchunks, q.nbeta, loc);
+    if (q.sblk) {   // dense blocks: w here, y in sblock_batched
+      q.wS[loc] = t - b;
+      continue;
+    }
     Y[i] = dn[i] * (X[i] - q.mie[loc] * (t - b));
   }
 }
@@ -584,6 +624,7 @@ struct grt_batch {
   // apply translates all of them at once on the owner's FP32 matrix-core product
   grt_ctx* block_owner = nullptr;
   int64_t block_stride = 0;   // distance between consecutive instances' vectors
+  bool any_shapes = false;    // some problem has dense scattering-matrix blocks
 };
 
 static grt_status bset(grt_batch* b, grt_status s, const std::string& m) {
@@ -721,6 +762,8 @@ static grt_status batch_apply_core(grt_batch* b, bool mixed) {
                                                  b->wout);
   else
     combine_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, b->xtmp, b->d_dnorm, b->wout, 0);
+  if (b->any_shapes)
+    sblock_batched<<<b->nseg, BT, 0, s>>>(b->dd, b->d_seg2inst, b->xtmp, b->d_dnorm, b->wout, 0);
   BHIP(b, hipGetLastError());
   return GRT_OK;
 }
@@ -756,6 +799,8 @@ static grt_status batch_apply(grt_batch* b, const cd* xh, bool use_graph, bool m
 static grt_status batch_rhs_hat(grt_batch* b, cd* Y) {
   BTRY(batch_lowrank(b, 1));
   combine_batched<<<b->nseg, BT, 0, b->stream>>>(b->dd, b->d_seg2inst, nullptr, b->d_dnorm, Y, 1);
+  if (b->any_shapes)
+    sblock_batched<<<b->nseg, BT, 0, b->stream>>>(b->dd, b->d_seg2inst, nullptr, b->d_dnorm, Y, 1);
   BHIP(b, hipGetLastError());
   return GRT_OK;
 }
@@ -1080,6 +1125,9 @@ static grt_status batch_create_impl(grt_batch** out, int64_t n, grt_ctx* const* 
     q.mpad = c->table_mpad;
     q.table32 = c->d_table32;
     q.mpad32 = c->table32_mpad;
+    q.sblk = c->d_sblk;
+    q.wS = c->d_wS;
+    if (c->d_sblk) b->any_shapes = true;
     q.split = c->d_table ? 1 : c->m2l_split;
     q.active = 1;
     q.seg0 = seg;

@@ -47,7 +47,7 @@ void free_all(grt_ctx* c) {
                   c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_htab,
                   c->d_y, c->d_scal, c->d_dotpart, c->d_x32, c->d_pT32,
                   c->d_pN, c->d_noff, c->d_nlist, c->d_dnorm, c->d_dinv, c->d_xtmp, c->d_ntgt, c->d_npart,
-                  c->d_table, c->d_table32};
+                  c->d_table, c->d_table32, c->d_sblk, c->d_wS};
   for (void* p : bufs)
     if (p) hipFree(p);
   c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal =
@@ -67,6 +67,8 @@ void free_all(grt_ctx* c) {
   c->d_npart = nullptr;
   c->d_table = nullptr;
   c->d_table32 = nullptr;
+  c->d_sblk = nullptr;
+  c->d_wS = nullptr;
   c->d_wtmp = nullptr;
   c->krylov_restart = 0;
   c->built = false;
@@ -183,6 +185,30 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
   c->hy.assign(inc->y, inc->y + M);
   c->hr.assign(inc->radius, inc->radius + M);
   c->hn.assign(inc->n_incl, inc->n_incl + M);
+  c->hshape.clear();
+  c->shape_nodes = 0;
+  if (inc->shape && M > 0) {
+    // non-circular inclusions (eq. par1): a1 > 0, |a2| < a1, a3 a positive integer,
+    // radius the enclosing circle a1 + |a2|
+    if (R > 1) return set_err(c, GRT_EUNSUP, "non-circular inclusions with several angles");
+    if (wave->P > 20) return set_err(c, GRT_EUNSUP, "non-circular inclusions need P <= 20");
+    const int nodes = inc->shape_nodes > 0 ? inc->shape_nodes : 64;
+    if (nodes < 16 || nodes > 512 || (nodes & 1))
+      return set_err(c, GRT_EINVAL, "shape_nodes must be even, in [16, 512]");
+    c->hshape.assign(inc->shape, inc->shape + 4 * M);
+    c->shape_nodes = nodes;
+    for (int64_t m = 0; m < M; ++m) {
+      const double a1 = c->hshape[4 * m], a2 = c->hshape[4 * m + 1];
+      const double a3 = c->hshape[4 * m + 2], rot = c->hshape[4 * m + 3];
+      if (!std::isfinite(a1) || !std::isfinite(a2) || !std::isfinite(rot) || !(a1 > 0) ||
+          !(std::fabs(a2) < a1) || !(a3 >= 1 && a3 <= 64 && a3 == std::floor(a3)))
+        return set_err(c, GRT_EINVAL, "bad shape of inclusion " + std::to_string(m));
+      const double rr = a1 + std::fabs(a2);
+      if (!(std::fabs(inc->radius[m] - rr) <= 1e-12 * rr))
+        return set_err(c, GRT_EINVAL, "radius of inclusion " + std::to_string(m) +
+                                          " must be its enclosing circle a1 + |a2|");
+    }
+  }
   for (int64_t m = 0; m < M; ++m) {
     if (!std::isfinite(c->hx[m]) || !std::isfinite(c->hy[m]) || !finite_pos(c->hr[m]) ||
         !finite_pos(c->hn[m]))
@@ -421,6 +447,40 @@ static grt_status check_translation(grt_ctx* c) {
   return GRT_OK;
 }
 
+namespace {
+// out[m][l][n] = mie[m][l] if l == n, else 0
+__global__ void mie_blocks_kernel(int64_t tot, int nb, const cd* mie, cd* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tot) return;
+  const int64_t m = e / ((int64_t)nb * nb);
+  const int r = (int)(e - m * nb * nb);
+  const int l = r / nb, n = r - l * nb;
+  out[e] = l == n ? mie[m * nb + l] : cd{0.0, 0.0};
+}
+}  // namespace
+
+grt_status grt_scattering_blocks(grt_ctx* c, void* out) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_translation(c);
+  if (st != GRT_OK) return st;
+  if (!out) return set_err(c, GRT_EINVAL, "null output");
+  const int nb = 2 * c->P + 1;
+  const size_t n = (size_t)c->M * nb * nb;
+  if (n == 0) return GRT_OK;
+  cd* o = static_cast<cd*>(out);
+  if (c->d_sblk) {
+    GRT_HIP(c, hipMemcpyAsync(o, c->d_sblk, sizeof(cd) * n, hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    // disks: the Mie diagonal
+    const int64_t tot = (int64_t)n;
+    mie_blocks_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, c->stream>>>(tot, nb, c->d_mie, o);
+    GRT_HIP(c, hipGetLastError());
+  }
+  GRT_HIP(c, hipStreamSynchronize(c->stream));
+  return GRT_OK;
+}
+
+
 extern "C++" {
 // Run fn(context of angle r, offset of its vectors) for every right-hand side.
 template <typename F>
@@ -493,6 +553,8 @@ grt_status grt_apply_ST_block(grt_ctx* c, const void* x, void* y) {
   if (st != GRT_OK) return st;
   if (!x || !y || x == y) return set_err(c, GRT_EINVAL, "bad vectors");
   if (c->M == 0) return GRT_OK;
+  if (has_shapes(c))
+    return set_err(c, GRT_EUNSUP, "the block translation takes disks (Mie diagonal) only");
   st = block_ready(c);
   if (st != GRT_OK) return st;
   st = block_product(c, static_cast<const cd*>(x), c->n_beta, c->d_dnorm, (int)c->n_rhs, c->stream);

@@ -132,6 +132,13 @@ struct grt_ctx {
   cd* d_table = nullptr;    // [M][4P+1][Mpad]
   int table_mpad = 0;
   int table_lanes = 1;      // lanes per target in the table kernel (1 or 2)
+  // non-circular inclusions: host shapes [M][4] = (a1, a2, a3, rot), boundary nodes
+  // of each one's integral equation, the resident scattering-matrix blocks
+  // [M][2P+1][2P+1] (row = outgoing order) and the apply's S w scratch vector
+  std::vector<double> hshape;
+  int shape_nodes = 0;
+  cd* d_sblk = nullptr;
+  cd* d_wS = nullptr;      // [n_beta]
   // resident FP32 table of the well-separated pairs (mixed-precision apply only)
   bool want_table32 = false;
   cf* d_table32 = nullptr;  // [M][4P+1][Mpad], near pairs zero
@@ -196,6 +203,13 @@ grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* s
 grt_status autotune_coupling(grt_ctx* c);
 constexpr int M2L_TUNE_MAX_WAVES = 16384;
 size_t table_bytes(const grt_ctx* c);
+
+// non-circular inclusions (inclusion.hip)
+bool has_shapes(const grt_ctx* c);
+grt_status build_scattering_blocks(grt_ctx* c);
+// y = x - S w (mode 0) or y = S w (mode 1), S the resident blocks; then y *= oscale
+void launch_sblock_apply(grt_ctx* c, const cd* x, const cd* w, cd* y, int mode,
+                         const double* oscale, hipStream_t s);
 
 // block translation of several right-hand sides on FP32 matrix cores (block.hip)
 int block_nbk(int P);

@@ -768,6 +768,12 @@ static grt_status build_inclusions(grt_ctx* c) {
     l2l_table_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, L, g.k[1], c->d_cx, c->d_cy,
                                                             c->d_l2l);
     GRT_HIP(c, hipGetLastError());
+    // non-circular inclusions: dense scattering-matrix blocks (sec. 4.1) in place of
+    // the Mie diagonal, which then serves only the enclosing circles' normalisation
+    if (has_shapes(c)) {
+      grt_status st = build_scattering_blocks(c);
+      if (st != GRT_OK) return st;
+    }
   }
   GRT_HIP(c, hipStreamSynchronize(s));
   return GRT_OK;

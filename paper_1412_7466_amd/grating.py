@@ -31,7 +31,8 @@ class grt_layers(C.Structure):
 
 class grt_inclusions(C.Structure):
     _fields_ = [("M", C.c_int64), ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
-                ("radius", C.POINTER(C.c_double)), ("n_incl", C.POINTER(C.c_double))]
+                ("radius", C.POINTER(C.c_double)), ("n_incl", C.POINTER(C.c_double)),
+                ("shape", C.POINTER(C.c_double)), ("shape_nodes", C.c_int)]
 
 
 class grt_incidence(C.Structure):
@@ -81,6 +82,7 @@ _PROTOS = {
     "grt_incident": (C.c_int, [_VP, _VP]),
     "grt_set_table": (C.c_int, [_VP, C.c_int]),
     "grt_set_table32": (C.c_int, [_VP, C.c_int]),
+    "grt_scattering_blocks": (C.c_int, [_VP, _VP]),
     "grt_table_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "grt_set_launch": (C.c_int, [_VP, C.c_int, C.c_int]),
     "grt_set_overlap": (C.c_int, [_VP, C.c_int]),
@@ -211,6 +213,11 @@ class Context:
                       for a in (pb.x, pb.y, pb.radius, pb.n_incl)]
         inc = grt_inclusions(M=pb.M, x=_dptr(self._arrs[0]), y=_dptr(self._arrs[1]),
                              radius=_dptr(self._arrs[2]), n_incl=_dptr(self._arrs[3]))
+        shape = getattr(pb, "shape", None)
+        if shape is not None:
+            self._arrs.append(np.ascontiguousarray(shape, dtype=np.float64).reshape(-1))
+            inc.shape = _dptr(self._arrs[4])
+            inc.shape_nodes = int(pb.shape_nodes)
         if phis is not None and len(phis) > 1:
             self._phis = np.ascontiguousarray(phis, dtype=np.float64)
             wave = grt_incidence(omega=pb.omega, phi=float(self._phis[0]), P=pb.P,
@@ -298,6 +305,16 @@ class Context:
         self._enter()
         self._check(self.lib.grt_set_table(self.h, int(mode)))
         self._leave()
+
+    def scattering_blocks(self):
+        """The block-diagonal scattering matrix, [M][2P+1][2P+1] complex (device)."""
+        nb = 2 * self.pb.P + 1
+        out = self.torch.zeros((self.pb.M, nb, nb), dtype=self.torch.complex128,
+                               device=f"cuda:{self.device}")
+        self._enter()
+        self._check(self.lib.grt_scattering_blocks(self.h, _VP(out.data_ptr())))
+        self._leave()
+        return out
 
     def set_table32(self, on=True):
         """Resident FP32 table of the well-separated pairs for the mixed-precision

@@ -291,12 +291,21 @@ def star(M, P, omega=10.0, seed=9, phi=-math.pi / 5, d=1.0, h=0.5, a2_rel=1.0 / 
     rotation U[0, 2 pi) per inclusion from a second seeded stream."""
     pb = make_problem(f"star_M{M}_P{P}", d, h, M, r_lo, r_hi, n_lo, n_hi, gap, seed, omega,
                       phi, P, **kw)
+    pb.name = f"star_M{M}_P{P}"
     rng = np.random.Generator(np.random.PCG64(seed + 5_000_000))
     a1 = pb.radius / (1.0 + a2_rel)
     rot = rng.uniform(0.0, 2.0 * math.pi, size=M)
     pb.shape = np.stack([a1, a2_rel * a1, np.full(M, float(a3)), rot], axis=1)
     pb.shape_nodes = int(shape_nodes)
     return pb
+
+
+def star_m1000(phi=-math.pi / 5, **kw) -> Problem:
+    """The M=1000 workload's packing (seed 2, enclosing radii U[0.004, 0.012], indices
+    U[1.5, 3.0], gap 0.002, omega=20, P=15) with three-lobed inclusions of eq. par1,
+    a2 / a1 = 1/3, turned at random: the same enclosing circles as m1000."""
+    return star(1000, 15, omega=20.0, seed=2, phi=phi, d=1.0, h=1.0, r_lo=0.004, r_hi=0.012,
+                n_lo=1.5, n_hi=3.0, gap=0.002, **kw)
 
 
 def empty_slab(omega=10.0, phi=-math.pi / 5, d=1.0, h=0.5, n_layer=STACK, **kw) -> Problem:

@@ -2,6 +2,8 @@
 
   tests/golden/m1000_oracle.npz      M=1000, P=15, omega=20 (the benchmarked workload)
   tests/golden/m1000_p20_oracle.npz  the same geometry at P=20
+  tests/golden/star_m1000_oracle.npz the same packing with three-lobed non-circular
+                                     inclusions (eq. par1), P=15
 
 Each holds the CPU FP64 oracle's GMRES solution to a 1e-12 normalised residual,
 its Bragg amplitudes and flux error, the diagonal normalisation D = |H_|n|(k2 r_m)|
@@ -13,7 +15,7 @@ Calls only oracle/ (and the seeded input generator).  About 10 minutes (P=15) an
 20 minutes (P=20) on 8 cores, 3-5 GB of memory: the oracle stores the image-summed
 Hankel generator of every (target, source) pair.
 
-    python tests/golden/make_m1000_oracle.py [m1000|m1000_p20]
+    python tests/golden/make_m1000_oracle.py [m1000|m1000_p20|star_m1000]
 """
 import os
 import sys

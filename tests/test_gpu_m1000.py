@@ -140,6 +140,29 @@ def test_m1000_p20():
         ctx.close()
 
 
+def test_star_m1000():
+    """Non-circular inclusions (eq. par1) on the M=1000 packing: K and T on the stored
+    probe, the FP64 and relaxed mixed solutions and their Bragg amplitudes against the
+    oracle (tests/golden/star_m1000_oracle.npz)."""
+    from paper_1412_7466_amd.grating import GRT_FP32_RELAXED
+    if not os.path.exists(os.path.join(GOLD, "star_m1000_oracle.npz")):
+        pytest.skip("tests/golden/star_m1000_oracle.npz not generated")
+    torch, ctx, gold, pb = _load("star_m1000")
+    try:
+        _check_apply(torch, ctx, gold, pb, "star_m1000")
+        beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000)
+        say(f"[gpu] star_m1000 FP64 iters={st.iters} resid={st.rel_resid:.2e} {st.seconds:.3f}s")
+        _check_solution(ctx, beta, gold, pb, "star_m1000 FP64")
+        ctx.set_table32(True)
+        beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000, precision=GRT_FP32_RELAXED,
+                             inner_tol=1e-6)
+        say(f"[gpu] star_m1000 relaxed iters={st.iters} fp32={st.fp32_applies} "
+            f"resid={st.rel_resid:.2e}")
+        _check_solution(ctx, beta, gold, pb, "star_m1000 relaxed")
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("inst", [9, 25, 29])
 def test_batched_workload_instances(inst):
     """Instances of the batched workload with a stored oracle LU solution
