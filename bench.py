@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # library's kernels are built without: their FP32 ceiling is the FP64 rate above)
 FP32_VALU_PEAK_TFLOPS = 157.3
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "m2l_table_traffic_m1000.md")
+TRAFFIC32_MD = os.path.join(ROOT, "profiles", "m2l_table32_traffic_m1000.md")
 KERNEL_SOURCES = ["translate.h", "apply.hip", "dev_bessel.h", "dev_common.h"]
 
 
@@ -50,13 +51,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_traffic(kernel):
+def committed_traffic(kernel, md=TRAFFIC_MD):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None
     when there is none or the kernel sources changed since it was taken."""
     import re
-    if not os.path.exists(TRAFFIC_MD):
+    if not os.path.exists(md):
         return None
-    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_MD).read(), re.S)
+    m = re.search(r"```json\n(.*?)\n```", open(md).read(), re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
@@ -89,7 +90,8 @@ def committed_flops(kernel, avg_ms):
             "frac": tf / FP64_VALU_PEAK_TFLOPS, "source": os.path.relpath(FLOPS_MD, ROOT)}
 
 
-def record_traffic(fetch_db, write_db, kernel, copy_bytes, commands):
+def record_traffic(fetch_db, write_db, kernel, copy_bytes, commands, md=TRAFFIC_MD,
+                   title="the resident-table translation kernel"):
     """Write the counter summary: FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the
     kernel, each scaled by what the same counter reads for the plain device copy of
     copy_bytes bytes in the same run."""
@@ -120,8 +122,8 @@ def record_traffic(fetch_db, write_db, kernel, copy_bytes, commands):
            "fetch_scale": sf, "write_scale": sw,
            "hbm_bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw,
            "copy_read_write_GBps": copy_gbs}
-    with open(TRAFFIC_MD, "w") as f:
-        f.write("# HBM traffic of the resident-table translation kernel, M=1000, P=15\n\n")
+    with open(md, "w") as f:
+        f.write(f"# HBM traffic of {title}, M=1000, P=15\n\n")
         f.write("Two rocprofv3 counter runs of the benchmark (table mode, default launch shape) "
                 "with a plain device copy of known size appended; each counter is scaled by "
                 "what it reads for the copy.\n\nCommands (repository root, one MI355X):\n\n"
@@ -139,7 +141,7 @@ FP64_COUNTERS = ["SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_
                  "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU",
                  "SQ_INSTS_VALU_FLOPS_FP32", "SQ_WAVES"]
 FLOP_KERNELS = ["m2l_table_kernel<15>", "m2l_table2_kernel<15>", "m2l_kernel<15, cd>",
-                "m2l_kernel<15, cf>"]
+                "m2l_kernel<15, cf>", "m2l_table32_kernel<15>"]
 
 
 def record_flops(db, commands):
@@ -523,7 +525,7 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
     """Many small problems (one angle, shared layer factors): one after another
     against one batched solve."""
     from paper_1412_7466_amd import inputs
-    from paper_1412_7466_amd.grating import Batch, Context, GRT_FP32
+    from paper_1412_7466_amd.grating import Batch, Context, GRT_FP32_RELAXED
     pbs = [inputs.warm_problem(1000 + i, held_out=True, M_range=M_range, P=15, omegas=(20.0,),
                                phis=(-math.pi / 5,))
            for i in range(n)]
@@ -553,10 +555,10 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
     batch.solve(tol=a.tol, restart=a.restart, graph=True)
     torch.cuda.synchronize()
     t_bgraph = time.perf_counter() - t
-    batch.solve(tol=a.tol, restart=a.restart, graph=True, precision=GRT_FP32)
+    batch.solve(tol=a.tol, restart=a.restart, graph=True, precision=GRT_FP32_RELAXED)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    bm, _ = batch.solve(tol=a.tol, restart=a.restart, graph=True, precision=GRT_FP32)
+    bm, _ = batch.solve(tol=a.tol, restart=a.restart, graph=True, precision=GRT_FP32_RELAXED)
     torch.cuda.synchronize()
     t_bmixed = time.perf_counter() - t
     res = {"workload": (f"{n} geometries of the warm-start rules with M uniform in "
@@ -564,7 +566,7 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
            "plain_fp64_sequential_solves_per_s": n / t_plain,
            "batched_fp64_solves_per_s": n / t_batch,
            "batched_graph_fp64_solves_per_s": n / t_bgraph,
-           "batched_graph_mixed_solves_per_s": n / t_bmixed,
+           "batched_graph_mixed_relaxed_solves_per_s": n / t_bmixed,
            "batched_mixed_max_rel_diff_vs_plain": max(
                float(torch.linalg.norm(b - p) / torch.linalg.norm(p))
                for b, (p, _) in zip(bm, plain)),
@@ -863,16 +865,22 @@ def main():
     if a.flops_record:
         cmd = (f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc {' '.join(FP64_COUNTERS)} "
                f"--kernel-include-regex 'm2l_' -d $OUT/pmc_fp64 -o run -- python3 "
-               f"$REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-sweep --no-autotune")
+               f"$REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-sweep --no-autotune "
+               f"--no-shapes")
         print(json.dumps(record_flops(a.flops_record, [cmd])))
         return
     if a.traffic_record:
         cmds = [f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc {c} --kernel-include-regex "
-                f"'m2l_table_kernel|copyBuffer' -d $OUT/pmc_{c.lower()} -o run -- "
-                f"python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-sweep "
-                f"--no-autotune --copy-probe-mib 1024" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+                f"'m2l_table_kernel|m2l_table32_kernel|copyBuffer' -d $OUT/pmc_{c.lower()} "
+                f"-o run -- python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline "
+                f"--no-sweep --no-autotune --no-shapes --copy-probe-mib 1024"
+                for c in ("FETCH_SIZE", "WRITE_SIZE")]
         print(json.dumps(record_traffic(a.traffic_record[0], a.traffic_record[1],
                                         "m2l_table_kernel<15>", 1024 * 1024 * 1024, cmds)))
+        print(json.dumps(record_traffic(a.traffic_record[0], a.traffic_record[1],
+                                        "m2l_table32_kernel<15>", 1024 * 1024 * 1024, cmds,
+                                        md=TRAFFIC32_MD,
+                                        title="the FP32 resident-table kernel of the mixed apply")))
         return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); "
