@@ -125,7 +125,8 @@ typedef struct {
                       in FP64                                                 */
   double inner_tol;/* GRT_FP32: relative tolerance of each inner solve (0: 1e-5).
                       GRT_FP32_RELAXED: relative residual below which the
-                      applies use K32 (0: 1e3 tol, at most 1e-2)              */
+                      applies use K32 (0: 1e5 tol, at most 1e-2: tol / (10 e)
+                      for the FP32 apply's relative error e of about 1e-7) */
   int max_refine;  /* GRT_FP32: most refinement steps (0: 10)                */
   int use_graph;   /* 1: every apply of K is replayed from a HIP graph captured
                       once per operator (dropped when the table, the launch

@@ -1312,7 +1312,7 @@ grt_status grt_batch_solve(grt_batch* b, const grt_solve_opts* o, void* const* b
   if (o->precision == GRT_FP64 || o->precision == GRT_FP32_RELAXED) {
     const double sw = o->precision == GRT_FP64 ? 0.0
                       : o->inner_tol > 0      ? o->inner_tol
-                                              : std::min(1e-2, 1e3 * tol);
+                                              : std::min(1e-2, 1e5 * tol);
     BTRY(batch_gmres(b, false, Bv, X, tol, maxit, m, o->use_x0 != 0, use_graph, r, sw,
                      &fast_steps));
   } else {

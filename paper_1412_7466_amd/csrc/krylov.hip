@@ -470,7 +470,7 @@ grt_status gmres_solve(grt_ctx* c, const grt_solve_opts* o, cd* x, grt_solve_sta
   CoreResult r;
   if (o->precision == GRT_FP64 || o->precision == GRT_FP32_RELAXED) {
     const bool relax = o->precision == GRT_FP32_RELAXED;
-    const double sw = o->inner_tol > 0 ? o->inner_tol : std::min(1e-2, 1e3 * tol);
+    const double sw = o->inner_tol > 0 ? o->inner_tol : std::min(1e-2, 1e5 * tol);
     GRT_TRY(gmres_core(c, apply_K, bvec, x, tol, maxit, m, &r, o->use_x0 != 0, graph,
                        relax ? apply_K_mixed : nullptr, sw));
     st->x0_rejected = r.x0_rejected ? 1 : 0;

@@ -370,7 +370,7 @@ class Context:
         """GMRES to tol (FP64 residual).  precision GRT_FP32: FP64 refinement around
         inner solves on the mixed operator (inner_tol 0: 1e-5); GRT_FP32_RELAXED: one
         FP64 GMRES whose applies switch to the mixed operator below inner_tol (0:
-        1e3 tol, at most 1e-2).  Returns (beta, stats) (lists of stats with several
+        1e5 tol, at most 1e-2).  Returns (beta, stats) (lists of stats with several
         angles)."""
         beta = self.new_vec() if out is None else out
         if x0 is not None:
