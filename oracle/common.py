@@ -65,6 +65,16 @@ class Geometry:
         self.cy = np.asarray(pb.y, float)
         self.rad = np.asarray(pb.radius, float)
         self.kp = pb.omega * np.asarray(pb.n_incl, float)
+        # polarisation: TM (u = E_z, u and du/dn continuous) or TE (u = H_z, u and
+        # (1/eps) du/dn continuous, eps = n^2).  For TE each layer's potentials carry
+        # the factor pv = eps of their layer and the flux rows the factor 1/eps of the
+        # layer whose field they take (so the hypersingular parts still cancel); TM
+        # has both factors 1.
+        self.te = getattr(pb, "polarization", "TM") == "TE"
+        self.eps = tuple(n ** 2 for n in pb.n_layer)
+        self.eps_incl = np.asarray(pb.n_incl, float) ** 2
+        self.pv = self.eps if self.te else (1.0, 1.0, 1.0)
+        self.fl = tuple(1.0 / e for e in self.eps) if self.te else (1.0, 1.0, 1.0)
         self.kappa = self.k1 * np.sin(pb.phi)
         self.alpha = np.exp(1j * self.kappa * self.d)
         self.cosphi = np.cos(pb.phi)

@@ -27,6 +27,9 @@ printed in sec. 5, which does not reproduce Graf's theorem.)
 
 Sign convention: A alpha + C beta = f and beta = S (T beta + B_phys alpha); the
 paper's B equals -B_phys.
+
+TE polarisation: the flux rows of C take (1/eps_2) d/dy and B_phys's single- and
+double-layer parts carry the middle layer's eps_2 (see oracle/layered.py).
 """
 from __future__ import annotations
 
@@ -66,7 +69,8 @@ def assemble_C(G):
     for y_line, sgn, rv, rn in ((G.h, -1.0, "g1v", "g1n"), (-G.h, 1.0, "g2v", "g2n")):
         yt = np.full_like(xg, y_line)
         C[R[rv]] = sgn * _particle_field_block(G, xg, yt, None, three)
-        C[R[rn]] = sgn * _particle_field_block(G, xg, yt, up, three)
+        # flux rows: (1/eps_2) d/dy for TE (the inclusions sit in the middle layer)
+        C[R[rn]] = sgn * G.fl[1] * _particle_field_block(G, xg, yt, up, three)
     yw = G.yw[1]
     for rr, tdir in (("w2v", None), ("w2d", (1.0, 0.0))):
         blk = 0
@@ -94,8 +98,9 @@ def assemble_Bphys(G):
             S = S + G.alpha ** l * sgn * outgoing(-n, k, vx, vy)
             _, gy = grad_wave(outgoing, -n, k, vx, vy)
             D = D + G.alpha ** l * sgn * gy
-        B[:, :, G.col[cs]] = 0.25j * G.hs * S
-        B[:, :, G.col[cm]] = 0.25j * G.hs * D
+        # the middle layer's potentials carry eps_2 for TE
+        B[:, :, G.col[cs]] = G.pv[1] * 0.25j * G.hs * S
+        B[:, :, G.col[cm]] = G.pv[1] * 0.25j * G.hs * D
     Q2 = G.Q[1]
     q = np.arange(-Q2, Q2 + 1)[None, None, :]
     cx2, cy2 = G.jc[1]

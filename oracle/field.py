@@ -187,6 +187,8 @@ class Field:
 
     def __init__(self, red, beta, n_fine=16384):
         G = self.G = red.G
+        if G.te:
+            raise NotImplementedError("field evaluation is written for TM")
         self.beta = np.zeros(0) if G.M == 0 else np.asarray(beta)
         # interior expansions exist for disks only; for the non-circular inclusions the
         # field is available outside their enclosing circles

@@ -26,6 +26,14 @@ Readings taken here, where the paper is silent or ambiguous:
     and the x-derivative on both walls;
   * columns of A are equilibrated to unit 2-norm before the pseudo-inverse.
 
+TE polarisation (u = H_z; the paper treats TM only): u and (1/eps) du/dn are
+continuous (eps = n^2).  Each layer's potentials carry the factor pv = eps of that
+layer and every interface flux row takes (1/eps) d/dn of the field on its side, so
+the hypersingular parts still cancel (flux rows keep [T_diff, -I + N_diff]); the
+value rows become [(pv_a + pv_b)/2 I + pv_a D_a - pv_b D_b, pv_a S_a - pv_b S_b],
+whose single-layer part is now log-singular on the line (weighted difference); J
+expansions in flux rows carry 1/eps of their layer.  TM is pv = 1, 1/eps -> 1.
+
 Column order: mu1, sig1, mu2, sig2, a2, a1, a3, c, d.
 Row order: Gamma_1 (value, normal), Gamma_2 (value, normal), wall 2 (value,
 x-derivative), wall 1, wall 3, Gamma_u (value, y-derivative), Gamma_d.
@@ -93,11 +101,13 @@ def _wall_cancelled(G, k, yw, sy_line, deriv):
     return S, D
 
 
-def self_kernel_split(ka, kb):
+def self_kernel_split(ka, kb, wa=1.0, wb=1.0):
     """Log split K(s) = phi(s) ln|s| + psi(s) of the flat-line kernel differences.
 
-    S_{ka} - S_{kb}: K(s) = (i/4)[H_0(ka|s|) - H_0(kb|s|)],
-        phi(s) = -[J_0(ka s) - J_0(kb s)] / (2 pi),   psi(0) = -ln(ka/kb) / (2 pi).
+    wa S_{ka} - wb S_{kb}: K(s) = (i/4)[wa H_0(ka|s|) - wb H_0(kb|s|)],
+        phi(s) = -[wa J_0(ka s) - wb J_0(kb s)] / (2 pi),
+        psi(0) = (wa - wb)(i/4 - gamma/(2 pi)) - [wa ln(ka/2) - wb ln(kb/2)] / (2 pi)
+        (= -ln(ka/kb) / (2 pi) for wa = wb = 1).
     T_{ka} - T_{kb}: K(s) = (i/4)[ka H_1(ka|s|) - kb H_1(kb|s|)] / |s|,
         phi(s) = -[ka J_1(ka s) - kb J_1(kb s)] / (2 pi s),  phi(0) = -(ka^2 - kb^2) / (4 pi),
         psi(0) = i (ka^2 - kb^2)/8 - [ka^2 ln(ka/2) - kb^2 ln(kb/2)] / (4 pi)
@@ -108,7 +118,7 @@ def self_kernel_split(ka, kb):
     """
     def phiS(s):
         s = np.abs(np.asarray(s, float))
-        return -(sp.j0(ka * s) - sp.j0(kb * s)) / (2 * np.pi)
+        return -(wa * sp.j0(ka * s) - wb * sp.j0(kb * s)) / (2 * np.pi)
 
     def phiT(s):
         s = np.abs(np.asarray(s, float))
@@ -118,15 +128,17 @@ def self_kernel_split(ka, kb):
         return np.where(z, -(ka ** 2 - kb ** 2) / (4 * np.pi), v)
 
     g = np.euler_gamma
-    psiS0 = -np.log(ka / kb) / (2 * np.pi)
+    psiS0 = ((wa - wb) * (0.25j - g / (2 * np.pi))
+             - (wa * np.log(ka / 2) - wb * np.log(kb / 2)) / (2 * np.pi))
     psiT0 = (0.125j * (ka ** 2 - kb ** 2)
              - (ka ** 2 * np.log(ka / 2) - kb ** 2 * np.log(kb / 2)) / (4 * np.pi)
              + (ka ** 2 - kb ** 2) * (1 - 2 * g) / (8 * np.pi))
-    return phiS, phiT, 0.0, -(ka ** 2 - kb ** 2) / (4 * np.pi), psiS0, psiT0
+    return (phiS, phiT, -(wa - wb) / (2 * np.pi), -(ka ** 2 - kb ** 2) / (4 * np.pi), psiS0,
+            psiT0)
 
 
-def self_line_blocks(G, ka, kb):
-    """Same-line blocks S_{ka} - S_{kb} and T_{ka} - T_{kb} with zeta correction.
+def self_line_blocks(G, ka, kb, wa=1.0, wb=1.0):
+    """Same-line blocks wa S_{ka} - wb S_{kb} and T_{ka} - T_{kb} with zeta correction.
 
     Returns (Sd, Td), each [N, N], acting on the density at the N nodes of the
     central copy; the three copies are folded in with alpha^l.
@@ -140,7 +152,7 @@ def self_line_blocks(G, ka, kb):
         a = np.abs(s)
         mask = a > 0
         aa = np.where(mask, a, 1.0)
-        ks = 0.25j * (sp.hankel1(0, ka * aa) - sp.hankel1(0, kb * aa))
+        ks = 0.25j * (wa * sp.hankel1(0, ka * aa) - wb * sp.hankel1(0, kb * aa))
         kt = 0.25j * (ka * sp.hankel1(1, ka * aa) - kb * sp.hankel1(1, kb * aa)) / aa
         ks = np.where(mask, ks, 0)
         kt = np.where(mask, kt, 0)
@@ -148,7 +160,7 @@ def self_line_blocks(G, ka, kb):
         Td += G.alpha ** l * kt * hs
     # local corrections on the (2K+1)-point stencil around each target
     p = np.arange(-K, K + 1)
-    phiS, phiT, phiS0, phiT0, psiS0, psiT0 = self_kernel_split(ka, kb)
+    phiS, phiT, phiS0, phiT0, psiS0, psiT0 = self_kernel_split(ka, kb, wa, wb)
     sv = p * hs
     wS = correction_weights(phiS(sv), phiS0, psiS0, hs, K)
     wT = correction_weights(phiT(sv), phiT0, psiT0, hs, K)
@@ -187,38 +199,39 @@ def assemble_A(G):
     yt1 = np.full(N, h)
     yt2 = np.full(N, -h)
     eye = np.eye(N)
-    # --- Gamma_1 rows: (u_1 - u_2) and d/dy of it
-    Sd1, Td1 = self_line_blocks(G, G.k1, G.k2)
-    A[R["g1v"], C["mu1"]] = eye
+    pv, fl = G.pv, G.fl
+    # --- Gamma_1 rows: (u_1 - u_2) and the flux difference (d/dy, times 1/eps for TE)
+    Sd1, Td1 = self_line_blocks(G, G.k1, G.k2, pv[0], pv[1])
+    A[R["g1v"], C["mu1"]] = 0.5 * (pv[0] + pv[1]) * eye
     A[R["g1v"], C["sig1"]] = Sd1
     A[R["g1n"], C["mu1"]] = Td1
     A[R["g1n"], C["sig1"]] = -eye
     S, D = _three_copy(G, G.k2, xg, yt1, -h)
-    A[R["g1v"], C["mu2"]] = -D
-    A[R["g1v"], C["sig2"]] = -S
+    A[R["g1v"], C["mu2"]] = -pv[1] * D
+    A[R["g1v"], C["sig2"]] = -pv[1] * S
     S, D = _three_copy(G, G.k2, xg, yt1, -h, up)
-    A[R["g1n"], C["mu2"]] = -D
-    A[R["g1n"], C["sig2"]] = -S
+    A[R["g1n"], C["mu2"]] = -fl[1] * pv[1] * D
+    A[R["g1n"], C["sig2"]] = -fl[1] * pv[1] * S
     A[R["g1v"], C["a2"]] = -_jblock(G, 1, xg, yt1)
-    A[R["g1n"], C["a2"]] = -_jblock(G, 1, xg, yt1, up)
+    A[R["g1n"], C["a2"]] = -fl[1] * _jblock(G, 1, xg, yt1, up)
     A[R["g1v"], C["a1"]] = _jblock(G, 0, xg, yt1)
-    A[R["g1n"], C["a1"]] = _jblock(G, 0, xg, yt1, up)
-    # --- Gamma_2 rows: (u_2 - u_3) and d/dy of it
-    Sd2, Td2 = self_line_blocks(G, G.k2, G.k3)
+    A[R["g1n"], C["a1"]] = fl[0] * _jblock(G, 0, xg, yt1, up)
+    # --- Gamma_2 rows: (u_2 - u_3) and the flux difference
+    Sd2, Td2 = self_line_blocks(G, G.k2, G.k3, pv[1], pv[2])
     S, D = _three_copy(G, G.k2, xg, yt2, h)
-    A[R["g2v"], C["mu1"]] = D
-    A[R["g2v"], C["sig1"]] = S
+    A[R["g2v"], C["mu1"]] = pv[1] * D
+    A[R["g2v"], C["sig1"]] = pv[1] * S
     S, D = _three_copy(G, G.k2, xg, yt2, h, up)
-    A[R["g2n"], C["mu1"]] = D
-    A[R["g2n"], C["sig1"]] = S
-    A[R["g2v"], C["mu2"]] = eye
+    A[R["g2n"], C["mu1"]] = fl[1] * pv[1] * D
+    A[R["g2n"], C["sig1"]] = fl[1] * pv[1] * S
+    A[R["g2v"], C["mu2"]] = 0.5 * (pv[1] + pv[2]) * eye
     A[R["g2v"], C["sig2"]] = Sd2
     A[R["g2n"], C["mu2"]] = Td2
     A[R["g2n"], C["sig2"]] = -eye
     A[R["g2v"], C["a2"]] = _jblock(G, 1, xg, yt2)
-    A[R["g2n"], C["a2"]] = _jblock(G, 1, xg, yt2, up)
+    A[R["g2n"], C["a2"]] = fl[1] * _jblock(G, 1, xg, yt2, up)
     A[R["g2v"], C["a3"]] = -_jblock(G, 2, xg, yt2)
-    A[R["g2n"], C["a3"]] = -_jblock(G, 2, xg, yt2, up)
+    A[R["g2n"], C["a3"]] = -fl[2] * _jblock(G, 2, xg, yt2, up)
     # --- wall rows: alpha u(L) - u(R), value and x-derivative
     right = (1.0, 0.0)
     for lay, rv, rd, lines in ((1, "w2v", "w2d", ((h, "mu1", "sig1"), (-h, "mu2", "sig2"))),
@@ -229,8 +242,8 @@ def assemble_A(G):
         for deriv, rr in ((False, rv), (True, rd)):
             for ys, cm, cs in lines:
                 S, D = _wall_cancelled(G, k, yw, ys, deriv)
-                A[R[rr], C[cm]] = D
-                A[R[rr], C[cs]] = S
+                A[R[rr], C[cm]] = pv[lay] * D
+                A[R[rr], C[cs]] = pv[lay] * S
             td = right if deriv else None
             JL = _jblock(G, lay, np.full_like(yw, -G.d / 2), yw, td)
             JR = _jblock(G, lay, np.full_like(yw, G.d / 2), yw, td)
@@ -240,11 +253,11 @@ def assemble_A(G):
     yu = np.full_like(xu, G.y0)
     E = np.exp(1j * G.kapn[None, :] * xu[:, None])
     S, D = _three_copy(G, G.k1, xu, yu, h)
-    A[R["uv"], C["mu1"]] = D
-    A[R["uv"], C["sig1"]] = S
+    A[R["uv"], C["mu1"]] = pv[0] * D
+    A[R["uv"], C["sig1"]] = pv[0] * S
     S, D = _three_copy(G, G.k1, xu, yu, h, up)
-    A[R["un"], C["mu1"]] = D
-    A[R["un"], C["sig1"]] = S
+    A[R["un"], C["mu1"]] = pv[0] * D
+    A[R["un"], C["sig1"]] = pv[0] * S
     A[R["uv"], C["a1"]] = _jblock(G, 0, xu, yu)
     A[R["un"], C["a1"]] = _jblock(G, 0, xu, yu, up)
     A[R["uv"], C["c"]] = -E
@@ -252,11 +265,11 @@ def assemble_A(G):
     # --- Gamma_d rows: u_3 - sum d_n e^{i kappa_n x}, d/dy likewise
     yd = -yu
     S, D = _three_copy(G, G.k3, xu, yd, -h)
-    A[R["dv"], C["mu2"]] = D
-    A[R["dv"], C["sig2"]] = S
+    A[R["dv"], C["mu2"]] = pv[2] * D
+    A[R["dv"], C["sig2"]] = pv[2] * S
     S, D = _three_copy(G, G.k3, xu, yd, -h, up)
-    A[R["dn"], C["mu2"]] = D
-    A[R["dn"], C["sig2"]] = S
+    A[R["dn"], C["mu2"]] = pv[2] * D
+    A[R["dn"], C["sig2"]] = pv[2] * S
     A[R["dv"], C["a3"]] = _jblock(G, 2, xu, yd)
     A[R["dn"], C["a3"]] = _jblock(G, 2, xu, yd, up)
     A[R["dv"], C["d"]] = -E
@@ -265,9 +278,10 @@ def assemble_A(G):
 
 
 def rhs_f(G):
-    """Right-hand side f of eq. Arhs: -u_inc and -du_inc/dy on Gamma_1, zero elsewhere."""
+    """Right-hand side f of eq. Arhs: -u_inc and -du_inc/dy (times 1/eps_1 for TE) on
+    Gamma_1, zero elsewhere."""
     f = np.zeros(G.n_rows, complex)
     ui = G.u_inc(G.xg, G.h)
     f[G.row["g1v"]] = -ui
-    f[G.row["g1n"]] = -(-1j * G.k1 * G.cosphi) * ui
+    f[G.row["g1n"]] = -G.fl[0] * (-1j * G.k1 * G.cosphi) * ui
     return f

@@ -82,6 +82,8 @@ class Reduced:
         # or, for the non-circular inclusions of eq. par1, a dense (2P+1)^2 block per
         # inclusion from its boundary integral equation (self.S, [M][2P+1][2P+1])
         self.S = None
+        if getattr(pb, "shape", None) is not None and G.M and G.te:
+            raise NotImplementedError("non-circular inclusions are written for TM")
         if getattr(pb, "shape", None) is not None and G.M:
             sh = np.asarray(pb.shape, float)
             self.S = np.stack([scattering_matrix(a1, a2, a3, rot, G.k2, kp, G.P,
@@ -89,7 +91,8 @@ class Reduced:
                                for (a1, a2, a3, rot), kp in zip(sh, G.kp)])
             self.s = None
         else:
-            self.s = (mie_coefficients(G.k2, G.kp, G.rad, G.P).reshape(-1) if G.M
+            te = dict(eps2=G.eps[1], epsp=G.eps_incl) if G.te else {}
+            self.s = (mie_coefficients(G.k2, G.kp, G.rad, G.P, **te).reshape(-1) if G.M
                       else np.zeros(0))
         n = np.abs(np.arange(-G.P, G.P + 1))
         self.D = (np.abs(sp.hankel1(n[None, :], G.k2 * G.rad[:, None])).reshape(-1)
@@ -186,8 +189,10 @@ class Reduced:
         prop1 = (np.abs(G.k1n.imag) == 0) & (G.k1n.real > 0)
         prop3 = (np.abs(G.k3n.imag) == 0) & (G.k3n.real > 0)
         inc = G.k1 * G.cosphi
+        # TE: the energy flux of a wave is (k_y / eps) |amplitude|^2
+        t3 = G.eps[0] / G.eps[2] if G.te else 1.0
         Rn = np.where(prop1, G.k1n.real * np.abs(c) ** 2 / inc, 0.0)
-        Tn = np.where(prop3, G.k3n.real * np.abs(d) ** 2 / inc, 0.0)
+        Tn = np.where(prop3, t3 * G.k3n.real * np.abs(d) ** 2 / inc, 0.0)
         flux = abs(Rn.sum() + Tn.sum() - 1.0)
         return dict(orders=G.rb, c=c, d=d, R=Rn, T=Tn, prop1=prop1, prop3=prop3,
                     flux_err=flux)

@@ -63,6 +63,9 @@ class Problem:
     # shape_nodes: boundary nodes of each inclusion's integral equation.
     shape: Optional[np.ndarray] = None
     shape_nodes: int = 64
+    # "TM" (the paper's polarisation: u = E_z, u and du/dn continuous) or "TE"
+    # (u = H_z: u and (1/eps) du/dn continuous, eps = n^2)
+    polarization: str = "TM"
 
     @property
     def M(self) -> int:
@@ -83,6 +86,8 @@ class Problem:
         if self.shape is not None:
             hsh.update(np.ascontiguousarray(self.shape, dtype=np.float64).tobytes())
             hsh.update(np.int64(self.shape_nodes).tobytes())
+        if self.polarization != "TM":
+            hsh.update(self.polarization.encode())
         return hsh.hexdigest()[:16]
 
 
