@@ -48,6 +48,7 @@ typedef enum {
 } grt_status;
 
 typedef enum { GRT_FP64 = 0, GRT_FP32 = 1, GRT_FP32_RELAXED = 2 } grt_precision;
+typedef enum { GRT_TM = 0, GRT_TE = 1 } grt_polarization;
 
 typedef struct grt_ctx grt_ctx;
 
@@ -104,6 +105,12 @@ typedef struct {
   int P;
   int64_t n_rhs;
   const double* phis;
+  /* GRT_TM (0, the paper's case: u = E_z, u and du/dn continuous) or GRT_TE (1:
+   * u = H_z, u and (1/eps) du/dn continuous, eps = n^2 of each medium; each layer's
+   * potentials then carry eps of the layer and the flux rows 1/eps, the Mie
+   * coefficients weight the radial derivatives by 1/eps, and the transmitted flux by
+   * eps_1/eps_3).  TE takes disks only and no field evaluation (GRT_EUNSUP). */
+  int polarization;
 } grt_incidence;
 
 typedef struct {

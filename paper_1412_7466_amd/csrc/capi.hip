@@ -175,6 +175,10 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
       return set_err(c, GRT_EINVAL, "|phi| must be < pi/2");
   }
   if (wave->P < 1 || wave->P > 40) return set_err(c, GRT_EINVAL, "P must be in [1, 40]");
+  if (wave->polarization != GRT_TM && wave->polarization != GRT_TE)
+    return set_err(c, GRT_EINVAL, "polarization must be GRT_TM or GRT_TE");
+  if (wave->polarization == GRT_TE && inc->shape && inc->M > 0)
+    return set_err(c, GRT_EUNSUP, "non-circular inclusions are TM only");
   if (!supported_P(wave->P)) return set_err(c, GRT_EUNSUP, "multipole order P not compiled in");
   const int64_t M = inc->M;
   if (M < 0 || M > 10000000) return set_err(c, GRT_EINVAL, "bad M");
@@ -270,6 +274,12 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
     g.k[l] = wave->omega * L.n_layer[l];
     g.Nw[l] = L.Nw[l];
     g.Q[l] = L.Q[l];
+  }
+  g.te = wave->polarization == GRT_TE ? 1 : 0;
+  for (int l = 0; l < 3; ++l) {
+    const double eps = L.n_layer[l] * L.n_layer[l];
+    g.pv[l] = g.te ? eps : 1.0;
+    g.fl[l] = g.te ? 1.0 / eps : 1.0;
   }
   g.kappa = g.k[0] * std::sin(phi0);
   g.alpha = cd{std::cos(g.kappa * L.d), std::sin(g.kappa * L.d)};
@@ -730,7 +740,8 @@ __global__ void bragg_finish_kernel(DevGeom g, double k1cos, const cd* cdv, doub
     double v1 = g.k[0] * g.k[0] - kapn * kapn;
     double v3 = g.k[2] * g.k[2] - kapn * kapn;
     double r = v1 > 0 ? sqrt(v1) * cabs2(cdv[i]) / k1cos : 0.0;
-    double t = v3 > 0 ? sqrt(v3) * cabs2(cdv[g.Nrb + i]) / k1cos : 0.0;
+    // TE: the flux of a wave is (k_y / eps) |amplitude|^2
+    double t = v3 > 0 ? (g.pv[0] / g.pv[2]) * sqrt(v3) * cabs2(cdv[g.Nrb + i]) / k1cos : 0.0;
     R[i] = r;
     T[i] = t;
     s += r + t;

@@ -22,6 +22,10 @@ struct DevGeom {
   double k[3];                  // layer wavenumbers (top, middle, bottom)
   double kappa;                 // k_1 sin(phi)
   cd alpha, alpha_inv;          // Bloch phase e^{i kappa d} and its inverse
+  // polarisation factors: the potentials of layer l carry pv[l] and the interface
+  // flux rows fl[l] for the field of layer l (TM: all 1; TE: eps_l and 1/eps_l)
+  double pv[3], fl[3];
+  int te;
   int N, Nu, n_rb_lo, Nrb, zeta_K, P, M;
   int Nw[3], Q[3];
   double jcy[3];                // J-expansion centres (0, jcy[l])

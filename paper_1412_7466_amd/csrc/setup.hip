@@ -69,26 +69,30 @@ __device__ double zeta_odd(double s) {
 }
 
 // The split K(s) = phi(s) ln|s| + psi(s) of the flat-line kernel differences:
-//   S_ka - S_kb: phi = -[J0(ka s) - J0(kb s)] / (2 pi), psi(0) = -ln(ka/kb) / (2 pi)
+//   wa S_ka - wb S_kb: phi = -[wa J0(ka s) - wb J0(kb s)] / (2 pi), phi(0) = -(wa-wb)/(2 pi),
+//     psi(0) = (wa-wb)(i/4 - gamma/(2 pi)) - [wa ln(ka/2) - wb ln(kb/2)]/(2 pi)
+//     (wa = wb = 1 in TM: psi(0) = -ln(ka/kb)/(2 pi); TE weights the layers by eps)
 //   T_ka - T_kb: phi = -[ka J1(ka s) - kb J1(kb s)] / (2 pi s), phi(0) = -(ka^2-kb^2)/(4 pi),
 //     psi(0) = i (ka^2-kb^2)/8 - [ka^2 ln(ka/2) - kb^2 ln(kb/2)]/(4 pi) + (ka^2-kb^2)(1-2 gamma)/(8 pi)
 // (small-argument series of J0, Y0, J1, Y1; the hypersingular parts cancel).
-__device__ void phi_vals(double ka, double kb, double s, bool tker, double& phi) {
+__device__ void phi_vals(double ka, double kb, double s, bool tker, double wa, double wb,
+                         double& phi) {
   if (s == 0.0) {
-    phi = tker ? -(ka * ka - kb * kb) / (4.0 * GRT_PI) : 0.0;
+    phi = tker ? -(ka * ka - kb * kb) / (4.0 * GRT_PI) : -(wa - wb) / (2.0 * GRT_PI);
     return;
   }
   double a0, a1, b0, b1, ya0, ya1, yb0, yb1;
   bessel01(ka * s, a0, a1, ya0, ya1);
   bessel01(kb * s, b0, b1, yb0, yb1);
-  phi = tker ? -(ka * a1 - kb * b1) / (2.0 * GRT_PI * s) : -(a0 - b0) / (2.0 * GRT_PI);
+  phi = tker ? -(ka * a1 - kb * b1) / (2.0 * GRT_PI * s) : -(wa * a0 - wb * b0) / (2.0 * GRT_PI);
 }
 
 // Single thread: Fornberg finite-difference weights on the stencil -K..K (unit
 // spacing), then the zeta-corrected trapezoid weights for the four self blocks
 //   w_p = hs sum_k 2 zeta'(-2k)/(2k)! c^{(2k)}_p phi(p hs) + [p = 0] hs (psi(0) + phi(0) ln(hs / 2 pi)),
 //   2 zeta'(-2k)/(2k)! = (-1)^k zeta(2k+1) / (2 pi)^{2k}.
-__global__ void zeta_weights_kernel(int K, double hs, double k1, double k2, double k3, cd* w) {
+__global__ void zeta_weights_kernel(int K, double hs, double k1, double k2, double k3, double pv0,
+                                    double pv1, double pv2, cd* w) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int n = 2 * K + 1;
   const int m = 2 * K;
@@ -125,10 +129,14 @@ __global__ void zeta_weights_kernel(int K, double hs, double k1, double k2, doub
     bool tker = blk & 1;
     double ka = (blk < 2) ? k1 : k2;
     double kb = (blk < 2) ? k2 : k3;
-    double phi0 = tker ? -(ka * ka - kb * kb) / (4.0 * GRT_PI) : 0.0;
+    double wa = (blk < 2) ? pv0 : pv1;   // S blocks: layer weights (TE: eps)
+    double wb = (blk < 2) ? pv1 : pv2;
+    double phi0 = tker ? -(ka * ka - kb * kb) / (4.0 * GRT_PI) : -(wa - wb) / (2.0 * GRT_PI);
     cd psi0;
     if (!tker) {
-      psi0 = cd{-log(ka / kb) / (2.0 * GRT_PI), 0.0};
+      psi0 = cd{-(wa - wb) * gam / (2.0 * GRT_PI) -
+                    (wa * log(0.5 * ka) - wb * log(0.5 * kb)) / (2.0 * GRT_PI),
+                0.25 * (wa - wb)};
     } else {
       double d2 = ka * ka - kb * kb;
       psi0 = cd{-(ka * ka * log(0.5 * ka) - kb * kb * log(0.5 * kb)) / (4.0 * GRT_PI) +
@@ -137,7 +145,7 @@ __global__ void zeta_weights_kernel(int K, double hs, double k1, double k2, doub
     }
     for (int j = 0; j < n; ++j) {
       double ph;
-      phi_vals(ka, kb, fabs((double)(j - K)) * hs, tker, ph);
+      phi_vals(ka, kb, fabs((double)(j - K)) * hs, tker, wa, wb, ph);
       double acc = 0.0;
       for (int k = 1; k <= K; ++k) acc += zc[k] * c[2 * k][j];
       cd wj{hs * acc * ph, 0.0};
@@ -217,7 +225,7 @@ __device__ void wall_cancelled(const DevGeom& g, double k, double y, int j, doub
 // Same-line self block entry (target node i, source node j) of S_ka - S_kb or
 // T_ka - T_kb: punctured three-copy trapezoid sum plus stencil corrections.
 __device__ cd self_entry(const DevGeom& g, double ka, double kb, bool tker, const cd* wc, int i,
-                         int j) {
+                         int j, double wa = 1.0, double wb = 1.0) {
   cd acc{0, 0};
   const int N = g.N, K = g.zeta_K;
   for (int l = -1; l <= 1; ++l) {
@@ -227,7 +235,8 @@ __device__ cd self_entry(const DevGeom& g, double ka, double kb, bool tker, cons
       cd ha0, ha1, hb0, hb1;
       hankel01(ka * s, ha0, ha1);
       hankel01(kb * s, hb0, hb1);
-      cd kv = tker ? times_i((0.25 / s) * (ka * ha1 - kb * hb1)) : times_i(0.25 * (ha0 - hb0));
+      cd kv = tker ? times_i((0.25 / s) * (ka * ha1 - kb * hb1))
+                   : times_i(0.25 * (wa * ha0 - wb * hb0));
       acc += (g.hs) * (w * kv);
     }
     int p = j + l * N - i;
@@ -277,18 +286,21 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
     case RB_G1N: {
       bool dv = (rb == RB_G1N);
       double tx = -0.5 * d + (i + 0.5) * g.hs, ty = h;
+      // layer factors: potentials of layer l carry pv[l]; flux rows take fl[l] of the
+      // field of layer l (the self blocks' T and identity parts are unchanged)
       switch (cb) {
         case CB_MU1:
           return dv ? self_entry(g, k1, k2, true, g.wcorr + 1 * K2, i, j)
-                    : (i == j ? cd{1, 0} : zero);
+                    : (i == j ? cd{0.5 * (g.pv[0] + g.pv[1]), 0} : zero);
         case CB_SIG1:
-          return dv ? (i == j ? cd{-1, 0} : zero) : self_entry(g, k1, k2, false, g.wcorr, i, j);
+          return dv ? (i == j ? cd{-1, 0} : zero)
+                    : self_entry(g, k1, k2, false, g.wcorr, i, j, g.pv[0], g.pv[1]);
         case CB_MU2:
         case CB_SIG2:
           three_copy(g, k2, tx, ty, j, -h, dv, 0.0, 1.0, S, D);
-          return -(cb == CB_MU2 ? D : S);
-        case CB_A2: return -jcol(g, 1, j - g.Q[1], tx, ty, dv, 0.0, 1.0);
-        case CB_A1: return jcol(g, 0, j - g.Q[0], tx, ty, dv, 0.0, 1.0);
+          return -((dv ? g.fl[1] : 1.0) * g.pv[1]) * (cb == CB_MU2 ? D : S);
+        case CB_A2: return -(dv ? g.fl[1] : 1.0) * jcol(g, 1, j - g.Q[1], tx, ty, dv, 0.0, 1.0);
+        case CB_A1: return (dv ? g.fl[0] : 1.0) * jcol(g, 0, j - g.Q[0], tx, ty, dv, 0.0, 1.0);
         default: return zero;
       }
     }
@@ -300,15 +312,15 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
         case CB_MU1:
         case CB_SIG1:
           three_copy(g, k2, tx, ty, j, h, dv, 0.0, 1.0, S, D);
-          return (cb == CB_MU1 ? D : S);
+          return ((dv ? g.fl[1] : 1.0) * g.pv[1]) * (cb == CB_MU1 ? D : S);
         case CB_MU2:
           return dv ? self_entry(g, k2, k3, true, g.wcorr + 3 * K2, i, j)
-                    : (i == j ? cd{1, 0} : zero);
+                    : (i == j ? cd{0.5 * (g.pv[1] + g.pv[2]), 0} : zero);
         case CB_SIG2:
           return dv ? (i == j ? cd{-1, 0} : zero)
-                    : self_entry(g, k2, k3, false, g.wcorr + 2 * K2, i, j);
-        case CB_A2: return jcol(g, 1, j - g.Q[1], tx, ty, dv, 0.0, 1.0);
-        case CB_A3: return -jcol(g, 2, j - g.Q[2], tx, ty, dv, 0.0, 1.0);
+                    : self_entry(g, k2, k3, false, g.wcorr + 2 * K2, i, j, g.pv[1], g.pv[2]);
+        case CB_A2: return (dv ? g.fl[1] : 1.0) * jcol(g, 1, j - g.Q[1], tx, ty, dv, 0.0, 1.0);
+        case CB_A3: return -(dv ? g.fl[2] : 1.0) * jcol(g, 2, j - g.Q[2], tx, ty, dv, 0.0, 1.0);
         default: return zero;
       }
     }
@@ -322,7 +334,7 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
       bool bot_line = (cb == CB_MU2 || cb == CB_SIG2);
       if ((top_line && lay != 2) || (bot_line && lay != 0)) {
         wall_cancelled(g, k, y, j, top_line ? h : -h, dv, S, D);
-        return (cb == CB_MU1 || cb == CB_MU2) ? D : S;
+        return g.pv[lay] * ((cb == CB_MU1 || cb == CB_MU2) ? D : S);
       }
       if (cb == jcb) {
         int q = j - g.Q[lay];
@@ -340,11 +352,11 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
       double k = upper ? k1 : k3;
       if (upper && (cb == CB_MU1 || cb == CB_SIG1)) {
         three_copy(g, k, tx, ty, j, h, dv, 0.0, 1.0, S, D);
-        return cb == CB_MU1 ? D : S;
+        return g.pv[0] * (cb == CB_MU1 ? D : S);
       }
       if (!upper && (cb == CB_MU2 || cb == CB_SIG2)) {
         three_copy(g, k, tx, ty, j, -h, dv, 0.0, 1.0, S, D);
-        return cb == CB_MU2 ? D : S;
+        return g.pv[2] * (cb == CB_MU2 ? D : S);
       }
       if (upper && cb == CB_A1) return jcol(g, 0, j - g.Q[0], tx, ty, dv, 0.0, 1.0);
       if (!upper && cb == CB_A3) return jcol(g, 2, j - g.Q[2], tx, ty, dv, 0.0, 1.0);
@@ -412,7 +424,8 @@ __global__ void build_Wv_kernel(const cd* VH, int ldv, const double* E, int i0, 
 // Mie coefficients of every disk (sec. 4.1), s_{-n} = s_n:
 //   s_n = -[k2 J_n'(x) J_n(y) - kp J_n(x) J_n'(y)] / [k2 H_n'(x) J_n(y) - kp H_n(x) J_n'(y)],
 // x = k2 R, y = kp R; Z_n' = Z_{n-1} - (n/x) Z_n, Z_0' = -Z_1.
-__global__ void mie_kernel(int M, int P, double k2, const double* rad, const double* kp, cd* s) {
+__global__ void mie_kernel(int M, int P, double k2, const double* rad, const double* kp, cd* s,
+                           int te, double eps2, double omega) {
   int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
   double R = rad[m];
@@ -431,8 +444,11 @@ __global__ void mie_kernel(int M, int P, double k2, const double* rad, const dou
     double djx = (n == 0) ? -jx[1] : jx[n - 1] - (n / x) * jx[n];
     double djy = (n == 0) ? -jy[1] : jy[n - 1] - (n / y) * jy[n];
     cd dH = (n == 0) ? -H[1] : H[n - 1] - (n / x) * H[n];
-    double num = k2 * djx * jy[n] - kp[m] * jx[n] * djy;
-    cd den = (k2 * jy[n]) * dH - (kp[m] * djy) * H[n];
+    // TE weights the radial derivatives by 1/eps of each side
+    const double w2 = te ? k2 / eps2 : k2;
+    const double wp = te ? omega * omega / kp[m] : kp[m];   // kp / eps_p = omega^2 / kp
+    double num = w2 * djx * jy[n] - wp * jx[n] * djy;
+    cd den = (w2 * jy[n]) * dH - (wp * djy) * H[n];
     cd sn = cdiv(cd{-num, 0.0}, den);
     s[(size_t)m * nb + P + n] = sn;
     s[(size_t)m * nb + P - n] = sn;
@@ -491,9 +507,24 @@ __global__ void rhs_f_kernel(DevGeom g, double k1cos, int n_g, cd* f) {
     int i = r % g.N;
     double x = -0.5 * g.d + (i + 0.5) * g.hs;
     cd ui = cexpi(g.kappa * x - k1cos * g.h);
-    v = (r < g.N) ? -ui : times_i(k1cos * ui);
+    // flux row: fl0 du_inc/dy; stored divided by fl1, the factor the W1 columns of the
+    // flux rows carry (so that W1 (f - C x) keeps C x in its TM form)
+    v = (r < g.N) ? -ui : (g.fl[0] / g.fl[1]) * times_i(k1cos * ui);
   }
   f[r] = v;
+}
+
+// TE: the flux rows of C x take 1/eps_2 (folded into the columns of W1 for those
+// rows) and the middle layer's potentials carry eps_2 (folded into the rows of W2 for
+// the interface densities), so the apply kernels keep their TM form.
+__global__ void te_fold_kernel(cd* W1, int rank, int n_g, cd* W2, int n_b, int n_dens, int N,
+                               double fl1, double pv1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (k >= rank) return;
+  if (i < n_g && ((i >= N && i < 2 * N) || (i >= 3 * N && i < 4 * N)))
+    W1[(size_t)k * n_g + i] = fl1 * W1[(size_t)k * n_g + i];
+  if (i < n_b && i < n_dens) W2[(size_t)i * rank + k] = pv1 * W2[(size_t)i * rank + k];
 }
 
 // y[i] = sum_k W[i][k] x[k], one 64-lane wavefront per row.
@@ -573,7 +604,7 @@ static std::string layer_key(const grt_ctx* c) {
   std::vector<double> v = {L.d, L.h, L.y0, L.n_layer[0], L.n_layer[1], L.n_layer[2], L.pinv_eps,
                            c->inc.omega, c->inc.phi};
   std::vector<int> iv = {c->device, L.N, L.Nw[0], L.Nw[1], L.Nw[2], L.Q[0], L.Q[1], L.Q[2], L.Nu,
-                         L.n_rb_lo, L.Nrb, L.zeta_K};
+                         L.n_rb_lo, L.Nrb, L.zeta_K, c->g.te};
   std::string k(reinterpret_cast<const char*>(v.data()), v.size() * sizeof(double));
   k.append(reinterpret_cast<const char*>(iv.data()), iv.size() * sizeof(int));
   return k;
@@ -672,7 +703,8 @@ static grt_status build_layers(grt_ctx* c) {
   GRT_HIP(c, hipMalloc(&c->d_htab, sizeof(double) * HTAB_SIZE));
   htab_kernel<<<1, 64, 0, s>>>(c->d_htab);
   GRT_HIP(c, hipMalloc(&c->d_wcorr, sizeof(cd) * 4 * (2 * K + 1)));
-  zeta_weights_kernel<<<1, 64, 0, s>>>(K, g.hs, g.k[0], g.k[1], g.k[2], c->d_wcorr);
+  zeta_weights_kernel<<<1, 64, 0, s>>>(K, g.hs, g.k[0], g.k[1], g.k[2], g.pv[0], g.pv[1],
+                                       g.pv[2], c->d_wcorr);
   g.wcorr = c->d_wcorr;
   GRT_HIP(c, hipGetLastError());
 
@@ -738,6 +770,12 @@ static grt_status build_layers(grt_ctx* c) {
     build_W1_kernel<<<g1, 256, 0, s>>>(c->d_U, m, c->d_sv, rank, c->n_g, c->d_W1);
     dim3 g2((rank + 255) / 256, c->n_b);
     build_Wv_kernel<<<g2, 256, 0, s>>>(c->d_VH, n, c->d_colscale, 0, c->n_b, rank, c->d_W2);
+    if (g.te) {
+      const int nmax = std::max(c->n_g, c->n_b);
+      dim3 gt((nmax + 255) / 256, rank);
+      te_fold_kernel<<<gt, 256, 0, s>>>(c->d_W1, rank, c->n_g, c->d_W2, c->n_b,
+                                        g.col_off[CB_A2], g.N, g.fl[1], g.pv[1]);
+    }
     dim3 g3((rank + 255) / 256, 2 * g.Nrb);
     build_Wv_kernel<<<g3, 256, 0, s>>>(c->d_VH, n, c->d_colscale, g.col_off[CB_C], 2 * g.Nrb, rank,
                                        c->d_W3);
@@ -757,7 +795,7 @@ static grt_status build_inclusions(grt_ctx* c) {
   if (c->M > 0) {
     GRT_HIP(c, hipMalloc(&c->d_mie, sizeof(cd) * c->n_beta));
     mie_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, c->P, g.k[1], c->d_rad, c->d_kp,
-                                                      c->d_mie);
+                                                      c->d_mie, g.te, g.pv[1], c->inc.omega);
     GRT_HIP(c, hipMalloc(&c->d_dnorm, sizeof(double) * c->n_beta));
     GRT_HIP(c, hipMalloc(&c->d_dinv, sizeof(double) * c->n_beta));
     GRT_HIP(c, hipMalloc(&c->d_xtmp, sizeof(cd) * c->n_beta));

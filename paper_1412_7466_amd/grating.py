@@ -20,6 +20,7 @@ GRT_OK, GRT_EINVAL, GRT_EGEOM, GRT_ENOMEM, GRT_EHIP, GRT_ENOCONV, GRT_ESTATE, GR
 STATUS_NAMES = {0: "GRT_OK", -1: "GRT_EINVAL", -2: "GRT_EGEOM", -3: "GRT_ENOMEM", -4: "GRT_EHIP",
                 -5: "GRT_ENOCONV", -6: "GRT_ESTATE", -7: "GRT_EUNSUP"}
 GRT_FP64, GRT_FP32, GRT_FP32_RELAXED = 0, 1, 2
+GRT_TM, GRT_TE = 0, 1
 
 
 class grt_layers(C.Structure):
@@ -37,7 +38,8 @@ class grt_inclusions(C.Structure):
 
 class grt_incidence(C.Structure):
     _fields_ = [("omega", C.c_double), ("phi", C.c_double), ("P", C.c_int),
-                ("n_rhs", C.c_int64), ("phis", C.POINTER(C.c_double))]
+                ("n_rhs", C.c_int64), ("phis", C.POINTER(C.c_double)),
+                ("polarization", C.c_int)]
 
 
 class grt_solve_opts(C.Structure):
@@ -218,13 +220,14 @@ class Context:
             self._arrs.append(np.ascontiguousarray(shape, dtype=np.float64).reshape(-1))
             inc.shape = _dptr(self._arrs[4])
             inc.shape_nodes = int(pb.shape_nodes)
+        pol = GRT_TE if getattr(pb, "polarization", "TM") == "TE" else GRT_TM
         if phis is not None and len(phis) > 1:
             self._phis = np.ascontiguousarray(phis, dtype=np.float64)
             wave = grt_incidence(omega=pb.omega, phi=float(self._phis[0]), P=pb.P,
-                                 n_rhs=len(self._phis), phis=_dptr(self._phis))
+                                 n_rhs=len(self._phis), phis=_dptr(self._phis), polarization=pol)
         else:
             wave = grt_incidence(omega=pb.omega, phi=pb.phi if phis is None else float(phis[0]),
-                                 P=pb.P, n_rhs=0, phis=None)
+                                 P=pb.P, n_rhs=0, phis=None, polarization=pol)
         self._check(self.lib.grt_set_problem(self.h, C.byref(lay), C.byref(inc), C.byref(wave)))
         self.pb = pb
         self.sizes = self.query()
