@@ -83,14 +83,35 @@ class Geometry:
         self.kapn = self.kappa + 2 * np.pi * self.rb / self.d
         self.k1n = sqrt_branch(self.k1 ** 2 - self.kapn ** 2)
         self.k3n = sqrt_branch(self.k3 ** 2 - self.kapn ** 2)
-        # interface nodes: cell-centred, equispaced in x, weight d/N
+        # interface nodes: cell-centred, equispaced in x (the graphs' parameter),
+        # trapezoid weight d/N per unit of x
         N = dd.N
         self.N = N
         self.hs = self.d / N
         self.xg = -self.d / 2 + (np.arange(N) + 0.5) * self.hs
         self.y0 = float(dd.y0)
-        # wall nodes: Gauss-Legendre on each layer's wall
-        spans = ((self.h, self.y0), (-self.h, self.h), (-self.y0, -self.h))
+        # interfaces y = f_j(x) (paper secs. 3, 6): flat at +-h, or graphs of period d
+        # with Fourier deviations; at the nodes their heights gy, unit normals gn
+        # (pointing up, (-f', 1) / |(1, f')|), speeds sp = |(1, f')| and second
+        # derivatives f'', and the arc-length weights gw = hs sp
+        iface = getattr(pb, "interface", None)
+        self.curved = iface is not None
+        self.iface = (np.zeros((2, 2, 0)) if iface is None
+                      else np.asarray(iface, float).reshape(2, 2, -1))
+        self.gy, self.gn, self.sp, self.gd2, self.gw = [], [], [], [], []
+        for j in range(2):
+            f0, f1, f2 = (self.f(j, self.xg, q) for q in range(3))
+            sp_ = np.sqrt(1.0 + f1 ** 2)
+            self.gy.append(f0)
+            self.gn.append((-f1 / sp_, 1.0 / sp_))
+            self.sp.append(sp_)
+            self.gd2.append(f2)
+            self.gw.append(self.hs * sp_)
+        # wall nodes: Gauss-Legendre on each layer's wall (the walls end on the
+        # interfaces at x = +-d/2)
+        e1 = float(self.f(0, np.array([self.d / 2]))[0])
+        e2 = float(self.f(1, np.array([self.d / 2]))[0])
+        spans = ((e1, self.y0), (e2, e1), (-self.y0, e2))
         self.yw = []
         for Nw, (a, b) in zip(dd.Nw, spans):
             t, _ = np.polynomial.legendre.leggauss(Nw)
@@ -125,6 +146,20 @@ class Geometry:
         self.n_rows = o
         self.nb = 2 * self.P + 1
         self.n_beta = self.M * self.nb
+
+    def f(self, j, x, q=0):
+        """q-th x-derivative of interface j's height function at the points x."""
+        x = np.asarray(x, float)
+        out = np.full_like(x, (self.h if j == 0 else -self.h) if q == 0 else 0.0)
+        a, b = self.iface[j]
+        for m in range(1, len(a) + 1):
+            w = 2 * np.pi * m / self.d
+            c, s = np.cos(w * x), np.sin(w * x)
+            # d^q/dx^q of a cos(w x) + b sin(w x)
+            dc = (c, -s, -c)[q] * w ** q
+            ds = (s, c, -s)[q] * w ** q
+            out = out + a[m - 1] * dc + b[m - 1] * ds
+        return out
 
     def u_inc(self, x, y):
         """Incident plane wave (top layer only)."""

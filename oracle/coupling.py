@@ -6,8 +6,8 @@ Paper sec. 5 (eqs. repre3_mod, matB, matC):
 
 C maps the outgoing coefficients beta of all inclusions (with their phased near
 copies l = -1, 0, 1) to the rows of the empty-structure system: minus the value
-and y-derivative on Gamma_1 (the row is u_1 - u_2), plus value and y-derivative on
-Gamma_2 (the row is u_2 - u_3), and the middle-layer wall discrepancy, which for a
+and normal derivative on Gamma_1 (the row is u_1 - u_2), plus value and normal
+derivative on Gamma_2 (the row is u_2 - u_3), and the middle-layer wall discrepancy, which for a
 three-copy source cancels to alpha^2 Phi(L - d) - alpha^{-1} Phi(L + 2d) with Phi
 the l = 0 field (and its x-derivative).  All other rows are zero.
 
@@ -28,7 +28,7 @@ printed in sec. 5, which does not reproduce Graf's theorem.)
 Sign convention: A alpha + C beta = f and beta = S (T beta + B_phys alpha); the
 paper's B equals -B_phys.
 
-TE polarisation: the flux rows of C take (1/eps_2) d/dy and B_phys's single- and
+TE polarisation: the flux rows of C take (1/eps_2) d/dn and B_phys's single- and
 double-layer parts carry the middle layer's eps_2 (see oracle/layered.py).
 """
 from __future__ import annotations
@@ -40,13 +40,17 @@ from .common import outgoing, incoming, grad_wave
 
 
 def _particle_field_block(G, tx, ty, tdir, images):
-    """[n_t, M*nb]: field (or derivative along tdir) of unit multipoles beta_m[n].
+    """[n_t, M*nb]: field (or derivative along tdir: scalars or per-target arrays)
+    of unit multipoles beta_m[n].
 
     images: list of (shift_x, weight) pairs applied to the inclusion copies.
     """
     P, M = G.P, G.M
     n = np.arange(-P, P + 1)[None, None, :]
     out = np.zeros((len(tx), M, 2 * P + 1), complex)
+    if tdir is not None:
+        tdir = tuple(np.broadcast_to(np.asarray(t, float), (len(tx),))[:, None, None]
+                     for t in tdir)
     for sx, w in images:
         vx = (tx[:, None] - G.cx[None, :] - sx)[:, :, None]
         vy = (ty[:, None] - G.cy[None, :])[:, :, None]
@@ -63,14 +67,13 @@ def assemble_C(G):
     """Dense C of size [n_rows, M(2P+1)]."""
     C = np.zeros((G.n_rows, G.n_beta), complex)
     R = G.row
-    up = (0.0, 1.0)
     three = [(l * G.d, G.alpha ** l) for l in (-1, 0, 1)]
     xg = G.xg
-    for y_line, sgn, rv, rn in ((G.h, -1.0, "g1v", "g1n"), (-G.h, 1.0, "g2v", "g2n")):
-        yt = np.full_like(xg, y_line)
+    for line, sgn, rv, rn in ((0, -1.0, "g1v", "g1n"), (1, 1.0, "g2v", "g2n")):
+        yt = G.gy[line]
         C[R[rv]] = sgn * _particle_field_block(G, xg, yt, None, three)
-        # flux rows: (1/eps_2) d/dy for TE (the inclusions sit in the middle layer)
-        C[R[rn]] = sgn * G.fl[1] * _particle_field_block(G, xg, yt, up, three)
+        # flux rows: d/dn (times 1/eps_2 for TE: the inclusions sit in the middle layer)
+        C[R[rn]] = sgn * G.fl[1] * _particle_field_block(G, xg, yt, G.gn[line], three)
     yw = G.yw[1]
     for rr, tdir in (("w2v", None), ("w2d", (1.0, 0.0))):
         blk = 0
@@ -87,20 +90,23 @@ def assemble_Bphys(G):
     B = np.zeros((M, nb, G.n_alpha), complex)
     n = np.arange(-P, P + 1)[None, :, None]
     k = G.k2
-    for y_line, cm, cs in ((G.h, "mu1", "sig1"), (-G.h, "mu2", "sig2")):
+    for line, cm, cs in ((0, "mu1", "sig1"), (1, "mu2", "sig2")):
         S = 0
         D = 0
+        nx, ny = (v[None, None, :] for v in G.gn[line])
         for l in (-1, 0, 1):
             vx = (G.xg[None, :] + l * G.d - G.cx[:, None])[:, None, :]
-            vy = (y_line - G.cy[:, None])[:, None, :] + 0 * vx
-            # H_n(k|v|) e^{-in theta_v} = (-1)^n F_{-n}(v)
+            vy = (G.gy[line][None, :] - G.cy[:, None])[:, None, :] + 0 * vx
+            # H_n(k|v|) e^{-in theta_v} = (-1)^n F_{-n}(v); the double layer takes its
+            # derivative along the source normal
             sgn = (-1.0) ** np.abs(n)
             S = S + G.alpha ** l * sgn * outgoing(-n, k, vx, vy)
-            _, gy = grad_wave(outgoing, -n, k, vx, vy)
-            D = D + G.alpha ** l * sgn * gy
-        # the middle layer's potentials carry eps_2 for TE
-        B[:, :, G.col[cs]] = G.pv[1] * 0.25j * G.hs * S
-        B[:, :, G.col[cm]] = G.pv[1] * 0.25j * G.hs * D
+            gx, gy = grad_wave(outgoing, -n, k, vx, vy)
+            D = D + G.alpha ** l * sgn * (nx * gx + ny * gy)
+        # arc-length weights; the middle layer's potentials carry eps_2 for TE
+        w = G.gw[line][None, None, :]
+        B[:, :, G.col[cs]] = G.pv[1] * 0.25j * w * S
+        B[:, :, G.col[cm]] = G.pv[1] * 0.25j * w * D
     Q2 = G.Q[1]
     q = np.arange(-Q2, Q2 + 1)[None, None, :]
     cx2, cy2 = G.jc[1]

@@ -189,6 +189,8 @@ class Field:
         G = self.G = red.G
         if G.te:
             raise NotImplementedError("field evaluation is written for TM")
+        if G.curved:
+            raise NotImplementedError("field evaluation is written for flat interfaces")
         self.beta = np.zeros(0) if G.M == 0 else np.asarray(beta)
         # interior expansions exist for disks only; for the non-circular inclusions the
         # field is available outside their enclosing circles

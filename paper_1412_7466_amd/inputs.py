@@ -7,8 +7,9 @@ no special functions, no linear algebra), so that both the CPU oracle and the
 HIP library can consume the same inputs without sharing any code that computes
 the answer.
 
-Problem statement (paper section 2): a period-d three-layer TM grating, flat
-interfaces Gamma_1 at y=+h and Gamma_2 at y=-h, refractive indices
+Problem statement (paper section 2): a period-d three-layer TM grating, interfaces
+Gamma_1 near y=+h and Gamma_2 near y=-h (flat, or graphs of period d given by
+their Fourier coefficients, as in the paper's section 6), refractive indices
 n_layer = (top, middle, bottom), M disks of radius r_m and index n_m inside the
 middle layer, plane-wave incidence at angle phi measured from the downward
 normal (so the horizontal wavenumber is k_1 sin(phi)), multipole order P.
@@ -66,6 +67,11 @@ class Problem:
     # "TM" (the paper's polarisation: u = E_z, u and du/dn continuous) or "TE"
     # (u = H_z: u and (1/eps) du/dn continuous, eps = n^2)
     polarization: str = "TM"
+    # curved interfaces (graphs of period d, paper secs. 3 and 6): interface[j] =
+    # [[a_1..a_F], [b_1..b_F]] for Gamma_1 (j = 0) and Gamma_2 (j = 1), the graph
+    # y = (+h or -h) + sum_m a_m cos(2 pi m x / d) + b_m sin(2 pi m x / d);
+    # None: both flat.
+    interface: Optional[np.ndarray] = None
 
     @property
     def M(self) -> int:
@@ -88,6 +94,9 @@ class Problem:
             hsh.update(np.int64(self.shape_nodes).tobytes())
         if self.polarization != "TM":
             hsh.update(self.polarization.encode())
+        if self.interface is not None:
+            hsh.update(b"interface")
+            hsh.update(np.ascontiguousarray(self.interface, dtype=np.float64).tobytes())
         return hsh.hexdigest()[:16]
 
 
@@ -189,10 +198,12 @@ def _round_up(v: int, m: int) -> int:
 
 
 def derive_discretization(d, h, n_layer, omega, phi, y_incl, P,
-                          zeta_K=6, pinv_eps=1e-10, N_min=120) -> Discretization:
+                          zeta_K=6, pinv_eps=1e-10, N_min=120, amp=0.0) -> Discretization:
     """Sizes of the discrete problem from the geometry and the frequency.
 
     * y0 = h + d/2; J centres at the middle of each truncated layer.
+    * amp bounds how far a curved interface leaves y = +-h (0 for flat ones); the
+      layers' extents below grow by it.
     * N = max(N_min, ceil(6 d / d_c), ceil(8 k_max d / pi)) rounded up to a
       multiple of 16; d_c is the smallest inclusion-centre-to-interface distance.
     * Q_j = max(ceil(k_j R_j + 15), ceil(ln(1e-14) / ln(R_j / D_j))) with R_j the
@@ -209,20 +220,21 @@ def derive_discretization(d, h, n_layer, omega, phi, y_incl, P,
     y0 = h + d / 2
     hu = (y0 - h) / 2  # half height of the top / bottom truncated layers
     if len(y_incl):
-        dc = float(np.min(np.minimum(h - np.asarray(y_incl), np.asarray(y_incl) + h)))
+        hc = h - amp
+        dc = float(np.min(np.minimum(hc - np.asarray(y_incl), np.asarray(y_incl) + hc)))
         n_dc = math.ceil(6 * d / dc)
     else:
         n_dc = 0
     N = _round_up(max(N_min, n_dc, math.ceil(8 * kmax * d / math.pi)), 16)
     # layer 1 (top) and 3 (bottom) share the geometry; layer 2 is the middle
-    R1 = math.hypot(d / 2, hu)
-    D1 = math.hypot(1.5 * d, hu)
-    R2 = math.hypot(d / 2, h)
+    R1 = math.hypot(d / 2, hu + amp)
+    D1 = math.hypot(1.5 * d, max(hu - amp, 0.0))
+    R2 = math.hypot(d / 2, h + amp)
     D2 = 1.5 * d
     Qs = []
     for kj, R, D in ((k[0], R1, D1), (k[1], R2, D2), (k[2], R1, D1)):
         Qs.append(max(math.ceil(kj * R + 15), math.ceil(math.log(1e-14) / math.log(R / D))))
-    H = (y0 - h, 2 * h, y0 - h)
+    H = (y0 - h + amp, 2 * (h + amp), y0 - h + amp)
     Nw = tuple(max(math.ceil(kj * Hj / 2) + 24, math.ceil(0.8 * (2 * Qj + 1)))
                for kj, Hj, Qj in zip(k, H, Qs))
     kappa = k[0] * math.sin(phi)
@@ -241,12 +253,42 @@ def derive_discretization(d, h, n_layer, omega, phi, y_incl, P,
 STACK = (1.0, 1.5, 2.0)
 
 
+def interface_profile(g1_cos=(), g1_sin=(), g2_cos=(), g2_sin=()) -> np.ndarray:
+    """The interface array of a Problem, [2][2][F]: Fourier coefficients (orders
+    1..F) of the deviations of Gamma_1 and Gamma_2 from y = +h and y = -h."""
+    F = max(1, len(g1_cos), len(g1_sin), len(g2_cos), len(g2_sin))
+    out = np.zeros((2, 2, F))
+    for j, (a, b) in enumerate(((g1_cos, g1_sin), (g2_cos, g2_sin))):
+        out[j, 0, :len(a)] = a
+        out[j, 1, :len(b)] = b
+    return out
+
+
+def interface_amplitude(interface) -> float:
+    """Bound on |y - (+-h)| over both interfaces (sum of the coefficients' sizes)."""
+    if interface is None:
+        return 0.0
+    return float(np.max(np.sum(np.abs(np.asarray(interface)), axis=(1, 2))))
+
+
+# the interfaces of the paper's examples 1 and 2 (d = 1, h = 1):
+# y = 1 + 0.1 sin(2 pi x) and y = -1 + 0.2 cos(2 pi x)
+PAPER_EX12_INTERFACE = ((), (0.1,), (0.2,), ())
+# and of its example 3: y = 1 + 0.05 sin(2 pi x) + 0.05 cos(2 pi x), y = -1 + 0.1 cos(2 pi x)
+PAPER_EX3_INTERFACE = ((0.05,), (0.05,), (0.1,), ())
+
+
 def make_problem(name, d, h, M, r_lo, r_hi, n_lo, n_hi, gap, seed, omega, phi, P,
-                 n_layer=STACK, **disc_kw) -> Problem:
-    x, y, r, n = pack_disks(M, d, h, r_lo, r_hi, n_lo, n_hi, gap, seed)
+                 n_layer=STACK, interface=None, **disc_kw) -> Problem:
+    amp = interface_amplitude(interface)
+    clear = None if interface is None else max(gap, 0.02) + amp
+    x, y, r, n = pack_disks(M, d, h, r_lo, r_hi, n_lo, n_hi, gap, seed, clearance=clear)
+    if interface is not None:
+        disc_kw.setdefault("amp", amp)
     disc = derive_discretization(d, h, n_layer, omega, phi, y, P, **disc_kw)
     return Problem(d=d, h=h, n_layer=tuple(n_layer), omega=omega, phi=phi, P=P,
-                   x=x, y=y, radius=r, n_incl=n, disc=disc, name=name, seed=seed)
+                   x=x, y=y, radius=r, n_incl=n, disc=disc, name=name, seed=seed,
+                   interface=None if interface is None else np.asarray(interface, float))
 
 
 def tiny_m4(phi=-math.pi / 5, **kw) -> Problem:
@@ -313,13 +355,38 @@ def star_m1000(phi=-math.pi / 5, **kw) -> Problem:
                 n_lo=1.5, n_hi=3.0, gap=0.002, **kw)
 
 
-def empty_slab(omega=10.0, phi=-math.pi / 5, d=1.0, h=0.5, n_layer=STACK, **kw) -> Problem:
-    """No inclusions: the empty layered structure."""
+def empty_slab(omega=10.0, phi=-math.pi / 5, d=1.0, h=0.5, n_layer=STACK, interface=None,
+               **kw) -> Problem:
+    """No inclusions: the empty layered structure (flat, or with the given curved
+    interfaces)."""
     e = np.zeros(0)
+    if interface is not None:
+        kw.setdefault("amp", interface_amplitude(interface))
     disc = derive_discretization(d, h, n_layer, omega, phi, e, 10, **kw)
     return Problem(d=d, h=h, n_layer=tuple(n_layer), omega=omega, phi=phi, P=10,
                    x=e, y=e.copy(), radius=e.copy(), n_incl=e.copy(), disc=disc,
-                   name="empty")
+                   name="empty" if interface is None else "empty_curved",
+                   interface=None if interface is None else np.asarray(interface, float))
+
+
+def curved(M, P, omega=10.0, seed=7, phi=-math.pi / 5, d=1.0, h=0.5,
+           interface=((), (0.05,), (0.04,), (0.02,)), **kw) -> Problem:
+    """small()'s inclusions between curved interfaces (default Gamma_1:
+    y = h + 0.05 sin(2 pi x), Gamma_2: y = -h + 0.04 cos(2 pi x) + 0.02 sin(2 pi x));
+    the packing keeps every disk at least 0.02 + the interfaces' amplitude from
+    y = +-h."""
+    pb = make_problem(f"curved_M{M}_P{P}", d, h, M, 0.02, 0.04, 1.5, 3.0, 0.01, seed,
+                      omega, phi, P, interface=interface_profile(*interface), **kw)
+    return pb
+
+
+def curved_m1000(phi=-math.pi / 5, **kw) -> Problem:
+    """The M=1000 workload's rules (d=1, h=1, radii U[0.004, 0.012], indices
+    U[1.5, 3.0], gap 0.002, omega=20, P=15, seed 2) between the interfaces of the
+    paper's examples 1 and 2, y = 1 + 0.1 sin(2 pi x) and y = -1 + 0.2 cos(2 pi x)."""
+    return make_problem("curved_m1000", 1.0, 1.0, 1000, 0.004, 0.012, 1.5, 3.0, 0.002, 2,
+                        20.0, phi, 15, interface=interface_profile(*PAPER_EX12_INTERFACE),
+                        **kw)
 
 
 # ----------------------------------------------------------------------------

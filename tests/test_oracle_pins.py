@@ -162,9 +162,9 @@ def test_wall_rows_cancelled_form():
     yw = G.yw[1]
     for deriv in (False, True):
         td = (1.0, 0.0) if deriv else None
-        SL, DL = _three_copy(G, G.k2, np.full_like(yw, -G.d / 2), yw, G.h, td)
-        SR, DR = _three_copy(G, G.k2, np.full_like(yw, G.d / 2), yw, G.h, td)
-        Sc, Dc = _wall_cancelled(G, G.k2, yw, G.h, deriv)
+        SL, DL = _three_copy(G, G.k2, np.full_like(yw, -G.d / 2), yw, 0, td)
+        SR, DR = _three_copy(G, G.k2, np.full_like(yw, G.d / 2), yw, 0, td)
+        Sc, Dc = _wall_cancelled(G, G.k2, yw, 0, deriv)
         assert np.max(np.abs(G.alpha * SL - SR - Sc)) < 1e-12 * np.max(np.abs(Sc))
         assert np.max(np.abs(G.alpha * DL - DR - Dc)) < 1e-12 * np.max(np.abs(Dc))
 
