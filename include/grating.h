@@ -52,9 +52,16 @@ typedef enum { GRT_TM = 0, GRT_TE = 1 } grt_polarization;
 
 typedef struct grt_ctx grt_ctx;
 
-/* Layered structure and its discretization (paper sec. 3).  Flat interfaces
- * Gamma_1: y = +h and Gamma_2: y = -h; artificial lines Gamma_u, Gamma_d at +-y0;
- * period d.  Discretization: N equispaced (cell-centred) nodes per interface,
+/* Layered structure and its discretization (paper sec. 3).  Interfaces Gamma_1
+ * near y = +h and Gamma_2 near y = -h: flat, or graphs of period d (the curved
+ * interfaces of secs. 3 and 6) given by n_fourier > 0 and iface, host
+ * [2][2][n_fourier] (copied): for Gamma_1 then Gamma_2, the cosine then the sine
+ * coefficients a_m, b_m (m = 1..n_fourier, at most 64) of the graph
+ *   y = (+h or -h) + sum_m a_m cos(2 pi m x / d) + b_m sin(2 pi m x / d);
+ * the graphs must keep Gamma_1 above Gamma_2 and both strictly between the
+ * artificial lines Gamma_u, Gamma_d at +-y0 (GRT_EINVAL).  Period d.
+ * Discretization: N nodes per interface, equispaced (cell-centred) in x, the
+ * graphs' parameter,
  * Nw[l] Gauss-Legendre nodes on the walls of layer l (0 top, 1 middle, 2 bottom),
  * J expansions of orders -Q[l]..Q[l] about (0, +-(h+y0)/2) and (0, 0), Nu nodes on
  * Gamma_u and on Gamma_d, Rayleigh-Bloch orders n_rb_lo .. n_rb_lo + Nrb - 1,
@@ -70,6 +77,8 @@ typedef struct {
   int n_rb_lo, Nrb;
   int zeta_K;
   double pinv_eps;
+  int n_fourier;        /* 0: flat interfaces                                    */
+  const double* iface;  /* [2][2][n_fourier] Fourier coefficients (see above)    */
 } grt_layers;
 
 /* M inclusions (paper sec. 4, 5): centres (x, y), radius and refractive index.
@@ -180,7 +189,9 @@ const char* grt_error_message(const grt_ctx* ctx);
 
 /* Copy and validate the problem (sec. 2).  GRT_EGEOM if two disks overlap under
  * the minimum image in x, a disk crosses an interface or a centre lies outside the
- * cell |x| <= d/2 (the near copies l = -1, 0, 1 of sec. 4.2 assume one cell). */
+ * cell |x| <= d/2 (the near copies l = -1, 0, 1 of sec. 4.2 assume one cell).  With
+ * curved interfaces a disk crosses one when a point of the graph within its x-range,
+ * sampled at spacing radius / 256, lies closer than its radius to the centre. */
 grt_status grt_set_problem(grt_ctx* ctx, const grt_layers* lay, const grt_inclusions* inc,
                            const grt_incidence* wave);
 
@@ -343,8 +354,8 @@ grt_status grt_bragg(grt_ctx* ctx, int64_t rhs, const void* beta_dev, int64_t ca
  * accuracy within a few node spacings (d/N) of an interface and are not the field on
  * it.  Allocates device scratch (O(n_alpha rank + M (2P+1) + n_pts)) and synchronises
  * the context stream.  GRT_EINVAL for null arrays or coordinates that are not finite
- * or exceed 1e6 in size,
- * GRT_ESTATE before grt_build. */
+ * or exceed 1e6 in size, GRT_EUNSUP for TE, non-circular inclusions and curved
+ * interfaces, GRT_ESTATE before grt_build. */
 grt_status grt_eval_field(grt_ctx* ctx, int64_t rhs, const void* beta_dev, int64_t n_pts,
                           const double* xy, double* u);
 

@@ -37,11 +37,11 @@ void free_all(grt_ctx* c) {
   c->d_blkw = nullptr;
   c->blk_Rp = 0;
   if (c->lf) {  // layer-side buffers belong to the shared factors
-    c->d_yw = c->d_colscale = c->d_sv = c->d_htab = nullptr;
+    c->d_yw = c->d_colscale = c->d_sv = c->d_htab = c->d_node = nullptr;
     c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_f = nullptr;
     c->lf.reset();
   }
-  void* bufs[] = {c->d_cx, c->d_cy, c->d_rad, c->d_kp, c->d_yw, c->d_wcorr, c->d_A,
+  void* bufs[] = {c->d_cx, c->d_cy, c->d_rad, c->d_kp, c->d_yw, c->d_node, c->d_wcorr, c->d_A,
                   c->d_colscale, c->d_sv, c->d_U, c->d_VH, c->d_W1, c->d_W2, c->d_W3,
                   c->d_mie, c->d_l2l, c->d_f, c->d_pT, c->d_pC, c->d_pB, c->d_pL,
                   c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_htab,
@@ -51,7 +51,7 @@ void free_all(grt_ctx* c) {
   for (void* p : bufs)
     if (p) hipFree(p);
   c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal =
-      c->d_htab = nullptr;
+      c->d_htab = c->d_node = nullptr;
   c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_mie = c->d_l2l =
       c->d_f = c->d_pT = c->d_pC = c->d_pB = c->d_pL = c->d_gvec = c->d_tvec = c->d_wvec =
           c->d_V = c->d_H = c->d_y = c->d_dotpart = nullptr;
@@ -164,6 +164,26 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
   if (L.N < 2 * L.zeta_K + 1 || L.N > 1000000) return set_err(c, GRT_EINVAL, "N too small for the stencil");
   if (L.Nu < 1 || L.Nrb < 1 || L.Nrb > 100000) return set_err(c, GRT_EINVAL, "bad Nu / Nrb");
   if (!(L.pinv_eps > 0 && L.pinv_eps < 1)) return set_err(c, GRT_EINVAL, "pinv_eps must be in (0, 1)");
+  if (L.n_fourier < 0 || L.n_fourier > 64)
+    return set_err(c, GRT_EINVAL, "n_fourier must be in [0, 64]");
+  if (L.n_fourier > 0 && !L.iface) return set_err(c, GRT_EINVAL, "n_fourier > 0 needs iface");
+  const int F = L.n_fourier;
+  std::vector<double> iface(L.iface ? L.iface : (const double*)nullptr,
+                            L.iface ? L.iface + 4 * F : (const double*)nullptr);
+  for (double v : iface)
+    if (!std::isfinite(v)) return set_err(c, GRT_EINVAL, "non-finite interface coefficient");
+  if (F > 0) {
+    // the graphs keep their order and stay between Gamma_u and Gamma_d
+    const int ns = 4096;
+    for (int i = 0; i < ns; ++i) {
+      const double x = -0.5 * L.d + (i + 0.5) * L.d / ns;
+      const double f1 = iface_height(iface.data(), F, 0, L.h, L.d, x, 0);
+      const double f2 = iface_height(iface.data(), F, 1, L.h, L.d, x, 0);
+      if (!(f1 > f2 && f1 < L.y0 && f2 > -L.y0))
+        return set_err(c, GRT_EINVAL, "curved interfaces must keep Gamma_1 above Gamma_2, "
+                                      "both strictly between -y0 and y0");
+    }
+  }
   if (!finite_pos(wave->omega)) return set_err(c, GRT_EINVAL, "omega must be > 0");
   const int64_t R = wave->n_rhs > 1 ? wave->n_rhs : 1;
   if (wave->n_rhs < 0 || R > 65536) return set_err(c, GRT_EINVAL, "n_rhs must be in [0, 65536]");
@@ -217,8 +237,23 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
     if (!std::isfinite(c->hx[m]) || !std::isfinite(c->hy[m]) || !finite_pos(c->hr[m]) ||
         !finite_pos(c->hn[m]))
       return set_err(c, GRT_EINVAL, "non-finite or non-positive inclusion data");
-    if (std::fabs(c->hy[m]) + c->hr[m] >= L.h)
+    if (F == 0 && std::fabs(c->hy[m]) + c->hr[m] >= L.h)
       return set_err(c, GRT_EGEOM, "inclusion " + std::to_string(m) + " touches an interface");
+    if (F > 0) {
+      // the centre between the graphs, and no graph point within the radius (sampled
+      // over the disk's x-range at spacing radius / 256)
+      const double xc = c->hx[m], yc = c->hy[m], r = c->hr[m];
+      bool hit = !(yc < iface_height(iface.data(), F, 0, L.h, L.d, xc, 0) &&
+                   yc > iface_height(iface.data(), F, 1, L.h, L.d, xc, 0));
+      for (int j = 0; j < 2 && !hit; ++j)
+        for (int i = -256; i <= 256 && !hit; ++i) {
+          const double x = xc + r * i / 256.0;
+          const double dy = iface_height(iface.data(), F, j, L.h, L.d, x, 0) - yc;
+          hit = (x - xc) * (x - xc) + dy * dy <= r * r;
+        }
+      if (hit)
+        return set_err(c, GRT_EGEOM, "inclusion " + std::to_string(m) + " touches an interface");
+    }
     if (std::fabs(c->hx[m]) > 0.5 * L.d)
       return set_err(c, GRT_EGEOM, "inclusion " + std::to_string(m) + " lies outside the cell |x| <= d/2");
   }
@@ -255,6 +290,8 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
     }
   }
   c->lay = L;
+  c->lay.iface = nullptr;  // the caller's array: the context keeps its own copy
+  c->hiface = iface;
   c->inc = *wave;
   c->inc.phi = phi0;
   c->inc.n_rhs = 0;
@@ -276,6 +313,7 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
     g.Q[l] = L.Q[l];
   }
   g.te = wave->polarization == GRT_TE ? 1 : 0;
+  g.curved = F > 0 ? 1 : 0;
   for (int l = 0; l < 3; ++l) {
     const double eps = L.n_layer[l] * L.n_layer[l];
     g.pv[l] = g.te ? eps : 1.0;

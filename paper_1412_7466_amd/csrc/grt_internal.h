@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include <memory>
 #include <string>
 #include <vector>
@@ -33,15 +35,39 @@ struct DevGeom {
   int col_off[CB_COUNT + 1];
   int n_rows, n_alpha;
   const double* yw[3];          // wall nodes (device)
-  const cd* wcorr;              // zeta-correction weights [4][2K+1]: S1, T1, S2, T2
+  // interface nodes (device) [2][N][NODE_STRIDE]: x, y, unit normal (nx, ny) pointing
+  // up, speed |(1, f')| and f'' of the graph y = f(x) (flat: y = +-h, n = (0, 1),
+  // speed 1, f'' = 0); the quadrature weight of node j is hs * speed
+  const double* node;
+  int curved;                   // 1: curved interfaces (graphs of period d)
+  // zeta-correction weights per target (device) [2 interfaces][4 kinds: S, D, N, T]
+  // [N targets][2K+1 stencil offsets]
+  const cd* wcorr;
 };
+constexpr int NODE_STRIDE = 6;
+
+// q-th x-derivative (q = 0, 1, 2) of interface j's height y = f_j(x): +h (j = 0) or
+// -h (j = 1) plus sum_m a_m cos(w_m x) + b_m sin(w_m x), w_m = 2 pi m / d, with
+// co[(j * 2 + 0) * F + m - 1] = a_m and co[(j * 2 + 1) * F + m - 1] = b_m (host).
+inline double iface_height(const double* co, int F, int j, double h, double d, double x, int q) {
+  double v = q == 0 ? (j == 0 ? h : -h) : 0.0;
+  for (int m = 1; m <= F; ++m) {
+    const double w = 2.0 * M_PI * m / d;
+    const double a = co[(j * 2 + 0) * F + m - 1], b = co[(j * 2 + 1) * F + m - 1];
+    const double cw = std::cos(w * x), sw = std::sin(w * x);
+    if (q == 0) v += a * cw + b * sw;
+    else if (q == 1) v += w * (-a * sw + b * cw);
+    else v += w * w * (-a * cw - b * sw);
+  }
+  return v;
+}
 
 // Device data of the empty layered structure (wall nodes, quadrature corrections,
 // A, its SVD, the pseudo-inverse factor blocks, f) shared by every problem with the
 // same layers, discretization, omega and phi.
 struct LayerFactors {
   int device = 0;
-  double *yw = nullptr, *colscale = nullptr, *sv = nullptr, *htab = nullptr;
+  double *yw = nullptr, *colscale = nullptr, *sv = nullptr, *htab = nullptr, *node = nullptr;
   cd *wcorr = nullptr, *A = nullptr, *U = nullptr, *VH = nullptr;
   cd *W1 = nullptr, *W2 = nullptr, *W3 = nullptr, *f = nullptr;
   int rank = 0;
@@ -80,6 +106,7 @@ struct grt_ctx {
   grt_incidence inc{};
   int64_t M = 0;
   std::vector<double> hx, hy, hr, hn;
+  std::vector<double> hiface;  // [2][2][n_fourier] interface Fourier coefficients
   // derived
   DevGeom g{};
   int P = 0, nb = 0;
@@ -90,6 +117,7 @@ struct grt_ctx {
   // device buffers owned by the context
   double *d_cx = nullptr, *d_cy = nullptr, *d_rad = nullptr, *d_kp = nullptr;
   double* d_yw = nullptr;
+  double* d_node = nullptr;  // [2][N][NODE_STRIDE] interface nodes
   cd* d_wcorr = nullptr;
   cd* d_A = nullptr;        // [n_alpha][n_rows] column-major, equilibrated
   double* d_colscale = nullptr;

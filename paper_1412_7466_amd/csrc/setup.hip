@@ -2,9 +2,10 @@
 //
 //  * the rectangular empty-structure matrix A of eq. matA, one thread per entry:
 //    layer potentials summed over the copies l = -1, 0, 1 with phases alpha^l
-//    (eqs. repre1-repre3), the same-line kernel differences S_ka - S_kb and
-//    T_ka - T_kb on the flat interfaces with zeta-corrected trapezoid weights
-//    (the paper's locally corrected Nystrom rule), J-expansion columns, wall
+//    (eqs. repre1-repre3) on flat or curved (graph) interfaces, the
+//    same-interface kernel differences (S, D, N, T of the layers on both sides) with
+//    zeta-corrected trapezoid weights per target (the paper's locally corrected
+//    Nystrom rule, in the graphs' parameter x), J-expansion columns, wall
 //    discrepancies in the cancelled form alpha u(L) - u(L+d) =
 //    alpha^2 Phi(L-d) - alpha^{-1} Phi(L+2d), Rayleigh-Bloch columns (eq. bound3);
 //  * unit-norm column equilibration, SVD by rocSOLVER, truncated Sigma^+ and the
@@ -68,31 +69,14 @@ __device__ double zeta_odd(double s) {
   return acc;
 }
 
-// The split K(s) = phi(s) ln|s| + psi(s) of the flat-line kernel differences:
-//   wa S_ka - wb S_kb: phi = -[wa J0(ka s) - wb J0(kb s)] / (2 pi), phi(0) = -(wa-wb)/(2 pi),
-//     psi(0) = (wa-wb)(i/4 - gamma/(2 pi)) - [wa ln(ka/2) - wb ln(kb/2)]/(2 pi)
-//     (wa = wb = 1 in TM: psi(0) = -ln(ka/kb)/(2 pi); TE weights the layers by eps)
-//   T_ka - T_kb: phi = -[ka J1(ka s) - kb J1(kb s)] / (2 pi s), phi(0) = -(ka^2-kb^2)/(4 pi),
-//     psi(0) = i (ka^2-kb^2)/8 - [ka^2 ln(ka/2) - kb^2 ln(kb/2)]/(4 pi) + (ka^2-kb^2)(1-2 gamma)/(8 pi)
-// (small-argument series of J0, Y0, J1, Y1; the hypersingular parts cancel).
-__device__ void phi_vals(double ka, double kb, double s, bool tker, double wa, double wb,
-                         double& phi) {
-  if (s == 0.0) {
-    phi = tker ? -(ka * ka - kb * kb) / (4.0 * GRT_PI) : -(wa - wb) / (2.0 * GRT_PI);
-    return;
-  }
-  double a0, a1, b0, b1, ya0, ya1, yb0, yb1;
-  bessel01(ka * s, a0, a1, ya0, ya1);
-  bessel01(kb * s, b0, b1, yb0, yb1);
-  phi = tker ? -(ka * a1 - kb * b1) / (2.0 * GRT_PI * s) : -(wa * a0 - wb * b0) / (2.0 * GRT_PI);
-}
-
 // Single thread: Fornberg finite-difference weights on the stencil -K..K (unit
-// spacing), then the zeta-corrected trapezoid weights for the four self blocks
-//   w_p = hs sum_k 2 zeta'(-2k)/(2k)! c^{(2k)}_p phi(p hs) + [p = 0] hs (psi(0) + phi(0) ln(hs / 2 pi)),
-//   2 zeta'(-2k)/(2k)! = (-1)^k zeta(2k+1) / (2 pi)^{2k}.
-__global__ void zeta_weights_kernel(int K, double hs, double k1, double k2, double k3, double pv0,
-                                    double pv1, double pv2, cd* w) {
+// spacing) combined with the zeta coefficients of the locally corrected trapezoid
+// rule for K(s) = phi(s) ln|s| + psi(s):
+//   zcw[p] = sum_k 2 zeta'(-2k)/(2k)! c^{(2k)}_p,  2 zeta'(-2k)/(2k)! = (-1)^k zeta(2k+1) / (2 pi)^{2k},
+// so that the correction weights of a target are (the term of order 2k is
+// zc_k hs^{2k+1} (phi tau)^{(2k)}(0) and the unit-spacing differences carry hs^{-2k})
+//   w_p = hs zcw[p] phi(p hs) + [p = 0] hs (psi(0) + phi(0) ln(hs / 2 pi)).
+__global__ void zeta_stencil_kernel(int K, double* zcw) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int n = 2 * K + 1;
   const int m = 2 * K;
@@ -119,41 +103,144 @@ __global__ void zeta_weights_kernel(int K, double hs, double k1, double k2, doub
     }
     c1 = c2;
   }
-  double zc[17];
-  for (int k = 1; k <= K; ++k) {
-    double sgn = (k & 1) ? -1.0 : 1.0;
-    zc[k] = sgn * zeta_odd(2.0 * k + 1.0) / pow(2.0 * GRT_PI, 2.0 * k);
-  }
-  const double gam = GRT_EULER_GAMMA;
-  for (int blk = 0; blk < 4; ++blk) {
-    bool tker = blk & 1;
-    double ka = (blk < 2) ? k1 : k2;
-    double kb = (blk < 2) ? k2 : k3;
-    double wa = (blk < 2) ? pv0 : pv1;   // S blocks: layer weights (TE: eps)
-    double wb = (blk < 2) ? pv1 : pv2;
-    double phi0 = tker ? -(ka * ka - kb * kb) / (4.0 * GRT_PI) : -(wa - wb) / (2.0 * GRT_PI);
-    cd psi0;
-    if (!tker) {
-      psi0 = cd{-(wa - wb) * gam / (2.0 * GRT_PI) -
-                    (wa * log(0.5 * ka) - wb * log(0.5 * kb)) / (2.0 * GRT_PI),
-                0.25 * (wa - wb)};
-    } else {
-      double d2 = ka * ka - kb * kb;
-      psi0 = cd{-(ka * ka * log(0.5 * ka) - kb * kb * log(0.5 * kb)) / (4.0 * GRT_PI) +
-                    d2 * (1.0 - 2.0 * gam) / (8.0 * GRT_PI),
-                0.125 * d2};
+  for (int j = 0; j < n; ++j) {
+    double acc = 0.0;
+    for (int k = 1; k <= K; ++k) {
+      double sgn = (k & 1) ? -1.0 : 1.0;
+      acc += sgn * zeta_odd(2.0 * k + 1.0) / pow(2.0 * GRT_PI, 2.0 * k) * c[2 * k][j];
     }
-    for (int j = 0; j < n; ++j) {
-      double ph;
-      phi_vals(ka, kb, fabs((double)(j - K)) * hs, tker, wa, wb, ph);
-      double acc = 0.0;
-      for (int k = 1; k <= K; ++k) acc += zc[k] * c[2 * k][j];
-      cd wj{hs * acc * ph, 0.0};
-      if (j == K) {
-        wj.r += hs * (psi0.r + phi0 * log(hs / (2.0 * GRT_PI)));
-        wj.i += hs * psi0.i;
+    zcw[j] = acc;
+  }
+}
+
+// The four same-interface kernel differences per unit of the source parameter x
+// (kind 0: wa S_a - wb S_b, 1: wa D_a - wb D_b, 2: N_a - N_b, 3: T_a - T_b) at
+// R = target - source (r > 0), target normal ns, source normal nt, source speed spd:
+//   S = (i/4)(wa H0_a - wb H0_b)
+//   D = (i/4)(wa ka H1_a - wb kb H1_b)(R.n_t)/r
+//   N = -(i/4)(ka H1_a - kb H1_b)(R.n_s)/r
+//   T = (i/4)[(ka H1_a - kb H1_b)(n_s.n_t)/r - (ka^2 H2_a - kb^2 H2_b)(R.n_s)(R.n_t)/r^2]
+// each times spd.  With logc, the coefficient phi of ln|s - t| instead: (i/4) H_n
+// replaced by -J_n / (2 pi) (the log part of Y_n).
+__device__ cd curve_kernel(int kind, bool logc, double ka, double kb, double wa, double wb,
+                           double Rx, double Ry, double snx, double sny, double tnx, double tny,
+                           double spd) {
+  const double r = sqrt(Rx * Rx + Ry * Ry);
+  cd Za[3], Zb[3];
+  const double ks[2] = {ka, kb};
+  for (int w = 0; w < 2; ++w) {
+    cd* Z = w ? Zb : Za;
+    const double z = ks[w] * r;
+    if (logc) {
+      double j0, j1, y0, y1;
+      bessel01(z, j0, j1, y0, y1);
+      const double c = -1.0 / (2.0 * GRT_PI);
+      Z[0] = cd{c * j0, 0.0};
+      Z[1] = cd{c * j1, 0.0};
+      Z[2] = cd{c * ((2.0 / z) * j1 - j0), 0.0};
+    } else {
+      cd h0, h1;
+      hankel01(z, h0, h1);
+      Z[0] = times_i(0.25 * h0);
+      Z[1] = times_i(0.25 * h1);
+      Z[2] = times_i(0.25 * ((2.0 / z) * h1 - h0));
+    }
+  }
+  const double Rs = Rx * snx + Ry * sny, Rt = Rx * tnx + Ry * tny;
+  cd v;
+  switch (kind) {
+    case 0: v = wa * Za[0] - wb * Zb[0]; break;
+    case 1: v = (Rt / r) * (wa * ka * Za[1] - wb * kb * Zb[1]); break;
+    case 2: v = (-Rs / r) * (ka * Za[1] - kb * Zb[1]); break;
+    default:
+      v = ((snx * tnx + sny * tny) / r) * (ka * Za[1] - kb * Zb[1]) -
+          (Rs * Rt / (r * r)) * (ka * ka * Za[2] - kb * kb * Zb[2]);
+  }
+  return spd * v;
+}
+
+// (phi(0), psi(0)) of the four kernel differences at a node of speed spd with
+// curvature term f2 = f'' (ln r = ln|s - t| + ln spd + O(s - t); the k-free singular
+// parts cancel in the differences except for the weighted double layer, whose
+// (R.n_t)/(2 pi r^2) tends to f'' / (4 pi spd^3)):
+//   S: phi0 = -(wa - wb) spd / (2 pi),
+//      psi0 = spd [(wa - wb)(i/4 - gamma/(2 pi) - ln(spd)/(2 pi)) - (wa ln(ka/2) - wb ln(kb/2))/(2 pi)]
+//   D: phi0 = 0, psi0 = (wa - wb) f'' / (4 pi spd^2);  N: phi0 = psi0 = 0
+//   T: phi0 = -(ka^2 - kb^2) spd / (4 pi),
+//      psi0 = spd [i (ka^2 - kb^2)/8 - (ka^2 ln(ka/2) - kb^2 ln(kb/2))/(4 pi)
+//                  + (ka^2 - kb^2)(1 - 2 gamma)/(8 pi) - (ka^2 - kb^2) ln(spd)/(4 pi)]
+// (small-argument series of J_n, Y_n).
+__device__ void curve_limits(int kind, double ka, double kb, double wa, double wb, double spd,
+                             double f2, double& phi0, cd& psi0) {
+  const double gam = GRT_EULER_GAMMA, pi = GRT_PI, lsp = log(spd);
+  const double d2 = ka * ka - kb * kb;
+  switch (kind) {
+    case 0:
+      phi0 = -(wa - wb) * spd / (2.0 * pi);
+      psi0 = cd{spd * ((wa - wb) * (-gam / (2.0 * pi) - lsp / (2.0 * pi)) -
+                       (wa * log(0.5 * ka) - wb * log(0.5 * kb)) / (2.0 * pi)),
+                spd * 0.25 * (wa - wb)};
+      break;
+    case 1:
+      phi0 = 0.0;
+      psi0 = cd{(wa - wb) * f2 / (4.0 * pi * spd * spd), 0.0};
+      break;
+    case 2:
+      phi0 = 0.0;
+      psi0 = cd{0.0, 0.0};
+      break;
+    default:
+      phi0 = -d2 * spd / (4.0 * pi);
+      psi0 = cd{spd * (-(ka * ka * log(0.5 * ka) - kb * kb * log(0.5 * kb)) / (4.0 * pi) +
+                       d2 * (1.0 - 2.0 * gam) / (8.0 * pi) - d2 * lsp / (4.0 * pi)),
+                spd * 0.125 * d2};
+  }
+}
+
+// Wavenumbers and layer weights of interface `line`'s same-interface blocks: the
+// layers above and below it; the single and double layers carry pv of their layer
+// (TE: eps), the flux rows' N and T parts are unweighted (fl pv = 1).
+__device__ __forceinline__ void line_pair(const DevGeom& g, int line, int kind, double& ka,
+                                          double& kb, double& wa, double& wb) {
+  ka = g.k[line];
+  kb = g.k[line + 1];
+  const bool weighted = kind < 2;
+  wa = weighted ? g.pv[line] : 1.0;
+  wb = weighted ? g.pv[line + 1] : 1.0;
+}
+
+// Correction weights of every target: one thread per (interface, target), all four
+// kinds; phi at the stencil nodes i + p (wrapping onto the copies l = -1, +1), then
+//   w_p = hs zcw[p] phi_p + [p = 0] hs (psi(0) + phi(0) ln(hs / 2 pi)).
+// The Bloch phase of a wrapped node is applied where the weight is used.
+__global__ void curve_weights_kernel(DevGeom g, const double* zcw, cd* w) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = g.N, K = g.zeta_K, n = 2 * K + 1;
+  if (t >= 2 * N) return;
+  const int line = t / N, i = t - line * N;
+  const double* ni = g.node + ((size_t)line * N + i) * NODE_STRIDE;
+  const double lhs = log(g.hs / (2.0 * GRT_PI));
+  for (int kind = 0; kind < 4; ++kind) {
+    double ka, kb, wa, wb;
+    line_pair(g, line, kind, ka, kb, wa, wb);
+    double phi0;
+    cd psi0;
+    curve_limits(kind, ka, kb, wa, wb, ni[4], ni[5], phi0, psi0);
+    cd* out = w + (((size_t)line * 4 + kind) * N + i) * n;
+    for (int p = -K; p <= K; ++p) {
+      cd ph;
+      if (p == 0) {
+        ph = cd{phi0, 0.0};
+      } else {
+        const int gi = i + p;
+        const int l = gi < 0 ? -1 : (gi >= N ? 1 : 0);
+        const double* nj = g.node + ((size_t)line * N + gi - l * N) * NODE_STRIDE;
+        ph = curve_kernel(kind, true, ka, kb, wa, wb, ni[0] - (nj[0] + l * g.d), ni[1] - nj[1],
+                          ni[2], ni[3], nj[2], nj[3], nj[4]);
       }
-      w[blk * n + j] = wj;
+      cd wp = (g.hs * zcw[p + K]) * ph;
+      if (p == 0) wp += g.hs * (psi0 + cd{phi0 * lhs, 0.0});
+      out[p + K] = wp;
     }
   }
 }
@@ -171,73 +258,82 @@ __device__ __forceinline__ cd alpha_pow(const DevGeom& g, int l) {
   return o;
 }
 
-// Single-layer G = (i/4) H0(kr) and double-layer dG/dn_y = (ik/4) H1(kr) R_y / r
-// (source normal +y), R = target - source; with deriv, their derivatives along
-// the unit direction (tx, ty) at the target:
-//   dS = -(ik/4) H1 (R.t)/r,  dD = (ik/4) [-k H2 R_y (R.t)/r^2 + H1 t_y / r].
-__device__ void lp_kernels(double k, double Rx, double Ry, bool deriv, double tx, double ty,
-                           cd& S, cd& D) {
+// Single-layer G = (i/4) H0(kr) and double-layer dG/dn_y = (ik/4) H1(kr) (R.n)/r
+// (source normal n = (nx, ny)), R = target - source; with deriv, their derivatives
+// along the unit direction (tx, ty) at the target:
+//   dS = -(ik/4) H1 (R.t)/r,  dD = (ik/4) [-k H2 (R.n)(R.t)/r^2 + H1 (n.t) / r].
+__device__ void lp_kernels(double k, double Rx, double Ry, double nx, double ny, bool deriv,
+                           double tx, double ty, cd& S, cd& D) {
   double r = sqrt(Rx * Rx + Ry * Ry);
   double z = k * r;
   cd h0, h1;
   hankel01(z, h0, h1);
+  const double Rn = Rx * nx + Ry * ny;
   if (!deriv) {
     S = times_i(0.25 * h0);
-    D = times_i((0.25 * k * Ry / r) * h1);
+    D = times_i((0.25 * k * Rn / r) * h1);
     return;
   }
   cd h2 = (2.0 / z) * h1 - h0;
   double Rt = Rx * tx + Ry * ty;
   S = times_i((-0.25 * k * Rt / r) * h1);
-  D = times_i((0.25 * k) * ((-k * Ry * Rt / (r * r)) * h2 + (ty / r) * h1));
+  D = times_i((0.25 * k) * ((-k * Rn * Rt / (r * r)) * h2 + ((nx * tx + ny * ty) / r) * h1));
 }
 
-// Three-copy trapezoid sum from interface node j on the line y = ys.
-__device__ void three_copy(const DevGeom& g, double k, double tx, double ty, int j, double ys,
+__device__ __forceinline__ const double* node_at(const DevGeom& g, int line, int j) {
+  return g.node + ((size_t)line * g.N + j) * NODE_STRIDE;
+}
+
+// Three-copy trapezoid sum from node j of interface `line` (arc-length weight
+// hs * speed).
+__device__ void three_copy(const DevGeom& g, double k, double tx, double ty, int line, int j,
                            bool deriv, double dx, double dy, cd& S, cd& D) {
-  double sx = -0.5 * g.d + (j + 0.5) * g.hs;
+  const double* nj = node_at(g, line, j);
   S = cd{0, 0};
   D = cd{0, 0};
   for (int l = -1; l <= 1; ++l) {
     cd a, b;
-    lp_kernels(k, tx - (sx + l * g.d), ty - ys, deriv, dx, dy, a, b);
+    lp_kernels(k, tx - (nj[0] + l * g.d), ty - nj[1], nj[2], nj[3], deriv, dx, dy, a, b);
     cd w = alpha_pow(g, l);
     S += w * a;
     D += w * b;
   }
-  S = g.hs * S;
-  D = g.hs * D;
+  const double wq = g.hs * nj[4];
+  S = wq * S;
+  D = wq * D;
 }
 
 // Wall discrepancy alpha u(L) - u(R) of the three copies of node j, cancelled:
 // alpha^2 Phi(-3d/2, y) - alpha^{-1} Phi(3d/2, y), Phi the l = 0 copy.
-__device__ void wall_cancelled(const DevGeom& g, double k, double y, int j, double ys, bool deriv,
+__device__ void wall_cancelled(const DevGeom& g, double k, double y, int line, int j, bool deriv,
                                cd& S, cd& D) {
-  double sx = -0.5 * g.d + (j + 0.5) * g.hs;
+  const double* nj = node_at(g, line, j);
   cd a1, b1, a2, b2;
-  lp_kernels(k, -1.5 * g.d - sx, y - ys, deriv, 1.0, 0.0, a1, b1);
-  lp_kernels(k, 1.5 * g.d - sx, y - ys, deriv, 1.0, 0.0, a2, b2);
+  lp_kernels(k, -1.5 * g.d - nj[0], y - nj[1], nj[2], nj[3], deriv, 1.0, 0.0, a1, b1);
+  lp_kernels(k, 1.5 * g.d - nj[0], y - nj[1], nj[2], nj[3], deriv, 1.0, 0.0, a2, b2);
   cd w1 = g.alpha * g.alpha, w2 = -g.alpha_inv;
-  S = g.hs * (w1 * a1 + w2 * a2);
-  D = g.hs * (w1 * b1 + w2 * b2);
+  const double wq = g.hs * nj[4];
+  S = wq * (w1 * a1 + w2 * a2);
+  D = wq * (w1 * b1 + w2 * b2);
 }
 
-// Same-line self block entry (target node i, source node j) of S_ka - S_kb or
-// T_ka - T_kb: punctured three-copy trapezoid sum plus stencil corrections.
-__device__ cd self_entry(const DevGeom& g, double ka, double kb, bool tker, const cd* wc, int i,
-                         int j, double wa = 1.0, double wb = 1.0) {
-  cd acc{0, 0};
+// Same-interface block entry (target node i, source node j) of interface `line`,
+// kind 0..3 (weighted S, weighted D, N, T differences): punctured three-copy
+// trapezoid sum plus the target's stencil corrections.
+__device__ cd self_entry(const DevGeom& g, int line, int kind, int i, int j) {
+  double ka, kb, wa, wb;
+  line_pair(g, line, kind, ka, kb, wa, wb);
   const int N = g.N, K = g.zeta_K;
+  const double* ni = node_at(g, line, i);
+  const double* nj = node_at(g, line, j);
+  const cd* wc = g.wcorr + (((size_t)line * 4 + kind) * N + i) * (2 * K + 1);
+  cd acc{0, 0};
   for (int l = -1; l <= 1; ++l) {
     cd w = alpha_pow(g, l);
     if (!(l == 0 && i == j)) {
-      double s = fabs((double)(i - j - l * N)) * g.hs;
-      cd ha0, ha1, hb0, hb1;
-      hankel01(ka * s, ha0, ha1);
-      hankel01(kb * s, hb0, hb1);
-      cd kv = tker ? times_i((0.25 / s) * (ka * ha1 - kb * hb1))
-                   : times_i(0.25 * (wa * ha0 - wb * hb0));
-      acc += (g.hs) * (w * kv);
+      cd kv = curve_kernel(kind, false, ka, kb, wa, wb, ni[0] - (nj[0] + l * g.d), ni[1] - nj[1],
+                           ni[2], ni[3], nj[2], nj[3], nj[4]);
+      acc += g.hs * (w * kv);
     }
     int p = j + l * N - i;
     if (p >= -K && p <= K) acc += w * wc[p + K];
@@ -276,51 +372,52 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
   while (col >= g.col_off[cb + 1]) ++cb;
   int i = row - g.row_off[rb];
   int j = col - g.col_off[cb];
-  const double h = g.h, d = g.d;
+  const double d = g.d;
   const double k1 = g.k[0], k2 = g.k[1], k3 = g.k[2];
-  const int K2 = 2 * g.zeta_K + 1;
   cd S, D;
   cd zero{0, 0};
   switch (rb) {
     case RB_G1V:
     case RB_G1N: {
       bool dv = (rb == RB_G1N);
-      double tx = -0.5 * d + (i + 0.5) * g.hs, ty = h;
+      const double* ni = node_at(g, 0, i);
+      const double tx = ni[0], ty = ni[1], nx = ni[2], ny = ni[3];
       // layer factors: potentials of layer l carry pv[l]; flux rows take fl[l] of the
-      // field of layer l (the self blocks' T and identity parts are unchanged)
+      // field of layer l (the self blocks' N, T and identity parts are unchanged)
       switch (cb) {
         case CB_MU1:
-          return dv ? self_entry(g, k1, k2, true, g.wcorr + 1 * K2, i, j)
-                    : (i == j ? cd{0.5 * (g.pv[0] + g.pv[1]), 0} : zero);
+          return dv ? self_entry(g, 0, 3, i, j)
+                    : (i == j ? cd{0.5 * (g.pv[0] + g.pv[1]), 0} : zero) + self_entry(g, 0, 1, i, j);
         case CB_SIG1:
-          return dv ? (i == j ? cd{-1, 0} : zero)
-                    : self_entry(g, k1, k2, false, g.wcorr, i, j, g.pv[0], g.pv[1]);
+          return dv ? (i == j ? cd{-1, 0} : zero) + self_entry(g, 0, 2, i, j)
+                    : self_entry(g, 0, 0, i, j);
         case CB_MU2:
         case CB_SIG2:
-          three_copy(g, k2, tx, ty, j, -h, dv, 0.0, 1.0, S, D);
+          three_copy(g, k2, tx, ty, 1, j, dv, nx, ny, S, D);
           return -((dv ? g.fl[1] : 1.0) * g.pv[1]) * (cb == CB_MU2 ? D : S);
-        case CB_A2: return -(dv ? g.fl[1] : 1.0) * jcol(g, 1, j - g.Q[1], tx, ty, dv, 0.0, 1.0);
-        case CB_A1: return (dv ? g.fl[0] : 1.0) * jcol(g, 0, j - g.Q[0], tx, ty, dv, 0.0, 1.0);
+        case CB_A2: return -(dv ? g.fl[1] : 1.0) * jcol(g, 1, j - g.Q[1], tx, ty, dv, nx, ny);
+        case CB_A1: return (dv ? g.fl[0] : 1.0) * jcol(g, 0, j - g.Q[0], tx, ty, dv, nx, ny);
         default: return zero;
       }
     }
     case RB_G2V:
     case RB_G2N: {
       bool dv = (rb == RB_G2N);
-      double tx = -0.5 * d + (i + 0.5) * g.hs, ty = -h;
+      const double* ni = node_at(g, 1, i);
+      const double tx = ni[0], ty = ni[1], nx = ni[2], ny = ni[3];
       switch (cb) {
         case CB_MU1:
         case CB_SIG1:
-          three_copy(g, k2, tx, ty, j, h, dv, 0.0, 1.0, S, D);
+          three_copy(g, k2, tx, ty, 0, j, dv, nx, ny, S, D);
           return ((dv ? g.fl[1] : 1.0) * g.pv[1]) * (cb == CB_MU1 ? D : S);
         case CB_MU2:
-          return dv ? self_entry(g, k2, k3, true, g.wcorr + 3 * K2, i, j)
-                    : (i == j ? cd{0.5 * (g.pv[1] + g.pv[2]), 0} : zero);
+          return dv ? self_entry(g, 1, 3, i, j)
+                    : (i == j ? cd{0.5 * (g.pv[1] + g.pv[2]), 0} : zero) + self_entry(g, 1, 1, i, j);
         case CB_SIG2:
-          return dv ? (i == j ? cd{-1, 0} : zero)
-                    : self_entry(g, k2, k3, false, g.wcorr + 2 * K2, i, j, g.pv[1], g.pv[2]);
-        case CB_A2: return (dv ? g.fl[1] : 1.0) * jcol(g, 1, j - g.Q[1], tx, ty, dv, 0.0, 1.0);
-        case CB_A3: return -(dv ? g.fl[2] : 1.0) * jcol(g, 2, j - g.Q[2], tx, ty, dv, 0.0, 1.0);
+          return dv ? (i == j ? cd{-1, 0} : zero) + self_entry(g, 1, 2, i, j)
+                    : self_entry(g, 1, 0, i, j);
+        case CB_A2: return (dv ? g.fl[1] : 1.0) * jcol(g, 1, j - g.Q[1], tx, ty, dv, nx, ny);
+        case CB_A3: return -(dv ? g.fl[2] : 1.0) * jcol(g, 2, j - g.Q[2], tx, ty, dv, nx, ny);
         default: return zero;
       }
     }
@@ -333,7 +430,7 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
       bool top_line = (cb == CB_MU1 || cb == CB_SIG1);
       bool bot_line = (cb == CB_MU2 || cb == CB_SIG2);
       if ((top_line && lay != 2) || (bot_line && lay != 0)) {
-        wall_cancelled(g, k, y, j, top_line ? h : -h, dv, S, D);
+        wall_cancelled(g, k, y, top_line ? 0 : 1, j, dv, S, D);
         return g.pv[lay] * ((cb == CB_MU1 || cb == CB_MU2) ? D : S);
       }
       if (cb == jcb) {
@@ -351,11 +448,11 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
       double ty = upper ? g.y0 : -g.y0;
       double k = upper ? k1 : k3;
       if (upper && (cb == CB_MU1 || cb == CB_SIG1)) {
-        three_copy(g, k, tx, ty, j, h, dv, 0.0, 1.0, S, D);
+        three_copy(g, k, tx, ty, 0, j, dv, 0.0, 1.0, S, D);
         return g.pv[0] * (cb == CB_MU1 ? D : S);
       }
       if (!upper && (cb == CB_MU2 || cb == CB_SIG2)) {
-        three_copy(g, k, tx, ty, j, -h, dv, 0.0, 1.0, S, D);
+        three_copy(g, k, tx, ty, 1, j, dv, 0.0, 1.0, S, D);
         return g.pv[2] * (cb == CB_MU2 ? D : S);
       }
       if (upper && cb == CB_A1) return jcol(g, 0, j - g.Q[0], tx, ty, dv, 0.0, 1.0);
@@ -498,18 +595,19 @@ __global__ void l2l_table_kernel(int M, int L, double k2, const double* cx, cons
   }
 }
 
-// f of eq. Arhs restricted to the Gamma_1 rows: -u_inc and -d_y u_inc at y = h.
+// f of eq. Arhs restricted to the Gamma_1 rows: -u_inc and -du_inc/dn at the nodes of
+// Gamma_1, du_inc/dn = i (kappa n_x - k1 cos(phi) n_y) u_inc.
 __global__ void rhs_f_kernel(DevGeom g, double k1cos, int n_g, cd* f) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_g) return;
   cd v{0, 0};
   if (r < 2 * g.N) {
-    int i = r % g.N;
-    double x = -0.5 * g.d + (i + 0.5) * g.hs;
-    cd ui = cexpi(g.kappa * x - k1cos * g.h);
-    // flux row: fl0 du_inc/dy; stored divided by fl1, the factor the W1 columns of the
+    const double* ni = g.node + (size_t)(r % g.N) * NODE_STRIDE;
+    cd ui = cexpi(g.kappa * ni[0] - k1cos * ni[1]);
+    // flux row: fl0 du_inc/dn; stored divided by fl1, the factor the W1 columns of the
     // flux rows carry (so that W1 (f - C x) keeps C x in its TM form)
-    v = (r < g.N) ? -ui : (g.fl[0] / g.fl[1]) * times_i(k1cos * ui);
+    v = (r < g.N) ? -ui
+                  : (-g.fl[0] / g.fl[1]) * times_i((g.kappa * ni[2] - k1cos * ni[3]) * ui);
   }
   f[r] = v;
 }
@@ -594,7 +692,7 @@ static grt_status rocblas_err(grt_ctx* c, const char* what, int st) {
 // ---------------------------------------------------------------------------
 LayerFactors::~LayerFactors() {
   hipSetDevice(device);
-  void* p[] = {yw, colscale, sv, htab, wcorr, A, U, VH, W1, W2, W3, f};
+  void* p[] = {yw, node, colscale, sv, htab, wcorr, A, U, VH, W1, W2, W3, f};
   for (void* q : p)
     if (q) hipFree(q);
 }
@@ -607,6 +705,9 @@ static std::string layer_key(const grt_ctx* c) {
                          L.n_rb_lo, L.Nrb, L.zeta_K, c->g.te};
   std::string k(reinterpret_cast<const char*>(v.data()), v.size() * sizeof(double));
   k.append(reinterpret_cast<const char*>(iv.data()), iv.size() * sizeof(int));
+  const int F = (int)(c->hiface.size() / 4);
+  k.append(reinterpret_cast<const char*>(&F), sizeof(int));
+  k.append(reinterpret_cast<const char*>(c->hiface.data()), c->hiface.size() * sizeof(double));
   return k;
 }
 
@@ -616,6 +717,8 @@ static std::map<std::string, std::weak_ptr<LayerFactors>> g_cache;
 static void attach_factors(grt_ctx* c, const std::shared_ptr<LayerFactors>& lf) {
   c->lf = lf;
   c->d_yw = lf->yw;
+  c->d_node = lf->node;
+  c->g.node = lf->node;
   c->d_colscale = lf->colscale;
   c->d_sv = lf->sv;
   c->d_htab = lf->htab;
@@ -655,6 +758,7 @@ grt_status setup_build(grt_ctx* c) {
     lf = std::make_shared<LayerFactors>();
     lf->device = c->device;
     lf->yw = c->d_yw;
+    lf->node = c->d_node;
     lf->colscale = c->d_colscale;
     lf->sv = c->d_sv;
     lf->htab = c->d_htab;
@@ -692,7 +796,37 @@ static grt_status build_layers(grt_ctx* c) {
   // wall nodes
   const int nwt = g.Nw[0] + g.Nw[1] + g.Nw[2];
   GRT_HIP(c, hipMalloc(&c->d_yw, sizeof(double) * nwt));
-  double spans[3][2] = {{g.h, g.y0}, {-g.h, g.h}, {-g.y0, -g.h}};
+  // interface nodes: x cell-centred, the graphs' heights, normals, speeds and f''
+  // (host arithmetic on the Fourier coefficients, O(N F))
+  const int F = (int)(c->hiface.size() / 4);
+  {
+    std::vector<double> nd((size_t)2 * g.N * NODE_STRIDE);
+    for (int line = 0; line < 2; ++line)
+      for (int i = 0; i < g.N; ++i) {
+        const double x = -0.5 * g.d + (i + 0.5) * g.hs;
+        const double* co = c->hiface.data();
+        const double f0 = F ? iface_height(co, F, line, g.h, g.d, x, 0) : (line ? -g.h : g.h);
+        const double f1 = F ? iface_height(co, F, line, g.h, g.d, x, 1) : 0.0;
+        const double f2 = F ? iface_height(co, F, line, g.h, g.d, x, 2) : 0.0;
+        const double sp = std::sqrt(1.0 + f1 * f1);
+        double* o = nd.data() + ((size_t)line * g.N + i) * NODE_STRIDE;
+        o[0] = x;
+        o[1] = f0;
+        o[2] = -f1 / sp;
+        o[3] = 1.0 / sp;
+        o[4] = sp;
+        o[5] = f2;
+      }
+    GRT_HIP(c, hipMalloc(&c->d_node, sizeof(double) * nd.size()));
+    GRT_HIP(c, hipMemcpyAsync(c->d_node, nd.data(), sizeof(double) * nd.size(),
+                              hipMemcpyHostToDevice, s));
+    GRT_HIP(c, hipStreamSynchronize(s));  // nd is a host temporary
+    g.node = c->d_node;
+  }
+  // the walls end on the interfaces at x = +-d/2
+  const double e1 = F ? iface_height(c->hiface.data(), F, 0, g.h, g.d, 0.5 * g.d, 0) : g.h;
+  const double e2 = F ? iface_height(c->hiface.data(), F, 1, g.h, g.d, 0.5 * g.d, 0) : -g.h;
+  double spans[3][2] = {{e1, g.y0}, {e2, e1}, {-g.y0, e2}};
   int off = 0;
   for (int l = 0; l < 3; ++l) {
     gl_nodes_kernel<<<(g.Nw[l] + 63) / 64, 64, 0, s>>>(g.Nw[l], spans[l][0], spans[l][1],
@@ -702,11 +836,18 @@ static grt_status build_layers(grt_ctx* c) {
   }
   GRT_HIP(c, hipMalloc(&c->d_htab, sizeof(double) * HTAB_SIZE));
   htab_kernel<<<1, 64, 0, s>>>(c->d_htab);
-  GRT_HIP(c, hipMalloc(&c->d_wcorr, sizeof(cd) * 4 * (2 * K + 1)));
-  zeta_weights_kernel<<<1, 64, 0, s>>>(K, g.hs, g.k[0], g.k[1], g.k[2], g.pv[0], g.pv[1],
-                                       g.pv[2], c->d_wcorr);
+  // per-target correction weights of the same-interface blocks
+  {
+    double* zcw = nullptr;
+    GRT_HIP(c, hipMalloc(&zcw, sizeof(double) * (2 * K + 1)));
+    zeta_stencil_kernel<<<1, 64, 0, s>>>(K, zcw);
+    GRT_HIP(c, hipMalloc(&c->d_wcorr, sizeof(cd) * (size_t)8 * g.N * (2 * K + 1)));
+    curve_weights_kernel<<<(2 * g.N + 127) / 128, 128, 0, s>>>(g, zcw, c->d_wcorr);
+    GRT_HIP(c, hipGetLastError());
+    GRT_HIP(c, hipStreamSynchronize(s));
+    hipFree(zcw);
+  }
   g.wcorr = c->d_wcorr;
-  GRT_HIP(c, hipGetLastError());
 
   // A, equilibrated
   const size_t nA = (size_t)g.n_rows * g.n_alpha;

@@ -621,7 +621,8 @@ constexpr int BX_TUNE_MAX_CHUNKS = 128;
 constexpr int CX_TILE = 8;    // inclusions staged in LDS at a time, per wave
 
 // Field of all multipoles (and their copies) at the C targets, one per lane:
-//   target t < N: Gamma_1 node, t < 2N: Gamma_2 node (value, d/dy over 3 copies),
+//   target t < N: Gamma_1 node, t < 2N: Gamma_2 node (value, normal derivative over
+//   3 copies),
 //   t < 2N + Nw2: middle wall node (value, d/dx, cancelled two-term form
 //   alpha^2 Phi(L-d) - alpha^{-1} Phi(L+2d), Phi the l = 0 field).
 // With F_n = H_n(k r) e^{in theta}: value = sum x[n] F_n and, by
@@ -660,10 +661,13 @@ __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restr
   double tx[3], ty;
   cd w[3];
   const bool wall = tt >= 2 * g.N;
+  double tnx = 0.0, tny = 1.0;  // the interface's normal at the target
   if (!wall) {
-    int i = tt % g.N;
-    double x0 = -0.5 * g.d + (i + 0.5) * g.hs;
-    ty = (tt < g.N) ? g.h : -g.h;
+    const double* nd = g.node + (size_t)tt * NODE_STRIDE;  // Gamma_1 nodes, then Gamma_2
+    const double x0 = nd[0];
+    ty = nd[1];
+    tnx = nd[2];
+    tny = nd[3];
     // copies of the source at x_m + l d are equivalent to targets at x - l d
     tx[0] = x0 + g.d; w[0] = g.alpha_inv;  // l = -1
     tx[1] = x0;       w[1] = cd{1.0, 0.0};
@@ -758,7 +762,9 @@ __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restr
     A += red[(v * 64 + lane) * 3 + 1];
     B += red[(v * 64 + lane) * 3 + 2];
   }
-  cd der = wall ? (0.5 * k) * (A - B) : times_i((0.5 * k) * (A + B));
+  // d/dx = (k/2)(A - B), d/dy = (ik/2)(A + B); interface rows take the normal derivative
+  const cd gx = (0.5 * k) * (A - B);
+  cd der = wall ? gx : tnx * gx + tny * times_i((0.5 * k) * (A + B));
   cd* o = partial + ((size_t)by_ * nt + t) * 2;
   o[0] = val;
   o[1] = der;
@@ -801,12 +807,15 @@ __device__ inline void cx_reduce_block(const DevGeom& g, const cd* partial, int 
 
 // Incoming coefficients at inclusion j from the interface densities (P2L, Graf's
 // theorem for H_0 about c_j):
-//   alpha_j[n] += (i/4) hs sum_l alpha^l [G^l_n sigma - (ik/2)(G^l_{n-1} + G^l_{n+1}) mu],
+//   alpha_j[n] += (i/4) w sum_l alpha^l [G^l_n sigma
+//                 + (k/2)((n_x - i n_y) G^l_{n-1} - (n_x + i n_y) G^l_{n+1}) mu],
 //   G^l_n = H_n(k|v_l|) e^{-in theta_l}, v_l = node + l d e_x - c_j,
-// the mu term being d/dy of the sigma term (gradient identity).  Sources: 2 lines x
-// N nodes, chunked over blockIdx.y; the three copies of a node share its densities,
-// so their generators are summed (weights alpha^l folded into H_0, H_1) before the
-// contraction.  Each order m of the sum feeds acc[m] (sigma) and acc[m -+ 1] (mu).
+// w = hs * speed the node's arc-length weight, the mu term being the derivative of
+// the sigma term along the source normal n (gradient identities
+// (d_x +- i d_y) G_n = +-k G_{n-+1}).  Sources: 2 interfaces x N nodes, chunked over
+// blockIdx.y; the three copies of a node share its densities, so their generators
+// are summed (weights alpha^l folded into H_0, H_1) before the contraction.  Each
+// order m of the sum feeds acc[m] (sigma) and acc[m -+ 1] (mu).
 constexpr int BX_WAVES = 4;  // waves per block: same 64 targets, nodes split 4 ways
 template <int P>
 __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restrict__ cx,
@@ -836,13 +845,17 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
   for (int sidx = s0; sidx < s1; ++sidx) {
     const int line = sidx / g.N;
     const int i = sidx - line * g.N;
-    const double sx0 = -0.5 * g.d + (i + 0.5) * g.hs;
-    const double syp = line == 0 ? g.h : -g.h;
+    const double* nd = g.node + (size_t)sidx * NODE_STRIDE;
+    const double sx0 = nd[0];
+    const double syp = nd[1];
     const cd mu = w[g.col_off[line == 0 ? CB_MU1 : CB_MU2] + i];
     const cd sg = w[g.col_off[line == 0 ? CB_SIG1 : CB_SIG2] + i];
-    const cd pre = times_i(cd{0.25 * g.hs, 0.0});     // (i/4) hs
+    const cd pre = times_i(cd{0.25 * g.hs * nd[4], 0.0});  // (i/4) hs speed
     const cd csig = pre * sg;
-    const cd cmu = pre * times_i((-0.5 * k) * mu);     // -(ik/2) mu (i/4) hs
+    const cd pmu = pre * mu;
+    // (k/2)(n_x - i n_y) for G_{n-1}, -(k/2)(n_x + i n_y) for G_{n+1}
+    const cd cmuA = cd{0.5 * k * nd[2], -0.5 * k * nd[3]} * pmu;
+    const cd cmuB = cd{-0.5 * k * nd[2], -0.5 * k * nd[3]} * pmu;
     cd hp[3], hc[3], ec[3], ep[3];
     double rz2[3];
 #pragma unroll
@@ -862,12 +875,12 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
       // scheduled together (register peak)
       asm volatile("" ::: "memory");
     }
-    // order 0: G_0 -> acc[0] (sigma), acc[+-1] (mu)
+    // order 0: G_0 -> acc[0] (sigma), acc[+1] (as G_{n-1}) and acc[-1] (as G_{n+1})
     const cd G0 = hp[0] + hp[1] + hp[2];
     cmac(acc[P], csig, G0);
     if (P >= 1) {
-      cmac(acc[P + 1], cmu, G0);
-      cmac(acc[P - 1], cmu, G0);
+      cmac(acc[P + 1], cmuA, G0);
+      cmac(acc[P - 1], cmuB, G0);
     }
 #pragma unroll
     for (int m = 1; m <= P + 1; ++m) {
@@ -889,11 +902,12 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
         cmac(acc[P + m], csig, Gp);
         cmac(acc[P - m], csig, Gm);
       }
-      // G_m feeds acc[m - 1] and acc[m + 1]; G_{-m} feeds acc[-m + 1] and acc[-m - 1]
-      if (m - 1 <= P) cmac(acc[P + m - 1], cmu, Gp);
-      if (m + 1 <= P) cmac(acc[P + m + 1], cmu, Gp);
-      if (1 - m >= -P) cmac(acc[P + 1 - m], cmu, Gm);
-      if (-m - 1 >= -P) cmac(acc[P - m - 1], cmu, Gm);
+      // G_m feeds acc[m - 1] (as G_{n+1}) and acc[m + 1] (as G_{n-1}); G_{-m} feeds
+      // acc[-m + 1] (as G_{n-1}) and acc[-m - 1] (as G_{n+1})
+      if (m - 1 <= P) cmac(acc[P + m - 1], cmuB, Gp);
+      if (m + 1 <= P) cmac(acc[P + m + 1], cmuA, Gp);
+      if (1 - m >= -P) cmac(acc[P + 1 - m], cmuA, Gm);
+      if (-m - 1 >= -P) cmac(acc[P - m - 1], cmuB, Gm);
       if (m <= P) {
 #pragma unroll
         for (int l = 0; l < 3; ++l) {

@@ -27,7 +27,8 @@ class grt_layers(C.Structure):
     _fields_ = [("d", C.c_double), ("h", C.c_double), ("y0", C.c_double),
                 ("n_layer", C.c_double * 3), ("N", C.c_int), ("Nw", C.c_int * 3),
                 ("Q", C.c_int * 3), ("Nu", C.c_int), ("n_rb_lo", C.c_int), ("Nrb", C.c_int),
-                ("zeta_K", C.c_int), ("pinv_eps", C.c_double)]
+                ("zeta_K", C.c_int), ("pinv_eps", C.c_double),
+                ("n_fourier", C.c_int), ("iface", C.POINTER(C.c_double))]
 
 
 class grt_inclusions(C.Structure):
@@ -211,6 +212,11 @@ class Context:
                          N=dd.N, Nw=(C.c_int * 3)(*dd.Nw), Q=(C.c_int * 3)(*dd.Q), Nu=dd.Nu,
                          n_rb_lo=dd.n_rb_lo, Nrb=dd.Nrb, zeta_K=dd.zeta_K,
                          pinv_eps=dd.pinv_eps)
+        iface = getattr(pb, "interface", None)
+        if iface is not None:
+            self._iface = np.ascontiguousarray(iface, dtype=np.float64).reshape(2, 2, -1)
+            lay.n_fourier = self._iface.shape[2]
+            lay.iface = _dptr(self._iface)
         self._arrs = [np.ascontiguousarray(a, dtype=np.float64)
                       for a in (pb.x, pb.y, pb.radius, pb.n_incl)]
         inc = grt_inclusions(M=pb.M, x=_dptr(self._arrs[0]), y=_dptr(self._arrs[1]),
