@@ -4,6 +4,8 @@
   tests/golden/m1000_p20_oracle.npz  the same geometry at P=20
   tests/golden/star_m1000_oracle.npz the same packing with three-lobed non-circular
                                      inclusions (eq. par1), P=15
+  tests/golden/curved_m1000_oracle.npz  the M=1000 rules between the curved interfaces
+                                     of the paper's examples 1 and 2, P=15
 
 Each holds the CPU FP64 oracle's GMRES solution to a 1e-12 normalised residual,
 its Bragg amplitudes and flux error, the diagonal normalisation D = |H_|n|(k2 r_m)|
@@ -15,7 +17,7 @@ Calls only oracle/ (and the seeded input generator).  About 10 minutes (P=15) an
 20 minutes (P=20) on 8 cores, 3-5 GB of memory: the oracle stores the image-summed
 Hankel generator of every (target, source) pair.
 
-    python tests/golden/make_m1000_oracle.py [m1000|m1000_p20|star_m1000]
+    python tests/golden/make_m1000_oracle.py [m1000|m1000_p20|star_m1000|curved_m1000]
 """
 import os
 import sys
