@@ -64,7 +64,11 @@ class Geometry:
         self.cx = np.asarray(pb.x, float)
         self.cy = np.asarray(pb.y, float)
         self.rad = np.asarray(pb.radius, float)
-        self.kp = pb.omega * np.asarray(pb.n_incl, float)
+        # inclusion wavenumbers: complex for absorbing inclusions (index n + i n_im)
+        n_im = getattr(pb, "n_incl_im", None)
+        self.lossy = n_im is not None
+        n_p = np.asarray(pb.n_incl, float) + (1j * np.asarray(n_im, float) if self.lossy else 0)
+        self.kp = pb.omega * n_p
         # polarisation: TM (u = E_z, u and du/dn continuous) or TE (u = H_z, u and
         # (1/eps) du/dn continuous, eps = n^2).  For TE each layer's potentials carry
         # the factor pv = eps of their layer and the flux rows the factor 1/eps of the
@@ -72,7 +76,7 @@ class Geometry:
         # has both factors 1.
         self.te = getattr(pb, "polarization", "TM") == "TE"
         self.eps = tuple(n ** 2 for n in pb.n_layer)
-        self.eps_incl = np.asarray(pb.n_incl, float) ** 2
+        self.eps_incl = n_p ** 2
         self.pv = self.eps if self.te else (1.0, 1.0, 1.0)
         self.fl = tuple(1.0 / e for e in self.eps) if self.te else (1.0, 1.0, 1.0)
         self.kappa = self.k1 * np.sin(pb.phi)

@@ -37,14 +37,15 @@ def mie_coefficients(k2, kp, R, P, eps2=None, epsp=None):
     """s_n, n = -P..P, for disks (arrays kp, R of length M) -> [M, 2P+1].
 
     TM: u and du/dr continuous at r = R.  With eps2, epsp given (TE: u and
-    (1/eps) du/dr continuous) the radial derivatives are weighted by 1/eps."""
-    kp = np.atleast_1d(np.asarray(kp, float))
+    (1/eps) du/dr continuous) the radial derivatives are weighted by 1/eps.  kp (and
+    epsp) may be complex: absorbing disks."""
+    kp = np.atleast_1d(np.asarray(kp))
     R = np.atleast_1d(np.asarray(R, float))
     n = np.arange(0, P + 1)[None, :]
     x = (k2 * R)[:, None]
     y = (kp * R)[:, None]
     w2 = k2 if eps2 is None else k2 / eps2
-    kpp = (kp if epsp is None else kp / np.atleast_1d(np.asarray(epsp, float)))[:, None]
+    kpp = (kp if epsp is None else kp / np.atleast_1d(np.asarray(epsp)))[:, None]
     num = w2 * sp.jvp(n, x) * sp.jv(n, y) - kpp * sp.jv(n, x) * sp.jvp(n, y)
     den = w2 * sp.h1vp(n, x) * sp.jv(n, y) - kpp * sp.hankel1(n, x) * sp.jvp(n, y)
     s = -num / den

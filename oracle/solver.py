@@ -84,6 +84,8 @@ class Reduced:
         self.S = None
         if getattr(pb, "shape", None) is not None and G.M and G.te:
             raise NotImplementedError("non-circular inclusions are written for TM")
+        if getattr(pb, "shape", None) is not None and G.M and G.lossy:
+            raise NotImplementedError("non-circular inclusions are written lossless")
         if getattr(pb, "shape", None) is not None and G.M:
             sh = np.asarray(pb.shape, float)
             self.S = np.stack([scattering_matrix(a1, a2, a3, rot, G.k2, kp, G.P,
@@ -180,8 +182,28 @@ class Reduced:
         g = self.f - (self.C @ beta if self.G.M else 0)
         return self.pinv.apply(g)
 
+    def absorbed(self, beta):
+        """Fraction of the incident energy flux absorbed by the (disk) inclusions.
+
+        Around disk m the field is sum_n (a_n J_n + b_n H_n) e^{in theta} with b = beta_m
+        and incoming a_n = b_n / s_n; its outward energy flux through a circle is
+        4 sum_n (|b_n|^2 + Re(conj(a_n) b_n)) (Wronskian J Y' - J' Y = 2 / (pi z)), so the
+        disk absorbs -4 sum_n |b_n|^2 (|s_n|^2 + Re s_n) / |s_n|^2 (zero for lossless
+        disks: |1 + 2 s_n| = 1).  Normalised by the incident flux d k_1 cos(phi) of one
+        period (TE: the flux densities carry 1/eps of their medium)."""
+        G = self.G
+        if not G.M or not G.lossy:
+            return 0.0
+        s = self.s
+        b = np.asarray(beta)
+        nz = np.abs(s) > 0
+        per = np.where(nz, np.abs(b) ** 2 * (np.abs(s) ** 2 + s.real) / np.where(nz, np.abs(s) ** 2, 1), 0)
+        w = G.eps[0] / G.eps[1] if G.te else 1.0
+        return float(-4.0 * w * per.sum() / (G.d * G.k1 * G.cosphi))
+
     def bragg(self, beta):
-        """Propagating orders, c_n, d_n, R_n, T_n and the flux error."""
+        """Propagating orders, c_n, d_n, R_n, T_n, the absorbed fraction and the flux
+        (energy balance) error |sum R + sum T + absorbed - 1|."""
         G = self.G
         al = self.alpha_vec(beta)
         c = al[G.col["c"]]
@@ -193,9 +215,10 @@ class Reduced:
         t3 = G.eps[0] / G.eps[2] if G.te else 1.0
         Rn = np.where(prop1, G.k1n.real * np.abs(c) ** 2 / inc, 0.0)
         Tn = np.where(prop3, t3 * G.k3n.real * np.abs(d) ** 2 / inc, 0.0)
-        flux = abs(Rn.sum() + Tn.sum() - 1.0)
+        ab = self.absorbed(beta) if G.M else 0.0
+        flux = abs(Rn.sum() + Tn.sum() + ab - 1.0)
         return dict(orders=G.rb, c=c, d=d, R=Rn, T=Tn, prop1=prop1, prop3=prop3,
-                    flux_err=flux)
+                    flux_err=flux, absorbed=ab)
 
 
 def gmres(Aop, b, tol=1e-11, maxit=2000, x0=None, restart=None):

@@ -72,6 +72,10 @@ class Problem:
     # y = (+h or -h) + sum_m a_m cos(2 pi m x / d) + b_m sin(2 pi m x / d);
     # None: both flat.
     interface: Optional[np.ndarray] = None
+    # absorbing inclusions: imaginary parts of the inclusions' refractive indices
+    # (n_incl + i n_incl_im, n_incl_im >= 0; the wave e^{i k x} with k = omega n decays);
+    # None: lossless
+    n_incl_im: Optional[np.ndarray] = None
 
     @property
     def M(self) -> int:
@@ -94,6 +98,9 @@ class Problem:
             hsh.update(np.int64(self.shape_nodes).tobytes())
         if self.polarization != "TM":
             hsh.update(self.polarization.encode())
+        if self.n_incl_im is not None:
+            hsh.update(b"n_incl_im")
+            hsh.update(np.ascontiguousarray(self.n_incl_im, dtype=np.float64).tobytes())
         if self.interface is not None:
             hsh.update(b"interface")
             hsh.update(np.ascontiguousarray(self.interface, dtype=np.float64).tobytes())
@@ -377,6 +384,16 @@ def curved(M, P, omega=10.0, seed=7, phi=-math.pi / 5, d=1.0, h=0.5,
     y = +-h."""
     pb = make_problem(f"curved_M{M}_P{P}", d, h, M, 0.02, 0.04, 1.5, 3.0, 0.01, seed,
                       omega, phi, P, interface=interface_profile(*interface), **kw)
+    return pb
+
+
+def lossy(M, P, omega=10.0, seed=7, phi=-math.pi / 5, loss=(0.05, 0.5), **kw) -> Problem:
+    """small()'s geometry with absorbing inclusions: the imaginary parts of the
+    indices U[loss] from a second seeded stream (seed + 6000000)."""
+    pb = small(M, P, omega=omega, seed=seed, phi=phi, **kw)
+    pb.name = f"lossy_M{M}_P{P}"
+    rng = np.random.Generator(np.random.PCG64(seed + 6_000_000))
+    pb.n_incl_im = rng.uniform(loss[0], loss[1], size=M)
     return pb
 
 
