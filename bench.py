@@ -365,17 +365,19 @@ def relaxed_m1000(a, torch, ctx, beta, err, use_graph, use_overlap, M, P, NB, fl
                                                "coefficients in + chunk partials out"}}}
 
 
-def shapes_m1000(a, torch):
-    """Non-circular inclusions (paper eq. par1, three lobes, a2/a1 = 1/3, turned at
-    random) on the M=1000 workload's packing: build time (including every inclusion's
-    integral equation), plain FP64 and relaxed mixed solves/s in the headline's
+def variant_m1000(a, torch, case="star_m1000"):
+    """A variant of the M=1000 workload: non-circular inclusions (star_m1000: paper eq.
+    par1, three lobes, a2/a1 = 1/3, turned at random, on the same packing) or curved
+    interfaces (curved_m1000: the paper's example 1-2 graphs, disks packed by the same
+    rules).  Build time (including every inclusion's integral equation or the curved
+    layer matrix), plain FP64 and relaxed mixed solves/s in the headline's
     configuration, and the error against the stored oracle solution."""
     import numpy as np
     from paper_1412_7466_amd import inputs
     from paper_1412_7466_amd.grating import Context, GRT_FP32_RELAXED
-    pb = inputs.star_m1000()
+    pb = getattr(inputs, case)()
     gold = None
-    gpath = os.path.join(ROOT, "tests", "golden", "star_m1000_oracle.npz")
+    gpath = os.path.join(ROOT, "tests", "golden", f"{case}_oracle.npz")
     if os.path.exists(gpath):
         gold = dict(np.load(gpath))
         if str(gold["digest"]) != pb.digest():
@@ -391,9 +393,12 @@ def shapes_m1000(a, torch):
     ctx.set_overlap(True)
     if not a.no_autotune:
         ctx.autotune()
-    out = {"workload": (f"star_m1000: the m1000 packing (M=1000, P=15, omega=20) with "
-                        f"three-lobed inclusions of eq. par1 (a2/a1 = 1/3, random rotations), "
-                        f"{pb.shape_nodes} boundary nodes each, GMRES to {a.tol:g}"),
+    what = (f"three-lobed inclusions of eq. par1 (a2/a1 = 1/3, random rotations), "
+            f"{pb.shape_nodes} boundary nodes each" if case == "star_m1000" else
+            f"disks between the curved interfaces y = 1 + 0.1 sin(2 pi x), "
+            f"y = -1 + 0.2 cos(2 pi x) (N = {pb.disc.N} nodes each, Q2 = {pb.disc.Q[1]})")
+    out = {"workload": (f"{case}: the m1000 rules (M=1000, P=15, omega=20) with {what}, "
+                        f"GMRES to {a.tol:g}"),
            "build_s": t_build}
     for key, kw in (("fp64", {}), ("relaxed_mixed", {"precision": GRT_FP32_RELAXED})):
         kw = dict(tol=a.tol, restart=a.restart, graph=True, **kw)
@@ -846,7 +851,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-shapes", action="store_true",
-                    help="skip the non-circular inclusion workload")
+                    help="skip the non-circular inclusion and curved interface workloads")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="end with a plain device copy of this size (counter calibration)")
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -1095,7 +1100,8 @@ def main():
         res["sweep"] = sweep(a, torch)
         res["sweep_small"] = small_sweep(a, torch)
     if not a.no_shapes:
-        res["shapes_m1000"] = shapes_m1000(a, torch)
+        res["shapes_m1000"] = variant_m1000(a, torch, "star_m1000")
+        res["curved_m1000"] = variant_m1000(a, torch, "curved_m1000")
     if a.batch_workload > 0:
         res["batch_workload"] = batch_config(a, torch, a.batch_workload)
     if a.block_workload > 0:

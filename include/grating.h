@@ -99,6 +99,14 @@ typedef struct {
   const double *x, *y, *radius, *n_incl;
   const double* shape;
   int shape_nodes;
+  /* Absorbing disks: n_incl_im (host [M], copied; NULL: lossless) holds the imaginary
+   * parts of the indices, n_incl + i n_incl_im with n_incl_im >= 0 (the field
+   * e^{i k x - i omega t} decays for Im k > 0).  The Mie coefficients of sec. 4.1 then
+   * take J_n at the complex argument k_p R (Miller's recurrence; GRT_EUNSUP when
+   * Im(k_p R) > 2 or |k_p R| > 40, where it is not validated), grt_bragg reports the
+   * absorbed fraction, and the rest of the path is unchanged.  Disks only, and no
+   * field evaluation or warm-start network (GRT_EUNSUP). */
+  const double* n_incl_im;
 } grt_inclusions;
 
 /* Plane wave of frequency omega (k_l = omega * n_l), angle phi from the downward
@@ -332,10 +340,16 @@ grt_status grt_solve(grt_ctx* ctx, const grt_solve_opts* opts, void* beta_dev,
  * n_rhs - 1): from beta (device, that angle's [M][2P+1] vector) form
  * alpha = A^+ (f - C beta) and return, for each of the Nrb orders (host arrays of
  * length >= Nrb): orders[i], c[2i..2i+1], d[2i..2i+1] (re, im), the reflected and
- * transmitted energy fractions R[i], T[i] (zero for evanescent orders) and the
- * flux error |sum R + sum T - 1|.  GRT_EINVAL for rhs out of range. */
+ * transmitted energy fractions R[i], T[i] (zero for evanescent orders), the fraction
+ * absorbed by the disks (absorbed, may be NULL; 0 without absorbing disks:
+ * -4 sum_{m,n} |b_n|^2 (|s_n|^2 + Re s_n) / |s_n|^2 over each disk's outgoing b = beta_m,
+ * the flux of sum_n (a_n J_n + b_n H_n) e^{in theta} through a circle with a_n = b_n / s_n,
+ * over the incident flux d k_1 cos(phi); TE weights each flux by 1/eps of its medium)
+ * and the energy-balance error |sum R + sum T + absorbed - 1| (the flux error of
+ * sec. 6 for lossless media).  GRT_EINVAL for rhs out of range. */
 grt_status grt_bragg(grt_ctx* ctx, int64_t rhs, const void* beta_dev, int64_t cap, int* orders,
-                     double* c, double* d, double* R, double* T, double* flux_err);
+                     double* c, double* d, double* R, double* T, double* flux_err,
+                     double* absorbed);
 
 /* The total field of right-hand side rhs at n_pts points (host xy[2 i], xy[2 i + 1])
  * for its solution beta (device, that angle's [M][2P+1] vector; ignored when M = 0),

@@ -41,7 +41,7 @@ void free_all(grt_ctx* c) {
     c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_f = nullptr;
     c->lf.reset();
   }
-  void* bufs[] = {c->d_cx, c->d_cy, c->d_rad, c->d_kp, c->d_yw, c->d_node, c->d_wcorr, c->d_A,
+  void* bufs[] = {c->d_cx, c->d_cy, c->d_rad, c->d_kp, c->d_kp_im, c->d_yw, c->d_node, c->d_wcorr, c->d_A,
                   c->d_colscale, c->d_sv, c->d_U, c->d_VH, c->d_W1, c->d_W2, c->d_W3,
                   c->d_mie, c->d_l2l, c->d_f, c->d_pT, c->d_pC, c->d_pB, c->d_pL,
                   c->d_gvec, c->d_tvec, c->d_wvec, c->d_V, c->d_H, c->d_htab,
@@ -51,7 +51,7 @@ void free_all(grt_ctx* c) {
   for (void* p : bufs)
     if (p) hipFree(p);
   c->d_cx = c->d_cy = c->d_rad = c->d_kp = c->d_yw = c->d_colscale = c->d_sv = c->d_scal =
-      c->d_htab = c->d_node = nullptr;
+      c->d_htab = c->d_node = c->d_kp_im = nullptr;
   c->d_wcorr = c->d_A = c->d_U = c->d_VH = c->d_W1 = c->d_W2 = c->d_W3 = c->d_mie = c->d_l2l =
       c->d_f = c->d_pT = c->d_pC = c->d_pB = c->d_pL = c->d_gvec = c->d_tvec = c->d_wvec =
           c->d_V = c->d_H = c->d_y = c->d_dotpart = nullptr;
@@ -211,6 +211,28 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
   c->hn.assign(inc->n_incl, inc->n_incl + M);
   c->hshape.clear();
   c->shape_nodes = 0;
+  c->hn_im.clear();
+  c->lossy = false;
+  if (inc->n_incl_im && M > 0) {
+    for (int64_t m = 0; m < M; ++m) {
+      const double v = inc->n_incl_im[m];
+      if (!std::isfinite(v) || v < 0)
+        return set_err(c, GRT_EINVAL, "n_incl_im must be finite and >= 0");
+      if (v > 0) c->lossy = true;
+    }
+    if (c->lossy) {
+      if (inc->shape) return set_err(c, GRT_EUNSUP, "absorbing inclusions must be disks");
+      for (int64_t m = 0; m < M; ++m) {
+        // the validated range of the complex-argument Bessel recurrence
+        const double zr = wave->omega * inc->n_incl[m] * inc->radius[m];
+        const double zi = wave->omega * inc->n_incl_im[m] * inc->radius[m];
+        if (zi > 2.0 || std::hypot(zr, zi) > 40.0)
+          return set_err(c, GRT_EUNSUP, "absorbing disk " + std::to_string(m) +
+                                            ": Im(k_p R) > 2 or |k_p R| > 40");
+      }
+      c->hn_im.assign(inc->n_incl_im, inc->n_incl_im + M);
+    }
+  }
   if (inc->shape && M > 0) {
     // non-circular inclusions (eq. par1): a1 > 0, |a2| < a1, a3 a positive integer,
     // radius the enclosing circle a1 + |a2|
@@ -383,6 +405,11 @@ static grt_status upload_inclusions(grt_ctx* c) {
     GRT_HIP(c, hipMemcpy(c->d_cy, c->hy.data(), sizeof(double) * M, hipMemcpyHostToDevice));
     GRT_HIP(c, hipMemcpy(c->d_rad, c->hr.data(), sizeof(double) * M, hipMemcpyHostToDevice));
     GRT_HIP(c, hipMemcpy(c->d_kp, kp.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+    if (c->lossy) {
+      for (int64_t m = 0; m < M; ++m) kp[m] = c->inc.omega * c->hn_im[m];
+      GRT_HIP(c, hipMalloc(&c->d_kp_im, sizeof(double) * M));
+      GRT_HIP(c, hipMemcpy(c->d_kp_im, kp.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+    }
   }
   return GRT_OK;
 }
@@ -788,15 +815,37 @@ __global__ void bragg_finish_kernel(DevGeom g, double k1cos, const cd* cdv, doub
 }
 }  // namespace
 
+// Fraction of the incident flux absorbed by the disks (see grating.h): from beta and
+// the Mie diagonal on the host.
+static grt_status absorbed_fraction(grt_ctx* c, const cd* beta, double* out) {
+  *out = 0.0;
+  if (!c->lossy || c->M == 0) return GRT_OK;
+  std::vector<cd> b(c->n_beta), s(c->n_beta);
+  GRT_HIP(c, hipMemcpyAsync(b.data(), beta, sizeof(cd) * c->n_beta, hipMemcpyDeviceToHost,
+                            c->stream));
+  GRT_HIP(c, hipMemcpyAsync(s.data(), c->d_mie, sizeof(cd) * c->n_beta, hipMemcpyDeviceToHost,
+                            c->stream));
+  GRT_HIP(c, hipStreamSynchronize(c->stream));
+  double acc = 0.0;
+  for (int64_t i = 0; i < c->n_beta; ++i) {
+    const double s2 = s[i].r * s[i].r + s[i].i * s[i].i;
+    if (s2 > 0) acc += (b[i].r * b[i].r + b[i].i * b[i].i) * (s2 + s[i].r) / s2;
+  }
+  const double w = c->g.te ? c->g.pv[0] / c->g.pv[1] : 1.0;  // eps_1 / eps_2
+  *out = -4.0 * w * acc / (c->g.d * c->g.k[0] * std::cos(c->inc.phi));
+  return GRT_OK;
+}
+
 grt_status grt_bragg(grt_ctx* c0, int64_t rhs, const void* beta, int64_t cap, int* orders,
-                     double* cc, double* dd, double* R, double* T, double* flux_err) {
+                     double* cc, double* dd, double* R, double* T, double* flux_err,
+                     double* absorbed) {
   GRT_CHECK_CTX(c0);
   grt_status st = check_built(c0);
   if (st != GRT_OK) return st;
   if (rhs < 0 || rhs >= c0->n_rhs) return set_err(c0, GRT_EINVAL, "rhs out of range");
   grt_ctx* c = rhs_ctx(c0, rhs);
   if (c != c0) {
-    st = grt_bragg(c, 0, beta, cap, orders, cc, dd, R, T, flux_err);
+    st = grt_bragg(c, 0, beta, cap, orders, cc, dd, R, T, flux_err, absorbed);
     return st == GRT_OK ? st : set_err(c0, st, c->err);
   }
   const int Nrb = c->g.Nrb;
@@ -829,6 +878,14 @@ grt_status grt_bragg(grt_ctx* c0, int64_t rhs, const void* beta, int64_t cap, in
         T[i] = hr[Nrb + i];
       }
       *flux_err = hr[2 * Nrb];
+      double ab = 0.0;
+      st = absorbed_fraction(c, static_cast<const cd*>(beta), &ab);
+      if (st == GRT_OK && c->lossy) {
+        double sum = ab - 1.0;
+        for (int i = 0; i < Nrb; ++i) sum += R[i] + T[i];
+        *flux_err = std::fabs(sum);
+      }
+      if (absorbed) *absorbed = ab;
     }
   }
   hipFree(dcd);

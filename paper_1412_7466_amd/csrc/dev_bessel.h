@@ -137,6 +137,41 @@ __host__ __device__ inline void bessel_jn_array(double x, int nmax, double* out)
   for (int n = 0; n <= nmax; ++n) out[n] *= scale;
 }
 
+// J_0..J_nmax at complex z (absorbing media; |Im z| of order 1 at most) into
+// out[0..nmax]: Miller's backward recurrence J_{n-1} = (2n/z) J_n - J_{n+1} from a
+// start far above max(nmax, |z|), normalised by J_0 + 2 sum_k J_{2k} = 1 (an identity
+// for every complex z).
+__host__ __device__ inline void bessel_jn_array_c(cd z, int nmax, cd* out) {
+  const double az = sqrt(cabs2(z));
+  if (az < 1e-300) {
+    out[0] = cd{1.0, 0.0};
+    for (int n = 1; n <= nmax; ++n) out[n] = cd{0.0, 0.0};
+    return;
+  }
+  int top = nmax > (int)az ? nmax : (int)az;
+  int N = (top + 34) & ~1;
+  const cd iz2 = cdiv(cd{2.0, 0.0}, z);
+  cd jp{0.0, 0.0}, jc{1e-30, 0.0}, seven{0.0, 0.0};
+  if (N <= nmax) out[N] = jc;
+  seven += jc;  // N even, >= 2
+  for (int n = N; n >= 1; --n) {
+    cd jm = (double)n * (iz2 * jc) - jp;
+    jp = jc;
+    jc = jm;
+    int m = n - 1;
+    if (m <= nmax) out[m] = jc;
+    if (m >= 2 && !(m & 1)) seven += jc;
+    if (cabs2(jc) > 1e200) {  // |jc| > 1e100: rescale everything stored so far
+      const double sc = 1e-100;
+      jc = sc * jc; jp = sc * jp; seven = sc * seven;
+      int hi = (N < nmax) ? N : nmax;
+      for (int q = m; q <= hi; ++q) out[q] = sc * out[q];
+    }
+  }
+  const cd scale = cdiv(cd{1.0, 0.0}, jc + 2.0 * seven);
+  for (int n = 0; n <= nmax; ++n) out[n] = out[n] * scale;
+}
+
 // J_{q-1}, J_q, J_{q+1} for any integer q at x >= 0 (Miller, normalised).
 __host__ __device__ inline void bessel_j_three(double x, int q, double& jm, double& j0, double& jpl) {
   int aq = q < 0 ? -q : q;

@@ -107,6 +107,8 @@ struct grt_ctx {
   int64_t M = 0;
   std::vector<double> hx, hy, hr, hn;
   std::vector<double> hiface;  // [2][2][n_fourier] interface Fourier coefficients
+  std::vector<double> hn_im;   // imaginary parts of the disks' indices (absorbing)
+  bool lossy = false;
   // derived
   DevGeom g{};
   int P = 0, nb = 0;
@@ -116,6 +118,7 @@ struct grt_ctx {
   int rank = 0;
   // device buffers owned by the context
   double *d_cx = nullptr, *d_cy = nullptr, *d_rad = nullptr, *d_kp = nullptr;
+  double* d_kp_im = nullptr;  // [M] Im k_p of absorbing disks (null: lossless)
   double* d_yw = nullptr;
   double* d_node = nullptr;  // [2][N][NODE_STRIDE] interface nodes
   cd* d_wcorr = nullptr;

@@ -808,6 +808,7 @@ grt_status grt_nn_get_params(grt_nn* n, float* host, int64_t count) {
 grt_status grt_nn_add_sample(grt_nn* n, grt_ctx* c, const void* beta_dev, int* id) {
   if (c && c->n_rhs > 1) return GRT_EUNSUP;   // one angle per sample / prediction
   if (c && has_shapes(c)) return GRT_EUNSUP;  // node features hold the Mie diagonal
+  if (c && c->lossy) return GRT_EUNSUP;       // and real indices
   if (!n || !c || !id) return GRT_EINVAL;
   if (!c->built || c->M == 0 || c->device != n->device)
     return nset(n, GRT_ESTATE, "context not built, without inclusions, or on another device");
@@ -939,6 +940,7 @@ grt_status grt_nn_train(grt_nn* n, int64_t n_ids, const int* ids, int epochs, fl
 grt_status grt_nn_predict(grt_nn* n, grt_ctx* c, void* beta0_dev) {
   if (c && c->n_rhs > 1) return GRT_EUNSUP;   // one angle per sample / prediction
   if (c && has_shapes(c)) return GRT_EUNSUP;  // node features hold the Mie diagonal
+  if (c && c->lossy) return GRT_EUNSUP;       // and real indices
   if (!n || !c || !beta0_dev) return GRT_EINVAL;
   if (!c->built || c->M == 0 || c->device != n->device)
     return nset(n, GRT_ESTATE, "context not built, without inclusions, or on another device");

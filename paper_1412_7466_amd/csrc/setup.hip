@@ -521,10 +521,43 @@ __global__ void build_Wv_kernel(const cd* VH, int ldv, const double* E, int i0, 
 // Mie coefficients of every disk (sec. 4.1), s_{-n} = s_n:
 //   s_n = -[k2 J_n'(x) J_n(y) - kp J_n(x) J_n'(y)] / [k2 H_n'(x) J_n(y) - kp H_n(x) J_n'(y)],
 // x = k2 R, y = kp R; Z_n' = Z_{n-1} - (n/x) Z_n, Z_0' = -Z_1.
-__global__ void mie_kernel(int M, int P, double k2, const double* rad, const double* kp, cd* s,
-                           int te, double eps2, double omega) {
+// Absorbing disk (complex k_p): the same formula with J_n(y), J_n'(y) and the interior
+// weight at complex y = k_p R.
+__device__ void mie_disk_complex(int P, double k2, double R, cd kpc, cd* s, int te, double eps2,
+                                 double omega) {
+  const double x = k2 * R;
+  const cd y = R * kpc;
+  double jx[48];
+  cd jy[48];
+  bessel_jn_array(x, P + 1, jx);
+  bessel_jn_array_c(y, P + 1, jy);
+  cd H[48];
+  hankel01(x, H[0], H[1]);
+  for (int n = 1; n <= P; ++n) H[n + 1] = (2.0 * n / x) * H[n] - H[n - 1];
+  const cd iy = cdiv(cd{1.0, 0.0}, y);
+  const double w2 = te ? k2 / eps2 : k2;
+  const cd wp = te ? cdiv(cd{omega * omega, 0.0}, kpc) : kpc;  // k_p / eps_p = omega^2 / k_p
+  for (int n = 0; n <= P; ++n) {
+    double djx = (n == 0) ? -jx[1] : jx[n - 1] - (n / x) * jx[n];
+    cd djy = (n == 0) ? -jy[1] : jy[n - 1] - (double)n * (iy * jy[n]);
+    cd dH = (n == 0) ? -H[1] : H[n - 1] - (n / x) * H[n];
+    cd num = (w2 * djx) * jy[n] - jx[n] * (wp * djy);
+    cd den = (w2 * jy[n]) * dH - (wp * djy) * H[n];
+    cd sn = -cdiv(num, den);
+    s[P + n] = sn;
+    s[P - n] = sn;
+  }
+}
+
+__global__ void mie_kernel(int M, int P, double k2, const double* rad, const double* kp,
+                           const double* kp_im, cd* s, int te, double eps2, double omega) {
   int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
+  if (kp_im && kp_im[m] != 0.0) {
+    mie_disk_complex(P, k2, rad[m], cd{kp[m], kp_im[m]}, s + (size_t)m * (2 * P + 1), te, eps2,
+                     omega);
+    return;
+  }
   double R = rad[m];
   double x = k2 * R, y = kp[m] * R;
   double jx[48], jy[48];
@@ -936,7 +969,8 @@ static grt_status build_inclusions(grt_ctx* c) {
   if (c->M > 0) {
     GRT_HIP(c, hipMalloc(&c->d_mie, sizeof(cd) * c->n_beta));
     mie_kernel<<<(int)((c->M + 63) / 64), 64, 0, s>>>((int)c->M, c->P, g.k[1], c->d_rad, c->d_kp,
-                                                      c->d_mie, g.te, g.pv[1], c->inc.omega);
+                                                      c->d_kp_im, c->d_mie, g.te, g.pv[1],
+                                                      c->inc.omega);
     GRT_HIP(c, hipMalloc(&c->d_dnorm, sizeof(double) * c->n_beta));
     GRT_HIP(c, hipMalloc(&c->d_dinv, sizeof(double) * c->n_beta));
     GRT_HIP(c, hipMalloc(&c->d_xtmp, sizeof(cd) * c->n_beta));

@@ -34,7 +34,8 @@ class grt_layers(C.Structure):
 class grt_inclusions(C.Structure):
     _fields_ = [("M", C.c_int64), ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
                 ("radius", C.POINTER(C.c_double)), ("n_incl", C.POINTER(C.c_double)),
-                ("shape", C.POINTER(C.c_double)), ("shape_nodes", C.c_int)]
+                ("shape", C.POINTER(C.c_double)), ("shape_nodes", C.c_int),
+                ("n_incl_im", C.POINTER(C.c_double))]
 
 
 class grt_incidence(C.Structure):
@@ -94,7 +95,7 @@ _PROTOS = {
     "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
     "grt_bragg": (C.c_int, [_VP, C.c_int64, _VP, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
-                            C.POINTER(C.c_double)]),
+                            C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "grt_eval_field": (C.c_int, [_VP, C.c_int64, _VP, C.c_int64, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),
     "grt_get_A": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -226,6 +227,10 @@ class Context:
             self._arrs.append(np.ascontiguousarray(shape, dtype=np.float64).reshape(-1))
             inc.shape = _dptr(self._arrs[4])
             inc.shape_nodes = int(pb.shape_nodes)
+        n_im = getattr(pb, "n_incl_im", None)
+        if n_im is not None:
+            self._n_im = np.ascontiguousarray(n_im, dtype=np.float64)
+            inc.n_incl_im = _dptr(self._n_im)
         pol = GRT_TE if getattr(pb, "polarization", "TM") == "TE" else GRT_TM
         if phis is not None and len(phis) > 1:
             self._phis = np.ascontiguousarray(phis, dtype=np.float64)
@@ -405,13 +410,14 @@ class Context:
         R = np.zeros(n)
         T = np.zeros(n)
         flux = C.c_double(0)
+        absorbed = C.c_double(0)
         bp = self._vec_ptr(beta, one=True) if beta is not None else _VP(0)
         self._enter()
         self._check(self.lib.grt_bragg(self.h, rhs, bp, n, orders, _dptr(c), _dptr(d), _dptr(R),
-                                       _dptr(T), C.byref(flux)))
+                                       _dptr(T), C.byref(flux), C.byref(absorbed)))
         self._leave()
         return dict(orders=np.array(orders[:]), c=c[0::2] + 1j * c[1::2], d=d[0::2] + 1j * d[1::2],
-                    R=R, T=T, flux_err=flux.value)
+                    R=R, T=T, flux_err=flux.value, absorbed=absorbed.value)
 
     def eval_field(self, beta, xy, rhs=0):
         """Total field at the points xy ([n, 2] float64, host) for the solution beta

@@ -27,6 +27,16 @@ extern "C" void h01(int n, const double* z, double* out) {
     out[4 * i] = a.r; out[4 * i + 1] = a.i; out[4 * i + 2] = b.r; out[4 * i + 3] = b.i;
   }
 }
+extern "C" void jnc(int n, const double* z, int nmax, double* out) {
+  cd buf[128];
+  for (int i = 0; i < n; ++i) {
+    bessel_jn_array_c(cd{z[2 * i], z[2 * i + 1]}, nmax, buf);
+    for (int q = 0; q <= nmax; ++q) {
+      out[(i * (nmax + 1) + q) * 2] = buf[q].r;
+      out[(i * (nmax + 1) + q) * 2 + 1] = buf[q].i;
+    }
+  }
+}
 """
 
 P = ctypes.POINTER(ctypes.c_double)
@@ -59,3 +69,25 @@ def test_hankel01_tab_against_scipy(lib):
     e0 = np.abs(h0 - sp.hankel1(0, z)) / np.abs(sp.hankel1(0, z))
     e1 = np.abs(h1 - sp.hankel1(1, z)) / np.abs(sp.hankel1(1, z))
     assert e0.max() < 1e-14 and e1.max() < 1e-14, (e0.max(), e1.max())
+
+
+def test_complex_bessel_j_array_against_scipy(lib):
+    """bessel_jn_array_c (Miller at complex argument, for absorbing inclusions) against
+    SciPy's J_n of complex argument: Re z in [1e-4, 60], Im z in [0, 2] (the library
+    takes absorbing inclusions with Im(k_p R) <= 2: beyond it the normalising sum
+    cancels like e^{|Im z|}), orders 0..40, relative error per entry."""
+    sp = pytest.importorskip("scipy.special")
+    rng = np.random.default_rng(2)
+    z = 10 ** rng.uniform(-4, np.log10(60), 600) + 1j * rng.uniform(0.0, 2.0, 600)
+    nmax = 40
+    zz = np.stack([z.real, z.imag], axis=1).reshape(-1).copy()
+    o = np.empty(2 * len(z) * (nmax + 1))
+    lib.jnc(len(z), zz.ctypes.data_as(P), nmax, o.ctypes.data_as(P))
+    o = o.reshape(len(z), nmax + 1, 2)
+    J = o[..., 0] + 1j * o[..., 1]
+    ref = sp.jv(np.arange(nmax + 1)[None, :], z[:, None])
+    err = np.abs(J - ref) / np.maximum(np.abs(ref), 1e-300)
+    big = np.abs(ref) > 1e-250
+    near = np.abs(z)[:, None] <= 40
+    assert np.max(err[big & near]) < 1e-12
+    assert np.max(err[big]) < 1e-10        # |z| up to 60: the recurrence's rounding grows

@@ -1,6 +1,7 @@
 """Full-size parity: the M=1000 workload the benchmark times (P=15) and the same
 geometry at P=20, against the CPU FP64 oracle's stored results
-(tests/golden/m1000_oracle.npz and m1000_p20_oracle.npz, written by
+(tests/golden/m1000_oracle.npz, m1000_p20_oracle.npz, star_m1000_oracle.npz and
+curved_m1000_oracle.npz, written by
 tests/golden/make_m1000_oracle.py from oracle/ only).
 
 Same launch configuration as the benchmark (the work split is a function of M and
@@ -159,6 +160,29 @@ def test_star_m1000():
         say(f"[gpu] star_m1000 relaxed iters={st.iters} fp32={st.fp32_applies} "
             f"resid={st.rel_resid:.2e}")
         _check_solution(ctx, beta, gold, pb, "star_m1000 relaxed")
+    finally:
+        ctx.close()
+
+
+def test_curved_m1000():
+    """The M=1000 rules between the curved interfaces of the paper's examples 1 and 2:
+    K and T on the stored probe, the FP64 and relaxed mixed solutions and their Bragg
+    amplitudes against the oracle (tests/golden/curved_m1000_oracle.npz)."""
+    from paper_1412_7466_amd.grating import GRT_FP32_RELAXED
+    if not os.path.exists(os.path.join(GOLD, "curved_m1000_oracle.npz")):
+        pytest.skip("tests/golden/curved_m1000_oracle.npz not generated")
+    torch, ctx, gold, pb = _load("curved_m1000")
+    try:
+        _check_apply(torch, ctx, gold, pb, "curved_m1000")
+        beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000)
+        say(f"[gpu] curved_m1000 FP64 iters={st.iters} resid={st.rel_resid:.2e} {st.seconds:.3f}s")
+        _check_solution(ctx, beta, gold, pb, "curved_m1000 FP64")
+        ctx.set_table32(True)
+        beta, st = ctx.solve(tol=1e-12, restart=200, maxit=1000, precision=GRT_FP32_RELAXED,
+                             inner_tol=1e-6)
+        say(f"[gpu] curved_m1000 relaxed iters={st.iters} fp32={st.fp32_applies} "
+            f"resid={st.rel_resid:.2e}")
+        _check_solution(ctx, beta, gold, pb, "curved_m1000 relaxed")
     finally:
         ctx.close()
 
