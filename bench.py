@@ -587,6 +587,63 @@ def small_sweep(a, torch, n=32, M_range=(20, 100)):
 FP32_MFMA_PEAK_TFLOPS = 157.3   # dense FP32 matrix-core peak of the MI355X
 
 
+def fmm_translation(a, torch):
+    """The fast cell translation against the dense one on the large block geometry's
+    packing (d=4, middle layer [-2, 2], radii U[0.005, 0.01], omega=40, P=20, first
+    angle) at M = fmm_M: translation-only build, T x timed with HIP events on the
+    context's stream for both (the dense translation with its generator on the fly),
+    and their difference on a probe (S T, per order in the basis D s of K)."""
+    import numpy as np
+    import scipy.special as sp
+    from paper_1412_7466_amd import inputs
+    from paper_1412_7466_amd.grating import Context
+    pb, _ = inputs.large_block(M=a.fmm_M, R=1)
+    P = pb.P
+    ctx = Context(0)
+    ctx.set_problem(pb)
+    ctx.build_translation()
+    k2 = pb.omega * pb.n_layer[1]
+    n = np.abs(np.arange(-P, P + 1))
+    D = np.abs(sp.hankel1(n[None, :], k2 * np.asarray(pb.radius)[:, None])).reshape(-1)
+    s = ctx.get_mie()
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(D.size) + 1j * rng.standard_normal(D.size)
+    x = torch.tensor(u / D, dtype=torch.complex128, device="cuda:0")
+    y = ctx.new_vec()
+    st = ctx.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(reps):
+        ctx.apply_T(x, y)
+        torch.cuda.synchronize()
+        ev[0].record(st)
+        for _ in range(reps):
+            ctx.apply_T(x, y)
+        ev[1].record(st)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps, y.cpu().numpy()
+
+    dense_ms, y0 = timed(2)
+    print(f"[bench] fmm leg: dense translation {dense_ms:.2f} ms", flush=True)
+    out = {"workload": (f"large block packing, M={pb.M}, omega={pb.omega:g}, P={P}, one angle: "
+                        f"T x by cells against the dense translation (generator on the fly)"),
+           "dense_ms": dense_ms}
+    for per_cell in (24, 40, 64):
+        t0 = time.perf_counter()
+        nx, ny, p = ctx.set_fmm(True, per_cell=per_cell)
+        torch.cuda.synchronize()
+        t_set = time.perf_counter() - t0
+        ms, y1 = timed(5)
+        e = np.abs(D * s * (y1 - y0)).reshape(pb.M, -1).max(0)
+        sc = np.abs(D * s * y0).reshape(pb.M, -1).max(0)
+        out[f"per_cell_{per_cell}"] = {"cells": [nx, ny], "p": p, "setup_s": t_set, "ms": ms,
+                                       "speedup_vs_dense": dense_ms / ms,
+                                       "max_rel_err_per_order_DsT": float((e / sc).max())}
+        print(f"[bench] fmm leg: {per_cell}/cell {nx}x{ny} p={p}: {ms:.2f} ms", flush=True)
+    ctx.close()
+    return out
+
+
 def block_translation(a, torch):
     """S T of R incidence angles at once on the FP32 matrix cores, on the large block
     geometry (d=4, omega=40, P=20, radii U[0.005, 0.01]): the context is built for the
@@ -863,6 +920,8 @@ def main():
                     help="also time S T of R angles at once on the FP32 matrix cores "
                          "(large block geometry, translation-only build)")
     ap.add_argument("--block-M", type=int, default=10000)
+    ap.add_argument("--fmm-M", type=int, default=0,
+                    help="also time the cell translation against the dense one at this M")
     ap.add_argument("--block-reps", type=int, default=2)
     ap.add_argument("--flops-record", metavar="PMC_DB",
                     help="write the FP64 counter summary from one counter run and exit")
@@ -1106,6 +1165,8 @@ def main():
         res["batch_workload"] = batch_config(a, torch, a.batch_workload)
     if a.block_workload > 0:
         res["block_translation"] = block_translation(a, torch)
+    if a.fmm_M > 0:
+        res["fmm_translation"] = fmm_translation(a, torch)
     if a.copy_probe_mib > 0:
         src = torch.ones(a.copy_probe_mib * 131072, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)

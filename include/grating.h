@@ -219,6 +219,22 @@ grt_status grt_build_translation(grt_ctx* ctx);
 
 grt_status grt_query(const grt_ctx* ctx, grt_sizes* out);
 
+/* Fast translation for large M (the fast-multipole acceleration of T that the
+ * paper's complexity remarks in secs. 5 and 7 name), enable = 1: a single-level cell
+ * scheme.  The inclusion centres are binned into square cells (about per_cell each, 0:
+ * 40; at least 3 across the period); a cell and the cells adjacent to it, the
+ * neighbours on the copies l = -1, +1 included, are translated pair by pair as in
+ * sec. 4.2, every other (cell, copy) pair through cell expansions of order p_cell
+ * (0: k_2 times the cell diagonal plus 25, at most 127): outgoing shift to the cell
+ * centre, multipole-to-local between cell centres (a generator table over cell
+ * offsets built here), local shift to each target (Graf's theorem each).  Same
+ * operator as the dense translation up to the expansions' truncation.  Afterwards
+ * grt_apply (FP64), grt_apply_T and FP64 grt_solve use it; mixed precision and
+ * batches need the dense translation (GRT_EUNSUP), as do several angles, P > 20,
+ * and disks wider than half a cell.  info (may be NULL): nx, ny, p.  enable = 0
+ * returns to the dense translation.  Allocates O(M + cells (p + offsets p)). */
+grt_status grt_set_fmm(grt_ctx* ctx, int enable, int p_cell, int per_cell, int* info);
+
 /* y = K x with K = I - S T + S B_phys A^+ C, the left-preconditioned Schur
  * operator of sec. 5 (B_phys = -B of the paper).  x, y: device [n_rhs][M][2P+1]
  * complex FP64 (each angle's own K), may not alias.  precision GRT_FP64:
@@ -377,7 +393,8 @@ grt_status grt_eval_field(grt_ctx* ctx, int64_t rhs, const void* beta_dev, int64
  * column scales to host buffers (diagnostics / tests; the first angle's). */
 grt_status grt_get_A(grt_ctx* ctx, double* A_host, double* colscale_host);
 
-/* Copy the Mie diagonal [M][2P+1] complex to a host buffer (diagnostics / tests). */
+/* Copy the Mie diagonal [M][2P+1] complex to a host buffer (diagnostics / tests; also
+ * after grt_build_translation). */
 grt_status grt_get_mie(grt_ctx* ctx, double* s_host);
 
 /* Kernel timing for measurement tools.  While enabled, every launch of the

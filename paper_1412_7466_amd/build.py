@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgrating.so")
 SOURCES = ["capi.hip", "setup.hip", "apply.hip", "krylov.hip", "batch.hip", "nn.hip", "field.hip",
-           "block.hip", "inclusion.hip"]
+           "block.hip", "inclusion.hip", "fmm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

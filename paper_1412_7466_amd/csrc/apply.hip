@@ -498,10 +498,20 @@ static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode,
     st = lowrank_tail(c, c->d_gvec, c->stream2);
     if (st != GRT_OK) return st;
     GRT_HIP(c, hipEventRecord(c->ev_join, c->stream2));
-    GRT_P_DISPATCH(launch_m2l, c->P, c, x);
+    if (c->fmm_on) {
+      st = fmm_apply(c, x, s);
+      if (st != GRT_OK) return st;
+    } else {
+      GRT_P_DISPATCH(launch_m2l, c->P, c, x);
+    }
     GRT_HIP(c, hipStreamWaitEvent(s, c->ev_join, 0));
   } else {
-    if (needT) GRT_P_DISPATCH(launch_m2l, c->P, c, x);
+    if (needT && c->fmm_on) {
+      grt_status st = fmm_apply(c, x, s);
+      if (st != GRT_OK) return st;
+    } else if (needT) {
+      GRT_P_DISPATCH(launch_m2l, c->P, c, x);
+    }
     if (needB) {
       grt_status st = cx_apply(c, x);
       if (st != GRT_OK) return st;
@@ -512,8 +522,9 @@ static grt_status run_apply(grt_ctx* c, const cd* x, cd* y, int mode,
   int n = (int)c->n_beta;
   // non-circular inclusions: w = T x - B x first, then y = x - S w with the blocks
   const bool dense = c->d_sblk && mode == 0;
+  const int tch = c->fmm_on ? fmm_partials() : c->m2l_nchunks;
   combine_kernel<<<(n + CMB_ENTRIES - 1) / CMB_ENTRIES, 256, 0, s>>>(
-      n, x, c->d_mie, c->d_pT, needT ? c->m2l_nchunks : 0, c->d_pB, needB ? c->b_nchunks : 0,
+      n, x, c->d_mie, c->d_pT, needT ? tch : 0, c->d_pB, needB ? c->b_nchunks : 0,
       needB ? c->d_pL : nullptr, dense ? c->d_wS : y, dense ? 4 : mode,
       dense ? nullptr : oscale);
   if (dense) launch_sblock_apply(c, x, c->d_wS, y, 0, oscale, s);
@@ -530,6 +541,7 @@ grt_status apply_K(grt_ctx* c, const cd* x, cd* y, const double* oscale) {
 // preconditioner.  With the two-stream option the FP64 layer correction runs on the
 // second stream alongside the translation.
 grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y, const double* oscale) {
+  if (c->fmm_on) return set_err(c, GRT_EUNSUP, "the cell translation is FP64 only");
   if (c->M == 0) return GRT_OK;
   hipStream_t s = c->stream;
   const int n = (int)c->n_beta;
@@ -648,6 +660,7 @@ grt_status table32_set(grt_ctx* c, bool on) {
 // keep the fastest.  Reports up to cap (chunks, split, ms) triples.
 grt_status autotune_m2l(grt_ctx* c, int cap, int* n_out, int* chunks_out, int* splits_out,
                         double* ms_out) {
+  if (c->fmm_on) return set_err(c, GRT_EUNSUP, "autotune the dense translation (cell translation on)");
   if (c->M == 0) {
     if (n_out) *n_out = 0;
     return GRT_OK;

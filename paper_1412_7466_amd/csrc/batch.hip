@@ -1233,8 +1233,10 @@ extern "C" {
 
 grt_status grt_batch_create(grt_batch** out, int64_t n, grt_ctx* const* ctxs, void* hip_stream) {
   if (!out || n <= 0 || !ctxs) return GRT_EINVAL;
-  for (int64_t i = 0; i < n; ++i)
+  for (int64_t i = 0; i < n; ++i) {
     if (ctxs[i] && ctxs[i]->n_rhs > 1) return GRT_EINVAL;   // its solves batch its angles
+    if (ctxs[i] && ctxs[i]->fmm_on) return GRT_EUNSUP;      // batches run the dense translation
+  }
   return batch_create_impl(out, n, ctxs, hip_stream);
 }
 

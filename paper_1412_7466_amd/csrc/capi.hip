@@ -26,6 +26,7 @@ namespace {
 void free_all(grt_ctx* c) {
   graph_reset(c);
   ++c->gen;
+  fmm_release(c);
   if (c->rhs_batch) {
     grt_batch_destroy(c->rhs_batch);
     c->rhs_batch = nullptr;
@@ -678,6 +679,32 @@ grt_status grt_set_overlap(grt_ctx* c, int on) {
   return GRT_OK;
 }
 
+grt_status grt_set_fmm(grt_ctx* c, int enable, int p_cell, int per_cell, int* info) {
+  GRT_CHECK_CTX(c);
+  grt_status st = check_translation(c);
+  if (st != GRT_OK) return st;
+  if (enable != 0 && enable != 1) return set_err(c, GRT_EINVAL, "enable must be 0 or 1");
+  if (p_cell < 0 || per_cell < 0) return set_err(c, GRT_EINVAL, "p_cell, per_cell must be >= 0");
+  if (enable && c->n_rhs > 1)
+    return set_err(c, GRT_EUNSUP, "the cell translation takes one angle");
+  GRT_HIP(c, hipSetDevice(c->device));
+  GRT_HIP(c, hipStreamSynchronize(c->stream));
+  graph_reset(c);
+  ++c->gen;
+  if (!enable) {
+    fmm_release(c);
+  } else {
+    st = fmm_setup(c, p_cell, per_cell);
+    if (st != GRT_OK) return st;
+  }
+  if (info) {
+    info[0] = c->fmm_on ? c->fmm_nx : 0;
+    info[1] = c->fmm_on ? c->fmm_ny : 0;
+    info[2] = c->fmm_on ? c->fmm_p : 0;
+  }
+  return GRT_OK;
+}
+
 grt_status grt_set_launch(grt_ctx* c, int m2l_chunks, int m2l_split) {
   GRT_CHECK_CTX(c);
   grt_status st = check_translation(c);
@@ -784,6 +811,8 @@ grt_status grt_solve(grt_ctx* c, const grt_solve_opts* o, void* beta, grt_solve_
   if (!(o->tol > 0 && o->tol < 1)) return set_err(c, GRT_EINVAL, "tol must be in (0, 1)");
   if (o->precision != GRT_FP64 && o->precision != GRT_FP32 && o->precision != GRT_FP32_RELAXED)
     return set_err(c, GRT_EINVAL, "precision must be GRT_FP64, GRT_FP32 or GRT_FP32_RELAXED");
+  if (c->fmm_on && o->precision != GRT_FP64)
+    return set_err(c, GRT_EUNSUP, "the cell translation is FP64 only");
   grt_solve_stats tmp{};
   grt_solve_stats* sp = stats ? stats : &tmp;
   if (c->M == 0) {
@@ -932,7 +961,7 @@ grt_status grt_profile_read(grt_ctx* c, double* m2l_ms_total, int64_t* m2l_launc
 
 grt_status grt_get_mie(grt_ctx* c, double* s_host) {
   GRT_CHECK_CTX(c);
-  grt_status st = check_built(c);
+  grt_status st = check_translation(c);  // the Mie diagonal is part of the translation build
   if (st != GRT_OK) return st;
   if (!s_host) return set_err(c, GRT_EINVAL, "null buffer");
   if (c->M > 0)

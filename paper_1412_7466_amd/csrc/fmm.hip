@@ -1,0 +1,380 @@
+// Fast translation for large M: a single-level cell scheme for T x (paper sec. 4.2
+// and the fast-multipole acceleration its complexity remarks name), computing the
+// same operator as the dense translation up to the truncation of the cell
+// expansions.
+//
+// The inclusion centres are binned into an nx x ny grid of cells tiling the period
+// (x in [-d/2, d/2)) and the centres' y range.  A source cell B, taken on copy
+// l = -1, 0, 1 (shifted by l d, phased by alpha^l), is near a target cell A when the
+// two are adjacent, |ax - (bx + l nx)| <= 1 and |ay - by| <= 1; those pairs are
+// translated directly, one inclusion pair at a time, and everything else goes
+// through the cells' expansions of order p (|mu| <= p):
+//   P2M  M_B[mu] = sum_{m in B} sum_nu G_{nu-mu}(C_B - c_m) x_m[nu]
+//   M2L  L_A[n]  = sum_B sum_mu tau^{(AB)}_{mu-n} M_B[mu],
+//        tau^{(AB)}_q = sum_{l: (A, B, l) far} alpha^l F_q(C_A - C_B - l d)
+//   L2L  y_j[n] += sum_q G_{q-n}(c_j - C_A) L_A[q]
+// with F_q(v) = H_q(k|v|) e^{iq arg v} and G_q(v) = J_q(k|v|) e^{iq arg v} (Graf's
+// theorem for the outgoing shift, the multipole-to-local translation and the local
+// shift).  On a uniform grid tau^{(AB)} depends only on (ax - bx, ay - by), so the
+// generators form a small table built once.  The near part writes one partial result
+// per neighbour slot (3 x 3), the far part one more; the combine sums them like the
+// dense translation's chunk partials.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "dev_bessel.h"
+#include "grt_internal.h"
+#include "translate.h"
+
+namespace {
+
+using namespace grt;
+
+constexpr int FMM_PMAX = 127;                 // cell order: 2p + 1 <= 255 threads
+constexpr int FMM_QMAX = FMM_PMAX + 40;       // |q| <= p + P in the inclusion <-> cell shifts
+constexpr int FMM_THREADS = 256;
+constexpr int FMM_SLOTS = 9;                  // near neighbour slots (dx, dy) in {-1,0,1}^2
+
+__device__ __forceinline__ cd copy_weight(cd alpha, cd alpha_inv, int l) {
+  return l == 0 ? cd{1.0, 0.0} : (l > 0 ? alpha : alpha_inv);
+}
+
+// Generator table: gen[e][q + 2p], q = -2p..2p, e = (dx + nx - 1)(2 ny - 1) + dy + ny - 1
+// for the cell offsets dx = ax - bx, dy = ay - by; the far copies only.
+__global__ void fmm_gen_kernel(int nx, int ny, double sx, double sy, int p, double k, cd alpha,
+                               cd alpha_inv, cd* gen) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ne = (2 * nx - 1) * (2 * ny - 1);
+  if (e >= ne) return;
+  const int dx = e / (2 * ny - 1) - (nx - 1), dy = e % (2 * ny - 1) - (ny - 1);
+  const int NQ = 4 * p + 1;
+  cd* row = gen + (size_t)e * NQ;
+  for (int q = 0; q < NQ; ++q) row[q] = cd{0.0, 0.0};
+  for (int l = -1; l <= 1; ++l) {
+    if (abs(dx - l * nx) <= 1 && abs(dy) <= 1) continue;  // near: translated directly
+    const double vx = (dx - l * nx) * sx, vy = dy * sy;    // C_A - C_B - l d
+    const double r = sqrt(vx * vx + vy * vy), z = k * r;
+    const cd e1{vx / r, vy / r};
+    const cd w = copy_weight(alpha, alpha_inv, l);
+    cd hp, hc;
+    hankel01(z, hp, hc);
+    row[2 * p] += w * hp;
+    cd ep = e1;
+    for (int q = 1; q <= 2 * p; ++q) {
+      const cd t = hc * ep;                 // H_q e^{iq phi}
+      cd tm = hc * conj(ep);                // H_{-q} e^{-iq phi} = (-1)^q H_q e^{-iq phi}
+      if (q & 1) tm = -tm;
+      row[2 * p + q] += w * t;
+      row[2 * p - q] += w * tm;
+      const cd hn = (2.0 * q / z) * hc - hp;  // upward recurrence
+      hp = hc;
+      hc = hn;
+      ep = ep * e1;
+    }
+  }
+}
+
+// G[QN + q] = J_q(k r) e^{iq theta}, q = -QN..QN, for v = r e^{i theta} (block-wide;
+// J by Miller on thread 0, the powers in parallel).  jn: LDS scratch of QN + 1.
+__device__ void local_row(double vx, double vy, double k, int QN, double* jn, cd* G) {
+  const double r = sqrt(vx * vx + vy * vy);
+  if (threadIdx.x == 0) bessel_jn_array(k * r, QN, jn);
+  __syncthreads();
+  const cd e1 = r > 0 ? cd{vx / r, vy / r} : cd{1.0, 0.0};
+  for (int q = threadIdx.x; q <= QN; q += blockDim.x) {
+    const cd ep = cpowi(e1, q);
+    G[QN + q] = jn[q] * ep;
+    const double s = (q & 1) ? -1.0 : 1.0;  // J_{-q} = (-1)^q J_q
+    G[QN - q] = (s * jn[q]) * conj(ep);
+  }
+  __syncthreads();
+}
+
+// P2M: one block per cell, thread t <-> mu = t - p.
+template <int P>
+__global__ void __launch_bounds__(FMM_THREADS) fmm_p2m_kernel(
+    const int* __restrict__ start, const int* __restrict__ order, const double* __restrict__ cx,
+    const double* __restrict__ cy, const cd* __restrict__ x, int ny, double x0, double y0,
+    double sx, double sy, int p, double k, cd* Mc) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ double jn[FMM_QMAX + 1];
+  __shared__ cd G[2 * FMM_QMAX + 1];
+  __shared__ cd xs[NB];
+  const int cell = blockIdx.x, t = threadIdx.x;
+  const double Cx = x0 + (cell / ny + 0.5) * sx, Cy = y0 + (cell % ny + 0.5) * sy;
+  const int QN = P + p;
+  cd acc{0.0, 0.0};
+  for (int e = start[cell]; e < start[cell + 1]; ++e) {
+    const int m = order[e];
+    __syncthreads();  // the previous inclusion's G and xs are no longer read
+    if (t < NB) xs[t] = x[(size_t)m * NB + t];
+    local_row(Cx - cx[m], Cy - cy[m], k, QN, jn, G);
+    if (t < 2 * p + 1) {
+      const int mu = t - p;
+#pragma unroll 4
+      for (int nu = -P; nu <= P; ++nu) cmac(acc, G[QN + nu - mu], xs[nu + P]);
+    }
+  }
+  if (t < 2 * p + 1) Mc[(size_t)cell * (2 * p + 1) + t] = acc;
+}
+
+// M2L: one block per target cell, thread t <-> n = t - p; every source cell's
+// multipole is staged in LDS and contracted with its generator row.
+__global__ void __launch_bounds__(FMM_THREADS) fmm_m2l_kernel(const cd* __restrict__ Mc,
+                                                             const cd* __restrict__ gen, int nx,
+                                                             int ny, int p, cd* L) {
+  __shared__ cd ms[2 * FMM_PMAX + 1];
+  const int A = blockIdx.x, t = threadIdx.x;
+  const int ax = A / ny, ay = A % ny;
+  const int NB = 2 * p + 1, NQ = 4 * p + 1;
+  cd acc{0.0, 0.0};
+  for (int B = 0; B < nx * ny; ++B) {
+    const int e = (ax - B / ny + nx - 1) * (2 * ny - 1) + (ay - B % ny + ny - 1);
+    __syncthreads();
+    if (t < NB) ms[t] = Mc[(size_t)B * NB + t];
+    __syncthreads();
+    if (t < NB) {
+      // tau_{mu - n} at index mu - n + 2p = i - t + 2p for mu = i - p
+      const cd* g = gen + (size_t)e * NQ + 2 * p - t;
+#pragma unroll 4
+      for (int i = 0; i < NB; ++i) cmac(acc, g[i], ms[i]);
+    }
+  }
+  if (t < NB) L[(size_t)A * NB + t] = acc;
+}
+
+// L2L: one block per cell; for each inclusion j of the cell, thread t <-> n = t - P:
+// out[j][n] = sum_q G_{q-n}(c_j - C_A) L_A[q].
+template <int P>
+__global__ void __launch_bounds__(FMM_THREADS) fmm_l2l_kernel(
+    const int* __restrict__ start, const int* __restrict__ order, const double* __restrict__ cx,
+    const double* __restrict__ cy, const cd* __restrict__ L, int ny, double x0, double y0,
+    double sx, double sy, int p, double k, cd* out) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ double jn[FMM_QMAX + 1];
+  __shared__ cd G[2 * FMM_QMAX + 1];
+  __shared__ cd ls[2 * FMM_PMAX + 1];
+  const int cell = blockIdx.x, t = threadIdx.x;
+  const double Cx = x0 + (cell / ny + 0.5) * sx, Cy = y0 + (cell % ny + 0.5) * sy;
+  const int QN = P + p;
+  for (int i = t; i < 2 * p + 1; i += blockDim.x) ls[i] = L[(size_t)cell * (2 * p + 1) + i];
+  for (int e = start[cell]; e < start[cell + 1]; ++e) {
+    const int j = order[e];
+    __syncthreads();
+    local_row(cx[j] - Cx, cy[j] - Cy, k, QN, jn, G);
+    if (t < NB) {
+      const int n = t - P;
+      cd acc{0.0, 0.0};
+#pragma unroll 4
+      for (int q = -p; q <= p; ++q) cmac(acc, G[QN + q - n], ls[q + p]);
+      out[(size_t)j * NB + t] = acc;
+    }
+  }
+}
+
+// Near part: grid (target groups, 9 neighbour slots), one wave per block, lane =
+// target.  Slot s = (dx + 1) 3 + (dy + 1) takes the source cell at (ax + dx, ay + dy)
+// (x wrapping onto the copies l = -1, +1); the pair (j, j, 0) is excluded.  Writes
+// partial s + 1 of every target of the group (zero for a slot outside the grid).
+template <int P>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 8))) fmm_near_kernel(
+    const int2* __restrict__ groups, const int* __restrict__ start, const int* __restrict__ order,
+    const double* __restrict__ cx, const double* __restrict__ cy, const cd* __restrict__ x,
+    int nx, int ny, double d, double k, cd alpha, cd alpha_inv, const double* __restrict__ htab,
+    cd* part, int64_t n_beta) {
+  constexpr int NB = 2 * P + 1;
+  __shared__ double stab[HTAB_SIZE];
+  __shared__ cd xs[NB];
+  for (int i = threadIdx.x; i < HTAB_SIZE; i += blockDim.x) stab[i] = htab[i];
+  __syncthreads();
+  const int2 gr = groups[blockIdx.x];  // (cell, first index into the cell's list)
+  const int A = gr.x;
+  const int e0 = start[A] + gr.y;
+  const int e = e0 + (int)threadIdx.x;
+  const bool live = e < start[A + 1];
+  const int j = live ? order[e] : 0;
+  const int slot = blockIdx.y;
+  const int sdx = slot / 3 - 1, sdy = slot % 3 - 1;
+  int bx = A / ny + sdx, l = 0;
+  if (bx < 0) { bx += nx; l = -1; }
+  if (bx >= nx) { bx -= nx; l = 1; }
+  const int by = A % ny + sdy;
+  cd acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
+  if (by >= 0 && by < ny) {
+    const int B = bx * ny + by;
+    // the dense kernels' pair routine with the one copy l weighted (the other two get
+    // weight zero: a little more generator work, the same register layout)
+    const cd wl[3] = {cd{0.0, 0.0}, copy_weight(alpha, alpha_inv, l), cd{0.0, 0.0}};
+    const double tx = live ? cx[j] : 0.0, ty = live ? cy[j] : 0.0;
+    for (int f = start[B]; f < start[B + 1]; ++f) {
+      const int m = order[f];
+      __syncthreads();  // the previous source's coefficients are no longer read
+      if (threadIdx.x < NB) xs[threadIdx.x] = x[(size_t)m * NB + threadIdx.x];
+      __syncthreads();
+      if (!live || (m == j && l == 0)) continue;
+      pair_accumulate<P, cd>(acc, (const cd*)xs, tx - (cx[m] + l * d), ty - cy[m], k, d, wl, false,
+                             false, (const double*)stab, 0.0);
+    }
+  }
+  if (live) {
+    cd* o = part + (size_t)(slot + 1) * n_beta + (size_t)j * NB;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) o[n] = acc[n];
+  }
+}
+
+template <int P>
+void launch_fmm(grt_ctx* c, const cd* x, hipStream_t s) {
+  const int ncell = c->fmm_nx * c->fmm_ny;
+  fmm_p2m_kernel<P><<<ncell, FMM_THREADS, 0, s>>>(c->d_fmm_start, c->d_fmm_order, c->d_cx,
+                                                  c->d_cy, x, c->fmm_ny, c->fmm_x0, c->fmm_y0,
+                                                  c->fmm_sx, c->fmm_sy, c->fmm_p, c->g.k[1],
+                                                  c->d_fmm_M);
+  fmm_m2l_kernel<<<ncell, FMM_THREADS, 0, s>>>(c->d_fmm_M, c->d_fmm_gen, c->fmm_nx, c->fmm_ny,
+                                              c->fmm_p, c->d_fmm_L);
+  fmm_l2l_kernel<P><<<ncell, FMM_THREADS, 0, s>>>(c->d_fmm_start, c->d_fmm_order, c->d_cx,
+                                                  c->d_cy, c->d_fmm_L, c->fmm_ny, c->fmm_x0,
+                                                  c->fmm_y0, c->fmm_sx, c->fmm_sy, c->fmm_p,
+                                                  c->g.k[1], c->d_pT);
+  dim3 grid((unsigned)c->fmm_ngroups, FMM_SLOTS);
+  fmm_near_kernel<P><<<grid, 64, 0, s>>>(c->d_fmm_groups, c->d_fmm_start, c->d_fmm_order,
+                                         c->d_cx, c->d_cy, x, c->fmm_nx, c->fmm_ny, c->g.d,
+                                         c->g.k[1], c->g.alpha, c->g.alpha_inv, c->d_htab,
+                                         c->d_pT, c->n_beta);
+}
+
+void free_fmm(grt_ctx* c) {
+  for (void* q : {(void*)c->d_fmm_start, (void*)c->d_fmm_order, (void*)c->d_fmm_groups,
+                  (void*)c->d_fmm_gen, (void*)c->d_fmm_M, (void*)c->d_fmm_L})
+    if (q) hipFree(q);
+  c->d_fmm_start = c->d_fmm_order = nullptr;
+  c->d_fmm_groups = nullptr;
+  c->d_fmm_gen = c->d_fmm_M = c->d_fmm_L = nullptr;
+  c->fmm_on = false;
+}
+
+}  // namespace
+
+int fmm_partials() { return 1 + FMM_SLOTS; }
+
+void fmm_release(grt_ctx* c) { free_fmm(c); }
+
+grt_status fmm_apply(grt_ctx* c, const cd* x, hipStream_t s) {
+  switch (c->P) {
+    case 1: launch_fmm<1>(c, x, s); break;
+    case 2: launch_fmm<2>(c, x, s); break;
+    case 3: launch_fmm<3>(c, x, s); break;
+    case 4: launch_fmm<4>(c, x, s); break;
+    case 5: launch_fmm<5>(c, x, s); break;
+    case 6: launch_fmm<6>(c, x, s); break;
+    case 8: launch_fmm<8>(c, x, s); break;
+    case 10: launch_fmm<10>(c, x, s); break;
+    case 12: launch_fmm<12>(c, x, s); break;
+    case 15: launch_fmm<15>(c, x, s); break;
+    case 20: launch_fmm<20>(c, x, s); break;
+    default: return set_err(c, GRT_EUNSUP, "the cell translation takes P <= 20");
+  }
+  GRT_HIP(c, hipGetLastError());
+  return GRT_OK;
+}
+
+grt_status fmm_setup(grt_ctx* c, int p_cell, int per_cell) {
+  free_fmm(c);
+  const int64_t M = c->M;
+  if (M == 0) return GRT_OK;
+  if (c->P > 20) return set_err(c, GRT_EUNSUP, "the cell translation takes P <= 20");
+  if (per_cell <= 0) per_cell = 40;
+  if (per_cell > 4096) return set_err(c, GRT_EINVAL, "per_cell must be at most 4096");
+  const double d = c->g.d, k = c->g.k[1];
+  double ymin = c->hy[0], ymax = c->hy[0];
+  for (int64_t m = 1; m < M; ++m) {
+    ymin = std::min(ymin, c->hy[m]);
+    ymax = std::max(ymax, c->hy[m]);
+  }
+  const double pad = 1e-9 * (1.0 + std::fabs(ymin) + std::fabs(ymax));
+  const double H = (ymax - ymin) + 2 * pad;
+  // square cells (a far pair of cells is then at least two sides apart while the two
+  // half-diagonals add to 1.41 sides), about per_cell inclusions each, at least 3
+  // across the period (so that a cell and its neighbours on the copies l = -1, 0, 1
+  // stay distinct); the grid is centred on the centres' y range
+  const double ncell_want = std::max(1.0, (double)M / per_cell);
+  const double s_want = std::sqrt(d * std::max(H, 1e-3 * d) / ncell_want);
+  const int nx = std::max(3, (int)std::lround(d / s_want));
+  const double sx = d / nx, sy = sx;
+  const int ny = std::max(1, (int)std::ceil(H / sx - 1e-9));
+  const double y0 = 0.5 * (ymin + ymax) - 0.5 * ny * sy;
+  // a target disk must stay inside the convergence region of its cell's local
+  // expansion: radius + half-diagonal + half-diagonal < two sides
+  const double rmax = *std::max_element(c->hr.begin(), c->hr.end());
+  if (rmax >= 0.5 * sx)
+    return set_err(c, GRT_EUNSUP, "inclusions too large for the cells: raise per_cell");
+  // order of the cell expansions: k times the cell diagonal plus 25 (the measured
+  // truncation error is then near 1e-13 relative on the preconditioned operator)
+  int p = p_cell > 0 ? p_cell : (int)std::ceil(k * std::sqrt(sx * sx + sy * sy) + 25.0);
+  if (p > FMM_PMAX)
+    return set_err(c, GRT_EUNSUP, "cell expansion order above 127: use fewer inclusions per cell");
+  if ((int64_t)nx * ny > 65536) return set_err(c, GRT_EUNSUP, "more than 65536 cells");
+  // the generators reach H_{2p}(z) at z = k 2 s (the closest far offset, two sides):
+  // keep its size, about (2p - 1)! (2 / z)^{2p} / pi, well inside FP64
+  {
+    const double z = 2.0 * k * sx, q = 2.0 * p;
+    if (std::lgamma(q) + q * std::log(2.0 / z) - std::log(M_PI) > 600.0)
+      return set_err(c, GRT_EUNSUP, "cell order too high for the cell size (generator overflow)");
+  }
+  // bin the centres (counting sort, stable)
+  const int ncell = nx * ny;
+  std::vector<int> cell(M), start(ncell + 1, 0), order(M);
+  for (int64_t m = 0; m < M; ++m) {
+    int ix = (int)std::floor((c->hx[m] + 0.5 * d) / sx);
+    int iy = (int)std::floor((c->hy[m] - y0) / sy);
+    ix = std::min(nx - 1, std::max(0, ix));
+    iy = std::min(ny - 1, std::max(0, iy));
+    cell[m] = ix * ny + iy;
+    ++start[cell[m] + 1];
+  }
+  for (int i = 0; i < ncell; ++i) start[i + 1] += start[i];
+  {
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    for (int64_t m = 0; m < M; ++m) order[fill[cell[m]]++] = (int)m;
+  }
+  std::vector<int2> groups;
+  for (int i = 0; i < ncell; ++i)
+    for (int o = 0; o < start[i + 1] - start[i]; o += 64) groups.push_back(int2{i, o});
+  const int tch = 1 + FMM_SLOTS;
+  if (c->m2l_nchunks_cap < tch) {  // room for the near slots' partials
+    if (c->d_pT) hipFree(c->d_pT);
+    c->d_pT = nullptr;
+    GRT_HIP(c, hipMalloc(&c->d_pT, sizeof(cd) * (size_t)tch * c->n_beta));
+    c->m2l_nchunks_cap = tch;
+  }
+  GRT_HIP(c, hipMalloc(&c->d_fmm_start, sizeof(int) * (ncell + 1)));
+  GRT_HIP(c, hipMalloc(&c->d_fmm_order, sizeof(int) * M));
+  GRT_HIP(c, hipMalloc(&c->d_fmm_groups, sizeof(int2) * groups.size()));
+  const size_t ne = (size_t)(2 * nx - 1) * (2 * ny - 1);
+  GRT_HIP(c, hipMalloc(&c->d_fmm_gen, sizeof(cd) * ne * (4 * p + 1)));
+  GRT_HIP(c, hipMalloc(&c->d_fmm_M, sizeof(cd) * (size_t)ncell * (2 * p + 1)));
+  GRT_HIP(c, hipMalloc(&c->d_fmm_L, sizeof(cd) * (size_t)ncell * (2 * p + 1)));
+  GRT_HIP(c, hipMemcpyAsync(c->d_fmm_start, start.data(), sizeof(int) * (ncell + 1),
+                            hipMemcpyHostToDevice, c->stream));
+  GRT_HIP(c, hipMemcpyAsync(c->d_fmm_order, order.data(), sizeof(int) * M, hipMemcpyHostToDevice,
+                            c->stream));
+  GRT_HIP(c, hipMemcpyAsync(c->d_fmm_groups, groups.data(), sizeof(int2) * groups.size(),
+                            hipMemcpyHostToDevice, c->stream));
+  fmm_gen_kernel<<<(unsigned)((ne + 63) / 64), 64, 0, c->stream>>>(
+      nx, ny, sx, sy, p, k, c->g.alpha, c->g.alpha_inv, c->d_fmm_gen);
+  GRT_HIP(c, hipGetLastError());
+  GRT_HIP(c, hipStreamSynchronize(c->stream));  // the host vectors above are temporaries
+  c->fmm_nx = nx;
+  c->fmm_ny = ny;
+  c->fmm_p = p;
+  c->fmm_sx = sx;
+  c->fmm_sy = sy;
+  c->fmm_x0 = -0.5 * d;
+  c->fmm_y0 = y0;
+  c->fmm_ngroups = (int)groups.size();
+  c->fmm_on = true;
+  return GRT_OK;
+}

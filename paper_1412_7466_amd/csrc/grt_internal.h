@@ -164,6 +164,17 @@ struct grt_ctx {
   uint64_t gen = 0;          // bumped whenever device buffers are freed or replaced (a
                              // batch built on this context checks it before solving)
   bool want_table = false;
+  // fast (cell) translation: grid, cell order, binned inclusions, generator table,
+  // cell multipoles and locals (fmm.hip)
+  bool fmm_on = false;
+  int fmm_nx = 0, fmm_ny = 0, fmm_p = 0, fmm_ngroups = 0;
+  double fmm_sx = 0, fmm_sy = 0, fmm_x0 = 0, fmm_y0 = 0;
+  int* d_fmm_start = nullptr;   // [ncell + 1] CSR offsets into d_fmm_order
+  int* d_fmm_order = nullptr;   // [M] inclusions by cell
+  int2* d_fmm_groups = nullptr; // [ngroups] (cell, offset) of each 64-target group
+  cd* d_fmm_gen = nullptr;      // [(2nx-1)(2ny-1)][4p+1] far generators by cell offset
+  cd* d_fmm_M = nullptr;        // [ncell][2p+1]
+  cd* d_fmm_L = nullptr;        // [ncell][2p+1]
   cd* d_table = nullptr;    // [M][4P+1][Mpad]
   int table_mpad = 0;
   int table_lanes = 1;      // lanes per target in the table kernel (1 or 2)
@@ -222,6 +233,12 @@ bool supported_P(int P);
 grt_status apply_K(grt_ctx* c, const cd* x, cd* y, const double* oscale = nullptr);
 grt_status apply_K_mixed(grt_ctx* c, const cd* x, cd* y, const double* oscale = nullptr);
 grt_status apply_T_only(grt_ctx* c, const cd* x, cd* y);
+// fast cell translation (fmm.hip): set up for the context's inclusions (p_cell 0:
+// automatic; per_cell 0: 40), apply into the partials d_pT[0 .. fmm_partials()), release
+grt_status fmm_setup(grt_ctx* c, int p_cell, int per_cell);
+grt_status fmm_apply(grt_ctx* c, const cd* x, hipStream_t s);
+void fmm_release(grt_ctx* c);
+int fmm_partials();
 grt_status apply_lowrank_only(grt_ctx* c, const cd* x, cd* y);
 grt_status rhs_b(grt_ctx* c, cd* b);
 grt_status incident_alpha(grt_ctx* c, cd* out);

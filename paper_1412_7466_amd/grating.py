@@ -90,6 +90,7 @@ _PROTOS = {
     "grt_table_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "grt_set_launch": (C.c_int, [_VP, C.c_int, C.c_int]),
     "grt_set_overlap": (C.c_int, [_VP, C.c_int]),
+    "grt_set_fmm": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "grt_autotune": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "grt_solve": (C.c_int, [_VP, C.POINTER(grt_solve_opts), _VP, C.POINTER(grt_solve_stats)]),
@@ -350,6 +351,15 @@ class Context:
         self._enter()
         self._check(self.lib.grt_set_overlap(self.h, int(bool(on))))
         self._leave()
+
+    def set_fmm(self, on=True, p_cell=0, per_cell=0):
+        """Fast cell translation for large M (on) or the dense one (off); returns
+        (nx, ny, p) of the cell grid."""
+        info = (C.c_int * 3)()
+        self._enter()
+        self._check(self.lib.grt_set_fmm(self.h, int(bool(on)), int(p_cell), int(per_cell), info))
+        self._leave()
+        return tuple(info[:])
 
     def autotune(self, cap=32):
         """Time the translation launch for several chunk counts (and, on the fly,
