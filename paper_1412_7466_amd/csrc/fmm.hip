@@ -35,6 +35,9 @@ constexpr int FMM_PMAX = 127;                 // cell order: 2p + 1 <= 255 threa
 constexpr int FMM_QMAX = FMM_PMAX + 40;       // |q| <= p + P in the inclusion <-> cell shifts
 constexpr int FMM_THREADS = 256;
 constexpr int FMM_SLOTS = 9;                  // near neighbour slots (dx, dy) in {-1,0,1}^2
+constexpr int FMM_CAP = 16;                   // inclusions per pass of the shift kernels
+constexpr int FMM_SPLIT = 4;                  // source-cell shares of the cell translation
+constexpr int FMM_STAGE = 4;                  // source cells staged in LDS at a time
 
 __device__ __forceinline__ cd copy_weight(cd alpha, cd alpha_inv, int l) {
   return l == 0 ? cd{1.0, 0.0} : (l > 0 ? alpha : alpha_inv);
@@ -75,100 +78,131 @@ __global__ void fmm_gen_kernel(int nx, int ny, double sx, double sy, int p, doub
   }
 }
 
-// G[QN + q] = J_q(k r) e^{iq theta}, q = -QN..QN, for v = r e^{i theta} (block-wide;
-// J by Miller on thread 0, the powers in parallel).  jn: LDS scratch of QN + 1.
-__device__ void local_row(double vx, double vy, double k, int QN, double* jn, cd* G) {
-  const double r = sqrt(vx * vx + vy * vy);
-  if (threadIdx.x == 0) bessel_jn_array(k * r, QN, jn);
-  __syncthreads();
-  const cd e1 = r > 0 ? cd{vx / r, vy / r} : cd{1.0, 0.0};
-  for (int q = threadIdx.x; q <= QN; q += blockDim.x) {
-    const cd ep = cpowi(e1, q);
-    G[QN + q] = jn[q] * ep;
-    const double s = (q & 1) ? -1.0 : 1.0;  // J_{-q} = (-1)^q J_q
-    G[QN - q] = (s * jn[q]) * conj(ep);
+// J_0..J_QN(k r) and e^{i theta} of v = C - c (P2M) or c - C (L2L) for up to FMM_CAP
+// inclusions of a cell at once, one thread each (Miller's recurrence is serial).
+__device__ __forceinline__ void shift_rows(const int* __restrict__ order, int base, int cnt,
+                                           const double* __restrict__ cx,
+                                           const double* __restrict__ cy, double Cx, double Cy,
+                                           double sgn, double k, int QN,
+                                           double (*jn)[FMM_QMAX + 1], cd* e1s) {
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    const int m = order[base + t];
+    const double vx = sgn * (Cx - cx[m]), vy = sgn * (Cy - cy[m]);
+    const double r = sqrt(vx * vx + vy * vy);
+    bessel_jn_array(k * r, QN, jn[t]);
+    e1s[t] = r > 0 ? cd{vx / r, vy / r} : cd{1.0, 0.0};
   }
-  __syncthreads();
 }
 
-// P2M: one block per cell, thread t <-> mu = t - p.
+// acc += sum_{i = 0..len-1} G_{q0 + i} c[i], G_q = J_q e^{iq theta} from the row (J_{-q} =
+// (-1)^q J_q), the phase carried along q by one product per term.
+__device__ __forceinline__ void shift_dot(cd& acc, const double* jn, cd e, int q0, int len,
+                                          const cd* c) {
+  cd ph = q0 >= 0 ? cpowi(e, q0) : cpowi(conj(e), -q0);
+  int q = q0;
+  for (int i = 0; i < len; ++i, ++q) {
+    const int aq = q < 0 ? -q : q;
+    const double jv = (q < 0 && (aq & 1)) ? -jn[aq] : jn[aq];
+    cmac(acc, jv * ph, c[i]);
+    ph = ph * e;
+  }
+}
+
+// P2M: one block per cell, thread t <-> mu = t - p, FMM_CAP inclusions per pass:
+// M_B[mu] = sum_m sum_nu G_{nu-mu}(C_B - c_m) x_m[nu].
 template <int P>
 __global__ void __launch_bounds__(FMM_THREADS) fmm_p2m_kernel(
     const int* __restrict__ start, const int* __restrict__ order, const double* __restrict__ cx,
     const double* __restrict__ cy, const cd* __restrict__ x, int ny, double x0, double y0,
     double sx, double sy, int p, double k, cd* Mc) {
   constexpr int NB = 2 * P + 1;
-  __shared__ double jn[FMM_QMAX + 1];
-  __shared__ cd G[2 * FMM_QMAX + 1];
-  __shared__ cd xs[NB];
+  __shared__ double jn[FMM_CAP][FMM_QMAX + 1];
+  __shared__ cd e1s[FMM_CAP];
+  __shared__ cd xs[FMM_CAP * NB];
   const int cell = blockIdx.x, t = threadIdx.x;
   const double Cx = x0 + (cell / ny + 0.5) * sx, Cy = y0 + (cell % ny + 0.5) * sy;
   const int QN = P + p;
   cd acc{0.0, 0.0};
-  for (int e = start[cell]; e < start[cell + 1]; ++e) {
-    const int m = order[e];
-    __syncthreads();  // the previous inclusion's G and xs are no longer read
-    if (t < NB) xs[t] = x[(size_t)m * NB + t];
-    local_row(Cx - cx[m], Cy - cy[m], k, QN, jn, G);
+  const int e0 = start[cell], e1 = start[cell + 1];
+  for (int base = e0; base < e1; base += FMM_CAP) {
+    const int cnt = min(FMM_CAP, e1 - base);
+    __syncthreads();  // the previous pass's rows are no longer read
+    shift_rows(order, base, cnt, cx, cy, Cx, Cy, 1.0, k, QN, jn, e1s);
+    for (int i = t; i < cnt * NB; i += blockDim.x)
+      xs[i] = x[(size_t)order[base + i / NB] * NB + i % NB];
+    __syncthreads();
     if (t < 2 * p + 1) {
       const int mu = t - p;
-#pragma unroll 4
-      for (int nu = -P; nu <= P; ++nu) cmac(acc, G[QN + nu - mu], xs[nu + P]);
+      for (int i = 0; i < cnt; ++i) shift_dot(acc, jn[i], e1s[i], -P - mu, NB, xs + i * NB);
     }
   }
   if (t < 2 * p + 1) Mc[(size_t)cell * (2 * p + 1) + t] = acc;
 }
 
-// M2L: one block per target cell, thread t <-> n = t - p; every source cell's
-// multipole is staged in LDS and contracted with its generator row.
+// M2L: block (target cell, share s of the source cells), thread t <-> n = t - p; the
+// share's source multipoles are staged in LDS FMM_STAGE cells at a time and
+// contracted with their generator rows; partial s of L_A is written.
 __global__ void __launch_bounds__(FMM_THREADS) fmm_m2l_kernel(const cd* __restrict__ Mc,
                                                              const cd* __restrict__ gen, int nx,
-                                                             int ny, int p, cd* L) {
-  __shared__ cd ms[2 * FMM_PMAX + 1];
-  const int A = blockIdx.x, t = threadIdx.x;
+                                                             int ny, int p, cd* Lpart) {
+  __shared__ cd ms[FMM_STAGE][2 * FMM_PMAX + 1];
+  const int A = blockIdx.x, share = blockIdx.y, t = threadIdx.x;
   const int ax = A / ny, ay = A % ny;
   const int NB = 2 * p + 1, NQ = 4 * p + 1;
+  const int ncell = nx * ny;
+  const int per = (ncell + FMM_SPLIT - 1) / FMM_SPLIT;
+  const int b0 = share * per, b1 = min(ncell, b0 + per);
   cd acc{0.0, 0.0};
-  for (int B = 0; B < nx * ny; ++B) {
-    const int e = (ax - B / ny + nx - 1) * (2 * ny - 1) + (ay - B % ny + ny - 1);
+  for (int B0 = b0; B0 < b1; B0 += FMM_STAGE) {
+    const int cnt = min(FMM_STAGE, b1 - B0);
     __syncthreads();
-    if (t < NB) ms[t] = Mc[(size_t)B * NB + t];
+    for (int i = t; i < cnt * NB; i += blockDim.x) ms[i / NB][i % NB] = Mc[(size_t)(B0 + i / NB) * NB + i % NB];
     __syncthreads();
     if (t < NB) {
-      // tau_{mu - n} at index mu - n + 2p = i - t + 2p for mu = i - p
-      const cd* g = gen + (size_t)e * NQ + 2 * p - t;
+      for (int c = 0; c < cnt; ++c) {
+        const int B = B0 + c;
+        const int e = (ax - B / ny + nx - 1) * (2 * ny - 1) + (ay - B % ny + ny - 1);
+        // tau_{mu - n} at index mu - n + 2p = i - t + 2p for mu = i - p
+        const cd* g = gen + (size_t)e * NQ + 2 * p - t;
 #pragma unroll 4
-      for (int i = 0; i < NB; ++i) cmac(acc, g[i], ms[i]);
+        for (int i = 0; i < NB; ++i) cmac(acc, g[i], ms[c][i]);
+      }
     }
   }
-  if (t < NB) L[(size_t)A * NB + t] = acc;
+  if (t < NB) Lpart[((size_t)share * ncell + A) * NB + t] = acc;
 }
 
-// L2L: one block per cell; for each inclusion j of the cell, thread t <-> n = t - P:
-// out[j][n] = sum_q G_{q-n}(c_j - C_A) L_A[q].
+// L2L: one block per cell, FMM_CAP inclusions per pass, one thread per (inclusion, n):
+// out[j][n] = sum_q G_{q-n}(c_j - C_A) L_A[q], L_A the sum of the FMM_SPLIT partials.
 template <int P>
 __global__ void __launch_bounds__(FMM_THREADS) fmm_l2l_kernel(
     const int* __restrict__ start, const int* __restrict__ order, const double* __restrict__ cx,
-    const double* __restrict__ cy, const cd* __restrict__ L, int ny, double x0, double y0,
-    double sx, double sy, int p, double k, cd* out) {
+    const double* __restrict__ cy, const cd* __restrict__ Lpart, int ncell, int ny, double x0,
+    double y0, double sx, double sy, int p, double k, cd* out) {
   constexpr int NB = 2 * P + 1;
-  __shared__ double jn[FMM_QMAX + 1];
-  __shared__ cd G[2 * FMM_QMAX + 1];
+  __shared__ double jn[FMM_CAP][FMM_QMAX + 1];
+  __shared__ cd e1s[FMM_CAP];
   __shared__ cd ls[2 * FMM_PMAX + 1];
   const int cell = blockIdx.x, t = threadIdx.x;
   const double Cx = x0 + (cell / ny + 0.5) * sx, Cy = y0 + (cell % ny + 0.5) * sy;
-  const int QN = P + p;
-  for (int i = t; i < 2 * p + 1; i += blockDim.x) ls[i] = L[(size_t)cell * (2 * p + 1) + i];
-  for (int e = start[cell]; e < start[cell + 1]; ++e) {
-    const int j = order[e];
+  const int QN = P + p, NL = 2 * p + 1;
+  for (int i = t; i < NL; i += blockDim.x) {
+    cd v{0.0, 0.0};
+    for (int s = 0; s < FMM_SPLIT; ++s) v += Lpart[((size_t)s * ncell + cell) * NL + i];
+    ls[i] = v;
+  }
+  const int e0 = start[cell], e1 = start[cell + 1];
+  for (int base = e0; base < e1; base += FMM_CAP) {
+    const int cnt = min(FMM_CAP, e1 - base);
+    __syncthreads();  // ls written / the previous pass's rows no longer read
+    shift_rows(order, base, cnt, cx, cy, Cx, Cy, -1.0, k, QN, jn, e1s);
     __syncthreads();
-    local_row(cx[j] - Cx, cy[j] - Cy, k, QN, jn, G);
-    if (t < NB) {
-      const int n = t - P;
+    for (int it = t; it < cnt * NB; it += blockDim.x) {
+      const int i = it / NB, n = it % NB - P;
       cd acc{0.0, 0.0};
-#pragma unroll 4
-      for (int q = -p; q <= p; ++q) cmac(acc, G[QN + q - n], ls[q + p]);
-      out[(size_t)j * NB + t] = acc;
+      shift_dot(acc, jn[i], e1s[i], -p - n, NL, ls);
+      out[(size_t)order[base + i] * NB + n + P] = acc;
     }
   }
 }
@@ -233,12 +267,12 @@ void launch_fmm(grt_ctx* c, const cd* x, hipStream_t s) {
                                                   c->d_cy, x, c->fmm_ny, c->fmm_x0, c->fmm_y0,
                                                   c->fmm_sx, c->fmm_sy, c->fmm_p, c->g.k[1],
                                                   c->d_fmm_M);
-  fmm_m2l_kernel<<<ncell, FMM_THREADS, 0, s>>>(c->d_fmm_M, c->d_fmm_gen, c->fmm_nx, c->fmm_ny,
-                                              c->fmm_p, c->d_fmm_L);
+  fmm_m2l_kernel<<<dim3(ncell, FMM_SPLIT), FMM_THREADS, 0, s>>>(
+      c->d_fmm_M, c->d_fmm_gen, c->fmm_nx, c->fmm_ny, c->fmm_p, c->d_fmm_L);
   fmm_l2l_kernel<P><<<ncell, FMM_THREADS, 0, s>>>(c->d_fmm_start, c->d_fmm_order, c->d_cx,
-                                                  c->d_cy, c->d_fmm_L, c->fmm_ny, c->fmm_x0,
-                                                  c->fmm_y0, c->fmm_sx, c->fmm_sy, c->fmm_p,
-                                                  c->g.k[1], c->d_pT);
+                                                  c->d_cy, c->d_fmm_L, ncell, c->fmm_ny,
+                                                  c->fmm_x0, c->fmm_y0, c->fmm_sx, c->fmm_sy,
+                                                  c->fmm_p, c->g.k[1], c->d_pT);
   dim3 grid((unsigned)c->fmm_ngroups, FMM_SLOTS);
   fmm_near_kernel<P><<<grid, 64, 0, s>>>(c->d_fmm_groups, c->d_fmm_start, c->d_fmm_order,
                                          c->d_cx, c->d_cy, x, c->fmm_nx, c->fmm_ny, c->g.d,
@@ -356,7 +390,7 @@ grt_status fmm_setup(grt_ctx* c, int p_cell, int per_cell) {
   const size_t ne = (size_t)(2 * nx - 1) * (2 * ny - 1);
   GRT_HIP(c, hipMalloc(&c->d_fmm_gen, sizeof(cd) * ne * (4 * p + 1)));
   GRT_HIP(c, hipMalloc(&c->d_fmm_M, sizeof(cd) * (size_t)ncell * (2 * p + 1)));
-  GRT_HIP(c, hipMalloc(&c->d_fmm_L, sizeof(cd) * (size_t)ncell * (2 * p + 1)));
+  GRT_HIP(c, hipMalloc(&c->d_fmm_L, sizeof(cd) * (size_t)FMM_SPLIT * ncell * (2 * p + 1)));
   GRT_HIP(c, hipMemcpyAsync(c->d_fmm_start, start.data(), sizeof(int) * (ncell + 1),
                             hipMemcpyHostToDevice, c->stream));
   GRT_HIP(c, hipMemcpyAsync(c->d_fmm_order, order.data(), sizeof(int) * M, hipMemcpyHostToDevice,

@@ -174,7 +174,7 @@ struct grt_ctx {
   int2* d_fmm_groups = nullptr; // [ngroups] (cell, offset) of each 64-target group
   cd* d_fmm_gen = nullptr;      // [(2nx-1)(2ny-1)][4p+1] far generators by cell offset
   cd* d_fmm_M = nullptr;        // [ncell][2p+1]
-  cd* d_fmm_L = nullptr;        // [ncell][2p+1]
+  cd* d_fmm_L = nullptr;        // [4 source shares][ncell][2p+1] partial locals
   cd* d_table = nullptr;    // [M][4P+1][Mpad]
   int table_mpad = 0;
   int table_lanes = 1;      // lanes per target in the table kernel (1 or 2)
