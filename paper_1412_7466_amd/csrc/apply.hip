@@ -111,17 +111,17 @@ __global__ void __launch_bounds__(64 * CX_WAVES) cx_kernel(DevGeom g, const doub
   cx_block<P>(g, cx, cy, x, partial, chunk, htab, blockIdx.x, blockIdx.y);
 }
 
-__global__ void __launch_bounds__(256) cx_reduce_kernel(DevGeom g, const cd* partial, int nchunks,
-                                                        cd* gv) {
-  cx_reduce_block(g, partial, nchunks, gv, blockIdx.x);
-}
-
 template <int P>
 __global__ void __launch_bounds__(64 * BX_WAVES) bx_kernel(DevGeom g, const double* __restrict__ cx,
                                                 const double* __restrict__ cy,
                                                 const cd* __restrict__ w, cd* partial, int chunk,
                                                 const double* __restrict__ htab) {
   bx_block<P>(g, cx, cy, w, partial, chunk, htab, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) cx_reduce_rows_kernel(DevGeom g, const cd* partial,
+                                                             int nchunks, cd* gv) {
+  cx_reduce_rows(g, partial, nchunks, gv, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) l2l_kernel(int M, int P, int Q2, const cd* __restrict__ E,
@@ -466,7 +466,7 @@ static grt_status lowrank_tail(grt_ctx* c, const cd* gvec, hipStream_t s = nullp
   {
     const int ntb = l2l_targets_per_block(c->P, c->g.Q[1]);
     const size_t sh = l2l_lds_bytes(c->P, c->g.Q[1], ntb);
-    l2l_kernel<<<(unsigned)((c->M + ntb - 1) / ntb), 256, sh, s>>>(
+    l2l_kernel<<<(unsigned)((c->M + ntb - 1) / ntb), 64, sh, s>>>(
         (int)c->M, c->P, c->g.Q[1], c->d_l2l, c->d_wvec + c->g.col_off[CB_A2], c->d_pL, ntb);
   }
   GRT_HIP(c, hipGetLastError());
@@ -477,7 +477,7 @@ static grt_status cx_apply(grt_ctx* c, const cd* x, hipStream_t s = nullptr) {
   if (!s) s = c->stream;
   const int nt = 2 * c->g.N + c->g.Nw[1];
   GRT_P_DISPATCH(launch_cx, c->P, c, x, s);
-  cx_reduce_kernel<<<(nt + 3) / 4, 256, 0, s>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
+  cx_reduce_rows_kernel<<<(nt + 255) / 256, 256, 0, s>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
   GRT_HIP(c, hipGetLastError());
   return GRT_OK;
 }
@@ -789,7 +789,8 @@ grt_status autotune_coupling(grt_ctx* c) {
       c->c_nchunks = nc;
       const double ms = time_it([&]() -> grt_status {
         GRT_P_DISPATCH(launch_cx, c->P, c, c->d_xtmp, s);
-        cx_reduce_kernel<<<(nt + 3) / 4, 256, 0, s>>>(c->g, c->d_pC, c->c_nchunks, c->d_gvec);
+        cx_reduce_rows_kernel<<<(nt + 255) / 256, 256, 0, s>>>(c->g, c->d_pC, c->c_nchunks,
+                                                               c->d_gvec);
         return GRT_OK;
       });
       if (ms < 0) break;

@@ -770,6 +770,39 @@ __device__ __forceinline__ void cx_block(const DevGeom& g, const double* __restr
   o[1] = der;
 }
 
+// Row placement of target t's value and derivative in g: Gamma_1 (the row is
+// u_1 - u_2 and the inclusions live in layer 2: minus), Gamma_2, middle wall.
+__device__ __forceinline__ void cx_store(const DevGeom& g, int t, cd v, cd dv, cd* gv) {
+  const int N = g.N;
+  if (t < N) {
+    gv[g.row_off[RB_G1V] + t] = -v;
+    gv[g.row_off[RB_G1N] + t] = -dv;
+  } else if (t < 2 * N) {
+    gv[g.row_off[RB_G2V] + t - N] = v;
+    gv[g.row_off[RB_G2N] + t - N] = dv;
+  } else {
+    gv[g.row_off[RB_W2V] + t - 2 * N] = v;
+    gv[g.row_off[RB_W2D] + t - 2 * N] = dv;
+  }
+}
+
+// The same sum with one thread per target, the chunks added in order: consecutive
+// threads read consecutive partials of a chunk (coalesced).
+__device__ inline void cx_reduce_rows(const DevGeom& g, const cd* partial, int nchunks, cd* gv,
+                                      int t) {
+  const int nt = 2 * g.N + g.Nw[1];
+  if (t >= nt) return;
+  cd v{0, 0}, dv{0, 0};
+  // unrolled: several chunks' loads in flight, added in chunk order
+#pragma unroll 8
+  for (int c = 0; c < nchunks; ++c) {
+    const cd* p = partial + ((size_t)c * nt + t) * 2;
+    v += p[0];
+    dv += p[1];
+  }
+  cx_store(g, t, v, dv, gv);
+}
+
 // g (rows Gamma_1 v/n, Gamma_2 v/n, wall-2 v/d) from the chunk partials: one
 // wavefront per target, lanes over chunks, fixed-order tree sum.
 __device__ inline void cx_reduce_block(const DevGeom& g, const cd* partial, int nchunks,
@@ -791,18 +824,7 @@ __device__ inline void cx_reduce_block(const DevGeom& g, const cd* partial, int 
     di += __shfl_xor(di, off, 64);
   }
   if (lane != 0) return;
-  cd v{vr, vi}, dv{dr, di};
-  const int N = g.N;
-  if (t < N) {  // Gamma_1: row is u_1 - u_2, the inclusions live in layer 2
-    gv[g.row_off[RB_G1V] + t] = -v;
-    gv[g.row_off[RB_G1N] + t] = -dv;
-  } else if (t < 2 * N) {
-    gv[g.row_off[RB_G2V] + t - N] = v;
-    gv[g.row_off[RB_G2N] + t - N] = dv;
-  } else {
-    gv[g.row_off[RB_W2V] + t - 2 * N] = v;
-    gv[g.row_off[RB_W2D] + t - 2 * N] = dv;
-  }
+  cx_store(g, t, cd{vr, vi}, cd{dr, di}, gv);
 }
 
 // Incoming coefficients at inclusion j from the interface densities (P2L, Graf's
@@ -946,7 +968,7 @@ __device__ __forceinline__ void bx_block(const DevGeom& g, const double* __restr
 // E_j stored at offset L = Q2 + P.  a2 and the block's E rows are staged in LDS
 // (extern shared: 2 Q2 + 1 + ntb (2L + 1) complex, see l2l_targets_per_block); one
 // thread per (target, n), consecutive n reading consecutive LDS entries.
-constexpr int L2L_TARGETS = 8;
+constexpr int L2L_TARGETS = 2;   // few targets per block: many blocks for M ~ 1000
 constexpr size_t L2L_LDS_BUDGET = 60 * 1024;
 // targets per block so that the staged rows fit the LDS budget
 __host__ __device__ inline int l2l_targets_per_block(int P, int Q2) {
