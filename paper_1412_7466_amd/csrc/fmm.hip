@@ -207,10 +207,64 @@ __global__ void __launch_bounds__(FMM_THREADS) fmm_l2l_kernel(
   }
 }
 
-// Near part: grid (target groups, 9 neighbour slots), one wave per block, lane =
-// target.  Slot s = (dx + 1) 3 + (dy + 1) takes the source cell at (ax + dx, ay + dy)
-// (x wrapping onto the copies l = -1, +1); the pair (j, j, 0) is excluded.  Writes
-// partial s + 1 of every target of the group (zero for a slot outside the grid).
+// One copy of one source: acc[n] += w sum_nu F_{nu-n}(v) b[nu], v = target - source,
+// F_q(v) = H_q(k|v|) e^{iq arg v} (H_0, H_1 from the table, the upward recurrence and
+// powers of e^{i arg v}), in the same order of operations as the dense kernels' pair
+// routine restricted to one copy.
+template <int P>
+__device__ __forceinline__ void copy_accumulate(cd* acc, const cd* b, double vx, double vy,
+                                                double k, cd w, const double* tab) {
+  constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
+  const double r = sqrt(vx * vx + vy * vy);
+  const double z = k * r;
+  const double ir = 1.0 / r;
+  const cd cc{vx * ir, vy * ir};
+  cd cq = cc;
+  const double rz2 = 2.0 / z;
+  cd h0, h1;
+  hankel01_tab(z, tab, h0, h1);
+  cd hp = w * h0, hc = w * h1;
+#pragma unroll
+  for (int n = 0; n < 2 * P + 1; ++n) cmac(acc[n], hp, b[n]);
+#pragma unroll
+  for (int qb = 0; qb < NQB; ++qb) {
+    cd tp[M2L_QB], tm[M2L_QB];
+#pragma unroll
+    for (int u = 0; u < M2L_QB; ++u) {
+      const int q = 1 + qb * M2L_QB + u;
+      cd sp{0.0, 0.0}, sm{0.0, 0.0};
+      if (q <= 2 * P) {
+        sp.r = fma(hc.r, cq.r, sp.r);
+        sp.r = fma(-hc.i, cq.i, sp.r);
+        sp.i = fma(hc.r, cq.i, sp.i);
+        sp.i = fma(hc.i, cq.r, sp.i);
+        sm.r = fma(hc.r, cq.r, sm.r);
+        sm.r = fma(hc.i, cq.i, sm.r);
+        sm.i = fma(hc.i, cq.r, sm.i);
+        sm.i = fma(-hc.r, cq.i, sm.i);
+        if (q & 1) sm = -sm;
+        if (q < 2 * P) {
+          const cd hn = (q * rz2) * hc - hp;
+          hp = hc;
+          hc = hn;
+          cq = cq * cc;
+        }
+      }
+      tp[u] = sp;
+      tm[u] = sm;
+    }
+    contract_block<P, cd, const cd*>(acc, b, qb, tp, tm);
+  }
+}
+
+// Near part: one wave per (target cell, row of neighbour cells dy, group of up to 21
+// of the cell's targets); lane = (target, column dx) for the 63 lanes, so the three
+// source cells of the row are taken side by side.  Slot s = (dx + 1) 3 + (dy + 1) takes
+// the source cell at (ax + dx, ay + dy) (x wrapping onto the copies l = -1, +1); the
+// pair (j, j, 0) is excluded.  Each lane loops over its own source cell (the source
+// coefficients are read from memory, lane by lane) and writes partial s + 1 of its
+// target (zero for a slot outside the grid).
+constexpr int FMM_NEAR_T = 21;  // targets per wave: 3 columns x 21 = 63 lanes
 template <int P>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 8))) fmm_near_kernel(
     const int2* __restrict__ groups, const int* __restrict__ start, const int* __restrict__ order,
@@ -219,17 +273,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 8)))
     cd* part, int64_t n_beta) {
   constexpr int NB = 2 * P + 1;
   __shared__ double stab[HTAB_SIZE];
-  __shared__ cd xs[NB];
   for (int i = threadIdx.x; i < HTAB_SIZE; i += blockDim.x) stab[i] = htab[i];
   __syncthreads();
-  const int2 gr = groups[blockIdx.x];  // (cell, first index into the cell's list)
-  const int A = gr.x;
-  const int e0 = start[A] + gr.y;
-  const int e = e0 + (int)threadIdx.x;
-  const bool live = e < start[A + 1];
-  const int j = live ? order[e] : 0;
-  const int slot = blockIdx.y;
-  const int sdx = slot / 3 - 1, sdy = slot % 3 - 1;
+  const int2 gr = groups[blockIdx.x];  // (cell, offset into its list * 4 + row)
+  const int A = gr.x, row = gr.y & 3, off = gr.y >> 2;
+  const int ti = threadIdx.x / 3, col = threadIdx.x % 3;
+  const int e = start[A] + off + ti;
+  const bool live = threadIdx.x < 3 * FMM_NEAR_T && ti < FMM_NEAR_T && e < start[A + 1];
+  if (!live) return;  // no barrier below
+  const int j = order[e];
+  const int slot = col * 3 + row;
+  const int sdx = col - 1, sdy = row - 1;
   int bx = A / ny + sdx, l = 0;
   if (bx < 0) { bx += nx; l = -1; }
   if (bx >= nx) { bx -= nx; l = 1; }
@@ -239,25 +293,25 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 8)))
   for (int n = 0; n < NB; ++n) acc[n] = cd{0.0, 0.0};
   if (by >= 0 && by < ny) {
     const int B = bx * ny + by;
-    // the dense kernels' pair routine with the one copy l weighted (the other two get
-    // weight zero: a little more generator work, the same register layout)
-    const cd wl[3] = {cd{0.0, 0.0}, copy_weight(alpha, alpha_inv, l), cd{0.0, 0.0}};
-    const double tx = live ? cx[j] : 0.0, ty = live ? cy[j] : 0.0;
+    const cd w = copy_weight(alpha, alpha_inv, l);
+    // at P = 20 the one-copy routine's accumulators end up in scratch memory: use the
+    // dense kernels' three-copy routine with the other two copies weighted zero there
+    const cd wl[3] = {cd{0.0, 0.0}, w, cd{0.0, 0.0}};
+    const double tx = cx[j], ty = cy[j];
     for (int f = start[B]; f < start[B + 1]; ++f) {
       const int m = order[f];
-      __syncthreads();  // the previous source's coefficients are no longer read
-      if (threadIdx.x < NB) xs[threadIdx.x] = x[(size_t)m * NB + threadIdx.x];
-      __syncthreads();
-      if (!live || (m == j && l == 0)) continue;
-      pair_accumulate<P, cd>(acc, (const cd*)xs, tx - (cx[m] + l * d), ty - cy[m], k, d, wl, false,
-                             false, (const double*)stab, 0.0);
+      if (m == j && l == 0) continue;
+      const cd* b = x + (size_t)m * NB;
+      if constexpr (P > 15)
+        pair_accumulate<P, cd>(acc, b, tx - (cx[m] + l * d), ty - cy[m], k, d, wl, false, false,
+                               (const double*)stab, 0.0);
+      else
+        copy_accumulate<P>(acc, b, tx - (cx[m] + l * d), ty - cy[m], k, w, (const double*)stab);
     }
   }
-  if (live) {
-    cd* o = part + (size_t)(slot + 1) * n_beta + (size_t)j * NB;
+  cd* o = part + (size_t)(slot + 1) * n_beta + (size_t)j * NB;
 #pragma unroll
-    for (int n = 0; n < NB; ++n) o[n] = acc[n];
-  }
+  for (int n = 0; n < NB; ++n) o[n] = acc[n];
 }
 
 template <int P>
@@ -273,8 +327,7 @@ void launch_fmm(grt_ctx* c, const cd* x, hipStream_t s) {
                                                   c->d_cy, c->d_fmm_L, ncell, c->fmm_ny,
                                                   c->fmm_x0, c->fmm_y0, c->fmm_sx, c->fmm_sy,
                                                   c->fmm_p, c->g.k[1], c->d_pT);
-  dim3 grid((unsigned)c->fmm_ngroups, FMM_SLOTS);
-  fmm_near_kernel<P><<<grid, 64, 0, s>>>(c->d_fmm_groups, c->d_fmm_start, c->d_fmm_order,
+  fmm_near_kernel<P><<<(unsigned)c->fmm_ngroups, 64, 0, s>>>(c->d_fmm_groups, c->d_fmm_start, c->d_fmm_order,
                                          c->d_cx, c->d_cy, x, c->fmm_nx, c->fmm_ny, c->g.d,
                                          c->g.k[1], c->g.alpha, c->g.alpha_inv, c->d_htab,
                                          c->d_pT, c->n_beta);
@@ -374,9 +427,11 @@ grt_status fmm_setup(grt_ctx* c, int p_cell, int per_cell) {
     std::vector<int> fill(start.begin(), start.end() - 1);
     for (int64_t m = 0; m < M; ++m) order[fill[cell[m]]++] = (int)m;
   }
+  // near groups: (cell, offset * 4 + row of neighbour cells), FMM_NEAR_T targets each
   std::vector<int2> groups;
   for (int i = 0; i < ncell; ++i)
-    for (int o = 0; o < start[i + 1] - start[i]; o += 64) groups.push_back(int2{i, o});
+    for (int o = 0; o < start[i + 1] - start[i]; o += FMM_NEAR_T)
+      for (int row = 0; row < 3; ++row) groups.push_back(int2{i, o * 4 + row});
   const int tch = 1 + FMM_SLOTS;
   if (c->m2l_nchunks_cap < tch) {  // room for the near slots' partials
     if (c->d_pT) hipFree(c->d_pT);
