@@ -115,3 +115,34 @@ def test_fmm_refused_where_unsupported(torch_cuda):
         c2.set_fmm(True)
     assert ei.value.status == GRT_EUNSUP
     c2.close()
+
+
+@pytest.mark.parametrize("case", ["star", "curved", "te", "lossy"])
+def test_fmm_with_other_features(torch_cuda, case):
+    """The cell translation only replaces T: with non-circular inclusions, curved
+    interfaces, TE or absorbing disks the K apply and the solution stay those of the
+    dense translation (1e-12 per order on K, 1e-10 on the solution)."""
+    from paper_1412_7466_amd.grating import Context
+    from parity import dscale, probe
+    torch = torch_cuda
+    pb = {"star": lambda: inputs.star(60, 8, seed=31),
+          "curved": lambda: inputs.curved(60, 8, seed=32),
+          "te": lambda: inputs.small(60, 8, seed=33),
+          "lossy": lambda: inputs.lossy(60, 8, seed=34)}[case]()
+    if case == "te":
+        pb.polarization = "TE"
+    ctx = Context(0)
+    ctx.set_problem(pb)
+    ctx.build()
+    xh = probe(pb, 5)
+    xd = torch.tensor(xh, dtype=torch.complex128, device="cuda:0")
+    D = dscale(pb)
+    y0 = ctx.apply(xd).cpu().numpy()
+    b0, s0 = ctx.solve(tol=1e-12, restart=150)
+    info = ctx.set_fmm(True, per_cell=8)
+    say(f"[gpu] fmm {case}: cells {info}")
+    check_orders(ctx.apply(xd).cpu().numpy(), y0, D, pb.P, 1e-12, tag=f"fmm {case} K")
+    b1, s1 = ctx.solve(tol=1e-12, restart=150)
+    check_orders(b1.cpu().numpy(), b0.cpu().numpy(), D, pb.P, 1e-10, 1e-11,
+                 tag=f"fmm {case} beta")
+    ctx.close()
