@@ -19,8 +19,16 @@ import scipy.special as sp
 
 
 def sqrt_branch(v):
-    """sqrt(v) for real v, non-negative real part or positive imaginary part."""
-    v = np.asarray(v, dtype=float)
+    """sqrt(v) for real v, non-negative real part or positive imaginary part.  For
+    v with positive imaginary part (an absorbing layer: k^2 - kappa_n^2 with Im k > 0)
+    the principal root, whose real and imaginary parts are both positive: each
+    Rayleigh-Bloch wave then carries energy away from the layers and decays."""
+    v = np.asarray(v)
+    if np.iscomplexobj(v) and np.any(v.imag != 0):
+        if np.any(v.imag < 0):
+            raise ValueError("the layer index must have a non-negative imaginary part")
+        return np.sqrt(v.astype(complex))
+    v = np.asarray(v.real if np.iscomplexobj(v) else v, dtype=float)
     out = np.where(v >= 0, np.sqrt(np.abs(v)) + 0j, 1j * np.sqrt(np.abs(v)))
     return out
 
@@ -58,6 +66,16 @@ class Geometry:
         dd = pb.disc
         self.d, self.h = float(pb.d), float(pb.h)
         self.k1, self.k2, self.k3 = (pb.omega * n for n in pb.n_layer)
+        # absorbing substrate: k_3 = omega (n_3 + i n3_im), Im k_3 > 0 (sec. 7 names
+        # complex permittivities as an extension); TM only
+        n3_im = float(getattr(pb, "n3_im", 0.0) or 0.0)
+        self.lossy3 = n3_im != 0.0
+        if self.lossy3:
+            if n3_im < 0:
+                raise ValueError("n3_im must be non-negative")
+            if getattr(pb, "polarization", "TM") == "TE":
+                raise NotImplementedError("an absorbing substrate is taken for TM only")
+            self.k3 = pb.omega * (pb.n_layer[2] + 1j * n3_im)
         self.kl = (self.k1, self.k2, self.k3)
         self.P = int(pb.P)
         self.M = int(len(pb.x))

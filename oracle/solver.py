@@ -209,14 +209,26 @@ class Reduced:
         c = al[G.col["c"]]
         d = al[G.col["d"]]
         prop1 = (np.abs(G.k1n.imag) == 0) & (G.k1n.real > 0)
-        prop3 = (np.abs(G.k3n.imag) == 0) & (G.k3n.real > 0)
         inc = G.k1 * G.cosphi
-        # TE: the energy flux of a wave is (k_y / eps) |amplitude|^2
-        t3 = G.eps[0] / G.eps[2] if G.te else 1.0
         Rn = np.where(prop1, G.k1n.real * np.abs(c) ** 2 / inc, 0.0)
-        Tn = np.where(prop3, t3 * G.k3n.real * np.abs(d) ** 2 / inc, 0.0)
         ab = self.absorbed(beta) if G.M else 0.0
-        flux = abs(Rn.sum() + Tn.sum() + ab - 1.0)
+        if G.lossy3:
+            # absorbing substrate: order n of the Rayleigh-Bloch expansion below
+            # Gamma_d carries the downward flux Re(k_3n) |d_n|^2 across Gamma_d (no
+            # cross terms: the kappa_n differ by multiples of 2 pi / d).  The layer
+            # also absorbs between Gamma_2 and Gamma_d, including the evanescent near
+            # field of inclusions close to the interface, which the amplitudes at
+            # Gamma_d no longer resolve; so R + T + A < 1 and flux_err is NaN.
+            # "Propagating" marks the orders with Re(k_3^2 - kappa_n^2) > 0.
+            prop3 = (G.k3 ** 2 - G.kapn ** 2).real > 0
+            Tn = G.k3n.real * np.abs(d) ** 2 / inc
+            flux = float("nan")
+        else:
+            prop3 = (np.abs(G.k3n.imag) == 0) & (G.k3n.real > 0)
+            # TE: the energy flux of a wave is (k_y / eps) |amplitude|^2
+            t3 = G.eps[0] / G.eps[2] if G.te else 1.0
+            Tn = np.where(prop3, t3 * G.k3n.real * np.abs(d) ** 2 / inc, 0.0)
+            flux = abs(Rn.sum() + Tn.sum() + ab - 1.0)
         return dict(orders=G.rb, c=c, d=d, R=Rn, T=Tn, prop1=prop1, prop3=prop3,
                     flux_err=flux, absorbed=ab)
 

@@ -76,6 +76,9 @@ class Problem:
     # (n_incl + i n_incl_im, n_incl_im >= 0; the wave e^{i k x} with k = omega n decays);
     # None: lossless
     n_incl_im: Optional[np.ndarray] = None
+    # absorbing substrate: imaginary part of the bottom layer's index (n_3 + i n3_im,
+    # n3_im >= 0); 0: lossless
+    n3_im: float = 0.0
 
     @property
     def M(self) -> int:
@@ -98,6 +101,8 @@ class Problem:
             hsh.update(np.int64(self.shape_nodes).tobytes())
         if self.polarization != "TM":
             hsh.update(self.polarization.encode())
+        if self.n3_im:
+            hsh.update(np.float64(self.n3_im).tobytes())
         if self.n_incl_im is not None:
             hsh.update(b"n_incl_im")
             hsh.update(np.ascontiguousarray(self.n_incl_im, dtype=np.float64).tobytes())
@@ -394,6 +399,19 @@ def lossy(M, P, omega=10.0, seed=7, phi=-math.pi / 5, loss=(0.05, 0.5), **kw) ->
     pb.name = f"lossy_M{M}_P{P}"
     rng = np.random.Generator(np.random.PCG64(seed + 6_000_000))
     pb.n_incl_im = rng.uniform(loss[0], loss[1], size=M)
+    return pb
+
+
+def lossy_substrate(M, P, omega=10.0, seed=7, phi=-math.pi / 5, n3_im=0.05,
+                    curved_iface=False, **kw) -> Problem:
+    """small()'s geometry (or curved()'s with curved_iface) over an absorbing
+    substrate: the bottom layer's index n_3 + i n3_im."""
+    if curved_iface:
+        pb = curved(M, P, omega=omega, seed=seed, phi=phi, **kw)
+    else:
+        pb = small(M, P, omega=omega, seed=seed, phi=phi, **kw)
+    pb.name = f"substrate_M{M}_P{P}" + ("_curved" if curved_iface else "")
+    pb.n3_im = float(n3_im)
     return pb
 
 
