@@ -79,6 +79,18 @@ typedef struct {
   double pinv_eps;
   int n_fourier;        /* 0: flat interfaces                                    */
   const double* iface;  /* [2][2][n_fourier] Fourier coefficients (see above)    */
+  /* Absorbing substrate (sec. 7 names complex permittivities as an extension): the
+   * bottom layer's index is n_layer[2] + i n3_im, 0 <= n3_im <= 0.1 n_layer[2]
+   * (GRT_EINVAL below 0, GRT_EUNSUP above the bound, where the complex-argument
+   * Hankel and Bessel routines of the layer matrix are not validated; GRT_EUNSUP
+   * also when |k_3| times the reach of the bottom layer's J expansion exceeds 60).
+   * The layer matrix then takes H_0, H_1 and J_n at complex arguments and the
+   * Rayleigh-Bloch wavenumbers k_3n with positive real and imaginary parts; the
+   * translation, C and B_phys (middle layer only) are unchanged.  TM only; no field
+   * evaluation (GRT_EUNSUP).  grt_bragg then reports T_n as the power order n carries
+   * across Gamma_d and flux_err as NaN: the substrate also absorbs between Gamma_2
+   * and Gamma_d.  0: lossless. */
+  double n3_im;
 } grt_layers;
 
 /* M inclusions (paper sec. 4, 5): centres (x, y), radius and refractive index.
@@ -362,7 +374,9 @@ grt_status grt_solve(grt_ctx* ctx, const grt_solve_opts* opts, void* beta_dev,
  * the flux of sum_n (a_n J_n + b_n H_n) e^{in theta} through a circle with a_n = b_n / s_n,
  * over the incident flux d k_1 cos(phi); TE weights each flux by 1/eps of its medium)
  * and the energy-balance error |sum R + sum T + absorbed - 1| (the flux error of
- * sec. 6 for lossless media).  GRT_EINVAL for rhs out of range. */
+ * sec. 6 for lossless media).  Over an absorbing substrate (grt_layers.n3_im > 0)
+ * T[i] is Re(k_3n) |d_n|^2 over the incident flux for every order (the power order
+ * n carries across Gamma_d) and flux_err is NaN.  GRT_EINVAL for rhs out of range. */
 grt_status grt_bragg(grt_ctx* ctx, int64_t rhs, const void* beta_dev, int64_t cap, int* orders,
                      double* c, double* d, double* R, double* T, double* flux_err,
                      double* absorbed);

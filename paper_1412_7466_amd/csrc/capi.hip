@@ -200,6 +200,26 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
     return set_err(c, GRT_EINVAL, "polarization must be GRT_TM or GRT_TE");
   if (wave->polarization == GRT_TE && inc->shape && inc->M > 0)
     return set_err(c, GRT_EUNSUP, "non-circular inclusions are TM only");
+  if (!std::isfinite(L.n3_im) || L.n3_im < 0)
+    return set_err(c, GRT_EINVAL, "n3_im must be finite and >= 0");
+  if (L.n3_im > 0) {
+    if (L.n3_im > 0.1 * L.n_layer[2])
+      return set_err(c, GRT_EUNSUP, "an absorbing substrate is taken for n3_im <= 0.1 n_3");
+    if (wave->polarization == GRT_TE)
+      return set_err(c, GRT_EUNSUP, "an absorbing substrate is taken for TM only");
+    // the bottom layer's J expansion about (0, -(h + y0) / 2) is evaluated up to the
+    // corners of Gamma_d and the highest point of Gamma_2
+    double hi = -L.h;
+    for (int i = 0; F > 0 && i < 4096; ++i)
+      hi = std::max(hi, iface_height(iface.data(), F, 1, L.h, L.d,
+                                     -0.5 * L.d + (i + 0.5) * L.d / 4096, 0));
+    const double reach = std::hypot(0.5 * L.d, std::max(hi + 0.5 * (L.h + L.y0),
+                                                        0.5 * (L.y0 - L.h)));
+    const double k3 = wave->omega * std::hypot(L.n_layer[2], L.n3_im);
+    if (k3 * reach > 60.0)
+      return set_err(c, GRT_EUNSUP, "absorbing substrate: |k_3| times the reach of its J "
+                                    "expansion above 60");
+  }
   if (!supported_P(wave->P)) return set_err(c, GRT_EUNSUP, "multipole order P not compiled in");
   const int64_t M = inc->M;
   if (M < 0 || M > 10000000) return set_err(c, GRT_EINVAL, "bad M");
@@ -332,6 +352,7 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
   g.hs = L.d / L.N;
   for (int l = 0; l < 3; ++l) {
     g.k[l] = wave->omega * L.n_layer[l];
+    g.k_im[l] = l == 2 ? wave->omega * L.n3_im : 0.0;
     g.Nw[l] = L.Nw[l];
     g.Q[l] = L.Q[l];
   }
@@ -829,18 +850,29 @@ __global__ void bragg_finish_kernel(DevGeom g, double k1cos, const cd* cdv, doub
                                     double* flux) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0.0;
+  const bool lossy3 = g.k_im[2] != 0.0;
   for (int i = 0; i < g.Nrb; ++i) {
     double kapn = g.kappa + 2.0 * M_PI * (g.n_rb_lo + i) / g.d;
     double v1 = g.k[0] * g.k[0] - kapn * kapn;
     double v3 = g.k[2] * g.k[2] - kapn * kapn;
     double r = v1 > 0 ? sqrt(v1) * cabs2(cdv[i]) / k1cos : 0.0;
-    // TE: the flux of a wave is (k_y / eps) |amplitude|^2
-    double t = v3 > 0 ? (g.pv[0] / g.pv[2]) * sqrt(v3) * cabs2(cdv[g.Nrb + i]) / k1cos : 0.0;
+    // TE: the flux of a wave is (k_y / eps) |amplitude|^2.  Absorbing substrate: every
+    // order carries Re(k_3n) |d_n|^2 across Gamma_d.
+    double t;
+    if (lossy3) {
+      const cd k3{g.k[2], g.k_im[2]};
+      const cd k3n = csqrt_principal(k3 * k3 - cd{kapn * kapn, 0.0});
+      t = k3n.r * cabs2(cdv[g.Nrb + i]) / k1cos;
+    } else {
+      t = v3 > 0 ? (g.pv[0] / g.pv[2]) * sqrt(v3) * cabs2(cdv[g.Nrb + i]) / k1cos : 0.0;
+    }
     R[i] = r;
     T[i] = t;
     s += r + t;
   }
-  *flux = fabs(s - 1.0);
+  // absorbing substrate: it also absorbs between Gamma_2 and Gamma_d, so R + T + A
+  // is no energy balance
+  *flux = lossy3 ? __builtin_nan("") : fabs(s - 1.0);
 }
 }  // namespace
 
@@ -909,7 +941,7 @@ grt_status grt_bragg(grt_ctx* c0, int64_t rhs, const void* beta, int64_t cap, in
       *flux_err = hr[2 * Nrb];
       double ab = 0.0;
       st = absorbed_fraction(c, static_cast<const cd*>(beta), &ab);
-      if (st == GRT_OK && c->lossy) {
+      if (st == GRT_OK && c->lossy && c->g.k_im[2] == 0.0) {  // else no balance (NaN)
         double sum = ab - 1.0;
         for (int i = 0; i < Nrb; ++i) sum += R[i] + T[i];
         *flux_err = std::fabs(sum);

@@ -25,21 +25,27 @@ __host__ __device__ __forceinline__ void bessel01(double x, double& j0, double& 
   if (x >= 20.0) {
     double ix = 1.0 / x;
     // nu = 0 and nu = 1 together: P + iQ = sum_k i^k a_k / x^k
+    // each series stops at its smallest term (the expansion is asymptotic: near
+    // x = 20 its terms turn to grow again around k = 2x before reaching 1e-17)
     double p0 = 1.0, q0 = 0.0, p1 = 1.0, q1 = 0.0;
     double t0 = 1.0, t1 = 1.0;
-    for (int k = 1; k < 60; ++k) {
+    bool on0 = true, on1 = true;
+    for (int k = 1; k < 60 && (on0 || on1); ++k) {
       double o = (2.0 * k - 1.0) * (2.0 * k - 1.0);
       double f = ix / (8.0 * k);
-      t0 *= (0.0 - o) * f;
-      t1 *= (4.0 - o) * f;
+      const double n0 = t0 * (0.0 - o) * f, n1 = t1 * (4.0 - o) * f;
+      on0 = on0 && fabs(n0) < fabs(t0) && fabs(t0) >= 1e-17;
+      on1 = on1 && fabs(n1) < fabs(t1) && fabs(t1) >= 1e-17;
+      const double a0 = on0 ? n0 : 0.0, a1 = on1 ? n1 : 0.0;
+      t0 = n0;
+      t1 = n1;
       // i^k: k%4 == 1 -> +i, 2 -> -1, 3 -> -i, 0 -> +1
       switch (k & 3) {
-        case 1: q0 += t0; q1 += t1; break;
-        case 2: p0 -= t0; p1 -= t1; break;
-        case 3: q0 -= t0; q1 -= t1; break;
-        default: p0 += t0; p1 += t1; break;
+        case 1: q0 += a0; q1 += a1; break;
+        case 2: p0 -= a0; p1 -= a1; break;
+        case 3: q0 -= a0; q1 -= a1; break;
+        default: p0 += a0; p1 += a1; break;
       }
-      if (fabs(t0) < 1e-17 && fabs(t1) < 1e-17) break;
     }
     double s, c;
     sincos(x, &s, &c);
@@ -214,6 +220,136 @@ __host__ __device__ inline void bessel_j_three(double x, int q, double& jm, doub
     jm = -sg * c;
     j0 = sg * b;
     jpl = -sg * a;
+  }
+}
+
+// Complex argument (absorbing layers): 0 < |z|, Im z >= 0 and of order one below
+// |z| = 20.  J_0, J_1 by Miller's recurrence normalised as for real x, and Y_0, Y_1
+// from the same Neumann sums (the identities hold for complex z, with the principal
+// ln(z/2)); J and Y grow like e^{Im z} while H = J + iY decays like e^{-Im z}, so H
+// keeps about e^{-2 Im z} of the FP64 precision.
+__host__ __device__ inline void bessel01_c(cd z, cd& j0, cd& j1, cd& y0, cd& y1) {
+  const double az = sqrt(cabs2(z));
+  const int N = ((int)az + 34) & ~1;
+  const cd iz2 = cdiv(cd{2.0, 0.0}, z);
+  cd jp{0.0, 0.0}, jc{1e-30, 0.0}, seven{0.0, 0.0}, sy0{0.0, 0.0}, sy1{0.0, 0.0}, jn1{0.0, 0.0};
+  {
+    const int k = N >> 1;
+    seven += jc;
+    sy0 += (((k & 1) ? -1.0 : 1.0) / (double)k) * jc;
+  }
+  for (int n = N; n >= 1; --n) {
+    cd jm = (double)n * (iz2 * jc) - jp;
+    jp = jc;
+    jc = jm;
+    const int m = n - 1;
+    if (m >= 2 && !(m & 1)) {
+      const int k = m >> 1;
+      seven += jc;
+      sy0 += (((k & 1) ? -1.0 : 1.0) / (double)k) * jc;
+    } else if (m & 1) {
+      const int p = m >> 1;
+      const double cm = (p == 0) ? -1.0 : (((p & 1) ? 1.0 : -1.0) * (1.0 / p + 1.0 / (p + 1)));
+      sy1 += cm * jc;
+      if (m == 1) jn1 = jc;
+    }
+    if (cabs2(jc) > 1e200) {
+      const double sc = 1e-100;
+      jc = sc * jc; jp = sc * jp; seven = sc * seven; sy0 = sc * sy0; sy1 = sc * sy1;
+      jn1 = sc * jn1;
+    }
+  }
+  const cd scale = cdiv(cd{1.0, 0.0}, jc + 2.0 * seven);
+  j0 = jc * scale;
+  j1 = jn1 * scale;
+  sy0 = sy0 * scale;
+  sy1 = sy1 * scale;
+  const cd lg{log(0.5 * az) + GRT_EULER_GAMMA, atan2(z.i, z.r)};
+  y0 = GRT_2_PI * (lg * j0 - 2.0 * sy0);
+  y1 = GRT_2_PI * (lg * j1 + sy1 - cdiv(j0, z));
+}
+
+// H_0, H_1 at complex z (0 < |z|, Im z >= 0); real z goes to hankel01 above.  For
+// |z| >= 20 Hankel's expansion (DLMF 10.17.5, valid for |ph z| < pi) with the
+// principal sqrt(2 / (pi z)); below it bessel01_c.
+__host__ __device__ inline void hankel01_c(cd z, cd& h0, cd& h1) {
+  if (z.i == 0.0 && z.r > 0.0) {
+    hankel01(z.r, h0, h1);
+    return;
+  }
+  const double az = sqrt(cabs2(z));
+  if (az >= 20.0) {
+    const cd iz = cdiv(cd{1.0, 0.0}, z);
+    // t_k = i^k a_k(nu) / z^k; each series stops at its smallest term
+    cd s0{1.0, 0.0}, s1{1.0, 0.0}, t0{1.0, 0.0}, t1{1.0, 0.0};
+    bool on0 = true, on1 = true;
+    for (int k = 1; k < 60 && (on0 || on1); ++k) {
+      const double o = (2.0 * k - 1.0) * (2.0 * k - 1.0);
+      const double f = 1.0 / (8.0 * k);
+      const cd n0 = ((0.0 - o) * f) * times_i(t0 * iz);
+      const cd n1 = ((4.0 - o) * f) * times_i(t1 * iz);
+      on0 = on0 && cabs2(n0) < cabs2(t0) && cabs2(t0) >= 1e-34;
+      on1 = on1 && cabs2(n1) < cabs2(t1) && cabs2(t1) >= 1e-34;
+      if (on0) s0 += n0;
+      if (on1) s1 += n1;
+      t0 = n0;
+      t1 = n1;
+    }
+    const cd amp = csqrt_principal(cdiv(cd{GRT_2_PI, 0.0}, z));
+    const cd e = exp(-z.i) * cexpi(z.r - 0.25 * GRT_PI);  // e^{i(z - pi/4)}
+    const cd ae = amp * e;
+    h0 = ae * s0;
+    h1 = ae * cd{s1.i, -s1.r};  // e^{-i pi/2} = -i
+    return;
+  }
+  cd j0, j1, y0, y1;
+  bessel01_c(z, j0, j1, y0, y1);
+  h0 = j0 + times_i(y0);
+  h1 = j1 + times_i(y1);
+}
+
+// J_{q-1}, J_q, J_{q+1} for any integer q at complex z (Im z of order one; Miller,
+// normalised as above).
+__host__ __device__ inline void bessel_j_three_c(cd z, int q, cd& jm, cd& j0, cd& jpl) {
+  const int aq = q < 0 ? -q : q;
+  const double az = sqrt(cabs2(z));
+  if (az < 1e-300) {
+    jm = cd{(q - 1 == 0) ? 1.0 : 0.0, 0.0};
+    j0 = cd{(q == 0) ? 1.0 : 0.0, 0.0};
+    jpl = cd{(q + 1 == 0) ? 1.0 : 0.0, 0.0};
+    return;
+  }
+  const int top = (aq + 1) > (int)az ? (aq + 1) : (int)az;
+  const int N = (top + 34) & ~1;
+  const cd iz2 = cdiv(cd{2.0, 0.0}, z);
+  cd jp{0.0, 0.0}, jc{1e-30, 0.0}, seven = jc;
+  cd v[3] = {cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}};  // J_{aq-1}, J_aq, J_{aq+1}
+  if (N == aq + 1) v[2] = jc;
+  for (int n = N; n >= 1; --n) {
+    cd jmv = (double)n * (iz2 * jc) - jp;
+    jp = jc;
+    jc = jmv;
+    const int m = n - 1;
+    if (m >= 2 && !(m & 1)) seven += jc;
+    if (m == aq - 1) v[0] = jc;
+    if (m == aq) v[1] = jc;
+    if (m == aq + 1) v[2] = jc;
+    if (cabs2(jc) > 1e200) {
+      const double sc = 1e-100;
+      jc = sc * jc; jp = sc * jp; seven = sc * seven;
+      v[0] = sc * v[0]; v[1] = sc * v[1]; v[2] = sc * v[2];
+    }
+  }
+  const cd scale = cdiv(cd{1.0, 0.0}, jc + 2.0 * seven);
+  cd a = v[0] * scale, b = v[1] * scale, c = v[2] * scale;
+  if (aq == 0) a = -c;  // J_{-1} = -J_1
+  if (q >= 0) {
+    jm = a; j0 = b; jpl = c;
+  } else {  // J_{-n} = (-1)^n J_n
+    const double sg = (aq & 1) ? -1.0 : 1.0;
+    jm = (-sg) * c;
+    j0 = sg * b;
+    jpl = (-sg) * a;
   }
 }
 

@@ -40,6 +40,19 @@ __host__ __device__ __forceinline__ void cmac(cd& acc, cd a, cd b) {
 }
 // i * a
 __host__ __device__ __forceinline__ cd times_i(cd a) { return cd{-a.i, a.r}; }
+// Principal square root; the smaller part from w.i / (2 x the larger) so that a
+// nearly real w loses nothing to cancellation.
+__host__ __device__ __forceinline__ cd csqrt_principal(cd w) {
+  const double a = sqrt(cabs2(w));
+  if (a == 0.0) return cd{0.0, 0.0};
+  if (w.r >= 0.0) {
+    const double re = sqrt(0.5 * (a + w.r));
+    return cd{re, w.i / (2.0 * re)};
+  }
+  const double im = sqrt(0.5 * (a - w.r));
+  return cd{fabs(w.i) / (2.0 * im), w.i < 0.0 ? -im : im};
+}
+
 __host__ __device__ __forceinline__ cd cexpi(double t) {
   double s, c;
   sincos(t, &s, &c);

@@ -270,6 +270,8 @@ extern "C" grt_status grt_eval_field(grt_ctx* c0, int64_t rhs, const void* beta_
     return set_err(c, GRT_EUNSUP, "field evaluation is written for flat interfaces");
   if (c->lossy)
     return set_err(c, GRT_EUNSUP, "field evaluation is written for lossless disks");
+  if (c->g.k_im[2] != 0.0)
+    return set_err(c, GRT_EUNSUP, "field evaluation is written for a lossless substrate");
   if (n_pts < 0 || n_pts > ((int64_t)1 << 30)) return set_err(c, GRT_EINVAL, "bad point count");
   if (n_pts == 0) return GRT_OK;
   if (!xy_host || !u_host) return set_err(c, GRT_EINVAL, "null point or output array");

@@ -21,7 +21,8 @@ enum ColBlock { CB_MU1 = 0, CB_SIG1, CB_MU2, CB_SIG2, CB_A2, CB_A1, CB_A3, CB_C,
 // Everything a device kernel needs to know about one problem (passed by value).
 struct DevGeom {
   double d, h, y0, hs;          // period, half thickness, Gamma_u height, d/N
-  double k[3];                  // layer wavenumbers (top, middle, bottom)
+  double k[3];                  // layer wavenumbers (top, middle, bottom): real parts
+  double k_im[3];               // their imaginary parts (absorbing substrate: k_im[2] > 0)
   double kappa;                 // k_1 sin(phi)
   cd alpha, alpha_inv;          // Bloch phase e^{i kappa d} and its inverse
   // polarisation factors: the potentials of layer l carry pv[l] and the interface

@@ -122,39 +122,48 @@ __global__ void zeta_stencil_kernel(int K, double* zcw) {
 //   T = (i/4)[(ka H1_a - kb H1_b)(n_s.n_t)/r - (ka^2 H2_a - kb^2 H2_b)(R.n_s)(R.n_t)/r^2]
 // each times spd.  With logc, the coefficient phi of ln|s - t| instead: (i/4) H_n
 // replaced by -J_n / (2 pi) (the log part of Y_n).
-__device__ cd curve_kernel(int kind, bool logc, double ka, double kb, double wa, double wb,
+__device__ cd curve_kernel(int kind, bool logc, cd ka, cd kb, double wa, double wb,
                            double Rx, double Ry, double snx, double sny, double tnx, double tny,
                            double spd) {
   const double r = sqrt(Rx * Rx + Ry * Ry);
   cd Za[3], Zb[3];
-  const double ks[2] = {ka, kb};
+  const cd ks[2] = {ka, kb};
   for (int w = 0; w < 2; ++w) {
     cd* Z = w ? Zb : Za;
-    const double z = ks[w] * r;
+    const cd z = r * ks[w];
+    const cd two_z = cdiv(cd{2.0, 0.0}, z);
     if (logc) {
-      double j0, j1, y0, y1;
-      bessel01(z, j0, j1, y0, y1);
+      cd j0, j1;
+      if (z.i == 0.0) {
+        double a, b, c, e;
+        bessel01(z.r, a, b, c, e);
+        j0 = cd{a, 0.0};
+        j1 = cd{b, 0.0};
+      } else {
+        cd y0, y1;
+        bessel01_c(z, j0, j1, y0, y1);
+      }
       const double c = -1.0 / (2.0 * GRT_PI);
-      Z[0] = cd{c * j0, 0.0};
-      Z[1] = cd{c * j1, 0.0};
-      Z[2] = cd{c * ((2.0 / z) * j1 - j0), 0.0};
+      Z[0] = c * j0;
+      Z[1] = c * j1;
+      Z[2] = c * (two_z * j1 - j0);
     } else {
       cd h0, h1;
-      hankel01(z, h0, h1);
+      hankel01_c(z, h0, h1);
       Z[0] = times_i(0.25 * h0);
       Z[1] = times_i(0.25 * h1);
-      Z[2] = times_i(0.25 * ((2.0 / z) * h1 - h0));
+      Z[2] = times_i(0.25 * (two_z * h1 - h0));
     }
   }
   const double Rs = Rx * snx + Ry * sny, Rt = Rx * tnx + Ry * tny;
   cd v;
   switch (kind) {
     case 0: v = wa * Za[0] - wb * Zb[0]; break;
-    case 1: v = (Rt / r) * (wa * ka * Za[1] - wb * kb * Zb[1]); break;
+    case 1: v = (Rt / r) * (wa * (ka * Za[1]) - wb * (kb * Zb[1])); break;
     case 2: v = (-Rs / r) * (ka * Za[1] - kb * Zb[1]); break;
     default:
       v = ((snx * tnx + sny * tny) / r) * (ka * Za[1] - kb * Zb[1]) -
-          (Rs * Rt / (r * r)) * (ka * ka * Za[2] - kb * kb * Zb[2]);
+          (Rs * Rt / (r * r)) * ((ka * ka) * Za[2] - (kb * kb) * Zb[2]);
   }
   return spd * v;
 }
@@ -170,40 +179,44 @@ __device__ cd curve_kernel(int kind, bool logc, double ka, double kb, double wa,
 //      psi0 = spd [i (ka^2 - kb^2)/8 - (ka^2 ln(ka/2) - kb^2 ln(kb/2))/(4 pi)
 //                  + (ka^2 - kb^2)(1 - 2 gamma)/(8 pi) - (ka^2 - kb^2) ln(spd)/(4 pi)]
 // (small-argument series of J_n, Y_n).
-__device__ void curve_limits(int kind, double ka, double kb, double wa, double wb, double spd,
-                             double f2, double& phi0, cd& psi0) {
+__device__ void curve_limits(int kind, cd ka, cd kb, double wa, double wb, double spd,
+                             double f2, cd& phi0, cd& psi0) {
   const double gam = GRT_EULER_GAMMA, pi = GRT_PI, lsp = log(spd);
-  const double d2 = ka * ka - kb * kb;
+  const cd d2 = ka * ka - kb * kb;
+  // principal ln(k / 2) (complex for an absorbing layer)
+  const cd la{log(0.5 * sqrt(cabs2(ka))), atan2(ka.i, ka.r)};
+  const cd lb{log(0.5 * sqrt(cabs2(kb))), atan2(kb.i, kb.r)};
   switch (kind) {
     case 0:
-      phi0 = -(wa - wb) * spd / (2.0 * pi);
-      psi0 = cd{spd * ((wa - wb) * (-gam / (2.0 * pi) - lsp / (2.0 * pi)) -
-                       (wa * log(0.5 * ka) - wb * log(0.5 * kb)) / (2.0 * pi)),
-                spd * 0.25 * (wa - wb)};
+      phi0 = cd{-(wa - wb) * spd / (2.0 * pi), 0.0};
+      psi0 = spd * (cd{(wa - wb) * (-gam / (2.0 * pi) - lsp / (2.0 * pi)), 0.25 * (wa - wb)} -
+                    (1.0 / (2.0 * pi)) * (wa * la - wb * lb));
       break;
     case 1:
-      phi0 = 0.0;
+      phi0 = cd{0.0, 0.0};
       psi0 = cd{(wa - wb) * f2 / (4.0 * pi * spd * spd), 0.0};
       break;
     case 2:
-      phi0 = 0.0;
+      phi0 = cd{0.0, 0.0};
       psi0 = cd{0.0, 0.0};
       break;
     default:
-      phi0 = -d2 * spd / (4.0 * pi);
-      psi0 = cd{spd * (-(ka * ka * log(0.5 * ka) - kb * kb * log(0.5 * kb)) / (4.0 * pi) +
-                       d2 * (1.0 - 2.0 * gam) / (8.0 * pi) - d2 * lsp / (4.0 * pi)),
-                spd * 0.125 * d2};
+      phi0 = (-spd / (4.0 * pi)) * d2;
+      psi0 = spd * ((-1.0 / (4.0 * pi)) * ((ka * ka) * la - (kb * kb) * lb) +
+                    ((1.0 - 2.0 * gam) / (8.0 * pi) - lsp / (4.0 * pi)) * d2 +
+                    times_i(0.125 * d2));
   }
 }
 
 // Wavenumbers and layer weights of interface `line`'s same-interface blocks: the
 // layers above and below it; the single and double layers carry pv of their layer
 // (TE: eps), the flux rows' N and T parts are unweighted (fl pv = 1).
-__device__ __forceinline__ void line_pair(const DevGeom& g, int line, int kind, double& ka,
-                                          double& kb, double& wa, double& wb) {
-  ka = g.k[line];
-  kb = g.k[line + 1];
+__device__ __forceinline__ cd layer_k(const DevGeom& g, int l) { return cd{g.k[l], g.k_im[l]}; }
+
+__device__ __forceinline__ void line_pair(const DevGeom& g, int line, int kind, cd& ka,
+                                          cd& kb, double& wa, double& wb) {
+  ka = layer_k(g, line);
+  kb = layer_k(g, line + 1);
   const bool weighted = kind < 2;
   wa = weighted ? g.pv[line] : 1.0;
   wb = weighted ? g.pv[line + 1] : 1.0;
@@ -221,16 +234,15 @@ __global__ void curve_weights_kernel(DevGeom g, const double* zcw, cd* w) {
   const double* ni = g.node + ((size_t)line * N + i) * NODE_STRIDE;
   const double lhs = log(g.hs / (2.0 * GRT_PI));
   for (int kind = 0; kind < 4; ++kind) {
-    double ka, kb, wa, wb;
+    cd ka, kb, phi0, psi0;
+    double wa, wb;
     line_pair(g, line, kind, ka, kb, wa, wb);
-    double phi0;
-    cd psi0;
     curve_limits(kind, ka, kb, wa, wb, ni[4], ni[5], phi0, psi0);
     cd* out = w + (((size_t)line * 4 + kind) * N + i) * n;
     for (int p = -K; p <= K; ++p) {
       cd ph;
       if (p == 0) {
-        ph = cd{phi0, 0.0};
+        ph = phi0;
       } else {
         const int gi = i + p;
         const int l = gi < 0 ? -1 : (gi >= N ? 1 : 0);
@@ -239,7 +251,7 @@ __global__ void curve_weights_kernel(DevGeom g, const double* zcw, cd* w) {
                           ni[2], ni[3], nj[2], nj[3], nj[4]);
       }
       cd wp = (g.hs * zcw[p + K]) * ph;
-      if (p == 0) wp += g.hs * (psi0 + cd{phi0 * lhs, 0.0});
+      if (p == 0) wp += g.hs * (psi0 + lhs * phi0);
       out[p + K] = wp;
     }
   }
@@ -262,22 +274,23 @@ __device__ __forceinline__ cd alpha_pow(const DevGeom& g, int l) {
 // (source normal n = (nx, ny)), R = target - source; with deriv, their derivatives
 // along the unit direction (tx, ty) at the target:
 //   dS = -(ik/4) H1 (R.t)/r,  dD = (ik/4) [-k H2 (R.n)(R.t)/r^2 + H1 (n.t) / r].
-__device__ void lp_kernels(double k, double Rx, double Ry, double nx, double ny, bool deriv,
+__device__ void lp_kernels(cd k, double Rx, double Ry, double nx, double ny, bool deriv,
                            double tx, double ty, cd& S, cd& D) {
   double r = sqrt(Rx * Rx + Ry * Ry);
-  double z = k * r;
+  const cd z = r * k;
   cd h0, h1;
-  hankel01(z, h0, h1);
+  hankel01_c(z, h0, h1);
   const double Rn = Rx * nx + Ry * ny;
+  const cd kh1 = k * h1;
   if (!deriv) {
     S = times_i(0.25 * h0);
-    D = times_i((0.25 * k * Rn / r) * h1);
+    D = times_i((0.25 * Rn / r) * kh1);
     return;
   }
-  cd h2 = (2.0 / z) * h1 - h0;
+  cd h2 = cdiv(cd{2.0, 0.0}, z) * h1 - h0;
   double Rt = Rx * tx + Ry * ty;
-  S = times_i((-0.25 * k * Rt / r) * h1);
-  D = times_i((0.25 * k) * ((-k * Rn * Rt / (r * r)) * h2 + ((nx * tx + ny * ty) / r) * h1));
+  S = times_i((-0.25 * Rt / r) * kh1);
+  D = times_i(0.25 * ((-Rn * Rt / (r * r)) * (k * (k * h2)) + ((nx * tx + ny * ty) / r) * kh1));
 }
 
 __device__ __forceinline__ const double* node_at(const DevGeom& g, int line, int j) {
@@ -286,7 +299,7 @@ __device__ __forceinline__ const double* node_at(const DevGeom& g, int line, int
 
 // Three-copy trapezoid sum from node j of interface `line` (arc-length weight
 // hs * speed).
-__device__ void three_copy(const DevGeom& g, double k, double tx, double ty, int line, int j,
+__device__ void three_copy(const DevGeom& g, cd k, double tx, double ty, int line, int j,
                            bool deriv, double dx, double dy, cd& S, cd& D) {
   const double* nj = node_at(g, line, j);
   S = cd{0, 0};
@@ -305,7 +318,7 @@ __device__ void three_copy(const DevGeom& g, double k, double tx, double ty, int
 
 // Wall discrepancy alpha u(L) - u(R) of the three copies of node j, cancelled:
 // alpha^2 Phi(-3d/2, y) - alpha^{-1} Phi(3d/2, y), Phi the l = 0 copy.
-__device__ void wall_cancelled(const DevGeom& g, double k, double y, int line, int j, bool deriv,
+__device__ void wall_cancelled(const DevGeom& g, cd k, double y, int line, int j, bool deriv,
                                cd& S, cd& D) {
   const double* nj = node_at(g, line, j);
   cd a1, b1, a2, b2;
@@ -321,7 +334,8 @@ __device__ void wall_cancelled(const DevGeom& g, double k, double y, int line, i
 // kind 0..3 (weighted S, weighted D, N, T differences): punctured three-copy
 // trapezoid sum plus the target's stencil corrections.
 __device__ cd self_entry(const DevGeom& g, int line, int kind, int i, int j) {
-  double ka, kb, wa, wb;
+  cd ka, kb;
+  double wa, wb;
   line_pair(g, line, kind, ka, kb, wa, wb);
   const int N = g.N, K = g.zeta_K;
   const double* ni = node_at(g, line, i);
@@ -346,23 +360,37 @@ __device__ cd self_entry(const DevGeom& g, int line, int kind, int i, int j) {
 // -+ k Z_{q+-1} e^{i(q+-1) theta}.
 __device__ cd jcol(const DevGeom& g, int lay, int q, double tx, double ty, bool deriv, double dx,
                    double dy) {
-  double k = g.k[lay];
+  const cd k = layer_k(g, lay);
   double vx = tx, vy = ty - g.jcy[lay];
   double r = sqrt(vx * vx + vy * vy);
-  double jm, j0, jp;
-  bessel_j_three(k * r, q, jm, j0, jp);
+  cd jm, j0, jp;
+  if (k.i == 0.0) {
+    double a, b, c;
+    bessel_j_three(k.r * r, q, a, b, c);
+    jm = cd{a, 0.0};
+    j0 = cd{b, 0.0};
+    jp = cd{c, 0.0};
+  } else {
+    bessel_j_three_c(r * k, q, jm, j0, jp);
+  }
   cd e = (r > 0) ? cd{vx / r, vy / r} : cd{1.0, 0.0};
   auto epow = [&](int n) { return n >= 0 ? cpowi(e, n) : cpowi(conj(e), -n); };
   if (!deriv) return j0 * epow(q);
   cd fm = jm * epow(q - 1), fp = jp * epow(q + 1);
-  cd gx = (0.5 * k) * (fm - fp);
-  cd gy = times_i((0.5 * k) * (fm + fp));
+  cd gx = 0.5 * (k * (fm - fp));
+  cd gy = times_i(0.5 * (k * (fm + fp)));
   return dx * gx + dy * gy;
 }
 
-__device__ cd kz_branch(double k, double kap) {
-  double v = k * k - kap * kap;
-  return v >= 0 ? cd{sqrt(v), 0.0} : cd{0.0, sqrt(-v)};
+// sqrt(k^2 - kap^2): non-negative real or positive imaginary part for real k; for an
+// absorbing layer (Im k > 0, so Im(k^2 - kap^2) > 0) the principal root, with positive
+// real and imaginary parts (the Rayleigh-Bloch wave decays away from the layers).
+__device__ cd kz_branch(cd k, double kap) {
+  if (k.i == 0.0) {
+    double v = k.r * k.r - kap * kap;
+    return v >= 0 ? cd{sqrt(v), 0.0} : cd{0.0, sqrt(-v)};
+  }
+  return csqrt_principal(k * k - cd{kap * kap, 0.0});
 }
 
 __device__ cd A_entry(const DevGeom& g, int row, int col) {
@@ -373,7 +401,7 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
   int i = row - g.row_off[rb];
   int j = col - g.col_off[cb];
   const double d = g.d;
-  const double k1 = g.k[0], k2 = g.k[1], k3 = g.k[2];
+  const cd k1 = layer_k(g, 0), k2 = layer_k(g, 1), k3 = layer_k(g, 2);
   cd S, D;
   cd zero{0, 0};
   switch (rb) {
@@ -425,7 +453,7 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
       int lay = (rb <= RB_W2D) ? 1 : (rb <= RB_W1D ? 0 : 2);
       bool dv = (rb == RB_W2D || rb == RB_W1D || rb == RB_W3D);
       double y = g.yw[lay][i];
-      double k = g.k[lay];
+      const cd k = layer_k(g, lay);
       int jcb = (lay == 1) ? CB_A2 : (lay == 0 ? CB_A1 : CB_A3);
       bool top_line = (cb == CB_MU1 || cb == CB_SIG1);
       bool bot_line = (cb == CB_MU2 || cb == CB_SIG2);
@@ -446,7 +474,7 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
       bool dv = (rb == RB_UN || rb == RB_DN);
       double tx = -0.5 * d + (i + 0.5) * d / g.Nu;
       double ty = upper ? g.y0 : -g.y0;
-      double k = upper ? k1 : k3;
+      const cd k = upper ? k1 : k3;
       if (upper && (cb == CB_MU1 || cb == CB_SIG1)) {
         three_copy(g, k, tx, ty, 0, j, dv, 0.0, 1.0, S, D);
         return g.pv[0] * (cb == CB_MU1 ? D : S);
@@ -733,7 +761,7 @@ LayerFactors::~LayerFactors() {
 static std::string layer_key(const grt_ctx* c) {
   const grt_layers& L = c->lay;
   std::vector<double> v = {L.d, L.h, L.y0, L.n_layer[0], L.n_layer[1], L.n_layer[2], L.pinv_eps,
-                           c->inc.omega, c->inc.phi};
+                           c->inc.omega, c->inc.phi, L.n3_im};
   std::vector<int> iv = {c->device, L.N, L.Nw[0], L.Nw[1], L.Nw[2], L.Q[0], L.Q[1], L.Q[2], L.Nu,
                          L.n_rb_lo, L.Nrb, L.zeta_K, c->g.te};
   std::string k(reinterpret_cast<const char*>(v.data()), v.size() * sizeof(double));

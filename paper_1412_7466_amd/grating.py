@@ -28,7 +28,8 @@ class grt_layers(C.Structure):
                 ("n_layer", C.c_double * 3), ("N", C.c_int), ("Nw", C.c_int * 3),
                 ("Q", C.c_int * 3), ("Nu", C.c_int), ("n_rb_lo", C.c_int), ("Nrb", C.c_int),
                 ("zeta_K", C.c_int), ("pinv_eps", C.c_double),
-                ("n_fourier", C.c_int), ("iface", C.POINTER(C.c_double))]
+                ("n_fourier", C.c_int), ("iface", C.POINTER(C.c_double)),
+                ("n3_im", C.c_double)]
 
 
 class grt_inclusions(C.Structure):
@@ -213,7 +214,7 @@ class Context:
         lay = grt_layers(d=pb.d, h=pb.h, y0=dd.y0, n_layer=(C.c_double * 3)(*pb.n_layer),
                          N=dd.N, Nw=(C.c_int * 3)(*dd.Nw), Q=(C.c_int * 3)(*dd.Q), Nu=dd.Nu,
                          n_rb_lo=dd.n_rb_lo, Nrb=dd.Nrb, zeta_K=dd.zeta_K,
-                         pinv_eps=dd.pinv_eps)
+                         pinv_eps=dd.pinv_eps, n3_im=float(getattr(pb, "n3_im", 0.0) or 0.0))
         iface = getattr(pb, "interface", None)
         if iface is not None:
             self._iface = np.ascontiguousarray(iface, dtype=np.float64).reshape(2, 2, -1)

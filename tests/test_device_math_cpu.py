@@ -37,6 +37,28 @@ extern "C" void jnc(int n, const double* z, int nmax, double* out) {
     }
   }
 }
+extern "C" void h01c(int n, const double* z, double* out) {
+  for (int i = 0; i < n; ++i) {
+    cd a, b;
+    hankel01_c(cd{z[2 * i], z[2 * i + 1]}, a, b);
+    out[4 * i] = a.r; out[4 * i + 1] = a.i; out[4 * i + 2] = b.r; out[4 * i + 3] = b.i;
+  }
+}
+extern "C" void j01c(int n, const double* z, double* out) {
+  for (int i = 0; i < n; ++i) {
+    cd a, b, c, d;
+    bessel01_c(cd{z[2 * i], z[2 * i + 1]}, a, b, c, d);
+    out[4 * i] = a.r; out[4 * i + 1] = a.i; out[4 * i + 2] = b.r; out[4 * i + 3] = b.i;
+  }
+}
+extern "C" void j3c(int n, const double* z, const int* q, double* out) {
+  for (int i = 0; i < n; ++i) {
+    cd a, b, c;
+    bessel_j_three_c(cd{z[2 * i], z[2 * i + 1]}, q[i], a, b, c);
+    out[6 * i] = a.r; out[6 * i + 1] = a.i; out[6 * i + 2] = b.r; out[6 * i + 3] = b.i;
+    out[6 * i + 4] = c.r; out[6 * i + 5] = c.i;
+  }
+}
 """
 
 P = ctypes.POINTER(ctypes.c_double)
@@ -91,3 +113,61 @@ def test_complex_bessel_j_array_against_scipy(lib):
     near = np.abs(z)[:, None] <= 40
     assert np.max(err[big & near]) < 1e-12
     assert np.max(err[big]) < 1e-10        # |z| up to 60: the recurrence's rounding grows
+
+
+def _substrate_arguments(rng, n):
+    """k_3 r for an absorbing substrate: |z| in [1e-4, 400], arg z in [0, atan 0.1]
+    (the library takes n3_im <= 0.1 n_3), so Im z <= 2 below |z| = 20."""
+    az = 10 ** rng.uniform(-4, np.log10(400), n)
+    th = rng.uniform(0.0, np.arctan(0.1), n)
+    return az * np.exp(1j * th)
+
+
+def test_complex_hankel_against_scipy(lib):
+    """hankel01_c (absorbing substrate: Hankel's expansion above |z| = 20, Miller with
+    Neumann's series below) against SciPy's H_0, H_1 of complex argument, and
+    bessel01_c's J_0, J_1."""
+    sp = pytest.importorskip("scipy.special")
+    rng = np.random.default_rng(5)
+    z = np.concatenate([_substrate_arguments(rng, 800), [20.0 + 1e-3j, 19.999 + 2j, 5.0 + 0j]])
+    zz = np.stack([z.real, z.imag], axis=1).reshape(-1).copy()
+    o = np.empty(4 * len(z))
+    lib.h01c(len(z), zz.ctypes.data_as(P), o.ctypes.data_as(P))
+    o = o.reshape(-1, 4)
+    for nu, col in ((0, 0), (1, 2)):
+        H = o[:, col] + 1j * o[:, col + 1]
+        ref = sp.hankel1(nu, z)
+        err = np.abs(H - ref) / np.abs(ref)
+        assert np.max(err) < 1e-13, (nu, z[np.argmax(err)], np.max(err))
+    small = np.abs(z) < 20      # where the library takes J_0, J_1 from bessel01_c
+    o2 = np.empty(4 * len(z))
+    lib.j01c(len(z), zz.ctypes.data_as(P), o2.ctypes.data_as(P))
+    o2 = o2.reshape(-1, 4)
+    for nu, col in ((0, 0), (1, 2)):
+        J = o2[:, col] + 1j * o2[:, col + 1]
+        ref = sp.jv(nu, z)
+        err = np.abs(J - ref) / np.maximum(np.abs(ref), 1e-3)
+        assert np.max(err[small]) < 1e-13
+
+
+def test_complex_j_three_against_scipy(lib):
+    """bessel_j_three_c (the substrate's J expansions): J_{q-1}, J_q, J_{q+1} for
+    q in [-40, 40] at |z| <= 60 (the J expansions' radius times |k_3|), relative error
+    per entry."""
+    sp = pytest.importorskip("scipy.special")
+    rng = np.random.default_rng(6)
+    z = _substrate_arguments(rng, 600)
+    z = z[np.abs(z) <= 60]
+    q = rng.integers(-40, 41, len(z)).astype(np.int32)
+    zz = np.stack([z.real, z.imag], axis=1).reshape(-1).copy()
+    o = np.empty(6 * len(z))
+    lib.j3c(len(z), zz.ctypes.data_as(P), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            o.ctypes.data_as(P))
+    o = o.reshape(-1, 3, 2)
+    J = o[..., 0] + 1j * o[..., 1]
+    ref = sp.jv(q[:, None] + np.arange(-1, 2)[None, :], z[:, None])
+    err = np.abs(J - ref) / np.maximum(np.abs(ref), 1e-200)
+    ok = np.abs(ref) > 1e-200
+    near = (np.abs(z) <= 40)[:, None]
+    assert np.max(err[ok & near]) < 1e-12
+    assert np.max(err[ok]) < 1e-10        # |z| up to 60: the recurrence's rounding grows
