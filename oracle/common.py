@@ -67,14 +67,12 @@ class Geometry:
         self.d, self.h = float(pb.d), float(pb.h)
         self.k1, self.k2, self.k3 = (pb.omega * n for n in pb.n_layer)
         # absorbing substrate: k_3 = omega (n_3 + i n3_im), Im k_3 > 0 (sec. 7 names
-        # complex permittivities as an extension); TM only
+        # complex permittivities as an extension); for TE its eps_3 = (n_3 + i n3_im)^2
         n3_im = float(getattr(pb, "n3_im", 0.0) or 0.0)
         self.lossy3 = n3_im != 0.0
         if self.lossy3:
             if n3_im < 0:
                 raise ValueError("n3_im must be non-negative")
-            if getattr(pb, "polarization", "TM") == "TE":
-                raise NotImplementedError("an absorbing substrate is taken for TM only")
             self.k3 = pb.omega * (pb.n_layer[2] + 1j * n3_im)
         self.kl = (self.k1, self.k2, self.k3)
         self.P = int(pb.P)
@@ -94,6 +92,8 @@ class Geometry:
         # has both factors 1.
         self.te = getattr(pb, "polarization", "TM") == "TE"
         self.eps = tuple(n ** 2 for n in pb.n_layer)
+        if self.lossy3:  # complex permittivity of the absorbing substrate
+            self.eps = (self.eps[0], self.eps[1], (pb.n_layer[2] + 1j * n3_im) ** 2)
         self.eps_incl = n_p ** 2
         self.pv = self.eps if self.te else (1.0, 1.0, 1.0)
         self.fl = tuple(1.0 / e for e in self.eps) if self.te else (1.0, 1.0, 1.0)

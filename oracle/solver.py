@@ -220,8 +220,9 @@ class Reduced:
             # field of inclusions close to the interface, which the amplitudes at
             # Gamma_d no longer resolve; so R + T + A < 1 and flux_err is NaN.
             # "Propagating" marks the orders with Re(k_3^2 - kappa_n^2) > 0.
+            # TE: the flux of a wave is Re(k_y / eps) |amplitude|^2, over k_1 cos(phi) / eps_1
             prop3 = (G.k3 ** 2 - G.kapn ** 2).real > 0
-            Tn = G.k3n.real * np.abs(d) ** 2 / inc
+            Tn = ((G.eps[0] * G.k3n / G.eps[2]).real if G.te else G.k3n.real) * np.abs(d) ** 2 / inc
             flux = float("nan")
         else:
             prop3 = (np.abs(G.k3n.imag) == 0) & (G.k3n.real > 0)
