@@ -85,11 +85,12 @@ typedef struct {
    * Hankel and Bessel routines of the layer matrix are not validated; GRT_EUNSUP
    * also when |k_3| times the reach of the bottom layer's J expansion exceeds 60).
    * The layer matrix then takes H_0, H_1 and J_n at complex arguments and the
-   * Rayleigh-Bloch wavenumbers k_3n with positive real and imaginary parts; the
-   * translation, C and B_phys (middle layer only) are unchanged.  TM only; no field
-   * evaluation (GRT_EUNSUP).  grt_bragg then reports T_n as the power order n carries
-   * across Gamma_d and flux_err as NaN: the substrate also absorbs between Gamma_2
-   * and Gamma_d.  0: lossless. */
+   * Rayleigh-Bloch wavenumbers k_3n with positive real and imaginary parts (TE: the
+   * substrate's eps_3 = (n_3 + i n3_im)^2 is complex too); the translation, C and
+   * B_phys (middle layer only) are unchanged.  TM and TE; no field evaluation
+   * (GRT_EUNSUP).  grt_bragg then reports T_n as the power order n carries across
+   * Gamma_d and flux_err as NaN: the substrate also absorbs between Gamma_2 and
+   * Gamma_d.  0: lossless. */
   double n3_im;
 } grt_layers;
 
@@ -376,7 +377,8 @@ grt_status grt_solve(grt_ctx* ctx, const grt_solve_opts* opts, void* beta_dev,
  * and the energy-balance error |sum R + sum T + absorbed - 1| (the flux error of
  * sec. 6 for lossless media).  Over an absorbing substrate (grt_layers.n3_im > 0)
  * T[i] is Re(k_3n) |d_n|^2 over the incident flux for every order (the power order
- * n carries across Gamma_d) and flux_err is NaN.  GRT_EINVAL for rhs out of range. */
+ * n carries across Gamma_d; TE: eps_1 Re(k_3n / eps_3) |d_n|^2 over k_1 cos(phi)) and
+ * flux_err is NaN.  GRT_EINVAL for rhs out of range. */
 grt_status grt_bragg(grt_ctx* ctx, int64_t rhs, const void* beta_dev, int64_t cap, int* orders,
                      double* c, double* d, double* R, double* T, double* flux_err,
                      double* absorbed);

@@ -205,8 +205,6 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
   if (L.n3_im > 0) {
     if (L.n3_im > 0.1 * L.n_layer[2])
       return set_err(c, GRT_EUNSUP, "an absorbing substrate is taken for n3_im <= 0.1 n_3");
-    if (wave->polarization == GRT_TE)
-      return set_err(c, GRT_EUNSUP, "an absorbing substrate is taken for TM only");
     // the bottom layer's J expansion about (0, -(h + y0) / 2) is evaluated up to the
     // corners of Gamma_d and the highest point of Gamma_2
     double hi = -L.h;
@@ -362,6 +360,14 @@ grt_status grt_set_problem(grt_ctx* c, const grt_layers* lay, const grt_inclusio
     const double eps = L.n_layer[l] * L.n_layer[l];
     g.pv[l] = g.te ? eps : 1.0;
     g.fl[l] = g.te ? 1.0 / eps : 1.0;
+  }
+  if (g.te && L.n3_im > 0) {  // eps_3 = (n_3 + i n3_im)^2 and its inverse
+    const cd e3 = cd{L.n_layer[2], L.n3_im} * cd{L.n_layer[2], L.n3_im};
+    const cd ie3 = cdiv(cd{1.0, 0.0}, e3);
+    g.pv[2] = e3.r;
+    g.pv_im[2] = e3.i;
+    g.fl[2] = ie3.r;
+    g.fl_im[2] = ie3.i;
   }
   g.kappa = g.k[0] * std::sin(phi0);
   g.alpha = cd{std::cos(g.kappa * L.d), std::sin(g.kappa * L.d)};
@@ -862,7 +868,9 @@ __global__ void bragg_finish_kernel(DevGeom g, double k1cos, const cd* cdv, doub
     if (lossy3) {
       const cd k3{g.k[2], g.k_im[2]};
       const cd k3n = csqrt_principal(k3 * k3 - cd{kapn * kapn, 0.0});
-      t = k3n.r * cabs2(cdv[g.Nrb + i]) / k1cos;
+      // TE: Re(k_3n / eps_3) eps_1
+      const double ky = g.te ? g.pv[0] * (k3n * cd{g.fl[2], g.fl_im[2]}).r : k3n.r;
+      t = ky * cabs2(cdv[g.Nrb + i]) / k1cos;
     } else {
       t = v3 > 0 ? (g.pv[0] / g.pv[2]) * sqrt(v3) * cabs2(cdv[g.Nrb + i]) / k1cos : 0.0;
     }

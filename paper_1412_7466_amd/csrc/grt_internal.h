@@ -28,6 +28,7 @@ struct DevGeom {
   // polarisation factors: the potentials of layer l carry pv[l] and the interface
   // flux rows fl[l] for the field of layer l (TM: all 1; TE: eps_l and 1/eps_l)
   double pv[3], fl[3];
+  double pv_im[3], fl_im[3];     // imaginary parts (TE over an absorbing substrate: layer 2)
   int te;
   int N, Nu, n_rb_lo, Nrb, zeta_K, P, M;
   int Nw[3], Q[3];

@@ -122,7 +122,7 @@ __global__ void zeta_stencil_kernel(int K, double* zcw) {
 //   T = (i/4)[(ka H1_a - kb H1_b)(n_s.n_t)/r - (ka^2 H2_a - kb^2 H2_b)(R.n_s)(R.n_t)/r^2]
 // each times spd.  With logc, the coefficient phi of ln|s - t| instead: (i/4) H_n
 // replaced by -J_n / (2 pi) (the log part of Y_n).
-__device__ cd curve_kernel(int kind, bool logc, cd ka, cd kb, double wa, double wb,
+__device__ cd curve_kernel(int kind, bool logc, cd ka, cd kb, cd wa, cd wb,
                            double Rx, double Ry, double snx, double sny, double tnx, double tny,
                            double spd) {
   const double r = sqrt(Rx * Rx + Ry * Ry);
@@ -179,7 +179,7 @@ __device__ cd curve_kernel(int kind, bool logc, cd ka, cd kb, double wa, double 
 //      psi0 = spd [i (ka^2 - kb^2)/8 - (ka^2 ln(ka/2) - kb^2 ln(kb/2))/(4 pi)
 //                  + (ka^2 - kb^2)(1 - 2 gamma)/(8 pi) - (ka^2 - kb^2) ln(spd)/(4 pi)]
 // (small-argument series of J_n, Y_n).
-__device__ void curve_limits(int kind, cd ka, cd kb, double wa, double wb, double spd,
+__device__ void curve_limits(int kind, cd ka, cd kb, cd wa, cd wb, double spd,
                              double f2, cd& phi0, cd& psi0) {
   const double gam = GRT_EULER_GAMMA, pi = GRT_PI, lsp = log(spd);
   const cd d2 = ka * ka - kb * kb;
@@ -188,13 +188,13 @@ __device__ void curve_limits(int kind, cd ka, cd kb, double wa, double wb, doubl
   const cd lb{log(0.5 * sqrt(cabs2(kb))), atan2(kb.i, kb.r)};
   switch (kind) {
     case 0:
-      phi0 = cd{-(wa - wb) * spd / (2.0 * pi), 0.0};
-      psi0 = spd * (cd{(wa - wb) * (-gam / (2.0 * pi) - lsp / (2.0 * pi)), 0.25 * (wa - wb)} -
+      phi0 = (-spd / (2.0 * pi)) * (wa - wb);
+      psi0 = spd * (cd{-gam / (2.0 * pi) - lsp / (2.0 * pi), 0.25} * (wa - wb) -
                     (1.0 / (2.0 * pi)) * (wa * la - wb * lb));
       break;
     case 1:
       phi0 = cd{0.0, 0.0};
-      psi0 = cd{(wa - wb) * f2 / (4.0 * pi * spd * spd), 0.0};
+      psi0 = (f2 / (4.0 * pi * spd * spd)) * (wa - wb);
       break;
     case 2:
       phi0 = cd{0.0, 0.0};
@@ -213,13 +213,17 @@ __device__ void curve_limits(int kind, cd ka, cd kb, double wa, double wb, doubl
 // (TE: eps), the flux rows' N and T parts are unweighted (fl pv = 1).
 __device__ __forceinline__ cd layer_k(const DevGeom& g, int l) { return cd{g.k[l], g.k_im[l]}; }
 
+// TE layer factors as complex numbers (complex for the absorbing substrate's eps_3)
+__device__ __forceinline__ cd layer_pv(const DevGeom& g, int l) { return cd{g.pv[l], g.pv_im[l]}; }
+__device__ __forceinline__ cd layer_fl(const DevGeom& g, int l) { return cd{g.fl[l], g.fl_im[l]}; }
+
 __device__ __forceinline__ void line_pair(const DevGeom& g, int line, int kind, cd& ka,
-                                          cd& kb, double& wa, double& wb) {
+                                          cd& kb, cd& wa, cd& wb) {
   ka = layer_k(g, line);
   kb = layer_k(g, line + 1);
   const bool weighted = kind < 2;
-  wa = weighted ? g.pv[line] : 1.0;
-  wb = weighted ? g.pv[line + 1] : 1.0;
+  wa = weighted ? layer_pv(g, line) : cd{1.0, 0.0};
+  wb = weighted ? layer_pv(g, line + 1) : cd{1.0, 0.0};
 }
 
 // Correction weights of every target: one thread per (interface, target), all four
@@ -234,8 +238,7 @@ __global__ void curve_weights_kernel(DevGeom g, const double* zcw, cd* w) {
   const double* ni = g.node + ((size_t)line * N + i) * NODE_STRIDE;
   const double lhs = log(g.hs / (2.0 * GRT_PI));
   for (int kind = 0; kind < 4; ++kind) {
-    cd ka, kb, phi0, psi0;
-    double wa, wb;
+    cd ka, kb, wa, wb, phi0, psi0;
     line_pair(g, line, kind, ka, kb, wa, wb);
     curve_limits(kind, ka, kb, wa, wb, ni[4], ni[5], phi0, psi0);
     cd* out = w + (((size_t)line * 4 + kind) * N + i) * n;
@@ -334,8 +337,7 @@ __device__ void wall_cancelled(const DevGeom& g, cd k, double y, int line, int j
 // kind 0..3 (weighted S, weighted D, N, T differences): punctured three-copy
 // trapezoid sum plus the target's stencil corrections.
 __device__ cd self_entry(const DevGeom& g, int line, int kind, int i, int j) {
-  cd ka, kb;
-  double wa, wb;
+  cd ka, kb, wa, wb;
   line_pair(g, line, kind, ka, kb, wa, wb);
   const int N = g.N, K = g.zeta_K;
   const double* ni = node_at(g, line, i);
@@ -440,12 +442,13 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
           return ((dv ? g.fl[1] : 1.0) * g.pv[1]) * (cb == CB_MU1 ? D : S);
         case CB_MU2:
           return dv ? self_entry(g, 1, 3, i, j)
-                    : (i == j ? cd{0.5 * (g.pv[1] + g.pv[2]), 0} : zero) + self_entry(g, 1, 1, i, j);
+                    : (i == j ? 0.5 * (layer_pv(g, 1) + layer_pv(g, 2)) : zero) +
+                          self_entry(g, 1, 1, i, j);
         case CB_SIG2:
           return dv ? (i == j ? cd{-1, 0} : zero) + self_entry(g, 1, 2, i, j)
                     : self_entry(g, 1, 0, i, j);
         case CB_A2: return (dv ? g.fl[1] : 1.0) * jcol(g, 1, j - g.Q[1], tx, ty, dv, nx, ny);
-        case CB_A3: return -(dv ? g.fl[2] : 1.0) * jcol(g, 2, j - g.Q[2], tx, ty, dv, nx, ny);
+        case CB_A3: return -((dv ? layer_fl(g, 2) : cd{1.0, 0.0}) * jcol(g, 2, j - g.Q[2], tx, ty, dv, nx, ny));
         default: return zero;
       }
     }
@@ -459,7 +462,7 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
       bool bot_line = (cb == CB_MU2 || cb == CB_SIG2);
       if ((top_line && lay != 2) || (bot_line && lay != 0)) {
         wall_cancelled(g, k, y, top_line ? 0 : 1, j, dv, S, D);
-        return g.pv[lay] * ((cb == CB_MU1 || cb == CB_MU2) ? D : S);
+        return layer_pv(g, lay) * ((cb == CB_MU1 || cb == CB_MU2) ? D : S);
       }
       if (cb == jcb) {
         int q = j - g.Q[lay];
@@ -481,7 +484,7 @@ __device__ cd A_entry(const DevGeom& g, int row, int col) {
       }
       if (!upper && (cb == CB_MU2 || cb == CB_SIG2)) {
         three_copy(g, k, tx, ty, 1, j, dv, 0.0, 1.0, S, D);
-        return g.pv[2] * (cb == CB_MU2 ? D : S);
+        return layer_pv(g, 2) * (cb == CB_MU2 ? D : S);
       }
       if (upper && cb == CB_A1) return jcol(g, 0, j - g.Q[0], tx, ty, dv, 0.0, 1.0);
       if (!upper && cb == CB_A3) return jcol(g, 2, j - g.Q[2], tx, ty, dv, 0.0, 1.0);

@@ -1,10 +1,11 @@
-"""An absorbing substrate on the GPU (bottom layer index n_3 + i n3_im, TM) against
+"""An absorbing substrate on the GPU (bottom layer index n_3 + i n3_im, TM and TE) against
 the CPU oracle's (pinned in tests/test_oracle_substrate.py: the Fresnel slab with
 complex k_3 and its energy balance, independence of the artificial line Gamma_d).
 
 The library assembles the layer matrix with H_0, H_1 and J_n at complex arguments
 (checked on the host in tests/test_device_math_cpu.py) and the Rayleigh-Bloch
-wavenumbers k_3n on the decaying branch; the apply kernels are unchanged.  Bars as for
+wavenumbers k_3n on the decaying branch (TE: the substrate's factors eps_3 and 1/eps_3
+complex); the apply kernels are unchanged.  Bars as for
 the lossless layers: equilibrated A to 1e-12, K, the right-hand side, solutions and
 Bragg amplitudes 1e-9; the transmitted powers 1e-9 relative.
 """
@@ -55,11 +56,13 @@ def _bragg(og, oo, tag):
     assert np.max(np.abs(og["T"][sel] - oo["T"][sel])) < 1e-9 * max(oo["T"][sel].sum(), 1e-3)
 
 
-@pytest.mark.parametrize("phi,n3_im", [(-math.pi / 5, 0.05), (0.3, 0.12)])
-def test_substrate_empty_slab(torch_cuda, phi, n3_im):
+@pytest.mark.parametrize("phi,n3_im,pol", [(-math.pi / 5, 0.05, "TM"), (0.3, 0.12, "TM"),
+                                           (0.3, 0.12, "TE")])
+def test_substrate_empty_slab(torch_cuda, phi, n3_im, pol):
     from oracle.solver import Reduced
     pb = inputs.empty_slab(phi=phi)
     pb.n3_im = n3_im
+    pb.polarization = pol
     red = Reduced(pb)
     ctx = _ctx(pb)
     og = ctx.bragg()
@@ -67,11 +70,12 @@ def test_substrate_empty_slab(torch_cuda, phi, n3_im):
     i0 = list(oo["orders"]).index(0)
     assert abs(og["c"][i0] - oo["c"][i0]) < 1e-12
     assert abs(og["d"][i0] - oo["d"][i0]) < 1e-12
+    assert abs(og["T"][i0] - oo["T"][i0]) < 1e-12
     assert math.isnan(og["flux_err"])
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["flat", "curved", "absorbing_disks"])
+@pytest.mark.parametrize("case", ["flat", "curved", "absorbing_disks", "te", "te_curved"])
 def test_substrate_pieces_and_solve(torch_cuda, case):
     from oracle.solver import Reduced
     from paper_1412_7466_amd.grating import GRT_FP32_RELAXED
@@ -80,7 +84,9 @@ def test_substrate_pieces_and_solve(torch_cuda, case):
         pb = inputs.lossy(12, 6, seed=21)
         pb.n3_im = 0.08
     else:
-        pb = inputs.lossy_substrate(12, 6, seed=21, n3_im=0.08, curved_iface=case == "curved")
+        pb = inputs.lossy_substrate(12, 6, seed=21, n3_im=0.08, curved_iface=case.endswith("curved"))
+        if case.startswith("te"):
+            pb.polarization = "TE"
     red = Reduced(pb)
     G = red.G
     ctx = _ctx(pb)
@@ -149,7 +155,7 @@ def test_substrate_refused_where_unsupported(torch_cuda):
     ctx.close()
     c2 = Context(0)
     for n3_im, pol, status in ((-0.01, "TM", GRT_EINVAL), (0.5, "TM", GRT_EUNSUP),
-                               (0.05, "TE", GRT_EUNSUP)):
+                               (0.5, "TE", GRT_EUNSUP)):
         bad = inputs.lossy_substrate(6, 6, seed=3, n3_im=n3_im)
         bad.polarization = pol
         with pytest.raises(GratingError) as ei:
