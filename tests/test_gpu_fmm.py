@@ -117,18 +117,20 @@ def test_fmm_refused_where_unsupported(torch_cuda):
     c2.close()
 
 
-@pytest.mark.parametrize("case", ["star", "curved", "te", "lossy"])
+@pytest.mark.parametrize("case", ["star", "curved", "te", "lossy", "substrate"])
 def test_fmm_with_other_features(torch_cuda, case):
     """The cell translation only replaces T: with non-circular inclusions, curved
-    interfaces, TE or absorbing disks the K apply and the solution stay those of the
-    dense translation (1e-12 per order on K, 1e-10 on the solution)."""
+    interfaces, TE, absorbing disks or an absorbing substrate the K apply and the
+    solution stay those of the dense translation (1e-12 per order on K, 1e-10 on the
+    solution)."""
     from paper_1412_7466_amd.grating import Context
     from parity import dscale, probe
     torch = torch_cuda
     pb = {"star": lambda: inputs.star(60, 8, seed=31),
           "curved": lambda: inputs.curved(60, 8, seed=32),
           "te": lambda: inputs.small(60, 8, seed=33),
-          "lossy": lambda: inputs.lossy(60, 8, seed=34)}[case]()
+          "lossy": lambda: inputs.lossy(60, 8, seed=34),
+          "substrate": lambda: inputs.lossy_substrate(60, 8, seed=35, n3_im=0.08)}[case]()
     if case == "te":
         pb.polarization = "TE"
     ctx = Context(0)
