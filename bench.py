@@ -628,7 +628,7 @@ def fmm_translation(a, torch):
     out = {"workload": (f"large block packing, M={pb.M}, omega={pb.omega:g}, P={P}, one angle: "
                         f"T x by cells against the dense translation (generator on the fly)"),
            "dense_ms": dense_ms}
-    for per_cell in (16, 24, 40, 64):
+    for per_cell in (8, 12, 16, 24, 40, 64):
         t0 = time.perf_counter()
         nx, ny, p = ctx.set_fmm(True, per_cell=per_cell)
         torch.cuda.synchronize()

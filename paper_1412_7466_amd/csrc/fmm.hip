@@ -37,7 +37,6 @@ constexpr int FMM_THREADS = 256;
 constexpr int FMM_SLOTS = 9;                  // near neighbour slots (dx, dy) in {-1,0,1}^2
 constexpr int FMM_CAP = 16;                   // inclusions per pass of the shift kernels
 constexpr int FMM_SPLIT = 4;                  // source-cell shares of the cell translation
-constexpr int FMM_STAGE = 4;                  // source cells staged in LDS at a time
 
 __device__ __forceinline__ cd copy_weight(cd alpha, cd alpha_inv, int l) {
   return l == 0 ? cd{1.0, 0.0} : (l > 0 ? alpha : alpha_inv);
@@ -140,37 +139,69 @@ __global__ void __launch_bounds__(FMM_THREADS) fmm_p2m_kernel(
   if (t < 2 * p + 1) Mc[(size_t)cell * (2 * p + 1) + t] = acc;
 }
 
-// M2L: block (target cell, share s of the source cells), thread t <-> n = t - p; the
-// share's source multipoles are staged in LDS FMM_STAGE cells at a time and
-// contracted with their generator rows; partial s of L_A is written.
+// M2L: block (target cell, share s of the source cells).  A thread holds FMM_RT
+// consecutive outputs n and keeps a sliding window of FMM_RT generator entries
+// tau_{mu - n}, so each generator load and each coefficient read from LDS serve
+// FMM_RT products; the block's threads form G = FMM_THREADS / NR groups (NR threads
+// cover the 2p + 1 outputs), group g taking every G-th source cell of the share, and
+// the groups' sums are added through LDS in group order; partial s of L_A is written.
+constexpr int FMM_RT = 4;
+static_assert(FMM_RT == 4, "the window is written out for four outputs");
 __global__ void __launch_bounds__(FMM_THREADS) fmm_m2l_kernel(const cd* __restrict__ Mc,
                                                              const cd* __restrict__ gen, int nx,
                                                              int ny, int p, cd* Lpart) {
-  __shared__ cd ms[FMM_STAGE][2 * FMM_PMAX + 1];
+  // G * NB <= FMM_RT * FMM_THREADS source coefficients, and as many partial sums
+  __shared__ cd ms[FMM_RT * FMM_THREADS];
   const int A = blockIdx.x, share = blockIdx.y, t = threadIdx.x;
   const int ax = A / ny, ay = A % ny;
   const int NB = 2 * p + 1, NQ = 4 * p + 1;
+  const int NR = (NB + FMM_RT - 1) / FMM_RT, G = FMM_THREADS / NR;
+  const int grp = t / NR, o = (t - grp * NR) * FMM_RT;  // outputs o .. o + FMM_RT - 1
   const int ncell = nx * ny;
   const int per = (ncell + FMM_SPLIT - 1) / FMM_SPLIT;
   const int b0 = share * per, b1 = min(ncell, b0 + per);
-  cd acc{0.0, 0.0};
-  for (int B0 = b0; B0 < b1; B0 += FMM_STAGE) {
-    const int cnt = min(FMM_STAGE, b1 - B0);
+  cd acc[FMM_RT];
+#pragma unroll
+  for (int u = 0; u < FMM_RT; ++u) acc[u] = cd{0.0, 0.0};
+  for (int B0 = b0; B0 < b1; B0 += G) {
+    const int cnt = min(G, b1 - B0);
     __syncthreads();
-    for (int i = t; i < cnt * NB; i += blockDim.x) ms[i / NB][i % NB] = Mc[(size_t)(B0 + i / NB) * NB + i % NB];
+    for (int i = t; i < cnt * NB; i += blockDim.x) ms[i] = Mc[(size_t)B0 * NB + i];
     __syncthreads();
-    if (t < NB) {
-      for (int c = 0; c < cnt; ++c) {
-        const int B = B0 + c;
-        const int e = (ax - B / ny + nx - 1) * (2 * ny - 1) + (ay - B % ny + ny - 1);
-        // tau_{mu - n} at index mu - n + 2p = i - t + 2p for mu = i - p
-        const cd* g = gen + (size_t)e * NQ + 2 * p - t;
-#pragma unroll 4
-        for (int i = 0; i < NB; ++i) cmac(acc, g[i], ms[c][i]);
+    if (grp < cnt) {
+      const int B = B0 + grp;
+      const int e = (ax - B / ny + nx - 1) * (2 * ny - 1) + (ay - B % ny + ny - 1);
+      const cd* gb = gen + (size_t)e * NQ + 2 * p;  // tau_q = gb[q], |q| <= 2p
+      const cd* m = ms + grp * NB;
+      // w[u] = tau_{i - (o + u)}: the coefficient of output o + u times M_B[i]; the
+      // padding outputs (o + u >= NB) reach q < -2p, read as zero
+      cd w[FMM_RT];  // the window before i = 0
+      w[0] = (-1 - o >= -2 * p) ? gb[-1 - o] : cd{0.0, 0.0};
+      w[1] = (-2 - o >= -2 * p) ? gb[-2 - o] : cd{0.0, 0.0};
+      w[2] = (-3 - o >= -2 * p) ? gb[-3 - o] : cd{0.0, 0.0};
+      w[3] = cd{0.0, 0.0};
+      for (int i = 0; i < NB; ++i) {
+        w[3] = w[2];
+        w[2] = w[1];
+        w[1] = w[0];
+        w[0] = (i - o >= -2 * p) ? gb[i - o] : cd{0.0, 0.0};
+        const cd mi = m[i];
+#pragma unroll
+        for (int u = 0; u < FMM_RT; ++u) cmac(acc[u], w[u], mi);
       }
     }
   }
-  if (t < NB) Lpart[((size_t)share * ncell + A) * NB + t] = acc;
+  __syncthreads();
+  if (grp < G) {
+#pragma unroll
+    for (int u = 0; u < FMM_RT; ++u) ms[grp * NR * FMM_RT + o + u] = acc[u];
+  }
+  __syncthreads();
+  for (int n = t; n < NB; n += blockDim.x) {
+    cd s{0.0, 0.0};
+    for (int g = 0; g < G; ++g) s += ms[g * NR * FMM_RT + n];
+    Lpart[((size_t)share * ncell + A) * NB + n] = s;
+  }
 }
 
 // L2L: one block per cell, FMM_CAP inclusions per pass, one thread per (inclusion, n):
@@ -373,7 +404,7 @@ grt_status fmm_setup(grt_ctx* c, int p_cell, int per_cell) {
   const int64_t M = c->M;
   if (M == 0) return GRT_OK;
   if (c->P > 20) return set_err(c, GRT_EUNSUP, "the cell translation takes P <= 20");
-  if (per_cell <= 0) per_cell = 40;
+  if (per_cell <= 0) per_cell = 16;
   if (per_cell > 4096) return set_err(c, GRT_EINVAL, "per_cell must be at most 4096");
   const double d = c->g.d, k = c->g.k[1];
   double ymin = c->hy[0], ymax = c->hy[0];
