@@ -234,9 +234,9 @@ grt_status grt_query(const grt_ctx* ctx, grt_sizes* out);
 
 /* Fast translation for large M (the fast-multipole acceleration of T that the
  * paper's complexity remarks in secs. 5 and 7 name), enable = 1: a single-level cell
- * scheme.  The inclusion centres are binned into square cells (about per_cell each, 0:
- * 16, the fastest measured at M = 10000; at least 3 across the period); a cell and the
- * cells adjacent to it, the
+ * scheme.  The inclusion centres are binned into square cells (about per_cell each; 0:
+ * at least 16 and cells at least 13 / (k_2 sqrt 2) wide, below which the default order
+ * loses accuracy; at least 3 across the period); a cell and the cells adjacent to it, the
  * neighbours on the copies l = -1, +1 included, are translated pair by pair as in
  * sec. 4.2, every other (cell, copy) pair through cell expansions of order p_cell
  * (0: k_2 times the cell diagonal plus 25, at most 127): outgoing shift to the cell

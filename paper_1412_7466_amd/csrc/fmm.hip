@@ -404,7 +404,6 @@ grt_status fmm_setup(grt_ctx* c, int p_cell, int per_cell) {
   const int64_t M = c->M;
   if (M == 0) return GRT_OK;
   if (c->P > 20) return set_err(c, GRT_EUNSUP, "the cell translation takes P <= 20");
-  if (per_cell <= 0) per_cell = 16;
   if (per_cell > 4096) return set_err(c, GRT_EINVAL, "per_cell must be at most 4096");
   const double d = c->g.d, k = c->g.k[1];
   double ymin = c->hy[0], ymax = c->hy[0];
@@ -414,6 +413,14 @@ grt_status fmm_setup(grt_ctx* c, int p_cell, int per_cell) {
   }
   const double pad = 1e-9 * (1.0 + std::fabs(ymin) + std::fabs(ymax));
   const double H = (ymax - ymin) + 2 * pad;
+  if (per_cell <= 0) {
+    // at least 16 inclusions per cell, and cells no narrower than k s sqrt(2) = 13: with
+    // smaller k s the order k s sqrt(2) + 25 no longer holds 1e-12 per order (measured:
+    // 2.4e-13 at k s sqrt(2) = 13.6, M = 10000; 6.4e-10 at 7.7, M = 30000)
+    const double s_min = 13.0 / (k * std::sqrt(2.0));
+    const double need = (double)M * s_min * s_min / (d * std::max(H, 1e-3 * d));
+    per_cell = (int)std::min(4096.0, std::max(16.0, std::ceil(need)));
+  }
   // square cells (a far pair of cells is then at least two sides apart while the two
   // half-diagonals add to 1.41 sides), about per_cell inclusions each, at least 3
   // across the period (so that a cell and its neighbours on the copies l = -1, 0, 1
