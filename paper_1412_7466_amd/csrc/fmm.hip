@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 8)))
     const int B = bx * ny + by;
     const cd w = copy_weight(alpha, alpha_inv, l);
     // at P = 20 the one-copy routine's accumulators end up in scratch memory: use the
-    // dense kernels' three-copy routine with the other two copies weighted zero there
+    // dense kernels' pair routine there, generating its middle copy only
     const cd wl[3] = {cd{0.0, 0.0}, w, cd{0.0, 0.0}};
     const double tx = cx[j], ty = cy[j];
     for (int f = start[B]; f < start[B + 1]; ++f) {
@@ -334,8 +334,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 8)))
       if (m == j && l == 0) continue;
       const cd* b = x + (size_t)m * NB;
       if constexpr (P > 15)
-        pair_accumulate<P, cd>(acc, b, tx - (cx[m] + l * d), ty - cy[m], k, d, wl, false, false,
-                               (const double*)stab, 0.0);
+        pair_accumulate<P, cd, const cd*, const double*, 0, 2 * P + 1, true>(
+            acc, b, tx - (cx[m] + l * d), ty - cy[m], k, d, wl, false, false,
+            (const double*)stab, 0.0);
       else
         copy_accumulate<P>(acc, b, tx - (cx[m] + l * d), ty - cy[m], k, w, (const double*)stab);
     }

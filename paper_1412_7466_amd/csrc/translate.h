@@ -39,18 +39,20 @@ __device__ inline cf to_acc(cd v, cf*) { return cf{(float)v.r, (float)v.i}; }
 // emit0(tau_0) is called first, then emit(qb, tp, tm) for each block of M2L_QB
 // orders with tp[u] = tau_q, tm[u] = tau_{-q}, q = 1 + qb M2L_QB + u (zero past 2P).
 // skip0 drops the copy l = 0 (the excluded self term); dead drops everything; with
-// zsafe > 0 the pair is dropped too when a kept copy has k rho < zsafe.
-template <int P, typename TabPtr, typename F0, typename F>
+// zsafe > 0 the pair is dropped too when a kept copy has k rho < zsafe.  MID_ONLY:
+// only the copy l = 0 (weight wl[1]) is generated.
+template <int P, typename TabPtr, typename F0, typename F, bool MID_ONLY = false>
 __device__ __forceinline__ void pair_generate(double dx, double dy, double k, double d,
                                               const cd* wl, bool skip0, bool dead, TabPtr tab,
                                               double zsafe, F0&& emit0, F&& emit) {
   constexpr int NQB = (2 * P + M2L_QB - 1) / M2L_QB;
+  constexpr int L0 = MID_ONLY ? 1 : 0, L1 = MID_ONLY ? 2 : 3;
   cd hp[3], hc[3], cc[3], cq[3];
   double rz2[3];
   double zz[3];
   bool near = false;
 #pragma unroll
-  for (int l = 0; l < 3; ++l) {
+  for (int l = L0; l < L1; ++l) {
     double ex = dx - (l - 1) * d;
     bool off = (skip0 && l == 1) || dead;
     double r = sqrt(ex * ex + dy * dy);
@@ -64,7 +66,7 @@ __device__ __forceinline__ void pair_generate(double dx, double dy, double k, do
     rz2[l] = 2.0 / z;
   }
 #pragma unroll
-  for (int l = 0; l < 3; ++l) {
+  for (int l = L0; l < L1; ++l) {
     bool off = (skip0 && l == 1) || dead || near;
     cd h0, h1;
     hankel01_tab(zz[l], tab, h0, h1);
@@ -72,7 +74,10 @@ __device__ __forceinline__ void pair_generate(double dx, double dy, double k, do
     hp[l] = w * h0;
     hc[l] = w * h1;
   }
-  emit0(hp[0] + hp[1] + hp[2]);
+  if constexpr (MID_ONLY)
+    emit0(hp[1]);
+  else
+    emit0(hp[0] + hp[1] + hp[2]);
 #pragma unroll
   for (int qb = 0; qb < NQB; ++qb) {
     cd tp[M2L_QB], tm[M2L_QB];
@@ -82,7 +87,7 @@ __device__ __forceinline__ void pair_generate(double dx, double dy, double k, do
       cd sp{0.0, 0.0}, sm{0.0, 0.0};
       if (q <= 2 * P) {
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
+        for (int l = L0; l < L1; ++l) {
           // sp += hc cq, sm += hc conj(cq), as FMAs
           sp.r = fma(hc[l].r, cq[l].r, sp.r);
           sp.r = fma(-hc[l].i, cq[l].i, sp.r);
@@ -96,7 +101,7 @@ __device__ __forceinline__ void pair_generate(double dx, double dy, double k, do
         if (q & 1) sm = -sm;  // H_{-q} = (-1)^q H_q
         if (q < 2 * P) {
 #pragma unroll
-          for (int l = 0; l < 3; ++l) {
+          for (int l = L0; l < L1; ++l) {
             cd hn = (q * rz2[l]) * hc[l] - hp[l];
             hp[l] = hc[l];
             hc[l] = hn;
@@ -146,26 +151,27 @@ __device__ __forceinline__ void contract_block(T* acc, BP b, int qb, const T* tp
 // coefficients acc[n - LO] of one target, n in [LO, LO + NH): acc[n] += sum_nu
 // tau_{nu-n} x[nu], with the generator computed on the fly.  T is the accumulation
 // type (cd: FP64, cf: FP32 with FP32 accumulation; the generator is FP64 either way).
-template <int P, typename T, typename BP, typename TabPtr, int LO = 0, int NH = 2 * P + 1>
+template <int P, typename T, typename BP, typename TabPtr, int LO = 0, int NH = 2 * P + 1,
+          bool MID_ONLY = false>
 __device__ __forceinline__ void pair_accumulate(T* acc, BP b, double dx, double dy, double k,
                                                 double d, const cd* wl, bool skip0, bool dead,
                                                 TabPtr tab, double zsafe) {
-  pair_generate<P>(
-      dx, dy, k, d, wl, skip0, dead, tab, zsafe,
-      [&](cd t0) {
-        const T t = to_acc(t0, (T*)nullptr);
+  auto e0 = [&](cd t0) {
+    const T t = to_acc(t0, (T*)nullptr);
 #pragma unroll
-        for (int n = 0; n < NH; ++n) cmac(acc[n], t, b[n + LO]);
-      },
-      [&](int qb, const cd* tp, const cd* tm) {
-        T a[M2L_QB], c[M2L_QB];
+    for (int n = 0; n < NH; ++n) cmac(acc[n], t, b[n + LO]);
+  };
+  auto e1 = [&](int qb, const cd* tp, const cd* tm) {
+    T a[M2L_QB], c[M2L_QB];
 #pragma unroll
-        for (int u = 0; u < M2L_QB; ++u) {
-          a[u] = to_acc(tp[u], (T*)nullptr);
-          c[u] = to_acc(tm[u], (T*)nullptr);
-        }
-        contract_block<P, T, BP, 1 << 20, LO, NH>(acc, b, qb, a, c);
-      });
+    for (int u = 0; u < M2L_QB; ++u) {
+      a[u] = to_acc(tp[u], (T*)nullptr);
+      c[u] = to_acc(tm[u], (T*)nullptr);
+    }
+    contract_block<P, T, BP, 1 << 20, LO, NH>(acc, b, qb, a, c);
+  };
+  pair_generate<P, TabPtr, decltype(e0)&, decltype(e1)&, MID_ONLY>(dx, dy, k, d, wl, skip0, dead,
+                                                                   tab, zsafe, e0, e1);
 }
 
 // Translation of the outgoing coefficients of sources [m0, m1) (and of their
