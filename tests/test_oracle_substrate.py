@@ -108,6 +108,21 @@ def test_solvers_agree_and_loss_matters():
     assert np.linalg.norm(red.D * (b0 - b_lu)) > 1e-3 * np.linalg.norm(red.D * b_lu)
 
 
+def test_curved_powers_do_not_depend_on_gamma_d():
+    """Curved Gamma_2 over the substrate: its same-interface blocks take the kernel
+    differences and zeta corrections at the complex k_3 (ln(k_3/2) complex); moving
+    Gamma_d must leave the reflected powers and the disks' coefficients unchanged."""
+    pb = inputs.lossy_substrate(8, 6, seed=32, n3_im=0.06, curved_iface=True)
+    pb2 = inputs.lossy_substrate(8, 6, seed=32, n3_im=0.06, curved_iface=True)
+    pb2.disc = dataclasses.replace(pb.disc, y0=pb.disc.y0 * 1.1)
+    red1, red2 = Reduced(pb), Reduced(pb2)
+    b1, b2 = red1.solve_lu(), red2.solve_lu()
+    o1, o2 = red1.bragg(b1), red2.bragg(b2)
+    assert np.max(np.abs(o1["R"] - o2["R"])) < 1e-9
+    D = red1.D
+    assert np.linalg.norm(D * (b1 - b2)) < 1e-8 * np.linalg.norm(D * b1)
+
+
 @pytest.mark.parametrize("curved", [False, True])
 def test_balance_not_reported(curved):
     """With disks (absorbing or not, flat or curved interfaces) R + T + A stays
