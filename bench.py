@@ -920,8 +920,9 @@ def main():
                     help="also time S T of R angles at once on the FP32 matrix cores "
                          "(large block geometry, translation-only build)")
     ap.add_argument("--block-M", type=int, default=10000)
-    ap.add_argument("--fmm-M", type=int, default=0,
-                    help="also time the cell translation against the dense one at this M")
+    ap.add_argument("--fmm-M", type=int, default=10000,
+                    help="also time the cell translation against the dense one at this M "
+                         "(0: skip)")
     ap.add_argument("--block-reps", type=int, default=2)
     ap.add_argument("--flops-record", metavar="PMC_DB",
                     help="write the FP64 counter summary from one counter run and exit")
